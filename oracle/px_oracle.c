@@ -1,0 +1,603 @@
+/*
+ * px_oracle.c -- reference oracle for the omegaFQ / omegaFQFmu
+ * frequency-domain linear response (plasmonX paper, Sections 2.1, 2.2, 6, 7).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, single-threaded FP64 C with no BLAS
+ * or LAPACK.  Only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the GPU library never does, and the two share
+ * no code, header, constant or helper.
+ *
+ * The steps follow the paper's statement of the model, in its order:
+ *   Eq. (fermi)       Fermi-like tunnelling damping f(r)
+ *   Eq. (kappa)       K_ij = [1 - f(r_ij)] A_i / r_ij  (i != j), 0 on the diagonal
+ *   Eq. (kappa_bar)   Kbar = K - diag(row sums of K)
+ *   Eq. (tqq)         T_ij = erf(r_ij / R_ij) / r_ij, R_ij = sqrt(R_i^2 + R_j^2)
+ *   Eq. (z_q_wfq)     z_q(w) = -(w / 2 n tau) (w tau + i)
+ *   Eq. (z-mu)        z_mu(w) = -1 / alpha_IB(w)
+ *   Eq. (wfq-system)  [Kbar T - z_q I] q = -Kbar V
+ *   Eq. (wfqfmu-system) for charges and dipoles
+ *   Section 6, "inversion": LU with partial pivoting, then forward/back solves
+ *   Section 7: d = sum_i q_i r_i (+ mu_i), alpha_kl = d_k / E_l, sigma_abs.
+ *
+ * Readings of points the paper leaves open (each listed in the design notes):
+ *   - T^qq diagonal = lim_{r->0} erf(r/R_ii)/r = sqrt(2/pi)/R_q (the Gaussian
+ *     self-interaction, i.e. the chemical hardness the paper mentions).
+ *   - Exchange pairs are kept only when r_ij <= cutoff (the workload fixes a
+ *     cutoff of 1.2 nearest-neighbour distances).
+ *   - The "n" of z_q is the Drude weight n/m*; for graphene it is
+ *     E_F / (pi t_g) with t_g an effective sheet thickness.
+ *   - V_i = -E0 r_i.l (e^{-i w t} convention); RHS of the dipole block = E0 e_l.
+ *   - T^qmu, T^muq, T^mumu are the first and second derivatives of the
+ *     Gaussian charge kernel erf(r/R)/r with widths sqrt(R_a^2 + R_b^2);
+ *     T^qmu_ii = 0 and T^mumu_ii = 0 (the dipole self term is 1/alpha_IB).
+ *   - sigma_abs for a subset P of polarizations is (4 pi w / c) times the mean
+ *     of Im alpha_ll over l in P (equal to the trace formula when P = {x,y,z}).
+ *
+ * Unknown layout for the dipole model: component-major blocks
+ *   [ q_0..q_{N-1} | mu_x,0.. | mu_y,0.. | mu_z,0.. ].
+ * Complex numbers are stored as interleaved (re, im) doubles.
+ *
+ * Parameter vector p[12] (same order as the workload parameter files):
+ *   0 a_eff (bohr^2)  1 r_q (bohr)  2 r_mu (bohr)  3 tau (a.u.)
+ *   4 density n (a.u.) 5 m* (a.u.)  6 fermi d  7 fermi s
+ *   8 r0 (Angstrom)   9 cutoff (Angstrom)  10 E_F (eV, >0 selects graphene)
+ *   11 t_g (bohr)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018 */
+static const double ANG_PER_BOHR = 0.529177210903;
+static const double EV_PER_HARTREE = 27.211386245988;
+static const double C_LIGHT_AU = 137.035999084;
+static const double PI = 3.14159265358979323846;
+
+typedef struct {
+    double a_eff, r_q, r_mu, tau, n, mstar, fd, fs, r0, rc, ef, tg;
+} material;
+
+static material unpack(const double* p)
+{
+    material m;
+    m.a_eff = p[0];
+    m.r_q = p[1];
+    m.r_mu = p[2];
+    m.tau = p[3];
+    m.n = p[4];
+    m.mstar = p[5];
+    m.fd = p[6];
+    m.fs = p[7];
+    m.r0 = p[8] / ANG_PER_BOHR;
+    m.rc = p[9] / ANG_PER_BOHR;
+    m.ef = p[10] / EV_PER_HARTREE;
+    m.tg = p[11];
+    return m;
+}
+
+static void to_bohr(int64_t n, const double* xyz_ang, double* xyz)
+{
+    for (int64_t i = 0; i < 3 * n; ++i) xyz[i] = xyz_ang[i] / ANG_PER_BOHR;
+}
+
+static double dist(const double* xyz, int64_t i, int64_t j, double* rv)
+{
+    double dx = xyz[3 * i] - xyz[3 * j];
+    double dy = xyz[3 * i + 1] - xyz[3 * j + 1];
+    double dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+    if (rv) { rv[0] = dx; rv[1] = dy; rv[2] = dz; }
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+/* Eq. (fermi): f(r) = 1 / (1 + exp[-d (r / (s r0) - 1)]) */
+static double fermi(const material* m, double r)
+{
+    return 1.0 / (1.0 + exp(-m->fd * (r / (m->fs * m->r0) - 1.0)));
+}
+
+/* Eq. (kappa) for one ordered pair (0 beyond the exchange cutoff). */
+static double kappa(const material* m, double r)
+{
+    if (r > m->rc) return 0.0;
+    return (1.0 - fermi(m, r)) * m->a_eff / r;
+}
+
+/* Drude weight entering z_q (reading: n/m*, graphene E_F/(pi t_g)). */
+double or_drude_weight(const double* p)
+{
+    material m = unpack(p);
+    if (m.ef > 0.0) return m.ef / (PI * m.tg);
+    return m.n / m.mstar;
+}
+
+/* Eq. (z_q_wfq): z_q(w) = -(w / (2 n tau)) (w tau + i);  w in Hartree. */
+void or_zq(const double* p, double w, double* z)
+{
+    material m = unpack(p);
+    double nn = or_drude_weight(p);
+    double pref = -w / (2.0 * nn * m.tau);
+    z[0] = pref * w * m.tau;
+    z[1] = pref;
+}
+
+/* Eq. (tqq) with the hardness reading for the diagonal. */
+static double tqq(double r, double ri, double rj)
+{
+    double rr = sqrt(ri * ri + rj * rj);
+    if (r == 0.0) return 2.0 / (sqrt(PI) * rr);  /* limit of erf(r/R)/r */
+    return erf(r / rr) / r;
+}
+
+/* g(r; R) = erf(r/R) - (2/sqrt(pi)) (r/R) exp(-(r/R)^2): -r^2 d/dr [erf(r/R)/r]. */
+static double gfun(double r, double rr)
+{
+    double x = r / rr;
+    return erf(x) - 2.0 / sqrt(PI) * x * exp(-x * x);
+}
+
+/* Dense Kbar, row-major N x N (Eqs. kappa, kappa_bar). */
+void or_build_kbar(int64_t n, const double* xyz_ang, const double* p, double* kbar)
+{
+    material m = unpack(p);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    to_bohr(n, xyz_ang, xyz);
+    for (int64_t i = 0; i < n; ++i) {
+        double rowsum = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double k = 0.0;
+            if (j != i) k = kappa(&m, dist(xyz, i, j, NULL));
+            kbar[i * n + j] = k;
+            rowsum += k;
+        }
+        kbar[i * n + i] = -rowsum;   /* Kbar_ii = K_ii - sum_k K_ik, K_ii = 0 */
+    }
+    free(xyz);
+}
+
+/* Dense T^qq, row-major N x N. */
+void or_build_tqq(int64_t n, const double* xyz_ang, const double* p, double* t)
+{
+    material m = unpack(p);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    to_bohr(n, xyz_ang, xyz);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            t[i * n + j] = tqq(i == j ? 0.0 : dist(xyz, i, j, NULL), m.r_q, m.r_q);
+    free(xyz);
+}
+
+/* The 4x4 interaction block between atoms i (row) and j (column) of the
+ * charge-dipole model, laid out blk[a][b], a,b in {q, mu_x, mu_y, mu_z}. */
+static void pair_block(const material* m, const double* rv, double r, int same, double blk[4][4])
+{
+    memset(blk, 0, sizeof(double) * 16);
+    if (same) {
+        blk[0][0] = tqq(0.0, m->r_q, m->r_q);
+        return;                      /* T^qmu_ii = 0, T^mumu_ii = 0 */
+    }
+    double rqq = sqrt(2.0) * m->r_q;
+    double rqm = sqrt(m->r_q * m->r_q + m->r_mu * m->r_mu);
+    double rmm = sqrt(2.0) * m->r_mu;
+    double r3 = r * r * r, r5 = r3 * r * r;
+    blk[0][0] = erf(r / rqq) / r;
+    /* potential at i from a unit dipole at j: -d/dr_i of the charge kernel */
+    double gq = gfun(r, rqm);
+    for (int a = 0; a < 3; ++a) {
+        blk[0][1 + a] = gq * rv[a] / r3;
+        blk[1 + a][0] = -gq * rv[a] / r3;   /* minus the field at i from a unit charge at j */
+    }
+    /* minus the Hessian of erf(r/R)/r, R = R_mumu */
+    double gm = gfun(r, rmm);
+    double x = r / rmm;
+    double gauss = 4.0 / sqrt(PI) / (rmm * rmm * rmm) * exp(-x * x);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double d = (a == b) ? 1.0 : 0.0;
+            blk[1 + a][1 + b] = gm * (r * r * d - 3.0 * rv[a] * rv[b]) / r5 + gauss * rv[a] * rv[b] / (r * r);
+        }
+}
+
+/* Dense 4N x 4N T of the charge-dipole model (component-major blocks). */
+void or_build_tfull(int64_t n, const double* xyz_ang, const double* p, double* t)
+{
+    material m = unpack(p);
+    int64_t nu = 4 * n;
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    to_bohr(n, xyz_ang, xyz);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double rv[3], blk[4][4];
+            double r = (i == j) ? 0.0 : dist(xyz, i, j, rv);
+            pair_block(&m, rv, r, i == j, blk);
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) t[(a * n + i) * nu + (b * n + j)] = blk[a][b];
+        }
+    free(xyz);
+}
+
+/* ---- complex LU with partial pivoting (Section 6, inversion solver) ---- */
+
+/* Factor the n x n complex matrix a (interleaved re/im, row-major) in place.
+ * Returns 0, or k+1 if the k-th pivot is exactly zero.  kmax < n stops after
+ * kmax elimination steps (used only to time a bounded sample of the work). */
+int64_t or_lu_factor_partial(int64_t n, double* a, int64_t* piv, int64_t kmax)
+{
+    if (kmax > n) kmax = n;
+    for (int64_t k = 0; k < kmax; ++k) {
+        int64_t pr = k;
+        double best = -1.0;
+        for (int64_t i = k; i < n; ++i) {
+            double v = hypot(a[2 * (i * n + k)], a[2 * (i * n + k) + 1]);
+            if (v > best) { best = v; pr = i; }
+        }
+        if (best == 0.0) return k + 1;
+        piv[k] = pr;
+        if (pr != k)
+            for (int64_t j = 0; j < 2 * n; ++j) {
+                double tmp = a[2 * k * n + j];
+                a[2 * k * n + j] = a[2 * pr * n + j];
+                a[2 * pr * n + j] = tmp;
+            }
+        double pr_re = a[2 * (k * n + k)], pr_im = a[2 * (k * n + k) + 1];
+        double den = pr_re * pr_re + pr_im * pr_im;
+        for (int64_t i = k + 1; i < n; ++i) {
+            double* ai = a + 2 * i * n;
+            double* ak = a + 2 * k * n;
+            /* l_ik = a_ik / a_kk */
+            double lr = (ai[2 * k] * pr_re + ai[2 * k + 1] * pr_im) / den;
+            double li = (ai[2 * k + 1] * pr_re - ai[2 * k] * pr_im) / den;
+            ai[2 * k] = lr;
+            ai[2 * k + 1] = li;
+            for (int64_t j = k + 1; j < n; ++j) {
+                double ur = ak[2 * j], ui = ak[2 * j + 1];
+                ai[2 * j] -= lr * ur - li * ui;
+                ai[2 * j + 1] -= lr * ui + li * ur;
+            }
+        }
+    }
+    return 0;
+}
+
+int64_t or_lu_factor(int64_t n, double* a, int64_t* piv)
+{
+    return or_lu_factor_partial(n, a, piv, n);
+}
+
+/* Solve (LU) x = P b in place for one right-hand side b (interleaved complex). */
+void or_lu_solve(int64_t n, const double* lu, const int64_t* piv, double* b)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t pr = piv[k];
+        if (pr != k) {
+            double t0 = b[2 * k], t1 = b[2 * k + 1];
+            b[2 * k] = b[2 * pr]; b[2 * k + 1] = b[2 * pr + 1];
+            b[2 * pr] = t0; b[2 * pr + 1] = t1;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {           /* L y = b, unit diagonal */
+        double sr = b[2 * i], si = b[2 * i + 1];
+        for (int64_t j = 0; j < i; ++j) {
+            double lr = lu[2 * (i * n + j)], li = lu[2 * (i * n + j) + 1];
+            sr -= lr * b[2 * j] - li * b[2 * j + 1];
+            si -= lr * b[2 * j + 1] + li * b[2 * j];
+        }
+        b[2 * i] = sr; b[2 * i + 1] = si;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {      /* U x = y */
+        double sr = b[2 * i], si = b[2 * i + 1];
+        for (int64_t j = i + 1; j < n; ++j) {
+            double ur = lu[2 * (i * n + j)], ui = lu[2 * (i * n + j) + 1];
+            sr -= ur * b[2 * j] - ui * b[2 * j + 1];
+            si -= ur * b[2 * j + 1] + ui * b[2 * j];
+        }
+        double dr = lu[2 * (i * n + i)], di = lu[2 * (i * n + i) + 1];
+        double den = dr * dr + di * di;
+        b[2 * i] = (sr * dr + si * di) / den;
+        b[2 * i + 1] = (si * dr - sr * di) / den;
+    }
+}
+
+/* ---- system assembly ---- */
+
+static int64_t n_unknowns(int model, int64_t n) { return model == 1 ? 4 * n : n; }
+
+/* Right-hand side for polarization l (0,1,2): -Kbar V with V_i = -E0 r_i,l,
+ * and, for the dipole model, the field E0 e_l at every atom.  kbar dense. */
+static void rhs(int model, int64_t n, const double* xyz, const double* kbar, int l, double e0, double* b)
+{
+    int64_t nu = n_unknowns(model, n);
+    memset(b, 0, sizeof(double) * 2 * nu);
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double v = -e0 * xyz[3 * j + l];
+            s += kbar[i * n + j] * v;
+        }
+        b[2 * i] = -s;
+    }
+    if (model == 1)
+        for (int64_t i = 0; i < n; ++i) b[2 * ((1 + l) * n + i)] = e0;
+}
+
+/* Dense complex system matrix A(w) (interleaved, row-major nu x nu).
+ * kt: for omegaFQ, Kbar T (N x N); for the dipole model, diag(Kbar, I) T. */
+static void system_matrix(int model, int64_t n, const double* kt, const double* zq, const double* zmu, double* a)
+{
+    int64_t nu = n_unknowns(model, n);
+    for (int64_t i = 0; i < nu; ++i)
+        for (int64_t j = 0; j < nu; ++j) {
+            a[2 * (i * nu + j)] = kt[i * nu + j];
+            a[2 * (i * nu + j) + 1] = 0.0;
+        }
+    for (int64_t i = 0; i < nu; ++i) {
+        const double* z = (i < n) ? zq : zmu;
+        a[2 * (i * nu + i)] -= z[0];
+        a[2 * (i * nu + i) + 1] -= z[1];
+    }
+}
+
+/* Real product diag(Kbar, I) T (or Kbar T for omegaFQ), dense.  Zero entries
+ * of the sparse Kbar are skipped (adding 0 * T_kj changes nothing). */
+static void kbar_times_t(int model, int64_t n, const double* kbar, const double* t, double* kt)
+{
+    int64_t nu = n_unknowns(model, n);
+    for (int64_t i = 0; i < n; ++i) {
+        double* row = kt + i * nu;
+        memset(row, 0, sizeof(double) * nu);
+        for (int64_t k = 0; k < n; ++k) {
+            double kik = kbar[i * n + k];
+            if (kik == 0.0) continue;
+            const double* tk = t + k * nu;
+            for (int64_t j = 0; j < nu; ++j) row[j] += kik * tk[j];
+        }
+    }
+    for (int64_t i = n; i < nu; ++i) memcpy(kt + i * nu, t + i * nu, sizeof(double) * nu);
+}
+
+static int popcount3(uint32_t m) { return (int)((m & 1u) + ((m >> 1) & 1u) + ((m >> 2) & 1u)); }
+
+/*
+ * Full spectrum by direct solves.
+ *   model      0 omegaFQ, 1 omegaFQFmu
+ *   xyz_ang    n x 3 coordinates (Angstrom)
+ *   p          parameter vector (see header)
+ *   omega_ev   n_omega frequencies (eV, > 0)
+ *   pol_mask   bit0 x, bit1 y, bit2 z
+ *   e0         field amplitude (a.u.)
+ *   alpha_ib   2*n_omega interleaved alpha_IB(w) (dipole model) or NULL
+ * Outputs:
+ *   q_out      [n_omega][n_pol][nu] complex (n_pol = bits set, in x,y,z order)
+ *   alpha_out  [n_omega][3][3] complex, alpha[k][l] = d_k / E0 (columns of
+ *              unrequested l stay zero)
+ *   sigma_out  [n_omega] absorption cross section (bohr^2)
+ * Returns 0, or a positive code if a factorization met a zero pivot.
+ */
+int64_t or_solve_spectrum(int model, int64_t n, const double* xyz_ang, const double* p, int64_t n_omega,
+                          const double* omega_ev, uint32_t pol_mask, double e0, const double* alpha_ib,
+                          double* q_out, double* alpha_out, double* sigma_out)
+{
+    int64_t nu = n_unknowns(model, n);
+    int npol = popcount3(pol_mask);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    double* kbar = (double*)malloc(sizeof(double) * n * n);
+    double* t = (double*)malloc(sizeof(double) * nu * nu);
+    double* kt = (double*)malloc(sizeof(double) * nu * nu);
+    double* a = (double*)malloc(sizeof(double) * 2 * nu * nu);
+    double* b = (double*)malloc(sizeof(double) * 2 * nu * 3);
+    int64_t* piv = (int64_t*)malloc(sizeof(int64_t) * nu);
+    int64_t status = 0;
+    to_bohr(n, xyz_ang, xyz);
+    or_build_kbar(n, xyz_ang, p, kbar);
+    if (model == 1) or_build_tfull(n, xyz_ang, p, t);
+    else or_build_tqq(n, xyz_ang, p, t);
+    kbar_times_t(model, n, kbar, t, kt);
+    int pols[3], ip = 0;
+    for (int l = 0; l < 3; ++l)
+        if (pol_mask & (1u << l)) pols[ip++] = l;
+    for (int ip2 = 0; ip2 < npol; ++ip2) rhs(model, n, xyz, kbar, pols[ip2], e0, b + 2 * nu * ip2);
+    for (int64_t w = 0; w < n_omega; ++w) {
+        double om = omega_ev[w] / EV_PER_HARTREE;
+        double zq[2], zmu[2] = {0.0, 0.0};
+        or_zq(p, om, zq);
+        if (model == 1) {            /* Eq. (z-mu): z_mu = -1 / alpha_IB */
+            double ar = alpha_ib[2 * w], ai = alpha_ib[2 * w + 1];
+            double den = ar * ar + ai * ai;
+            zmu[0] = -ar / den;
+            zmu[1] = ai / den;
+        }
+        system_matrix(model, n, kt, zq, zmu, a);
+        int64_t rc = or_lu_factor(nu, a, piv);
+        if (rc != 0 && status == 0) status = rc;
+        double* al = alpha_out + 18 * w;
+        memset(al, 0, sizeof(double) * 18);
+        double im_sum = 0.0;
+        for (int ip2 = 0; ip2 < npol; ++ip2) {
+            int l = pols[ip2];
+            double* q = q_out + 2 * nu * (w * npol + ip2);
+            memcpy(q, b + 2 * nu * ip2, sizeof(double) * 2 * nu);
+            if (rc == 0) or_lu_solve(nu, a, piv, q);
+            for (int k = 0; k < 3; ++k) {          /* d_k = sum q_i r_ik (+ mu_k,i) */
+                double dr = 0.0, di = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    dr += q[2 * i] * xyz[3 * i + k];
+                    di += q[2 * i + 1] * xyz[3 * i + k];
+                }
+                if (model == 1)
+                    for (int64_t i = 0; i < n; ++i) {
+                        dr += q[2 * ((1 + k) * n + i)];
+                        di += q[2 * ((1 + k) * n + i) + 1];
+                    }
+                al[2 * (3 * k + l)] = dr / e0;
+                al[2 * (3 * k + l) + 1] = di / e0;
+            }
+            im_sum += al[2 * (3 * l + l) + 1];
+        }
+        sigma_out[w] = 4.0 * PI * om / C_LIGHT_AU * (im_sum / npol);
+    }
+    free(xyz); free(kbar); free(t); free(kt); free(a); free(b); free(piv);
+    return status;
+}
+
+/*
+ * Matrix-free operator apply y = A(w) x for ncol complex columns, each with
+ * its own frequency (and alpha_IB for the dipole model).  x, y: [ncol][nu]
+ * interleaved complex.  O(N^2) per column with every kernel entry evaluated
+ * on the fly; usable at sizes where the dense matrices do not fit.
+ */
+void or_apply(int model, int64_t n, const double* xyz_ang, const double* p, int64_t ncol,
+              const double* omega_ev, const double* alpha_ib, const double* x, double* y)
+{
+    material m = unpack(p);
+    int64_t nu = n_unknowns(model, n);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    double* u = (double*)malloc(sizeof(double) * 2 * nu * ncol);
+    to_bohr(n, xyz_ang, xyz);
+    memset(u, 0, sizeof(double) * 2 * nu * ncol);
+    /* u = T x */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double rv[3] = {0, 0, 0};
+            double r = (i == j) ? 0.0 : dist(xyz, i, j, rv);
+            if (model == 0) {
+                double tij = tqq(r, m.r_q, m.r_q);
+                for (int64_t c = 0; c < ncol; ++c) {
+                    u[2 * (c * nu + i)] += tij * x[2 * (c * nu + j)];
+                    u[2 * (c * nu + i) + 1] += tij * x[2 * (c * nu + j) + 1];
+                }
+            } else {
+                double blk[4][4];
+                pair_block(&m, rv, r, i == j, blk);
+                for (int64_t c = 0; c < ncol; ++c)
+                    for (int a = 0; a < 4; ++a)
+                        for (int b = 0; b < 4; ++b) {
+                            u[2 * (c * nu + a * n + i)] += blk[a][b] * x[2 * (c * nu + b * n + j)];
+                            u[2 * (c * nu + a * n + i) + 1] += blk[a][b] * x[2 * (c * nu + b * n + j) + 1];
+                        }
+            }
+        }
+    /* y = diag(Kbar, I) u - diag(z_q, z_mu) x ;  (Kbar u)_i = sum_j K_ij (u_j - u_i) */
+    for (int64_t c = 0; c < ncol; ++c) {
+        double om = omega_ev[c] / EV_PER_HARTREE;
+        double zq[2], zmu[2] = {0.0, 0.0};
+        or_zq(p, om, zq);
+        if (model == 1) {
+            double ar = alpha_ib[2 * c], ai = alpha_ib[2 * c + 1];
+            double den = ar * ar + ai * ai;
+            zmu[0] = -ar / den;
+            zmu[1] = ai / den;
+        }
+        const double* uc = u + 2 * c * nu;
+        const double* xc = x + 2 * c * nu;
+        double* yc = y + 2 * c * nu;
+        for (int64_t i = 0; i < n; ++i) {
+            double sr = 0.0, si = 0.0, ksum = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double k = kappa(&m, dist(xyz, i, j, NULL));
+                if (k == 0.0) continue;
+                sr += k * uc[2 * j];
+                si += k * uc[2 * j + 1];
+                ksum += k;
+            }
+            sr -= ksum * uc[2 * i];
+            si -= ksum * uc[2 * i + 1];
+            yc[2 * i] = sr - (zq[0] * xc[2 * i] - zq[1] * xc[2 * i + 1]);
+            yc[2 * i + 1] = si - (zq[0] * xc[2 * i + 1] + zq[1] * xc[2 * i]);
+        }
+        for (int64_t i = n; i < nu; ++i) {
+            yc[2 * i] = uc[2 * i] - (zmu[0] * xc[2 * i] - zmu[1] * xc[2 * i + 1]);
+            yc[2 * i + 1] = uc[2 * i + 1] - (zmu[0] * xc[2 * i + 1] + zmu[1] * xc[2 * i]);
+        }
+    }
+    free(xyz); free(u);
+}
+
+/* Right-hand side b for polarization l (0,1,2), [nu] interleaved complex,
+ * computed with the sparse neighbour sum (O(N^2) distance checks). */
+void or_rhs(int model, int64_t n, const double* xyz_ang, const double* p, int l, double e0, double* b)
+{
+    material m = unpack(p);
+    int64_t nu = n_unknowns(model, n);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    to_bohr(n, xyz_ang, xyz);
+    memset(b, 0, sizeof(double) * 2 * nu);
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double k = kappa(&m, dist(xyz, i, j, NULL));
+            /* (Kbar V)_i = sum_j K_ij (V_j - V_i),  V = -E0 r_l */
+            s += k * ((-e0 * xyz[3 * j + l]) - (-e0 * xyz[3 * i + l]));
+        }
+        b[2 * i] = -s;
+    }
+    if (model == 1)
+        for (int64_t i = 0; i < n; ++i) b[2 * ((1 + l) * n + i)] = e0;
+    free(xyz);
+}
+
+/* Sampled rows of the real product T X: Y[c][r] = sum_u T[rows[r]][u] X[c][u]
+ * for real columns X (ncol x nu).  rows index unknowns (0..nu-1). */
+void or_tapply_rows(int model, int64_t n, const double* xyz_ang, const double* p, int64_t nrows,
+                    const int64_t* rows, int64_t ncol, const double* x, double* yout)
+{
+    material m = unpack(p);
+    int64_t nu = n_unknowns(model, n);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    to_bohr(n, xyz_ang, xyz);
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t row = rows[r];
+        int64_t i = row % n, a = row / n;
+        for (int64_t c = 0; c < ncol; ++c) yout[c * nrows + r] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double rv[3] = {0, 0, 0};
+            double rr = (i == j) ? 0.0 : dist(xyz, i, j, rv);
+            if (model == 0) {
+                double tij = tqq(rr, m.r_q, m.r_q);
+                for (int64_t c = 0; c < ncol; ++c) yout[c * nrows + r] += tij * x[c * nu + j];
+            } else {
+                double blk[4][4];
+                pair_block(&m, rv, rr, i == j, blk);
+                for (int64_t c = 0; c < ncol; ++c)
+                    for (int b = 0; b < 4; ++b) yout[c * nrows + r] += blk[a][b] * x[c * nu + b * n + j];
+            }
+        }
+    }
+    free(xyz);
+}
+
+/* Dense assembly of A(w) for one frequency (for timing a bounded sample of
+ * the direct solver at large N): a = interleaved complex nu x nu. */
+void or_assemble(int model, int64_t n, const double* xyz_ang, const double* p, double omega_ev,
+                 const double* alpha_ib1, double* a)
+{
+    int64_t nu = n_unknowns(model, n);
+    double* kbar = (double*)malloc(sizeof(double) * n * n);
+    double* t = (double*)malloc(sizeof(double) * nu * nu);
+    double* kt = (double*)malloc(sizeof(double) * nu * nu);
+    or_build_kbar(n, xyz_ang, p, kbar);
+    if (model == 1) or_build_tfull(n, xyz_ang, p, t);
+    else or_build_tqq(n, xyz_ang, p, t);
+    kbar_times_t(model, n, kbar, t, kt);
+    free(t);
+    double om = omega_ev / EV_PER_HARTREE;
+    double zq[2], zmu[2] = {0.0, 0.0};
+    or_zq(p, om, zq);
+    if (model == 1) {
+        double ar = alpha_ib1[0], ai = alpha_ib1[1];
+        double den = ar * ar + ai * ai;
+        zmu[0] = -ar / den;
+        zmu[1] = ai / den;
+    }
+    system_matrix(model, n, kt, zq, zmu, a);
+    free(kbar); free(kt);
+}
+
+/* Unit constants as used by this oracle (so tests can check them). */
+void or_constants(double* out3)
+{
+    out3[0] = ANG_PER_BOHR;
+    out3[1] = EV_PER_HARTREE;
+    out3[2] = C_LIGHT_AU;
+}

@@ -1,0 +1,418 @@
+"""Pins of the reference oracle against what the paper and mathematics fix.
+
+Nothing here re-types the oracle's formulas and compares them with
+themselves.  Each pin uses an independent route: quadrature of the Gaussian
+densities the paper defines (Section 2.1), finite differences (the paper
+derives T^qmu and T^mumu by differentiation, Section 2.2), textbook limits
+(point charges and point dipoles), closed forms derived by hand for tiny
+systems, a library linear solver and eigensolver, and physical invariants
+(charge conservation, reciprocity, passivity, the f-sum rule, isotropy).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+import scipy.integrate as si
+import scipy.special as sp
+
+import oracle as O
+from workloads import configs as C
+from workloads import geometry as G
+from workloads import materials as M
+
+pytestmark = pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+
+# unit conversions as the oracle carries them (pinned to CODATA below)
+BOHR = O.constants()["ang_per_bohr"]
+HARTREE_EV = O.constants()["ev_per_hartree"]
+AG = M.load("ag_wfq")
+AU = M.load("au_wfqfmu")
+
+
+def pv(p, **kw):
+    return M.param_vector(M.with_overrides(p, **kw))
+
+
+def gauss_coulomb(d, s2):
+    """Coulomb energy of two unit Gaussian charges rho = exp(-r^2/R^2)/(pi^1.5 R^3)
+    with R1^2 + R2^2 = s2 at distance d (bohr), by 1-D quadrature in Fourier
+    space: (2/pi) int_0^inf exp(-k^2 s2 / 4) sin(k d)/(k d) dk."""
+    if d == 0.0:
+        f = lambda k: np.exp(-k * k * s2 / 4.0)
+    else:
+        f = lambda k: np.exp(-k * k * s2 / 4.0) * np.sinc(k * d / np.pi)
+    kmax = 40.0 / np.sqrt(s2)
+    val, _ = si.quad(f, 0.0, kmax, limit=400, epsabs=1e-15, epsrel=1e-13)
+    return 2.0 / np.pi * val
+
+
+# ---------------------------------------------------------------- constants
+
+def test_unit_constants_are_codata():
+    """The oracle carries CODATA 2018; the library of record may carry a later
+    adjustment, which moves these by < 1e-9 relative."""
+    c = O.constants()
+    assert c["ang_per_bohr"] == pytest.approx(sc.physical_constants["Bohr radius"][0] * 1e10, rel=1e-8)
+    assert c["ev_per_hartree"] == pytest.approx(sc.physical_constants["Hartree energy in eV"][0], rel=1e-8)
+    assert c["c_au"] == pytest.approx(1.0 / sc.fine_structure, rel=1e-8)
+
+
+# ---------------------------------------------------------------- kernels
+
+@pytest.mark.parametrize("d_bohr", [0.0, 0.3, 1.0, 2.5, 4.0, 7.5, 15.0])
+def test_tqq_equals_gaussian_charge_coulomb_energy(d_bohr):
+    """T^qq (Eq. tqq) including its diagonal is the Coulomb energy between the
+    Gaussian densities of Section 2.1."""
+    rq = AG["r_q_bohr"]
+    if d_bohr == 0.0:
+        xyz = np.zeros((1, 3))
+        t = O.tqq(xyz, pv(AG))[0, 0]
+    else:
+        xyz = G.two_atoms(d_bohr * BOHR)
+        t = O.tqq(xyz, pv(AG))[0, 1]
+    ref = gauss_coulomb(d_bohr, 2 * rq * rq)
+    assert t == pytest.approx(ref, rel=1e-10)
+
+
+def test_tqq_tends_to_point_charges():
+    xyz = G.two_atoms(60.0)
+    t = O.tqq(xyz, pv(AG))[0, 1]
+    assert t == pytest.approx(1.0 / (60.0 / BOHR), rel=1e-14)
+
+
+def _charge_kernel(ri, rj, s2):
+    d = np.linalg.norm(np.asarray(ri) - np.asarray(rj))
+    return sp.erf(d / np.sqrt(s2)) / d
+
+
+@pytest.mark.parametrize("d_ang", [1.2, 2.9, 4.1, 6.5])
+def test_dipole_kernels_are_derivatives_of_charge_kernel(d_ang):
+    """T^qmu, T^muq, T^mumu (Eq. wfqfmu-system) as finite differences of the
+    charge kernel (pinned above) with respect to the dipole positions."""
+    p = AU
+    rq, rm = p["r_q_bohr"], p["r_mu_bohr"]
+    direction = np.array([0.3, -0.5, 0.81])
+    direction /= np.linalg.norm(direction)
+    xyz = np.array([[0.0, 0.0, 0.0], d_ang * direction])
+    n = 2
+    t = O.tfull(xyz, pv(p))
+    rb = xyz / BOHR
+    h = 1e-4
+    e = np.eye(3)
+    i, j = 0, 1
+    for a in range(3):
+        # potential at i from a unit dipole at j along a  = d/d r_j,a of the kernel
+        fd = (_charge_kernel(rb[i], rb[j] + h * e[a], rq * rq + rm * rm)
+              - _charge_kernel(rb[i], rb[j] - h * e[a], rq * rq + rm * rm)) / (2 * h)
+        assert t[0 * n + i, (1 + a) * n + j] == pytest.approx(fd, rel=1e-7, abs=1e-12)
+        # minus field at i from a unit charge at j = d/d r_i,a of the kernel
+        fd2 = (_charge_kernel(rb[i] + h * e[a], rb[j], rm * rm + rq * rq)
+               - _charge_kernel(rb[i] - h * e[a], rb[j], rm * rm + rq * rq)) / (2 * h)
+        assert t[(1 + a) * n + i, 0 * n + j] == pytest.approx(fd2, rel=1e-7, abs=1e-12)
+        for b in range(3):
+            s2 = 2 * rm * rm
+            fpp = _charge_kernel(rb[i] + h * e[a], rb[j] + h * e[b], s2)
+            fpm = _charge_kernel(rb[i] + h * e[a], rb[j] - h * e[b], s2)
+            fmp = _charge_kernel(rb[i] - h * e[a], rb[j] + h * e[b], s2)
+            fmm = _charge_kernel(rb[i] - h * e[a], rb[j] - h * e[b], s2)
+            fd3 = (fpp - fpm - fmp + fmm) / (4 * h * h)
+            assert t[(1 + a) * n + i, (1 + b) * n + j] == pytest.approx(fd3, rel=2e-6, abs=1e-9)
+    # the self blocks (hardness reading): only T^qq_ii is non-zero
+    assert t[0, 0] == pytest.approx(np.sqrt(2 / np.pi) / rq, rel=1e-14)
+    for a in range(3):
+        assert t[0, (1 + a) * n] == 0.0 and t[(1 + a) * n, 0] == 0.0
+        for b in range(3):
+            assert t[(1 + a) * n, (1 + b) * n] == 0.0
+
+
+def test_dipole_kernel_point_limit_is_textbook_dipole_tensor():
+    """With vanishing widths, T^mumu is minus the point-dipole field tensor
+    (3 r r^T - r^2 I)/r^5 and T^qmu the point-dipole potential r^T/r^3."""
+    p = M.with_overrides(AU, r_mu_bohr=1e-7, r_q_bohr=1e-7)
+    xyz = np.array([[0.0, 0.0, 0.0], [3.1, -1.7, 2.2]])
+    t = O.tfull(xyz, M.param_vector(p))
+    r = (xyz[0] - xyz[1]) / BOHR
+    d = np.linalg.norm(r)
+    tensor = (d * d * np.eye(3) - 3 * np.outer(r, r)) / d ** 5
+    n = 2
+    assert np.allclose(t[n:, n:].reshape(3, 2, 3, 2)[:, 0, :, 1], tensor, rtol=1e-12, atol=0)
+    assert np.allclose(t[0, n:].reshape(3, 2)[:, 1], r / d ** 3, rtol=1e-12)
+
+
+def test_tfull_is_symmetric_and_tqq_is_positive_definite():
+    xyz = G.fcc_sphere_radius(6.0, seed=7)
+    t = O.tfull(xyz, pv(AU))
+    assert np.abs(t - t.T).max() <= 1e-15 * np.abs(t).max()
+    tq = O.tqq(xyz, pv(AG))
+    np.linalg.cholesky(tq)                       # Gram matrix of Gaussians: SPD
+    assert np.linalg.eigvalsh(tq).min() > 0
+
+
+def test_fermi_damping_half_point_and_cutoff():
+    """Eq. (fermi) gives f = 1/2 at r = s r0, so K = A / (2 s r0) there;
+    pairs beyond the exchange cutoff do not exchange charge."""
+    s, r0 = AG["fermi_s"], AG["r0_ang"]
+    assert s * r0 < AG["cutoff_ang"]
+    k = O.kbar(G.two_atoms(s * r0), pv(AG))
+    assert k[0, 1] == pytest.approx(AG["a_eff_bohr2"] / (2 * s * r0 / BOHR), rel=1e-14)
+    assert k[0, 0] == pytest.approx(-k[0, 1], rel=1e-15)
+    k2 = O.kbar(G.two_atoms(AG["cutoff_ang"] * 1.0001), pv(AG))
+    assert np.all(k2 == 0.0)
+    # deep inside the tunnelling region (r << s r0) the damping vanishes
+    k3 = O.kbar(G.two_atoms(0.2 * r0), pv(AG))
+    assert k3[0, 1] == pytest.approx(AG["a_eff_bohr2"] / (0.2 * r0 / BOHR), rel=1e-4)
+
+
+def test_kbar_laplacian_structure():
+    xyz = C.small_sphere()["xyz"]
+    k = O.kbar(xyz, pv(AG))
+    assert np.abs(k.sum(axis=1)).max() < 1e-14 * np.abs(k).max()
+    assert np.array_equal(k, k.T)
+    assert np.linalg.eigvalsh(k).max() < 1e-12
+    # every fcc site inside the sphere has at most 12 neighbours within 1.2 r0
+    off = (k != 0) & ~np.eye(len(k), dtype=bool)
+    assert off.sum(axis=1).max() == 12
+
+
+# ---------------------------------------------------------------- solver
+
+def test_own_lu_matches_library_solver():
+    rng = np.random.default_rng(11)
+    for n in (1, 5, 60, 200):
+        a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        b = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+        x = O.lu_solve(a, b)
+        ref = np.linalg.solve(a, b)
+        assert np.abs(x - ref).max() <= 1e-11 * np.abs(ref).max()
+    # a matrix that needs pivoting (zero leading entry)
+    a = np.array([[0, 1, 2], [3, 0, 1], [1, 1, 0]], dtype=complex)
+    b = np.array([1, 2, 3], dtype=complex)
+    assert np.allclose(O.lu_solve(a, b), np.linalg.solve(a, b), rtol=1e-14)
+
+
+def test_two_atom_closed_form():
+    """Two atoms at distance l = s r0 along x:  alpha_xx = k l^2 / (2 k (eta - t) + z)
+    with k = A/(2 s r0), eta = sqrt(2/pi)/R_q, t = erf(l/(sqrt2 R_q))/l,
+    and alpha_yy = alpha_zz = 0 (derived by hand from Eq. wfq-system)."""
+    p = AG
+    l_ang = p["fermi_s"] * p["r0_ang"]
+    l = l_ang / BOHR
+    k = p["a_eff_bohr2"] / (2 * l)
+    rq = p["r_q_bohr"]
+    eta = np.sqrt(2 / np.pi) / rq
+    t = sp.erf(l / (np.sqrt(2) * rq)) / l
+    dw = p["density_au"] / p["eff_mass_au"]
+    om_ev = np.array([0.5, 2.0, 3.3, 7.0])
+    out = O.solve_spectrum(0, G.two_atoms(l_ang), pv(p), om_ev, 0b111, 1e-4)
+    for w_i, wev in enumerate(om_ev):
+        w = wev / HARTREE_EV
+        z = -(w / (2 * dw * p["tau_au"])) * (w * p["tau_au"] + 1j)
+        axx = k * l * l / (2 * k * (eta - t) + z)
+        al = out["alpha"][w_i]
+        assert al[0, 0] == pytest.approx(axx, rel=1e-12)
+        assert abs(al[1, 1]) < 1e-12 * abs(axx) and abs(al[2, 2]) < 1e-12 * abs(axx)
+        assert abs(al[0, 1]) < 1e-12 * abs(axx)
+
+
+def test_two_atom_response_is_a_drude_lorentz_oscillator():
+    """The pair's alpha(w) must be f / (w0^2 - w^2 - i w / tau): damping rate
+    exactly 1/tau and oscillator strength f = 2 (n/m*) K_12 l^2 (the f-sum
+    rule of the Drude model), whatever the kernel values."""
+    p = AG
+    l_ang = 2.95
+    xyz = G.two_atoms(l_ang)
+    k12 = O.kbar(xyz, pv(p))[0, 1]
+    l = l_ang / BOHR
+    om_ev = np.linspace(0.5, 8.0, 9)
+    al = O.solve_spectrum(0, xyz, pv(p), om_ev, 0b001, 1e-4)["alpha"][:, 0, 0]
+    w = om_ev / HARTREE_EV
+    inv = 1.0 / al
+    # Re(1/alpha) = (w0^2 - w^2)/f  -> slope in w^2 is -1/f
+    slope, icpt = np.polyfit(w * w, inv.real, 1)
+    f = -1.0 / slope
+    gamma = -(inv.imag * f) / w
+    dw = p["density_au"] / p["eff_mass_au"]
+    assert f == pytest.approx(2 * dw * k12 * l * l, rel=1e-10)
+    assert np.allclose(gamma, 1.0 / p["tau_au"], rtol=1e-10)
+    assert icpt * f > 0                                   # w0^2 > 0
+
+
+def test_spectral_route_matches_direct_solve():
+    """alpha_xx(w) = sum_m w_m^2 / (lambda_m + z(w)) with (lambda, U) the
+    eigenpairs of L^1/2 T L^1/2 (L = -Kbar) and w = U^T L^1/2 x."""
+    xyz = G.fcc_sphere_radius(7.0, seed=3)
+    p = pv(AG)
+    kb = O.kbar(xyz, p)
+    t = O.tqq(xyz, p)
+    lw, lu = np.linalg.eigh(-kb)
+    lh = (lu * np.sqrt(np.clip(lw, 0, None))) @ lu.T
+    lam, u = np.linalg.eigh(lh @ t @ lh)
+    x = xyz[:, 0] / BOHR
+    wts = u.T @ lh @ x
+    om_ev = np.linspace(1.0, 6.0, 23)
+    out = O.solve_spectrum(0, xyz, p, om_ev, 0b001, 1e-4)
+    dw = AG["density_au"] / AG["eff_mass_au"]
+    tau = AG["tau_au"]
+    for i, wev in enumerate(om_ev):
+        w = wev / HARTREE_EV
+        z = -(w / (2 * dw * tau)) * (w * tau + 1j)
+        ref = np.sum(wts ** 2 / (lam + z))
+        assert out["alpha"][i, 0, 0] == pytest.approx(ref, rel=1e-9)
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_invariants_on_jittered_sphere():
+    c = C.small_sphere()
+    p = pv(c["params"])
+    om = np.array([2.0, 3.5, 3.55, 5.0])
+    out = O.solve_spectrum(0, c["xyz"], p, om, 0b111, 1e-4)
+    q = out["q"]
+    al = out["alpha"]
+    # charge conservation (a single connected fragment)
+    assert np.abs(q.sum(axis=2)).max() <= 1e-12 * np.abs(q).max()
+    # reciprocity: alpha is complex symmetric
+    for a in al:
+        assert np.abs(a - a.T).max() <= 1e-9 * np.abs(a).max()
+    # passivity
+    assert np.all(np.diagonal(al, axis1=1, axis2=2).imag > 0)
+    assert np.all(out["sigma"] > 0)
+    # linear in E0 and independent of the origin
+    out2 = O.solve_spectrum(0, c["xyz"] + np.array([3.0, -7.0, 11.0]), p, om, 0b111, 3e-3)
+    assert np.allclose(out2["alpha"], al, rtol=1e-10, atol=1e-10 * np.abs(al).max())
+    assert np.allclose(out2["q"] / 30.0, q, rtol=1e-9, atol=1e-12 * np.abs(q).max())
+
+
+def test_charge_conserved_per_fragment():
+    """Two clusters farther apart than the exchange cutoff: each keeps zero net
+    charge (the nullspace of Kbar is one constant per connected fragment)."""
+    xyz = G.gap_dimer(160, gap=6.0, seed=9)
+    n1 = 80
+    out = O.solve_spectrum(0, xyz, pv(AG), np.array([3.0]), 0b001, 1e-4)
+    q = out["q"][0, 0]
+    assert abs(q[:n1].sum()) <= 1e-12 * np.abs(q).max()
+    assert abs(q[n1:].sum()) <= 1e-12 * np.abs(q).max()
+    assert np.abs(q[:n1]).max() > 1e-3 * np.abs(q).max()
+
+
+def test_oh_cluster_is_isotropic():
+    xyz = G.fcc_sphere_radius(9.0, jitter=0.0)
+    out = O.solve_spectrum(0, xyz, pv(AG), np.array([2.5, 3.6, 4.4]), 0b111, 1e-4)
+    for a in out["alpha"]:
+        iso = np.trace(a) / 3
+        assert np.abs(a - iso * np.eye(3)).max() <= 1e-10 * abs(iso)
+
+
+def test_high_frequency_limit_is_the_f_sum_rule():
+    """w^2 alpha_xx(w) -> -2 (n/m*) sum_{i<j} K_ij (x_i - x_j)^2 (free-electron
+    limit: independent of T)."""
+    xyz = G.fcc_sphere_radius(8.0, seed=5)
+    p = pv(AG)
+    kb = O.kbar(xyz, p)
+    x = xyz[:, 0] / BOHR
+    bond = 0.0
+    n = len(x)
+    for i in range(n):
+        for j in range(i + 1, n):
+            bond += kb[i, j] * (x[i] - x[j]) ** 2
+    dw = AG["density_au"] / AG["eff_mass_au"]
+    wev = 2.0e5
+    al = O.solve_spectrum(0, xyz, p, np.array([wev]), 0b001, 1e-4)["alpha"][0, 0, 0]
+    w = wev / HARTREE_EV
+    assert (w * w * al).real == pytest.approx(-2 * dw * bond, rel=1e-6)
+
+
+# ---------------------------------------------------------------- dipole model
+
+def test_single_atom_dipole_model_is_alpha_ib():
+    aib = np.array([17.0 + 2.0j, 9.0 + 0.5j])
+    out = O.solve_spectrum(1, np.zeros((1, 3)), pv(AU), np.array([2.0, 3.0]), 0b111, 1e-4, aib)
+    for w in range(2):
+        assert np.allclose(out["alpha"][w], aib[w] * np.eye(3), rtol=1e-13, atol=1e-13)
+        assert np.abs(out["q"][w][:, 0]).max() == 0.0
+
+
+def test_point_dipole_pair_is_applequist():
+    """Two atoms beyond the exchange cutoff with (nearly) point dipoles: no
+    charge flows and the pair polarizability is the classical coupled-dipole
+    result 2a/(1 - 2a/r^3) along the axis and 2a/(1 + a/r^3) across it."""
+    p = M.with_overrides(AU, r_mu_bohr=1e-6)
+    d_ang = 5.0
+    r = d_ang / BOHR
+    a = 11.0 + 1.5j
+    out = O.solve_spectrum(1, G.two_atoms(d_ang), M.param_vector(p), np.array([2.4]), 0b111, 1e-4, np.array([a]))
+    al = out["alpha"][0]
+    assert al[0, 0] == pytest.approx(2 * a / (1 - 2 * a / r ** 3), rel=1e-10)
+    assert al[1, 1] == pytest.approx(2 * a / (1 + a / r ** 3), rel=1e-10)
+    assert al[2, 2] == pytest.approx(2 * a / (1 + a / r ** 3), rel=1e-10)
+    assert np.abs(out["q"][0][:, :2]).max() == 0.0
+
+
+def test_dipole_model_without_interband_term_reduces_to_charges():
+    xyz = G.fcc_sphere_radius(7.0, seed=4)
+    om = np.array([2.0, 3.2, 4.5])
+    aib = np.full(3, 1e-13 + 0j)
+    a1 = O.solve_spectrum(1, xyz, pv(AU), om, 0b001, 1e-4, aib)["alpha"][:, 0, 0]
+    a0 = O.solve_spectrum(0, xyz, pv(AU), om, 0b001, 1e-4)["alpha"][:, 0, 0]
+    assert np.allclose(a1, a0, rtol=1e-8)
+
+
+def test_dipole_model_reciprocity_passivity_conservation():
+    xyz = G.fcc_sphere_radius(6.5, seed=8)
+    om = np.array([1.8, 2.6, 3.4])
+    aib = M.interband_alpha(AU, om)
+    out = O.solve_spectrum(1, xyz, pv(AU), om, 0b111, 1e-4, aib)
+    n = len(xyz)
+    for a in out["alpha"]:
+        assert np.abs(a - a.T).max() <= 1e-9 * np.abs(a).max()
+        assert np.all(np.diag(a).imag > 0)
+    assert np.abs(out["q"][:, :, :n].sum(axis=2)).max() <= 1e-12 * np.abs(out["q"]).max()
+
+
+# ---------------------------------------------------------------- paper trend
+
+def _prf(xyz, p, lo, hi):
+    grid = np.linspace(lo, hi, 25)
+    s = O.solve_spectrum(0, xyz, p, grid, 0b001, 1e-4)["sigma"]
+    i = int(np.argmax(s))
+    fine = np.linspace(grid[max(i - 1, 0)], grid[min(i + 1, len(grid) - 1)], 25)
+    s2 = O.solve_spectrum(0, xyz, p, fine, 0b001, 1e-4)["sigma"]
+    return fine[int(np.argmax(s2))]
+
+
+def test_graphene_disk_plasmon_trend_matches_paper_ratio():
+    """Doubling a graphene disk's atom count at fixed E_F red-shifts its plasmon
+    by the ratio the paper prints for its 10k -> 20k-atom disks (0.26/0.30
+    eV), within the spread expected between small and large disks."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_graphene_prf.json")) as f:
+        gold = json.load(f)
+    ratio_paper = gold["prf_ev"]["20000"] / gold["prf_ev"]["10000"]
+    p = pv(M.load("graphene_wfq"))
+    w1 = _prf(G.graphene_disk_n(300), p, 0.2, 1.2)
+    w2 = _prf(G.graphene_disk_n(600), p, 0.2, 1.2)
+    assert w2 / w1 == pytest.approx(ratio_paper, rel=0.06)
+
+
+def test_stored_small_sphere_spectrum_is_reproduced():
+    """Regression fixture written by tests/golden/make_golden.py (oracle only)."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "small_sphere_sigma.json")) as f:
+        gold = json.load(f)
+    c = C.small_sphere()
+    out = O.solve_spectrum(0, c["xyz"], pv(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
+    assert np.allclose(out["sigma"], gold["sigma_bohr2"], rtol=1e-12, atol=0)
+
+
+def test_sigma_is_textbook_absorption_cross_section():
+    """Quasi-static absorption cross section of a polarizable particle
+    (Gaussian units): C_abs = 4 pi k Im alpha, k = w / c, averaged over the
+    solved polarizations; the speed of light from the library of record."""
+    c_au = 1.0 / sc.fine_structure
+    c = C.small_sphere()
+    out = O.solve_spectrum(0, c["xyz"], pv(c["params"]), c["omega_ev"], 0b001, 1e-4)
+    k = c["omega_ev"] / HARTREE_EV / c_au
+    assert np.allclose(out["sigma"], 4 * np.pi * k * out["alpha"][:, 0, 0].imag, rtol=1e-8)
+    out3 = O.solve_spectrum(0, c["xyz"], pv(c["params"]), c["omega_ev"][:5], 0b111, 1e-4)
+    tr = np.trace(out3["alpha"], axis1=1, axis2=2).imag
+    assert np.allclose(out3["sigma"], 4 * np.pi * k[:5] * tr / 3, rtol=1e-8)
