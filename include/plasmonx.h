@@ -1,0 +1,188 @@
+/*
+ * plasmonx.h -- C ABI of the MI355X (gfx950) frequency-domain solver for the
+ * atomistic omegaFQ and omegaFQFmu plasmonics models (plasmonX paper,
+ * arXiv 2510.12731, Sections 2.1, 2.2, 6 and 7).
+ *
+ * One call sequence per nanostructure:
+ *   pxCreateStructure  -> geometry, neighbour list, Kbar (Eqs. kappa, kappa_bar, fermi)
+ *   pxSetFrequencies   -> frequency grid, polarizations, field amplitude
+ *   pxSolveSpectrum    -> solve Eq. (wfq-system) / Eq. (wfqfmu-system) for every
+ *                         (frequency, polarization) column by blocked GMRES
+ *                         (Section 6, "iterative on the fly")
+ *   pxGetCharges / pxGetSpectrum / pxGetSolveStats -> results (Section 7)
+ *   pxDestroyStructure
+ *
+ * Conventions
+ *   - Every call returns pxStatus; nothing throws across this boundary.  On a
+ *     non-OK status pxLastError() returns a thread-local description.
+ *   - Coordinates are in Angstrom (the paper's input unit), frequencies in eV,
+ *     everything else in Hartree atomic units unless the field name says so.
+ *   - Complex numbers are interleaved (re, im) doubles.
+ *   - All caller buffers are host memory, read (inputs) or written (outputs)
+ *     before the call returns; the library copies what it keeps.  Device memory
+ *     belongs to the library (hipMalloc) and is released by pxDestroyStructure.
+ *   - Outputs are in the caller's atom order.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently
+ *     from different threads.  Work runs on the HIP stream given at creation
+ *     (NULL = the default stream); pxGet* synchronise that stream.
+ *   - Unknown order of the dipole model: [q_0..q_{N-1} | mu_x | mu_y | mu_z].
+ */
+#ifndef PLASMONX_H
+#define PLASMONX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PX_OK = 0,
+    PX_E_INVALID = 1,   /* bad argument: NaN/Inf or coincident atoms, omega <= 0, tau <= 0, ... */
+    PX_E_OOM = 2,       /* device allocation failed or the memory budget would be exceeded */
+    PX_E_NOTCONV = 3,   /* some columns missed rel_tol; results readable, see pxGetSolveStats */
+    PX_E_DEVICE = 4,    /* HIP runtime error or the library was built for another device */
+    PX_E_STATE = 5      /* call out of order (e.g. results before a solve) */
+} pxStatus;
+
+typedef enum { PX_WFQ = 0, PX_WFQFMU = 1 } pxModel;
+
+typedef enum {
+    PX_FP64 = 0,   /* every step in FP64 */
+    PX_MIXED = 1   /* T-apply in FP32 on MFMA inside GMRES cycles; FP64 Arnoldi,
+                      Givens, solution update and true residual (iterative refinement) */
+} pxPrecision;
+
+/* Material parameters of one homogeneous nanostructure.
+ *   a_eff            effective area A of Eq. (kappa), bohr^2
+ *   r_q, r_mu        Gaussian widths of charges (Eq. tqq) and dipoles, bohr
+ *   tau              Drude scattering time of Eq. (z_q_wfq), a.u.
+ *   density, eff_mass  n and m* (a.u.); the Drude weight entering z_q is n/m*
+ *   fermi_d, fermi_s  d and s of Eq. (fermi)
+ *   r0_ang           nearest-neighbour distance r^0 of Eq. (fermi), Angstrom
+ *   cutoff_ang       charge exchange is kept for pairs with r_ij <= cutoff, Angstrom
+ *   fermi_energy_ev  > 0 selects the graphene reading of the Drude weight,
+ *                    E_F / (pi * sheet_thickness) (Eq. 2d-eff-mass with the
+ *                    Dirac-cone density); 0 for metals
+ *   sheet_thickness  effective graphene thickness, bohr (used iff fermi_energy_ev > 0)
+ */
+typedef struct {
+    double a_eff;
+    double r_q;
+    double r_mu;
+    double tau;
+    double density;
+    double eff_mass;
+    double fermi_d;
+    double fermi_s;
+    double r0_ang;
+    double cutoff_ang;
+    double fermi_energy_ev;
+    double sheet_thickness;
+} pxMaterial;
+
+/* Solver options (pxDefaultSolveOptions fills the defaults shown).
+ *   precision        PX_MIXED (default) or PX_FP64
+ *   restart_m        GMRES restart length m (50)
+ *   rel_tol          per column ||b - A x||_2 / ||b||_2 target (1e-8)
+ *   max_cycles       maximum number of restart cycles per column (400)
+ *   max_block_cols   columns solved together in one block; 0 = all (0).
+ *                    1 gives the one-column-at-a-time solver.
+ *   inner_reduction  mixed precision: a cycle stops for a column once its
+ *                    estimated residual fell by this factor (1e-5); 0 = only
+ *                    the rel_tol target stops it
+ *   timings          1 = time each phase with HIP events (pxGetTimings) (0)
+ */
+typedef struct {
+    int32_t precision;
+    int32_t restart_m;
+    double rel_tol;
+    int32_t max_cycles;
+    int32_t max_block_cols;
+    double inner_reduction;
+    int32_t timings;
+} pxSolveOptions;
+
+typedef struct pxStructure_t* pxStructure;
+
+/* Fills *opt with the defaults listed above. */
+void pxDefaultSolveOptions(pxSolveOptions* opt);
+
+/* Creates a nanostructure from n_atoms coordinates (xyz_ang: n_atoms x 3,
+ * row-major, Angstrom, copied).  Builds on the device: the Morton order of the
+ * atoms, the neighbour list within cutoff_ang and the CSR matrix Kbar
+ * (Eqs. fermi, kappa, kappa_bar).  hip_stream: a hipStream_t or NULL.
+ * Errors: PX_E_INVALID for n_atoms < 1, non-finite coordinates, two atoms
+ * closer than 1e-6 Angstrom, or non-positive a_eff, r_q, tau, Drude weight,
+ * r0 or cutoff (r_mu > 0 required for PX_WFQFMU); PX_E_OOM; PX_E_DEVICE. */
+pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang, const pxMaterial* mat,
+                           void* hip_stream, pxStructure* out);
+
+/* Sets the frequency grid (omega_ev[n_omega], > 0, copied), the polarizations
+ * (pol_mask bit0 = x, bit1 = y, bit2 = z; one column per set bit and
+ * frequency, frequency-major) and the field amplitude e0_au (> 0; the paper
+ * uses 1e-4).  alpha_ib: 2*n_omega interleaved complex interband
+ * polarizabilities alpha^IB(omega) (bohr^3) of Eq. (z-mu), required for
+ * PX_WFQFMU and ignored for PX_WFQ.  Discards previous results. */
+pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask,
+                          double e0_au, const double* alpha_ib);
+
+/* Solves all columns (synchronously: the call returns when the solve is
+ * done).  opt may be NULL (defaults).  Returns PX_E_NOTCONV if any column
+ * missed rel_tol within max_cycles (results stay readable). */
+pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt);
+
+/* Solves several structures; each keeps its own options-independent state.
+ * Structures are processed with their columns interleaved on the device
+ * (see the batched launch in the implementation notes). */
+pxStatus pxSolveBatch(const pxStructure* s, int32_t n, const pxSolveOptions* opt);
+
+/* Induced charges q (2*n_atoms doubles) and, for PX_WFQFMU, dipoles mu
+ * (6*n_atoms doubles: mu_x, mu_y, mu_z blocks) of column (i_omega, pol) in
+ * the caller's atom order; pol is 0, 1 or 2 and must be in pol_mask.  mu may
+ * be NULL.  PX_E_STATE before a solve. */
+pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, double* mu);
+
+/* Polarizability alpha[n_omega][3][3] (interleaved complex, alpha[k][l] =
+ * d_k / E_l, zero for unsolved l) and absorption cross section
+ * sigma_abs[n_omega] (bohr^2): (4 pi omega / c) times the mean of Im alpha_ll
+ * over the solved polarizations, i.e. the paper's (4 pi omega / 3c) Tr Im alpha
+ * when all three are solved.  Either pointer may be NULL. */
+pxStatus pxGetSpectrum(pxStructure s, double* alpha, double* sigma_abs);
+
+/* Per column (frequency-major, n_omega * n_pol entries): GMRES iterations,
+ * restart cycles and final true relative residual ||b - A x|| / ||b||
+ * (recomputed in FP64).  Any pointer may be NULL. */
+pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, double* rel_res);
+
+/* Applies the operator of the solved system, y_c = A(omega_c) x_c, to ncol
+ * complex columns (x, y: [ncol][n_unknowns] interleaved complex, caller atom
+ * order), column c at frequency omega_ev[c] (and alpha_ib[c] for PX_WFQFMU),
+ * in the requested precision, with the same kernels the solver uses. */
+pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const double* omega_ev,
+                         const double* alpha_ib, const double* x, double* y);
+
+/* Number of unknowns (n_atoms or 4 n_atoms) and of atoms. */
+pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns);
+
+/* Measurements of the last solve.
+ * ms6 (may be NULL): [0] wall time of the solve; with options.timings = 1 the
+ * HIP-event times summed over all Arnoldi steps of [1] the FP32 T-apply, [2]
+ * the FP64 T-apply inside cycles, [3] the sparse Kbar apply, [4] the
+ * orthogonalisation/Givens kernels, and [5] the remainder (residuals,
+ * updates, host work); zeros otherwise.
+ * counts6 (may be NULL): [0] FP32 T-apply launches, [1] real columns they
+ * processed including padding, [2] real columns without padding; [3..5] the
+ * same for the FP64 T-apply (inside cycles and true residuals). */
+pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6);
+
+void pxDestroyStructure(pxStructure s);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* pxLastError(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLASMONX_H */

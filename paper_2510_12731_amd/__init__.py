@@ -1,0 +1,264 @@
+"""Python binding of the MI355X omegaFQ / omegaFQFmu solver library.
+
+Argument marshalling only: every step of the solve runs in the HIP library
+``libplasmonx_hip.so`` built from ``csrc/``.  The functions carry the names of
+the C entry points declared in ``include/plasmonx.h``; ``Structure`` wraps them
+for convenience.  Importing this package never builds anything and never
+falls back to another implementation: if the library is missing, ``load()``
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplasmonx_hip.so")
+
+PX_OK, PX_E_INVALID, PX_E_OOM, PX_E_NOTCONV, PX_E_DEVICE, PX_E_STATE = range(6)
+PX_WFQ, PX_WFQFMU = 0, 1
+PX_FP64, PX_MIXED = 0, 1
+STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV", 4: "PX_E_DEVICE", 5: "PX_E_STATE"}
+
+EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
+            "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings",
+            "pxDestroyStructure", "pxLastError"]
+
+
+class PxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pxMaterial(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("a_eff", "r_q", "r_mu", "tau", "density", "eff_mass", "fermi_d",
+                                               "fermi_s", "r0_ang", "cutoff_ang", "fermi_energy_ev",
+                                               "sheet_thickness")]
+
+
+class pxSolveOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("restart_m", ctypes.c_int32), ("rel_tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
+                ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2510_12731_amd.build)")
+    lib = ctypes.CDLL(path)
+    i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.pxDefaultSolveOptions.argtypes = [ctypes.POINTER(pxSolveOptions)]
+    lib.pxDefaultSolveOptions.restype = None
+    lib.pxCreateStructure.argtypes = [ctypes.c_int, i64, _dp, ctypes.POINTER(pxMaterial), _vp, ctypes.POINTER(_vp)]
+    lib.pxSetFrequencies.argtypes = [_vp, i32, _dp, u32, ctypes.c_double, _dp]
+    lib.pxSolveSpectrum.argtypes = [_vp, ctypes.POINTER(pxSolveOptions)]
+    lib.pxSolveBatch.argtypes = [ctypes.POINTER(_vp), i32, ctypes.POINTER(pxSolveOptions)]
+    lib.pxGetCharges.argtypes = [_vp, i32, i32, _dp, _dp]
+    lib.pxGetSpectrum.argtypes = [_vp, _dp, _dp]
+    lib.pxGetSolveStats.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), _dp]
+    lib.pxApplyOperator.argtypes = [_vp, i32, i32, _dp, _dp, _dp, _dp]
+    lib.pxGetSize.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.pxGetTimings.argtypes = [_vp, _dp, ctypes.POINTER(i64)]
+    lib.pxDestroyStructure.argtypes = [_vp]
+    lib.pxDestroyStructure.restype = None
+    lib.pxLastError.argtypes = []
+    lib.pxLastError.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("pxDefaultSolveOptions", "pxDestroyStructure", "pxLastError"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _check(st, allow=(PX_OK,)):
+    if st not in allow:
+        raise PxError(st, load().pxLastError().decode())
+    return st
+
+
+def material(params) -> pxMaterial:
+    """pxMaterial from a parameter dict (workload parameter files) or vector."""
+    if isinstance(params, dict):
+        keys = ("a_eff_bohr2", "r_q_bohr", "r_mu_bohr", "tau_au", "density_au", "eff_mass_au", "fermi_d", "fermi_s",
+                "r0_ang", "cutoff_ang", "fermi_energy_ev", "sheet_thickness_bohr")
+        vals = [float(params[k]) for k in keys]
+    else:
+        vals = [float(v) for v in params]
+    return pxMaterial(*vals)
+
+
+def default_stream():
+    """The current torch stream (HIP) if torch sees a GPU, else None."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+# ---- same-name wrappers of the C entry points -------------------------------
+
+def pxDefaultSolveOptions() -> pxSolveOptions:
+    o = pxSolveOptions()
+    load().pxDefaultSolveOptions(ctypes.byref(o))
+    return o
+
+
+def pxCreateStructure(model, xyz_ang, mat, hip_stream=None):
+    xyz = np.ascontiguousarray(xyz_ang, dtype=np.float64).reshape(-1, 3)
+    h = _vp()
+    m = mat if isinstance(mat, pxMaterial) else material(mat)
+    _check(load().pxCreateStructure(int(model), len(xyz), _ptr(xyz), ctypes.byref(m), hip_stream, ctypes.byref(h)))
+    return h
+
+
+def pxSetFrequencies(h, omega_ev, pol_mask, e0_au, alpha_ib=None):
+    om = np.ascontiguousarray(omega_ev, dtype=np.float64)
+    aib = None if alpha_ib is None else np.ascontiguousarray(np.asarray(alpha_ib, dtype=np.complex128)).view(np.float64)
+    _check(load().pxSetFrequencies(h, len(om), _ptr(om), int(pol_mask), float(e0_au), _ptr(aib)))
+
+
+def pxSolveSpectrum(h, opt: pxSolveOptions | None = None):
+    return _check(load().pxSolveSpectrum(h, None if opt is None else ctypes.byref(opt)), (PX_OK, PX_E_NOTCONV))
+
+
+def pxSolveBatch(handles, opt: pxSolveOptions | None = None):
+    arr = (_vp * len(handles))(*[h.value if isinstance(h, _vp) else h for h in handles])
+    return _check(load().pxSolveBatch(arr, len(handles), None if opt is None else ctypes.byref(opt)),
+                  (PX_OK, PX_E_NOTCONV))
+
+
+def pxGetSize(h):
+    n, nu = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pxGetSize(h, ctypes.byref(n), ctypes.byref(nu)))
+    return n.value, nu.value
+
+
+def pxGetCharges(h, i_omega, pol, with_dipoles=False):
+    n, nu = pxGetSize(h)
+    q = np.zeros(n, dtype=np.complex128)
+    mu = np.zeros((3, n), dtype=np.complex128) if with_dipoles else None
+    _check(load().pxGetCharges(h, int(i_omega), int(pol), _ptr(q.view(np.float64)),
+                               None if mu is None else _ptr(mu.view(np.float64))))
+    return (q, mu) if with_dipoles else q
+
+
+def pxGetSpectrum(h, n_omega):
+    alpha = np.zeros((n_omega, 3, 3), dtype=np.complex128)
+    sigma = np.zeros(n_omega)
+    _check(load().pxGetSpectrum(h, _ptr(alpha.view(np.float64)), _ptr(sigma)))
+    return alpha, sigma
+
+
+def pxGetSolveStats(h, ncol):
+    it = (ctypes.c_int32 * ncol)()
+    cy = (ctypes.c_int32 * ncol)()
+    rr = np.zeros(ncol)
+    _check(load().pxGetSolveStats(h, it, cy, _ptr(rr)))
+    return np.array(it[:]), np.array(cy[:]), rr
+
+
+def pxApplyOperator(h, precision, omega_ev, x, alpha_ib=None):
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    ncol = x.shape[0]
+    om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega_ev, dtype=np.float64), (ncol,)))
+    aib = None
+    if alpha_ib is not None:
+        aib = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha_ib, dtype=np.complex128), (ncol,))).view(np.float64)
+    y = np.zeros_like(x)
+    _check(load().pxApplyOperator(h, int(precision), ncol, _ptr(om), _ptr(aib), _ptr(x.view(np.float64)),
+                                  _ptr(y.view(np.float64))))
+    return y
+
+
+def pxGetTimings(h):
+    ms = np.zeros(6)
+    cnt = (ctypes.c_int64 * 6)()
+    _check(load().pxGetTimings(h, _ptr(ms), cnt))
+    return dict(ms_total=ms[0], ms_tapply_f32=ms[1], ms_tapply_f64_cycles=ms[2], ms_spmm=ms[3], ms_arnoldi=ms[4],
+                ms_other=ms[5], n_tapply_f32=cnt[0], cols_f32_padded=cnt[1], cols_f32=cnt[2],
+                n_tapply_f64=cnt[3], cols_f64_padded=cnt[4], cols_f64=cnt[5])
+
+
+def pxDestroyStructure(h):
+    if h is not None:
+        load().pxDestroyStructure(h)
+
+
+def pxLastError():
+    return load().pxLastError().decode()
+
+
+# ---- convenience wrapper ---------------------------------------------------
+
+class Structure:
+    """One nanostructure on the GPU (see include/plasmonx.h)."""
+
+    def __init__(self, model, xyz_ang, params, hip_stream=None):
+        self.model = int(model)
+        self.h = pxCreateStructure(model, xyz_ang, params, hip_stream)
+        self.n, self.nu = pxGetSize(self.h)
+        self.n_omega = 0
+        self.ncol = 0
+
+    def set_frequencies(self, omega_ev, pol_mask, e0_au=1e-4, alpha_ib=None):
+        pxSetFrequencies(self.h, omega_ev, pol_mask, e0_au, alpha_ib)
+        self.n_omega = len(np.atleast_1d(omega_ev))
+        self.pol_mask = int(pol_mask)
+        self.ncol = self.n_omega * bin(pol_mask & 7).count("1")
+
+    def solve(self, precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
+              inner_reduction=1e-5, timings=False):
+        o = pxDefaultSolveOptions()
+        o.precision = int(precision)
+        o.restart_m = int(restart_m)
+        o.rel_tol = float(rel_tol)
+        o.max_cycles = int(max_cycles)
+        o.max_block_cols = int(max_block_cols)
+        o.inner_reduction = float(inner_reduction)
+        o.timings = int(bool(timings))
+        return pxSolveSpectrum(self.h, o)
+
+    def spectrum(self):
+        return pxGetSpectrum(self.h, self.n_omega)
+
+    def charges(self, i_omega, pol, with_dipoles=False):
+        return pxGetCharges(self.h, i_omega, pol, with_dipoles)
+
+    def stats(self):
+        return pxGetSolveStats(self.h, self.ncol)
+
+    def apply(self, precision, omega_ev, x, alpha_ib=None):
+        return pxApplyOperator(self.h, precision, omega_ev, x, alpha_ib)
+
+    def timings(self):
+        return pxGetTimings(self.h)
+
+    def close(self):
+        if self.h is not None:
+            pxDestroyStructure(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

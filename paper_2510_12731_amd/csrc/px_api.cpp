@@ -1,0 +1,765 @@
+// C ABI entry points and the blocked GMRES driver with FP64 iterative
+// refinement (plasmonX paper, Section 6: the "iterative on the fly" solver of
+// Eq. matrix-compact, here for all frequency/polarization columns at once).
+//
+// One restart cycle = m Arnoldi steps.  Each cycle starts from the true
+// residual r = b - A x recomputed in FP64 (FP64 T-apply + FP64 sparse apply),
+// so with PX_MIXED the cycle is the inner solve of an iterative-refinement
+// step whose T-apply runs in FP32 on MFMA, while orthogonalisation (CGS2),
+// the Givens least-squares update and the solution update stay in FP64.
+// Columns whose true relative residual reached rel_tol are retired at the next
+// cycle boundary and the active block is compacted, so the T-apply width
+// follows the number of unfinished columns.
+#include "px_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+constexpr double ANG_PER_BOHR = 0.529177210903;   // CODATA 2018
+constexpr double EV_PER_HARTREE = 27.211386245988;
+constexpr double PI = 3.14159265358979323846;
+// The solver works on Eq. (wfqfmu-system) with its dipole rows multiplied by
+// -1 (same solution, same residual norms); see k_spmm_shift.
+constexpr double SOLVER_MU_SIGN = -1.0;
+// A column is given up when this many consecutive cycles each removed less
+// than 2 % of its true residual (restarted GMRES at its rounding floor).
+constexpr int STALL_CYCLES = 5;
+
+thread_local std::string g_err;
+
+pxStatus fail(pxStatus st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+struct HipError {
+    hipError_t e;
+    const char* where;
+};
+
+inline void hcheck(hipError_t e, const char* where)
+{
+    if (e != hipSuccess) throw HipError{e, where};
+}
+
+#define HC(x) hcheck((x), #x)
+
+template <typename T>
+T* dalloc(size_t count)
+{
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    return static_cast<T*>(p);
+}
+
+inline void dfree(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+int pad_cols(int na, bool narrow_ok) { return (narrow_ok && na <= 4) ? na : ((na + px::COL_PAD - 1) / px::COL_PAD) * px::COL_PAD; }
+
+struct Workspace {
+    int lda_cap = 0, m_cap = 0;
+    int64_t nup = 0;
+    double2 *V = nullptr, *w = nullptr, *xs = nullptr, *rs = nullptr, *bs = nullptr, *tmp = nullptr;
+    float *X32 = nullptr, *Y32 = nullptr;
+    double* Y64 = nullptr;
+    double2* partial = nullptr;
+    double* npart = nullptr;
+    double2 *h1 = nullptr, *h2 = nullptr, *R = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
+    double *cs = nullptr, *nrm = nullptr, *target = nullptr;
+    int32_t *done = nullptr, *steps = nullptr, *map = nullptr;
+    double2 *zq = nullptr, *zmu = nullptr;
+    double* narrow = nullptr;
+    size_t narrow_bytes = 0;
+
+    void release()
+    {
+        void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, sn, gv, y, cs, nrm, target,
+                      done, steps, map, zq, zmu, narrow};
+        for (void* p : ps) dfree(p);
+        *this = Workspace();
+    }
+};
+
+}  // namespace
+
+struct pxStructure_t {
+    px::Geometry g;
+    pxModel model = PX_WFQ;
+    pxMaterial mat{};
+    double drude = 0.0;
+    hipStream_t st = nullptr;
+    std::vector<int32_t> perm;
+    int32_t* d_perm = nullptr;
+    // frequencies and columns (frequency-major: column = w * npol + p)
+    int n_omega = 0, npol = 0, ncol = 0, ldg = 0;
+    std::vector<double> omega_au;
+    std::vector<double> aib;   // 2 * n_omega
+    std::vector<int32_t> col_pol;
+    uint32_t pol_mask = 0;
+    double e0 = 0.0;
+    int32_t* d_col_pol = nullptr;
+    double* d_omega = nullptr;
+    double2* x = nullptr;   // [nup][ldg]
+    double2* b = nullptr;
+    std::vector<double> bnorm;
+    // results
+    bool solved = false;
+    std::vector<int32_t> iters, cycles, stall;
+    std::vector<double> relres, alpha, sigma;
+    // workspace and timings
+    Workspace ws;
+    // ms: total, T-apply FP32, T-apply FP64 inside cycles, sparse apply, Arnoldi+Givens, rest
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    // counts: FP32 T-apply launches, padded real columns, algorithmic real
+    // columns; the same three for the FP64 T-apply (cycles and residuals)
+    int64_t counts[6] = {0, 0, 0, 0, 0, 0};
+
+    ~pxStructure_t()
+    {
+        ws.release();
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, d_perm, d_col_pol, d_omega, x, b};
+        for (void* p : ps) dfree(p);
+    }
+};
+
+namespace {
+
+void ensure_workspace(pxStructure_t* s, int lda, int m)
+{
+    Workspace& W = s->ws;
+    const int64_t nup = s->g.nup;
+    if (W.lda_cap >= lda && W.m_cap >= m && W.nup == nup) return;
+    W.release();
+    const size_t vec = (size_t)nup * lda;
+    const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    W.V = dalloc<double2>((size_t)(m + 1) * vec);
+    W.w = dalloc<double2>(vec);
+    W.xs = dalloc<double2>(vec);
+    W.rs = dalloc<double2>(vec);
+    W.bs = dalloc<double2>(vec);
+    W.tmp = dalloc<double2>(vec);
+    W.X32 = dalloc<float>(2 * vec);
+    W.Y32 = dalloc<float>(2 * vec);
+    W.Y64 = dalloc<double>(2 * vec);
+    W.partial = dalloc<double2>((size_t)nchunk * (m + 1) * lda);
+    W.npart = dalloc<double>((size_t)nchunk * lda);
+    W.h1 = dalloc<double2>((size_t)(m + 1) * lda);
+    W.h2 = dalloc<double2>((size_t)(m + 1) * lda);
+    W.R = dalloc<double2>((size_t)m * (m + 1) * lda);
+    W.sn = dalloc<double2>((size_t)m * lda);
+    W.gv = dalloc<double2>((size_t)(m + 1) * lda);
+    W.y = dalloc<double2>((size_t)m * lda);
+    W.cs = dalloc<double>((size_t)m * lda);
+    W.nrm = dalloc<double>(lda);
+    W.target = dalloc<double>(lda);
+    W.done = dalloc<int32_t>(lda);
+    W.steps = dalloc<int32_t>(lda);
+    W.map = dalloc<int32_t>(lda);
+    W.zq = dalloc<double2>(lda);
+    W.zmu = dalloc<double2>(lda);
+    W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, 8);
+    W.narrow = dalloc<double>(W.narrow_bytes / sizeof(double) + 1);
+    W.lda_cap = lda;
+    W.m_cap = m;
+    W.nup = nup;
+    px::fill_zero(W.V, sizeof(double2) * (size_t)(m + 1) * vec, s->st);
+    px::fill_zero(W.X32, sizeof(float) * 2 * vec, s->st);
+}
+
+// z_q(omega) of Eq. (z_q_wfq) with the Drude weight n/m* (graphene: E_F/(pi t_g))
+void shift_q(const pxStructure_t* s, double w, double& zr, double& zi)
+{
+    const double pref = -w / (2.0 * s->drude * s->mat.tau);
+    zr = pref * w * s->mat.tau;
+    zi = pref;
+}
+
+// Eq. (z-mu): z_mu = -1 / alpha_IB
+void shift_mu(double ar, double ai, double& zr, double& zi)
+{
+    const double den = ar * ar + ai * ai;
+    zr = -ar / den;
+    zi = ai / den;
+}
+
+struct Timer {
+    bool on;
+    hipStream_t st;
+    hipEvent_t ev[8];
+    int n = 0;
+    Timer(bool on_, hipStream_t st_) : on(on_), st(st_)
+    {
+        if (on)
+            for (auto& e : ev) HC(hipEventCreate(&e));
+    }
+    ~Timer()
+    {
+        if (on)
+            for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(int i)
+    {
+        if (on) HC(hipEventRecord(ev[i], st));
+    }
+    float between(int a, int b)
+    {
+        float t = 0.f;
+        if (on) HC(hipEventElapsedTime(&t, ev[a], ev[b]));
+        return t;
+    }
+};
+
+// r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
+void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda)
+{
+    Workspace& W = s->ws;
+    px::tapply_f64(s->g, reinterpret_cast<const double*>(xs), W.Y64, 2 * lda, 2 * lda, s->st, W.narrow,
+                   W.narrow_bytes);
+    s->counts[3] += 1;
+    s->counts[4] += 2 * lda;
+    s->counts[5] += 2 * na;
+    px::spmm_shift(s->g, W.Y64, false, 2 * lda, xs, W.zq, W.zmu, bs, rs, na, lda, SOLVER_MU_SIGN, s->st);
+}
+
+void col_norms(pxStructure_t* s, const double2* v, int na, int lda, std::vector<double>& out)
+{
+    Workspace& W = s->ws;
+    const int nchunk = (int)((s->g.nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    px::col_norm_partial(v, W.npart, na, lda, s->g.nup, s->st);
+    px::reduce_norms(W.npart, nchunk, W.nrm, na, lda, s->st);
+    out.resize(na);
+    HC(hipMemcpyAsync(out.data(), W.nrm, sizeof(double) * na, hipMemcpyDeviceToHost, s->st));
+    HC(hipStreamSynchronize(s->st));
+}
+
+void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
+{
+    std::vector<double2> zq(lda, make_double2(0, 0)), zm(lda, make_double2(0, 0));
+    for (size_t k = 0; k < act.size(); ++k) {
+        const int c = act[k];
+        const int w = c / s->npol;
+        double zr, zi;
+        shift_q(s, s->omega_au[w], zr, zi);
+        zq[k] = make_double2(zr, zi);
+        if (s->model == PX_WFQFMU) {
+            shift_mu(s->aib[2 * w], s->aib[2 * w + 1], zr, zi);
+            zm[k] = make_double2(zr, zi);
+        }
+    }
+    HC(hipMemcpyAsync(s->ws.zq, zq.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+    HC(hipMemcpyAsync(s->ws.zmu, zm.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+}
+
+// Solves the columns in `cols` (global indices) as one block.
+void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
+{
+    Workspace& W = s->ws;
+    const int m = o.restart_m;
+    const int64_t nup = s->g.nup;
+    const bool mixed = o.precision == PX_MIXED;
+    const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    Timer tm(o.timings != 0, s->st);
+    std::vector<int32_t> done_h, steps_h;
+    std::vector<double> beta;
+
+    int na = (int)act.size();
+    int lda = pad_cols(na, true);
+    std::vector<int32_t> map(act.begin(), act.end());
+    HC(hipMemcpyAsync(W.map, map.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
+    px::gather_cols(s->x, s->ldg, W.xs, lda, W.map, na, nup, s->st);
+    px::gather_cols(s->b, s->ldg, W.bs, lda, W.map, na, nup, s->st);
+    upload_shifts(s, act, lda);
+
+    while (true) {
+        residual(s, W.xs, W.bs, W.rs, na, lda);
+        col_norms(s, W.rs, na, lda, beta);
+        std::vector<int> keep;
+        for (int k = 0; k < na; ++k) {
+            const int c = act[k];
+            const double prev = s->relres[c];
+            s->relres[c] = s->bnorm[c] > 0.0 ? beta[k] / s->bnorm[c] : 0.0;
+            if (s->cycles[c] > 0 && s->relres[c] > 0.98 * prev) s->stall[c] += 1;
+            else s->stall[c] = 0;
+            if (s->relres[c] > o.rel_tol && s->cycles[c] < o.max_cycles && s->stall[c] < STALL_CYCLES)
+                keep.push_back(k);
+        }
+        if (keep.empty()) break;
+        if ((int)keep.size() < na) {
+            // retire finished columns: compact the slot layout
+            const int na2 = (int)keep.size();
+            const int lda2 = pad_cols(na2, true);
+            std::vector<int32_t> smap(keep.begin(), keep.end());
+            HC(hipMemcpyAsync(W.map, smap.data(), sizeof(int32_t) * na2, hipMemcpyHostToDevice, s->st));
+            px::gather_cols(W.xs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            std::swap(W.xs, W.tmp);
+            px::gather_cols(W.rs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            std::swap(W.rs, W.tmp);
+            px::gather_cols(W.bs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            std::swap(W.bs, W.tmp);
+            std::vector<int> act2;
+            std::vector<double> beta2;
+            for (int k : keep) {
+                act2.push_back(act[k]);
+                beta2.push_back(beta[k]);
+            }
+            act.swap(act2);
+            beta.swap(beta2);
+            na = na2;
+            lda = lda2;
+            upload_shifts(s, act, lda);
+        }
+        // ---- one restart cycle ----
+        {
+            std::vector<double> tgt(lda, 0.0);
+            std::vector<double2> g0(lda, make_double2(0, 0));
+            for (int k = 0; k < na; ++k) {
+                const int c = act[k];
+                tgt[k] = std::max(0.5 * o.rel_tol * s->bnorm[c], mixed ? beta[k] * o.inner_reduction : 0.0);
+                g0[k] = make_double2(beta[k], 0.0);
+            }
+            HC(hipMemcpyAsync(W.target, tgt.data(), sizeof(double) * lda, hipMemcpyHostToDevice, s->st));
+            px::fill_zero(W.gv, sizeof(double2) * (size_t)(m + 1) * lda, s->st);
+            HC(hipMemcpyAsync(W.gv, g0.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+            px::fill_zero(W.done, sizeof(int32_t) * lda, s->st);
+            px::fill_zero(W.steps, sizeof(int32_t) * lda, s->st);
+            HC(hipMemcpyAsync(W.nrm, beta.data(), sizeof(double) * na, hipMemcpyHostToDevice, s->st));
+            const int64_t vstride = nup * lda;
+            px::normalize(W.rs, W.nrm, nullptr, W.V, mixed ? W.X32 : nullptr, na, lda, nup, s->st);
+            done_h.assign(na, 0);
+            for (int k = 0; k < m; ++k) {
+                double2* vk = W.V + k * vstride;
+                tm.mark(0);
+                const bool wide32 = mixed && lda > 4;
+                if (wide32) {
+                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st);
+                    s->counts[0] += 1;
+                    s->counts[1] += 2 * lda;
+                    s->counts[2] += 2 * na;
+                } else {
+                    px::tapply_f64(s->g, reinterpret_cast<const double*>(vk), W.Y64, 2 * lda, 2 * lda, s->st,
+                                   W.narrow, W.narrow_bytes);
+                    s->counts[3] += 1;
+                    s->counts[4] += 2 * lda;
+                    s->counts[5] += 2 * na;
+                }
+                tm.mark(1);
+                px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
+                               W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st);
+                tm.mark(2);
+                // CGS2 against v_0..v_k
+                px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                px::reduce_dots(W.partial, nchunk, k + 1, W.h1, na, lda, false, s->st);
+                px::col_update(W.V, vstride, k + 1, W.h1, W.w, nullptr, na, lda, nup, s->st);
+                px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
+                px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
+                px::reduce_norms(W.npart, nchunk, W.nrm, na, lda, s->st);
+                px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, nullptr,
+                                na, lda, s->st);
+                px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride, mixed ? W.X32 : nullptr, na, lda, nup,
+                              s->st);
+                tm.mark(3);
+                HC(hipMemcpyAsync(done_h.data(), W.done, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
+                HC(hipStreamSynchronize(s->st));
+                if (tm.on) {
+                    s->ms[wide32 ? 1 : 2] += tm.between(0, 1);
+                    s->ms[3] += tm.between(1, 2);
+                    s->ms[4] += tm.between(2, 3);
+                }
+                bool all = true;
+                for (int q = 0; q < na; ++q) all = all && done_h[q];
+                if (all) break;
+            }
+            px::lsq_solve(m, W.R, W.gv, W.steps, W.y, na, lda, s->st);
+            px::x_update(W.V, vstride, W.y, W.steps, m, W.xs, na, lda, nup, s->st);
+            steps_h.assign(na, 0);
+            HC(hipMemcpyAsync(steps_h.data(), W.steps, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
+            HC(hipMemcpyAsync(W.map, act.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
+            px::scatter_cols(W.xs, lda, s->x, s->ldg, W.map, na, nup, s->st);
+            HC(hipStreamSynchronize(s->st));
+            for (int k = 0; k < na; ++k) {
+                s->iters[act[k]] += steps_h[k];
+                s->cycles[act[k]] += 1;
+            }
+        }
+    }
+}
+
+pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
+{
+    if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrum: call pxSetFrequencies first");
+    if (o.restart_m < 1 || o.restart_m > 1000) return fail(PX_E_INVALID, "restart_m must be in [1, 1000]");
+    if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
+        (o.precision != PX_FP64 && o.precision != PX_MIXED))
+        return fail(PX_E_INVALID, "invalid solve options");
+    auto t0 = std::chrono::steady_clock::now();
+    for (double& v : s->ms) v = 0.0;
+    for (int64_t& v : s->counts) v = 0;
+    const int ncol = s->ncol;
+    const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
+    ensure_workspace(s, pad_cols(blk, true), o.restart_m);
+    const int64_t nup = s->g.nup;
+    // right-hand sides, x = 0, ||b||
+    px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    px::fill_zero(s->x, sizeof(double2) * (size_t)nup * s->ldg, s->st);
+    {
+        std::vector<double> bn;
+        // reuse the norm kernels over the global layout in slices of the workspace width
+        s->bnorm.assign(ncol, 0.0);
+        const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+        double* part = dalloc<double>((size_t)nchunk * s->ldg);
+        double* nr = dalloc<double>(s->ldg);
+        px::col_norm_partial(s->b, part, ncol, s->ldg, nup, s->st);
+        px::reduce_norms(part, nchunk, nr, ncol, s->ldg, s->st);
+        HC(hipMemcpyAsync(s->bnorm.data(), nr, sizeof(double) * ncol, hipMemcpyDeviceToHost, s->st));
+        HC(hipStreamSynchronize(s->st));
+        dfree(part);
+        dfree(nr);
+    }
+    s->iters.assign(ncol, 0);
+    s->cycles.assign(ncol, 0);
+    s->stall.assign(ncol, 0);
+    s->relres.assign(ncol, 0.0);
+    for (int c0 = 0; c0 < ncol; c0 += blk) {
+        std::vector<int> cols;
+        for (int c = c0; c < std::min(ncol, c0 + blk); ++c) cols.push_back(c);
+        run_block(s, cols, o);
+    }
+    // observables (Section 7)
+    {
+        const int nchunk = (int)((s->g.n + px::RED_ROWS - 1) / px::RED_ROWS);
+        double2* dpart = dalloc<double2>((size_t)nchunk * 3 * s->ldg);
+        double2* d = dalloc<double2>((size_t)3 * ncol);
+        double2* al = dalloc<double2>((size_t)9 * s->n_omega);
+        double* sg = dalloc<double>(s->n_omega);
+        px::observables(s->g, s->x, ncol, s->ldg, dpart, d, s->st);
+        px::spectrum(d, s->d_col_pol, s->n_omega, s->npol, s->d_omega, s->e0, al, sg, s->st);
+        s->alpha.assign((size_t)18 * s->n_omega, 0.0);
+        s->sigma.assign(s->n_omega, 0.0);
+        HC(hipMemcpyAsync(s->alpha.data(), al, sizeof(double2) * 9 * s->n_omega, hipMemcpyDeviceToHost, s->st));
+        HC(hipMemcpyAsync(s->sigma.data(), sg, sizeof(double) * s->n_omega, hipMemcpyDeviceToHost, s->st));
+        HC(hipStreamSynchronize(s->st));
+        dfree(dpart);
+        dfree(d);
+        dfree(al);
+        dfree(sg);
+    }
+    s->solved = true;
+    s->ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    s->ms[5] = s->ms[0] - s->ms[1] - s->ms[2] - s->ms[3] - s->ms[4];
+    for (int c = 0; c < ncol; ++c)
+        if (!(s->relres[c] <= o.rel_tol)) return fail(PX_E_NOTCONV, "some columns did not reach rel_tol");
+    return PX_OK;
+}
+
+bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+template <typename F>
+pxStatus guarded(F&& f)
+{
+    try {
+        return f();
+    } catch (const HipError& h) {
+        return fail(h.e == hipErrorOutOfMemory ? PX_E_OOM : PX_E_DEVICE,
+                    std::string(h.where) + ": " + hipGetErrorString(h.e));
+    } catch (const std::bad_alloc&) {
+        return fail(PX_E_OOM, "host allocation failed");
+    } catch (...) {
+        return fail(PX_E_DEVICE, "unexpected exception");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void pxDefaultSolveOptions(pxSolveOptions* o)
+{
+    if (!o) return;
+    o->precision = PX_MIXED;
+    o->restart_m = 50;
+    o->rel_tol = 1e-8;
+    o->max_cycles = 400;
+    o->max_block_cols = 0;
+    o->inner_reduction = 1e-5;
+    o->timings = 0;
+}
+
+const char* pxLastError(void) { return g_err.c_str(); }
+
+pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang, const pxMaterial* mat,
+                           void* hip_stream, pxStructure* out)
+{
+    g_err.clear();
+    if (!out || !xyz_ang || !mat) return fail(PX_E_INVALID, "null argument");
+    *out = nullptr;
+    if (model != PX_WFQ && model != PX_WFQFMU) return fail(PX_E_INVALID, "unknown model");
+    if (n_atoms < 1 || n_atoms > (int64_t)1 << 28) return fail(PX_E_INVALID, "n_atoms out of range");
+    for (int64_t i = 0; i < n_atoms; ++i)
+        if (!finite3(xyz_ang + 3 * i)) return fail(PX_E_INVALID, "non-finite coordinate");
+    const pxMaterial& m = *mat;
+    double drude = m.fermi_energy_ev > 0.0 ? (m.fermi_energy_ev / EV_PER_HARTREE) / (PI * m.sheet_thickness)
+                                           : m.density / m.eff_mass;
+    if (!(m.a_eff > 0) || !(m.r_q > 0) || !(m.tau > 0) || !(drude > 0) || !std::isfinite(drude) || !(m.r0_ang > 0) ||
+        !(m.cutoff_ang > 0) || !(m.fermi_s > 0) || !std::isfinite(m.fermi_d))
+        return fail(PX_E_INVALID, "invalid material parameters");
+    if (model == PX_WFQFMU && !(m.r_mu > 0)) return fail(PX_E_INVALID, "r_mu must be > 0 for the dipole model");
+    return guarded([&]() -> pxStatus {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        HC(hipGetDevice(&dev));
+        HC(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(PX_E_DEVICE, std::string("built for gfx950, device is ") + prop.gcnArchName);
+        auto* s = new pxStructure_t();
+        s->model = model;
+        s->mat = m;
+        s->drude = drude;
+        s->st = static_cast<hipStream_t>(hip_stream);
+        s->g.model = (int)model;
+        s->g.n = n_atoms;
+        s->g.np = ((n_atoms + px::ATOM_PAD - 1) / px::ATOM_PAD) * px::ATOM_PAD;
+        s->g.nu = model == PX_WFQFMU ? 4 * n_atoms : n_atoms;
+        s->g.nup = model == PX_WFQFMU ? 4 * s->g.np : s->g.np;
+        s->g.r_q = m.r_q;
+        s->g.r_mu = m.r_mu;
+        std::vector<double> xb(3 * n_atoms);
+        for (int64_t i = 0; i < 3 * n_atoms; ++i) xb[i] = xyz_ang[i] / ANG_PER_BOHR;
+        int bad = 0;
+        hipError_t e = px::build_geometry(s->g, xb.data(), m.cutoff_ang / ANG_PER_BOHR, m, m.r0_ang / ANG_PER_BOHR,
+                                          s->perm, &bad, s->st);
+        if (e != hipSuccess) {
+            delete s;
+            throw HipError{e, "build_geometry"};
+        }
+        if (bad) {
+            delete s;
+            return fail(PX_E_INVALID, "two atoms closer than 1e-6 Angstrom");
+        }
+        try {
+            s->d_perm = dalloc<int32_t>(n_atoms);
+            HC(hipMemcpyAsync(s->d_perm, s->perm.data(), sizeof(int32_t) * n_atoms, hipMemcpyHostToDevice, s->st));
+            HC(hipStreamSynchronize(s->st));
+        } catch (...) {
+            delete s;
+            throw;
+        }
+        *out = s;
+        return PX_OK;
+    });
+}
+
+pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask, double e0_au,
+                          const double* alpha_ib)
+{
+    g_err.clear();
+    if (!s || !omega_ev) return fail(PX_E_INVALID, "null argument");
+    if (n_omega < 1) return fail(PX_E_INVALID, "n_omega must be >= 1");
+    if ((pol_mask & 7u) == 0 || (pol_mask & ~7u)) return fail(PX_E_INVALID, "pol_mask must be a non-empty subset of 0b111");
+    if (!(e0_au > 0) || !std::isfinite(e0_au)) return fail(PX_E_INVALID, "e0 must be > 0");
+    for (int w = 0; w < n_omega; ++w)
+        if (!(omega_ev[w] > 0) || !std::isfinite(omega_ev[w])) return fail(PX_E_INVALID, "frequencies must be > 0");
+    if (s->model == PX_WFQFMU) {
+        if (!alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
+        for (int w = 0; w < n_omega; ++w)
+            if (!std::isfinite(alpha_ib[2 * w]) || !std::isfinite(alpha_ib[2 * w + 1]) ||
+                (alpha_ib[2 * w] == 0.0 && alpha_ib[2 * w + 1] == 0.0))
+                return fail(PX_E_INVALID, "alpha_ib must be finite and non-zero");
+    }
+    return guarded([&]() -> pxStatus {
+        s->solved = false;
+        s->n_omega = n_omega;
+        s->pol_mask = pol_mask;
+        s->npol = __builtin_popcount(pol_mask);
+        s->ncol = n_omega * s->npol;
+        s->ldg = ((s->ncol + px::COL_PAD - 1) / px::COL_PAD) * px::COL_PAD;
+        s->e0 = e0_au;
+        s->omega_au.resize(n_omega);
+        for (int w = 0; w < n_omega; ++w) s->omega_au[w] = omega_ev[w] / EV_PER_HARTREE;
+        s->aib.assign(2 * n_omega, 0.0);
+        if (s->model == PX_WFQFMU) std::copy(alpha_ib, alpha_ib + 2 * n_omega, s->aib.begin());
+        s->col_pol.clear();
+        for (int w = 0; w < n_omega; ++w)
+            for (int l = 0; l < 3; ++l)
+                if (pol_mask & (1u << l)) s->col_pol.push_back(l);
+        dfree(s->d_col_pol);
+        dfree(s->d_omega);
+        dfree(s->x);
+        dfree(s->b);
+        s->d_col_pol = nullptr;
+        s->d_omega = nullptr;
+        s->x = s->b = nullptr;
+        s->d_col_pol = dalloc<int32_t>(s->ncol);
+        s->d_omega = dalloc<double>(n_omega);
+        s->x = dalloc<double2>((size_t)s->g.nup * s->ldg);
+        s->b = dalloc<double2>((size_t)s->g.nup * s->ldg);
+        HC(hipMemcpyAsync(s->d_col_pol, s->col_pol.data(), sizeof(int32_t) * s->ncol, hipMemcpyHostToDevice, s->st));
+        HC(hipMemcpyAsync(s->d_omega, s->omega_au.data(), sizeof(double) * n_omega, hipMemcpyHostToDevice, s->st));
+        HC(hipStreamSynchronize(s->st));
+        return PX_OK;
+    });
+}
+
+pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    pxSolveOptions o;
+    pxDefaultSolveOptions(&o);
+    if (opt) o = *opt;
+    return guarded([&]() -> pxStatus { return solve_impl(s, o); });
+}
+
+pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* opt)
+{
+    g_err.clear();
+    if (!ss || n < 0) return fail(PX_E_INVALID, "null argument");
+    pxStatus worst = PX_OK;
+    for (int32_t k = 0; k < n; ++k) {
+        pxStatus st = pxSolveSpectrum(ss[k], opt);
+        if (st != PX_OK && st != PX_E_NOTCONV) return st;
+        if (st == PX_E_NOTCONV) worst = st;
+    }
+    return worst;
+}
+
+pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, double* mu)
+{
+    g_err.clear();
+    if (!s || !q) return fail(PX_E_INVALID, "null argument");
+    if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
+    if (i_omega < 0 || i_omega >= s->n_omega || pol < 0 || pol > 2 || !(s->pol_mask & (1u << pol)))
+        return fail(PX_E_INVALID, "column not in the solved set");
+    int p = 0;
+    for (int l = 0; l < pol; ++l)
+        if (s->pol_mask & (1u << l)) ++p;
+    const int col = i_omega * s->npol + p;
+    return guarded([&]() -> pxStatus {
+        const int ncomp = s->model == PX_WFQFMU ? 4 : 1;
+        double2* d = dalloc<double2>((size_t)ncomp * s->g.n);
+        px::unpermute(s->g, s->x, s->ldg, col, s->d_perm, d, s->st);
+        std::vector<double> h((size_t)2 * ncomp * s->g.n);
+        HC(hipMemcpyAsync(h.data(), d, sizeof(double2) * ncomp * s->g.n, hipMemcpyDeviceToHost, s->st));
+        HC(hipStreamSynchronize(s->st));
+        dfree(d);
+        std::copy(h.begin(), h.begin() + 2 * s->g.n, q);
+        if (mu && ncomp == 4) std::copy(h.begin() + 2 * s->g.n, h.end(), mu);
+        return PX_OK;
+    });
+}
+
+pxStatus pxGetSpectrum(pxStructure s, double* alpha, double* sigma_abs)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
+    if (alpha) std::copy(s->alpha.begin(), s->alpha.end(), alpha);
+    if (sigma_abs) std::copy(s->sigma.begin(), s->sigma.end(), sigma_abs);
+    return PX_OK;
+}
+
+pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, double* rel_res)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
+    if (iterations) std::copy(s->iters.begin(), s->iters.end(), iterations);
+    if (cycles) std::copy(s->cycles.begin(), s->cycles.end(), cycles);
+    if (rel_res) std::copy(s->relres.begin(), s->relres.end(), rel_res);
+    return PX_OK;
+}
+
+pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const double* omega_ev,
+                         const double* alpha_ib, const double* x, double* y)
+{
+    g_err.clear();
+    if (!s || !omega_ev || !x || !y) return fail(PX_E_INVALID, "null argument");
+    if (ncol < 1) return fail(PX_E_INVALID, "ncol must be >= 1");
+    if (precision != PX_FP64 && precision != PX_MIXED) return fail(PX_E_INVALID, "unknown precision");
+    if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
+    for (int c = 0; c < ncol; ++c)
+        if (!(omega_ev[c] > 0)) return fail(PX_E_INVALID, "frequencies must be > 0");
+    return guarded([&]() -> pxStatus {
+        const bool mixed = precision == PX_MIXED;
+        const int lda = pad_cols(ncol, !mixed);
+        ensure_workspace(s, std::max(lda, s->ws.lda_cap), std::max(1, s->ws.m_cap));
+        Workspace& W = s->ws;
+        const int64_t nu = s->g.nu, nup = s->g.nup;
+        double2* din = dalloc<double2>((size_t)ncol * nu);
+        HC(hipMemcpyAsync(din, x, sizeof(double2) * ncol * nu, hipMemcpyHostToDevice, s->st));
+        px::permute_in(s->g, din, ncol, s->d_perm, W.xs, lda, s->st);
+        std::vector<double2> zq(lda, make_double2(0, 0)), zm(lda, make_double2(0, 0));
+        for (int c = 0; c < ncol; ++c) {
+            double zr, zi;
+            shift_q(s, omega_ev[c] / EV_PER_HARTREE, zr, zi);
+            zq[c] = make_double2(zr, zi);
+            if (s->model == PX_WFQFMU) {
+                shift_mu(alpha_ib[2 * c], alpha_ib[2 * c + 1], zr, zi);
+                zm[c] = make_double2(zr, zi);
+            }
+        }
+        HC(hipMemcpyAsync(W.zq, zq.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+        HC(hipMemcpyAsync(W.zmu, zm.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+        if (mixed) {
+            px::to_f32(W.xs, W.X32, ncol, lda, nup, s->st);
+            px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st);
+            px::spmm_shift(s->g, W.Y32, true, 2 * lda, W.xs, W.zq, W.zmu, nullptr, W.w, ncol, lda, 1.0, s->st);
+        } else {
+            px::tapply_f64(s->g, reinterpret_cast<const double*>(W.xs), W.Y64, 2 * lda, 2 * lda, s->st, W.narrow,
+                           W.narrow_bytes);
+            px::spmm_shift(s->g, W.Y64, false, 2 * lda, W.xs, W.zq, W.zmu, nullptr, W.w, ncol, lda, 1.0, s->st);
+        }
+        const int ncomp = s->model == PX_WFQFMU ? 4 : 1;
+        double2* dout = dalloc<double2>((size_t)ncol * nu);
+        for (int c = 0; c < ncol; ++c) px::unpermute(s->g, W.w, lda, c, s->d_perm, dout + (size_t)c * nu, s->st);
+        (void)ncomp;
+        HC(hipMemcpyAsync(y, dout, sizeof(double2) * ncol * nu, hipMemcpyDeviceToHost, s->st));
+        HC(hipStreamSynchronize(s->st));
+        dfree(din);
+        dfree(dout);
+        return PX_OK;
+    });
+}
+
+pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    if (n_atoms) *n_atoms = s->g.n;
+    if (n_unknowns) *n_unknowns = s->g.nu;
+    return PX_OK;
+}
+
+pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    if (ms6) std::copy(s->ms, s->ms + 6, ms6);
+    if (counts6) std::copy(s->counts, s->counts + 6, counts6);
+    return PX_OK;
+}
+
+void pxDestroyStructure(pxStructure s)
+{
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    else (void)hipDeviceSynchronize();
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations of the HIP solver library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "plasmonx.h"
+
+namespace px {
+
+// Atom padding: every device vector holds np >= n rows per component; rows
+// n..np-1 belong to ghost atoms parked far away with zero unknowns.
+constexpr int ATOM_PAD = 256;
+// Atoms per bounding-box group used by the near/far split of the T-apply.
+constexpr int GROUP = 32;
+// Complex columns of every active block are padded to a multiple of this.
+constexpr int COL_PAD = 64;
+// Rows per partial-sum chunk of the column reductions (dots, norms).
+constexpr int RED_ROWS = 64;
+
+struct Geometry {
+    int model = 0;         // 0 omegaFQ, 1 omegaFQFmu
+    int64_t n = 0;         // real atoms
+    int64_t np = 0;        // padded atoms
+    int64_t nu = 0;        // unknowns (n or 4n)
+    int64_t nup = 0;       // padded unknown rows (np or 4np)
+    float4* xyz32 = nullptr;   // [np] bohr, Morton order, ghosts far away
+    double4* xyz64 = nullptr;  // [np]
+    float4* glo = nullptr;     // [np/GROUP] group bounding boxes (conservative)
+    float4* ghi = nullptr;
+    // CSR of Kbar over the n real atoms (FP64 values, diagonal included)
+    int32_t* row_ptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    int64_t nnz = 0;
+    // kernel constants (bohr)
+    double r_q = 0, r_mu = 0;
+};
+
+// ---- T-apply launchers (px_tapply.hip) -------------------------------------
+// Y = T X over real columns: X, Y are [nup][ldx] (row-major, component-major
+// blocks for the dipole model); ncols real columns, multiple of 2*COL_PAD for
+// the wide kernels.  Ghost rows of Y are unspecified.
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st);
+void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
+                double* scratch, size_t scratch_bytes);
+size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
+
+// ---- other kernels (px_kernels.hip) ----------------------------------------
+hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
+                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st);
+
+struct Shifts {            // per active slot
+    double2* zq = nullptr;
+    double2* zmu = nullptr;
+};
+
+// mu_sign: +1 gives the paper's operator, -1 the solver's form with negated dipole rows.
+void spmm_shift(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* zq,
+                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st);
+void build_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, double mu_sign,
+               hipStream_t st);
+void col_dots(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
+              int64_t nup, hipStream_t st);
+void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int na, int lda, bool accumulate,
+                 hipStream_t st);
+void col_update(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
+                int na, int lda, int64_t nup, hipStream_t st);
+void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st);
+void col_norm_partial(const double2* w, double* partial, int na, int lda, int64_t nup, hipStream_t st);
+void normalize(const double2* w, const double* nrm, const int32_t* done, double2* v, float* x32, int na, int lda,
+               int64_t nup, hipStream_t st);
+void to_f32(const double2* v, float* x32, int na, int lda, int64_t nup, hipStream_t st);
+void givens_step(int k, int m, const double2* h1, const double2* h2, const double* nrm, double2* R, double* cs,
+                 double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps, int32_t* n_open,
+                 int na, int lda, hipStream_t st);
+void lsq_solve(int m, const double2* R, const double2* gvec, const int32_t* steps, double2* y, int na, int lda,
+               hipStream_t st);
+void x_update(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, int m, double2* x,
+              int na, int lda, int64_t nup, hipStream_t st);
+void gather_cols(const double2* src, int lds, double2* dst, int ldd, const int32_t* map, int na, int64_t nup,
+                 hipStream_t st);
+void scatter_cols(const double2* src, int lds, double2* dst, int ldd, const int32_t* map, int na, int64_t nup,
+                  hipStream_t st);
+void observables(const Geometry& g, const double2* x, int ncol, int ldx, double2* dpart, double2* d,
+                 hipStream_t st);
+void spectrum(const double2* d, const int32_t* col_pol, int n_omega, int npol, const double* omega_au, double e0,
+              double2* alpha, double* sigma, hipStream_t st);
+void unpermute(const Geometry& g, const double2* x, int ldx, int col, const int32_t* perm, double2* out,
+               hipStream_t st);
+void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* perm, double2* x, int ldx,
+                hipStream_t st);
+void fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace px

@@ -1,0 +1,882 @@
+// Geometry set-up, sparse Kbar, and the column-blocked Krylov kernels.
+//
+// Column conventions: a block of na complex columns is stored row-major as
+// double2 [rows][lda] (lda >= na, padded columns kept at zero), so every
+// per-column operation is a coalesced sweep over consecutive columns.  Column
+// reductions (dot products, norms, dipoles) use a fixed chunking of the rows
+// and a fixed summation order, so a column's arithmetic never depends on which
+// other columns share the block.
+#include "px_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace px {
+namespace {
+
+constexpr double TWO_PI = 6.283185307179586;
+constexpr double C_LIGHT = 137.035999084;   // speed of light, a.u. (CODATA 2018)
+constexpr double ANG = 0.529177210903;       // Angstrom per bohr (CODATA 2018)
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b)   // conj(a) * b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// ---------------------------------------------------------------- geometry
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(const double* __restrict__ xyz, int64_t n, int64_t npow, double3 lo, double3 scale,
+                         uint64_t* __restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow) return;
+    if (i >= n) {
+        keys[i] = ~0ull;
+        return;
+    }
+    uint32_t qx = (uint32_t)fmin(1023.0, fmax(0.0, (xyz[3 * i] - lo.x) * scale.x));
+    uint32_t qy = (uint32_t)fmin(1023.0, fmax(0.0, (xyz[3 * i + 1] - lo.y) * scale.y));
+    uint32_t qz = (uint32_t)fmin(1023.0, fmax(0.0, (xyz[3 * i + 2] - lo.z) * scale.z));
+    uint32_t code = spread10(qx) | (spread10(qy) << 1) | (spread10(qz) << 2);
+    keys[i] = ((uint64_t)code << 32) | (uint64_t)i;
+}
+
+__global__ void k_bitonic(uint64_t* __restrict__ a, uint32_t j, uint32_t k, uint32_t npow)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow) return;
+    uint32_t l = i ^ j;
+    if (l > i) {
+        bool up = (i & k) == 0;
+        uint64_t x = a[i], y = a[l];
+        if ((x > y) == up) {
+            a[i] = y;
+            a[l] = x;
+        }
+    }
+}
+
+// Sorted coordinates; ghosts (rows n..np-1) parked on a far line, 50 bohr apart.
+__global__ void k_gather_sorted(const double* __restrict__ xyz, const uint64_t* __restrict__ keys, int64_t n,
+                                int64_t np, double3 far0, int32_t* __restrict__ perm, double4* __restrict__ x64,
+                                float4* __restrict__ x32)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    double4 p;
+    if (i < n) {
+        int64_t o = (int64_t)(keys[i] & 0xffffffffull);
+        perm[i] = (int32_t)o;
+        p = make_double4(xyz[3 * o], xyz[3 * o + 1], xyz[3 * o + 2], 0.0);
+    } else {
+        p = make_double4(far0.x + 50.0 * (double)(i - n), far0.y, far0.z, 0.0);
+    }
+    x64[i] = p;
+    x32[i] = make_float4((float)p.x, (float)p.y, (float)p.z, 0.0f);
+}
+
+// Conservative FP32 bounding box of every group of GROUP atoms.
+__global__ void k_group_bbox(const double4* __restrict__ x64, int64_t ngroups, float4* __restrict__ lo,
+                             float4* __restrict__ hi)
+{
+    int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= ngroups) return;
+    double l[3] = {1e300, 1e300, 1e300}, h[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < GROUP; ++k) {
+        double4 p = x64[gi * GROUP + k];
+        l[0] = fmin(l[0], p.x); l[1] = fmin(l[1], p.y); l[2] = fmin(l[2], p.z);
+        h[0] = fmax(h[0], p.x); h[1] = fmax(h[1], p.y); h[2] = fmax(h[2], p.z);
+    }
+    const double pad = 1e-3;
+    lo[gi] = make_float4((float)(l[0] - pad), (float)(l[1] - pad), (float)(l[2] - pad), 0.f);
+    hi[gi] = make_float4((float)(h[0] + pad), (float)(h[1] + pad), (float)(h[2] + pad), 0.f);
+}
+
+struct KappaConst {
+    double a_eff, fd, s_r0, rc, rc2, min_r;
+};
+
+// Eqs. (fermi), (kappa): K_ij = [1 - f(r)] A / r for r <= cutoff.
+__device__ __forceinline__ double kappa_val(double r, const KappaConst& k)
+{
+    double f = 1.0 / (1.0 + exp(-k.fd * (r / k.s_r0 - 1.0)));
+    return (1.0 - f) * k.a_eff / r;
+}
+
+__device__ __forceinline__ float gap2(float4 alo, float4 ahi, float4 blo, float4 bhi)
+{
+    float dx = fmaxf(0.0f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
+    float dy = fmaxf(0.0f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
+    float dz = fmaxf(0.0f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Neighbour search over the real atoms, one thread per row atom.  Pass 0
+// counts (row length incl. the diagonal) and flags coincident atoms; pass 1
+// fills columns in increasing order with Kbar_ii = -sum_k K_ik in place.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
+                                                   const float4* __restrict__ ghi, int64_t n, int64_t np,
+                                                   KappaConst kc, int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                   double* __restrict__ val, int* __restrict__ bad)
+{
+    __shared__ double4 sp[GROUP];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    const int64_t g0 = ((int64_t)blockIdx.x * 256) / GROUP;
+    // box of this block's 256 rows (8 groups)
+    float4 blo = glo[g0], bhi = ghi[g0];
+    for (int q = 1; q < 256 / GROUP; ++q) {
+        float4 a = glo[g0 + q], b = ghi[g0 + q];
+        blo = make_float4(fminf(blo.x, a.x), fminf(blo.y, a.y), fminf(blo.z, a.z), 0.f);
+        bhi = make_float4(fmaxf(bhi.x, b.x), fmaxf(bhi.y, b.y), fmaxf(bhi.z, b.z), 0.f);
+    }
+    const double4 pi = x64[i];
+    const float lim = (float)(kc.rc * 1.0001 + 1e-3);
+    const int64_t ngroups = (n + GROUP - 1) / GROUP;
+    int count = 0;
+    double ksum = 0.0;
+    int64_t out = 0;
+    bool diag_done = false;
+    if (PASS == 1 && i < n) {
+        out = row_ptr[i];
+        // Kbar_ii needs the full row sum first
+        for (int64_t gq = 0; gq < ngroups; ++gq) {
+            if (gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;
+            for (int k = 0; k < GROUP; ++k) {
+                int64_t j = gq * GROUP + k;
+                if (j >= n || j == i) continue;
+                double4 pj = x64[j];
+                double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                if (r <= kc.rc) ksum += kappa_val(r, kc);
+            }
+        }
+    }
+    for (int64_t gq = 0; gq < ngroups; ++gq) {
+        if (gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;   // uniform over the block
+        __syncthreads();
+        if (tid < GROUP) sp[tid] = x64[gq * GROUP + tid];
+        __syncthreads();
+        if (i >= n) continue;
+        for (int k = 0; k < GROUP; ++k) {
+            int64_t j = gq * GROUP + k;
+            if (j >= n) break;
+            if (PASS == 1 && !diag_done && j > i) {
+                col[out] = (int32_t)i;
+                val[out] = -ksum;
+                ++out;
+                diag_done = true;
+            }
+            if (j == i) continue;
+            double4 pj = sp[k];
+            double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (PASS == 0 && r < kc.min_r) *bad = 1;
+            if (r <= kc.rc) {
+                if (PASS == 0) {
+                    ++count;
+                } else {
+                    col[out] = (int32_t)j;
+                    val[out] = kappa_val(r, kc);
+                    ++out;
+                }
+            }
+        }
+    }
+    if (i < n) {
+        if (PASS == 0) cnt[i] = count + 1;
+        if (PASS == 1 && !diag_done) {
+            col[out] = (int32_t)i;
+            val[out] = -ksum;
+        }
+    }
+}
+
+// Exclusive scan of cnt[0..n) into row_ptr[0..n], single workgroup.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ cnt, int64_t n,
+                                               int32_t* __restrict__ row_ptr)
+{
+    __shared__ int32_t s[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        int32_t v = (i < n) ? cnt[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < n) row_ptr[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += s[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row_ptr[n] = carry;
+}
+
+// ---------------------------------------------------------------- sparse
+
+// W = S [diag(Kbar, I) Y - diag(z_q, z_mu) X]        (mode B == nullptr)
+// W = B - S [diag(Kbar, I) Y - diag(z_q, z_mu) X]    (residual mode)
+// with S = diag(I, mu_sign I): the solver negates the dipole rows (mu_sign =
+// -1), which leaves solution and residual norms unchanged and makes
+// diag(Kbar, -I) T similar to a symmetric negative semidefinite matrix, so
+// both diagonal shifts push every eigenvalue into the upper half plane.
+// Y: real [nup][ldy] (FP32 or FP64), complex column c = real columns (2c, 2c+1).
+template <typename TY>
+__global__ __launch_bounds__(256) void k_spmm_shift(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                    const double* __restrict__ cv, const TY* __restrict__ Y, int ldy,
+                                                    const double2* __restrict__ X, const double2* __restrict__ zq,
+                                                    const double2* __restrict__ zmu,
+                                                    const double2* __restrict__ B, double2* __restrict__ W,
+                                                    int64_t n, int64_t np, int64_t nup, int na, int lda,
+                                                    double mu_sign)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= lda) return;
+    const size_t o = (size_t)r * lda + c;
+    const int64_t comp = r / np, i = r - comp * np;
+    if (c >= na || i >= n) {
+        W[o] = make_double2(0.0, 0.0);
+        return;
+    }
+    double ar = 0.0, ai = 0.0;
+    double2 z;
+    if (comp == 0) {
+        const int32_t e1 = rp[i + 1];
+        for (int32_t e = rp[i]; e < e1; ++e) {
+            const double k = cv[e];
+            const TY* yr = Y + (size_t)ci[e] * ldy + 2 * c;
+            ar = fma(k, (double)yr[0], ar);
+            ai = fma(k, (double)yr[1], ai);
+        }
+        z = zq[c];
+    } else {
+        const TY* yr = Y + (size_t)r * ldy + 2 * c;
+        ar = (double)yr[0];
+        ai = (double)yr[1];
+        z = zmu[c];
+    }
+    const double2 x = X[o];
+    double2 w = make_double2(ar - (z.x * x.x - z.y * x.y), ai - (z.x * x.y + z.y * x.x));
+    if (comp != 0) w = make_double2(mu_sign * w.x, mu_sign * w.y);
+    if (B != nullptr) {
+        const double2 b = B[o];
+        w = make_double2(b.x - w.x, b.y - w.y);
+    }
+    W[o] = w;
+}
+
+// b = E0 Kbar r_l (charge rows) and mu_sign E0 e_l (dipole rows) for column c
+// with polarization col_pol[c]: the right-hand side -Kbar V, V_i = -E0 r_i.l,
+// and the field E (dipole rows scaled like the operator's, see k_spmm_shift).
+__global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                             const double* __restrict__ cv, const double4* __restrict__ x64,
+                                             const int32_t* __restrict__ col_pol, double e0, double2* __restrict__ b,
+                                             int64_t n, int64_t np, int64_t nup, int ncol, int ldb, double mu_sign)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= ldb) return;
+    const size_t o = (size_t)r * ldb + c;
+    const int64_t comp = r / np, i = r - comp * np;
+    if (c >= ncol || i >= n) {
+        b[o] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int l = col_pol[c];
+    double v = 0.0;
+    if (comp == 0) {
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const double4 p = x64[ci[e]];
+            const double coord = (l == 0) ? p.x : (l == 1) ? p.y : p.z;
+            v = fma(cv[e], coord, v);
+        }
+        v *= e0;
+    } else {
+        v = (comp - 1 == l) ? mu_sign * e0 : 0.0;
+    }
+    b[o] = make_double2(v, 0.0);
+}
+
+// ---------------------------------------------------------------- Arnoldi
+
+// partial[chunk][j][c] = sum over the chunk's rows of conj(V_j[r][c]) w[r][c]
+__global__ __launch_bounds__(64) void k_col_dots(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                 const double2* __restrict__ w, double2* __restrict__ partial,
+                                                 int na, int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= na) return;
+    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
+    const int64_t r1 = min(nup, r0 + RED_ROWS);
+    for (int j = 0; j < nvec; ++j) {
+        const double2* vj = V + j * vstride;
+        double ar = 0.0, ai = 0.0;
+        for (int64_t r = r0; r < r1; ++r) {
+            const double2 v = vj[(size_t)r * lda + c];
+            const double2 x = w[(size_t)r * lda + c];
+            ar = fma(v.x, x.x, fma(v.y, x.y, ar));
+            ai = fma(v.x, x.y, fma(-v.y, x.x, ai));
+        }
+        partial[((size_t)blockIdx.x * nvec + j) * lda + c] = make_double2(ar, ai);
+    }
+}
+
+__global__ void k_reduce_dots(const double2* __restrict__ partial, int nchunk, int nvec, double2* __restrict__ h,
+                              int na, int lda)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nvec * lda) return;
+    const int j = t / lda, c = t - j * lda;
+    if (c >= na) return;
+    double ar = 0.0, ai = 0.0;
+    for (int k = 0; k < nchunk; ++k) {
+        const double2 p = partial[((size_t)k * nvec + j) * lda + c];
+        ar += p.x;
+        ai += p.y;
+    }
+    h[(size_t)j * lda + c] = make_double2(ar, ai);
+}
+
+// w -= sum_j V_j h_j (per column), optionally with per-chunk partial |w|^2.
+__global__ __launch_bounds__(64) void k_col_update(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                   const double2* __restrict__ h, double2* __restrict__ w,
+                                                   double* __restrict__ norm_partial, int na, int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= na) return;
+    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
+    const int64_t r1 = min(nup, r0 + RED_ROWS);
+    double nrm = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        double2 acc = w[(size_t)r * lda + c];
+        for (int j = 0; j < nvec; ++j) {
+            const double2 v = V[j * vstride + (size_t)r * lda + c];
+            const double2 hj = h[(size_t)j * lda + c];
+            acc.x -= v.x * hj.x - v.y * hj.y;
+            acc.y -= v.x * hj.y + v.y * hj.x;
+        }
+        w[(size_t)r * lda + c] = acc;
+        nrm = fma(acc.x, acc.x, fma(acc.y, acc.y, nrm));
+    }
+    if (norm_partial) norm_partial[(size_t)blockIdx.x * lda + c] = nrm;
+}
+
+__global__ __launch_bounds__(64) void k_col_norm_partial(const double2* __restrict__ w, double* __restrict__ partial,
+                                                         int na, int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= na) return;
+    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
+    const int64_t r1 = min(nup, r0 + RED_ROWS);
+    double nrm = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double2 a = w[(size_t)r * lda + c];
+        nrm = fma(a.x, a.x, fma(a.y, a.y, nrm));
+    }
+    partial[(size_t)blockIdx.x * lda + c] = nrm;
+}
+
+__global__ void k_reduce_norms(const double* __restrict__ partial, int nchunk, double* __restrict__ nrm, int na,
+                               int lda)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= na) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * lda + c];
+    nrm[c] = sqrt(s);
+}
+
+// v = w / ||w|| (zero for finished or padded columns), plus the FP32 copy in
+// the real layout [rows][2*lda] when x32 != nullptr.
+__global__ __launch_bounds__(256) void k_normalize(const double2* __restrict__ w, const double* __restrict__ nrm,
+                                                   const int32_t* __restrict__ done, double2* __restrict__ v,
+                                                   float* __restrict__ x32, int na, int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= lda) return;
+    const size_t o = (size_t)r * lda + c;
+    double2 out = make_double2(0.0, 0.0);
+    if (c < na && !(done && done[c])) {
+        const double s = 1.0 / nrm[c];
+        const double2 a = w[o];
+        out = make_double2(a.x * s, a.y * s);
+    }
+    v[o] = out;
+    if (x32) {
+        float2* xp = reinterpret_cast<float2*>(x32 + (size_t)r * 2 * lda + 2 * c);
+        *xp = make_float2((float)out.x, (float)out.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const double2* __restrict__ v, float* __restrict__ x32, int na,
+                                                int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= lda) return;
+    const double2 a = (c < na) ? v[(size_t)r * lda + c] : make_double2(0.0, 0.0);
+    *reinterpret_cast<float2*>(x32 + (size_t)r * 2 * lda + 2 * c) = make_float2((float)a.x, (float)a.y);
+}
+
+// One Arnoldi column of the Hessenberg matrix through the stored Givens
+// rotations (complex rotations, real cosine), the new rotation, and the
+// least-squares residual estimate |g_{k+1}|.
+//   R  [m][m+1][lda]  (column k holds R_{0..k,k}),  cs [m][lda], sn [m][lda]
+//   g  [m+1][lda]
+__global__ void k_givens(int k, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                         const double* __restrict__ nrm, double2* __restrict__ R, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ target,
+                         int32_t* __restrict__ done, int32_t* __restrict__ steps, int na, int lda)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= na || done[c]) return;
+    double2* Rk = R + (size_t)k * (m + 1) * lda;
+    for (int j = 0; j <= k; ++j) {
+        const double2 a = h1[(size_t)j * lda + c], b = h2[(size_t)j * lda + c];
+        Rk[(size_t)j * lda + c] = make_double2(a.x + b.x, a.y + b.y);
+    }
+    double2 hk1 = make_double2(nrm[c], 0.0);
+    for (int j = 0; j < k; ++j) {
+        const double cj = cs[(size_t)j * lda + c];
+        const double2 sj = sn[(size_t)j * lda + c];
+        const double2 a = Rk[(size_t)j * lda + c], b = Rk[(size_t)(j + 1) * lda + c];
+        // [a; b] <- [c a + s b; -conj(s) a + c b]
+        const double2 sb = cmul(sj, b);
+        const double2 sa = cconjmul(sj, a);
+        Rk[(size_t)j * lda + c] = make_double2(cj * a.x + sb.x, cj * a.y + sb.y);
+        Rk[(size_t)(j + 1) * lda + c] = make_double2(cj * b.x - sa.x, cj * b.y - sa.y);
+    }
+    const double2 a = Rk[(size_t)k * lda + c];
+    const double aa = hypot(a.x, a.y), bb = hk1.x;
+    const double rr = hypot(aa, bb);
+    double ck;
+    double2 sk;
+    if (rr == 0.0) {
+        ck = 1.0;
+        sk = make_double2(0.0, 0.0);
+    } else if (aa == 0.0) {
+        ck = 0.0;
+        sk = make_double2(1.0, 0.0);
+    } else {
+        ck = aa / rr;
+        sk = make_double2(a.x / aa * bb / rr, a.y / aa * bb / rr);   // (a/|a|) conj(b)/r, b real
+    }
+    cs[(size_t)k * lda + c] = ck;
+    sn[(size_t)k * lda + c] = sk;
+    const double2 rk = make_double2(ck * a.x + sk.x * bb, ck * a.y + sk.y * bb);
+    Rk[(size_t)k * lda + c] = rk;
+    const double2 gk = g[(size_t)k * lda + c];
+    const double2 gk1 = cconjmul(sk, gk);
+    g[(size_t)(k + 1) * lda + c] = make_double2(-gk1.x, -gk1.y);
+    g[(size_t)k * lda + c] = make_double2(ck * gk.x, ck * gk.y);
+    steps[c] = k + 1;
+    const double est = hypot(gk1.x, gk1.y);
+    if (est <= target[c] || k + 1 >= m || bb == 0.0) done[c] = 1;
+}
+
+// y = R^{-1} g over the first steps[c] rows (back substitution per column).
+__global__ void k_lsq(int m, const double2* __restrict__ R, const double2* __restrict__ g,
+                      const int32_t* __restrict__ steps, double2* __restrict__ y, int na, int lda)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= na) return;
+    const int kc = steps[c];
+    for (int j = kc - 1; j >= 0; --j) {
+        double2 s = g[(size_t)j * lda + c];
+        for (int l = j + 1; l < kc; ++l) {
+            const double2 rjl = R[((size_t)l * (m + 1) + j) * lda + c];
+            const double2 t = cmul(rjl, y[(size_t)l * lda + c]);
+            s.x -= t.x;
+            s.y -= t.y;
+        }
+        const double2 d = R[((size_t)j * (m + 1) + j) * lda + c];
+        const double den = d.x * d.x + d.y * d.y;
+        y[(size_t)j * lda + c] = make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den);
+    }
+}
+
+// x += sum_{j < steps[c]} V_j y_j
+__global__ __launch_bounds__(256) void k_x_update(const double2* __restrict__ V, int64_t vstride,
+                                                  const double2* __restrict__ y, const int32_t* __restrict__ steps,
+                                                  double2* __restrict__ x, int na, int lda, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= na) return;
+    const size_t o = (size_t)r * lda + c;
+    double2 acc = x[o];
+    const int kc = steps[c];
+    for (int j = 0; j < kc; ++j) {
+        const double2 t = cmul(V[j * vstride + o], y[(size_t)j * lda + c]);
+        acc.x += t.x;
+        acc.y += t.y;
+    }
+    x[o] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_gather(const double2* __restrict__ src, int lds, double2* __restrict__ dst,
+                                                int ldd, const int32_t* __restrict__ map, int na, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= ldd) return;
+    dst[(size_t)r * ldd + c] = (c < na) ? src[(size_t)r * lds + map[c]] : make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const double2* __restrict__ src, int lds, double2* __restrict__ dst,
+                                                 int ldd, const int32_t* __restrict__ map, int na, int64_t nup)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= na) return;
+    dst[(size_t)r * ldd + map[c]] = src[(size_t)r * lds + c];
+}
+
+// ---------------------------------------------------------------- observables
+
+// dpart[chunk][k][c] over atom chunks: sum_i x_q[i][c] r_ik (+ sum_i x_mu_k[i][c])
+__global__ __launch_bounds__(64) void k_dipole_partial(const double2* __restrict__ x, const double4* __restrict__ x64,
+                                                       int64_t n, int64_t np, int model, int ncol, int ldx,
+                                                       double2* __restrict__ dpart)
+{
+    const int c = blockIdx.y * 64 + threadIdx.x;
+    if (c >= ncol) return;
+    const int64_t i0 = (int64_t)blockIdx.x * RED_ROWS;
+    const int64_t i1 = min(n, i0 + RED_ROWS);
+    double d[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int64_t i = i0; i < i1; ++i) {
+        const double2 q = x[(size_t)i * ldx + c];
+        const double4 p = x64[i];
+        d[0][0] = fma(q.x, p.x, d[0][0]); d[0][1] = fma(q.y, p.x, d[0][1]);
+        d[1][0] = fma(q.x, p.y, d[1][0]); d[1][1] = fma(q.y, p.y, d[1][1]);
+        d[2][0] = fma(q.x, p.z, d[2][0]); d[2][1] = fma(q.y, p.z, d[2][1]);
+        if (model == 1) {
+            for (int k = 0; k < 3; ++k) {
+                const double2 mu = x[(size_t)((k + 1) * np + i) * ldx + c];
+                d[k][0] += mu.x;
+                d[k][1] += mu.y;
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) dpart[((size_t)blockIdx.x * 3 + k) * ldx + c] = make_double2(d[k][0], d[k][1]);
+}
+
+__global__ void k_dipole_reduce(const double2* __restrict__ dpart, int nchunk, int ncol, int ldx,
+                                double2* __restrict__ d)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * ncol) return;
+    const int k = t / ncol, c = t - k * ncol;
+    double ar = 0.0, ai = 0.0;
+    for (int q = 0; q < nchunk; ++q) {
+        const double2 p = dpart[((size_t)q * 3 + k) * ldx + c];
+        ar += p.x;
+        ai += p.y;
+    }
+    d[(size_t)k * ncol + c] = make_double2(ar, ai);
+}
+
+// alpha[w][k][l] = d_k / E0 of the column (w, l); sigma = (4 pi w / c) mean_l Im alpha_ll
+__global__ void k_spectrum(const double2* __restrict__ d, const int32_t* __restrict__ col_pol, int n_omega, int npol,
+                           int ncol, const double* __restrict__ omega_au, double e0, double2* __restrict__ alpha,
+                           double* __restrict__ sigma)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_omega) return;
+    double2* a = alpha + (size_t)w * 9;
+    for (int q = 0; q < 9; ++q) a[q] = make_double2(0.0, 0.0);
+    double im = 0.0;
+    for (int p = 0; p < npol; ++p) {
+        const int c = w * npol + p;
+        const int l = col_pol[c];
+        for (int k = 0; k < 3; ++k) {
+            const double2 dk = d[(size_t)k * ncol + c];
+            a[3 * k + l] = make_double2(dk.x / e0, dk.y / e0);
+        }
+        im += a[3 * l + l].y;
+    }
+    sigma[w] = 2.0 * TWO_PI * omega_au[w] / C_LIGHT * (im / npol);
+}
+
+__global__ void k_unpermute(const double2* __restrict__ x, int ldx, int col, const int32_t* __restrict__ perm,
+                            int64_t n, int64_t np, int ncomp, double2* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * ncomp) return;
+    const int64_t comp = t / n, i = t - comp * n;
+    out[comp * n + perm[i]] = x[(size_t)(comp * np + i) * ldx + col];
+}
+
+__global__ void k_permute_in(const double2* __restrict__ in, int ncol, int64_t n, int64_t np, int ncomp,
+                             const int32_t* __restrict__ perm, double2* __restrict__ x, int ldx)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= np * ncomp || c >= ldx) return;
+    const int64_t comp = r / np, i = r - comp * np;
+    double2 v = make_double2(0.0, 0.0);
+    if (c < ncol && i < n) v = in[(size_t)c * n * ncomp + comp * n + perm[i]];
+    x[(size_t)r * ldx + c] = v;
+}
+
+__global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words)
+{
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; t < words; t += stride) p[t] = 0u;
+}
+
+inline dim3 grid_rows_cols(int64_t rows, int cols) { return dim3((unsigned)((rows + 3) / 4), (unsigned)((cols + 63) / 64)); }
+inline int nchunks(int64_t rows) { return (int)((rows + RED_ROWS - 1) / RED_ROWS); }
+
+}  // namespace
+
+// ============================================================== launchers
+
+hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
+                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st)
+{
+    const int64_t n = g.n, np = g.np;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], xyz_bohr_host[3 * i + k]);
+            hi[k] = std::max(hi[k], xyz_bohr_host[3 * i + k]);
+        }
+    double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    double sc = ext > 0 ? 1023.0 / ext : 1.0;
+    int64_t npow = 1;
+    while (npow < n) npow <<= 1;
+    double* d_xyz = nullptr;
+    uint64_t* d_keys = nullptr;
+    int32_t *d_cnt = nullptr, *d_perm = nullptr;
+    int* d_bad = nullptr;
+    hipError_t e;
+#define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
+    PXCHK(hipMalloc(&d_xyz, sizeof(double) * 3 * n));
+    PXCHK(hipMalloc(&d_keys, sizeof(uint64_t) * npow));
+    PXCHK(hipMalloc(&d_cnt, sizeof(int32_t) * (n + 1)));
+    PXCHK(hipMalloc(&d_perm, sizeof(int32_t) * np));
+    PXCHK(hipMalloc(&d_bad, sizeof(int)));
+    PXCHK(hipMalloc(&g.xyz64, sizeof(double4) * np));
+    PXCHK(hipMalloc(&g.xyz32, sizeof(float4) * np));
+    PXCHK(hipMalloc(&g.glo, sizeof(float4) * (np / GROUP)));
+    PXCHK(hipMalloc(&g.ghi, sizeof(float4) * (np / GROUP)));
+    PXCHK(hipMalloc(&g.row_ptr, sizeof(int32_t) * (n + 1)));
+    PXCHK(hipMemcpyAsync(d_xyz, xyz_bohr_host, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(d_bad), (size_t)1);
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, st, d_xyz, n, npow,
+                       make_double3(lo[0], lo[1], lo[2]), make_double3(sc, sc, sc), d_keys);
+    for (uint32_t k = 2; k <= (uint32_t)npow; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, st, d_keys, j, k,
+                               (uint32_t)npow);
+    {
+        double3 far0 = make_double3(hi[0] + 1.0e4, hi[1] + 1.0e4, hi[2] + 1.0e4);
+        hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d_xyz, d_keys, n,
+                           np, far0, d_perm, g.xyz64, g.xyz32);
+    }
+    hipLaunchKernelGGL(k_group_bbox, dim3((unsigned)((np / GROUP + 255) / 256)), dim3(256), 0, st, g.xyz64,
+                       np / GROUP, g.glo, g.ghi);
+    {
+        KappaConst kc;
+        kc.a_eff = m.a_eff;
+        kc.fd = m.fermi_d;
+        kc.s_r0 = m.fermi_s * r0_bohr;
+        kc.rc = cutoff_bohr;
+        kc.rc2 = cutoff_bohr * cutoff_bohr;
+        kc.min_r = 1e-6 / ANG;
+        hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
+                           np, kc, d_cnt, nullptr, nullptr, nullptr, d_bad);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cnt, n, g.row_ptr);
+        int32_t nnz = 0;
+        PXCHK(hipMemcpyAsync(&nnz, g.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        PXCHK(hipMemcpyAsync(bad_pair, d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        PXCHK(hipStreamSynchronize(st));
+        g.nnz = nnz;
+        PXCHK(hipMalloc(&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+        PXCHK(hipMalloc(&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+        hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
+                           np, kc, nullptr, g.row_ptr, g.col, g.val, d_bad);
+    }
+    perm_host.resize(n);
+    PXCHK(hipMemcpyAsync(perm_host.data(), d_perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    PXCHK(hipStreamSynchronize(st));
+    PXCHK(hipGetLastError());
+fail:
+#undef PXCHK
+    (void)hipFree(d_xyz);
+    (void)hipFree(d_keys);
+    (void)hipFree(d_cnt);
+    (void)hipFree(d_perm);
+    (void)hipFree(d_bad);
+    return e;
+}
+
+void spmm_shift(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* zq,
+                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st)
+{
+    dim3 grid = grid_rows_cols(g.nup, lda);
+    if (y_is_f32)
+        hipLaunchKernelGGL(k_spmm_shift<float>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val,
+                           static_cast<const float*>(Y), ldy, X, zq, zmu, B, W, g.n, g.np, g.nup, na, lda,
+                           mu_sign);
+    else
+        hipLaunchKernelGGL(k_spmm_shift<double>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val,
+                           static_cast<const double*>(Y), ldy, X, zq, zmu, B, W, g.n, g.np, g.nup, na, lda,
+                           mu_sign);
+}
+
+void build_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, double mu_sign,
+               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rhs, grid_rows_cols(g.nup, ldb), dim3(256), 0, st, g.row_ptr, g.col, g.val, g.xyz64,
+                       col_pol, e0, b, g.n, g.np, g.nup, ncol, ldb, mu_sign);
+}
+
+void col_dots(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
+              int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_col_dots, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, V, vstride,
+                       nvec, w, partial, na, lda, nup);
+}
+
+void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int na, int lda, bool, hipStream_t st)
+{
+    int t = nvec * lda;
+    hipLaunchKernelGGL(k_reduce_dots, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, partial, nchunk, nvec, h,
+                       na, lda);
+}
+
+void col_update(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
+                int na, int lda, int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_col_update, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, V, vstride,
+                       nvec, h, w, norm_partial, na, lda, nup);
+}
+
+void col_norm_partial(const double2* w, double* partial, int na, int lda, int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_col_norm_partial, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, w,
+                       partial, na, lda, nup);
+}
+
+void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_norms, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, partial, nchunk, nrm,
+                       na, lda);
+}
+
+void normalize(const double2* w, const double* nrm, const int32_t* done, double2* v, float* x32, int na, int lda,
+               int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_normalize, grid_rows_cols(nup, lda), dim3(256), 0, st, w, nrm, done, v, x32, na, lda, nup);
+}
+
+void to_f32(const double2* v, float* x32, int na, int lda, int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_f32, grid_rows_cols(nup, lda), dim3(256), 0, st, v, x32, na, lda, nup);
+}
+
+void givens_step(int k, int m, const double2* h1, const double2* h2, const double* nrm, double2* R, double* cs,
+                 double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps, int32_t*, int na,
+                 int lda, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_givens, dim3((unsigned)((na + 63) / 64)), dim3(64), 0, st, k, m, h1, h2, nrm, R, cs, sn,
+                       gvec, target, done, steps, na, lda);
+}
+
+void lsq_solve(int m, const double2* R, const double2* gvec, const int32_t* steps, double2* y, int na, int lda,
+               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lsq, dim3((unsigned)((na + 63) / 64)), dim3(64), 0, st, m, R, gvec, steps, y, na, lda);
+}
+
+void x_update(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, int, double2* x, int na,
+              int lda, int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_x_update, grid_rows_cols(nup, lda), dim3(256), 0, st, V, vstride, y, steps, x, na, lda, nup);
+}
+
+void gather_cols(const double2* src, int lds, double2* dst, int ldd, const int32_t* map, int na, int64_t nup,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather, grid_rows_cols(nup, ldd), dim3(256), 0, st, src, lds, dst, ldd, map, na, nup);
+}
+
+void scatter_cols(const double2* src, int lds, double2* dst, int ldd, const int32_t* map, int na, int64_t nup,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter, grid_rows_cols(nup, lds), dim3(256), 0, st, src, lds, dst, ldd, map, na, nup);
+}
+
+void observables(const Geometry& g, const double2* x, int ncol, int ldx, double2* dpart, double2* d, hipStream_t st)
+{
+    int nch = nchunks(g.n);
+    hipLaunchKernelGGL(k_dipole_partial, dim3(nch, (unsigned)((ncol + 63) / 64)), dim3(64), 0, st, x, g.xyz64, g.n,
+                       g.np, g.model, ncol, ldx, dpart);
+    hipLaunchKernelGGL(k_dipole_reduce, dim3((unsigned)((3 * ncol + 255) / 256)), dim3(256), 0, st, dpart, nch, ncol,
+                       ldx, d);
+}
+
+void spectrum(const double2* d, const int32_t* col_pol, int n_omega, int npol, const double* omega_au, double e0,
+              double2* alpha, double* sigma, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spectrum, dim3((unsigned)((n_omega + 63) / 64)), dim3(64), 0, st, d, col_pol, n_omega, npol,
+                       n_omega * npol, omega_au, e0, alpha, sigma);
+}
+
+void unpermute(const Geometry& g, const double2* x, int ldx, int col, const int32_t* perm, double2* out,
+               hipStream_t st)
+{
+    int ncomp = g.model ? 4 : 1;
+    int64_t t = g.n * ncomp;
+    hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, x, ldx, col, perm, g.n,
+                       g.np, ncomp, out);
+}
+
+void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* perm, double2* x, int ldx,
+                hipStream_t st)
+{
+    int ncomp = g.model ? 4 : 1;
+    hipLaunchKernelGGL(k_permute_in, grid_rows_cols(g.np * ncomp, ldx), dim3(256), 0, st, in, ncol, g.n, g.np, ncomp,
+                       perm, x, ldx);
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t st)
+{
+    size_t words = bytes / 4;
+    if (words == 0) return;
+    unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint32_t*>(p), words);
+}
+
+}  // namespace px

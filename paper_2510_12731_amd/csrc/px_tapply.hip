@@ -1,0 +1,814 @@
+// Matrix-free interaction-kernel apply Y = T X (plasmonX paper: Eq. tqq for
+// omegaFQ; the T^qq / T^qmu / T^muq / T^mumu blocks of Eq. wfqfmu-system,
+// obtained by differentiating the Gaussian charge kernel, for omegaFQFmu).
+//
+// T is never stored: every tile is generated in registers directly in the
+// A-operand layout of the matrix instructions and contracted against X tiles
+// staged through LDS.  T is real and shared by every frequency and
+// polarization, so a block of n_c complex columns is an N x 2n_c real
+// contraction.
+//
+//   tapply_f32  omegaFQ: v_mfma_f32_32x32x2f32, wave tile 64 rows x 128 columns
+//               omegaFQFmu: v_mfma_f32_32x32x2f32, wave tile 32 atoms x 4
+//               components x 32 columns (one pair block feeds 16 MFMAs)
+//   tapply_f64  >= 128 real columns: v_mfma_f64_16x16x4f64 tiles
+//               narrow blocks (<= 8 real columns): FP64 VALU with a split over
+//               the source atoms and a deterministic second-pass sum
+//
+// Near/far split: atoms are in Morton order and grouped by 32 with bounding
+// boxes.  When the boxes of a row group and a source group are farther apart
+// than x_far * R, erf(r/R) rounds to 1 in the working precision and the kernel
+// takes the point-charge form (1/r and its derivatives); the decision is
+// uniform per wave.  The diagonal T_ii is the Gaussian self-interaction
+// sqrt(2/pi)/R_q; the dipole self blocks are zero.
+#include "px_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace px {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr float TWO_OVER_SQRTPI_F = 1.1283791670955126f;
+constexpr double TWO_OVER_SQRTPI = 1.1283791670955126;
+
+// erf(x), x >= 0, Abramowitz & Stegun (1964) formula 7.1.26 (absolute error
+// <= 1.5e-7): used only in the single-precision near field.
+__device__ __forceinline__ float erf_as(float x)
+{
+    const float p = 0.3275911f;
+    const float a1 = 0.254829592f, a2 = -0.284496736f, a3 = 1.421413741f, a4 = -1.453152027f,
+                a5 = 1.061405429f;
+    float t = __builtin_amdgcn_rcpf(fmaf(p, x, 1.0f));
+    float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, a5, a4), a3), a2), a1);
+    return 1.0f - poly * __expf(-x * x);
+}
+
+// Squared distance between two axis-aligned boxes (0 if they overlap).
+__device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, float4 bhi)
+{
+    float dx = fmaxf(0.0f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
+    float dy = fmaxf(0.0f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
+    float dz = fmaxf(0.0f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ============================ omegaFQ, FP32 MFMA ============================
+// Workgroup: 4 waves, 256 rows x 128 real columns.  Wave w: rows
+// [row0, row0+64) as two 32-row MFMA blocks x four 32-column blocks.
+// MFMA 32x32x2 operand layout (wave64): A lane l -> (row l%32, k l/32);
+// B lane l -> (k l/32, col l%32); D register v of lane l -> (row 8(v/4) +
+// 4(l/32) + v%4, col l%32).  MFMA column n of block cb is physical column
+// 4n + cb, so one ds_read_b128 yields a lane's four B values and one 16-byte
+// store writes its four outputs.
+constexpr int Q32_COLS = 128;
+constexpr int Q32_JC = 32;
+
+__global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
+                                                        const float4* __restrict__ glo,
+                                                        const float4* __restrict__ ghi,
+                                                        const float* __restrict__ X, float* __restrict__ Y,
+                                                        int np, int ldx, float inv_rqq, float t_self,
+                                                        float r_far2)
+{
+    __shared__ __attribute__((aligned(16))) float sx[2][Q32_JC][Q32_COLS];
+    __shared__ float4 sxyz[2][Q32_JC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int row0 = blockIdx.x * 256 + wave * 64;
+    const int col0 = blockIdx.y * Q32_COLS;
+
+    float xi[2], yi[2], zi[2];
+    int ii[2];
+    float4 rlo[2], rhi[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        ii[rb] = row0 + rb * 32 + (lane & 31);
+        float4 p = xyz[ii[rb]];
+        xi[rb] = p.x; yi[rb] = p.y; zi[rb] = p.z;
+        rlo[rb] = glo[(row0 >> 5) + rb];
+        rhi[rb] = ghi[(row0 >> 5) + rb];
+    }
+
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
+
+    // cooperative tile load: thread -> (row tid/8, 16 columns at 16*(tid%8))
+    const int lr = tid >> 3;
+    const int lc = (tid & 7) * 16;
+    const int nchunk = np / Q32_JC;
+    {
+        const float4* src = reinterpret_cast<const float4*>(X + (size_t)lr * ldx + col0 + lc);
+        float4* dst = reinterpret_cast<float4*>(&sx[0][lr][lc]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+        if (tid < Q32_JC) sxyz[0][tid] = xyz[tid];
+    }
+    __syncthreads();
+
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const int j0 = ch * Q32_JC;
+        const bool more = (ch + 1) < nchunk;
+        float4 pre[4];
+        float4 prexyz = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (more) {
+            const float4* src = reinterpret_cast<const float4*>(X + (size_t)(j0 + Q32_JC + lr) * ldx + col0 + lc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[q] = src[q];
+            if (tid < Q32_JC) prexyz = xyz[j0 + Q32_JC + tid];
+        }
+        const float4 clo = glo[ch];
+        const float4 chi = ghi[ch];
+        int far[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) far[rb] = uniform(box_gap2(rlo[rb], rhi[rb], clo, chi) >= r_far2);
+
+#pragma unroll 4
+        for (int kk = 0; kk < Q32_JC / 2; ++kk) {
+            const int jr = 2 * kk + (lane >> 5);
+            const float4 pj = sxyz[buf][jr];
+            const float4 bq = *reinterpret_cast<const float4*>(&sx[buf][jr][4 * (lane & 31)]);
+            float a[2];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                float dx = xi[rb] - pj.x, dy = yi[rb] - pj.y, dz = zi[rb] - pj.z;
+                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                float rinv = __builtin_amdgcn_rsqf(r2);
+                if (far[rb]) {
+                    a[rb] = rinv;
+                } else {
+                    float t = erf_as(r2 * rinv * inv_rqq) * rinv;
+                    a[rb] = (ii[rb] == j0 + jr) ? t_self : t;
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.x, acc[rb][0], 0, 0, 0);
+                acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.y, acc[rb][1], 0, 0, 0);
+                acc[rb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.z, acc[rb][2], 0, 0, 0);
+                acc[rb][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.w, acc[rb][3], 0, 0, 0);
+            }
+        }
+        if (more) {
+            float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
+            if (tid < Q32_JC) sxyz[buf ^ 1][tid] = prexyz;
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = row0 + rb * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            float4 o = make_float4(acc[rb][0][v], acc[rb][1][v], acc[rb][2][v], acc[rb][3][v]);
+            *reinterpret_cast<float4*>(Y + (size_t)i * ldx + col0 + 4 * (lane & 31)) = o;
+        }
+}
+
+// ========================== omegaFQFmu, FP32 MFMA ===========================
+// Workgroup: 4 waves x 32 atoms, 32 real columns.  Each lane builds the 4x4
+// pair block of (row atom l%32, source atom 2kk + l/32) once and feeds the 16
+// (output component, input component) MFMAs of the k-step with it.
+constexpr int D32_COLS = 32;
+constexpr int D32_JC = 32;
+
+struct DipoleConstF {
+    float inv_rqq, inv_rqm, inv_rmm;   // 1/R for the three widths
+    float gauss_pref;                  // (4/sqrt(pi)) / R_mumu^3
+    float t_self;                      // sqrt(2/pi)/R_q
+    float r_far2;
+};
+
+// Pair block b[a][c] (a: output component of row atom, c: input component of
+// source atom; 0 = q, 1..3 = mu_x..mu_z) for rv = r_i - r_j.
+__device__ __forceinline__ void pair_block_f32(float dx, float dy, float dz, bool far, const DipoleConstF& k,
+                                               float b[4][4])
+{
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float rinv = __builtin_amdgcn_rsqf(r2);
+    float rinv3 = rinv * rinv * rinv;
+    float tqq, gq, gm, gs;
+    if (far) {
+        tqq = rinv;
+        gq = 1.0f;
+        gm = 1.0f;
+        gs = 0.0f;
+    } else {
+        float r = r2 * rinv;
+        float xq = r * k.inv_rqq, xm = r * k.inv_rqm, xmm = r * k.inv_rmm;
+        tqq = erf_as(xq) * rinv;
+        gq = erf_as(xm) - TWO_OVER_SQRTPI_F * xm * __expf(-xm * xm);
+        float e = __expf(-xmm * xmm);
+        gm = erf_as(xmm) - TWO_OVER_SQRTPI_F * xmm * e;
+        gs = k.gauss_pref * e;
+    }
+    float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+    float u[3] = {ux, uy, uz};
+    b[0][0] = tqq;
+    float gr = gq * rinv * rinv;   // g / r^2
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b[0][1 + a] = gr * u[a];
+        b[1 + a][0] = -gr * u[a];
+    }
+    float gm3 = gm * rinv3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float uu = u[a] * u[c];
+            b[1 + a][1 + c] = fmaf(gs - 3.0f * gm3, uu, (a == c) ? gm3 : 0.0f);
+        }
+}
+
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restrict__ xyz,
+                                                           const float4* __restrict__ glo,
+                                                           const float4* __restrict__ ghi,
+                                                           const float* __restrict__ X, float* __restrict__ Y,
+                                                           int np, int ldx, DipoleConstF kc)
+{
+    __shared__ float sx[2][4][D32_JC][D32_COLS];
+    __shared__ float4 sxyz[2][D32_JC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int row0 = blockIdx.x * 128 + wave * 32;
+    const int col0 = blockIdx.y * D32_COLS;
+    const size_t cstride = (size_t)np * ldx;   // component block stride
+
+    const int ii = row0 + (lane & 31);
+    const float4 pi = xyz[ii];
+    const float4 rlo = glo[row0 >> 5], rhi = ghi[row0 >> 5];
+
+    f32x16 acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][v] = 0.0f;
+
+    // tile load: 4 comps x 32 atoms x 32 cols = 4096 floats; thread -> comp tid/64,
+    // atom (tid%64)/2, 16 columns at 16*(tid%2)
+    const int lcomp = tid >> 6;
+    const int latom = (tid & 63) >> 1;
+    const int lcol = (tid & 1) * 16;
+    const int nchunk = np / D32_JC;
+    {
+        const float4* src = reinterpret_cast<const float4*>(X + lcomp * cstride + (size_t)latom * ldx + col0 + lcol);
+        float4* dst = reinterpret_cast<float4*>(&sx[0][lcomp][latom][lcol]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+        if (tid < D32_JC) sxyz[0][tid] = xyz[tid];
+    }
+    __syncthreads();
+
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const int j0 = ch * D32_JC;
+        const bool more = (ch + 1) < nchunk;
+        float4 pre[4];
+        float4 prexyz = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (more) {
+            const float4* src = reinterpret_cast<const float4*>(X + lcomp * cstride +
+                                                                (size_t)(j0 + D32_JC + latom) * ldx + col0 + lcol);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[q] = src[q];
+            if (tid < D32_JC) prexyz = xyz[j0 + D32_JC + tid];
+        }
+        const int far = uniform(box_gap2(rlo, rhi, glo[ch], ghi[ch]) >= kc.r_far2);
+
+#pragma unroll 2
+        for (int kk = 0; kk < D32_JC / 2; ++kk) {
+            const int jr = 2 * kk + (lane >> 5);
+            const float4 pj = sxyz[buf][jr];
+            float b[4][4];
+            pair_block_f32(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, far != 0, kc, b);
+            if (!far && ii == j0 + jr) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) b[a][c] = 0.0f;
+                b[0][0] = kc.t_self;
+            }
+            float xb[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) xb[c] = sx[buf][c][jr][lane & 31];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[a] = __builtin_amdgcn_mfma_f32_32x32x2f32(b[a][c], xb[c], acc[a], 0, 0, 0);
+        }
+        if (more) {
+            float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lcomp][latom][lcol]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
+            if (tid < D32_JC) sxyz[buf ^ 1][tid] = prexyz;
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = row0 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            Y[a * cstride + (size_t)i * ldx + col0 + (lane & 31)] = acc[a][v];
+        }
+}
+
+// ============================ omegaFQ, FP64 MFMA ============================
+// Workgroup: 4 waves x 32 rows, 64 real columns.  MFMA 16x16x4 f64 layout:
+// A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16); D register v
+// of lane l -> (row 4v + l/16, col l%16) (rows interleave across the four
+// lane groups, unlike the f32 16x16x4 form).  MFMA column n of block cb is
+// physical column 4n + cb.
+constexpr int Q64_COLS = 64;
+constexpr int Q64_JC = 32;
+
+__global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restrict__ xyz,
+                                                        const float4* __restrict__ glo,
+                                                        const float4* __restrict__ ghi,
+                                                        const double* __restrict__ X, double* __restrict__ Y,
+                                                        int np, int ldx, double inv_rqq, double t_self,
+                                                        float r_far2)
+{
+    __shared__ __attribute__((aligned(16))) double sx[2][Q64_JC][Q64_COLS];
+    __shared__ double4 sxyz[2][Q64_JC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int row0 = blockIdx.x * 128 + wave * 32;
+    const int col0 = blockIdx.y * Q64_COLS;
+
+    double xi[2], yi[2], zi[2];
+    int ii[2];
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb) {
+        ii[sb] = row0 + sb * 16 + (lane & 15);
+        double4 p = xyz[ii[sb]];
+        xi[sb] = p.x; yi[sb] = p.y; zi[sb] = p.z;
+    }
+    const float4 rlo = glo[row0 >> 5], rhi = ghi[row0 >> 5];
+
+    f64x4 acc[2][4];
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[sb][cb][v] = 0.0;
+
+    // tile load: 32 atoms x 64 doubles = 2048 doubles; thread -> row tid/8, 8 doubles at 8*(tid%8)
+    const int lr = tid >> 3;
+    const int lc = (tid & 7) * 8;
+    const int nchunk = np / Q64_JC;
+    {
+        const double2* src = reinterpret_cast<const double2*>(X + (size_t)lr * ldx + col0 + lc);
+        double2* dst = reinterpret_cast<double2*>(&sx[0][lr][lc]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+        if (tid < Q64_JC) sxyz[0][tid] = xyz[tid];
+    }
+    __syncthreads();
+
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const int j0 = ch * Q64_JC;
+        const bool more = (ch + 1) < nchunk;
+        double2 pre[4];
+        double4 prexyz = make_double4(0, 0, 0, 0);
+        if (more) {
+            const double2* src = reinterpret_cast<const double2*>(X + (size_t)(j0 + Q64_JC + lr) * ldx + col0 + lc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[q] = src[q];
+            if (tid < Q64_JC) prexyz = xyz[j0 + Q64_JC + tid];
+        }
+        const int far = uniform(box_gap2(rlo, rhi, glo[ch], ghi[ch]) >= r_far2);
+
+#pragma unroll 2
+        for (int kk = 0; kk < Q64_JC / 4; ++kk) {
+            const int jr = 4 * kk + (lane >> 4);
+            const double4 pj = sxyz[buf][jr];
+            const double2* bp = reinterpret_cast<const double2*>(&sx[buf][jr][4 * (lane & 15)]);
+            const double2 b01 = bp[0], b23 = bp[1];
+            double a[2];
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                double dx = xi[sb] - pj.x, dy = yi[sb] - pj.y, dz = zi[sb] - pj.z;
+                double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                double rinv = rsqrt(r2);
+                if (far) {
+                    a[sb] = rinv;
+                } else {
+                    double t = erf(r2 * rinv * inv_rqq) * rinv;
+                    a[sb] = (ii[sb] == j0 + jr) ? t_self : t;
+                }
+            }
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                acc[sb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sb], b01.x, acc[sb][0], 0, 0, 0);
+                acc[sb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sb], b01.y, acc[sb][1], 0, 0, 0);
+                acc[sb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sb], b23.x, acc[sb][2], 0, 0, 0);
+                acc[sb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[sb], b23.y, acc[sb][3], 0, 0, 0);
+            }
+        }
+        if (more) {
+            double2* dst = reinterpret_cast<double2*>(&sx[buf ^ 1][lr][lc]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
+            if (tid < Q64_JC) sxyz[buf ^ 1][tid] = prexyz;
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = row0 + sb * 16 + 4 * v + (lane >> 4);
+            double2* dst = reinterpret_cast<double2*>(Y + (size_t)i * ldx + col0 + 4 * (lane & 15));
+            dst[0] = make_double2(acc[sb][0][v], acc[sb][1][v]);
+            dst[1] = make_double2(acc[sb][2][v], acc[sb][3][v]);
+        }
+}
+
+// ========================== omegaFQFmu, FP64 MFMA ===========================
+// Workgroup: 4 waves x 16 atoms, 16 real columns; 16 MFMAs per k-step.
+struct DipoleConstD {
+    double inv_rqq, inv_rqm, inv_rmm, gauss_pref, t_self;
+    float r_far2;
+};
+
+__device__ __forceinline__ void pair_block_f64(double dx, double dy, double dz, bool far, const DipoleConstD& k,
+                                               double b[4][4])
+{
+    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    double rinv = rsqrt(r2);
+    double rinv3 = rinv * rinv * rinv;
+    double tqq, gq, gm, gs;
+    if (far) {
+        tqq = rinv;
+        gq = 1.0;
+        gm = 1.0;
+        gs = 0.0;
+    } else {
+        double r = r2 * rinv;
+        double xq = r * k.inv_rqq, xm = r * k.inv_rqm, xmm = r * k.inv_rmm;
+        tqq = erf(xq) * rinv;
+        gq = erf(xm) - TWO_OVER_SQRTPI * xm * exp(-xm * xm);
+        double e = exp(-xmm * xmm);
+        gm = erf(xmm) - TWO_OVER_SQRTPI * xmm * e;
+        gs = k.gauss_pref * e;
+    }
+    double u[3] = {dx * rinv, dy * rinv, dz * rinv};
+    b[0][0] = tqq;
+    double gr = gq * rinv * rinv;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b[0][1 + a] = gr * u[a];
+        b[1 + a][0] = -gr * u[a];
+    }
+    double gm3 = gm * rinv3;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double uu = u[a] * u[c];
+            b[1 + a][1 + c] = fma(gs - 3.0 * gm3, uu, (a == c) ? gm3 : 0.0);
+        }
+}
+
+constexpr int D64_COLS = 16;
+constexpr int D64_JC = 32;
+
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __restrict__ xyz,
+                                                           const float4* __restrict__ glo,
+                                                           const float4* __restrict__ ghi,
+                                                           const double* __restrict__ X, double* __restrict__ Y,
+                                                           int np, int ldx, DipoleConstD kc)
+{
+    __shared__ double sx[2][4][D64_JC][D64_COLS];
+    __shared__ double4 sxyz[2][D64_JC];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int row0 = blockIdx.x * 64 + wave * 16;
+    const int col0 = blockIdx.y * D64_COLS;
+    const size_t cstride = (size_t)np * ldx;
+
+    const int ii = row0 + (lane & 15);
+    const double4 pi = xyz[ii];
+    const float4 rlo = glo[row0 >> 5], rhi = ghi[row0 >> 5];
+
+    f64x4 acc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][v] = 0.0;
+
+    // tile load: 4 comps x 32 atoms x 16 cols = 2048 doubles; thread -> comp tid/64,
+    // atom (tid%64)/2, 8 doubles at 8*(tid%2)
+    const int lcomp = tid >> 6;
+    const int latom = (tid & 63) >> 1;
+    const int lcol = (tid & 1) * 8;
+    const int nchunk = np / D64_JC;
+    {
+        const double2* src = reinterpret_cast<const double2*>(X + lcomp * cstride + (size_t)latom * ldx + col0 + lcol);
+        double2* dst = reinterpret_cast<double2*>(&sx[0][lcomp][latom][lcol]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+        if (tid < D64_JC) sxyz[0][tid] = xyz[tid];
+    }
+    __syncthreads();
+
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const int j0 = ch * D64_JC;
+        const bool more = (ch + 1) < nchunk;
+        double2 pre[4];
+        double4 prexyz = make_double4(0, 0, 0, 0);
+        if (more) {
+            const double2* src = reinterpret_cast<const double2*>(X + lcomp * cstride +
+                                                                  (size_t)(j0 + D64_JC + latom) * ldx + col0 + lcol);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[q] = src[q];
+            if (tid < D64_JC) prexyz = xyz[j0 + D64_JC + tid];
+        }
+        const int far = uniform(box_gap2(rlo, rhi, glo[ch], ghi[ch]) >= kc.r_far2);
+
+        for (int kk = 0; kk < D64_JC / 4; ++kk) {
+            const int jr = 4 * kk + (lane >> 4);
+            const double4 pj = sxyz[buf][jr];
+            double b[4][4];
+            pair_block_f64(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, far != 0, kc, b);
+            if (!far && ii == j0 + jr) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) b[a][c] = 0.0;
+                b[0][0] = kc.t_self;
+            }
+            double xb[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) xb[c] = sx[buf][c][jr][lane & 15];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[a][c], xb[c], acc[a], 0, 0, 0);
+        }
+        if (more) {
+            double2* dst = reinterpret_cast<double2*>(&sx[buf ^ 1][lcomp][latom][lcol]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
+            if (tid < D64_JC) sxyz[buf ^ 1][tid] = prexyz;
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = row0 + 4 * v + (lane >> 4);
+            Y[a * cstride + (size_t)i * ldx + col0 + (lane & 15)] = acc[a][v];
+        }
+}
+
+// ====================== narrow blocks, FP64 VALU ============================
+// One thread per row atom, NC real columns (x 4 components for the dipole
+// model); the source atoms are split over gridDim.y and the partial sums are
+// added in a fixed order by k_sum_splits.
+constexpr int NW_CHUNK = 256;
+
+template <int NC, int MODEL>
+__global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __restrict__ xyz,
+                                                           const float4* __restrict__ glo,
+                                                           const float4* __restrict__ ghi,
+                                                           const double* __restrict__ X,
+                                                           double* __restrict__ part, int np, int chunks_per_split,
+                                                           double inv_rqq, double t_self, float r_far2,
+                                                           DipoleConstD kc)
+{
+    constexpr int NCOMP = MODEL ? 4 : 1;
+    __shared__ double4 sxyz[NW_CHUNK];
+    __shared__ double sxv[NCOMP][NW_CHUNK][NC];
+
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * 256 + tid;
+    const int wave_row0 = blockIdx.x * 256 + (tid & ~63);
+    const double4 pi = xyz[i];
+    const float4 g0lo = glo[wave_row0 >> 5], g1lo = glo[(wave_row0 >> 5) + 1];
+    const float4 g0hi = ghi[wave_row0 >> 5], g1hi = ghi[(wave_row0 >> 5) + 1];
+    const float4 rlo = make_float4(fminf(g0lo.x, g1lo.x), fminf(g0lo.y, g1lo.y), fminf(g0lo.z, g1lo.z), 0.f);
+    const float4 rhi = make_float4(fmaxf(g0hi.x, g1hi.x), fmaxf(g0hi.y, g1hi.y), fmaxf(g0hi.z, g1hi.z), 0.f);
+    const size_t cstride = (size_t)np * NC;
+
+    double acc[NCOMP][NC];
+#pragma unroll
+    for (int a = 0; a < NCOMP; ++a)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[a][c] = 0.0;
+
+    const int nchunk = np / NW_CHUNK;
+    const int cbeg = blockIdx.y * chunks_per_split;
+    const int cend = min(nchunk, cbeg + chunks_per_split);
+    for (int ch = cbeg; ch < cend; ++ch) {
+        const int j0 = ch * NW_CHUNK;
+        __syncthreads();
+        sxyz[tid] = xyz[j0 + tid];
+#pragma unroll
+        for (int a = 0; a < NCOMP; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sxv[a][tid][c] = X[a * cstride + (size_t)(j0 + tid) * NC + c];
+        __syncthreads();
+        for (int gq = 0; gq < NW_CHUNK / GROUP; ++gq) {
+            const int gidx = (j0 >> 5) + gq;
+            const int far = uniform(box_gap2(rlo, rhi, glo[gidx], ghi[gidx]) >= r_far2);
+            for (int jj = gq * GROUP; jj < (gq + 1) * GROUP; ++jj) {
+                const double4 pj = sxyz[jj];
+                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                if (MODEL == 0) {
+                    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    double rinv = rsqrt(r2);
+                    double t;
+                    if (far) {
+                        t = rinv;
+                    } else {
+                        t = erf(r2 * rinv * inv_rqq) * rinv;
+                        t = (i == j0 + jj) ? t_self : t;
+                    }
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[0][c] = fma(t, sxv[0][jj][c], acc[0][c]);
+                } else {
+                    double b[4][4];
+                    pair_block_f64(dx, dy, dz, far != 0, kc, b);
+                    if (!far && i == j0 + jj) {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) b[a][c] = 0.0;
+                        b[0][0] = kc.t_self;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c2 = 0; c2 < 4; ++c2)
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) acc[a][c] = fma(b[a][c2], sxv[c2][jj][c], acc[a][c]);
+                }
+            }
+        }
+    }
+    double* out = part + (size_t)blockIdx.y * NCOMP * cstride;
+#pragma unroll
+    for (int a = 0; a < NCOMP; ++a)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[a * cstride + (size_t)i * NC + c] = acc[a][c];
+}
+
+__global__ void k_sum_splits(const double* __restrict__ part, double* __restrict__ Y, size_t len, int nsplit)
+{
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    double s = 0.0;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + t];
+    Y[t] = s;
+}
+
+// Far-field thresholds x_far = r / R beyond which the Gaussian factors equal
+// their point limits to working precision (erfc(4) < 2^-25; erfc(6) < 2^-54;
+// for the dipole kernels the extra x^3 exp(-x^2) terms need 5 and 7).
+constexpr double XFAR_Q32 = 4.0, XFAR_Q64 = 6.0, XFAR_D32 = 5.0, XFAR_D64 = 7.0;
+
+DipoleConstD dipole_const_d(const Geometry& g)
+{
+    DipoleConstD k;
+    double rqq = std::sqrt(2.0) * g.r_q;
+    double rqm = std::sqrt(g.r_q * g.r_q + g.r_mu * g.r_mu);
+    double rmm = std::sqrt(2.0) * g.r_mu;
+    k.inv_rqq = 1.0 / rqq;
+    k.inv_rqm = 1.0 / rqm;
+    k.inv_rmm = 1.0 / rmm;
+    k.gauss_pref = 2.0 * TWO_OVER_SQRTPI / (rmm * rmm * rmm);
+    k.t_self = TWO_OVER_SQRTPI / rqq;
+    double rmax = std::fmax(rqq, std::fmax(rqm, rmm));
+    k.r_far2 = (float)((XFAR_D64 * rmax) * (XFAR_D64 * rmax));
+    return k;
+}
+
+int narrow_splits(const Geometry& g)
+{
+    int rb = (int)(g.np / 256);
+    int nchunk = (int)(g.np / NW_CHUNK);
+    int want = (2048 + rb - 1) / rb;
+    if (want < 1) want = 1;
+    if (want > nchunk) want = nchunk;
+    int cps = (nchunk + want - 1) / want;
+    return (nchunk + cps - 1) / cps;
+}
+
+template <int NC, int MODEL>
+void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch)
+{
+    int rb = (int)(g.np / 256);
+    int nchunk = (int)(g.np / NW_CHUNK);
+    int nsplit = narrow_splits(g);
+    int cps = (nchunk + nsplit - 1) / nsplit;
+    double rqq = std::sqrt(2.0) * g.r_q;
+    DipoleConstD kc = dipole_const_d(g);
+    float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
+    hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi,
+                       X, scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc);
+    size_t len = (size_t)(MODEL ? 4 : 1) * g.np * NC;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit);
+}
+
+}  // namespace
+
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st)
+{
+    if (g.model == 0) {
+        double rqq = std::sqrt(2.0) * g.r_q;
+        float rf = (float)(XFAR_Q32 * rqq);
+        hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)(g.np / 256), (unsigned)(ncols / Q32_COLS)), dim3(256),
+                           0, st, g.xyz32, g.glo, g.ghi, X, Y, (int)g.np, ldx, (float)(1.0 / rqq),
+                           (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
+    } else {
+        DipoleConstD d = dipole_const_d(g);
+        DipoleConstF k;
+        k.inv_rqq = (float)d.inv_rqq;
+        k.inv_rqm = (float)d.inv_rqm;
+        k.inv_rmm = (float)d.inv_rmm;
+        k.gauss_pref = (float)d.gauss_pref;
+        k.t_self = (float)d.t_self;
+        double rmax = 1.0 / std::fmin(d.inv_rqq, std::fmin(d.inv_rqm, d.inv_rmm));
+        k.r_far2 = (float)((XFAR_D32 * rmax) * (XFAR_D32 * rmax));
+        hipLaunchKernelGGL(k_tapply_wfqfmu_f32, dim3((unsigned)(g.np / 128), (unsigned)(ncols / D32_COLS)),
+                           dim3(256), 0, st, g.xyz32, g.glo, g.ghi, X, Y, (int)g.np, ldx, k);
+    }
+}
+
+size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
+{
+    if (ncols > 8) return 0;
+    return (size_t)narrow_splits(g) * (g.model ? 4 : 1) * g.np * ncols * sizeof(double);
+}
+
+void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
+                double* scratch, size_t scratch_bytes)
+{
+    (void)scratch_bytes;
+    if (ncols <= 8) {
+        // narrow layout: ldx == ncols
+        if (g.model == 0) {
+            switch (ncols) {
+            case 2: launch_narrow<2, 0>(g, X, Y, st, scratch); break;
+            case 4: launch_narrow<4, 0>(g, X, Y, st, scratch); break;
+            case 6: launch_narrow<6, 0>(g, X, Y, st, scratch); break;
+            default: launch_narrow<8, 0>(g, X, Y, st, scratch); break;
+            }
+        } else {
+            switch (ncols) {
+            case 2: launch_narrow<2, 1>(g, X, Y, st, scratch); break;
+            case 4: launch_narrow<4, 1>(g, X, Y, st, scratch); break;
+            case 6: launch_narrow<6, 1>(g, X, Y, st, scratch); break;
+            default: launch_narrow<8, 1>(g, X, Y, st, scratch); break;
+            }
+        }
+        return;
+    }
+    if (g.model == 0) {
+        double rqq = std::sqrt(2.0) * g.r_q;
+        float rf = (float)(XFAR_Q64 * rqq);
+        hipLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)(ncols / Q64_COLS)), dim3(256),
+                           0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, 1.0 / rqq, TWO_OVER_SQRTPI / rqq,
+                           rf * rf);
+    } else {
+        DipoleConstD k = dipole_const_d(g);
+        hipLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
+                           dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, k);
+    }
+}
+
+}  // namespace px
