@@ -83,7 +83,11 @@ typedef struct {
 
 /* Solver options (pxDefaultSolveOptions fills the defaults shown).
  *   precision        PX_MIXED (default) or PX_FP64
- *   restart_m        GMRES restart length m (50)
+ *   restart_m        GMRES restart length m at the start (50)
+ *   max_restart_m    the restart length doubles, up to this value, whenever
+ *                    some column's true residual fell by less than 30 % over
+ *                    its last cycle (restarted GMRES stagnates at the sharp
+ *                    plasmon resonances); <= restart_m keeps m fixed (200)
  *   rel_tol          per column ||b - A x||_2 / ||b||_2 target (1e-8)
  *   max_cycles       maximum number of restart cycles per column (400)
  *   max_block_cols   columns solved together in one block; 0 = all (0).
@@ -92,6 +96,9 @@ typedef struct {
  *                    estimated residual fell by this factor (1e-5); 0 = only
  *                    the rel_tol target stops it
  *   timings          1 = time each phase with HIP events (pxGetTimings) (0)
+ *   stall_cycles     a column is given up (and reported unconverged) after
+ *                    this many consecutive cycles that each removed less than
+ *                    2 % of its true residual; 0 = never (8)
  */
 typedef struct {
     int32_t precision;
@@ -101,6 +108,8 @@ typedef struct {
     int32_t max_block_cols;
     double inner_reduction;
     int32_t timings;
+    int32_t stall_cycles;
+    int32_t max_restart_m;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;

@@ -42,7 +42,8 @@ class pxMaterial(ctypes.Structure):
 class pxSolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("restart_m", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
-                ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32)]
+                ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
+                ("max_restart_m", ctypes.c_int32)]
 
 
 _lib = None
@@ -226,7 +227,7 @@ class Structure:
         self.ncol = self.n_omega * bin(pol_mask & 7).count("1")
 
     def solve(self, precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
-              inner_reduction=1e-5, timings=False):
+              inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200):
         o = pxDefaultSolveOptions()
         o.precision = int(precision)
         o.restart_m = int(restart_m)
@@ -235,6 +236,8 @@ class Structure:
         o.max_block_cols = int(max_block_cols)
         o.inner_reduction = float(inner_reduction)
         o.timings = int(bool(timings))
+        o.stall_cycles = int(stall_cycles)
+        o.max_restart_m = int(max_restart_m)
         return pxSolveSpectrum(self.h, o)
 
     def spectrum(self):

@@ -30,9 +30,6 @@ constexpr double PI = 3.14159265358979323846;
 // The solver works on Eq. (wfqfmu-system) with its dipole rows multiplied by
 // -1 (same solution, same residual norms); see k_spmm_shift.
 constexpr double SOLVER_MU_SIGN = -1.0;
-// A column is given up when this many consecutive cycles each removed less
-// than 2 % of its true residual (restarted GMRES at its rounding floor).
-constexpr int STALL_CYCLES = 5;
 
 thread_local std::string g_err;
 
@@ -85,11 +82,12 @@ struct Workspace {
     double2 *zq = nullptr, *zmu = nullptr;
     double* narrow = nullptr;
     size_t narrow_bytes = 0;
+    float* split32 = nullptr;
 
     void release()
     {
         void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, sn, gv, y, cs, nrm, target,
-                      done, steps, map, zq, zmu, narrow};
+                      done, steps, map, zq, zmu, narrow, split32};
         for (void* p : ps) dfree(p);
         *this = Workspace();
     }
@@ -146,7 +144,7 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     if (W.lda_cap >= lda && W.m_cap >= m && W.nup == nup) return;
     W.release();
     const size_t vec = (size_t)nup * lda;
-    const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    const int nchunk = px::arnoldi_chunks(nup);
     W.V = dalloc<double2>((size_t)(m + 1) * vec);
     W.w = dalloc<double2>(vec);
     W.xs = dalloc<double2>(vec);
@@ -157,7 +155,7 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.Y32 = dalloc<float>(2 * vec);
     W.Y64 = dalloc<double>(2 * vec);
     W.partial = dalloc<double2>((size_t)nchunk * (m + 1) * lda);
-    W.npart = dalloc<double>((size_t)nchunk * lda);
+    W.npart = dalloc<double>((size_t)std::max(nchunk, px::update_chunks(nup)) * lda);
     W.h1 = dalloc<double2>((size_t)(m + 1) * lda);
     W.h2 = dalloc<double2>((size_t)(m + 1) * lda);
     W.R = dalloc<double2>((size_t)m * (m + 1) * lda);
@@ -174,6 +172,7 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.zmu = dalloc<double2>(lda);
     W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, 8);
     W.narrow = dalloc<double>(W.narrow_bytes / sizeof(double) + 1);
+    W.split32 = dalloc<float>(px::tapply_f32_scratch_bytes(s->g, 2 * lda) / sizeof(float) + 1);
     W.lda_cap = lda;
     W.m_cap = m;
     W.nup = nup;
@@ -239,7 +238,7 @@ void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* r
 void col_norms(pxStructure_t* s, const double2* v, int na, int lda, std::vector<double>& out)
 {
     Workspace& W = s->ws;
-    const int nchunk = (int)((s->g.nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    const int nchunk = px::arnoldi_chunks(s->g.nup);
     px::col_norm_partial(v, W.npart, na, lda, s->g.nup, s->st);
     px::reduce_norms(W.npart, nchunk, W.nrm, na, lda, s->st);
     out.resize(na);
@@ -269,10 +268,11 @@ void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
 void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
 {
     Workspace& W = s->ws;
-    const int m = o.restart_m;
+    int m = o.restart_m;
+    const int m_max = std::max(o.restart_m, o.max_restart_m);
     const int64_t nup = s->g.nup;
     const bool mixed = o.precision == PX_MIXED;
-    const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+    const int nchunk = px::arnoldi_chunks(nup);
     Timer tm(o.timings != 0, s->st);
     std::vector<int32_t> done_h, steps_h;
     std::vector<double> beta;
@@ -289,14 +289,23 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
         residual(s, W.xs, W.bs, W.rs, na, lda);
         col_norms(s, W.rs, na, lda, beta);
         std::vector<int> keep;
+        bool slow = false;
         for (int k = 0; k < na; ++k) {
             const int c = act[k];
             const double prev = s->relres[c];
             s->relres[c] = s->bnorm[c] > 0.0 ? beta[k] / s->bnorm[c] : 0.0;
             if (s->cycles[c] > 0 && s->relres[c] > 0.98 * prev) s->stall[c] += 1;
             else s->stall[c] = 0;
-            if (s->relres[c] > o.rel_tol && s->cycles[c] < o.max_cycles && s->stall[c] < STALL_CYCLES)
+            if (s->relres[c] > o.rel_tol && s->cycles[c] < o.max_cycles &&
+                (o.stall_cycles == 0 || s->stall[c] < o.stall_cycles)) {
                 keep.push_back(k);
+                if (s->cycles[c] > 0 && s->relres[c] > 0.7 * prev) slow = true;
+            }
+        }
+        if (slow && m < m_max) {
+            // a longer Krylov space for every remaining column of the block
+            m = std::min(2 * m, m_max);
+            for (int k : keep) s->stall[act[k]] = 0;
         }
         if (keep.empty()) break;
         if ((int)keep.size() < na) {
@@ -346,7 +355,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 tm.mark(0);
                 const bool wide32 = mixed && lda > 4;
                 if (wide32) {
-                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st);
+                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32);
                     s->counts[0] += 1;
                     s->counts[1] += 2 * lda;
                     s->counts[2] += 2 * na;
@@ -368,7 +377,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
                 px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
                 px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
-                px::reduce_norms(W.npart, nchunk, W.nrm, na, lda, s->st);
+                px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st);
                 px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, nullptr,
                                 na, lda, s->st);
                 px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride, mixed ? W.X32 : nullptr, na, lda, nup,
@@ -403,8 +412,10 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
 pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
 {
     if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrum: call pxSetFrequencies first");
-    if (o.restart_m < 1 || o.restart_m > 1000) return fail(PX_E_INVALID, "restart_m must be in [1, 1000]");
+    if (o.restart_m < 1 || o.restart_m > 1000 || o.max_restart_m > 1000)
+        return fail(PX_E_INVALID, "restart_m and max_restart_m must be in [1, 1000]");
     if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
+        o.stall_cycles < 0 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     auto t0 = std::chrono::steady_clock::now();
@@ -412,7 +423,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     for (int64_t& v : s->counts) v = 0;
     const int ncol = s->ncol;
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
-    ensure_workspace(s, pad_cols(blk, true), o.restart_m);
+    ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
     const int64_t nup = s->g.nup;
     // right-hand sides, x = 0, ||b||
     px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
@@ -421,7 +432,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
         std::vector<double> bn;
         // reuse the norm kernels over the global layout in slices of the workspace width
         s->bnorm.assign(ncol, 0.0);
-        const int nchunk = (int)((nup + px::RED_ROWS - 1) / px::RED_ROWS);
+        const int nchunk = px::arnoldi_chunks(nup);
         double* part = dalloc<double>((size_t)nchunk * s->ldg);
         double* nr = dalloc<double>(s->ldg);
         px::col_norm_partial(s->b, part, ncol, s->ldg, nup, s->st);
@@ -498,6 +509,8 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->max_block_cols = 0;
     o->inner_reduction = 1e-5;
     o->timings = 0;
+    o->stall_cycles = 8;
+    o->max_restart_m = 200;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }
@@ -717,7 +730,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
         HC(hipMemcpyAsync(W.zmu, zm.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
         if (mixed) {
             px::to_f32(W.xs, W.X32, ncol, lda, nup, s->st);
-            px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st);
+            px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32);
             px::spmm_shift(s->g, W.Y32, true, 2 * lda, W.xs, W.zq, W.zmu, nullptr, W.w, ncol, lda, 1.0, s->st);
         } else {
             px::tapply_f64(s->g, reinterpret_cast<const double*>(W.xs), W.Y64, 2 * lda, 2 * lda, s->st, W.narrow,

@@ -18,8 +18,17 @@ constexpr int ATOM_PAD = 256;
 constexpr int GROUP = 32;
 // Complex columns of every active block are padded to a multiple of this.
 constexpr int COL_PAD = 64;
-// Rows per partial-sum chunk of the column reductions (dots, norms).
+// Rows per partial-sum chunk of the dipole reduction.
 constexpr int RED_ROWS = 64;
+// Rows per partial-sum chunk of the Arnoldi reductions (dots, norms), basis
+// vectors per dot-product block, rows per thread in the basis update.
+constexpr int ARN_ROWS = 256;
+constexpr int ARN_JB = 8;
+constexpr int ARN_RG = 8;
+inline int arnoldi_chunks(int64_t rows) { return (int)((rows + ARN_ROWS - 1) / ARN_ROWS); }
+// Rows per block of the basis update (its norm partials come in these chunks).
+constexpr int UPD_ROWS = 4 * ARN_RG;
+inline int update_chunks(int64_t rows) { return (int)((rows + UPD_ROWS - 1) / UPD_ROWS); }
 
 struct Geometry {
     int model = 0;         // 0 omegaFQ, 1 omegaFQFmu
@@ -44,7 +53,9 @@ struct Geometry {
 // Y = T X over real columns: X, Y are [nup][ldx] (row-major, component-major
 // blocks for the dipole model); ncols real columns, multiple of 2*COL_PAD for
 // the wide kernels.  Ghost rows of Y are unspecified.
-void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st);
+// scratch: tapply_f32_scratch_bytes(g, ncols) bytes (split-K partial sums).
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch);
+size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols);
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
                 double* scratch, size_t scratch_bytes);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
@@ -67,6 +78,7 @@ void col_dots(const double2* V, int64_t vstride, int nvec, const double2* w, dou
               int64_t nup, hipStream_t st);
 void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int na, int lda, bool accumulate,
                  hipStream_t st);
+// norm_partial (may be null): update_chunks(nup) x lda partial sums of |w|^2.
 void col_update(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
                 int na, int lda, int64_t nup, hipStream_t st);
 void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st);

@@ -326,25 +326,53 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ rp, con
 
 // ---------------------------------------------------------------- Arnoldi
 
-// partial[chunk][j][c] = sum over the chunk's rows of conj(V_j[r][c]) w[r][c]
-__global__ __launch_bounds__(64) void k_col_dots(const double2* __restrict__ V, int64_t vstride, int nvec,
-                                                 const double2* __restrict__ w, double2* __restrict__ partial,
-                                                 int na, int lda, int64_t nup)
+// Column reductions over chunks of ARN_ROWS rows: a 256-thread block (4 waves
+// x 64 columns) covers one chunk; wave w takes rows w, w+4, ... and the four
+// wave sums are added in a fixed order through LDS.
+
+// partial[chunk][j][c] = sum over the chunk's rows of conj(V_j[r][c]) w[r][c],
+// for the ARN_JB basis vectors j0.. of this block (grid.z).
+__global__ __launch_bounds__(256) void k_col_dots(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                  const double2* __restrict__ w, double2* __restrict__ partial,
+                                                  int na, int lda, int64_t nup)
 {
-    const int c = blockIdx.y * 64 + threadIdx.x;
-    if (c >= na) return;
-    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
-    const int64_t r1 = min(nup, r0 + RED_ROWS);
-    for (int j = 0; j < nvec; ++j) {
-        const double2* vj = V + j * vstride;
-        double ar = 0.0, ai = 0.0;
-        for (int64_t r = r0; r < r1; ++r) {
-            const double2 v = vj[(size_t)r * lda + c];
+    __shared__ double2 red[4][ARN_JB][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
+    const int j0 = blockIdx.z * ARN_JB;
+    const int nj = min(ARN_JB, nvec - j0);
+    const int64_t r0 = (int64_t)blockIdx.x * ARN_ROWS;
+    const int64_t r1 = min(nup, r0 + ARN_ROWS);
+    double ar[ARN_JB], ai[ARN_JB];
+#pragma unroll
+    for (int q = 0; q < ARN_JB; ++q) ar[q] = ai[q] = 0.0;
+    if (c < na) {
+        const double2* vb = V + (size_t)j0 * vstride + c;
+        for (int64_t r = r0 + wave; r < r1; r += 4) {
             const double2 x = w[(size_t)r * lda + c];
-            ar = fma(v.x, x.x, fma(v.y, x.y, ar));
-            ai = fma(v.x, x.y, fma(-v.y, x.x, ai));
+#pragma unroll
+            for (int q = 0; q < ARN_JB; ++q) {
+                if (q < nj) {
+                    const double2 v = vb[(size_t)q * vstride + (size_t)r * lda];
+                    ar[q] = fma(v.x, x.x, fma(v.y, x.y, ar[q]));
+                    ai[q] = fma(v.x, x.y, fma(-v.y, x.x, ai[q]));
+                }
+            }
         }
-        partial[((size_t)blockIdx.x * nvec + j) * lda + c] = make_double2(ar, ai);
+    }
+#pragma unroll
+    for (int q = 0; q < ARN_JB; ++q) red[wave][q][lane] = make_double2(ar[q], ai[q]);
+    __syncthreads();
+    if (wave == 0 && c < na) {
+        for (int q = 0; q < nj; ++q) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sr += red[k][q][lane].x;
+                si += red[k][q][lane].y;
+            }
+            partial[((size_t)blockIdx.x * nvec + j0 + q) * lda + c] = make_double2(sr, si);
+        }
     }
 }
 
@@ -364,53 +392,104 @@ __global__ void k_reduce_dots(const double2* __restrict__ partial, int nchunk, i
     h[(size_t)j * lda + c] = make_double2(ar, ai);
 }
 
-// w -= sum_j V_j h_j (per column), optionally with per-chunk partial |w|^2.
-__global__ __launch_bounds__(64) void k_col_update(const double2* __restrict__ V, int64_t vstride, int nvec,
-                                                   const double2* __restrict__ h, double2* __restrict__ w,
-                                                   double* __restrict__ norm_partial, int na, int lda, int64_t nup)
+// w -= sum_j V_j h_j (per column); with norm_partial, also |w|^2 per chunk of
+// UPD_ROWS rows.  A 256-thread block covers UPD_ROWS rows x 64 columns; each
+// wave updates ARN_RG consecutive rows, so every h_j load feeds ARN_RG basis
+// loads, and the basis loop is unrolled by two for more loads in flight.
+__global__ __launch_bounds__(256) void k_col_update(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                    const double2* __restrict__ h, double2* __restrict__ w,
+                                                    double* __restrict__ norm_partial, int na, int lda, int64_t nup)
 {
-    const int c = blockIdx.y * 64 + threadIdx.x;
-    if (c >= na) return;
-    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
-    const int64_t r1 = min(nup, r0 + RED_ROWS);
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
+    const int64_t rg = (int64_t)blockIdx.x * UPD_ROWS + wave * ARN_RG;
+    const int nr = (int)max((int64_t)0, min((int64_t)ARN_RG, nup - rg));
     double nrm = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-        double2 acc = w[(size_t)r * lda + c];
-        for (int j = 0; j < nvec; ++j) {
-            const double2 v = V[j * vstride + (size_t)r * lda + c];
-            const double2 hj = h[(size_t)j * lda + c];
-            acc.x -= v.x * hj.x - v.y * hj.y;
-            acc.y -= v.x * hj.y + v.y * hj.x;
+    if (c < na && nr > 0) {
+        double2 acc[ARN_RG];
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q)
+            acc[q] = (q < nr) ? w[(size_t)(rg + q) * lda + c] : make_double2(0.0, 0.0);
+        const double2* vb = V + (size_t)rg * lda + c;
+        int j = 0;
+        for (; j + 1 < nvec; j += 2) {
+            const double2 h0 = h[(size_t)j * lda + c];
+            const double2 h1 = h[(size_t)(j + 1) * lda + c];
+            const double2* v0 = vb + (size_t)j * vstride;
+            const double2* v1 = v0 + vstride;
+#pragma unroll
+            for (int q = 0; q < ARN_RG; ++q) {
+                if (q < nr) {
+                    const double2 a = v0[(size_t)q * lda];
+                    const double2 b = v1[(size_t)q * lda];
+                    acc[q].x -= (a.x * h0.x - a.y * h0.y) + (b.x * h1.x - b.y * h1.y);
+                    acc[q].y -= (a.x * h0.y + a.y * h0.x) + (b.x * h1.y + b.y * h1.x);
+                }
+            }
         }
-        w[(size_t)r * lda + c] = acc;
-        nrm = fma(acc.x, acc.x, fma(acc.y, acc.y, nrm));
+        if (j < nvec) {
+            const double2 h0 = h[(size_t)j * lda + c];
+            const double2* v0 = vb + (size_t)j * vstride;
+#pragma unroll
+            for (int q = 0; q < ARN_RG; ++q) {
+                if (q < nr) {
+                    const double2 a = v0[(size_t)q * lda];
+                    acc[q].x -= a.x * h0.x - a.y * h0.y;
+                    acc[q].y -= a.x * h0.y + a.y * h0.x;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q) {
+            if (q < nr) {
+                w[(size_t)(rg + q) * lda + c] = acc[q];
+                nrm = fma(acc[q].x, acc[q].x, fma(acc[q].y, acc[q].y, nrm));
+            }
+        }
     }
-    if (norm_partial) norm_partial[(size_t)blockIdx.x * lda + c] = nrm;
+    if (norm_partial) {
+        red[wave][lane] = nrm;
+        __syncthreads();
+        if (wave == 0 && c < na)
+            norm_partial[(size_t)blockIdx.x * lda + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    }
 }
 
-__global__ __launch_bounds__(64) void k_col_norm_partial(const double2* __restrict__ w, double* __restrict__ partial,
-                                                         int na, int lda, int64_t nup)
+__global__ __launch_bounds__(256) void k_col_norm_partial(const double2* __restrict__ w, double* __restrict__ partial,
+                                                          int na, int lda, int64_t nup)
 {
-    const int c = blockIdx.y * 64 + threadIdx.x;
-    if (c >= na) return;
-    const int64_t r0 = (int64_t)blockIdx.x * RED_ROWS;
-    const int64_t r1 = min(nup, r0 + RED_ROWS);
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
+    const int64_t r0 = (int64_t)blockIdx.x * ARN_ROWS;
+    const int64_t r1 = min(nup, r0 + ARN_ROWS);
     double nrm = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-        const double2 a = w[(size_t)r * lda + c];
-        nrm = fma(a.x, a.x, fma(a.y, a.y, nrm));
-    }
-    partial[(size_t)blockIdx.x * lda + c] = nrm;
+    if (c < na)
+        for (int64_t r = r0 + wave; r < r1; r += 4) {
+            const double2 a = w[(size_t)r * lda + c];
+            nrm = fma(a.x, a.x, fma(a.y, a.y, nrm));
+        }
+    red[wave][lane] = nrm;
+    __syncthreads();
+    if (wave == 0 && c < na)
+        partial[(size_t)blockIdx.x * lda + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-__global__ void k_reduce_norms(const double* __restrict__ partial, int nchunk, double* __restrict__ nrm, int na,
-                               int lda)
+// nrm[c] = sqrt(sum_k partial[k][c]); 256 threads = 64 columns x 4 waves, wave
+// w sums chunks w, w+4, ...; the four sums are combined in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_norms(const double* __restrict__ partial, int nchunk,
+                                                      double* __restrict__ nrm, int na, int lda)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= na) return;
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += partial[(size_t)k * lda + c];
-    nrm[c] = sqrt(s);
+    if (c < na)
+        for (int k = wave; k < nchunk; k += 4) s += partial[(size_t)k * lda + c];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && c < na) nrm[c] = sqrt(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 // v = w / ||w|| (zero for finished or padded columns), plus the FP32 copy in
@@ -656,6 +735,7 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words)
 
 inline dim3 grid_rows_cols(int64_t rows, int cols) { return dim3((unsigned)((rows + 3) / 4), (unsigned)((cols + 63) / 64)); }
 inline int nchunks(int64_t rows) { return (int)((rows + RED_ROWS - 1) / RED_ROWS); }
+inline int arn_chunks(int64_t rows) { return (int)((rows + ARN_ROWS - 1) / ARN_ROWS); }
 
 }  // namespace
 
@@ -765,8 +845,8 @@ void build_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b,
 void col_dots(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
               int64_t nup, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_col_dots, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, V, vstride,
-                       nvec, w, partial, na, lda, nup);
+    hipLaunchKernelGGL(k_col_dots, dim3(arn_chunks(nup), (unsigned)((na + 63) / 64), (unsigned)((nvec + ARN_JB - 1) / ARN_JB)),
+                       dim3(256), 0, st, V, vstride, nvec, w, partial, na, lda, nup);
 }
 
 void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int na, int lda, bool, hipStream_t st)
@@ -779,20 +859,20 @@ void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int n
 void col_update(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
                 int na, int lda, int64_t nup, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_col_update, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, V, vstride,
-                       nvec, h, w, norm_partial, na, lda, nup);
+    hipLaunchKernelGGL(k_col_update, dim3(update_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, V,
+                       vstride, nvec, h, w, norm_partial, na, lda, nup);
 }
 
 void col_norm_partial(const double2* w, double* partial, int na, int lda, int64_t nup, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_col_norm_partial, dim3(nchunks(nup), (unsigned)((na + 63) / 64)), dim3(64), 0, st, w,
+    hipLaunchKernelGGL(k_col_norm_partial, dim3(arn_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, w,
                        partial, na, lda, nup);
 }
 
 void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_norms, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, partial, nchunk, nrm,
-                       na, lda);
+    hipLaunchKernelGGL(k_reduce_norms, dim3((unsigned)((na + 63) / 64)), dim3(256), 0, st, partial, nchunk, nrm, na,
+                       lda);
 }
 
 void normalize(const double2* w, const double* nrm, const int32_t* done, double2* v, float* x32, int na, int lda,

@@ -70,12 +70,28 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 constexpr int Q32_COLS = 128;
 constexpr int Q32_JC = 32;
 
+// The source atoms are split over gridDim.z (split-K); split z writes its
+// partial sums to Y + z * zstride and k_sum_splits_f32 adds them in a fixed
+// order.  The split count depends only on the atom count, so a column's
+// arithmetic does not depend on which other columns share the launch.
+__device__ __forceinline__ void mfma8(f32x16 (&acc)[2][4], float a0, float a1, float4 b)
+{
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.x, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.y, acc[0][1], 0, 0, 0);
+    acc[0][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.z, acc[0][2], 0, 0, 0);
+    acc[0][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.w, acc[0][3], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.x, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.y, acc[1][1], 0, 0, 0);
+    acc[1][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.z, acc[1][2], 0, 0, 0);
+    acc[1][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.w, acc[1][3], 0, 0, 0);
+}
+
 __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
                                                         const float4* __restrict__ glo,
                                                         const float4* __restrict__ ghi,
                                                         const float* __restrict__ X, float* __restrict__ Y,
-                                                        int np, int ldx, float inv_rqq, float t_self,
-                                                        float r_far2)
+                                                        int np, int ldx, int chunks_per_split, size_t zstride,
+                                                        float inv_rqq, float t_self, float r_far2)
 {
     __shared__ __attribute__((aligned(16))) float sx[2][Q32_JC][Q32_COLS];
     __shared__ float4 sxyz[2][Q32_JC];
@@ -85,18 +101,21 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict
     const int wave = tid >> 6;
     const int row0 = blockIdx.x * 256 + wave * 64;
     const int col0 = blockIdx.y * Q32_COLS;
+    const int nchunk = np / Q32_JC;
+    const int cbeg = blockIdx.z * chunks_per_split;
+    const int cend = min(nchunk, cbeg + chunks_per_split);
+    Y += blockIdx.z * zstride;
 
     float xi[2], yi[2], zi[2];
     int ii[2];
-    float4 rlo[2], rhi[2];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
         ii[rb] = row0 + rb * 32 + (lane & 31);
         float4 p = xyz[ii[rb]];
         xi[rb] = p.x; yi[rb] = p.y; zi[rb] = p.z;
-        rlo[rb] = glo[(row0 >> 5) + rb];
-        rhi[rb] = ghi[(row0 >> 5) + rb];
     }
+    const float4 rlo0 = glo[row0 >> 5], rhi0 = ghi[row0 >> 5];
+    const float4 rlo1 = glo[(row0 >> 5) + 1], rhi1 = ghi[(row0 >> 5) + 1];
 
     f32x16 acc[2][4];
 #pragma unroll
@@ -109,65 +128,73 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict
     // cooperative tile load: thread -> (row tid/8, 16 columns at 16*(tid%8))
     const int lr = tid >> 3;
     const int lc = (tid & 7) * 16;
-    const int nchunk = np / Q32_JC;
-    {
-        const float4* src = reinterpret_cast<const float4*>(X + (size_t)lr * ldx + col0 + lc);
+    if (cbeg < cend) {
+        const int j0 = cbeg * Q32_JC;
+        const float4* src = reinterpret_cast<const float4*>(X + (size_t)(j0 + lr) * ldx + col0 + lc);
         float4* dst = reinterpret_cast<float4*>(&sx[0][lr][lc]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) dst[q] = src[q];
-        if (tid < Q32_JC) sxyz[0][tid] = xyz[tid];
+        if (tid < Q32_JC) sxyz[0][tid] = xyz[j0 + tid];
     }
     __syncthreads();
 
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
+    for (int ch = cbeg; ch < cend; ++ch) {
+        const int buf = (ch - cbeg) & 1;
         const int j0 = ch * Q32_JC;
-        const bool more = (ch + 1) < nchunk;
-        float4 pre[4];
-        float4 prexyz = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (more) {
-            const float4* src = reinterpret_cast<const float4*>(X + (size_t)(j0 + Q32_JC + lr) * ldx + col0 + lc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pre[q] = src[q];
-            if (tid < Q32_JC) prexyz = xyz[j0 + Q32_JC + tid];
-        }
+        const bool more = (ch + 1) < cend;
+        // next chunk: global -> registers now, registers -> LDS in mid-loop
+        // (on the last chunk the loads re-read this chunk's rows and are never stored)
+        const int jn = more ? j0 + Q32_JC : j0;
+        const float4* nsrc = reinterpret_cast<const float4*>(X + (size_t)(jn + lr) * ldx + col0 + lc);
+        const float4 pre0 = nsrc[0];
+        const float4 pre1 = nsrc[1];
+        const float4 pre2 = nsrc[2];
+        const float4 pre3 = nsrc[3];
+        const float4 prexyz = xyz[jn + (tid & (Q32_JC - 1))];
         const float4 clo = glo[ch];
         const float4 chi = ghi[ch];
-        int far[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb) far[rb] = uniform(box_gap2(rlo[rb], rhi[rb], clo, chi) >= r_far2);
+        const int far0 = uniform(box_gap2(rlo0, rhi0, clo, chi) >= r_far2);
+        const int far1 = uniform(box_gap2(rlo1, rhi1, clo, chi) >= r_far2);
+        const int half = lane >> 5;
+        const int col4 = 4 * (lane & 31);
 
-#pragma unroll 4
+        const int allfar = far0 & far1;
+        // operands of the next k-step are read from LDS before this step's MFMAs
+        float4 pj = sxyz[buf][half];
+        float4 bq = *reinterpret_cast<const float4*>(&sx[buf][half][col4]);
+#pragma unroll
         for (int kk = 0; kk < Q32_JC / 2; ++kk) {
-            const int jr = 2 * kk + (lane >> 5);
-            const float4 pj = sxyz[buf][jr];
-            const float4 bq = *reinterpret_cast<const float4*>(&sx[buf][jr][4 * (lane & 31)]);
-            float a[2];
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                float dx = xi[rb] - pj.x, dy = yi[rb] - pj.y, dz = zi[rb] - pj.z;
-                float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float rinv = __builtin_amdgcn_rsqf(r2);
-                if (far[rb]) {
-                    a[rb] = rinv;
-                } else {
-                    float t = erf_as(r2 * rinv * inv_rqq) * rinv;
-                    a[rb] = (ii[rb] == j0 + jr) ? t_self : t;
-                }
+            float4 pjn = pj, bqn = bq;
+            if (kk + 1 < Q32_JC / 2) {
+                pjn = sxyz[buf][2 * kk + 2 + half];
+                bqn = *reinterpret_cast<const float4*>(&sx[buf][2 * kk + 2 + half][col4]);
             }
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                acc[rb][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.x, acc[rb][0], 0, 0, 0);
-                acc[rb][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.y, acc[rb][1], 0, 0, 0);
-                acc[rb][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.z, acc[rb][2], 0, 0, 0);
-                acc[rb][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rb], bq.w, acc[rb][3], 0, 0, 0);
+            const float dx0 = xi[0] - pj.x, dy0 = yi[0] - pj.y, dz0 = zi[0] - pj.z;
+            const float dx1 = xi[1] - pj.x, dy1 = yi[1] - pj.y, dz1 = zi[1] - pj.z;
+            const float r20 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
+            const float r21 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
+            float a0 = __builtin_amdgcn_rsqf(r20);
+            float a1 = __builtin_amdgcn_rsqf(r21);
+            if (!allfar) {
+                // Gaussian near field (wave-uniform branch; only the A values change)
+                const int j = j0 + 2 * kk + half;
+                const float t0 = erf_as(r20 * a0 * inv_rqq) * a0;
+                const float t1 = erf_as(r21 * a1 * inv_rqq) * a1;
+                a0 = far0 ? a0 : ((ii[0] == j) ? t_self : t0);
+                a1 = far1 ? a1 : ((ii[1] == j) ? t_self : t1);
             }
-        }
-        if (more) {
-            float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
-            if (tid < Q32_JC) sxyz[buf ^ 1][tid] = prexyz;
+            mfma8(acc, a0, a1, bq);
+            pj = pjn;
+            bq = bqn;
+            if (kk == Q32_JC / 4 && more) {
+                // the other buffer was released at the previous barrier
+                float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
+                dst[0] = pre0;
+                dst[1] = pre1;
+                dst[2] = pre2;
+                dst[3] = pre3;
+                if (tid < Q32_JC) sxyz[buf ^ 1][tid] = prexyz;
+            }
         }
         __syncthreads();
     }
@@ -180,6 +207,20 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict
             float4 o = make_float4(acc[rb][0][v], acc[rb][1][v], acc[rb][2][v], acc[rb][3][v]);
             *reinterpret_cast<float4*>(Y + (size_t)i * ldx + col0 + 4 * (lane & 31)) = o;
         }
+}
+
+// Y[t] = sum_{z < nsplit} P[z][t], in order.
+__global__ void k_sum_splits_f32(const float* __restrict__ P, float* __restrict__ Y, size_t len, size_t zstride,
+                                 int nsplit)
+{
+    size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (t >= len) return;
+    float4 s = *reinterpret_cast<const float4*>(P + t);
+    for (int z = 1; z < nsplit; ++z) {
+        const float4 v = *reinterpret_cast<const float4*>(P + z * zstride + t);
+        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+    *reinterpret_cast<float4*>(Y + t) = s;
 }
 
 // ========================== omegaFQFmu, FP32 MFMA ===========================
@@ -744,16 +785,44 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit);
 }
 
+int f32_splits(const Geometry& g)
+{
+    // about 512 row-block x split workgroups per column block, at least 8 source chunks each
+    const int rb = (int)(g.np / 256);
+    const int nchunk = (int)(g.np / Q32_JC);
+    int sp = (512 + rb - 1) / rb;
+    sp = std::max(1, std::min(sp, nchunk / 8));
+    const int cps = (nchunk + sp - 1) / sp;
+    return (nchunk + cps - 1) / cps;
+}
+
 }  // namespace
 
-void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st)
+size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols)
+{
+    if (g.model != 0) return 0;
+    const int sp = f32_splits(g);
+    return sp > 1 ? (size_t)sp * g.np * ncols * sizeof(float) : 0;
+}
+
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch)
 {
     if (g.model == 0) {
         double rqq = std::sqrt(2.0) * g.r_q;
         float rf = (float)(XFAR_Q32 * rqq);
-        hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)(g.np / 256), (unsigned)(ncols / Q32_COLS)), dim3(256),
-                           0, st, g.xyz32, g.glo, g.ghi, X, Y, (int)g.np, ldx, (float)(1.0 / rqq),
-                           (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
+        const int nchunk = (int)(g.np / Q32_JC);
+        const int sp = f32_splits(g);
+        const int cps = (nchunk + sp - 1) / sp;
+        const size_t zstride = (size_t)g.np * ldx;
+        float* dst = sp > 1 ? scratch : Y;
+        hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)(g.np / 256), (unsigned)(ncols / Q32_COLS), (unsigned)sp),
+                           dim3(256), 0, st, g.xyz32, g.glo, g.ghi, X, dst, (int)g.np, ldx, cps, zstride,
+                           (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
+        if (sp > 1) {
+            const size_t len = (size_t)g.np * ldx;
+            hipLaunchKernelGGL(k_sum_splits_f32, dim3((unsigned)((len / 4 + 255) / 256)), dim3(256), 0, st, scratch, Y,
+                               len, zstride, sp);
+        }
     } else {
         DipoleConstD d = dipole_const_d(g);
         DipoleConstF k;

@@ -55,7 +55,7 @@ def test_struct_layouts_match_header(tmp_path):
 def test_default_options(lib):
     o = px.pxDefaultSolveOptions()
     assert (o.precision, o.restart_m, o.rel_tol, o.max_cycles, o.max_block_cols) == (px.PX_MIXED, 50, 1e-8, 400, 0)
-    assert o.inner_reduction == 1e-5 and o.timings == 0
+    assert o.inner_reduction == 1e-5 and o.timings == 0 and o.stall_cycles == 8
 
 
 def _mat():
