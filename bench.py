@@ -58,6 +58,21 @@ def one_step(px, case, precision, timings, max_block_cols=0, cols=None):
     return dict(status=st, sigma=sigma, alpha=alpha, iters=it, cycles=cyc, relres=rr, timings=tm)
 
 
+def measured_traffic(kernel_src, summary):
+    """HBM bytes per full-width launch from the committed counter summary, or
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+    except OSError:
+        return None, None
+    kv = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("-", "#")))
+    if kv.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None, None
+    return int(kv["traffic_bytes_per_launch"]), int(kv["traffic_launch_real_columns"])
+
+
 def cpu_baseline(case, lu_steps):
     """Oracle on the host: dense assembly of A(w) for one frequency of the
     workload plus the first lu_steps elimination steps of its LU; the full
@@ -99,6 +114,10 @@ def main():
     ap.add_argument("--no-fp64-blocked", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lu-steps", type=int, default=4)
+    ap.add_argument("--kernel-sample", action="store_true",
+                    help="one restart cycle of 4 steps on the full workload (hardware-counter runs)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only copy this many GiB device-to-device (scales HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box here has a single MI355X and the solver does not shard; "
@@ -107,6 +126,15 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+        return
     px = ensure_built()
     import paper_2510_12731_amd as pxm
     from workloads import configs as C
@@ -114,6 +142,15 @@ def main():
     case = C.sphere_20k(args.n, args.n_omega)
     ncol = len(case["omega_ev"]) * bin(case["pol_mask"]).count("1")
     log(f"[bench] workload {case['name']}: N={len(case['xyz'])}, {ncol} columns")
+    if args.kernel_sample:
+        s = pxm.Structure(case["model"], case["xyz"], case["params"], pxm.default_stream())
+        s.set_frequencies(case["omega_ev"], case["pol_mask"], case["e0"])
+        st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True)
+        tm = s.timings()
+        s.close()
+        print(json.dumps({"kernel_sample": True, "status": int(st), "tapply_f32_launches": int(tm["n_tapply_f32"]),
+                          "cols_f32_padded": int(tm["cols_f32_padded"])}), flush=True)
+        return
 
     for w in range(args.warmup):
         r = one_step(pxm, case, pxm.PX_MIXED, True)
@@ -140,8 +177,13 @@ def main():
     ms_t = sum(r["timings"]["ms_tapply_f32"] for r in runs)
     flops = 2.0 * n * n * cols
     achieved = flops / (ms_t * 1e-3) / 1e12 if ms_t > 0 else 0.0
+    traffic, traffic_cols = measured_traffic("paper_2510_12731_amd/csrc/px_tapply.hip",
+                                             "tapply_f32_sphere20k_hbm_counters.md")
     roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), traffic=None,
+                frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), traffic=traffic,
+                traffic_note=(None if traffic is None else
+                              f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
+                              f"algorithmic {2 * 4 * len(case['xyz']) * traffic_cols} B"),
                 kernel="k_tapply_wfq_f32", launches=int(n_launch),
                 avg_launch_ms=round(ms_t / max(n_launch, 1), 4),
                 avg_algorithmic_gflop_per_launch=round(flops / max(n_launch, 1) / 1e9, 2))
@@ -199,7 +241,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 MFMA T-apply + f64 refinement",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": case["name"], "n_atoms": n, "n_omega": int(len(case["omega_ev"])),
                    "polarizations": 3, "columns": ncol, "restart_m": 50, "rel_tol": 1e-8},
