@@ -96,6 +96,9 @@ typedef struct {
  *                    estimated residual fell by this factor (1e-5); 0 = only
  *                    the rel_tol target stops it
  *   timings          1 = time each phase with HIP events (pxGetTimings) (0)
+ *   block_cols       columns per segment of the stacked multi-structure block
+ *                    used by pxSolveBatch and the server (multiple of 64;
+ *                    0 = 64)
  *   stall_cycles     a column is given up (and reported unconverged) after
  *                    this many consecutive cycles that each removed less than
  *                    2 % of its true residual; 0 = never (8)
@@ -110,6 +113,7 @@ typedef struct {
     int32_t timings;
     int32_t stall_cycles;
     int32_t max_restart_m;
+    int32_t block_cols;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;
@@ -141,10 +145,48 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
  * missed rel_tol within max_cycles (results stay readable). */
 pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt);
 
-/* Solves several structures; each keeps its own options-independent state.
- * Structures are processed with their columns interleaved on the device
- * (see the batched launch in the implementation notes). */
+/* Solves several structures together (all must use the same HIP stream and
+ * have their frequencies set).  Every structure's columns are cut into
+ * segments of opt->block_cols columns; the segments of all structures form one
+ * stacked block whose Arnoldi steps run as single grouped launches (one
+ * T-apply over a tile list covering every structure, one sparse apply, one
+ * pass of each orthogonalisation kernel), with segments retiring at restart
+ * boundaries.  Results are read per structure with pxGet*.  Returns
+ * PX_E_NOTCONV if any column of any structure missed rel_tol. */
 pxStatus pxSolveBatch(const pxStructure* s, int32_t n, const pxSolveOptions* opt);
+
+/* ---- continuous batching ----------------------------------------------------
+ * A server keeps one stacked block resident on the device and runs restart
+ * cycles over it.  Structures submitted while others are being solved join
+ * the block at the next cycle boundary if their segments fit the memory
+ * budget (first come, first served); finished structures leave at cycle
+ * boundaries, so requests of different sizes overlap on the device.
+ * Structures stay owned by the caller and must outlive their time in the
+ * server; their results are read with pxGet* once pxServerStep returned them.
+ * Calls on one server are not thread-safe. */
+typedef struct pxServer_t* pxServer;
+
+/* memory_budget_bytes bounds the server's resident Krylov storage (the basis
+ * of the largest restart length and the block's vectors); opt as for
+ * pxSolveSpectrum (may be NULL), including block_cols.  The stream is the
+ * one every submitted structure must use. */
+pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out);
+
+/* Queues a structure whose frequencies are set.  PX_E_OOM if it can never fit
+ * the budget; PX_E_INVALID for a different stream. */
+pxStatus pxServerSubmit(pxServer sv, pxStructure s);
+
+/* Admits queued structures that fit, runs one restart cycle, and writes up to
+ * max_finished structures that completed into finished[] (*n_finished of
+ * them; more are returned by later calls).  With nothing queued or active it
+ * returns at once with *n_finished = 0. */
+pxStatus pxServerStep(pxServer sv, pxStructure* finished, int32_t max_finished, int32_t* n_finished);
+
+/* Queue length, structures in the block, rows in use and row capacity. */
+pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_t* rows_in_use,
+                       int64_t* rows_capacity);
+
+void pxServerDestroy(pxServer sv);
 
 /* Induced charges q (2*n_atoms doubles) and, for PX_WFQFMU, dipoles mu
  * (6*n_atoms doubles: mu_x, mu_y, mu_z blocks) of column (i_omega, pol) in

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV",
 
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings",
-            "pxDestroyStructure", "pxLastError"]
+            "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
+            "pxServerQuery", "pxServerDestroy"]
 
 
 class PxError(RuntimeError):
@@ -43,7 +44,7 @@ class pxSolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("restart_m", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
                 ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
-                ("max_restart_m", ctypes.c_int32)]
+                ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32)]
 
 
 _lib = None
@@ -72,12 +73,19 @@ def load(path: str = LIB_PATH):
     lib.pxApplyOperator.argtypes = [_vp, i32, i32, _dp, _dp, _dp, _dp]
     lib.pxGetSize.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pxGetTimings.argtypes = [_vp, _dp, ctypes.POINTER(i64)]
+    lib.pxServerCreate.argtypes = [ctypes.c_double, ctypes.POINTER(pxSolveOptions), _vp, ctypes.POINTER(_vp)]
+    lib.pxServerSubmit.argtypes = [_vp, _vp]
+    lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
+    lib.pxServerQuery.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64)]
+    lib.pxServerDestroy.argtypes = [_vp]
+    lib.pxServerDestroy.restype = None
     lib.pxDestroyStructure.argtypes = [_vp]
     lib.pxDestroyStructure.restype = None
     lib.pxLastError.argtypes = []
     lib.pxLastError.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("pxDefaultSolveOptions", "pxDestroyStructure", "pxLastError"):
+        if name not in ("pxDefaultSolveOptions", "pxDestroyStructure", "pxLastError", "pxServerDestroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,7 +216,85 @@ def pxLastError():
     return load().pxLastError().decode()
 
 
+def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
+                  inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0):
+    o = pxDefaultSolveOptions()
+    o.precision = int(precision)
+    o.restart_m = int(restart_m)
+    o.rel_tol = float(rel_tol)
+    o.max_cycles = int(max_cycles)
+    o.max_block_cols = int(max_block_cols)
+    o.inner_reduction = float(inner_reduction)
+    o.timings = int(bool(timings))
+    o.stall_cycles = int(stall_cycles)
+    o.max_restart_m = int(max_restart_m)
+    o.block_cols = int(block_cols)
+    return o
+
+
+def pxServerCreate(memory_budget_bytes, opt=None, hip_stream=None):
+    h = _vp()
+    _check(load().pxServerCreate(float(memory_budget_bytes), None if opt is None else ctypes.byref(opt), hip_stream,
+                                 ctypes.byref(h)))
+    return h
+
+
+def pxServerSubmit(sv, h):
+    _check(load().pxServerSubmit(sv, h))
+
+
+def pxServerStep(sv, max_finished=64):
+    arr = (_vp * max_finished)()
+    n = ctypes.c_int32()
+    _check(load().pxServerStep(sv, arr, max_finished, ctypes.byref(n)))
+    return [arr[k] for k in range(n.value)]
+
+
+def pxServerQuery(sv):
+    q, a = ctypes.c_int32(), ctypes.c_int32()
+    r, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pxServerQuery(sv, ctypes.byref(q), ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)))
+    return dict(queued=q.value, active=a.value, rows_in_use=r.value, rows_capacity=c.value)
+
+
+def pxServerDestroy(sv):
+    if sv is not None:
+        load().pxServerDestroy(sv)
+
+
 # ---- convenience wrapper ---------------------------------------------------
+
+def solve_batch(structures, **kw):
+    """pxSolveBatch over Structure objects (keyword options as solve_options)."""
+    return pxSolveBatch([st.h for st in structures], solve_options(**kw))
+
+
+class Server:
+    """Continuous-batching server (pxServerCreate ...)."""
+
+    def __init__(self, memory_budget_bytes, hip_stream=None, **kw):
+        self.h = pxServerCreate(memory_budget_bytes, solve_options(**kw), hip_stream)
+
+    def submit(self, structure):
+        pxServerSubmit(self.h, structure.h)
+
+    def step(self, max_finished=64):
+        return pxServerStep(self.h, max_finished)
+
+    def query(self):
+        return pxServerQuery(self.h)
+
+    def close(self):
+        if self.h is not None:
+            pxServerDestroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Structure:
     """One nanostructure on the GPU (see include/plasmonx.h)."""
@@ -226,19 +312,8 @@ class Structure:
         self.pol_mask = int(pol_mask)
         self.ncol = self.n_omega * bin(pol_mask & 7).count("1")
 
-    def solve(self, precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
-              inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200):
-        o = pxDefaultSolveOptions()
-        o.precision = int(precision)
-        o.restart_m = int(restart_m)
-        o.rel_tol = float(rel_tol)
-        o.max_cycles = int(max_cycles)
-        o.max_block_cols = int(max_block_cols)
-        o.inner_reduction = float(inner_reduction)
-        o.timings = int(bool(timings))
-        o.stall_cycles = int(stall_cycles)
-        o.max_restart_m = int(max_restart_m)
-        return pxSolveSpectrum(self.h, o)
+    def solve(self, **kw):
+        return pxSolveSpectrum(self.h, solve_options(**kw))
 
     def spectrum(self):
         return pxGetSpectrum(self.h, self.n_omega)

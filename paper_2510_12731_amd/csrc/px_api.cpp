@@ -11,6 +11,10 @@
 // cycle boundary and the active block is compacted, so the T-apply width
 // follows the number of unfinished columns.
 #include "px_internal.h"
+#include "px_state.h"
+#include "px_engine.h"
+
+#include <deque>
 
 #include <hip/hip_runtime.h>
 
@@ -22,16 +26,17 @@
 #include <string>
 #include <vector>
 
+using namespace pxs;
+
 namespace {
 
-constexpr double ANG_PER_BOHR = 0.529177210903;   // CODATA 2018
-constexpr double EV_PER_HARTREE = 27.211386245988;
-constexpr double PI = 3.14159265358979323846;
-// The solver works on Eq. (wfqfmu-system) with its dipole rows multiplied by
-// -1 (same solution, same residual norms); see k_spmm_shift.
-constexpr double SOLVER_MU_SIGN = -1.0;
-
 thread_local std::string g_err;
+
+int pad_cols(int na, bool narrow_ok) { return (narrow_ok && na <= 4) ? na : ((na + px::COL_PAD - 1) / px::COL_PAD) * px::COL_PAD; }
+
+}  // namespace
+
+namespace pxs {
 
 pxStatus fail(pxStatus st, const std::string& msg)
 {
@@ -39,101 +44,66 @@ pxStatus fail(pxStatus st, const std::string& msg)
     return st;
 }
 
-struct HipError {
-    hipError_t e;
-    const char* where;
-};
-
-inline void hcheck(hipError_t e, const char* where)
+void shift_q(double drude, double tau, double w, double& zr, double& zi)
 {
-    if (e != hipSuccess) throw HipError{e, where};
+    const double pref = -w / (2.0 * drude * tau);
+    zr = pref * w * tau;
+    zi = pref;
 }
 
-#define HC(x) hcheck((x), #x)
-
-template <typename T>
-T* dalloc(size_t count)
+void shift_mu(double ar, double ai, double& zr, double& zi)
 {
-    void* p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
-    return static_cast<T*>(p);
+    const double den = ar * ar + ai * ai;
+    zr = -ar / den;
+    zi = ai / den;
 }
 
-inline void dfree(void* p)
+void prepare_solve(pxStructure_t* s)
 {
-    if (p) (void)hipFree(p);
+    const int ncol = s->ncol;
+    const int64_t nup = s->g.nup;
+    px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    px::fill_zero(s->x, sizeof(double2) * (size_t)nup * s->ldg, s->st);
+    s->bnorm.assign(ncol, 0.0);
+    const int nchunk = px::arnoldi_chunks(nup);
+    double* part = dalloc<double>((size_t)nchunk * s->ldg);
+    double* nr = dalloc<double>(s->ldg);
+    px::col_norm_partial(s->b, part, ncol, s->ldg, nup, s->st);
+    px::reduce_norms(part, nchunk, nr, ncol, s->ldg, s->st);
+    HC(hipMemcpyAsync(s->bnorm.data(), nr, sizeof(double) * ncol, hipMemcpyDeviceToHost, s->st));
+    HC(hipStreamSynchronize(s->st));
+    dfree(part);
+    dfree(nr);
+    s->iters.assign(ncol, 0);
+    s->cycles.assign(ncol, 0);
+    s->stall.assign(ncol, 0);
+    s->relres.assign(ncol, 0.0);
+    s->solved = false;
 }
 
-int pad_cols(int na, bool narrow_ok) { return (narrow_ok && na <= 4) ? na : ((na + px::COL_PAD - 1) / px::COL_PAD) * px::COL_PAD; }
+void finish_solve(pxStructure_t* s)
+{
+    const int ncol = s->ncol;
+    const int nchunk = (int)((s->g.n + px::RED_ROWS - 1) / px::RED_ROWS);
+    double2* dpart = dalloc<double2>((size_t)nchunk * 3 * s->ldg);
+    double2* d = dalloc<double2>((size_t)3 * ncol);
+    double2* al = dalloc<double2>((size_t)9 * s->n_omega);
+    double* sg = dalloc<double>(s->n_omega);
+    px::observables(s->g, s->x, ncol, s->ldg, dpart, d, s->st);
+    px::spectrum(d, s->d_col_pol, s->n_omega, s->npol, s->d_omega, s->e0, al, sg, s->st);
+    s->alpha.assign((size_t)18 * s->n_omega, 0.0);
+    s->sigma.assign(s->n_omega, 0.0);
+    HC(hipMemcpyAsync(s->alpha.data(), al, sizeof(double2) * 9 * s->n_omega, hipMemcpyDeviceToHost, s->st));
+    HC(hipMemcpyAsync(s->sigma.data(), sg, sizeof(double) * s->n_omega, hipMemcpyDeviceToHost, s->st));
+    HC(hipStreamSynchronize(s->st));
+    dfree(dpart);
+    dfree(d);
+    dfree(al);
+    dfree(sg);
+    s->solved = true;
+}
 
-struct Workspace {
-    int lda_cap = 0, m_cap = 0;
-    int64_t nup = 0;
-    double2 *V = nullptr, *w = nullptr, *xs = nullptr, *rs = nullptr, *bs = nullptr, *tmp = nullptr;
-    float *X32 = nullptr, *Y32 = nullptr;
-    double* Y64 = nullptr;
-    double2* partial = nullptr;
-    double* npart = nullptr;
-    double2 *h1 = nullptr, *h2 = nullptr, *R = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
-    double *cs = nullptr, *nrm = nullptr, *target = nullptr;
-    int32_t *done = nullptr, *steps = nullptr, *map = nullptr;
-    double2 *zq = nullptr, *zmu = nullptr;
-    double* narrow = nullptr;
-    size_t narrow_bytes = 0;
-    float* split32 = nullptr;
-
-    void release()
-    {
-        void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, sn, gv, y, cs, nrm, target,
-                      done, steps, map, zq, zmu, narrow, split32};
-        for (void* p : ps) dfree(p);
-        *this = Workspace();
-    }
-};
-
-}  // namespace
-
-struct pxStructure_t {
-    px::Geometry g;
-    pxModel model = PX_WFQ;
-    pxMaterial mat{};
-    double drude = 0.0;
-    hipStream_t st = nullptr;
-    std::vector<int32_t> perm;
-    int32_t* d_perm = nullptr;
-    // frequencies and columns (frequency-major: column = w * npol + p)
-    int n_omega = 0, npol = 0, ncol = 0, ldg = 0;
-    std::vector<double> omega_au;
-    std::vector<double> aib;   // 2 * n_omega
-    std::vector<int32_t> col_pol;
-    uint32_t pol_mask = 0;
-    double e0 = 0.0;
-    int32_t* d_col_pol = nullptr;
-    double* d_omega = nullptr;
-    double2* x = nullptr;   // [nup][ldg]
-    double2* b = nullptr;
-    std::vector<double> bnorm;
-    // results
-    bool solved = false;
-    std::vector<int32_t> iters, cycles, stall;
-    std::vector<double> relres, alpha, sigma;
-    // workspace and timings
-    Workspace ws;
-    // ms: total, T-apply FP32, T-apply FP64 inside cycles, sparse apply, Arnoldi+Givens, rest
-    double ms[6] = {0, 0, 0, 0, 0, 0};
-    // counts: FP32 T-apply launches, padded real columns, algorithmic real
-    // columns; the same three for the FP64 T-apply (cycles and residuals)
-    int64_t counts[6] = {0, 0, 0, 0, 0, 0};
-
-    ~pxStructure_t()
-    {
-        ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, d_perm, d_col_pol, d_omega, x, b};
-        for (void* p : ps) dfree(p);
-    }
-};
+}  // namespace pxs
 
 namespace {
 
@@ -180,21 +150,6 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     px::fill_zero(W.X32, sizeof(float) * 2 * vec, s->st);
 }
 
-// z_q(omega) of Eq. (z_q_wfq) with the Drude weight n/m* (graphene: E_F/(pi t_g))
-void shift_q(const pxStructure_t* s, double w, double& zr, double& zi)
-{
-    const double pref = -w / (2.0 * s->drude * s->mat.tau);
-    zr = pref * w * s->mat.tau;
-    zi = pref;
-}
-
-// Eq. (z-mu): z_mu = -1 / alpha_IB
-void shift_mu(double ar, double ai, double& zr, double& zi)
-{
-    const double den = ar * ar + ai * ai;
-    zr = -ar / den;
-    zi = ai / den;
-}
 
 struct Timer {
     bool on;
@@ -253,7 +208,7 @@ void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
         const int c = act[k];
         const int w = c / s->npol;
         double zr, zi;
-        shift_q(s, s->omega_au[w], zr, zi);
+        shift_q(s->drude, s->mat.tau, s->omega_au[w], zr, zi);
         zq[k] = make_double2(zr, zi);
         if (s->model == PX_WFQFMU) {
             shift_mu(s->aib[2 * w], s->aib[2 * w + 1], zr, zi);
@@ -409,68 +364,34 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
     }
 }
 
-pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
+pxStatus check_options(const pxSolveOptions& o)
 {
-    if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrum: call pxSetFrequencies first");
     if (o.restart_m < 1 || o.restart_m > 1000 || o.max_restart_m > 1000)
         return fail(PX_E_INVALID, "restart_m and max_restart_m must be in [1, 1000]");
     if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
-        o.stall_cycles < 0 ||
+        o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
+    return PX_OK;
+}
+
+pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
+{
+    if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrum: call pxSetFrequencies first");
+    if (check_options(o) != PX_OK) return PX_E_INVALID;
     auto t0 = std::chrono::steady_clock::now();
     for (double& v : s->ms) v = 0.0;
     for (int64_t& v : s->counts) v = 0;
     const int ncol = s->ncol;
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
     ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
-    const int64_t nup = s->g.nup;
-    // right-hand sides, x = 0, ||b||
-    px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
-    px::fill_zero(s->x, sizeof(double2) * (size_t)nup * s->ldg, s->st);
-    {
-        std::vector<double> bn;
-        // reuse the norm kernels over the global layout in slices of the workspace width
-        s->bnorm.assign(ncol, 0.0);
-        const int nchunk = px::arnoldi_chunks(nup);
-        double* part = dalloc<double>((size_t)nchunk * s->ldg);
-        double* nr = dalloc<double>(s->ldg);
-        px::col_norm_partial(s->b, part, ncol, s->ldg, nup, s->st);
-        px::reduce_norms(part, nchunk, nr, ncol, s->ldg, s->st);
-        HC(hipMemcpyAsync(s->bnorm.data(), nr, sizeof(double) * ncol, hipMemcpyDeviceToHost, s->st));
-        HC(hipStreamSynchronize(s->st));
-        dfree(part);
-        dfree(nr);
-    }
-    s->iters.assign(ncol, 0);
-    s->cycles.assign(ncol, 0);
-    s->stall.assign(ncol, 0);
-    s->relres.assign(ncol, 0.0);
+    prepare_solve(s);
     for (int c0 = 0; c0 < ncol; c0 += blk) {
         std::vector<int> cols;
         for (int c = c0; c < std::min(ncol, c0 + blk); ++c) cols.push_back(c);
         run_block(s, cols, o);
     }
-    // observables (Section 7)
-    {
-        const int nchunk = (int)((s->g.n + px::RED_ROWS - 1) / px::RED_ROWS);
-        double2* dpart = dalloc<double2>((size_t)nchunk * 3 * s->ldg);
-        double2* d = dalloc<double2>((size_t)3 * ncol);
-        double2* al = dalloc<double2>((size_t)9 * s->n_omega);
-        double* sg = dalloc<double>(s->n_omega);
-        px::observables(s->g, s->x, ncol, s->ldg, dpart, d, s->st);
-        px::spectrum(d, s->d_col_pol, s->n_omega, s->npol, s->d_omega, s->e0, al, sg, s->st);
-        s->alpha.assign((size_t)18 * s->n_omega, 0.0);
-        s->sigma.assign(s->n_omega, 0.0);
-        HC(hipMemcpyAsync(s->alpha.data(), al, sizeof(double2) * 9 * s->n_omega, hipMemcpyDeviceToHost, s->st));
-        HC(hipMemcpyAsync(s->sigma.data(), sg, sizeof(double) * s->n_omega, hipMemcpyDeviceToHost, s->st));
-        HC(hipStreamSynchronize(s->st));
-        dfree(dpart);
-        dfree(d);
-        dfree(al);
-        dfree(sg);
-    }
-    s->solved = true;
+    finish_solve(s);
     s->ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     s->ms[5] = s->ms[0] - s->ms[1] - s->ms[2] - s->ms[3] - s->ms[4];
     for (int c = 0; c < ncol; ++c)
@@ -511,6 +432,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->timings = 0;
     o->stall_cycles = 8;
     o->max_restart_m = 200;
+    o->block_cols = 0;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }
@@ -642,13 +564,63 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
 {
     g_err.clear();
     if (!ss || n < 0) return fail(PX_E_INVALID, "null argument");
-    pxStatus worst = PX_OK;
+    if (n == 0) return PX_OK;
+    pxSolveOptions o;
+    pxDefaultSolveOptions(&o);
+    if (opt) o = *opt;
+    if (check_options(o) != PX_OK) return PX_E_INVALID;
     for (int32_t k = 0; k < n; ++k) {
-        pxStatus st = pxSolveSpectrum(ss[k], opt);
-        if (st != PX_OK && st != PX_E_NOTCONV) return st;
-        if (st == PX_E_NOTCONV) worst = st;
+        if (!ss[k]) return fail(PX_E_INVALID, "null structure");
+        if (ss[k]->ncol == 0) return fail(PX_E_STATE, "pxSolveBatch: every structure needs pxSetFrequencies");
+        if (ss[k]->st != ss[0]->st) return fail(PX_E_INVALID, "pxSolveBatch: structures use different streams");
     }
-    return worst;
+    return guarded([&]() -> pxStatus {
+        auto t0 = std::chrono::steady_clock::now();
+        const int Bc = o.block_cols > 0 ? o.block_cols : 64;
+        const int m_max = std::max(o.restart_m, o.max_restart_m);
+        hipStream_t st = ss[0]->st;
+        int64_t rows = 0;
+        int nseg = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            nseg += (ss[k]->ncol + Bc - 1) / Bc;
+            rows += (int64_t)((ss[k]->ncol + Bc - 1) / Bc) * ss[k]->g.nup;
+        }
+        size_t free_b = 0, total_b = 0;
+        HC(hipMemGetInfo(&free_b, &total_b));
+        const int64_t fit = (int64_t)(0.8 * (double)free_b / (double)Engine::bytes_per_row(Bc, m_max));
+        const int64_t cap = std::min(rows, fit);
+        int64_t biggest = 0;
+        for (int32_t k = 0; k < n; ++k)
+            biggest = std::max<int64_t>(biggest, (int64_t)((ss[k]->ncol + Bc - 1) / Bc) * ss[k]->g.nup);
+        if (cap < biggest) return fail(PX_E_OOM, "pxSolveBatch: the largest structure does not fit in device memory");
+        Engine eng(st, Bc, o, std::max(cap, biggest), nseg);
+        std::deque<pxStructure_t*> queue;
+        for (int32_t k = 0; k < n; ++k) {
+            for (double& v : ss[k]->ms) v = 0.0;
+            for (int64_t& v : ss[k]->counts) v = 0;
+            prepare_solve(ss[k]);
+            queue.push_back(ss[k]);
+        }
+        while (!queue.empty() || !eng.idle()) {
+            while (!queue.empty() && eng.can_admit(queue.front())) {
+                eng.admit(queue.front());
+                queue.pop_front();
+            }
+            eng.cycle();
+        }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        pxStatus worst = PX_OK;
+        for (int32_t k = 0; k < n; ++k) {
+            ss[k]->ms[0] = ms;
+            ss[k]->ms[5] = ms;
+            ss[k]->counts[0] = eng.stats().tapply_f32;
+            ss[k]->counts[3] = eng.stats().tapply_f64 + eng.stats().residuals;
+            for (int c = 0; c < ss[k]->ncol; ++c)
+                if (!(ss[k]->relres[c] <= o.rel_tol)) worst = PX_E_NOTCONV;
+        }
+        if (worst != PX_OK) return fail(worst, "some columns did not reach rel_tol");
+        return PX_OK;
+    });
 }
 
 pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, double* mu)
@@ -719,7 +691,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
         std::vector<double2> zq(lda, make_double2(0, 0)), zm(lda, make_double2(0, 0));
         for (int c = 0; c < ncol; ++c) {
             double zr, zi;
-            shift_q(s, omega_ev[c] / EV_PER_HARTREE, zr, zi);
+            shift_q(s->drude, s->mat.tau, omega_ev[c] / EV_PER_HARTREE, zr, zi);
             zq[c] = make_double2(zr, zi);
             if (s->model == PX_WFQFMU) {
                 shift_mu(alpha_ib[2 * c], alpha_ib[2 * c + 1], zr, zi);
@@ -773,6 +745,103 @@ void pxDestroyStructure(pxStructure s)
     if (s->st) (void)hipStreamSynchronize(s->st);
     else (void)hipDeviceSynchronize();
     delete s;
+}
+
+struct pxServer_t {
+    pxs::Engine* eng = nullptr;
+    std::deque<pxStructure_t*> queue;
+    std::deque<pxStructure_t*> done;
+    hipStream_t st = nullptr;
+    pxSolveOptions o{};
+};
+
+pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out)
+{
+    g_err.clear();
+    if (!out) return fail(PX_E_INVALID, "null argument");
+    *out = nullptr;
+    pxSolveOptions o;
+    pxDefaultSolveOptions(&o);
+    if (opt) o = *opt;
+    if (check_options(o) != PX_OK) return PX_E_INVALID;
+    if (!(memory_budget_bytes > 0)) return fail(PX_E_INVALID, "memory budget must be > 0");
+    return guarded([&]() -> pxStatus {
+        const int Bc = o.block_cols > 0 ? o.block_cols : 64;
+        const int m_max = std::max(o.restart_m, o.max_restart_m);
+        const int64_t rows = (int64_t)(memory_budget_bytes / (double)Engine::bytes_per_row(Bc, m_max));
+        if (rows < 256) return fail(PX_E_OOM, "memory budget below one segment");
+        auto* sv = new pxServer_t();
+        sv->st = static_cast<hipStream_t>(hip_stream);
+        sv->o = o;
+        sv->o.block_cols = Bc;
+        try {
+            sv->eng = new Engine(sv->st, Bc, o, rows, (int)std::max<int64_t>(1, rows / 256));
+        } catch (...) {
+            delete sv;
+            throw;
+        }
+        *out = sv;
+        return PX_OK;
+    });
+}
+
+pxStatus pxServerSubmit(pxServer sv, pxStructure s)
+{
+    g_err.clear();
+    if (!sv || !s) return fail(PX_E_INVALID, "null argument");
+    if (s->ncol == 0) return fail(PX_E_STATE, "pxServerSubmit: call pxSetFrequencies first");
+    if (s->st != sv->st) return fail(PX_E_INVALID, "pxServerSubmit: structure uses another stream");
+    if (sv->eng->rows_for(s) > sv->eng->rows_capacity())
+        return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");
+    return guarded([&]() -> pxStatus {
+        for (double& v : s->ms) v = 0.0;
+        for (int64_t& v : s->counts) v = 0;
+        prepare_solve(s);
+        sv->queue.push_back(s);
+        return PX_OK;
+    });
+}
+
+pxStatus pxServerStep(pxServer sv, pxStructure* finished, int32_t max_finished, int32_t* n_finished)
+{
+    g_err.clear();
+    if (!sv || !n_finished || (max_finished > 0 && !finished)) return fail(PX_E_INVALID, "null argument");
+    return guarded([&]() -> pxStatus {
+        while (!sv->queue.empty() && sv->eng->can_admit(sv->queue.front())) {
+            sv->eng->admit(sv->queue.front());
+            sv->queue.pop_front();
+        }
+        if (!sv->eng->idle())
+            for (pxStructure_t* s : sv->eng->cycle()) sv->done.push_back(s);
+        int32_t k = 0;
+        while (k < max_finished && !sv->done.empty()) {
+            finished[k++] = sv->done.front();
+            sv->done.pop_front();
+        }
+        *n_finished = k;
+        return PX_OK;
+    });
+}
+
+pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_t* rows_in_use,
+                       int64_t* rows_capacity)
+{
+    g_err.clear();
+    if (!sv) return fail(PX_E_INVALID, "null server");
+    if (n_queued) *n_queued = (int32_t)sv->queue.size();
+    if (n_active) *n_active = sv->eng->n_structures();
+    if (rows_in_use) *rows_in_use = sv->eng->rows_in_use();
+    if (rows_capacity) *rows_capacity = sv->eng->rows_capacity();
+    return PX_OK;
+}
+
+void pxServerDestroy(pxServer sv)
+{
+    if (!sv) return;
+    if (sv->st) (void)hipStreamSynchronize(sv->st);
+    else (void)hipDeviceSynchronize();
+    delete sv->eng;
+    delete sv;
 }
 
 }  // extern "C"

@@ -60,6 +60,31 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
                 double* scratch, size_t scratch_bytes);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
+// Grouped T-apply over the segments of a stacked block (each segment one
+// structure's padded rows starting at row_off; real columns ldx, a multiple
+// of 128).  setup() builds and uploads the tile lists; run_* launch one kernel
+// per precision and model for all segments.
+struct GroupSeg {
+    const Geometry* g;
+    int64_t row_off;
+};
+class GroupedTApply {
+  public:
+    GroupedTApply();
+    ~GroupedTApply();
+    GroupedTApply(const GroupedTApply&) = delete;
+    GroupedTApply& operator=(const GroupedTApply&) = delete;
+    hipError_t setup(const std::vector<GroupSeg>& segs, int ldx, int64_t rows, hipStream_t st);
+    size_t partial_bytes() const;   // split-K scratch needed by run_f32
+    int64_t f32_tiles() const;
+    void run_f32(const float* X, float* Y, float* partial, hipStream_t st) const;
+    void run_f64(const double* X, double* Y, hipStream_t st) const;
+
+  private:
+    struct Impl;
+    Impl* impl;
+};
+
 // ---- other kernels (px_kernels.hip) ----------------------------------------
 hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
                           double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st);
@@ -106,5 +131,28 @@ void unpermute(const Geometry& g, const double2* x, int ldx, int col, const int3
 void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* perm, double2* x, int ldx,
                 hipStream_t st);
 void fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// ---- stacked segments (px_engine.cpp) ---------------------------------------
+// One segment of a stacked block: a structure's padded rows (np or 4 np) with
+// Bc columns, starting at row_off (a multiple of 256).
+struct SegInfo {
+    int64_t row_off, n, np;
+    int32_t model, pad;
+    const int32_t* rp;
+    const int32_t* ci;
+    const double* cv;
+};
+void spmm_seg(const SegInfo* segs, const int32_t* chunk_seg, const void* Y, bool y_is_f32, int ldy, const double2* X,
+              const double2* zq, const double2* zmu, const double2* B, double2* W, int64_t rows, int Bc, int nseg,
+              double mu_sign, hipStream_t st);
+void reduce_dots_seg(const double2* partial, const int32_t* seg_beg, int nvec, double2* h, int nseg, int Bc,
+                     hipStream_t st);
+void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st);
+void col_update_seg(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
+                    const int32_t* chunk_seg, int Bc, int nseg, int64_t rows, hipStream_t st);
+void normalize_seg(const double2* w, const double* nrm, const int32_t* done, const int32_t* chunk_seg, double2* v,
+                   float* x32, int Bc, int64_t rows, hipStream_t st);
+void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
+                  double2* x, int Bc, int nseg, int64_t rows, hipStream_t st);
 
 }  // namespace px

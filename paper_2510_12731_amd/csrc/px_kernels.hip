@@ -733,6 +733,174 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words)
     for (; t < words; t += stride) p[t] = 0u;
 }
 
+// ============================ stacked segments ==============================
+// A stacked block holds several segments (structure x block of Bc columns),
+// each a contiguous, 256-row-aligned range of rows; chunk_seg maps every
+// 256-row chunk to its segment.  Per-column state is indexed by the flat
+// column seg * Bc + c (leading dimension nseg * Bc).
+
+__global__ __launch_bounds__(256) void k_spmm_seg(const SegInfo* __restrict__ segs,
+                                                  const int32_t* __restrict__ chunk_seg, const void* __restrict__ Yv,
+                                                  int y_f32, int ldy, const double2* __restrict__ X,
+                                                  const double2* __restrict__ zq, const double2* __restrict__ zmu,
+                                                  const double2* __restrict__ B, double2* __restrict__ W, int64_t rows,
+                                                  int Bc, int ldf, double mu_sign)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows || c >= Bc) return;
+    const size_t o = (size_t)r * Bc + c;
+    const int sg = chunk_seg[r >> 8];
+    const SegInfo& S = segs[sg];
+    const int64_t lr = r - S.row_off;
+    const int64_t comp = lr / S.np, i = lr - comp * S.np;
+    if (i >= S.n) {
+        W[o] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int f = sg * Bc + c;
+    double ar = 0.0, ai = 0.0;
+    double2 z;
+    if (comp == 0) {
+        for (int32_t e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+            const double k = S.cv[e];
+            const size_t yo = (size_t)(S.row_off + S.ci[e]) * ldy + 2 * c;
+            const double yr = y_f32 ? (double)static_cast<const float*>(Yv)[yo] : static_cast<const double*>(Yv)[yo];
+            const double yi = y_f32 ? (double)static_cast<const float*>(Yv)[yo + 1]
+                                    : static_cast<const double*>(Yv)[yo + 1];
+            ar = fma(k, yr, ar);
+            ai = fma(k, yi, ai);
+        }
+        z = zq[f];
+    } else {
+        const size_t yo = (size_t)r * ldy + 2 * c;
+        ar = y_f32 ? (double)static_cast<const float*>(Yv)[yo] : static_cast<const double*>(Yv)[yo];
+        ai = y_f32 ? (double)static_cast<const float*>(Yv)[yo + 1] : static_cast<const double*>(Yv)[yo + 1];
+        z = zmu[f];
+    }
+    const double2 x = X[o];
+    double2 w = make_double2(ar - (z.x * x.x - z.y * x.y), ai - (z.x * x.y + z.y * x.x));
+    if (comp != 0) w = make_double2(mu_sign * w.x, mu_sign * w.y);
+    if (B != nullptr) {
+        const double2 b = B[o];
+        w = make_double2(b.x - w.x, b.y - w.y);
+    }
+    W[o] = w;
+    (void)ldf;
+}
+
+// h[j][seg*Bc + c] = sum of partial[k][j][c] over the segment's chunks k
+__global__ void k_reduce_dots_seg(const double2* __restrict__ partial, const int32_t* __restrict__ seg_beg,
+                                  int nvec, double2* __restrict__ h, int nseg, int Bc)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ldf = nseg * Bc;
+    if (t >= nvec * ldf) return;
+    const int j = t / ldf, f = t - j * ldf;
+    const int sg = f / Bc, c = f - sg * Bc;
+    double ar = 0.0, ai = 0.0;
+    for (int k = seg_beg[sg]; k < seg_beg[sg + 1]; ++k) {
+        const double2 p = partial[((size_t)k * nvec + j) * Bc + c];
+        ar += p.x;
+        ai += p.y;
+    }
+    h[(size_t)j * ldf + f] = make_double2(ar, ai);
+}
+
+// nrm[seg*Bc + c] = sqrt(sum of partial[k][c] over the segment's chunks k)
+__global__ void k_reduce_norms_seg(const double* __restrict__ partial, const int32_t* __restrict__ seg_beg,
+                                   double* __restrict__ nrm, int nseg, int Bc)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nseg * Bc) return;
+    const int sg = f / Bc, c = f - sg * Bc;
+    double s = 0.0;
+    for (int k = seg_beg[sg]; k < seg_beg[sg + 1]; ++k) s += partial[(size_t)k * Bc + c];
+    nrm[f] = sqrt(s);
+}
+
+// w -= sum_j V_j h_j with h per flat column; norm partials per UPD_ROWS rows.
+__global__ __launch_bounds__(256) void k_col_update_seg(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                                        const double2* __restrict__ h, double2* __restrict__ w,
+                                                        double* __restrict__ norm_partial,
+                                                        const int32_t* __restrict__ chunk_seg, int Bc, int ldf,
+                                                        int64_t rows)
+{
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
+    const int64_t rg = (int64_t)blockIdx.x * UPD_ROWS + wave * ARN_RG;
+    double nrm = 0.0;
+    if (c < Bc && rg < rows) {
+        const int f = chunk_seg[rg >> 8] * Bc + c;
+        double2 acc[ARN_RG];
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q) acc[q] = w[(size_t)(rg + q) * Bc + c];
+        const double2* vb = V + (size_t)rg * Bc + c;
+        for (int j = 0; j < nvec; ++j) {
+            const double2 hj = h[(size_t)j * ldf + f];
+            const double2* vj = vb + (size_t)j * vstride;
+#pragma unroll
+            for (int q = 0; q < ARN_RG; ++q) {
+                const double2 a = vj[(size_t)q * Bc];
+                acc[q].x -= a.x * hj.x - a.y * hj.y;
+                acc[q].y -= a.x * hj.y + a.y * hj.x;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q) {
+            w[(size_t)(rg + q) * Bc + c] = acc[q];
+            nrm = fma(acc[q].x, acc[q].x, fma(acc[q].y, acc[q].y, nrm));
+        }
+    }
+    if (norm_partial) {
+        red[wave][lane] = nrm;
+        __syncthreads();
+        if (wave == 0 && c < Bc)
+            norm_partial[(size_t)blockIdx.x * Bc + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_normalize_seg(const double2* __restrict__ w, const double* __restrict__ nrm,
+                                                       const int32_t* __restrict__ done,
+                                                       const int32_t* __restrict__ chunk_seg, double2* __restrict__ v,
+                                                       float* __restrict__ x32, int Bc, int64_t rows)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows || c >= Bc) return;
+    const size_t o = (size_t)r * Bc + c;
+    const int f = chunk_seg[r >> 8] * Bc + c;
+    double2 out = make_double2(0.0, 0.0);
+    if (!done[f]) {
+        const double s = 1.0 / nrm[f];
+        const double2 a = w[o];
+        out = make_double2(a.x * s, a.y * s);
+    }
+    v[o] = out;
+    if (x32) *reinterpret_cast<float2*>(x32 + (size_t)r * 2 * Bc + 2 * c) = make_float2((float)out.x, (float)out.y);
+}
+
+__global__ __launch_bounds__(256) void k_x_update_seg(const double2* __restrict__ V, int64_t vstride,
+                                                      const double2* __restrict__ y, const int32_t* __restrict__ steps,
+                                                      const int32_t* __restrict__ chunk_seg, double2* __restrict__ x,
+                                                      int Bc, int ldf, int64_t rows)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows || c >= Bc) return;
+    const size_t o = (size_t)r * Bc + c;
+    const int f = chunk_seg[r >> 8] * Bc + c;
+    double2 acc = x[o];
+    const int kc = steps[f];
+    for (int j = 0; j < kc; ++j) {
+        const double2 t = cmul(V[j * vstride + o], y[(size_t)j * ldf + f]);
+        acc.x += t.x;
+        acc.y += t.y;
+    }
+    x[o] = acc;
+}
+
 inline dim3 grid_rows_cols(int64_t rows, int cols) { return dim3((unsigned)((rows + 3) / 4), (unsigned)((cols + 63) / 64)); }
 inline int nchunks(int64_t rows) { return (int)((rows + RED_ROWS - 1) / RED_ROWS); }
 inline int arn_chunks(int64_t rows) { return (int)((rows + ARN_ROWS - 1) / ARN_ROWS); }
@@ -957,6 +1125,51 @@ void fill_zero(void* p, size_t bytes, hipStream_t st)
     if (words == 0) return;
     unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, reinterpret_cast<uint32_t*>(p), words);
+}
+
+// ---- stacked-segment launchers ----------------------------------------------
+
+void spmm_seg(const SegInfo* segs, const int32_t* chunk_seg, const void* Y, bool y_is_f32, int ldy, const double2* X,
+              const double2* zq, const double2* zmu, const double2* B, double2* W, int64_t rows, int Bc, int nseg,
+              double mu_sign, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_spmm_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, segs, chunk_seg, Y, y_is_f32 ? 1 : 0,
+                       ldy, X, zq, zmu, B, W, rows, Bc, nseg * Bc, mu_sign);
+}
+
+void reduce_dots_seg(const double2* partial, const int32_t* seg_beg, int nvec, double2* h, int nseg, int Bc,
+                     hipStream_t st)
+{
+    const int t = nvec * nseg * Bc;
+    hipLaunchKernelGGL(k_reduce_dots_seg, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, partial, seg_beg, nvec,
+                       h, nseg, Bc);
+}
+
+void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_norms_seg, dim3((unsigned)((nseg * Bc + 255) / 256)), dim3(256), 0, st, partial,
+                       seg_beg, nrm, nseg, Bc);
+}
+
+void col_update_seg(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
+                    const int32_t* chunk_seg, int Bc, int nseg, int64_t rows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_col_update_seg, dim3(update_chunks(rows), (unsigned)((Bc + 63) / 64)), dim3(256), 0, st, V,
+                       vstride, nvec, h, w, norm_partial, chunk_seg, Bc, nseg * Bc, rows);
+}
+
+void normalize_seg(const double2* w, const double* nrm, const int32_t* done, const int32_t* chunk_seg, double2* v,
+                   float* x32, int Bc, int64_t rows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_normalize_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, w, nrm, done, chunk_seg, v, x32, Bc,
+                       rows);
+}
+
+void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
+                  double2* x, int Bc, int nseg, int64_t rows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_x_update_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, V, vstride, y, steps, chunk_seg, x,
+                       Bc, nseg * Bc, rows);
 }
 
 }  // namespace px

@@ -86,7 +86,7 @@ __device__ __forceinline__ void mfma8(f32x16 (&acc)[2][4], float a0, float a1, f
     acc[1][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.w, acc[1][3], 0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
+__device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, const float4* __restrict__ xyz,
                                                         const float4* __restrict__ glo,
                                                         const float4* __restrict__ ghi,
                                                         const float* __restrict__ X, float* __restrict__ Y,
@@ -99,12 +99,12 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int row0 = blockIdx.x * 256 + wave * 64;
-    const int col0 = blockIdx.y * Q32_COLS;
+    const int row0 = bx * 256 + wave * 64;
+    const int col0 = by * Q32_COLS;
     const int nchunk = np / Q32_JC;
-    const int cbeg = blockIdx.z * chunks_per_split;
+    const int cbeg = bz * chunks_per_split;
     const int cend = min(nchunk, cbeg + chunks_per_split);
-    Y += blockIdx.z * zstride;
+    Y += bz * zstride;
 
     float xi[2], yi[2], zi[2];
     int ii[2];
@@ -209,6 +209,16 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict
         }
 }
 
+__global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
+                                                        const float4* __restrict__ glo,
+                                                        const float4* __restrict__ ghi,
+                                                        const float* __restrict__ X, float* __restrict__ Y,
+                                                        int np, int ldx, int chunks_per_split, size_t zstride,
+                                                        float inv_rqq, float t_self, float r_far2)
+{
+    tapply_wfq_f32_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, chunks_per_split, zstride, inv_rqq, t_self, r_far2);
+}
+
 // Y[t] = sum_{z < nsplit} P[z][t], in order.
 __global__ void k_sum_splits_f32(const float* __restrict__ P, float* __restrict__ Y, size_t len, size_t zstride,
                                  int nsplit)
@@ -279,7 +289,7 @@ __device__ __forceinline__ void pair_block_f32(float dx, float dy, float dz, boo
         }
 }
 
-__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restrict__ xyz,
+__device__ __forceinline__ void tapply_wfqfmu_f32_body(int bx, int by, int bz, const float4* __restrict__ xyz,
                                                            const float4* __restrict__ glo,
                                                            const float4* __restrict__ ghi,
                                                            const float* __restrict__ X, float* __restrict__ Y,
@@ -291,8 +301,8 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restr
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int row0 = blockIdx.x * 128 + wave * 32;
-    const int col0 = blockIdx.y * D32_COLS;
+    const int row0 = bx * 128 + wave * 32;
+    const int col0 = by * D32_COLS;
     const size_t cstride = (size_t)np * ldx;   // component block stride
 
     const int ii = row0 + (lane & 31);
@@ -375,6 +385,15 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restr
         }
 }
 
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restrict__ xyz,
+                                                           const float4* __restrict__ glo,
+                                                           const float4* __restrict__ ghi,
+                                                           const float* __restrict__ X, float* __restrict__ Y,
+                                                           int np, int ldx, DipoleConstF kc)
+{
+    tapply_wfqfmu_f32_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, kc);
+}
+
 // ============================ omegaFQ, FP64 MFMA ============================
 // Workgroup: 4 waves x 32 rows, 64 real columns.  MFMA 16x16x4 f64 layout:
 // A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16); D register v
@@ -384,7 +403,7 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restr
 constexpr int Q64_COLS = 64;
 constexpr int Q64_JC = 32;
 
-__global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restrict__ xyz,
+__device__ __forceinline__ void tapply_wfq_f64_body(int bx, int by, int bz, const double4* __restrict__ xyz,
                                                         const float4* __restrict__ glo,
                                                         const float4* __restrict__ ghi,
                                                         const double* __restrict__ X, double* __restrict__ Y,
@@ -397,8 +416,8 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restric
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int row0 = blockIdx.x * 128 + wave * 32;
-    const int col0 = blockIdx.y * Q64_COLS;
+    const int row0 = bx * 128 + wave * 32;
+    const int col0 = by * Q64_COLS;
 
     double xi[2], yi[2], zi[2];
     int ii[2];
@@ -492,6 +511,16 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restric
         }
 }
 
+__global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restrict__ xyz,
+                                                        const float4* __restrict__ glo,
+                                                        const float4* __restrict__ ghi,
+                                                        const double* __restrict__ X, double* __restrict__ Y,
+                                                        int np, int ldx, double inv_rqq, double t_self,
+                                                        float r_far2)
+{
+    tapply_wfq_f64_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, inv_rqq, t_self, r_far2);
+}
+
 // ========================== omegaFQFmu, FP64 MFMA ===========================
 // Workgroup: 4 waves x 16 atoms, 16 real columns; 16 MFMAs per k-step.
 struct DipoleConstD {
@@ -541,7 +570,7 @@ __device__ __forceinline__ void pair_block_f64(double dx, double dy, double dz, 
 constexpr int D64_COLS = 16;
 constexpr int D64_JC = 32;
 
-__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __restrict__ xyz,
+__device__ __forceinline__ void tapply_wfqfmu_f64_body(int bx, int by, int bz, const double4* __restrict__ xyz,
                                                            const float4* __restrict__ glo,
                                                            const float4* __restrict__ ghi,
                                                            const double* __restrict__ X, double* __restrict__ Y,
@@ -553,8 +582,8 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __rest
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int row0 = blockIdx.x * 64 + wave * 16;
-    const int col0 = blockIdx.y * D64_COLS;
+    const int row0 = bx * 64 + wave * 16;
+    const int col0 = by * D64_COLS;
     const size_t cstride = (size_t)np * ldx;
 
     const int ii = row0 + (lane & 15);
@@ -634,6 +663,15 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __rest
             const int i = row0 + 4 * v + (lane >> 4);
             Y[a * cstride + (size_t)i * ldx + col0 + (lane & 15)] = acc[a][v];
         }
+}
+
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __restrict__ xyz,
+                                                           const float4* __restrict__ glo,
+                                                           const float4* __restrict__ ghi,
+                                                           const double* __restrict__ X, double* __restrict__ Y,
+                                                           int np, int ldx, DipoleConstD kc)
+{
+    tapply_wfqfmu_f64_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, kc);
 }
 
 // ====================== narrow blocks, FP64 VALU ============================
@@ -735,6 +773,86 @@ __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + t];
     Y[t] = s;
+}
+
+// ====================== grouped launches (many segments) ====================
+// A stacked block holds several segments (structure x column block), each a
+// contiguous range of rows starting at row_off; one launch covers every
+// segment's tiles, listed as int4 {segment, row block, column block, split}.
+struct GroupConst {
+    const float4* xyz32;
+    const double4* xyz64;
+    const float4* glo;
+    const float4* ghi;
+    int64_t row_off;
+    int np, model, chunks_per_split, pad;
+    float inv_rqq32, t_self32, rfar32;
+    double inv_rqq64, t_self64;
+    float rfar64;
+    DipoleConstF d32;
+    DipoleConstD d64;
+};
+
+__global__ __launch_bounds__(256) void k_tapply_wfq_f32_grouped(const GroupConst* __restrict__ gc,
+                                                                const int4* __restrict__ tiles,
+                                                                const float* __restrict__ X, float* __restrict__ P,
+                                                                int ldx, size_t zstride)
+{
+    const int4 t = tiles[blockIdx.x];
+    const GroupConst& c = gc[t.x];
+    tapply_wfq_f32_body(t.y, t.z, t.w, c.xyz32, c.glo, c.ghi, X + (size_t)c.row_off * ldx, P + (size_t)c.row_off * ldx,
+                        c.np, ldx, c.chunks_per_split, zstride, c.inv_rqq32, c.t_self32, c.rfar32);
+}
+
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32_grouped(const GroupConst* __restrict__ gc,
+                                                                   const int4* __restrict__ tiles,
+                                                                   const float* __restrict__ X,
+                                                                   float* __restrict__ Y, int ldx)
+{
+    const int4 t = tiles[blockIdx.x];
+    const GroupConst& c = gc[t.x];
+    tapply_wfqfmu_f32_body(t.y, t.z, 0, c.xyz32, c.glo, c.ghi, X + (size_t)c.row_off * ldx,
+                           Y + (size_t)c.row_off * ldx, c.np, ldx, c.d32);
+}
+
+__global__ __launch_bounds__(256) void k_tapply_wfq_f64_grouped(const GroupConst* __restrict__ gc,
+                                                                const int4* __restrict__ tiles,
+                                                                const double* __restrict__ X, double* __restrict__ Y,
+                                                                int ldx)
+{
+    const int4 t = tiles[blockIdx.x];
+    const GroupConst& c = gc[t.x];
+    tapply_wfq_f64_body(t.y, t.z, 0, c.xyz64, c.glo, c.ghi, X + (size_t)c.row_off * ldx, Y + (size_t)c.row_off * ldx,
+                        c.np, ldx, c.inv_rqq64, c.t_self64, c.rfar64);
+}
+
+__global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64_grouped(const GroupConst* __restrict__ gc,
+                                                                   const int4* __restrict__ tiles,
+                                                                   const double* __restrict__ X,
+                                                                   double* __restrict__ Y, int ldx)
+{
+    const int4 t = tiles[blockIdx.x];
+    const GroupConst& c = gc[t.x];
+    tapply_wfqfmu_f64_body(t.y, t.z, 0, c.xyz64, c.glo, c.ghi, X + (size_t)c.row_off * ldx,
+                           Y + (size_t)c.row_off * ldx, c.np, ldx, c.d64);
+}
+
+// Y[r][:] = sum_{z < nsplit} P[z][r][:] for the rows of omegaFQ segments
+// (row_model[r / 256] == 0); other rows are left alone.
+__global__ void k_sum_splits_grouped(const float* __restrict__ P, float* __restrict__ Y,
+                                     const int32_t* __restrict__ chunk_model, int64_t rows, int ldx, size_t zstride,
+                                     int nsplit)
+{
+    const size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (t >= (size_t)rows * ldx) return;
+    const int64_t r = (int64_t)(t / ldx);
+    if (chunk_model[r >> 8] != 0) return;
+    float4 s = *reinterpret_cast<const float4*>(P + t);
+    for (int z = 1; z < nsplit; ++z) {
+        const float4 v = *reinterpret_cast<const float4*>(P + z * zstride + t);
+        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    }
+    *reinterpret_cast<float4*>(Y + t) = s;
 }
 
 // Far-field thresholds x_far = r / R beyond which the Gaussian factors equal
@@ -878,6 +996,156 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
         hipLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
                            dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, k);
     }
+}
+
+// ---- grouped launches -------------------------------------------------------
+
+struct GroupedTApply::Impl {
+    GroupConst* d_gc = nullptr;
+    int4* d_t32q = nullptr;   // FP32 omegaFQ tiles
+    int4* d_t32d = nullptr;   // FP32 dipole tiles
+    int4* d_t64q = nullptr;
+    int4* d_t64d = nullptr;
+    int32_t* d_chunk_model = nullptr;
+    int n32q = 0, n32d = 0, n64q = 0, n64d = 0;
+    int nsplit = 1;
+    int64_t rows = 0;
+    int ldx = 0;
+    void release()
+    {
+        void* ps[] = {d_gc, d_t32q, d_t32d, d_t64q, d_t64d, d_chunk_model};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        d_gc = nullptr;
+        d_t32q = d_t32d = d_t64q = d_t64d = nullptr;
+        d_chunk_model = nullptr;
+    }
+};
+
+GroupedTApply::GroupedTApply() : impl(new Impl) {}
+GroupedTApply::~GroupedTApply()
+{
+    impl->release();
+    delete impl;
+}
+
+static hipError_t upload(void** dst, const void* src, size_t bytes, hipStream_t st)
+{
+    hipError_t e = hipMalloc(dst, bytes > 0 ? bytes : 16);
+    if (e != hipSuccess) return e;
+    if (bytes > 0) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
+    return e;
+}
+
+hipError_t GroupedTApply::setup(const std::vector<GroupSeg>& segs, int ldx, int64_t rows, hipStream_t st)
+{
+    impl->release();
+    impl->rows = rows;
+    impl->ldx = ldx;
+    std::vector<GroupConst> gc(segs.size());
+    std::vector<int4> t32q, t32d, t64q, t64d;
+    std::vector<int32_t> chunk_model((size_t)(rows / 256) + 1, 1);
+    // split-K for the FP32 omegaFQ tiles: enough workgroups for the whole chip
+    int base = 0;
+    for (const GroupSeg& sg : segs)
+        if (sg.g->model == 0) base += (int)(sg.g->np / 256) * (ldx / Q32_COLS);
+    int nsplit = base > 0 ? std::max(1, std::min(8, (2048 + base - 1) / base)) : 1;
+    impl->nsplit = nsplit;
+    for (size_t k = 0; k < segs.size(); ++k) {
+        const Geometry& g = *segs[k].g;
+        GroupConst c{};
+        c.xyz32 = g.xyz32;
+        c.xyz64 = g.xyz64;
+        c.glo = g.glo;
+        c.ghi = g.ghi;
+        c.row_off = segs[k].row_off;
+        c.np = (int)g.np;
+        c.model = g.model;
+        const double rqq = std::sqrt(2.0) * g.r_q;
+        c.inv_rqq32 = (float)(1.0 / rqq);
+        c.t_self32 = (float)(TWO_OVER_SQRTPI / rqq);
+        c.rfar32 = (float)((XFAR_Q32 * rqq) * (XFAR_Q32 * rqq));
+        c.inv_rqq64 = 1.0 / rqq;
+        c.t_self64 = TWO_OVER_SQRTPI / rqq;
+        c.rfar64 = (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
+        const int nchunk = (int)(g.np / Q32_JC);
+        const int sp = std::max(1, std::min(nsplit, nchunk));
+        c.chunks_per_split = (nchunk + sp - 1) / sp;
+        if (g.model == 1) {
+            c.d64 = dipole_const_d(g);
+            c.d32.inv_rqq = (float)c.d64.inv_rqq;
+            c.d32.inv_rqm = (float)c.d64.inv_rqm;
+            c.d32.inv_rmm = (float)c.d64.inv_rmm;
+            c.d32.gauss_pref = (float)c.d64.gauss_pref;
+            c.d32.t_self = (float)c.d64.t_self;
+            const double rmax = 1.0 / std::fmin(c.d64.inv_rqq, std::fmin(c.d64.inv_rqm, c.d64.inv_rmm));
+            c.d32.r_far2 = (float)((XFAR_D32 * rmax) * (XFAR_D32 * rmax));
+        }
+        gc[k] = c;
+        const int kk = (int)k;
+        if (g.model == 0) {
+            for (int64_t r = segs[k].row_off / 256; r < (segs[k].row_off + g.nup) / 256; ++r) chunk_model[r] = 0;
+            for (int z = 0; z < nsplit; ++z)
+                for (int cb = 0; cb < ldx / Q32_COLS; ++cb)
+                    for (int rb = 0; rb < (int)(g.np / 256); ++rb) t32q.push_back(make_int4(kk, rb, cb, z));
+            for (int cb = 0; cb < ldx / Q64_COLS; ++cb)
+                for (int rb = 0; rb < (int)(g.np / 128); ++rb) t64q.push_back(make_int4(kk, rb, cb, 0));
+        } else {
+            for (int cb = 0; cb < ldx / D32_COLS; ++cb)
+                for (int rb = 0; rb < (int)(g.np / 128); ++rb) t32d.push_back(make_int4(kk, rb, cb, 0));
+            for (int cb = 0; cb < ldx / D64_COLS; ++cb)
+                for (int rb = 0; rb < (int)(g.np / 64); ++rb) t64d.push_back(make_int4(kk, rb, cb, 0));
+        }
+    }
+    impl->n32q = (int)t32q.size();
+    impl->n32d = (int)t32d.size();
+    impl->n64q = (int)t64q.size();
+    impl->n64d = (int)t64d.size();
+    hipError_t e;
+    if ((e = upload((void**)&impl->d_gc, gc.data(), sizeof(GroupConst) * gc.size(), st)) != hipSuccess) return e;
+    if ((e = upload((void**)&impl->d_t32q, t32q.data(), sizeof(int4) * t32q.size(), st)) != hipSuccess) return e;
+    if ((e = upload((void**)&impl->d_t32d, t32d.data(), sizeof(int4) * t32d.size(), st)) != hipSuccess) return e;
+    if ((e = upload((void**)&impl->d_t64q, t64q.data(), sizeof(int4) * t64q.size(), st)) != hipSuccess) return e;
+    if ((e = upload((void**)&impl->d_t64d, t64d.data(), sizeof(int4) * t64d.size(), st)) != hipSuccess) return e;
+    if ((e = upload((void**)&impl->d_chunk_model, chunk_model.data(), sizeof(int32_t) * chunk_model.size(), st)) !=
+        hipSuccess)
+        return e;
+    return hipStreamSynchronize(st);
+}
+
+size_t GroupedTApply::partial_bytes() const
+{
+    return impl->nsplit > 1 ? (size_t)impl->nsplit * impl->rows * impl->ldx * sizeof(float) : 0;
+}
+
+int64_t GroupedTApply::f32_tiles() const { return impl->n32q + impl->n32d; }
+
+void GroupedTApply::run_f32(const float* X, float* Y, float* partial, hipStream_t st) const
+{
+    const size_t zstride = (size_t)impl->rows * impl->ldx;
+    if (impl->n32q > 0) {
+        float* dst = impl->nsplit > 1 ? partial : Y;
+        hipLaunchKernelGGL(k_tapply_wfq_f32_grouped, dim3(impl->n32q), dim3(256), 0, st, impl->d_gc, impl->d_t32q, X,
+                           dst, impl->ldx, zstride);
+        if (impl->nsplit > 1) {
+            const size_t len = (size_t)impl->rows * impl->ldx;
+            hipLaunchKernelGGL(k_sum_splits_grouped, dim3((unsigned)((len / 4 + 255) / 256)), dim3(256), 0, st,
+                               partial, Y, impl->d_chunk_model, impl->rows, impl->ldx, zstride, impl->nsplit);
+        }
+    }
+    if (impl->n32d > 0)
+        hipLaunchKernelGGL(k_tapply_wfqfmu_f32_grouped, dim3(impl->n32d), dim3(256), 0, st, impl->d_gc, impl->d_t32d,
+                           X, Y, impl->ldx);
+}
+
+void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st) const
+{
+    if (impl->n64q > 0)
+        hipLaunchKernelGGL(k_tapply_wfq_f64_grouped, dim3(impl->n64q), dim3(256), 0, st, impl->d_gc, impl->d_t64q, X, Y,
+                           impl->ldx);
+    if (impl->n64d > 0)
+        hipLaunchKernelGGL(k_tapply_wfqfmu_f64_grouped, dim3(impl->n64d), dim3(256), 0, st, impl->d_gc, impl->d_t64d,
+                           X, Y, impl->ldx);
 }
 
 }  // namespace px
