@@ -103,6 +103,118 @@ def cpu_baseline(case, lu_steps):
                 measured_s=round(t2 - t0, 2))
 
 
+def make_structure(pxm, case):
+    s = pxm.Structure(case["model"], case["xyz"], case["params"], pxm.default_stream())
+    s.set_frequencies(case["omega_ev"], case["pol_mask"], case["e0"], case["alpha_ib"])
+    return s
+
+
+def ncols(case):
+    return len(case["omega_ev"]) * bin(case["pol_mask"]).count("1")
+
+
+def batch_run(pxm, cases, precision, block_cols=64):
+    """All structures in one stacked block (pxSolveBatch); returns timing and statuses."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ss = [make_structure(pxm, c) for c in cases]
+    st = pxm.solve_batch(ss, precision=precision, rel_tol=1e-8, block_cols=block_cols, max_restart_m=100)
+    sig = [s.spectrum()[1] for s in ss]
+    rr = max(float(s.stats()[2].max()) for s in ss)
+    for s in ss:
+        s.close()
+    torch.cuda.synchronize()
+    return dict(seconds=time.perf_counter() - t0, status=int(st), relres_max=rr, sigma=sig)
+
+
+def sequential_run(pxm, cases, precision, max_block_cols=0):
+    """One structure after the other, each with pxSolveSpectrum."""
+    import torch
+    out = []
+    for c in cases:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = make_structure(pxm, c)
+        st = s.solve(precision=precision, rel_tol=1e-8, max_block_cols=max_block_cols, max_restart_m=100)
+        sig = s.spectrum()[1]
+        s.close()
+        torch.cuda.synchronize()
+        out.append(dict(seconds=time.perf_counter() - t0, status=int(st), sigma=sig))
+    return out
+
+
+def serving_run(pxm, cases, arrivals, budget_bytes, block_cols=64):
+    """Continuous batching: request k arrives at arrivals[k] (s after start) and
+    joins the server's block at the next restart boundary that has room."""
+    import torch
+    sv = pxm.Server(budget_bytes, pxm.default_stream(), precision=pxm.PX_MIXED, rel_tol=1e-8,
+                    block_cols=block_cols, max_restart_m=100)
+    t0 = time.perf_counter()
+    pending = list(range(len(cases)))
+    live = {}
+    lat = [None] * len(cases)
+    sig = [None] * len(cases)
+    peak_rows = 0
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and arrivals[pending[0]] <= now:
+            k = pending.pop(0)
+            s = make_structure(pxm, cases[k])
+            sv.submit(s)
+            live[s.h.value] = (k, s)
+        q = sv.query()
+        if q["active"] == 0 and q["queued"] == 0:
+            if pending:
+                time.sleep(max(0.0, arrivals[pending[0]] - (time.perf_counter() - t0)))
+            continue
+        for h in sv.step():
+            k, s = live.pop(h)
+            lat[k] = time.perf_counter() - t0 - arrivals[k]
+            sig[k] = s.spectrum()[1]
+            s.close()
+        peak_rows = max(peak_rows, sv.query()["rows_in_use"])
+    makespan = time.perf_counter() - t0
+    cap = sv.query()["rows_capacity"]
+    sv.close()
+    return dict(latency=lat, makespan=makespan, sigma=sig, peak_rows=peak_rows, rows_capacity=cap)
+
+
+def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
+    from workloads import configs as C
+    rng = np.random.default_rng(seed)
+    cases = [C.serving_request(rng, n_min, n_max) for _ in range(n_req)]
+    cols = sum(ncols(c) for c in cases)
+    seq = sequential_run(pxm, cases, pxm.PX_MIXED)
+    t_seq = sum(r["seconds"] for r in seq)
+    lam = load * n_req / t_seq
+    arrivals = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / lam, n_req)) - 0.0
+    arrivals -= arrivals[0]
+    # sequential one-at-a-time under the same arrivals: FIFO queue
+    t, lat_seq = 0.0, []
+    for a, r in zip(arrivals, seq):
+        t = max(t, a) + r["seconds"]
+        lat_seq.append(t - a)
+    budget = 0.5 * torch_free_bytes()
+    srv = serving_run(pxm, cases, arrivals, budget, block_cols)
+    err = max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"]))) for a, b in zip(srv["sigma"], seq))
+    lat = np.array(srv["latency"])
+    return dict(requests=n_req, columns=cols, n_range=[n_min, n_max], arrival_rate_per_s=round(lam, 3),
+                load=load, solves_per_s=round(cols / srv["makespan"], 2),
+                p50_s=round(float(np.percentile(lat, 50)), 3), p99_s=round(float(np.percentile(lat, 99)), 3),
+                one_at_a_time_solves_per_s=round(cols / max(t, 1e-9), 2),
+                one_at_a_time_p50_s=round(float(np.percentile(lat_seq, 50)), 3),
+                one_at_a_time_p99_s=round(float(np.percentile(lat_seq, 99)), 3),
+                peak_rows=srv["peak_rows"], rows_capacity=srv["rows_capacity"],
+                sigma_rel_err_mix_vs_alone=err)
+
+
+def torch_free_bytes():
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    return float(free)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +230,11 @@ def main():
                     help="one restart cycle of 4 steps on the full workload (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
+    ap.add_argument("--workload", default="sphere",
+                    choices=["sphere", "batch-full", "serving-full"],
+                    help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
+                         "serving mix, printed as their own JSON lines")
+    ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box here has a single MI355X and the solver does not shard; "
@@ -138,6 +255,27 @@ def main():
     px = ensure_built()
     import paper_2510_12731_amd as pxm
     from workloads import configs as C
+
+    if args.workload == "batch-full":
+        cases = C.graphene_batch()
+        log(f"[bench] graphene batch: {len(cases)} structures, N {min(len(c['xyz']) for c in cases)}-"
+            f"{max(len(c['xyz']) for c in cases)}")
+        rb = batch_run(pxm, cases, pxm.PX_MIXED)
+        cols = sum(ncols(c) for c in cases)
+        print(json.dumps({"workload": "graphene_batch_64", "columns": cols, "mixed_batched_s": round(rb["seconds"], 2),
+                          "mixed_batched_solves_per_s": round(cols / rb["seconds"], 2), "status": rb["status"],
+                          "relres_max": rb["relres_max"]}), flush=True)
+        seq = sequential_run(pxm, cases, pxm.PX_FP64)
+        t64 = sum(r["seconds"] for r in seq)
+        err = max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"]))) for a, b in zip(rb["sigma"], seq))
+        print(json.dumps({"workload": "graphene_batch_64", "fp64_per_structure_s": round(t64, 2),
+                          "fp64_per_structure_solves_per_s": round(cols / t64, 2),
+                          "speedup": round(t64 / rb["seconds"], 2), "sigma_rel_err_vs_fp64": err}), flush=True)
+        return
+    if args.workload == "serving-full":
+        out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75)
+        print(json.dumps({"workload": "serving_mix_full", **out}), flush=True)
+        return
 
     case = C.sphere_20k(args.n, args.n_omega)
     ncol = len(case["omega_ev"]) * bin(case["pol_mask"]).count("1")
@@ -224,6 +362,23 @@ def main():
         extra["speedup_vs_fp64_blocked"] = round(value * (tb - ta) / ncol, 2)
         extra["sigma_rel_err_mixed_vs_fp64_blocked"] = float(
             np.max(np.abs(last["sigma"] - rb["sigma"])) / np.max(np.abs(rb["sigma"])))
+
+    if not args.no_extras:
+        from workloads import configs as C2
+        log("[bench] batch extra ...")
+        gb = C2.graphene_batch(n_struct=8, n_min=2000, n_max=12000)
+        rb = batch_run(pxm, gb, pxm.PX_MIXED)
+        cols = sum(ncols(c) for c in gb)
+        seq = sequential_run(pxm, gb, pxm.PX_FP64)
+        t64 = sum(r["seconds"] for r in seq)
+        extra["batch"] = dict(structures=len(gb), n_range=[2000, 12000], columns=cols,
+                              mixed_batched_solves_per_s=round(cols / rb["seconds"], 2),
+                              fp64_per_structure_solves_per_s=round(cols / t64, 2),
+                              speedup=round(t64 / rb["seconds"], 2), status=rb["status"],
+                              sigma_rel_err_vs_fp64=max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"])))
+                                                        for a, b in zip(rb["sigma"], seq)))
+        log("[bench] serving extra ...")
+        extra["serving"] = serving_extra(pxm, 16, 1000, 4000, 5, 0.75)
 
     cpu = None
     if not args.no_cpu_baseline:

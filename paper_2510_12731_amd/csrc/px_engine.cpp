@@ -234,15 +234,17 @@ std::vector<pxStructure_t*> Engine::cycle()
             const int gc = e.c0 + c, f = k * Bc_ + c;
             const double prev = s->relres[gc];
             s->relres[gc] = s->bnorm[gc] > 0.0 ? beta[f] / s->bnorm[gc] : 0.0;
-            if (s->cycles[gc] > 0 && s->relres[gc] > 0.98 * prev) s->stall[gc] += 1;
-            else s->stall[gc] = 0;
+            // x is unchanged since the last residual if that pass only retired segments
+            const bool moved = !relaid_only_ && s->cycles[gc] > 0;
+            if (moved && s->relres[gc] > 0.98 * prev) s->stall[gc] += 1;
+            else if (moved) s->stall[gc] = 0;
             if (s->relres[gc] > o_.rel_tol && s->cycles[gc] < o_.max_cycles &&
                 (o_.stall_cycles == 0 || s->stall[gc] < o_.stall_cycles)) {
                 active = true;
                 done[f] = 0;
                 tgt[f] = std::max(0.5 * o_.rel_tol * s->bnorm[gc], mixed ? beta[f] * o_.inner_reduction : 0.0);
                 g0[f] = make_double2(beta[f], 0.0);
-                if (s->cycles[gc] > 0 && s->relres[gc] > 0.7 * prev) slow = true;
+                if (moved && s->relres[gc] > 0.7 * prev) slow = true;
             }
         }
         if (!active) {
@@ -262,9 +264,11 @@ std::vector<pxStructure_t*> Engine::cycle()
         segs_.erase(std::remove_if(segs_.begin(), segs_.end(), [](const EngineSeg& e) { return e.finished; }),
                     segs_.end());
         dirty_ = true;
+        relaid_only_ = true;
         HC(hipStreamSynchronize(st_));
         return finished;   // the remaining segments restart from a fresh layout
     }
+    relaid_only_ = false;
     if (slow && m_ < m_max_) {
         m_ = std::min(2 * m_, m_max_);
         for (EngineSeg& e : segs_)

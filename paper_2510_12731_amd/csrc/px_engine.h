@@ -58,6 +58,7 @@ class Engine {
     std::vector<EngineSeg> segs_;
     std::map<pxStructure_t*, int> open_;   // structure -> segments not yet retired
     bool dirty_ = true;
+    bool relaid_only_ = false;   // last cycle() only retired segments (x unchanged)
     int64_t rows_ = 0, pending_rows_ = 0;
     EngineStats stats_;
     px::GroupedTApply gt_;
