@@ -53,6 +53,11 @@ typedef enum {
                       Givens, solution update and true residual (iterative refinement) */
 } pxPrecision;
 
+typedef enum {
+    PX_ORTHO_CGS2 = 0,   /* classical Gram-Schmidt, two passes per Arnoldi step */
+    PX_ORTHO_DCGS2 = 1   /* the second pass delayed into the next step */
+} pxOrtho;
+
 /* Material parameters of one homogeneous nanostructure.
  *   a_eff            effective area A of Eq. (kappa), bohr^2
  *   r_q, r_mu        Gaussian widths of charges (Eq. tqq) and dipoles, bohr
@@ -102,6 +107,11 @@ typedef struct {
  *   stall_cycles     a column is given up (and reported unconverged) after
  *                    this many consecutive cycles that each removed less than
  *                    2 % of its true residual; 0 = never (8)
+ *   ortho            Arnoldi orthogonalisation: PX_ORTHO_DCGS2 (default),
+ *                    classical Gram-Schmidt twice with the second pass delayed
+ *                    into the next step (one dot and one update pass over the
+ *                    basis per step), or PX_ORTHO_CGS2, both passes in the
+ *                    same step (two of each)
  */
 typedef struct {
     int32_t precision;
@@ -114,6 +124,7 @@ typedef struct {
     int32_t stall_cycles;
     int32_t max_restart_m;
     int32_t block_cols;
+    int32_t ortho;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libplasmonx_hip.so")
 PX_OK, PX_E_INVALID, PX_E_OOM, PX_E_NOTCONV, PX_E_DEVICE, PX_E_STATE = range(6)
 PX_WFQ, PX_WFQFMU = 0, 1
 PX_FP64, PX_MIXED = 0, 1
+PX_ORTHO_CGS2, PX_ORTHO_DCGS2 = 0, 1
 STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV", 4: "PX_E_DEVICE", 5: "PX_E_STATE"}
 
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
@@ -44,7 +45,7 @@ class pxSolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("restart_m", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
                 ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
-                ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32)]
+                ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("ortho", ctypes.c_int32)]
 
 
 _lib = None
@@ -217,7 +218,8 @@ def pxLastError():
 
 
 def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
-                  inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0):
+                  inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
+                  ortho=None):
     o = pxDefaultSolveOptions()
     o.precision = int(precision)
     o.restart_m = int(restart_m)
@@ -229,6 +231,8 @@ def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400
     o.stall_cycles = int(stall_cycles)
     o.max_restart_m = int(max_restart_m)
     o.block_cols = int(block_cols)
+    if ortho is not None:
+        o.ortho = int(ortho)
     return o
 
 

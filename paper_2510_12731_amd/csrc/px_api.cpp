@@ -124,11 +124,16 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.X32 = dalloc<float>(2 * vec);
     W.Y32 = dalloc<float>(2 * vec);
     W.Y64 = dalloc<double>(2 * vec);
-    W.partial = dalloc<double2>((size_t)nchunk * (m + 1) * lda);
+    W.partial = dalloc<double2>(std::max((size_t)nchunk * (m + 1), px::dot_partial_slabs(nup, m + 1)) * 2 * lda);
     W.npart = dalloc<double>((size_t)std::max(nchunk, px::update_chunks(nup)) * lda);
     W.h1 = dalloc<double2>((size_t)(m + 1) * lda);
     W.h2 = dalloc<double2>((size_t)(m + 1) * lda);
     W.R = dalloc<double2>((size_t)m * (m + 1) * lda);
+    W.H = dalloc<double2>((size_t)m * (m + 1) * lda);
+    W.G = dalloc<double2>((size_t)(m + 1) * 2 * lda);
+    W.coefQ = dalloc<double2>((size_t)m * 2 * lda);
+    W.coefV = dalloc<double2>((size_t)2 * lda);
+    W.aux = dalloc<double2>((size_t)2 * lda);
     W.sn = dalloc<double2>((size_t)m * lda);
     W.gv = dalloc<double2>((size_t)(m + 1) * lda);
     W.y = dalloc<double2>((size_t)m * lda);
@@ -227,6 +232,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
     const int m_max = std::max(o.restart_m, o.max_restart_m);
     const int64_t nup = s->g.nup;
     const bool mixed = o.precision == PX_MIXED;
+    const bool dcgs2 = o.ortho == PX_ORTHO_DCGS2;
     const int nchunk = px::arnoldi_chunks(nup);
     Timer tm(o.timings != 0, s->st);
     std::vector<int32_t> done_h, steps_h;
@@ -325,16 +331,26 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
                                W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st);
                 tm.mark(2);
-                // CGS2 against v_0..v_k
-                px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
-                px::reduce_dots(W.partial, nchunk, k + 1, W.h1, na, lda, false, s->st);
-                px::col_update(W.V, vstride, k + 1, W.h1, W.w, nullptr, na, lda, nup, s->st);
-                px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
-                px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
-                px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
+                if (dcgs2) {
+                    // one dot pass and one update pass; column k-1 is finished here
+                    px::dots2(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                    px::reduce_dots2(W.partial, nup, k + 1, W.G, na, lda, s->st);
+                    px::dcgs2_coef(k, m, false, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
+                                   W.aux, W.coefQ, W.coefV, na, lda, s->st);
+                    px::dcgs2_update(W.V, vstride, k, W.coefQ, W.coefV, W.w, W.npart, na, lda, nup, s->st);
+                } else {
+                    // CGS2 against v_0..v_k
+                    px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                    px::reduce_dots(W.partial, nchunk, k + 1, W.h1, na, lda, false, s->st);
+                    px::col_update(W.V, vstride, k + 1, W.h1, W.w, nullptr, na, lda, nup, s->st);
+                    px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                    px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
+                    px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
+                }
                 px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st);
-                px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, nullptr,
-                                na, lda, s->st);
+                if (!dcgs2)
+                    px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
+                                    nullptr, na, lda, s->st);
                 px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride, mixed ? W.X32 : nullptr, na, lda, nup,
                               s->st);
                 tm.mark(3);
@@ -348,6 +364,13 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 bool all = true;
                 for (int q = 0; q < na; ++q) all = all && done_h[q];
                 if (all) break;
+                if (dcgs2 && k == m - 1) {
+                    // the last basis vector's correction finishes column m-1
+                    px::dots2(W.V, vstride, m + 1, W.V + m * vstride, W.partial, na, lda, nup, s->st);
+                    px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st);
+                    px::dcgs2_coef(m, m, true, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
+                                   W.aux, W.coefQ, W.coefV, na, lda, s->st);
+                }
             }
             px::lsq_solve(m, W.R, W.gv, W.steps, W.y, na, lda, s->st);
             px::x_update(W.V, vstride, W.y, W.steps, m, W.xs, na, lda, nup, s->st);
@@ -370,6 +393,7 @@ pxStatus check_options(const pxSolveOptions& o)
         return fail(PX_E_INVALID, "restart_m and max_restart_m must be in [1, 1000]");
     if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
+        (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -433,6 +457,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->stall_cycles = 8;
     o->max_restart_m = 200;
     o->block_cols = 0;
+    o->ortho = PX_ORTHO_DCGS2;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }

@@ -132,6 +132,24 @@ void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* p
                 hipStream_t st);
 void fill_zero(void* p, size_t bytes, hipStream_t st);
 
+// CGS2 with delayed reorthogonalisation (px_kernels.hip): G is [nvec][2][lda],
+// H the raw Hessenberg [m][m+1][lda], coefQ [m][2][lda], coefV [2][lda].
+// The dot pass sums dot_rows(nvec) rows per partial; partial holds
+// dot_chunks(nup, nvec) x nvec x 2 x lda values, at most
+// dot_partial_slabs(nup, nvec_max) x 2 x lda for bases up to nvec_max vectors.
+int dot_rows(int nvec);
+inline int dot_chunks(int64_t nup, int nvec) { return (int)((nup + dot_rows(nvec) - 1) / dot_rows(nvec)); }
+size_t dot_partial_slabs(int64_t nup, int nvec_max);
+void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
+           int64_t nup, hipStream_t st);
+void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st);
+// aux: [2][lda] scratch (rho, c_k) between the column-serial and the row-parallel part
+void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
+                double* cs, double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps,
+                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st);
+void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
+                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st);
+
 // ---- stacked segments (px_engine.cpp) ---------------------------------------
 // One segment of a stacked block: a structure's padded rows (np or 4 np) with
 // Bc columns, starting at row_off (a multiple of 256).

@@ -503,7 +503,7 @@ __global__ __launch_bounds__(256) void k_normalize(const double2* __restrict__ w
     if (r >= nup || c >= lda) return;
     const size_t o = (size_t)r * lda + c;
     double2 out = make_double2(0.0, 0.0);
-    if (c < na && !(done && done[c])) {
+    if (c < na && !(done && done[c]) && nrm[c] > 0.0) {
         const double s = 1.0 / nrm[c];
         const double2 a = w[o];
         out = make_double2(a.x * s, a.y * s);
@@ -530,19 +530,15 @@ __global__ __launch_bounds__(256) void k_to_f32(const double2* __restrict__ v, f
 // least-squares residual estimate |g_{k+1}|.
 //   R  [m][m+1][lda]  (column k holds R_{0..k,k}),  cs [m][lda], sn [m][lda]
 //   g  [m+1][lda]
-__global__ void k_givens(int k, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
-                         const double* __restrict__ nrm, double2* __restrict__ R, double* __restrict__ cs,
-                         double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ target,
-                         int32_t* __restrict__ done, int32_t* __restrict__ steps, int na, int lda)
+// Rotates column k of R (rows 0..k already hold the Hessenberg entries,
+// bb = the real sub-diagonal entry H_{k+1,k}) through the stored rotations,
+// forms rotation k and updates g, steps and done.
+__device__ void rotate_column(int k, int m, int c, int lda, double bb, double2* __restrict__ R,
+                              double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                              const double* __restrict__ target, int32_t* __restrict__ done,
+                              int32_t* __restrict__ steps)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= na || done[c]) return;
     double2* Rk = R + (size_t)k * (m + 1) * lda;
-    for (int j = 0; j <= k; ++j) {
-        const double2 a = h1[(size_t)j * lda + c], b = h2[(size_t)j * lda + c];
-        Rk[(size_t)j * lda + c] = make_double2(a.x + b.x, a.y + b.y);
-    }
-    double2 hk1 = make_double2(nrm[c], 0.0);
     for (int j = 0; j < k; ++j) {
         const double cj = cs[(size_t)j * lda + c];
         const double2 sj = sn[(size_t)j * lda + c];
@@ -554,7 +550,7 @@ __global__ void k_givens(int k, int m, const double2* __restrict__ h1, const dou
         Rk[(size_t)(j + 1) * lda + c] = make_double2(cj * b.x - sa.x, cj * b.y - sa.y);
     }
     const double2 a = Rk[(size_t)k * lda + c];
-    const double aa = hypot(a.x, a.y), bb = hk1.x;
+    const double aa = hypot(a.x, a.y);
     const double rr = hypot(aa, bb);
     double ck;
     double2 sk;
@@ -570,8 +566,7 @@ __global__ void k_givens(int k, int m, const double2* __restrict__ h1, const dou
     }
     cs[(size_t)k * lda + c] = ck;
     sn[(size_t)k * lda + c] = sk;
-    const double2 rk = make_double2(ck * a.x + sk.x * bb, ck * a.y + sk.y * bb);
-    Rk[(size_t)k * lda + c] = rk;
+    Rk[(size_t)k * lda + c] = make_double2(ck * a.x + sk.x * bb, ck * a.y + sk.y * bb);
     const double2 gk = g[(size_t)k * lda + c];
     const double2 gk1 = cconjmul(sk, gk);
     g[(size_t)(k + 1) * lda + c] = make_double2(-gk1.x, -gk1.y);
@@ -579,6 +574,21 @@ __global__ void k_givens(int k, int m, const double2* __restrict__ h1, const dou
     steps[c] = k + 1;
     const double est = hypot(gk1.x, gk1.y);
     if (est <= target[c] || k + 1 >= m || bb == 0.0) done[c] = 1;
+}
+
+__global__ void k_givens(int k, int m, const double2* __restrict__ h1, const double2* __restrict__ h2,
+                         const double* __restrict__ nrm, double2* __restrict__ R, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, const double* __restrict__ target,
+                         int32_t* __restrict__ done, int32_t* __restrict__ steps, int na, int lda)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= na || done[c]) return;
+    double2* Rk = R + (size_t)k * (m + 1) * lda;
+    for (int j = 0; j <= k; ++j) {
+        const double2 a = h1[(size_t)j * lda + c], b = h2[(size_t)j * lda + c];
+        Rk[(size_t)j * lda + c] = make_double2(a.x + b.x, a.y + b.y);
+    }
+    rotate_column(k, m, c, lda, nrm[c], R, cs, sn, g, target, done, steps);
 }
 
 // y = R^{-1} g over the first steps[c] rows (back substitution per column).
@@ -731,6 +741,277 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words)
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; t < words; t += stride) p[t] = 0u;
+}
+
+// ============ CGS2 with delayed reorthogonalisation (two passes) =============
+// Step k holds v_0..v_{k-1} orthonormal and u = V_k, a vector that had one
+// projection pass.  With w~ = A u (the matvec of this step):
+//   one dot pass   G[j][0] = <v_j, u>, G[j][1] = <v_j, w~>  (j <= k, v_k := u)
+//   coefficients   s = G[<k][0], rho^2 = <u,u> - |s|^2, v_k = (u - V s) / rho;
+//                  the previous Hessenberg column gets its lagged correction
+//                  H[<k][k-1] += b s, H[k][k-1] = b rho (b = its tentative norm)
+//                  and its Givens rotation; c = V_k^H w~, h = (c - H s) / rho
+//   one update     v_k = u/rho - V (s/rho),  w' = w~/rho - (c_k/rho^2) u - V d
+//                  with d = (c_<k - (c_k/rho) s) / rho, and |w'|^2 partials.
+// w' is normalised into V_{k+1} for the next step; its own second pass is the
+// next step's lagged correction.
+
+// partial[chunk][j][t][c], t = 0: <V_j, V_{nvec-1}>, t = 1: <V_j, w>.
+// One wave per (DOT_JB basis vectors, row chunk, 64 columns).  Loads are
+// unconditional (the last group repeats its final vector), so a row's
+// DOT_JB + 2 loads issue back to back.  The hardware hands block L to XCD
+// L mod 8; the blocks are renumbered so that the j-groups of one row chunk,
+// which all read the same rows of u and w, run on one XCD and share its L2.
+constexpr int DOT_JB = 8;
+__global__ __launch_bounds__(64) void k_dots2(const double2* __restrict__ V, int64_t vstride, int nvec,
+                                              const double2* __restrict__ w, double2* __restrict__ partial, int na,
+                                              int lda, int64_t nup, int rows_per, int njg, int nch)
+{
+    const int nb = gridDim.x, L = blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, x = L & 7;
+    const int lam = (x < r8 ? x * (q8 + 1) : r8 * (q8 + 1) + (x - r8) * q8) + (L >> 3);
+    const int jg = lam % njg;
+    const int rest = lam / njg;
+    const int chunk = rest % nch;
+    const int c = (rest / nch) * 64 + (int)threadIdx.x;
+    if (c >= na) return;
+    const int j0 = jg * DOT_JB;
+    const int64_t r0 = (int64_t)chunk * rows_per;
+    const int64_t r1 = min(nup, r0 + rows_per);
+    const double2* vq[DOT_JB];
+#pragma unroll
+    for (int q = 0; q < DOT_JB; ++q) vq[q] = V + (size_t)min(j0 + q, nvec - 1) * vstride + c;
+    const double2* u = V + (size_t)(nvec - 1) * vstride + c;
+    const double2* wc = w + c;
+    double a0r[DOT_JB], a0i[DOT_JB], a1r[DOT_JB], a1i[DOT_JB];
+#pragma unroll
+    for (int q = 0; q < DOT_JB; ++q) a0r[q] = a0i[q] = a1r[q] = a1i[q] = 0.0;
+#pragma unroll 2
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t o = (size_t)r * lda;
+        const double2 x0 = u[o];
+        const double2 x1 = wc[o];
+        double2 v[DOT_JB];
+#pragma unroll
+        for (int q = 0; q < DOT_JB; ++q) v[q] = vq[q][o];
+#pragma unroll
+        for (int q = 0; q < DOT_JB; ++q) {
+            a0r[q] = fma(v[q].x, x0.x, fma(v[q].y, x0.y, a0r[q]));
+            a0i[q] = fma(v[q].x, x0.y, fma(-v[q].y, x0.x, a0i[q]));
+            a1r[q] = fma(v[q].x, x1.x, fma(v[q].y, x1.y, a1r[q]));
+            a1i[q] = fma(v[q].x, x1.y, fma(-v[q].y, x1.x, a1i[q]));
+        }
+    }
+    const int nj = min(DOT_JB, nvec - j0);
+#pragma unroll
+    for (int q = 0; q < DOT_JB; ++q)
+        if (q < nj) {
+            double2* o = partial + (((size_t)chunk * nvec + j0 + q) * 2) * lda + c;
+            o[0] = make_double2(a0r[q], a0i[q]);
+            o[lda] = make_double2(a1r[q], a1i[q]);
+        }
+}
+
+// G[j][t][c] = sum over chunks
+__global__ void k_reduce_dots2(const double2* __restrict__ partial, int nchunk, int nvec, double2* __restrict__ G,
+                               int na, int lda)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nvec * 2 * lda) return;
+    const int jt = t / lda, c = t - jt * lda;
+    if (c >= na) return;
+    double ar = 0.0, ai = 0.0;
+    for (int k = 0; k < nchunk; ++k) {
+        const double2 p = partial[((size_t)k * nvec * 2 + jt) * lda + c];
+        ar += p.x;
+        ai += p.y;
+    }
+    G[(size_t)jt * lda + c] = make_double2(ar, ai);
+}
+
+// Step k, per column (one thread each): rho of the corrected v_k, the lagged
+// correction of Hessenberg column k-1 (H[<k][k-1] += b s, H[k][k-1] = b rho)
+// with its Givens rotation, and c_k = <v_k, w~>.  aux[c] = (rho, c_k).
+// final_only: the cycle's last correction, nothing after the rotation.
+__global__ void k_dcgs2_fix(int k, int m, int final_only, const double2* __restrict__ G,
+                            const double* __restrict__ nrm, double2* __restrict__ H, double2* __restrict__ R,
+                            double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
+                            const double* __restrict__ target, int32_t* __restrict__ done,
+                            int32_t* __restrict__ steps, double2* __restrict__ aux, int na, int lda)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= na || done[c]) return;
+    const size_t ld2 = 2 * (size_t)lda;
+    const double2* Gs = G + c;              // s_j = Gs[j * ld2]
+    const double2* Gt = G + lda + c;        // t_j = <v_j, w~> = Gt[j * ld2]
+    double ss = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < k; ++j) {
+        const double2 sj = Gs[(size_t)j * ld2];
+        ss = fma(sj.x, sj.x, fma(sj.y, sj.y, ss));
+    }
+    const double rho = sqrt(fmax(Gs[(size_t)k * ld2].x - ss, 1e-300));
+    if (k >= 1) {
+        const int col = k - 1;
+        const double b = nrm[c];
+        double2* Hc = H + (size_t)col * (m + 1) * lda + c;
+        double2* Rc = R + (size_t)col * (m + 1) * lda + c;
+        // corrected entries h_j = H[j][col] + b s_j, rotated on the fly by the
+        // col stored rotations; a carries the partially rotated entry j
+        double2 a;
+        {
+            const double2 h = Hc[0], sj = Gs[0];
+            a = make_double2(fma(b, sj.x, h.x), fma(b, sj.y, h.y));
+            Hc[0] = a;
+        }
+#pragma unroll 4
+        for (int j = 0; j < col; ++j) {
+            const double2 h = Hc[(size_t)(j + 1) * lda], sv = Gs[(size_t)(j + 1) * ld2];
+            const double cj = cs[(size_t)j * lda + c];
+            const double2 sj = sn[(size_t)j * lda + c];
+            const double2 hb = make_double2(fma(b, sv.x, h.x), fma(b, sv.y, h.y));
+            Hc[(size_t)(j + 1) * lda] = hb;
+            // [a; hb] <- [c a + s hb; -conj(s) a + c hb]
+            const double2 sb = cmul(sj, hb);
+            const double2 sa = cconjmul(sj, a);
+            Rc[(size_t)j * lda] = make_double2(cj * a.x + sb.x, cj * a.y + sb.y);
+            a = make_double2(cj * hb.x - sa.x, cj * hb.y - sa.y);
+        }
+        const double bb = b * rho;
+        Hc[(size_t)k * lda] = make_double2(bb, 0.0);
+        const double aa = hypot(a.x, a.y);
+        const double rr = hypot(aa, bb);
+        double ck;
+        double2 sk;
+        if (rr == 0.0) {
+            ck = 1.0;
+            sk = make_double2(0.0, 0.0);
+        } else if (aa == 0.0) {
+            ck = 0.0;
+            sk = make_double2(1.0, 0.0);
+        } else {
+            ck = aa / rr;
+            sk = make_double2(a.x / aa * bb / rr, a.y / aa * bb / rr);
+        }
+        cs[(size_t)col * lda + c] = ck;
+        sn[(size_t)col * lda + c] = sk;
+        Rc[(size_t)col * lda] = make_double2(ck * a.x + sk.x * bb, ck * a.y + sk.y * bb);
+        const double2 gk = g[(size_t)col * lda + c];
+        const double2 gk1 = cconjmul(sk, gk);
+        g[(size_t)(col + 1) * lda + c] = make_double2(-gk1.x, -gk1.y);
+        g[(size_t)col * lda + c] = make_double2(ck * gk.x, ck * gk.y);
+        steps[c] = col + 1;
+        if (hypot(gk1.x, gk1.y) <= target[c] || col + 1 >= m || bb == 0.0) {
+            done[c] = 1;
+            return;
+        }
+    }
+    if (final_only) return;
+    double2 cv = Gt[(size_t)k * ld2];
+#pragma unroll 4
+    for (int j = 0; j < k; ++j) {
+        const double2 st = cconjmul(Gs[(size_t)j * ld2], Gt[(size_t)j * ld2]);
+        cv.x -= st.x;
+        cv.y -= st.y;
+    }
+    aux[c] = make_double2(rho, 0.0);
+    aux[lda + c] = make_double2(cv.x / rho, cv.y / rho);
+}
+
+// Step k, one wave per (row i <= k, 64 columns): the tentative Hessenberg
+// column h_i = (c_i - (H s)_i) / rho, and the update coefficients
+// coefQ[i] = (s_i / rho, d_i) for i < k, coefV = (1/rho, c_k/rho^2) for i = k.
+// Columns that are done get zero coefficients.
+__global__ __launch_bounds__(256) void k_dcgs2_coef(int k, int m, const double2* __restrict__ G,
+                                                    const double2* __restrict__ aux, double2* __restrict__ H,
+                                                    const int32_t* __restrict__ done, double2* __restrict__ coefQ,
+                                                    double2* __restrict__ coefV, int na, int lda)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i > k || c >= na) return;
+    const size_t ld2 = 2 * (size_t)lda;
+    double2* cq = (i < k) ? coefQ + (size_t)i * ld2 + c : coefV + c;
+    if (done[c]) {
+        cq[0] = make_double2(0.0, 0.0);
+        cq[lda] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double rho = aux[c].x;
+    const double2 ckr = aux[lda + c];        // c_k = <v_k, w~>
+    const double2 e = make_double2(ckr.x / rho, ckr.y / rho);
+    // (H s)_i over the columns j >= i - 1 (H is upper Hessenberg)
+    double hr = 0.0, hi = 0.0;
+    const double2* Hi = H + (size_t)i * lda + c;
+    const double2* Gs = G + c;
+#pragma unroll 4
+    for (int j = (i > 0 ? i - 1 : 0); j < k; ++j) {
+        const double2 h = Hi[(size_t)j * (m + 1) * lda], sj = Gs[(size_t)j * ld2];
+        hr = fma(h.x, sj.x, fma(-h.y, sj.y, hr));
+        hi = fma(h.x, sj.y, fma(h.y, sj.x, hi));
+    }
+    const double2 ci = (i < k) ? G[(size_t)i * ld2 + lda + c] : ckr;
+    H[((size_t)k * (m + 1) + i) * lda + c] = make_double2((ci.x - hr) / rho, (ci.y - hi) / rho);
+    if (i < k) {
+        const double2 si = Gs[(size_t)i * ld2];
+        const double2 es = cmul(e, si);
+        cq[0] = make_double2(si.x / rho, si.y / rho);
+        cq[lda] = make_double2((ci.x - es.x) / rho, (ci.y - es.y) / rho);
+    } else {
+        cq[0] = make_double2(1.0 / rho, 0.0);
+        cq[lda] = make_double2(e.x / rho, e.y / rho);
+    }
+}
+
+// V_k <- V_k/rho - sum_j V_j (s_j/rho);  w <- w/rho - (c_k/rho^2) V_k(old) - sum_j V_j d_j
+__global__ __launch_bounds__(256) void k_dcgs2_update(double2* __restrict__ V, int64_t vstride, int k,
+                                                      const double2* __restrict__ coefQ,
+                                                      const double2* __restrict__ coefV, double2* __restrict__ w,
+                                                      double* __restrict__ norm_partial, int na, int lda, int64_t nup)
+{
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.y * 64 + lane;
+    const int64_t rg = (int64_t)blockIdx.x * UPD_ROWS + wave * ARN_RG;
+    const size_t ld2 = 2 * (size_t)lda;
+    double nrm = 0.0;
+    if (c < na && rg < nup) {
+        const double2 p = coefV[c], qv = coefV[lda + c];
+        double2* u = V + (size_t)k * vstride + (size_t)rg * lda + c;
+        double2 av[ARN_RG], aw[ARN_RG];
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q) {
+            const double2 uu = u[(size_t)q * lda];
+            const double2 ww = w[(size_t)(rg + q) * lda + c];
+            const double2 t = cmul(qv, uu);
+            av[q] = make_double2(p.x * uu.x, p.x * uu.y);
+            aw[q] = make_double2(p.x * ww.x - t.x, p.x * ww.y - t.y);
+        }
+        const double2* vb = V + (size_t)rg * lda + c;
+#pragma unroll 2
+        for (int j = 0; j < k; ++j) {
+            const double2 a = coefQ[(size_t)j * ld2 + c];
+            const double2 d = coefQ[(size_t)j * ld2 + lda + c];
+            const double2* vj = vb + (size_t)j * vstride;
+#pragma unroll
+            for (int q = 0; q < ARN_RG; ++q) {
+                const double2 v = vj[(size_t)q * lda];
+                const double2 ta = cmul(v, a), td = cmul(v, d);
+                av[q].x -= ta.x; av[q].y -= ta.y;
+                aw[q].x -= td.x; aw[q].y -= td.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ARN_RG; ++q) {
+            u[(size_t)q * lda] = av[q];
+            w[(size_t)(rg + q) * lda + c] = aw[q];
+            nrm = fma(aw[q].x, aw[q].x, fma(aw[q].y, aw[q].y, nrm));
+        }
+    }
+    red[wave][lane] = nrm;
+    __syncthreads();
+    if (wave == 0 && c < na)
+        norm_partial[(size_t)blockIdx.x * lda + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // ============================ stacked segments ==============================
@@ -1170,6 +1451,55 @@ void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int
 {
     hipLaunchKernelGGL(k_x_update_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, V, vstride, y, steps, chunk_seg, x,
                        Bc, nseg * Bc, rows);
+}
+
+// ---- delayed-reorthogonalisation launchers ------------------------------------
+
+int dot_rows(int nvec)
+{
+    // shorter row chunks for short bases keep enough waves in flight
+    return nvec > 48 ? 256 : (nvec > 16 ? 128 : 64);
+}
+
+size_t dot_partial_slabs(int64_t nup, int nvec_max)
+{
+    size_t best = 0;
+    for (int v = 1; v <= nvec_max; ++v) best = std::max(best, (size_t)dot_chunks(nup, v) * v);
+    return best;
+}
+
+void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
+           int64_t nup, hipStream_t st)
+{
+    const int rows = dot_rows(nvec), nch = dot_chunks(nup, nvec);
+    const int njg = (nvec + DOT_JB - 1) / DOT_JB, ncb = (na + 63) / 64;
+    hipLaunchKernelGGL(k_dots2, dim3((unsigned)(njg * nch * ncb)), dim3(64), 0, st, V, vstride, nvec, w, partial,
+                       na, lda, nup, rows, njg, nch);
+}
+
+void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st)
+{
+    const int t = nvec * 2 * lda;
+    hipLaunchKernelGGL(k_reduce_dots2, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, partial,
+                       dot_chunks(nup, nvec), nvec, G, na, lda);
+}
+
+void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
+                double* cs, double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps,
+                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dcgs2_fix, dim3((unsigned)((na + 63) / 64)), dim3(64), 0, st, k, m, final_only ? 1 : 0, G,
+                       nrm, H, R, cs, sn, gvec, target, done, steps, aux, na, lda);
+    if (final_only) return;
+    hipLaunchKernelGGL(k_dcgs2_coef, dim3((unsigned)((k + 4) / 4), (unsigned)((na + 63) / 64)), dim3(256), 0, st, k,
+                       m, G, aux, H, done, coefQ, coefV, na, lda);
+}
+
+void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
+                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dcgs2_update, dim3(update_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, V,
+                       vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup);
 }
 
 }  // namespace px

@@ -57,6 +57,7 @@ struct Workspace {
     double2* partial = nullptr;
     double* npart = nullptr;
     double2 *h1 = nullptr, *h2 = nullptr, *R = nullptr, *sn = nullptr, *gv = nullptr, *y = nullptr;
+    double2 *H = nullptr, *G = nullptr, *coefQ = nullptr, *coefV = nullptr, *aux = nullptr;   // delayed reorth.
     double *cs = nullptr, *nrm = nullptr, *target = nullptr;
     int32_t *done = nullptr, *steps = nullptr, *map = nullptr;
     double2 *zq = nullptr, *zmu = nullptr;
@@ -66,7 +67,7 @@ struct Workspace {
 
     void release()
     {
-        void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, sn, gv, y, cs, nrm, target,
+        void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, H, G, coefQ, coefV, aux, sn, gv, y, cs, nrm, target,
                       done, steps, map, zq, zmu, narrow, split32};
         for (void* p : ps) dfree(p);
         *this = Workspace();

@@ -73,10 +73,10 @@ def test_operator_apply_matches_oracle(model, n):
 
 # ------------------------------------------------------------ full solves
 
-def _solve(model, xyz, params, om, pol, aib, precision, rel_tol, max_block_cols=0):
+def _solve(model, xyz, params, om, pol, aib, precision, rel_tol, max_block_cols=0, **kw):
     s = make(model, xyz, params)
     s.set_frequencies(om, pol, 1e-4, aib)
-    st = s.solve(precision=precision, rel_tol=rel_tol, max_block_cols=max_block_cols)
+    st = s.solve(precision=precision, rel_tol=rel_tol, max_block_cols=max_block_cols, **kw)
     alpha, sigma = s.spectrum()
     it, cyc, rr = s.stats()
     return s, st, alpha, sigma, it, rr
@@ -150,6 +150,36 @@ def test_one_column_solver_matches_blocked_solver():
     _, st2, _, s2, it2, _ = _solve(0, c["xyz"], c["params"], om, 0b001, None, px.PX_FP64, 1e-12)
     assert st1 == px.PX_OK and st2 == px.PX_OK
     assert rel_err(s1, s2) <= 1e-9
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(px.PX_FP64, 1e-12, 1e-10), (px.PX_MIXED, 1e-8, 1e-5)])
+def test_orthogonalisation_variants_agree(precision, tol, bound):
+    """Both Arnoldi orthogonalisations (two passes in the same step, or the
+    second delayed into the next step) reach the oracle's spectrum.  With
+    restart_m = 12 the cases take several cycles (full-length cycles that end
+    with the final correction, and columns finishing at different steps), on
+    both models."""
+    xyz = G.fcc_rod_n(300, seed=31)
+    p = M.load("au_wfqfmu")
+    om = np.linspace(1.6, 3.4, 7)
+    aib = M.interband_alpha(p, om)
+    ref = O.solve_spectrum(1, xyz, M.param_vector(p), om, 0b101, 1e-4, aib)
+    c = C.small_sphere()
+    ref_s = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
+    for ortho in (px.PX_ORTHO_CGS2, px.PX_ORTHO_DCGS2):
+        say(f"[ortho {ortho}] precision={precision}")
+        s, st, alpha, sigma, it, rr = _solve(1, xyz, p, om, 0b101, aib, precision, tol, ortho=ortho, restart_m=12,
+                                             max_restart_m=12, stall_cycles=0)
+        e = rel_err(sigma, ref["sigma"])
+        say(f"   rod: status {st} iters max {it.max()} relres max {rr.max():.2e} rel_err {e:.2e}")
+        assert st == px.PX_OK and e <= bound
+        s.close()
+        s, st, alpha, sigma, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
+                                             tol, ortho=ortho, restart_m=12, max_restart_m=12, stall_cycles=0)
+        e = rel_err(sigma, ref_s["sigma"])
+        say(f"   sphere: status {st} iters max {it.max()} relres max {rr.max():.2e} rel_err {e:.2e}")
+        assert st == px.PX_OK and e <= bound
+        s.close()
 
 
 def test_gap_dimer_conserves_charge_per_fragment():
