@@ -73,11 +73,17 @@ Engine::Engine(hipStream_t st, int Bc, const pxSolveOptions& o, int64_t rows_cap
     X32_ = dalloc<float>(2 * vec);
     Y32_ = dalloc<float>(2 * vec);
     Y64_ = dalloc<double>(2 * vec);
-    partial_ = dalloc<double2>((size_t)(rows_cap_ / 256) * (m_max_ + 1) * Bc_);
+    partial_ = dalloc<double2>(std::max((size_t)(rows_cap_ / 256) * (m_max_ + 1),
+                                        px::dot_partial_slabs(rows_cap_, m_max_ + 1)) * 2 * Bc_);
     npart_ = dalloc<double>((size_t)px::update_chunks(rows_cap_) * Bc_);
     h1_ = dalloc<double2>((size_t)(m_max_ + 1) * ldf);
     h2_ = dalloc<double2>((size_t)(m_max_ + 1) * ldf);
     R_ = dalloc<double2>((size_t)m_max_ * (m_max_ + 1) * ldf);
+    H_ = dalloc<double2>((size_t)m_max_ * (m_max_ + 1) * ldf);
+    G_ = dalloc<double2>((size_t)(m_max_ + 1) * 2 * ldf);
+    coefQ_ = dalloc<double2>((size_t)m_max_ * 2 * ldf);
+    coefV_ = dalloc<double2>((size_t)2 * ldf);
+    aux_ = dalloc<double2>((size_t)2 * ldf);
     sn_ = dalloc<double2>((size_t)m_max_ * ldf);
     gv_ = dalloc<double2>((size_t)(m_max_ + 1) * ldf);
     y_ = dalloc<double2>((size_t)m_max_ * ldf);
@@ -98,7 +104,8 @@ Engine::Engine(hipStream_t st, int Bc, const pxSolveOptions& o, int64_t rows_cap
 
 Engine::~Engine()
 {
-    void* ps[] = {V_, w_, xs_, rs_, bs_, xs2_, bs2_, X32_, Y32_, Y64_, partial_, npart_, h1_, h2_, R_, sn_, gv_, y_,
+    void* ps[] = {V_, w_, xs_, rs_, bs_, xs2_, bs2_, X32_, Y32_, Y64_, partial_, npart_, h1_, h2_, R_, H_, G_,
+                  coefQ_, coefV_, aux_, sn_, gv_, y_,
                   cs_, nrm_, target_, done_, steps_, zq_, zmu_, seginfo_, chunk_seg_, beg256_, beg32_, split_};
     for (void* p : ps) dfree(p);
 }
@@ -209,6 +216,7 @@ std::vector<pxStructure_t*> Engine::cycle()
     const int nseg = (int)segs_.size();
     const int ldf = nseg * Bc_;
     const bool mixed = o_.precision == PX_MIXED;
+    const bool dcgs2 = o_.ortho == PX_ORTHO_DCGS2;
     const int64_t rows = rows_;
 
     // ---- true residual of every segment (FP64)
@@ -297,14 +305,23 @@ std::vector<pxStructure_t*> Engine::cycle()
         }
         px::spmm_seg(seginfo_, chunk_seg_, mixed ? (const void*)Y32_ : (const void*)Y64_, mixed, 2 * Bc_, vk, zq_,
                      zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_);
-        px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
-        px::reduce_dots_seg(partial_, beg256_, k + 1, h1_, nseg, Bc_, st_);
-        px::col_update_seg(V_, vstride, k + 1, h1_, w_, nullptr, chunk_seg_, Bc_, nseg, rows, st_);
-        px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
-        px::reduce_dots_seg(partial_, beg256_, k + 1, h2_, nseg, Bc_, st_);
-        px::col_update_seg(V_, vstride, k + 1, h2_, w_, npart_, chunk_seg_, Bc_, nseg, rows, st_);
+        if (dcgs2) {
+            px::dots2(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
+            px::reduce_dots2(partial_, rows, k + 1, G_, Bc_, Bc_, st_, beg256_, nseg);
+            px::dcgs2_coef(k, m, false, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
+                           ldf, ldf, st_);
+            px::dcgs2_update(V_, vstride, k, coefQ_, coefV_, w_, npart_, Bc_, Bc_, rows, st_, chunk_seg_, ldf);
+        } else {
+            px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
+            px::reduce_dots_seg(partial_, beg256_, k + 1, h1_, nseg, Bc_, st_);
+            px::col_update_seg(V_, vstride, k + 1, h1_, w_, nullptr, chunk_seg_, Bc_, nseg, rows, st_);
+            px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
+            px::reduce_dots_seg(partial_, beg256_, k + 1, h2_, nseg, Bc_, st_);
+            px::col_update_seg(V_, vstride, k + 1, h2_, w_, npart_, chunk_seg_, Bc_, nseg, rows, st_);
+        }
         px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_);
-        px::givens_step(k, m, h1_, h2_, nrm_, R_, cs_, sn_, gv_, target_, done_, steps_, nullptr, ldf, ldf, st_);
+        if (!dcgs2)
+            px::givens_step(k, m, h1_, h2_, nrm_, R_, cs_, sn_, gv_, target_, done_, steps_, nullptr, ldf, ldf, st_);
         px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows, st_);
         HC(hipMemcpyAsync(done_h.data(), done_, sizeof(int32_t) * ldf, hipMemcpyDeviceToHost, st_));
         HC(hipStreamSynchronize(st_));
@@ -312,6 +329,13 @@ std::vector<pxStructure_t*> Engine::cycle()
         bool all = true;
         for (int f = 0; f < ldf && all; ++f) all = done_h[f] != 0;
         if (all) break;
+        if (dcgs2 && k == m - 1) {
+            // the last basis vector's correction finishes column m-1
+            px::dots2(V_, vstride, m + 1, V_ + m * vstride, partial_, Bc_, Bc_, rows, st_);
+            px::reduce_dots2(partial_, rows, m + 1, G_, Bc_, Bc_, st_, beg256_, nseg);
+            px::dcgs2_coef(m, m, true, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
+                           ldf, ldf, st_);
+        }
     }
     px::lsq_solve(m, R_, gv_, steps_, y_, ldf, ldf, st_);
     px::x_update_seg(V_, vstride, y_, steps_, chunk_seg_, xs_, Bc_, nseg, rows, st_);

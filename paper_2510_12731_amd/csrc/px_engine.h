@@ -70,6 +70,7 @@ class Engine {
     double2* partial_ = nullptr;
     double* npart_ = nullptr;
     double2 *h1_ = nullptr, *h2_ = nullptr, *R_ = nullptr, *sn_ = nullptr, *gv_ = nullptr, *y_ = nullptr;
+    double2 *H_ = nullptr, *G_ = nullptr, *coefQ_ = nullptr, *coefV_ = nullptr, *aux_ = nullptr;
     double *cs_ = nullptr, *nrm_ = nullptr, *target_ = nullptr;
     int32_t *done_ = nullptr, *steps_ = nullptr;
     double2 *zq_ = nullptr, *zmu_ = nullptr;

@@ -142,13 +142,19 @@ inline int dot_chunks(int64_t nup, int nvec) { return (int)((nup + dot_rows(nvec
 size_t dot_partial_slabs(int64_t nup, int nvec_max);
 void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
            int64_t nup, hipStream_t st);
-void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st);
+// With segments (seg_beg: first 256-row chunk of each of nseg segments of lda
+// columns), G is indexed by the flat column seg * lda + c.
+void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st,
+                  const int32_t* seg_beg = nullptr, int nseg = 1);
 // aux: [2][lda] scratch (rho, c_k) between the column-serial and the row-parallel part
 void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
                 double* cs, double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps,
                 double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st);
+// chunk_seg (per 256-row chunk: its segment) switches to flat coefficients of
+// leading dimension ldc.
 void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
-                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st);
+                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st,
+                  const int32_t* chunk_seg = nullptr, int ldc = 0);
 
 // ---- stacked segments (px_engine.cpp) ---------------------------------------
 // One segment of a stacked block: a structure's padded rows (np or 4 np) with

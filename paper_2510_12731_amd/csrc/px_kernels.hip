@@ -812,21 +812,29 @@ __global__ __launch_bounds__(64) void k_dots2(const double2* __restrict__ V, int
         }
 }
 
-// G[j][t][c] = sum over chunks
-__global__ void k_reduce_dots2(const double2* __restrict__ partial, int nchunk, int nvec, double2* __restrict__ G,
-                               int na, int lda)
+// G[j][t][f] = sum of the partials over the row chunks of f's segment.
+// Without segments (seg_beg null) f = c < na and all nch chunks count; with
+// segments f = seg * ld + c over nseg segments of ld columns, seg_beg holding
+// each segment's first 256-row chunk.
+__global__ void k_reduce_dots2(const double2* __restrict__ partial, int nch, int rows_per, int nvec,
+                               double2* __restrict__ G, int na, int ld, const int32_t* __restrict__ seg_beg, int nseg)
 {
+    const int ldf = nseg * ld;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nvec * 2 * lda) return;
-    const int jt = t / lda, c = t - jt * lda;
-    if (c >= na) return;
+    if (t >= nvec * 2 * ldf) return;
+    const int jt = t / ldf, f = t - jt * ldf;
+    const int sg = f / ld, c = f - sg * ld;
+    if (!seg_beg && c >= na) return;
+    const int per = 256 / rows_per;
+    const int k0 = seg_beg ? seg_beg[sg] * per : 0;
+    const int k1 = seg_beg ? seg_beg[sg + 1] * per : nch;
     double ar = 0.0, ai = 0.0;
-    for (int k = 0; k < nchunk; ++k) {
-        const double2 p = partial[((size_t)k * nvec * 2 + jt) * lda + c];
+    for (int k = k0; k < k1; ++k) {
+        const double2 p = partial[((size_t)k * nvec * 2 + jt) * ld + c];
         ar += p.x;
         ai += p.y;
     }
-    G[(size_t)jt * lda + c] = make_double2(ar, ai);
+    G[(size_t)jt * ldf + f] = make_double2(ar, ai);
 }
 
 // Step k, per column (one thread each): rho of the corrected v_k, the lagged
@@ -964,19 +972,23 @@ __global__ __launch_bounds__(256) void k_dcgs2_coef(int k, int m, const double2*
 }
 
 // V_k <- V_k/rho - sum_j V_j (s_j/rho);  w <- w/rho - (c_k/rho^2) V_k(old) - sum_j V_j d_j
+// With segments (chunk_seg non-null) the coefficients of row r's column c sit
+// at flat index chunk_seg[r / 256] * lda + c of leading dimension ldc.
 __global__ __launch_bounds__(256) void k_dcgs2_update(double2* __restrict__ V, int64_t vstride, int k,
                                                       const double2* __restrict__ coefQ,
                                                       const double2* __restrict__ coefV, double2* __restrict__ w,
-                                                      double* __restrict__ norm_partial, int na, int lda, int64_t nup)
+                                                      double* __restrict__ norm_partial, int na, int lda, int64_t nup,
+                                                      const int32_t* __restrict__ chunk_seg, int ldc)
 {
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = blockIdx.y * 64 + lane;
     const int64_t rg = (int64_t)blockIdx.x * UPD_ROWS + wave * ARN_RG;
-    const size_t ld2 = 2 * (size_t)lda;
+    const size_t ld2 = 2 * (size_t)ldc;
     double nrm = 0.0;
     if (c < na && rg < nup) {
-        const double2 p = coefV[c], qv = coefV[lda + c];
+        const int f = chunk_seg ? chunk_seg[rg >> 8] * lda + c : c;
+        const double2 p = coefV[f], qv = coefV[ldc + f];
         double2* u = V + (size_t)k * vstride + (size_t)rg * lda + c;
         double2 av[ARN_RG], aw[ARN_RG];
 #pragma unroll
@@ -990,8 +1002,8 @@ __global__ __launch_bounds__(256) void k_dcgs2_update(double2* __restrict__ V, i
         const double2* vb = V + (size_t)rg * lda + c;
 #pragma unroll 2
         for (int j = 0; j < k; ++j) {
-            const double2 a = coefQ[(size_t)j * ld2 + c];
-            const double2 d = coefQ[(size_t)j * ld2 + lda + c];
+            const double2 a = coefQ[(size_t)j * ld2 + f];
+            const double2 d = coefQ[(size_t)j * ld2 + ldc + f];
             const double2* vj = vb + (size_t)j * vstride;
 #pragma unroll
             for (int q = 0; q < ARN_RG; ++q) {
@@ -1477,11 +1489,12 @@ void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double
                        na, lda, nup, rows, njg, nch);
 }
 
-void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st)
+void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st,
+                  const int32_t* seg_beg, int nseg)
 {
-    const int t = nvec * 2 * lda;
+    const int t = nvec * 2 * lda * nseg;
     hipLaunchKernelGGL(k_reduce_dots2, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, partial,
-                       dot_chunks(nup, nvec), nvec, G, na, lda);
+                       dot_chunks(nup, nvec), dot_rows(nvec), nvec, G, na, lda, seg_beg, nseg);
 }
 
 void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
@@ -1496,10 +1509,11 @@ void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* n
 }
 
 void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
-                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st)
+                  double* norm_partial, int na, int lda, int64_t nup, hipStream_t st, const int32_t* chunk_seg,
+                  int ldc)
 {
     hipLaunchKernelGGL(k_dcgs2_update, dim3(update_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, V,
-                       vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup);
+                       vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup, chunk_seg, chunk_seg ? ldc : lda);
 }
 
 }  // namespace px
