@@ -60,8 +60,11 @@ __device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, fl
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ============================ omegaFQ, FP32 MFMA ============================
-// Workgroup: 4 waves, 256 rows x 128 real columns.  Wave w: rows
-// [row0, row0+64) as two 32-row MFMA blocks x four 32-column blocks.
+// Workgroup: 8 waves, 256 rows x 128 real columns; the X tile of each source
+// chunk is staged once in LDS for all eight.  Wave w: rows [row0, row0 + 32)
+// as one 32-row MFMA block x four 32-column blocks, i.e. 64 accumulator
+// registers, so four waves share each SIMD and hide one another's T
+// generation, LDS reads and barriers behind their MFMAs.
 // MFMA 32x32x2 operand layout (wave64): A lane l -> (row l%32, k l/32);
 // B lane l -> (k l/32, col l%32); D register v of lane l -> (row 8(v/4) +
 // 4(l/32) + v%4, col l%32).  MFMA column n of block cb is physical column
@@ -69,75 +72,67 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // store writes its four outputs.
 constexpr int Q32_COLS = 128;
 constexpr int Q32_JC = 32;
+constexpr int Q32_THREADS = 512;
 
-// The source atoms are split over gridDim.z (split-K); split z writes its
-// partial sums to Y + z * zstride and k_sum_splits_f32 adds them in a fixed
-// order.  The split count depends only on the atom count, so a column's
-// arithmetic does not depend on which other columns share the launch.
-__device__ __forceinline__ void mfma8(f32x16 (&acc)[2][4], float a0, float a1, float4 b)
+// Work decomposition (stream-K): the (output tile, source chunk) iterations of
+// all tiles are laid end to end and cut into one equal contiguous range per
+// resident workgroup, so every CU gets the same MFMA work whatever the tile
+// count.  A range covers the tail of one tile, any number of whole tiles and
+// the head of another; whole tiles are written to Y directly, the partial
+// first and last pieces to two scratch slots per workgroup, which
+// k_sk_fixup adds in workgroup order (a fixed order for a given launch shape).
+__device__ __forceinline__ void mfma4(f32x16 (&acc)[4], float a, float4 b)
 {
-    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.x, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.y, acc[0][1], 0, 0, 0);
-    acc[0][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.z, acc[0][2], 0, 0, 0);
-    acc[0][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b.w, acc[0][3], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.x, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.y, acc[1][1], 0, 0, 0);
-    acc[1][2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.z, acc[1][2], 0, 0, 0);
-    acc[1][3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b.w, acc[1][3], 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b.x, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b.y, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b.z, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b.w, acc[3], 0, 0, 0);
 }
 
-__device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, const float4* __restrict__ xyz,
+// Output tile (row block bx, column block by) over source chunks [cbeg, cend);
+// the 256 x 128 result goes to out (its element (0, 0)), rows ldo apart.
+__device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int cbeg, int cend,
+                                                        const float4* __restrict__ xyz,
                                                         const float4* __restrict__ glo,
                                                         const float4* __restrict__ ghi,
-                                                        const float* __restrict__ X, float* __restrict__ Y,
-                                                        int np, int ldx, int chunks_per_split, size_t zstride,
-                                                        float inv_rqq, float t_self, float r_far2)
+                                                        const float* __restrict__ X, float* __restrict__ out, int ldo,
+                                                        int ldx, float inv_rqq, float t_self, float r_far2)
 {
     __shared__ __attribute__((aligned(16))) float sx[2][Q32_JC][Q32_COLS];
     __shared__ float4 sxyz[2][Q32_JC];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int row0 = bx * 256 + wave * 64;
+    const int wave = uniform(tid >> 6);
+    const int row0 = bx * 256 + wave * 32;
     const int col0 = by * Q32_COLS;
-    const int nchunk = np / Q32_JC;
-    const int cbeg = bz * chunks_per_split;
-    const int cend = min(nchunk, cbeg + chunks_per_split);
-    Y += bz * zstride;
 
-    float xi[2], yi[2], zi[2];
-    int ii[2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-        ii[rb] = row0 + rb * 32 + (lane & 31);
-        float4 p = xyz[ii[rb]];
-        xi[rb] = p.x; yi[rb] = p.y; zi[rb] = p.z;
-    }
-    const float4 rlo0 = glo[row0 >> 5], rhi0 = ghi[row0 >> 5];
-    const float4 rlo1 = glo[(row0 >> 5) + 1], rhi1 = ghi[(row0 >> 5) + 1];
+    const int ii = row0 + (lane & 31);
+    const float4 pi = xyz[ii];
+    const float xi = pi.x, yi = pi.y, zi = pi.z;
+    const float4 rlo = glo[row0 >> 5], rhi = ghi[row0 >> 5];
 
-    f32x16 acc[2][4];
+    f32x16 acc[4];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[rb][cb][v] = 0.0f;
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
 
-    // cooperative tile load: thread -> (row tid/8, 16 columns at 16*(tid%8))
-    const int lr = tid >> 3;
-    const int lc = (tid & 7) * 16;
+    // cooperative tile load: thread -> (row tid/16, 8 columns at 8*(tid%16))
+    const int lr = tid >> 4;
+    const int lc = (tid & 15) * 8;
     if (cbeg < cend) {
         const int j0 = cbeg * Q32_JC;
         const float4* src = reinterpret_cast<const float4*>(X + (size_t)(j0 + lr) * ldx + col0 + lc);
         float4* dst = reinterpret_cast<float4*>(&sx[0][lr][lc]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+        dst[0] = src[0];
+        dst[1] = src[1];
         if (tid < Q32_JC) sxyz[0][tid] = xyz[j0 + tid];
     }
     __syncthreads();
 
+    const int half = lane >> 5;
+    const int col4 = 4 * (lane & 31);
     for (int ch = cbeg; ch < cend; ++ch) {
         const int buf = (ch - cbeg) & 1;
         const int j0 = ch * Q32_JC;
@@ -148,17 +143,8 @@ __device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, cons
         const float4* nsrc = reinterpret_cast<const float4*>(X + (size_t)(jn + lr) * ldx + col0 + lc);
         const float4 pre0 = nsrc[0];
         const float4 pre1 = nsrc[1];
-        const float4 pre2 = nsrc[2];
-        const float4 pre3 = nsrc[3];
         const float4 prexyz = xyz[jn + (tid & (Q32_JC - 1))];
-        const float4 clo = glo[ch];
-        const float4 chi = ghi[ch];
-        const int far0 = uniform(box_gap2(rlo0, rhi0, clo, chi) >= r_far2);
-        const int far1 = uniform(box_gap2(rlo1, rhi1, clo, chi) >= r_far2);
-        const int half = lane >> 5;
-        const int col4 = 4 * (lane & 31);
-
-        const int allfar = far0 & far1;
+        const int far = uniform(box_gap2(rlo, rhi, glo[ch], ghi[ch]) >= r_far2);
         // operands of the next k-step are read from LDS before this step's MFMAs
         float4 pj = sxyz[buf][half];
         float4 bq = *reinterpret_cast<const float4*>(&sx[buf][half][col4]);
@@ -169,21 +155,18 @@ __device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, cons
                 pjn = sxyz[buf][2 * kk + 2 + half];
                 bqn = *reinterpret_cast<const float4*>(&sx[buf][2 * kk + 2 + half][col4]);
             }
-            const float dx0 = xi[0] - pj.x, dy0 = yi[0] - pj.y, dz0 = zi[0] - pj.z;
-            const float dx1 = xi[1] - pj.x, dy1 = yi[1] - pj.y, dz1 = zi[1] - pj.z;
-            const float r20 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
-            const float r21 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
-            float a0 = __builtin_amdgcn_rsqf(r20);
-            float a1 = __builtin_amdgcn_rsqf(r21);
-            if (!allfar) {
-                // Gaussian near field (wave-uniform branch; only the A values change)
+            const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            float a = __builtin_amdgcn_rsqf(r2);
+            // Gaussian near field, only for the k-steps where some pair of the
+            // wave is closer than the far threshold (wave-uniform branches;
+            // only the A value changes)
+            if (!far && __any(r2 < r_far2)) {
                 const int j = j0 + 2 * kk + half;
-                const float t0 = erf_as(r20 * a0 * inv_rqq) * a0;
-                const float t1 = erf_as(r21 * a1 * inv_rqq) * a1;
-                a0 = far0 ? a0 : ((ii[0] == j) ? t_self : t0);
-                a1 = far1 ? a1 : ((ii[1] == j) ? t_self : t1);
+                const float t = erf_as(r2 * a * inv_rqq) * a;
+                a = (ii == j) ? t_self : t;
             }
-            mfma8(acc, a0, a1, bq);
+            mfma4(acc, a, bq);
             pj = pjn;
             bq = bqn;
             if (kk == Q32_JC / 4 && more) {
@@ -191,8 +174,6 @@ __device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, cons
                 float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
                 dst[0] = pre0;
                 dst[1] = pre1;
-                dst[2] = pre2;
-                dst[3] = pre3;
                 if (tid < Q32_JC) sxyz[buf ^ 1][tid] = prexyz;
             }
         }
@@ -200,37 +181,84 @@ __device__ __forceinline__ void tapply_wfq_f32_body(int bx, int by, int bz, cons
     }
 
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = row0 + rb * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            float4 o = make_float4(acc[rb][0][v], acc[rb][1][v], acc[rb][2][v], acc[rb][3][v]);
-            *reinterpret_cast<float4*>(Y + (size_t)i * ldx + col0 + 4 * (lane & 31)) = o;
-        }
-}
-
-__global__ __launch_bounds__(256) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
-                                                        const float4* __restrict__ glo,
-                                                        const float4* __restrict__ ghi,
-                                                        const float* __restrict__ X, float* __restrict__ Y,
-                                                        int np, int ldx, int chunks_per_split, size_t zstride,
-                                                        float inv_rqq, float t_self, float r_far2)
-{
-    tapply_wfq_f32_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, chunks_per_split, zstride, inv_rqq, t_self, r_far2);
-}
-
-// Y[t] = sum_{z < nsplit} P[z][t], in order.
-__global__ void k_sum_splits_f32(const float* __restrict__ P, float* __restrict__ Y, size_t len, size_t zstride,
-                                 int nsplit)
-{
-    size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (t >= len) return;
-    float4 s = *reinterpret_cast<const float4*>(P + t);
-    for (int z = 1; z < nsplit; ++z) {
-        const float4 v = *reinterpret_cast<const float4*>(P + z * zstride + t);
-        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    for (int v = 0; v < 16; ++v) {
+        const int i = wave * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const float4 o = make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
+        *reinterpret_cast<float4*>(out + (size_t)i * ldo + col4) = o;
     }
-    *reinterpret_cast<float4*>(Y + t) = s;
+}
+
+// ---- stream-K bookkeeping ----------------------------------------------------
+// Tiles t = 0..T-1 with C_t chunks each start at iteration pre[t]; without a
+// tile list (single structure) tile t is (row block t % RB, column block
+// t / RB) with C chunks.  Workgroup b owns iterations [begin(b), begin(b+1)).
+struct SkGrid {
+    const int4* tiles;       // {segment, row block, column block, chunks} or null
+    const int64_t* pre;      // [T + 1] or null
+    int T, RB, C, G;
+    int64_t total;
+};
+
+constexpr int SK_TILE_FLOATS = 256 * Q32_COLS;
+
+__device__ __forceinline__ int64_t sk_begin(const SkGrid& s, int b) { return s.total * b / s.G; }
+__device__ __forceinline__ int64_t sk_pre(const SkGrid& s, int t) { return s.pre ? s.pre[t] : (int64_t)t * s.C; }
+
+__device__ int sk_tile_of(const SkGrid& s, int64_t i)
+{
+    if (!s.pre) return (int)(i / s.C);
+    int lo = 0, hi = s.T - 1;   // largest t with pre[t] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.pre[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ int sk_block_of(const SkGrid& s, int64_t i)
+{
+    int b = (int)(i * s.G / s.total);   // largest b with begin(b) <= i
+    while (b + 1 < s.G && sk_begin(s, b + 1) <= i) ++b;
+    while (b > 0 && sk_begin(s, b) > i) --b;
+    return b;
+}
+
+// Workgroup b's pieces: calls f(tile, c0, c1, slot) in order; slot is -1 for
+// a whole tile, else the scratch slot (2b for the first piece, 2b+1 for the
+// last).
+template <class F>
+__device__ __forceinline__ void sk_pieces(const SkGrid& s, int b, F&& f)
+{
+    int64_t it = sk_begin(s, b);
+    const int64_t end = sk_begin(s, b + 1);
+    bool first = true;
+    while (it < end) {
+        const int t = uniform(sk_tile_of(s, it));
+        const int64_t p0 = sk_pre(s, t);
+        const int ct = s.tiles ? s.tiles[t].w : s.C;
+        const int c0 = (int)(it - p0);
+        const int c1 = (int)min((int64_t)ct, (int64_t)c0 + (end - it));
+        const int slot = (c0 == 0 && c1 == ct) ? -1 : 2 * b + (first ? 0 : 1);
+        f(t, c0, c1, slot);
+        it += c1 - c0;
+        first = false;
+    }
+}
+
+__global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32(const float4* __restrict__ xyz,
+                                                                const float4* __restrict__ glo,
+                                                                const float4* __restrict__ ghi,
+                                                                const float* __restrict__ X, float* __restrict__ Y,
+                                                                float* __restrict__ partial, int ldx, SkGrid sk,
+                                                                float inv_rqq, float t_self, float r_far2)
+{
+    sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
+        const int rb = t % sk.RB, cb = t / sk.RB;
+        float* out = slot < 0 ? Y + (size_t)rb * 256 * ldx + cb * Q32_COLS : partial + (size_t)slot * SK_TILE_FLOATS;
+        tapply_wfq_f32_body(rb, cb, c0, c1, xyz, glo, ghi, X, out, slot < 0 ? ldx : Q32_COLS, ldx, inv_rqq, t_self,
+                            r_far2);
+    });
 }
 
 // ========================== omegaFQFmu, FP32 MFMA ===========================
@@ -349,9 +377,12 @@ __device__ __forceinline__ void tapply_wfqfmu_f32_body(int bx, int by, int bz, c
         for (int kk = 0; kk < D32_JC / 2; ++kk) {
             const int jr = 2 * kk + (lane >> 5);
             const float4 pj = sxyz[buf][jr];
+            const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            // point forms unless some pair of the wave is inside the far threshold
+            const bool fstep = far || !__any(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < kc.r_far2);
             float b[4][4];
-            pair_block_f32(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, far != 0, kc, b);
-            if (!far && ii == j0 + jr) {
+            pair_block_f32(dx, dy, dz, fstep, kc, b);
+            if (!fstep && ii == j0 + jr) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -470,16 +501,18 @@ __device__ __forceinline__ void tapply_wfq_f64_body(int bx, int by, int bz, cons
             const double4 pj = sxyz[buf][jr];
             const double2* bp = reinterpret_cast<const double2*>(&sx[buf][jr][4 * (lane & 15)]);
             const double2 b01 = bp[0], b23 = bp[1];
-            double a[2];
+            double a[2], r2[2];
 #pragma unroll
             for (int sb = 0; sb < 2; ++sb) {
                 double dx = xi[sb] - pj.x, dy = yi[sb] - pj.y, dz = zi[sb] - pj.z;
-                double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                double rinv = rsqrt(r2);
-                if (far) {
-                    a[sb] = rinv;
-                } else {
-                    double t = erf(r2 * rinv * inv_rqq) * rinv;
+                r2[sb] = fma(dx, dx, fma(dy, dy, dz * dz));
+                a[sb] = rsqrt(r2[sb]);
+            }
+            // Gaussian form only for the k-steps with a pair inside the far threshold
+            if (!far && __any(r2[0] < (double)r_far2 || r2[1] < (double)r_far2)) {
+#pragma unroll
+                for (int sb = 0; sb < 2; ++sb) {
+                    const double t = erf(r2[sb] * a[sb] * inv_rqq) * a[sb];
                     a[sb] = (ii[sb] == j0 + jr) ? t_self : t;
                 }
             }
@@ -629,9 +662,11 @@ __device__ __forceinline__ void tapply_wfqfmu_f64_body(int bx, int by, int bz, c
         for (int kk = 0; kk < D64_JC / 4; ++kk) {
             const int jr = 4 * kk + (lane >> 4);
             const double4 pj = sxyz[buf][jr];
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            const bool fstep = far || !__any(fma(dx, dx, fma(dy, dy, dz * dz)) < (double)kc.r_far2);
             double b[4][4];
-            pair_block_f64(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, far != 0, kc, b);
-            if (!far && ii == j0 + jr) {
+            pair_block_f64(dx, dy, dz, fstep, kc, b);
+            if (!fstep && ii == j0 + jr) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -727,11 +762,12 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
             for (int jj = gq * GROUP; jj < (gq + 1) * GROUP; ++jj) {
                 const double4 pj = sxyz[jj];
                 const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const bool fstep = far || !__any(r2 < (double)r_far2);
                 if (MODEL == 0) {
-                    double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     double rinv = rsqrt(r2);
                     double t;
-                    if (far) {
+                    if (fstep) {
                         t = rinv;
                     } else {
                         t = erf(r2 * rinv * inv_rqq) * rinv;
@@ -741,8 +777,8 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
                     for (int c = 0; c < NC; ++c) acc[0][c] = fma(t, sxv[0][jj][c], acc[0][c]);
                 } else {
                     double b[4][4];
-                    pair_block_f64(dx, dy, dz, far != 0, kc, b);
-                    if (!far && i == j0 + jj) {
+                    pair_block_f64(dx, dy, dz, fstep, kc, b);
+                    if (!fstep && i == j0 + jj) {
 #pragma unroll
                         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -785,7 +821,7 @@ struct GroupConst {
     const float4* glo;
     const float4* ghi;
     int64_t row_off;
-    int np, model, chunks_per_split, pad;
+    int np, model;
     float inv_rqq32, t_self32, rfar32;
     double inv_rqq64, t_self64;
     float rfar64;
@@ -793,15 +829,52 @@ struct GroupConst {
     DipoleConstD d64;
 };
 
-__global__ __launch_bounds__(256) void k_tapply_wfq_f32_grouped(const GroupConst* __restrict__ gc,
-                                                                const int4* __restrict__ tiles,
-                                                                const float* __restrict__ X, float* __restrict__ P,
-                                                                int ldx, size_t zstride)
+__global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32_grouped(const GroupConst* __restrict__ gc,
+                                                                        const float* __restrict__ X,
+                                                                        float* __restrict__ Y,
+                                                                        float* __restrict__ partial, int ldx,
+                                                                        SkGrid sk)
 {
-    const int4 t = tiles[blockIdx.x];
-    const GroupConst& c = gc[t.x];
-    tapply_wfq_f32_body(t.y, t.z, t.w, c.xyz32, c.glo, c.ghi, X + (size_t)c.row_off * ldx, P + (size_t)c.row_off * ldx,
-                        c.np, ldx, c.chunks_per_split, zstride, c.inv_rqq32, c.t_self32, c.rfar32);
+    sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
+        const int4 tl = sk.tiles[t];
+        const GroupConst& c = gc[tl.x];
+        float* out = slot < 0 ? Y + ((size_t)c.row_off + (size_t)tl.y * 256) * ldx + tl.z * Q32_COLS
+                              : partial + (size_t)slot * SK_TILE_FLOATS;
+        tapply_wfq_f32_body(tl.y, tl.z, c0, c1, c.xyz32, c.glo, c.ghi, X + (size_t)c.row_off * ldx, out,
+                            slot < 0 ? ldx : Q32_COLS, ldx, c.inv_rqq32, c.t_self32, c.rfar32);
+    });
+}
+
+// Sums the scratch slots of every tile that several workgroups share, in
+// workgroup order, into Y.  Grid: 32 workgroups of 256 threads per tile, one
+// float4 per thread.  gc / tiles null: the single-structure layout.
+__global__ __launch_bounds__(256) void k_sk_fixup(const float* __restrict__ partial, float* __restrict__ Y, int ldx,
+                                                  SkGrid sk, const GroupConst* __restrict__ gc)
+{
+    const int t = blockIdx.x >> 5;
+    const int64_t p0 = sk_pre(sk, t);
+    const int ct = sk.tiles ? sk.tiles[t].w : sk.C;
+    const int blo = sk_block_of(sk, p0), bhi = sk_block_of(sk, p0 + ct - 1);
+    if (blo == bhi) return;
+    const int q = (blockIdx.x & 31) * 256 + threadIdx.x;   // float4 index in the tile
+    const int row = q >> 5, col = (q & 31) * 4;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int b = blo; b <= bhi; ++b) {
+        const int slot = (b == blo && sk_begin(sk, b) < p0) ? 2 * b + 1 : 2 * b;
+        const float4 v = *reinterpret_cast<const float4*>(partial + (size_t)slot * SK_TILE_FLOATS + row * Q32_COLS + col);
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+    size_t r0;
+    int cb;
+    if (sk.tiles) {
+        const int4 tl = sk.tiles[t];
+        r0 = (size_t)gc[tl.x].row_off + (size_t)tl.y * 256;
+        cb = tl.z;
+    } else {
+        r0 = (size_t)(t % sk.RB) * 256;
+        cb = t / sk.RB;
+    }
+    *reinterpret_cast<float4*>(Y + (r0 + row) * ldx + cb * Q32_COLS + col) = acc;
 }
 
 __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32_grouped(const GroupConst* __restrict__ gc,
@@ -837,23 +910,6 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64_grouped(const GroupCo
                            Y + (size_t)c.row_off * ldx, c.np, ldx, c.d64);
 }
 
-// Y[r][:] = sum_{z < nsplit} P[z][r][:] for the rows of omegaFQ segments
-// (row_model[r / 256] == 0); other rows are left alone.
-__global__ void k_sum_splits_grouped(const float* __restrict__ P, float* __restrict__ Y,
-                                     const int32_t* __restrict__ chunk_model, int64_t rows, int ldx, size_t zstride,
-                                     int nsplit)
-{
-    const size_t t = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (t >= (size_t)rows * ldx) return;
-    const int64_t r = (int64_t)(t / ldx);
-    if (chunk_model[r >> 8] != 0) return;
-    float4 s = *reinterpret_cast<const float4*>(P + t);
-    for (int z = 1; z < nsplit; ++z) {
-        const float4 v = *reinterpret_cast<const float4*>(P + z * zstride + t);
-        s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
-    }
-    *reinterpret_cast<float4*>(Y + t) = s;
-}
 
 // Far-field thresholds x_far = r / R beyond which the Gaussian factors equal
 // their point limits to working precision (erfc(4) < 2^-25; erfc(6) < 2^-54;
@@ -903,24 +959,32 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit);
 }
 
-int f32_splits(const Geometry& g)
+// Resident 512-thread FP32 workgroups: two per CU (LDS and registers allow
+// two), counted once per device.
+int sk_slots()
 {
-    // about 512 row-block x split workgroups per column block, at least 8 source chunks each
-    const int rb = (int)(g.np / 256);
-    const int nchunk = (int)(g.np / Q32_JC);
-    int sp = (512 + rb - 1) / rb;
-    sp = std::max(1, std::min(sp, nchunk / 8));
-    const int cps = (nchunk + sp - 1) / sp;
-    return (nchunk + cps - 1) / cps;
+    static int slots[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (slots[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        slots[dev] = 2 * cu;
+    }
+    return slots[dev];
 }
+
+// Workgroups of a stream-K launch over `total` iterations: every resident
+// slot, but at least 8 source chunks (256 atoms) each.
+int sk_workgroups(int64_t total) { return (int)std::max<int64_t>(1, std::min<int64_t>(sk_slots(), total / 8)); }
 
 }  // namespace
 
 size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols)
 {
+    (void)ncols;
     if (g.model != 0) return 0;
-    const int sp = f32_splits(g);
-    return sp > 1 ? (size_t)sp * g.np * ncols * sizeof(float) : 0;
+    return (size_t)2 * sk_slots() * SK_TILE_FLOATS * sizeof(float);
 }
 
 void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch)
@@ -928,19 +992,16 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
     if (g.model == 0) {
         double rqq = std::sqrt(2.0) * g.r_q;
         float rf = (float)(XFAR_Q32 * rqq);
-        const int nchunk = (int)(g.np / Q32_JC);
-        const int sp = f32_splits(g);
-        const int cps = (nchunk + sp - 1) / sp;
-        const size_t zstride = (size_t)g.np * ldx;
-        float* dst = sp > 1 ? scratch : Y;
-        hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)(g.np / 256), (unsigned)(ncols / Q32_COLS), (unsigned)sp),
-                           dim3(256), 0, st, g.xyz32, g.glo, g.ghi, X, dst, (int)g.np, ldx, cps, zstride,
-                           (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
-        if (sp > 1) {
-            const size_t len = (size_t)g.np * ldx;
-            hipLaunchKernelGGL(k_sum_splits_f32, dim3((unsigned)((len / 4 + 255) / 256)), dim3(256), 0, st, scratch, Y,
-                               len, zstride, sp);
-        }
+        SkGrid sk{};
+        sk.RB = (int)(g.np / 256);
+        sk.C = (int)(g.np / Q32_JC);
+        sk.T = sk.RB * (ncols / Q32_COLS);
+        sk.total = (int64_t)sk.T * sk.C;
+        sk.G = sk_workgroups(sk.total);
+        hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, g.xyz32, g.glo, g.ghi, X,
+                           Y, scratch, ldx, sk, (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
+        hipLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * sk.T)), dim3(256), 0, st, scratch, Y, ldx, sk,
+                           (const GroupConst*)nullptr);
     } else {
         DipoleConstD d = dipole_const_d(g);
         DipoleConstF k;
@@ -1006,19 +1067,19 @@ struct GroupedTApply::Impl {
     int4* d_t32d = nullptr;   // FP32 dipole tiles
     int4* d_t64q = nullptr;
     int4* d_t64d = nullptr;
-    int32_t* d_chunk_model = nullptr;
+    int64_t* d_pre32q = nullptr;   // stream-K iteration offsets of the FP32 omegaFQ tiles
     int n32q = 0, n32d = 0, n64q = 0, n64d = 0;
-    int nsplit = 1;
+    SkGrid sk{};
     int64_t rows = 0;
     int ldx = 0;
     void release()
     {
-        void* ps[] = {d_gc, d_t32q, d_t32d, d_t64q, d_t64d, d_chunk_model};
+        void* ps[] = {d_gc, d_t32q, d_t32d, d_t64q, d_t64d, d_pre32q};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         d_gc = nullptr;
         d_t32q = d_t32d = d_t64q = d_t64d = nullptr;
-        d_chunk_model = nullptr;
+        d_pre32q = nullptr;
     }
 };
 
@@ -1044,13 +1105,7 @@ hipError_t GroupedTApply::setup(const std::vector<GroupSeg>& segs, int ldx, int6
     impl->ldx = ldx;
     std::vector<GroupConst> gc(segs.size());
     std::vector<int4> t32q, t32d, t64q, t64d;
-    std::vector<int32_t> chunk_model((size_t)(rows / 256) + 1, 1);
-    // split-K for the FP32 omegaFQ tiles: enough workgroups for the whole chip
-    int base = 0;
-    for (const GroupSeg& sg : segs)
-        if (sg.g->model == 0) base += (int)(sg.g->np / 256) * (ldx / Q32_COLS);
-    int nsplit = base > 0 ? std::max(1, std::min(8, (2048 + base - 1) / base)) : 1;
-    impl->nsplit = nsplit;
+    std::vector<int64_t> pre32q(1, 0);
     for (size_t k = 0; k < segs.size(); ++k) {
         const Geometry& g = *segs[k].g;
         GroupConst c{};
@@ -1069,8 +1124,6 @@ hipError_t GroupedTApply::setup(const std::vector<GroupSeg>& segs, int ldx, int6
         c.t_self64 = TWO_OVER_SQRTPI / rqq;
         c.rfar64 = (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
         const int nchunk = (int)(g.np / Q32_JC);
-        const int sp = std::max(1, std::min(nsplit, nchunk));
-        c.chunks_per_split = (nchunk + sp - 1) / sp;
         if (g.model == 1) {
             c.d64 = dipole_const_d(g);
             c.d32.inv_rqq = (float)c.d64.inv_rqq;
@@ -1084,10 +1137,11 @@ hipError_t GroupedTApply::setup(const std::vector<GroupSeg>& segs, int ldx, int6
         gc[k] = c;
         const int kk = (int)k;
         if (g.model == 0) {
-            for (int64_t r = segs[k].row_off / 256; r < (segs[k].row_off + g.nup) / 256; ++r) chunk_model[r] = 0;
-            for (int z = 0; z < nsplit; ++z)
-                for (int cb = 0; cb < ldx / Q32_COLS; ++cb)
-                    for (int rb = 0; rb < (int)(g.np / 256); ++rb) t32q.push_back(make_int4(kk, rb, cb, z));
+            for (int cb = 0; cb < ldx / Q32_COLS; ++cb)
+                for (int rb = 0; rb < (int)(g.np / 256); ++rb) {
+                    t32q.push_back(make_int4(kk, rb, cb, nchunk));
+                    pre32q.push_back(pre32q.back() + nchunk);
+                }
             for (int cb = 0; cb < ldx / Q64_COLS; ++cb)
                 for (int rb = 0; rb < (int)(g.np / 128); ++rb) t64q.push_back(make_int4(kk, rb, cb, 0));
         } else {
@@ -1107,31 +1161,30 @@ hipError_t GroupedTApply::setup(const std::vector<GroupSeg>& segs, int ldx, int6
     if ((e = upload((void**)&impl->d_t32d, t32d.data(), sizeof(int4) * t32d.size(), st)) != hipSuccess) return e;
     if ((e = upload((void**)&impl->d_t64q, t64q.data(), sizeof(int4) * t64q.size(), st)) != hipSuccess) return e;
     if ((e = upload((void**)&impl->d_t64d, t64d.data(), sizeof(int4) * t64d.size(), st)) != hipSuccess) return e;
-    if ((e = upload((void**)&impl->d_chunk_model, chunk_model.data(), sizeof(int32_t) * chunk_model.size(), st)) !=
-        hipSuccess)
+    if ((e = upload((void**)&impl->d_pre32q, pre32q.data(), sizeof(int64_t) * pre32q.size(), st)) != hipSuccess)
         return e;
+    impl->sk.tiles = impl->d_t32q;
+    impl->sk.pre = impl->d_pre32q;
+    impl->sk.T = impl->n32q;
+    impl->sk.total = pre32q.back();
+    impl->sk.G = impl->sk.total > 0 ? sk_workgroups(impl->sk.total) : 0;
     return hipStreamSynchronize(st);
 }
 
 size_t GroupedTApply::partial_bytes() const
 {
-    return impl->nsplit > 1 ? (size_t)impl->nsplit * impl->rows * impl->ldx * sizeof(float) : 0;
+    return impl->n32q > 0 ? (size_t)2 * sk_slots() * SK_TILE_FLOATS * sizeof(float) : 0;
 }
 
 int64_t GroupedTApply::f32_tiles() const { return impl->n32q + impl->n32d; }
 
 void GroupedTApply::run_f32(const float* X, float* Y, float* partial, hipStream_t st) const
 {
-    const size_t zstride = (size_t)impl->rows * impl->ldx;
     if (impl->n32q > 0) {
-        float* dst = impl->nsplit > 1 ? partial : Y;
-        hipLaunchKernelGGL(k_tapply_wfq_f32_grouped, dim3(impl->n32q), dim3(256), 0, st, impl->d_gc, impl->d_t32q, X,
-                           dst, impl->ldx, zstride);
-        if (impl->nsplit > 1) {
-            const size_t len = (size_t)impl->rows * impl->ldx;
-            hipLaunchKernelGGL(k_sum_splits_grouped, dim3((unsigned)((len / 4 + 255) / 256)), dim3(256), 0, st,
-                               partial, Y, impl->d_chunk_model, impl->rows, impl->ldx, zstride, impl->nsplit);
-        }
+        hipLaunchKernelGGL(k_tapply_wfq_f32_grouped, dim3((unsigned)impl->sk.G), dim3(Q32_THREADS), 0, st, impl->d_gc,
+                           X, Y, partial, impl->ldx, impl->sk);
+        hipLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * impl->n32q)), dim3(256), 0, st, partial, Y, impl->ldx,
+                           impl->sk, impl->d_gc);
     }
     if (impl->n32d > 0)
         hipLaunchKernelGGL(k_tapply_wfqfmu_f32_grouped, dim3(impl->n32d), dim3(256), 0, st, impl->d_gc, impl->d_t32d,
