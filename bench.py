@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -54,8 +55,9 @@ def one_step(px, case, precision, timings, max_block_cols=0, cols=None):
     alpha, sigma = s.spectrum()
     it, cyc, rr = s.stats()
     tm = s.timings()
+    wk = s.work()
     s.close()
-    return dict(status=st, sigma=sigma, alpha=alpha, iters=it, cycles=cyc, relres=rr, timings=tm)
+    return dict(status=st, sigma=sigma, alpha=alpha, iters=it, cycles=cyc, relres=rr, timings=tm, work=wk)
 
 
 def measured_traffic(kernel_src, summary):
@@ -218,7 +220,7 @@ def torch_free_bytes():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--n-omega", type=int, default=128)
@@ -298,8 +300,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
+    step_s = []
     for k in range(args.steps):
+        ta = time.perf_counter()
         runs.append(one_step(pxm, case, pxm.PX_MIXED, True))
+        step_s.append(time.perf_counter() - ta)
         log(f"[bench] step {k}: status {runs[-1]['status']} {runs[-1]['timings']['ms_total'] / 1e3:.2f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -322,11 +327,24 @@ def main():
                 traffic_note=(None if traffic is None else
                               f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
                               f"algorithmic {2 * 4 * len(case['xyz']) * traffic_cols} B"),
-                kernel="k_tapply_wfq_f32", launches=int(n_launch),
+                kernel="k_tapply_wfq_f32 (+ k_sk_fixup)", launches=int(n_launch),
                 avg_launch_ms=round(ms_t / max(n_launch, 1), 4),
                 avg_algorithmic_gflop_per_launch=round(flops / max(n_launch, 1) / 1e9, 2))
 
+    # path roofline: the ideal time of the solve's algorithmic work at the
+    # peaks (FP32 and FP64 matrix, HBM) over its measured wall time
+    wk = last["work"]
+    ideal_s = wk["flop_f32"] / (FP32_MFMA_PEAK_TFLOPS * 1e12) + wk["flop_f64"] / (FP64_MFMA_PEAK_TFLOPS * 1e12) + \
+        wk["hbm_bytes"] / (HBM_PEAK_GBS * 1e9)
+    solve_s = tm["ms_total"] / 1e3
+    path = dict(ideal_ms=round(ideal_s * 1e3, 1), solve_ms=round(solve_s * 1e3, 1), frac=round(ideal_s / solve_s, 4),
+                flop_f32=wk["flop_f32"], flop_f64=wk["flop_f64"], hbm_bytes=wk["hbm_bytes"],
+                peaks="FP32 matrix 157.3 TFLOP/s, FP64 matrix 78.6 TFLOP/s, HBM 8 TB/s")
+
+    med = float(np.median(step_s))
     extra = dict(
+        median_step_s=round(med, 3), median_step_freq_solves_per_s=round(ncol / med, 3),
+        path_roofline=path,
         iterations_max=int(last["iters"].max()), iterations_mean=round(float(last["iters"].mean()), 1),
         relres_max=float(last["relres"].max()),
         phase_ms=dict(tapply_f32=round(tm["ms_tapply_f32"], 1), tapply_f64_in_cycles=round(tm["ms_tapply_f64_cycles"], 1),

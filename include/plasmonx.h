@@ -238,6 +238,19 @@ pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns);
  * same for the FP64 T-apply (inside cycles and true residuals). */
 pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6);
 
+/* Algorithmic work of the last pxSolveSpectrum (the method's own work, no
+ * padding, no re-reads): work3[0] FLOP of the FP32 T-apply (2 N_u^2 per real
+ * column and Arnoldi step), work3[1] FLOP of the FP64 T-apply (steps of FP64
+ * cycles and true residuals), work3[2] HBM bytes of the bandwidth-bound
+ * phases: per step and column the sparse apply (N_u x 40 B: FP32 T X, FP64
+ * X, FP64 result), the orthogonalisation (one dot and one update pass:
+ * N_u x 16 B x (2k + 6) at step k; two of each for CGS2: N_u x 16 B x
+ * (4k + 10)) and the normalisation (N_u x 40 B); per cycle the residual's
+ * vector traffic (N_u x 80 B) and the solution update (N_u x 16 B x
+ * (steps + 2)).  N_u = unknowns (atoms, or 4 x atoms for PX_WFQFMU).
+ * Dividing each by its peak gives the ideal time of the solve. */
+pxStatus pxGetWork(pxStructure s, double* work3);
+
 void pxDestroyStructure(pxStructure s);
 
 /* Thread-local description of the last error of this thread ("" if none). */

@@ -24,7 +24,7 @@ PX_ORTHO_CGS2, PX_ORTHO_DCGS2 = 0, 1
 STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV", 4: "PX_E_DEVICE", 5: "PX_E_STATE"}
 
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
-            "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings",
+            "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy"]
 
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
     lib.pxApplyOperator.argtypes = [_vp, i32, i32, _dp, _dp, _dp, _dp]
     lib.pxGetSize.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pxGetTimings.argtypes = [_vp, _dp, ctypes.POINTER(i64)]
+    lib.pxGetWork.argtypes = [_vp, _dp]
     lib.pxServerCreate.argtypes = [ctypes.c_double, ctypes.POINTER(pxSolveOptions), _vp, ctypes.POINTER(_vp)]
     lib.pxServerSubmit.argtypes = [_vp, _vp]
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
@@ -197,6 +198,13 @@ def pxApplyOperator(h, precision, omega_ev, x, alpha_ib=None):
     _check(load().pxApplyOperator(h, int(precision), ncol, _ptr(om), _ptr(aib), _ptr(x.view(np.float64)),
                                   _ptr(y.view(np.float64))))
     return y
+
+
+def pxGetWork(h):
+    """Algorithmic work of the last solve: FP32 T-apply FLOP, FP64 T-apply FLOP, HBM bytes."""
+    w = np.zeros(3)
+    _check(load().pxGetWork(h, _ptr(w)))
+    return dict(flop_f32=float(w[0]), flop_f64=float(w[1]), hbm_bytes=float(w[2]))
 
 
 def pxGetTimings(h):
@@ -333,6 +341,9 @@ class Structure:
 
     def timings(self):
         return pxGetTimings(self.h)
+
+    def work(self):
+        return pxGetWork(self.h)
 
     def close(self):
         if self.h is not None:

@@ -192,6 +192,9 @@ void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* r
     s->counts[3] += 1;
     s->counts[4] += 2 * lda;
     s->counts[5] += 2 * na;
+    const double nu = (double)s->g.nu;
+    s->work[1] += 2.0 * nu * nu * 2.0 * na;
+    s->work[2] += 80.0 * nu * na;
     px::spmm_shift(s->g, W.Y64, false, 2 * lda, xs, W.zq, W.zmu, bs, rs, na, lda, SOLVER_MU_SIGN, s->st);
 }
 
@@ -315,18 +318,24 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 double2* vk = W.V + k * vstride;
                 tm.mark(0);
                 const bool wide32 = mixed && lda > 4;
+                const double nu = (double)s->g.nu;
+                int n_open = 0;
+                for (int q = 0; q < na; ++q) n_open += done_h[q] ? 0 : 1;
                 if (wide32) {
                     px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32);
                     s->counts[0] += 1;
                     s->counts[1] += 2 * lda;
                     s->counts[2] += 2 * na;
+                    s->work[0] += 2.0 * nu * nu * 2.0 * n_open;
                 } else {
                     px::tapply_f64(s->g, reinterpret_cast<const double*>(vk), W.Y64, 2 * lda, 2 * lda, s->st,
                                    W.narrow, W.narrow_bytes);
                     s->counts[3] += 1;
                     s->counts[4] += 2 * lda;
                     s->counts[5] += 2 * na;
+                    s->work[1] += 2.0 * nu * nu * 2.0 * n_open;
                 }
+                s->work[2] += nu * n_open * (40.0 + 40.0 + 16.0 * (dcgs2 ? 2.0 * k + 6.0 : 4.0 * k + 10.0));
                 tm.mark(1);
                 px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
                                W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st);
@@ -366,6 +375,9 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 if (all) break;
                 if (dcgs2 && k == m - 1) {
                     // the last basis vector's correction finishes column m-1
+                    int n_open = 0;
+                    for (int q = 0; q < na; ++q) n_open += done_h[q] ? 0 : 1;
+                    s->work[2] += (double)s->g.nu * n_open * 16.0 * (m + 2);
                     px::dots2(W.V, vstride, m + 1, W.V + m * vstride, W.partial, na, lda, nup, s->st);
                     px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st);
                     px::dcgs2_coef(m, m, true, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
@@ -382,6 +394,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             for (int k = 0; k < na; ++k) {
                 s->iters[act[k]] += steps_h[k];
                 s->cycles[act[k]] += 1;
+                s->work[2] += 16.0 * (double)s->g.nu * (steps_h[k] + 2);
             }
         }
     }
@@ -406,6 +419,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     auto t0 = std::chrono::steady_clock::now();
     for (double& v : s->ms) v = 0.0;
     for (int64_t& v : s->counts) v = 0;
+    for (double& v : s->work) v = 0.0;
     const int ncol = s->ncol;
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
     ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
@@ -752,6 +766,14 @@ pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns)
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (n_atoms) *n_atoms = s->g.n;
     if (n_unknowns) *n_unknowns = s->g.nu;
+    return PX_OK;
+}
+
+pxStatus pxGetWork(pxStructure s, double* work3)
+{
+    g_err.clear();
+    if (!s || !work3) return fail(PX_E_INVALID, "null argument");
+    std::copy(s->work, s->work + 3, work3);
     return PX_OK;
 }
 

@@ -112,6 +112,7 @@ struct pxStructure_t {
     // counts: FP32 T-apply launches, padded real columns, algorithmic real
     // columns; the same three for the FP64 T-apply (cycles and residuals)
     int64_t counts[6] = {0, 0, 0, 0, 0, 0};
+    double work[3] = {0, 0, 0};   // algorithmic FP32 FLOP, FP64 FLOP, HBM bytes of the last solve
 
     ~pxStructure_t()
     {
