@@ -60,6 +60,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run python -m paper_2510_12731_amd.build)")
+    # torch bundles its own HIP runtime under the same soname as ROCm's
+    # (libamdhip64.so.7); whichever is loaded first serves the whole process.
+    # Import torch first so that the library and torch's streams share one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     lib.pxDefaultSolveOptions.argtypes = [ctypes.POINTER(pxSolveOptions)]

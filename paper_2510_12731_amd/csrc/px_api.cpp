@@ -150,38 +150,13 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.split32 = dalloc<float>(px::tapply_f32_scratch_bytes(s->g, 2 * lda) / sizeof(float) + 1);
     W.lda_cap = lda;
     W.m_cap = m;
+    s->sync.ensure(m + 1);
     W.nup = nup;
     px::fill_zero(W.V, sizeof(double2) * (size_t)(m + 1) * vec, s->st);
     px::fill_zero(W.X32, sizeof(float) * 2 * vec, s->st);
 }
 
 
-struct Timer {
-    bool on;
-    hipStream_t st;
-    hipEvent_t ev[8];
-    int n = 0;
-    Timer(bool on_, hipStream_t st_) : on(on_), st(st_)
-    {
-        if (on)
-            for (auto& e : ev) HC(hipEventCreate(&e));
-    }
-    ~Timer()
-    {
-        if (on)
-            for (auto& e : ev) (void)hipEventDestroy(e);
-    }
-    void mark(int i)
-    {
-        if (on) HC(hipEventRecord(ev[i], st));
-    }
-    float between(int a, int b)
-    {
-        float t = 0.f;
-        if (on) HC(hipEventElapsedTime(&t, ev[a], ev[b]));
-        return t;
-    }
-};
 
 // r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
 void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda)
@@ -227,6 +202,9 @@ void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
     HC(hipMemcpyAsync(s->ws.zmu, zm.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
 }
 
+// Steps the host enqueues ahead of the last stop flag it looked at.
+constexpr int kLag = 2;
+
 // Solves the columns in `cols` (global indices) as one block.
 void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
 {
@@ -237,7 +215,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
     const bool mixed = o.precision == PX_MIXED;
     const bool dcgs2 = o.ortho == PX_ORTHO_DCGS2;
     const int nchunk = px::arnoldi_chunks(nup);
-    Timer tm(o.timings != 0, s->st);
+    StepTimer tm(o.timings != 0);
     std::vector<int32_t> done_h, steps_h;
     std::vector<double> beta;
 
@@ -313,40 +291,35 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             HC(hipMemcpyAsync(W.nrm, beta.data(), sizeof(double) * na, hipMemcpyHostToDevice, s->st));
             const int64_t vstride = nup * lda;
             px::normalize(W.rs, W.nrm, nullptr, W.V, mixed ? W.X32 : nullptr, na, lda, nup, s->st);
+            const bool wide32 = mixed && lda > 4;
+            // delayed orthogonalisation: the host enqueues steps ahead of the device and a
+            // device flag, raised once the rotations have finished every column, ends them
+            int32_t* stop = dcgs2 ? s->sync.flag() : nullptr;
+            if (stop) s->sync.reset(s->st);
+            tm.ensure(m);
+            int launched = 0;
             done_h.assign(na, 0);
             for (int k = 0; k < m; ++k) {
+                if (stop && k >= kLag && s->sync.stopped(k - kLag)) break;
                 double2* vk = W.V + k * vstride;
-                tm.mark(0);
-                const bool wide32 = mixed && lda > 4;
-                const double nu = (double)s->g.nu;
-                int n_open = 0;
-                for (int q = 0; q < na; ++q) n_open += done_h[q] ? 0 : 1;
-                if (wide32) {
-                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32);
-                    s->counts[0] += 1;
-                    s->counts[1] += 2 * lda;
-                    s->counts[2] += 2 * na;
-                    s->work[0] += 2.0 * nu * nu * 2.0 * n_open;
-                } else {
+                tm.mark(k, 0, s->st);
+                if (wide32)
+                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32, stop);
+                else
                     px::tapply_f64(s->g, reinterpret_cast<const double*>(vk), W.Y64, 2 * lda, 2 * lda, s->st,
-                                   W.narrow, W.narrow_bytes);
-                    s->counts[3] += 1;
-                    s->counts[4] += 2 * lda;
-                    s->counts[5] += 2 * na;
-                    s->work[1] += 2.0 * nu * nu * 2.0 * n_open;
-                }
-                s->work[2] += nu * n_open * (40.0 + 40.0 + 16.0 * (dcgs2 ? 2.0 * k + 6.0 : 4.0 * k + 10.0));
-                tm.mark(1);
+                                   W.narrow, W.narrow_bytes, stop);
+                tm.mark(k, 1, s->st);
                 px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
-                               W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st);
-                tm.mark(2);
+                               W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st, stop);
+                tm.mark(k, 2, s->st);
                 if (dcgs2) {
                     // one dot pass and one update pass; column k-1 is finished here
-                    px::dots2(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
-                    px::reduce_dots2(W.partial, nup, k + 1, W.G, na, lda, s->st);
+                    px::dots2(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st, stop);
+                    px::reduce_dots2(W.partial, nup, k + 1, W.G, na, lda, s->st, nullptr, 1, stop);
                     px::dcgs2_coef(k, m, false, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
-                                   W.aux, W.coefQ, W.coefV, na, lda, s->st);
-                    px::dcgs2_update(W.V, vstride, k, W.coefQ, W.coefV, W.w, W.npart, na, lda, nup, s->st);
+                                   W.aux, W.coefQ, W.coefV, na, lda, s->st, stop);
+                    px::dcgs2_update(W.V, vstride, k, W.coefQ, W.coefV, W.w, W.npart, na, lda, nup, s->st, nullptr,
+                                     0, stop);
                 } else {
                     // CGS2 against v_0..v_k
                     px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
@@ -356,32 +329,29 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                     px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
                     px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
                 }
-                px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st);
+                px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st, stop);
                 if (!dcgs2)
                     px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
                                     nullptr, na, lda, s->st);
                 px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride, mixed ? W.X32 : nullptr, na, lda, nup,
-                              s->st);
-                tm.mark(3);
-                HC(hipMemcpyAsync(done_h.data(), W.done, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
-                HC(hipStreamSynchronize(s->st));
-                if (tm.on) {
-                    s->ms[wide32 ? 1 : 2] += tm.between(0, 1);
-                    s->ms[3] += tm.between(1, 2);
-                    s->ms[4] += tm.between(2, 3);
-                }
-                bool all = true;
-                for (int q = 0; q < na; ++q) all = all && done_h[q];
-                if (all) break;
+                              s->st, stop);
                 if (dcgs2 && k == m - 1) {
                     // the last basis vector's correction finishes column m-1
-                    int n_open = 0;
-                    for (int q = 0; q < na; ++q) n_open += done_h[q] ? 0 : 1;
-                    s->work[2] += (double)s->g.nu * n_open * 16.0 * (m + 2);
-                    px::dots2(W.V, vstride, m + 1, W.V + m * vstride, W.partial, na, lda, nup, s->st);
-                    px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st);
+                    px::dots2(W.V, vstride, m + 1, W.V + m * vstride, W.partial, na, lda, nup, s->st, stop);
+                    px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st, nullptr, 1, stop);
                     px::dcgs2_coef(m, m, true, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
-                                   W.aux, W.coefQ, W.coefV, na, lda, s->st);
+                                   W.aux, W.coefQ, W.coefV, na, lda, s->st, stop);
+                }
+                tm.mark(k, 3, s->st);
+                ++launched;
+                if (stop) {
+                    s->sync.publish(k, s->st);
+                } else {
+                    HC(hipMemcpyAsync(done_h.data(), W.done, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
+                    HC(hipStreamSynchronize(s->st));
+                    bool all = true;
+                    for (int q = 0; q < na; ++q) all = all && done_h[q];
+                    if (all) break;
                 }
             }
             px::lsq_solve(m, W.R, W.gv, W.steps, W.y, na, lda, s->st);
@@ -391,11 +361,26 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             HC(hipMemcpyAsync(W.map, act.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
             px::scatter_cols(W.xs, lda, s->x, s->ldg, W.map, na, nup, s->st);
             HC(hipStreamSynchronize(s->st));
-            for (int k = 0; k < na; ++k) {
-                s->iters[act[k]] += steps_h[k];
-                s->cycles[act[k]] += 1;
-                s->work[2] += 16.0 * (double)s->g.nu * (steps_h[k] + 2);
+            tm.collect(launched, s->ms[wide32 ? 1 : 2], s->ms[3], s->ms[4]);
+            // accounting: column q took part in the matvecs of its first M_q steps (the delayed
+            // variant learns that a column is done one step after its last useful matvec)
+            const double nu = (double)s->g.nu;
+            int executed = 0;
+            int64_t colsum = 0;
+            for (int q = 0; q < na; ++q) {
+                const int mq = dcgs2 ? std::min(steps_h[q] + 1, m) : steps_h[q];
+                executed = std::max(executed, mq);
+                colsum += mq;
+                for (int k = 0; k < mq; ++k) s->work[2] += nu * (80.0 + 16.0 * (dcgs2 ? 2.0 * k + 6.0 : 4.0 * k + 10.0));
+                if (dcgs2 && steps_h[q] == m) s->work[2] += nu * 16.0 * (m + 2);   // final correction pass
+                s->iters[act[q]] += steps_h[q];
+                s->cycles[act[q]] += 1;
+                s->work[2] += 16.0 * nu * (steps_h[q] + 2);
             }
+            s->counts[wide32 ? 0 : 3] += executed;
+            s->counts[wide32 ? 1 : 4] += (int64_t)executed * 2 * lda;
+            s->counts[wide32 ? 2 : 5] += 2 * colsum;
+            s->work[wide32 ? 0 : 1] += 2.0 * nu * nu * 2.0 * (double)colsum;
         }
     }
 }

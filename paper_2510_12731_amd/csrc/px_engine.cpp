@@ -48,6 +48,9 @@ namespace pxs {
 
 using px::GroupSeg;
 
+// Steps the host enqueues ahead of the last stop flag it looked at.
+constexpr int kLag = 2;
+
 size_t Engine::bytes_per_row(int Bc, int m_max)
 {
     // Krylov basis + 7 column blocks (w, x, r, b and the repacking copies) in
@@ -60,6 +63,7 @@ Engine::Engine(hipStream_t st, int Bc, const pxSolveOptions& o, int64_t rows_cap
 {
     m_max_ = std::max(o.restart_m, o.max_restart_m);
     m_ = o.restart_m;
+    sync_.ensure(m_max_ + 1);
     rows_cap_ = ((rows_cap + 255) / 256) * 256;
     const size_t vec = (size_t)rows_cap_ * Bc_;
     const int ldf = nseg_cap_ * Bc_;
@@ -294,23 +298,25 @@ std::vector<pxStructure_t*> Engine::cycle()
     HC(hipMemcpyAsync(nrm_, beta.data(), sizeof(double) * ldf, hipMemcpyHostToDevice, st_));
     px::normalize_seg(rs_, nrm_, done_, chunk_seg_, V_, mixed ? X32_ : nullptr, Bc_, rows, st_);
     std::vector<int32_t> done_h(ldf);
+    // delayed orthogonalisation: steps run ahead of the host, a device flag ends them
+    int32_t* stop = dcgs2 ? sync_.flag() : nullptr;
+    if (stop) sync_.reset(st_);
     for (int k = 0; k < m; ++k) {
+        if (stop && k >= kLag && sync_.stopped(k - kLag)) break;
         double2* vk = V_ + k * vstride;
         if (mixed) {
-            gt_.run_f32(X32_, Y32_, split_, st_);
-            stats_.tapply_f32 += 1;
+            gt_.run_f32(X32_, Y32_, split_, st_, stop);
         } else {
-            gt_.run_f64(reinterpret_cast<const double*>(vk), Y64_, st_);
-            stats_.tapply_f64 += 1;
+            gt_.run_f64(reinterpret_cast<const double*>(vk), Y64_, st_, stop);
         }
         px::spmm_seg(seginfo_, chunk_seg_, mixed ? (const void*)Y32_ : (const void*)Y64_, mixed, 2 * Bc_, vk, zq_,
-                     zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_);
+                     zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_, stop);
         if (dcgs2) {
-            px::dots2(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
-            px::reduce_dots2(partial_, rows, k + 1, G_, Bc_, Bc_, st_, beg256_, nseg);
+            px::dots2(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_, stop);
+            px::reduce_dots2(partial_, rows, k + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
             px::dcgs2_coef(k, m, false, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
-                           ldf, ldf, st_);
-            px::dcgs2_update(V_, vstride, k, coefQ_, coefV_, w_, npart_, Bc_, Bc_, rows, st_, chunk_seg_, ldf);
+                           ldf, ldf, st_, stop);
+            px::dcgs2_update(V_, vstride, k, coefQ_, coefV_, w_, npart_, Bc_, Bc_, rows, st_, chunk_seg_, ldf, stop);
         } else {
             px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
             px::reduce_dots_seg(partial_, beg256_, k + 1, h1_, nseg, Bc_, st_);
@@ -319,22 +325,28 @@ std::vector<pxStructure_t*> Engine::cycle()
             px::reduce_dots_seg(partial_, beg256_, k + 1, h2_, nseg, Bc_, st_);
             px::col_update_seg(V_, vstride, k + 1, h2_, w_, npart_, chunk_seg_, Bc_, nseg, rows, st_);
         }
-        px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_);
+        px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_, stop);
         if (!dcgs2)
             px::givens_step(k, m, h1_, h2_, nrm_, R_, cs_, sn_, gv_, target_, done_, steps_, nullptr, ldf, ldf, st_);
-        px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows, st_);
-        HC(hipMemcpyAsync(done_h.data(), done_, sizeof(int32_t) * ldf, hipMemcpyDeviceToHost, st_));
-        HC(hipStreamSynchronize(st_));
-        stats_.steps += 1;
-        bool all = true;
-        for (int f = 0; f < ldf && all; ++f) all = done_h[f] != 0;
-        if (all) break;
+        px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows, st_,
+                          stop);
         if (dcgs2 && k == m - 1) {
             // the last basis vector's correction finishes column m-1
-            px::dots2(V_, vstride, m + 1, V_ + m * vstride, partial_, Bc_, Bc_, rows, st_);
-            px::reduce_dots2(partial_, rows, m + 1, G_, Bc_, Bc_, st_, beg256_, nseg);
+            px::dots2(V_, vstride, m + 1, V_ + m * vstride, partial_, Bc_, Bc_, rows, st_, stop);
+            px::reduce_dots2(partial_, rows, m + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
             px::dcgs2_coef(m, m, true, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
-                           ldf, ldf, st_);
+                           ldf, ldf, st_, stop);
+        }
+        if (stop) {
+            sync_.publish(k, st_);
+        } else {
+            HC(hipMemcpyAsync(done_h.data(), done_, sizeof(int32_t) * ldf, hipMemcpyDeviceToHost, st_));
+            HC(hipStreamSynchronize(st_));
+            stats_.steps += 1;
+            (mixed ? stats_.tapply_f32 : stats_.tapply_f64) += 1;
+            bool all = true;
+            for (int f = 0; f < ldf && all; ++f) all = done_h[f] != 0;
+            if (all) break;
         }
     }
     px::lsq_solve(m, R_, gv_, steps_, y_, ldf, ldf, st_);
@@ -342,6 +354,7 @@ std::vector<pxStructure_t*> Engine::cycle()
     std::vector<int32_t> steps_h(ldf);
     HC(hipMemcpyAsync(steps_h.data(), steps_, sizeof(int32_t) * ldf, hipMemcpyDeviceToHost, st_));
     HC(hipStreamSynchronize(st_));
+    int executed = 0;
     for (int k = 0; k < nseg; ++k) {
         const EngineSeg& e = segs_[k];
         for (int c = 0; c < e.nc; ++c) {
@@ -349,8 +362,11 @@ std::vector<pxStructure_t*> Engine::cycle()
             if (done[f]) continue;   // column was already finished at the cycle start
             e.s->iters[e.c0 + c] += steps_h[f];
             e.s->cycles[e.c0 + c] += 1;
+            executed = std::max(executed, dcgs2 ? std::min(steps_h[f] + 1, m) : steps_h[f]);
         }
     }
+    if (dcgs2) stats_.steps += executed;
+    (mixed ? stats_.tapply_f32 : stats_.tapply_f64) += dcgs2 ? executed : 0;
     stats_.cycles += 1;
     return finished;
 }

@@ -76,6 +76,7 @@ class Engine {
     double2 *zq_ = nullptr, *zmu_ = nullptr;
     px::SegInfo* seginfo_ = nullptr;
     int32_t *chunk_seg_ = nullptr, *beg256_ = nullptr, *beg32_ = nullptr;
+    StepSync sync_;   // stop flag of the Arnoldi steps
 };
 
 }  // namespace pxs

@@ -54,10 +54,10 @@ struct Geometry {
 // blocks for the dipole model); ncols real columns, multiple of 2*COL_PAD for
 // the wide kernels.  Ghost rows of Y are unspecified.
 // scratch: tapply_f32_scratch_bytes(g, ncols) bytes (split-K partial sums).
-void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch);
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch, const int32_t* stop = nullptr);
 size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols);
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes);
+                double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
 // Grouped T-apply over the segments of a stacked block (each segment one
@@ -77,8 +77,8 @@ class GroupedTApply {
     hipError_t setup(const std::vector<GroupSeg>& segs, int ldx, int64_t rows, hipStream_t st);
     size_t partial_bytes() const;   // split-K scratch needed by run_f32
     int64_t f32_tiles() const;
-    void run_f32(const float* X, float* Y, float* partial, hipStream_t st) const;
-    void run_f64(const double* X, double* Y, hipStream_t st) const;
+    void run_f32(const float* X, float* Y, float* partial, hipStream_t st, const int32_t* stop = nullptr) const;
+    void run_f64(const double* X, double* Y, hipStream_t st, const int32_t* stop = nullptr) const;
 
   private:
     struct Impl;
@@ -96,7 +96,7 @@ struct Shifts {            // per active slot
 
 // mu_sign: +1 gives the paper's operator, -1 the solver's form with negated dipole rows.
 void spmm_shift(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* zq,
-                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st);
+                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st, const int32_t* stop = nullptr);
 void build_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, double mu_sign,
                hipStream_t st);
 void col_dots(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
@@ -106,10 +106,10 @@ void reduce_dots(const double2* partial, int nchunk, int nvec, double2* h, int n
 // norm_partial (may be null): update_chunks(nup) x lda partial sums of |w|^2.
 void col_update(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
                 int na, int lda, int64_t nup, hipStream_t st);
-void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st);
+void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st, const int32_t* stop = nullptr);
 void col_norm_partial(const double2* w, double* partial, int na, int lda, int64_t nup, hipStream_t st);
 void normalize(const double2* w, const double* nrm, const int32_t* done, double2* v, float* x32, int na, int lda,
-               int64_t nup, hipStream_t st);
+               int64_t nup, hipStream_t st, const int32_t* stop = nullptr);
 void to_f32(const double2* v, float* x32, int na, int lda, int64_t nup, hipStream_t st);
 void givens_step(int k, int m, const double2* h1, const double2* h2, const double* nrm, double2* R, double* cs,
                  double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps, int32_t* n_open,
@@ -141,20 +141,23 @@ int dot_rows(int nvec);
 inline int dot_chunks(int64_t nup, int nvec) { return (int)((nup + dot_rows(nvec) - 1) / dot_rows(nvec)); }
 size_t dot_partial_slabs(int64_t nup, int nvec_max);
 void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
-           int64_t nup, hipStream_t st);
+           int64_t nup, hipStream_t st, const int32_t* stop = nullptr);
 // With segments (seg_beg: first 256-row chunk of each of nseg segments of lda
 // columns), G is indexed by the flat column seg * lda + c.
 void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st,
-                  const int32_t* seg_beg = nullptr, int nseg = 1);
-// aux: [2][lda] scratch (rho, c_k) between the column-serial and the row-parallel part
+                  const int32_t* seg_beg = nullptr, int nseg = 1, const int32_t* stop = nullptr);
+// aux: [2][lda] scratch (rho, c_k) between the column-serial and the row-parallel part.
+// stop (optional): set to 1 once the rotations have finished every one of the na
+// columns; every kernel of an Arnoldi step that is given the flag returns at once
+// when it is set.
 void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
                 double* cs, double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps,
-                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st);
+                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st, int32_t* stop = nullptr);
 // chunk_seg (per 256-row chunk: its segment) switches to flat coefficients of
 // leading dimension ldc.
 void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
                   double* norm_partial, int na, int lda, int64_t nup, hipStream_t st,
-                  const int32_t* chunk_seg = nullptr, int ldc = 0);
+                  const int32_t* chunk_seg = nullptr, int ldc = 0, const int32_t* stop = nullptr);
 
 // ---- stacked segments (px_engine.cpp) ---------------------------------------
 // One segment of a stacked block: a structure's padded rows (np or 4 np) with
@@ -168,14 +171,14 @@ struct SegInfo {
 };
 void spmm_seg(const SegInfo* segs, const int32_t* chunk_seg, const void* Y, bool y_is_f32, int ldy, const double2* X,
               const double2* zq, const double2* zmu, const double2* B, double2* W, int64_t rows, int Bc, int nseg,
-              double mu_sign, hipStream_t st);
+              double mu_sign, hipStream_t st, const int32_t* stop = nullptr);
 void reduce_dots_seg(const double2* partial, const int32_t* seg_beg, int nvec, double2* h, int nseg, int Bc,
                      hipStream_t st);
-void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st);
+void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st, const int32_t* stop = nullptr);
 void col_update_seg(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
                     const int32_t* chunk_seg, int Bc, int nseg, int64_t rows, hipStream_t st);
 void normalize_seg(const double2* w, const double* nrm, const int32_t* done, const int32_t* chunk_seg, double2* v,
-                   float* x32, int Bc, int64_t rows, hipStream_t st);
+                   float* x32, int Bc, int64_t rows, hipStream_t st, const int32_t* stop = nullptr);
 void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
                   double2* x, int Bc, int nseg, int64_t rows, hipStream_t st);
 

@@ -254,8 +254,10 @@ __global__ __launch_bounds__(256) void k_spmm_shift(const int32_t* __restrict__ 
                                                     const double2* __restrict__ zmu,
                                                     const double2* __restrict__ B, double2* __restrict__ W,
                                                     int64_t n, int64_t np, int64_t nup, int na, int lda,
-                                                    double mu_sign)
+                                                    double mu_sign,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= nup || c >= lda) return;
@@ -479,8 +481,10 @@ __global__ __launch_bounds__(256) void k_col_norm_partial(const double2* __restr
 // nrm[c] = sqrt(sum_k partial[k][c]); 256 threads = 64 columns x 4 waves, wave
 // w sums chunks w, w+4, ...; the four sums are combined in a fixed order.
 __global__ __launch_bounds__(256) void k_reduce_norms(const double* __restrict__ partial, int nchunk,
-                                                      double* __restrict__ nrm, int na, int lda)
+                                                      double* __restrict__ nrm, int na, int lda,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = blockIdx.x * 64 + lane;
@@ -496,8 +500,10 @@ __global__ __launch_bounds__(256) void k_reduce_norms(const double* __restrict__
 // the real layout [rows][2*lda] when x32 != nullptr.
 __global__ __launch_bounds__(256) void k_normalize(const double2* __restrict__ w, const double* __restrict__ nrm,
                                                    const int32_t* __restrict__ done, double2* __restrict__ v,
-                                                   float* __restrict__ x32, int na, int lda, int64_t nup)
+                                                   float* __restrict__ x32, int na, int lda, int64_t nup,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= nup || c >= lda) return;
@@ -765,8 +771,10 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, size_t words)
 constexpr int DOT_JB = 8;
 __global__ __launch_bounds__(64) void k_dots2(const double2* __restrict__ V, int64_t vstride, int nvec,
                                               const double2* __restrict__ w, double2* __restrict__ partial, int na,
-                                              int lda, int64_t nup, int rows_per, int njg, int nch)
+                                              int lda, int64_t nup, int rows_per, int njg, int nch,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int nb = gridDim.x, L = blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, x = L & 7;
     const int lam = (x < r8 ? x * (q8 + 1) : r8 * (q8 + 1) + (x - r8) * q8) + (L >> 3);
@@ -817,8 +825,10 @@ __global__ __launch_bounds__(64) void k_dots2(const double2* __restrict__ V, int
 // segments f = seg * ld + c over nseg segments of ld columns, seg_beg holding
 // each segment's first 256-row chunk.
 __global__ void k_reduce_dots2(const double2* __restrict__ partial, int nch, int rows_per, int nvec,
-                               double2* __restrict__ G, int na, int ld, const int32_t* __restrict__ seg_beg, int nseg)
+                               double2* __restrict__ G, int na, int ld, const int32_t* __restrict__ seg_beg, int nseg,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int ldf = nseg * ld;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nvec * 2 * ldf) return;
@@ -845,8 +855,10 @@ __global__ void k_dcgs2_fix(int k, int m, int final_only, const double2* __restr
                             const double* __restrict__ nrm, double2* __restrict__ H, double2* __restrict__ R,
                             double* __restrict__ cs, double2* __restrict__ sn, double2* __restrict__ g,
                             const double* __restrict__ target, int32_t* __restrict__ done,
-                            int32_t* __restrict__ steps, double2* __restrict__ aux, int na, int lda)
+                            int32_t* __restrict__ steps, double2* __restrict__ aux, int na, int lda,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= na || done[c]) return;
     const size_t ld2 = 2 * (size_t)lda;
@@ -926,6 +938,15 @@ __global__ void k_dcgs2_fix(int k, int m, int final_only, const double2* __restr
     aux[lda + c] = make_double2(cv.x / rho, cv.y / rho);
 }
 
+// stop = 1 when every one of the n columns is done (one workgroup).
+__global__ __launch_bounds__(256) void k_all_done(const int32_t* __restrict__ done, int n, int32_t* __restrict__ stop)
+{
+    int open = 0;
+    for (int c = threadIdx.x; c < n; c += 256) open |= (done[c] == 0);
+    open = __syncthreads_or(open);
+    if (threadIdx.x == 0) stop[0] = open ? 0 : 1;
+}
+
 // Step k, one wave per (row i <= k, 64 columns): the tentative Hessenberg
 // column h_i = (c_i - (H s)_i) / rho, and the update coefficients
 // coefQ[i] = (s_i / rho, d_i) for i < k, coefV = (1/rho, c_k/rho^2) for i = k.
@@ -933,8 +954,10 @@ __global__ void k_dcgs2_fix(int k, int m, int final_only, const double2* __restr
 __global__ __launch_bounds__(256) void k_dcgs2_coef(int k, int m, const double2* __restrict__ G,
                                                     const double2* __restrict__ aux, double2* __restrict__ H,
                                                     const int32_t* __restrict__ done, double2* __restrict__ coefQ,
-                                                    double2* __restrict__ coefV, int na, int lda)
+                                                    double2* __restrict__ coefV, int na, int lda,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i > k || c >= na) return;
@@ -978,8 +1001,10 @@ __global__ __launch_bounds__(256) void k_dcgs2_update(double2* __restrict__ V, i
                                                       const double2* __restrict__ coefQ,
                                                       const double2* __restrict__ coefV, double2* __restrict__ w,
                                                       double* __restrict__ norm_partial, int na, int lda, int64_t nup,
-                                                      const int32_t* __restrict__ chunk_seg, int ldc)
+                                                      const int32_t* __restrict__ chunk_seg, int ldc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = blockIdx.y * 64 + lane;
@@ -1037,8 +1062,10 @@ __global__ __launch_bounds__(256) void k_spmm_seg(const SegInfo* __restrict__ se
                                                   int y_f32, int ldy, const double2* __restrict__ X,
                                                   const double2* __restrict__ zq, const double2* __restrict__ zmu,
                                                   const double2* __restrict__ B, double2* __restrict__ W, int64_t rows,
-                                                  int Bc, int ldf, double mu_sign)
+                                                  int Bc, int ldf, double mu_sign,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= rows || c >= Bc) return;
@@ -1102,8 +1129,10 @@ __global__ void k_reduce_dots_seg(const double2* __restrict__ partial, const int
 
 // nrm[seg*Bc + c] = sqrt(sum of partial[k][c] over the segment's chunks k)
 __global__ void k_reduce_norms_seg(const double* __restrict__ partial, const int32_t* __restrict__ seg_beg,
-                                   double* __restrict__ nrm, int nseg, int Bc)
+                                   double* __restrict__ nrm, int nseg, int Bc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nseg * Bc) return;
     const int sg = f / Bc, c = f - sg * Bc;
@@ -1157,8 +1186,10 @@ __global__ __launch_bounds__(256) void k_col_update_seg(const double2* __restric
 __global__ __launch_bounds__(256) void k_normalize_seg(const double2* __restrict__ w, const double* __restrict__ nrm,
                                                        const int32_t* __restrict__ done,
                                                        const int32_t* __restrict__ chunk_seg, double2* __restrict__ v,
-                                                       float* __restrict__ x32, int Bc, int64_t rows)
+                                                       float* __restrict__ x32, int Bc, int64_t rows,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= rows || c >= Bc) return;
@@ -1283,17 +1314,17 @@ fail:
 }
 
 void spmm_shift(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* zq,
-                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st)
+                const double2* zmu, const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st, const int32_t* stop)
 {
     dim3 grid = grid_rows_cols(g.nup, lda);
     if (y_is_f32)
         hipLaunchKernelGGL(k_spmm_shift<float>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val,
                            static_cast<const float*>(Y), ldy, X, zq, zmu, B, W, g.n, g.np, g.nup, na, lda,
-                           mu_sign);
+                           mu_sign, stop);
     else
         hipLaunchKernelGGL(k_spmm_shift<double>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val,
                            static_cast<const double*>(Y), ldy, X, zq, zmu, B, W, g.n, g.np, g.nup, na, lda,
-                           mu_sign);
+                           mu_sign, stop);
 }
 
 void build_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, double mu_sign,
@@ -1330,16 +1361,16 @@ void col_norm_partial(const double2* w, double* partial, int na, int lda, int64_
                        partial, na, lda, nup);
 }
 
-void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st)
+void reduce_norms(const double* partial, int nchunk, double* nrm, int na, int lda, hipStream_t st, const int32_t* stop)
 {
     hipLaunchKernelGGL(k_reduce_norms, dim3((unsigned)((na + 63) / 64)), dim3(256), 0, st, partial, nchunk, nrm, na,
-                       lda);
+                       lda, stop);
 }
 
 void normalize(const double2* w, const double* nrm, const int32_t* done, double2* v, float* x32, int na, int lda,
-               int64_t nup, hipStream_t st)
+               int64_t nup, hipStream_t st, const int32_t* stop)
 {
-    hipLaunchKernelGGL(k_normalize, grid_rows_cols(nup, lda), dim3(256), 0, st, w, nrm, done, v, x32, na, lda, nup);
+    hipLaunchKernelGGL(k_normalize, grid_rows_cols(nup, lda), dim3(256), 0, st, w, nrm, done, v, x32, na, lda, nup, stop);
 }
 
 void to_f32(const double2* v, float* x32, int na, int lda, int64_t nup, hipStream_t st)
@@ -1424,10 +1455,10 @@ void fill_zero(void* p, size_t bytes, hipStream_t st)
 
 void spmm_seg(const SegInfo* segs, const int32_t* chunk_seg, const void* Y, bool y_is_f32, int ldy, const double2* X,
               const double2* zq, const double2* zmu, const double2* B, double2* W, int64_t rows, int Bc, int nseg,
-              double mu_sign, hipStream_t st)
+              double mu_sign, hipStream_t st, const int32_t* stop)
 {
     hipLaunchKernelGGL(k_spmm_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, segs, chunk_seg, Y, y_is_f32 ? 1 : 0,
-                       ldy, X, zq, zmu, B, W, rows, Bc, nseg * Bc, mu_sign);
+                       ldy, X, zq, zmu, B, W, rows, Bc, nseg * Bc, mu_sign, stop);
 }
 
 void reduce_dots_seg(const double2* partial, const int32_t* seg_beg, int nvec, double2* h, int nseg, int Bc,
@@ -1438,10 +1469,10 @@ void reduce_dots_seg(const double2* partial, const int32_t* seg_beg, int nvec, d
                        h, nseg, Bc);
 }
 
-void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st)
+void reduce_norms_seg(const double* partial, const int32_t* seg_beg, double* nrm, int nseg, int Bc, hipStream_t st, const int32_t* stop)
 {
     hipLaunchKernelGGL(k_reduce_norms_seg, dim3((unsigned)((nseg * Bc + 255) / 256)), dim3(256), 0, st, partial,
-                       seg_beg, nrm, nseg, Bc);
+                       seg_beg, nrm, nseg, Bc, stop);
 }
 
 void col_update_seg(const double2* V, int64_t vstride, int nvec, const double2* h, double2* w, double* norm_partial,
@@ -1452,10 +1483,10 @@ void col_update_seg(const double2* V, int64_t vstride, int nvec, const double2* 
 }
 
 void normalize_seg(const double2* w, const double* nrm, const int32_t* done, const int32_t* chunk_seg, double2* v,
-                   float* x32, int Bc, int64_t rows, hipStream_t st)
+                   float* x32, int Bc, int64_t rows, hipStream_t st, const int32_t* stop)
 {
     hipLaunchKernelGGL(k_normalize_seg, grid_rows_cols(rows, Bc), dim3(256), 0, st, w, nrm, done, chunk_seg, v, x32, Bc,
-                       rows);
+                       rows, stop);
 }
 
 void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
@@ -1481,39 +1512,41 @@ size_t dot_partial_slabs(int64_t nup, int nvec_max)
 }
 
 void dots2(const double2* V, int64_t vstride, int nvec, const double2* w, double2* partial, int na, int lda,
-           int64_t nup, hipStream_t st)
+           int64_t nup, hipStream_t st, const int32_t* stop)
 {
     const int rows = dot_rows(nvec), nch = dot_chunks(nup, nvec);
     const int njg = (nvec + DOT_JB - 1) / DOT_JB, ncb = (na + 63) / 64;
     hipLaunchKernelGGL(k_dots2, dim3((unsigned)(njg * nch * ncb)), dim3(64), 0, st, V, vstride, nvec, w, partial,
-                       na, lda, nup, rows, njg, nch);
+                       na, lda, nup, rows, njg, nch, stop);
 }
 
 void reduce_dots2(const double2* partial, int64_t nup, int nvec, double2* G, int na, int lda, hipStream_t st,
-                  const int32_t* seg_beg, int nseg)
+                  const int32_t* seg_beg, int nseg, const int32_t* stop)
 {
     const int t = nvec * 2 * lda * nseg;
     hipLaunchKernelGGL(k_reduce_dots2, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, partial,
-                       dot_chunks(nup, nvec), dot_rows(nvec), nvec, G, na, lda, seg_beg, nseg);
+                       dot_chunks(nup, nvec), dot_rows(nvec), nvec, G, na, lda, seg_beg, nseg, stop);
 }
 
 void dcgs2_coef(int k, int m, bool final_only, const double2* G, const double* nrm, double2* H, double2* R,
                 double* cs, double2* sn, double2* gvec, const double* target, int32_t* done, int32_t* steps,
-                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st)
+                double2* aux, double2* coefQ, double2* coefV, int na, int lda, hipStream_t st, int32_t* stop)
 {
     hipLaunchKernelGGL(k_dcgs2_fix, dim3((unsigned)((na + 63) / 64)), dim3(64), 0, st, k, m, final_only ? 1 : 0, G,
-                       nrm, H, R, cs, sn, gvec, target, done, steps, aux, na, lda);
+                       nrm, H, R, cs, sn, gvec, target, done, steps, aux, na, lda, stop);
+    // with a stop flag: raise it as soon as the rotations have finished every column
+    if (stop) hipLaunchKernelGGL(k_all_done, dim3(1), dim3(256), 0, st, done, na, stop);
     if (final_only) return;
     hipLaunchKernelGGL(k_dcgs2_coef, dim3((unsigned)((k + 4) / 4), (unsigned)((na + 63) / 64)), dim3(256), 0, st, k,
-                       m, G, aux, H, done, coefQ, coefV, na, lda);
+                       m, G, aux, H, done, coefQ, coefV, na, lda, stop);
 }
 
 void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, const double2* coefV, double2* w,
                   double* norm_partial, int na, int lda, int64_t nup, hipStream_t st, const int32_t* chunk_seg,
-                  int ldc)
+                  int ldc, const int32_t* stop)
 {
     hipLaunchKernelGGL(k_dcgs2_update, dim3(update_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, V,
-                       vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup, chunk_seg, chunk_seg ? ldc : lda);
+                       vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup, chunk_seg, chunk_seg ? ldc : lda, stop);
 }
 
 }  // namespace px

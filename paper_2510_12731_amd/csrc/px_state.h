@@ -74,6 +74,103 @@ struct Workspace {
     }
 };
 
+// Lagged host polling of the device stop flag that every kernel of an Arnoldi
+// step reads: the host enqueues steps ahead of the device and only looks at
+// the flag published after step k - lag, so it never waits for the step it
+// just enqueued, and the steps enqueued after the last column finished cost
+// one near-empty launch per kernel.
+class StepSync {
+  public:
+    StepSync() = default;
+    StepSync(const StepSync&) = delete;
+    StepSync& operator=(const StepSync&) = delete;
+    ~StepSync() { release(); }
+    void ensure(int steps)
+    {
+        if (steps <= cap_) return;
+        release();
+        d_flag_ = dalloc<int32_t>(1);
+        if (hipHostMalloc((void**)&h_flags_, sizeof(int32_t) * steps, hipHostMallocDefault) != hipSuccess)
+            throw HipError{hipErrorOutOfMemory, "hipHostMalloc"};
+        ev_.resize(steps);
+        for (auto& e : ev_) HC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        cap_ = steps;
+    }
+    int32_t* flag() const { return d_flag_; }
+    // device-side reset, a kernel (so that the sequence can be graph-captured)
+    void reset(hipStream_t st) { px::fill_zero(d_flag_, sizeof(int32_t), st); }
+    void publish(int k, hipStream_t st)
+    {
+        HC(hipMemcpyAsync(h_flags_ + k, d_flag_, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HC(hipEventRecord(ev_[k], st));
+    }
+    bool stopped(int k)
+    {
+        HC(hipEventSynchronize(ev_[k]));
+        return h_flags_[k] != 0;
+    }
+
+  private:
+    void release()
+    {
+        for (auto& e : ev_) (void)hipEventDestroy(e);
+        ev_.clear();
+        if (h_flags_) (void)hipHostFree(h_flags_);
+        dfree(d_flag_);
+        h_flags_ = nullptr;
+        d_flag_ = nullptr;
+        cap_ = 0;
+    }
+    int cap_ = 0;
+    int32_t* d_flag_ = nullptr;
+    int32_t* h_flags_ = nullptr;
+    std::vector<hipEvent_t> ev_;
+};
+
+// Per-step phase timing with HIP events, read after the cycle's final sync.
+class StepTimer {
+  public:
+    explicit StepTimer(bool on) : on_(on) {}
+    StepTimer(const StepTimer&) = delete;
+    StepTimer& operator=(const StepTimer&) = delete;
+    ~StepTimer()
+    {
+        for (auto& e : ev_) (void)hipEventDestroy(e);
+    }
+    void ensure(int steps)
+    {
+        if (!on_) return;
+        while ((int)ev_.size() < 4 * steps) {
+            hipEvent_t e;
+            HC(hipEventCreate(&e));
+            ev_.push_back(e);
+        }
+    }
+    void mark(int k, int i, hipStream_t st)
+    {
+        if (on_) HC(hipEventRecord(ev_[4 * k + i], st));
+    }
+    // adds the phase times of steps [0, nsteps) to ms[1..4] style slots: t01 -> a, t12 -> b, t23 -> c
+    void collect(int nsteps, double& a, double& b, double& c)
+    {
+        if (!on_) return;
+        for (int k = 0; k < nsteps; ++k) {
+            float t = 0.f;
+            HC(hipEventElapsedTime(&t, ev_[4 * k], ev_[4 * k + 1]));
+            a += t;
+            HC(hipEventElapsedTime(&t, ev_[4 * k + 1], ev_[4 * k + 2]));
+            b += t;
+            HC(hipEventElapsedTime(&t, ev_[4 * k + 2], ev_[4 * k + 3]));
+            c += t;
+        }
+    }
+    bool on() const { return on_; }
+
+  private:
+    bool on_;
+    std::vector<hipEvent_t> ev_;
+};
+
 // z_q(omega) of Eq. (z_q_wfq) with the Drude weight n/m* (graphene: E_F/(pi t_g)), omega in Hartree
 void shift_q(double drude, double tau, double w, double& zr, double& zi);
 // Eq. (z-mu): z_mu = -1 / alpha_IB
@@ -113,6 +210,7 @@ struct pxStructure_t {
     // columns; the same three for the FP64 T-apply (cycles and residuals)
     int64_t counts[6] = {0, 0, 0, 0, 0, 0};
     double work[3] = {0, 0, 0};   // algorithmic FP32 FLOP, FP64 FLOP, HBM bytes of the last solve
+    pxs::StepSync sync;           // stop flag of the Arnoldi steps
 
     ~pxStructure_t()
     {

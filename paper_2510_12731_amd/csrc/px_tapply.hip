@@ -251,8 +251,10 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32(const float4* __
                                                                 const float4* __restrict__ ghi,
                                                                 const float* __restrict__ X, float* __restrict__ Y,
                                                                 float* __restrict__ partial, int ldx, SkGrid sk,
-                                                                float inv_rqq, float t_self, float r_far2)
+                                                                float inv_rqq, float t_self, float r_far2,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
         const int rb = t % sk.RB, cb = t / sk.RB;
         float* out = slot < 0 ? Y + (size_t)rb * 256 * ldx + cb * Q32_COLS : partial + (size_t)slot * SK_TILE_FLOATS;
@@ -420,8 +422,10 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32(const float4* __restr
                                                            const float4* __restrict__ glo,
                                                            const float4* __restrict__ ghi,
                                                            const float* __restrict__ X, float* __restrict__ Y,
-                                                           int np, int ldx, DipoleConstF kc)
+                                                           int np, int ldx, DipoleConstF kc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     tapply_wfqfmu_f32_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, kc);
 }
 
@@ -549,8 +553,10 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restric
                                                         const float4* __restrict__ ghi,
                                                         const double* __restrict__ X, double* __restrict__ Y,
                                                         int np, int ldx, double inv_rqq, double t_self,
-                                                        float r_far2)
+                                                        float r_far2,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     tapply_wfq_f64_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, inv_rqq, t_self, r_far2);
 }
 
@@ -704,8 +710,10 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64(const double4* __rest
                                                            const float4* __restrict__ glo,
                                                            const float4* __restrict__ ghi,
                                                            const double* __restrict__ X, double* __restrict__ Y,
-                                                           int np, int ldx, DipoleConstD kc)
+                                                           int np, int ldx, DipoleConstD kc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     tapply_wfqfmu_f64_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, kc);
 }
 
@@ -722,8 +730,10 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
                                                            const double* __restrict__ X,
                                                            double* __restrict__ part, int np, int chunks_per_split,
                                                            double inv_rqq, double t_self, float r_far2,
-                                                           DipoleConstD kc)
+                                                           DipoleConstD kc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     constexpr int NCOMP = MODEL ? 4 : 1;
     __shared__ double4 sxyz[NW_CHUNK];
     __shared__ double sxv[NCOMP][NW_CHUNK][NC];
@@ -802,8 +812,10 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
         for (int c = 0; c < NC; ++c) out[a * cstride + (size_t)i * NC + c] = acc[a][c];
 }
 
-__global__ void k_sum_splits(const double* __restrict__ part, double* __restrict__ Y, size_t len, int nsplit)
+__global__ void k_sum_splits(const double* __restrict__ part, double* __restrict__ Y, size_t len, int nsplit,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= len) return;
     double s = 0.0;
@@ -833,8 +845,10 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32_grouped(const Gr
                                                                         const float* __restrict__ X,
                                                                         float* __restrict__ Y,
                                                                         float* __restrict__ partial, int ldx,
-                                                                        SkGrid sk)
+                                                                        SkGrid sk,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
         const int4 tl = sk.tiles[t];
         const GroupConst& c = gc[tl.x];
@@ -849,8 +863,10 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32_grouped(const Gr
 // workgroup order, into Y.  Grid: 32 workgroups of 256 threads per tile, one
 // float4 per thread.  gc / tiles null: the single-structure layout.
 __global__ __launch_bounds__(256) void k_sk_fixup(const float* __restrict__ partial, float* __restrict__ Y, int ldx,
-                                                  SkGrid sk, const GroupConst* __restrict__ gc)
+                                                  SkGrid sk, const GroupConst* __restrict__ gc,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int t = blockIdx.x >> 5;
     const int64_t p0 = sk_pre(sk, t);
     const int ct = sk.tiles ? sk.tiles[t].w : sk.C;
@@ -880,8 +896,10 @@ __global__ __launch_bounds__(256) void k_sk_fixup(const float* __restrict__ part
 __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32_grouped(const GroupConst* __restrict__ gc,
                                                                    const int4* __restrict__ tiles,
                                                                    const float* __restrict__ X,
-                                                                   float* __restrict__ Y, int ldx)
+                                                                   float* __restrict__ Y, int ldx,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int4 t = tiles[blockIdx.x];
     const GroupConst& c = gc[t.x];
     tapply_wfqfmu_f32_body(t.y, t.z, 0, c.xyz32, c.glo, c.ghi, X + (size_t)c.row_off * ldx,
@@ -891,8 +909,10 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f32_grouped(const GroupCo
 __global__ __launch_bounds__(256) void k_tapply_wfq_f64_grouped(const GroupConst* __restrict__ gc,
                                                                 const int4* __restrict__ tiles,
                                                                 const double* __restrict__ X, double* __restrict__ Y,
-                                                                int ldx)
+                                                                int ldx,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int4 t = tiles[blockIdx.x];
     const GroupConst& c = gc[t.x];
     tapply_wfq_f64_body(t.y, t.z, 0, c.xyz64, c.glo, c.ghi, X + (size_t)c.row_off * ldx, Y + (size_t)c.row_off * ldx,
@@ -902,8 +922,10 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f64_grouped(const GroupConst
 __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64_grouped(const GroupConst* __restrict__ gc,
                                                                    const int4* __restrict__ tiles,
                                                                    const double* __restrict__ X,
-                                                                   double* __restrict__ Y, int ldx)
+                                                                   double* __restrict__ Y, int ldx,
+    const int32_t* __restrict__ stop)
 {
+    if (stop && *stop) return;   // every column of the block is done
     const int4 t = tiles[blockIdx.x];
     const GroupConst& c = gc[t.x];
     tapply_wfqfmu_f64_body(t.y, t.z, 0, c.xyz64, c.glo, c.ghi, X + (size_t)c.row_off * ldx,
@@ -944,7 +966,7 @@ int narrow_splits(const Geometry& g)
 }
 
 template <int NC, int MODEL>
-void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch)
+void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch, const int32_t* stop)
 {
     int rb = (int)(g.np / 256);
     int nchunk = (int)(g.np / NW_CHUNK);
@@ -954,9 +976,9 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     DipoleConstD kc = dipole_const_d(g);
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
     hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi,
-                       X, scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc);
+                       X, scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc, stop);
     size_t len = (size_t)(MODEL ? 4 : 1) * g.np * NC;
-    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit);
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit, stop);
 }
 
 // Resident 512-thread FP32 workgroups: two per CU (LDS and registers allow
@@ -987,7 +1009,7 @@ size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols)
     return (size_t)2 * sk_slots() * SK_TILE_FLOATS * sizeof(float);
 }
 
-void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch)
+void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch, const int32_t* stop)
 {
     if (g.model == 0) {
         double rqq = std::sqrt(2.0) * g.r_q;
@@ -999,9 +1021,9 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
         sk.total = (int64_t)sk.T * sk.C;
         sk.G = sk_workgroups(sk.total);
         hipLaunchKernelGGL(k_tapply_wfq_f32, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, g.xyz32, g.glo, g.ghi, X,
-                           Y, scratch, ldx, sk, (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf);
+                           Y, scratch, ldx, sk, (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf, stop);
         hipLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * sk.T)), dim3(256), 0, st, scratch, Y, ldx, sk,
-                           (const GroupConst*)nullptr);
+                           (const GroupConst*)nullptr, stop);
     } else {
         DipoleConstD d = dipole_const_d(g);
         DipoleConstF k;
@@ -1013,7 +1035,7 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
         double rmax = 1.0 / std::fmin(d.inv_rqq, std::fmin(d.inv_rqm, d.inv_rmm));
         k.r_far2 = (float)((XFAR_D32 * rmax) * (XFAR_D32 * rmax));
         hipLaunchKernelGGL(k_tapply_wfqfmu_f32, dim3((unsigned)(g.np / 128), (unsigned)(ncols / D32_COLS)),
-                           dim3(256), 0, st, g.xyz32, g.glo, g.ghi, X, Y, (int)g.np, ldx, k);
+                           dim3(256), 0, st, g.xyz32, g.glo, g.ghi, X, Y, (int)g.np, ldx, k, stop);
     }
 }
 
@@ -1024,24 +1046,24 @@ size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 }
 
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes)
+                double* scratch, size_t scratch_bytes, const int32_t* stop)
 {
     (void)scratch_bytes;
     if (ncols <= 8) {
         // narrow layout: ldx == ncols
         if (g.model == 0) {
             switch (ncols) {
-            case 2: launch_narrow<2, 0>(g, X, Y, st, scratch); break;
-            case 4: launch_narrow<4, 0>(g, X, Y, st, scratch); break;
-            case 6: launch_narrow<6, 0>(g, X, Y, st, scratch); break;
-            default: launch_narrow<8, 0>(g, X, Y, st, scratch); break;
+            case 2: launch_narrow<2, 0>(g, X, Y, st, scratch, stop); break;
+            case 4: launch_narrow<4, 0>(g, X, Y, st, scratch, stop); break;
+            case 6: launch_narrow<6, 0>(g, X, Y, st, scratch, stop); break;
+            default: launch_narrow<8, 0>(g, X, Y, st, scratch, stop); break;
             }
         } else {
             switch (ncols) {
-            case 2: launch_narrow<2, 1>(g, X, Y, st, scratch); break;
-            case 4: launch_narrow<4, 1>(g, X, Y, st, scratch); break;
-            case 6: launch_narrow<6, 1>(g, X, Y, st, scratch); break;
-            default: launch_narrow<8, 1>(g, X, Y, st, scratch); break;
+            case 2: launch_narrow<2, 1>(g, X, Y, st, scratch, stop); break;
+            case 4: launch_narrow<4, 1>(g, X, Y, st, scratch, stop); break;
+            case 6: launch_narrow<6, 1>(g, X, Y, st, scratch, stop); break;
+            default: launch_narrow<8, 1>(g, X, Y, st, scratch, stop); break;
             }
         }
         return;
@@ -1051,11 +1073,11 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
         float rf = (float)(XFAR_Q64 * rqq);
         hipLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)(ncols / Q64_COLS)), dim3(256),
                            0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, 1.0 / rqq, TWO_OVER_SQRTPI / rqq,
-                           rf * rf);
+                           rf * rf, stop);
     } else {
         DipoleConstD k = dipole_const_d(g);
         hipLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
-                           dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, k);
+                           dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, k, stop);
     }
 }
 
@@ -1178,27 +1200,27 @@ size_t GroupedTApply::partial_bytes() const
 
 int64_t GroupedTApply::f32_tiles() const { return impl->n32q + impl->n32d; }
 
-void GroupedTApply::run_f32(const float* X, float* Y, float* partial, hipStream_t st) const
+void GroupedTApply::run_f32(const float* X, float* Y, float* partial, hipStream_t st, const int32_t* stop) const
 {
     if (impl->n32q > 0) {
         hipLaunchKernelGGL(k_tapply_wfq_f32_grouped, dim3((unsigned)impl->sk.G), dim3(Q32_THREADS), 0, st, impl->d_gc,
-                           X, Y, partial, impl->ldx, impl->sk);
+                           X, Y, partial, impl->ldx, impl->sk, stop);
         hipLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * impl->n32q)), dim3(256), 0, st, partial, Y, impl->ldx,
-                           impl->sk, impl->d_gc);
+                           impl->sk, impl->d_gc, stop);
     }
     if (impl->n32d > 0)
         hipLaunchKernelGGL(k_tapply_wfqfmu_f32_grouped, dim3(impl->n32d), dim3(256), 0, st, impl->d_gc, impl->d_t32d,
-                           X, Y, impl->ldx);
+                           X, Y, impl->ldx, stop);
 }
 
-void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st) const
+void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st, const int32_t* stop) const
 {
     if (impl->n64q > 0)
         hipLaunchKernelGGL(k_tapply_wfq_f64_grouped, dim3(impl->n64q), dim3(256), 0, st, impl->d_gc, impl->d_t64q, X, Y,
-                           impl->ldx);
+                           impl->ldx, stop);
     if (impl->n64d > 0)
         hipLaunchKernelGGL(k_tapply_wfqfmu_f64_grouped, dim3(impl->n64d), dim3(256), 0, st, impl->d_gc, impl->d_t64d,
-                           X, Y, impl->ldx);
+                           X, Y, impl->ldx, stop);
 }
 
 }  // namespace px
