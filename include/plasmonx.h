@@ -112,6 +112,12 @@ typedef struct {
  *                    into the next step (one dot and one update pass over the
  *                    basis per step), or PX_ORTHO_CGS2, both passes in the
  *                    same step (two of each)
+ *   graph_steps      pxSolveBatch and the server with PX_ORTHO_DCGS2: the
+ *                    Arnoldi steps of a cycle are captured into HIP graphs of
+ *                    this many steps, once per block layout and restart
+ *                    length, and replayed; 0 launches every kernel directly.
+ *                    In [0, 64] (8).  pxSolveSpectrum ignores it (its block
+ *                    layout changes at nearly every restart as columns retire).
  */
 typedef struct {
     int32_t precision;
@@ -125,6 +131,7 @@ typedef struct {
     int32_t max_restart_m;
     int32_t block_cols;
     int32_t ortho;
+    int32_t graph_steps;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;

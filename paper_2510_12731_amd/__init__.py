@@ -45,7 +45,8 @@ class pxSolveOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("restart_m", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
                 ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
-                ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("ortho", ctypes.c_int32)]
+                ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("ortho", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -234,7 +235,7 @@ def pxLastError():
 
 def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
                   inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
-                  ortho=None):
+                  ortho=None, graph_steps=None):
     o = pxDefaultSolveOptions()
     o.precision = int(precision)
     o.restart_m = int(restart_m)
@@ -248,6 +249,8 @@ def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400
     o.block_cols = int(block_cols)
     if ortho is not None:
         o.ortho = int(ortho)
+    if graph_steps is not None:
+        o.graph_steps = int(graph_steps)
     return o
 
 

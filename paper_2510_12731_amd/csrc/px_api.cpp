@@ -391,7 +391,7 @@ pxStatus check_options(const pxSolveOptions& o)
         return fail(PX_E_INVALID, "restart_m and max_restart_m must be in [1, 1000]");
     if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
-        (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) ||
+        (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) || o.graph_steps < 0 || o.graph_steps > 64 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -457,6 +457,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->max_restart_m = 200;
     o->block_cols = 0;
     o->ortho = PX_ORTHO_DCGS2;
+    o->graph_steps = 8;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }

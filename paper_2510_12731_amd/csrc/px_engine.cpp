@@ -59,8 +59,12 @@ size_t Engine::bytes_per_row(int Bc, int m_max)
 }
 
 Engine::Engine(hipStream_t st, int Bc, const pxSolveOptions& o, int64_t rows_cap, int nseg_cap)
-    : st_(st), Bc_(Bc), o_(o), rows_cap_(rows_cap), nseg_cap_(nseg_cap)
+    : caller_(st), Bc_(Bc), o_(o), rows_cap_(rows_cap), nseg_cap_(nseg_cap)
 {
+    // the engine's own stream (default priority, non-blocking so that it can be
+    // captured into graphs), ordered after the caller's stream at every cycle
+    HC(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    HC(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
     m_max_ = std::max(o.restart_m, o.max_restart_m);
     m_ = o.restart_m;
     sync_.ensure(m_max_ + 1);
@@ -108,10 +112,14 @@ Engine::Engine(hipStream_t st, int Bc, const pxSolveOptions& o, int64_t rows_cap
 
 Engine::~Engine()
 {
+    (void)hipStreamSynchronize(st_);
+    drop_graphs();
     void* ps[] = {V_, w_, xs_, rs_, bs_, xs2_, bs2_, X32_, Y32_, Y64_, partial_, npart_, h1_, h2_, R_, H_, G_,
                   coefQ_, coefV_, aux_, sn_, gv_, y_,
                   cs_, nrm_, target_, done_, steps_, zq_, zmu_, seginfo_, chunk_seg_, beg256_, beg32_, split_};
     for (void* p : ps) dfree(p);
+    (void)hipEventDestroy(ev_in_);
+    (void)hipStreamDestroy(st_);
 }
 
 int Engine::segments_for(const pxStructure_t* s) const { return (s->ncol + Bc_ - 1) / Bc_; }
@@ -142,6 +150,7 @@ void Engine::admit(pxStructure_t* s)
 
 void Engine::layout()
 {
+    drop_graphs();   // captured launches hold this layout's sizes and pointers
     // new row offsets; copy surviving segments' x and b, gather fresh ones from their structure
     int64_t off = 0;
     for (EngineSeg& e : segs_) {
@@ -212,10 +221,82 @@ void Engine::px_launch_gather(const double2* src, int lds, int col0, int ncols, 
                        rows);
 }
 
+void Engine::drop_graphs()
+{
+    for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+    graphs_.clear();
+}
+
+// Steps k0 .. k1-1 of a cycle of restart length m (delayed orthogonalisation,
+// stop flag): the launch sequence that is captured into a graph.
+void Engine::enqueue_steps(int k0, int k1, int m, int32_t* stop)
+{
+    const int nseg = (int)segs_.size();
+    const int ldf = nseg * Bc_;
+    const bool mixed = o_.precision == PX_MIXED;
+    const int64_t rows = rows_;
+    const int64_t vstride = rows * Bc_;
+    for (int k = k0; k < k1; ++k) {
+        double2* vk = V_ + k * vstride;
+        if (mixed)
+            gt_.run_f32(X32_, Y32_, split_, st_, stop);
+        else
+            gt_.run_f64(reinterpret_cast<const double*>(vk), Y64_, st_, stop);
+        px::spmm_seg(seginfo_, chunk_seg_, mixed ? (const void*)Y32_ : (const void*)Y64_, mixed, 2 * Bc_, vk, zq_,
+                     zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_, stop);
+        px::dots2(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_, stop);
+        px::reduce_dots2(partial_, rows, k + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
+        px::dcgs2_coef(k, m, false, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_, ldf,
+                       ldf, st_, stop);
+        px::dcgs2_update(V_, vstride, k, coefQ_, coefV_, w_, npart_, Bc_, Bc_, rows, st_, chunk_seg_, ldf, stop);
+        px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_, stop);
+        px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows, st_,
+                          stop);
+        if (k == m - 1) {
+            // the last basis vector's correction finishes column m-1
+            px::dots2(V_, vstride, m + 1, V_ + m * vstride, partial_, Bc_, Bc_, rows, st_, stop);
+            px::reduce_dots2(partial_, rows, m + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
+            px::dcgs2_coef(m, m, true, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
+                           ldf, ldf, st_, stop);
+        }
+    }
+}
+
+// Launches steps k0 .. k1-1 as a graph, capturing it on first use; the graph
+// reads everything a cycle changes (targets, g, flags, shifts) from device
+// memory, so it stays valid until the layout or the restart length changes.
+void Engine::launch_steps_graph(int k0, int k1, int m, int32_t* stop)
+{
+    const int64_t key = ((int64_t)m << 20) | ((int64_t)k0 << 10) | (int64_t)(k1 - k0);
+    auto it = graphs_.find(key);
+    if (it == graphs_.end()) {
+        hipGraph_t g = nullptr;
+        HC(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_steps(k0, k1, m, stop);
+        } catch (...) {
+            (void)hipStreamEndCapture(st_, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        HC(hipStreamEndCapture(st_, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HC(e);
+        it = graphs_.emplace(key, ex).first;
+        stats_.graphs += 1;
+    }
+    HC(hipGraphLaunch(it->second, st_));
+}
+
 std::vector<pxStructure_t*> Engine::cycle()
 {
     std::vector<pxStructure_t*> finished;
     if (segs_.empty()) return finished;
+    // work the caller queued on its stream (frequencies, x, b) comes first
+    HC(hipEventRecord(ev_in_, caller_));
+    HC(hipStreamWaitEvent(st_, ev_in_, 0));
     if (dirty_) layout();
     const int nseg = (int)segs_.size();
     const int ldf = nseg * Bc_;
@@ -298,48 +379,36 @@ std::vector<pxStructure_t*> Engine::cycle()
     HC(hipMemcpyAsync(nrm_, beta.data(), sizeof(double) * ldf, hipMemcpyHostToDevice, st_));
     px::normalize_seg(rs_, nrm_, done_, chunk_seg_, V_, mixed ? X32_ : nullptr, Bc_, rows, st_);
     std::vector<int32_t> done_h(ldf);
-    // delayed orthogonalisation: steps run ahead of the host, a device flag ends them
-    int32_t* stop = dcgs2 ? sync_.flag() : nullptr;
-    if (stop) sync_.reset(st_);
-    for (int k = 0; k < m; ++k) {
-        if (stop && k >= kLag && sync_.stopped(k - kLag)) break;
-        double2* vk = V_ + k * vstride;
-        if (mixed) {
-            gt_.run_f32(X32_, Y32_, split_, st_, stop);
-        } else {
-            gt_.run_f64(reinterpret_cast<const double*>(vk), Y64_, st_, stop);
+    if (dcgs2) {
+        // steps run ahead of the host; a device flag, raised once the rotations have
+        // finished every column, turns the remaining launches into no-ops
+        int32_t* stop = sync_.flag();
+        sync_.reset(st_);
+        const int chunk = o_.graph_steps > 0 ? o_.graph_steps : 1;
+        for (int k0 = 0, j = 0; k0 < m; k0 += chunk, ++j) {
+            if (j >= kLag && sync_.stopped(j - kLag)) break;
+            const int k1 = std::min(m, k0 + chunk);
+            if (o_.graph_steps > 0) launch_steps_graph(k0, k1, m, stop);
+            else enqueue_steps(k0, k1, m, stop);
+            sync_.publish(j, st_);
         }
-        px::spmm_seg(seginfo_, chunk_seg_, mixed ? (const void*)Y32_ : (const void*)Y64_, mixed, 2 * Bc_, vk, zq_,
-                     zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_, stop);
-        if (dcgs2) {
-            px::dots2(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_, stop);
-            px::reduce_dots2(partial_, rows, k + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
-            px::dcgs2_coef(k, m, false, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
-                           ldf, ldf, st_, stop);
-            px::dcgs2_update(V_, vstride, k, coefQ_, coefV_, w_, npart_, Bc_, Bc_, rows, st_, chunk_seg_, ldf, stop);
-        } else {
+    } else {
+        for (int k = 0; k < m; ++k) {
+            double2* vk = V_ + k * vstride;
+            if (mixed) gt_.run_f32(X32_, Y32_, split_, st_);
+            else gt_.run_f64(reinterpret_cast<const double*>(vk), Y64_, st_);
+            px::spmm_seg(seginfo_, chunk_seg_, mixed ? (const void*)Y32_ : (const void*)Y64_, mixed, 2 * Bc_, vk, zq_,
+                         zmu_, nullptr, w_, rows, Bc_, nseg, SOLVER_MU_SIGN, st_);
             px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
             px::reduce_dots_seg(partial_, beg256_, k + 1, h1_, nseg, Bc_, st_);
             px::col_update_seg(V_, vstride, k + 1, h1_, w_, nullptr, chunk_seg_, Bc_, nseg, rows, st_);
             px::col_dots(V_, vstride, k + 1, w_, partial_, Bc_, Bc_, rows, st_);
             px::reduce_dots_seg(partial_, beg256_, k + 1, h2_, nseg, Bc_, st_);
             px::col_update_seg(V_, vstride, k + 1, h2_, w_, npart_, chunk_seg_, Bc_, nseg, rows, st_);
-        }
-        px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_, stop);
-        if (!dcgs2)
+            px::reduce_norms_seg(npart_, beg32_, nrm_, nseg, Bc_, st_);
             px::givens_step(k, m, h1_, h2_, nrm_, R_, cs_, sn_, gv_, target_, done_, steps_, nullptr, ldf, ldf, st_);
-        px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows, st_,
-                          stop);
-        if (dcgs2 && k == m - 1) {
-            // the last basis vector's correction finishes column m-1
-            px::dots2(V_, vstride, m + 1, V_ + m * vstride, partial_, Bc_, Bc_, rows, st_, stop);
-            px::reduce_dots2(partial_, rows, m + 1, G_, Bc_, Bc_, st_, beg256_, nseg, stop);
-            px::dcgs2_coef(m, m, true, G_, nrm_, H_, R_, cs_, sn_, gv_, target_, done_, steps_, aux_, coefQ_, coefV_,
-                           ldf, ldf, st_, stop);
-        }
-        if (stop) {
-            sync_.publish(k, st_);
-        } else {
+            px::normalize_seg(w_, nrm_, done_, chunk_seg_, V_ + (k + 1) * vstride, mixed ? X32_ : nullptr, Bc_, rows,
+                              st_);
             HC(hipMemcpyAsync(done_h.data(), done_, sizeof(int32_t) * ldf, hipMemcpyDeviceToHost, st_));
             HC(hipStreamSynchronize(st_));
             stats_.steps += 1;

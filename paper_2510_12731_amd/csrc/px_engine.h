@@ -18,7 +18,7 @@ struct EngineSeg {
 };
 
 struct EngineStats {
-    int64_t cycles = 0, steps = 0, residuals = 0, tapply_f32 = 0, tapply_f64 = 0;
+    int64_t cycles = 0, steps = 0, residuals = 0, tapply_f32 = 0, tapply_f64 = 0, graphs = 0;
 };
 
 class Engine {
@@ -47,9 +47,15 @@ class Engine {
 
   private:
     void layout();
+    void drop_graphs();
+    void enqueue_steps(int k0, int k1, int m, int32_t* stop);
+    void launch_steps_graph(int k0, int k1, int m, int32_t* stop);
     void px_launch_gather(const double2* src, int lds, int col0, int ncols, double2* dst, int64_t rows);
 
-    hipStream_t st_;
+    hipStream_t caller_;           // the stream the structures and the caller use
+    hipStream_t st_ = nullptr;     // the engine's own stream
+    hipEvent_t ev_in_ = nullptr;
+    std::map<int64_t, hipGraphExec_t> graphs_;   // captured step chunks of the current layout
     int Bc_;
     pxSolveOptions o_;
     int m_max_ = 0, m_ = 0;

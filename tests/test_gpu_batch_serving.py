@@ -94,6 +94,32 @@ def test_batch_fp64_matches_oracle_tightly():
     assert st == px.PX_OK
 
 
+def test_batch_graph_replays_match_eager_launches():
+    """The batched engine captures chunks of Arnoldi steps into HIP graphs and
+    replays them in every restart cycle, with the residual, admission and
+    bookkeeping work done eagerly in between.  Every replay must give what the
+    same launches give eagerly: the spectra of a many-cycle batch solved with
+    graphs (chunks of 3 and 8 steps) and without must agree to rounding."""
+    cs = cases()
+    ref = None
+    for gs in (0, 3, 8):
+        batch = [make(c) for c in cs]
+        st = px.solve_batch(batch, precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64, restart_m=20,
+                            max_restart_m=40, graph_steps=gs)
+        assert st == px.PX_OK
+        sig = [s.spectrum()[1] for s in batch]
+        cyc = max(int(s.stats()[1].max()) for s in batch)
+        if ref is None:
+            ref = sig
+            say(f"[graphs] eager: {cyc} cycles")
+        else:
+            e = max(rel_err(a, b) for a, b in zip(sig, ref))
+            say(f"[graphs] chunks of {gs} steps: {cyc} cycles, vs eager {e:.1e}")
+            assert cyc >= 3 and e <= 1e-12
+        for s in batch:
+            s.close()
+
+
 def test_server_alone_vs_mix_and_admission():
     cs = cases()
     # rows: graphene 2 x 768, sphere 512, rod 4 x 256; a budget of ~2600 rows
