@@ -46,18 +46,44 @@ def ensure_built():
     return px.load()
 
 
-def one_step(px, case, precision, timings, max_block_cols=0, cols=None):
+def one_step(px, case, precision, timings, max_block_cols=0, t_apply=None):
     om = case["omega_ev"]
     s = px.Structure(case["model"], case["xyz"], case["params"], px.default_stream())
     pol = case["pol_mask"]
     s.set_frequencies(om, pol, case["e0"], case["alpha_ib"])
-    st = s.solve(precision=precision, restart_m=50, rel_tol=1e-8, max_block_cols=max_block_cols, timings=timings)
+    st = s.solve(precision=precision, restart_m=50, rel_tol=1e-8, max_block_cols=max_block_cols, timings=timings,
+                 t_apply=t_apply)
     alpha, sigma = s.spectrum()
     it, cyc, rr = s.stats()
     tm = s.timings()
     wk = s.work()
+    ta = s.tapply_stats()
     s.close()
-    return dict(status=st, sigma=sigma, alpha=alpha, iters=it, cycles=cyc, relres=rr, timings=tm, work=wk)
+    return dict(status=st, sigma=sigma, alpha=alpha, iters=it, cycles=cyc, relres=rr, timings=tm, work=wk, tapply=ta)
+
+
+def tapply_roofline(runs, n, traffic, traffic_cols):
+    """Roofline of the FP32 T-apply method that took the most time in these
+    runs: algorithmic FLOP (2 N^2 per real column still iterating) over the
+    HIP-event time of that method's launches, against the FP32 matrix peak."""
+    keys = ("f32_on_the_fly", "f32_stored")
+    ms = {k: sum(r["tapply"]["ms_" + k] for r in runs) for k in keys}
+    dom = max(keys, key=lambda k: ms[k])
+    fl = sum(r["tapply"]["flop_" + dom] for r in runs)
+    nl = sum(r["tapply"][dom] for r in runs)
+    achieved = fl / (ms[dom] * 1e-3) / 1e12 if ms[dom] > 0 else 0.0
+    fly = dom == "f32_on_the_fly"
+    return dict(bound="mfma", achieved=round(achieved, 2), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                traffic=traffic if fly else None,
+                traffic_note=(f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
+                              f"algorithmic {2 * 4 * n * traffic_cols} B" if fly and traffic is not None else None),
+                kernel=("k_tapply_wfq_f32 (+ k_sk_fixup), T generated on the fly" if fly else
+                        "rocBLAS sgemm on the stored T (autotuner's choice for this width)"),
+                launches=int(nl), avg_launch_ms=round(ms[dom] / max(nl, 1), 4),
+                avg_algorithmic_gflop_per_launch=round(fl / max(nl, 1) / 1e9, 2),
+                method_ms={k: round(v, 1) for k, v in ms.items()},
+                method_launches={k: int(sum(r["tapply"][k] for r in runs)) for k in keys})
 
 
 def measured_traffic(kernel_src, summary):
@@ -197,6 +223,12 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
     for a, r in zip(arrivals, seq):
         t = max(t, a) + r["seconds"]
         lat_seq.append(t - a)
+    # the plain FP64 solver one request at a time, same arrivals, FIFO
+    seq64 = sequential_run(pxm, cases, pxm.PX_FP64)
+    t64, lat64 = 0.0, []
+    for a, r in zip(arrivals, seq64):
+        t64 = max(t64, a) + r["seconds"]
+        lat64.append(t64 - a)
     budget = 0.5 * torch_free_bytes()
     srv = serving_run(pxm, cases, arrivals, budget, block_cols)
     err = max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"]))) for a, b in zip(srv["sigma"], seq))
@@ -204,9 +236,14 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
     return dict(requests=n_req, columns=cols, n_range=[n_min, n_max], arrival_rate_per_s=round(lam, 3),
                 load=load, solves_per_s=round(cols / srv["makespan"], 2),
                 p50_s=round(float(np.percentile(lat, 50)), 3), p99_s=round(float(np.percentile(lat, 99)), 3),
-                one_at_a_time_solves_per_s=round(cols / max(t, 1e-9), 2),
-                one_at_a_time_p50_s=round(float(np.percentile(lat_seq, 50)), 3),
-                one_at_a_time_p99_s=round(float(np.percentile(lat_seq, 99)), 3),
+                mixed_one_at_a_time_solves_per_s=round(cols / max(t, 1e-9), 2),
+                mixed_one_at_a_time_p50_s=round(float(np.percentile(lat_seq, 50)), 3),
+                mixed_one_at_a_time_p99_s=round(float(np.percentile(lat_seq, 99)), 3),
+                fp64_one_at_a_time_solves_per_s=round(cols / max(t64, 1e-9), 2),
+                fp64_one_at_a_time_p50_s=round(float(np.percentile(lat64, 50)), 3),
+                fp64_one_at_a_time_p99_s=round(float(np.percentile(lat64, 99)), 3),
+                sigma_rel_err_mix_vs_fp64=max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"])))
+                                              for a, b in zip(srv["sigma"], seq64)),
                 peak_rows=srv["peak_rows"], rows_capacity=srv["rows_capacity"],
                 sigma_rel_err_mix_vs_alone=err)
 
@@ -229,7 +266,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lu-steps", type=int, default=4)
     ap.add_argument("--kernel-sample", action="store_true",
-                    help="one restart cycle of 4 steps on the full workload (hardware-counter runs)")
+                    help="one restart cycle of 4 steps on the full workload, T on the fly (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
     ap.add_argument("--workload", default="sphere",
@@ -237,6 +274,7 @@ def main():
                     help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
                          "serving mix, printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
+    ap.add_argument("--no-on-the-fly", action="store_true", help="skip the on-the-fly-only comparison step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box here has a single MI355X and the solver does not shard; "
@@ -285,7 +323,8 @@ def main():
     if args.kernel_sample:
         s = pxm.Structure(case["model"], case["xyz"], case["params"], pxm.default_stream())
         s.set_frequencies(case["omega_ev"], case["pol_mask"], case["e0"])
-        st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True)
+        st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True,
+                     t_apply=pxm.PX_TAPPLY_ON_THE_FLY)
         tm = s.timings()
         s.close()
         print(json.dumps({"kernel_sample": True, "status": int(st), "tapply_f32_launches": int(tm["n_tapply_f32"]),
@@ -314,22 +353,10 @@ def main():
     tm = last["timings"]
     n = len(case["xyz"])
 
-    # roofline of the FP32 T-apply (MFMA): algorithmic 4 N^2 FLOP per complex column
-    n_launch = sum(r["timings"]["n_tapply_f32"] for r in runs)
-    cols = sum(r["timings"]["cols_f32"] for r in runs)            # real columns, no padding
-    ms_t = sum(r["timings"]["ms_tapply_f32"] for r in runs)
-    flops = 2.0 * n * n * cols
-    achieved = flops / (ms_t * 1e-3) / 1e12 if ms_t > 0 else 0.0
+    # roofline of the dominant FP32 T-apply method (MFMA)
     traffic, traffic_cols = measured_traffic("paper_2510_12731_amd/csrc/px_tapply.hip",
                                              "tapply_f32_sphere20k_hbm_counters.md")
-    roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), traffic=traffic,
-                traffic_note=(None if traffic is None else
-                              f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
-                              f"algorithmic {2 * 4 * len(case['xyz']) * traffic_cols} B"),
-                kernel="k_tapply_wfq_f32 (+ k_sk_fixup)", launches=int(n_launch),
-                avg_launch_ms=round(ms_t / max(n_launch, 1), 4),
-                avg_algorithmic_gflop_per_launch=round(flops / max(n_launch, 1) / 1e9, 2))
+    roof = tapply_roofline(runs, n, traffic, traffic_cols)
 
     # path roofline: the ideal time of the solve's algorithmic work at the
     # peaks (FP32 and FP64 matrix, HBM) over its measured wall time
@@ -351,6 +378,18 @@ def main():
                       spmm=round(tm["ms_spmm"], 1), arnoldi_givens=round(tm["ms_arnoldi"], 1),
                       rest=round(tm["ms_other"], 1)))
 
+    # the same step with T generated on the fly only (hand-written kernels throughout)
+    if not args.no_on_the_fly:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r_otf = one_step(pxm, case, pxm.PX_MIXED, True, t_apply=pxm.PX_TAPPLY_ON_THE_FLY)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        extra["on_the_fly_only"] = dict(value=round(ncol / (tb - ta), 3), unit="freq-solves/s",
+                                        seconds=round(tb - ta, 2), status=int(r_otf["status"]),
+                                        roofline=tapply_roofline([r_otf], n, traffic, traffic_cols))
+    extra["tapply_launches"] = {k: int(v) for k, v in last["tapply"].items() if not k.startswith(("ms_", "flop_"))}
+
     # plain FP64 solver, one column at a time, on a sample of the columns
     if args.fp64_sample > 0:
         idx = np.linspace(0, len(case["omega_ev"]) - 1, args.fp64_sample).round().astype(int)
@@ -359,12 +398,13 @@ def main():
         sub["pol_mask"] = 0b001
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        r64 = one_step(pxm, sub, pxm.PX_FP64, False, max_block_cols=1)
+        r64 = one_step(pxm, sub, pxm.PX_FP64, False, max_block_cols=1, t_apply=pxm.PX_TAPPLY_ON_THE_FLY)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         v64 = len(idx) / (tb - ta)
         extra["fp64_one_column"] = dict(value=round(v64, 4), unit="freq-solves/s",
-                                        sample=f"{len(idx)} x-polarized columns spread over the grid",
+                                        sample=f"{len(idx)} x-polarized columns spread over the grid; "
+                                               "hand-written FP64 kernels (T on the fly)",
                                         iterations=r64["iters"].tolist(), seconds=round(tb - ta, 2))
         extra["speedup_vs_fp64_one_column"] = round(value / v64, 2)
         sig_ref = r64["sigma"]

@@ -54,6 +54,12 @@ typedef enum {
 } pxPrecision;
 
 typedef enum {
+    PX_TAPPLY_AUTO = 0,        /* the autotuner times both methods per shape and keeps the faster */
+    PX_TAPPLY_ON_THE_FLY = 1,  /* T generated in registers by the hand-written kernels */
+    PX_TAPPLY_STORED = 2       /* dense T stored once per structure, one GEMM per apply */
+} pxTApply;
+
+typedef enum {
     PX_ORTHO_CGS2 = 0,   /* classical Gram-Schmidt, two passes per Arnoldi step */
     PX_ORTHO_DCGS2 = 1   /* the second pass delayed into the next step */
 } pxOrtho;
@@ -118,6 +124,16 @@ typedef struct {
  *                    length, and replayed; 0 launches every kernel directly.
  *                    In [0, 64] (8).  pxSolveSpectrum ignores it (its block
  *                    layout changes at nearly every restart as columns retire).
+ *   t_apply          how pxSolveSpectrum applies T in its cycles and true
+ *                    residuals: PX_TAPPLY_AUTO (default) times, on the
+ *                    structure itself, the on-the-fly kernels and a GEMM
+ *                    (rocBLAS) on T stored densely (N_u^2 x 4 B in FP32,
+ *                    x 8 B in FP64, only when that fits a quarter of the free
+ *                    device memory) the first time a (model, atoms, columns,
+ *                    precision) shape occurs in the process, and keeps the
+ *                    faster; PX_TAPPLY_ON_THE_FLY / PX_TAPPLY_STORED force one
+ *                    (STORED fails with PX_E_OOM if T does not fit).
+ *                    pxSolveBatch and the server always generate T on the fly.
  */
 typedef struct {
     int32_t precision;
@@ -132,6 +148,7 @@ typedef struct {
     int32_t block_cols;
     int32_t ortho;
     int32_t graph_steps;
+    int32_t t_apply;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;
@@ -257,6 +274,15 @@ pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6);
  * (steps + 2)).  N_u = unknowns (atoms, or 4 x atoms for PX_WFQFMU).
  * Dividing each by its peak gives the ideal time of the solve. */
 pxStatus pxGetWork(pxStructure s, double* work3);
+
+/* T-apply of the last pxSolveSpectrum by method (autotuner or options):
+ * launches4 (may be NULL) [0] FP32 on the fly, [1] FP32 stored T, [2] FP64 on
+ * the fly, [3] FP64 stored T (cycles and true residuals); ms4 (may be NULL)
+ * the HIP-event milliseconds of the same launches inside cycles (zeros unless
+ * options.timings = 1; true residuals are not timed); flop4 (may be NULL)
+ * their algorithmic FLOP inside cycles (2 N_u^2 per real column of a column
+ * that was still iterating). */
+pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double* flop4);
 
 void pxDestroyStructure(pxStructure s);
 

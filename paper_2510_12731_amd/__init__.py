@@ -21,10 +21,11 @@ PX_OK, PX_E_INVALID, PX_E_OOM, PX_E_NOTCONV, PX_E_DEVICE, PX_E_STATE = range(6)
 PX_WFQ, PX_WFQFMU = 0, 1
 PX_FP64, PX_MIXED = 0, 1
 PX_ORTHO_CGS2, PX_ORTHO_DCGS2 = 0, 1
+PX_TAPPLY_AUTO, PX_TAPPLY_ON_THE_FLY, PX_TAPPLY_STORED = 0, 1, 2
 STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV", 4: "PX_E_DEVICE", 5: "PX_E_STATE"}
 
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
-            "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork",
+            "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy"]
 
@@ -46,7 +47,7 @@ class pxSolveOptions(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
                 ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
                 ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("ortho", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("t_apply", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH):
     lib.pxGetSize.argtypes = [_vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.pxGetTimings.argtypes = [_vp, _dp, ctypes.POINTER(i64)]
     lib.pxGetWork.argtypes = [_vp, _dp]
+    lib.pxGetTApplyStats.argtypes = [_vp, ctypes.POINTER(i64), _dp, _dp]
     lib.pxServerCreate.argtypes = [ctypes.c_double, ctypes.POINTER(pxSolveOptions), _vp, ctypes.POINTER(_vp)]
     lib.pxServerSubmit.argtypes = [_vp, _vp]
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
@@ -215,6 +217,19 @@ def pxGetWork(h):
     return dict(flop_f32=float(w[0]), flop_f64=float(w[1]), hbm_bytes=float(w[2]))
 
 
+def pxGetTApplyStats(h):
+    """T-apply launches (and their timed milliseconds) of the last solve by method."""
+    st = (ctypes.c_int64 * 4)()
+    ms = np.zeros(4)
+    fl = np.zeros(4)
+    _check(load().pxGetTApplyStats(h, st, _ptr(ms), _ptr(fl)))
+    names = ("f32_on_the_fly", "f32_stored", "f64_on_the_fly", "f64_stored")
+    out = {nm: int(st[k]) for k, nm in enumerate(names)}
+    out.update({"ms_" + nm: float(ms[k]) for k, nm in enumerate(names)})
+    out.update({"flop_" + nm: float(fl[k]) for k, nm in enumerate(names)})
+    return out
+
+
 def pxGetTimings(h):
     ms = np.zeros(6)
     cnt = (ctypes.c_int64 * 6)()
@@ -235,7 +250,7 @@ def pxLastError():
 
 def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
                   inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
-                  ortho=None, graph_steps=None):
+                  ortho=None, graph_steps=None, t_apply=None):
     o = pxDefaultSolveOptions()
     o.precision = int(precision)
     o.restart_m = int(restart_m)
@@ -251,6 +266,8 @@ def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400
         o.ortho = int(ortho)
     if graph_steps is not None:
         o.graph_steps = int(graph_steps)
+    if t_apply is not None:
+        o.t_apply = int(t_apply)
     return o
 
 
@@ -354,6 +371,9 @@ class Structure:
 
     def work(self):
         return pxGetWork(self.h)
+
+    def tapply_stats(self):
+        return pxGetTApplyStats(self.h)
 
     def close(self):
         if self.h is not None:

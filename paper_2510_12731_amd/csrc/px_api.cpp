@@ -15,8 +15,12 @@
 #include "px_engine.h"
 
 #include <deque>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -56,6 +60,11 @@ void shift_mu(double ar, double ai, double& zr, double& zi)
     const double den = ar * ar + ai * ai;
     zr = -ar / den;
     zi = ai / den;
+}
+
+void release_blas(void* handle)
+{
+    if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
 void prepare_solve(pxStructure_t* s)
@@ -158,12 +167,146 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
 
 
 
-// r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
-void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda)
+// ---- T-apply method: on-the-fly kernels or the stored T with one GEMM --------
+// The autotuner times both on the structure itself (after one warm-up launch
+// each) the first time a (model, atoms, columns, precision) shape is applied
+// and keeps the faster for the rest of the process.  The stored T costs
+// nup^2 x 4 (FP32) or 8 (FP64) bytes and is only tried when that fits in a
+// quarter of the free device memory.
+enum { TA_FLY = 1, TA_STORED = 2 };
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int, int>, int> g_tune;
+
+rocblas_handle blas_of(pxStructure_t* s)
+{
+    if (!s->blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas_create_handle"};
+        s->blas = h;
+    }
+    rocblas_handle h = static_cast<rocblas_handle>(s->blas);
+    if (rocblas_set_stream(h, s->st) != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas_set_stream"};
+    return h;
+}
+
+bool stored_fits(pxStructure_t* s, bool f32)
+{
+    if ((f32 ? (void*)s->t32 : (void*)s->t64) != nullptr) return true;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    const double bytes = (double)s->g.nup * (double)s->g.nup * (f32 ? 4.0 : 8.0);
+    return bytes <= 0.25 * (double)fr;
+}
+
+void ensure_stored(pxStructure_t* s, bool f32)
+{
+    const size_t n2 = (size_t)s->g.nup * (size_t)s->g.nup;
+    if (f32 && !s->t32) {
+        s->t32 = dalloc<float>(n2);
+        px::tdense_f32(s->g, s->t32, s->st);
+    }
+    if (!f32 && !s->t64) {
+        s->t64 = dalloc<double>(n2);
+        px::tdense_f64(s->g, s->t64, s->st);
+    }
+}
+
+// Y = T X with X, Y row-major [nup][ldx]: as column-major matrices this is
+// Y^T = X^T T^T, one GEMM with T's row-major buffer as the second operand.
+void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols)
+{
+    rocblas_handle h = blas_of(s);
+    const rocblas_int m = ncols, n = (rocblas_int)s->g.nup;
+    rocblas_status e;
+    if (f32) {
+        const float one = 1.f, zero = 0.f;
+        e = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, n, &one,
+                          static_cast<const float*>(X), ldx, s->t32, n, &zero, static_cast<float*>(Y), ldx);
+    } else {
+        const double one = 1.0, zero = 0.0;
+        e = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, n, &one,
+                          static_cast<const double*>(X), ldx, s->t64, n, &zero, static_cast<double*>(Y), ldx);
+    }
+    if (e != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas gemm"};
+}
+
+void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop)
 {
     Workspace& W = s->ws;
-    px::tapply_f64(s->g, reinterpret_cast<const double*>(xs), W.Y64, 2 * lda, 2 * lda, s->st, W.narrow,
-                   W.narrow_bytes);
+    if (f32)
+        px::tapply_f32(s->g, static_cast<const float*>(X), static_cast<float*>(Y), ldx, ncols, s->st, W.split32,
+                       stop);
+    else
+        px::tapply_f64(s->g, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st, W.narrow,
+                       W.narrow_bytes, stop);
+}
+
+float time_apply(pxStructure_t* s, bool f32, int method, const void* X, void* Y, int ldx, int ncols)
+{
+    hipEvent_t a, b;
+    HC(hipEventCreate(&a));
+    HC(hipEventCreate(&b));
+    auto run = [&]() {
+        if (method == TA_STORED) apply_stored(s, f32, X, Y, ldx, ncols);
+        else apply_fly(s, f32, X, Y, ldx, ncols, nullptr);
+    };
+    run();   // warm-up
+    HC(hipEventRecord(a, s->st));
+    run();
+    run();
+    HC(hipEventRecord(b, s->st));
+    HC(hipEventSynchronize(b));
+    float ms = 0.f;
+    HC(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+// The method for this shape: forced by the options, else the tuner's choice.
+int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const pxSolveOptions& o)
+{
+    if (o.t_apply == PX_TAPPLY_ON_THE_FLY) return TA_FLY;
+    if (o.t_apply == PX_TAPPLY_STORED) {
+        ensure_stored(s, f32);
+        return TA_STORED;
+    }
+    const auto key = std::make_tuple((int)s->g.model, (int64_t)s->g.n, ncols, f32 ? 32 : 64);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            if (it->second == TA_STORED) {
+                if (!stored_fits(s, f32)) return TA_FLY;
+                ensure_stored(s, f32);
+            }
+            return it->second;
+        }
+    }
+    if (!stored_fits(s, f32)) return TA_FLY;
+    ensure_stored(s, f32);
+    const float t_fly = time_apply(s, f32, TA_FLY, X, Y, ldx, ncols);
+    const float t_st = time_apply(s, f32, TA_STORED, X, Y, ldx, ncols);
+    const int m = t_st < t_fly ? TA_STORED : TA_FLY;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = m;
+    return m;
+}
+
+void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop)
+{
+    if (method == TA_STORED) apply_stored(s, f32, X, Y, ldx, ncols);
+    else apply_fly(s, f32, X, Y, ldx, ncols, stop);
+}
+
+// r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
+void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda,
+              const pxSolveOptions& o)
+{
+    Workspace& W = s->ws;
+    const int method = tapply_method(s, false, xs, W.Y64, 2 * lda, 2 * lda, o);
+    tapply(s, method, false, xs, W.Y64, 2 * lda, 2 * lda, nullptr);
+    s->tstats[method == TA_STORED ? 3 : 2] += 1;
     s->counts[3] += 1;
     s->counts[4] += 2 * lda;
     s->counts[5] += 2 * na;
@@ -228,7 +371,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
     upload_shifts(s, act, lda);
 
     while (true) {
-        residual(s, W.xs, W.bs, W.rs, na, lda);
+        residual(s, W.xs, W.bs, W.rs, na, lda, o);
         col_norms(s, W.rs, na, lda, beta);
         std::vector<int> keep;
         bool slow = false;
@@ -292,6 +435,10 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             const int64_t vstride = nup * lda;
             px::normalize(W.rs, W.nrm, nullptr, W.V, mixed ? W.X32 : nullptr, na, lda, nup, s->st);
             const bool wide32 = mixed && lda > 4;
+            const int method = wide32 ? tapply_method(s, true, W.X32, W.Y32, 2 * lda, 2 * lda, o)
+                                      : tapply_method(s, false, W.V, W.Y64, 2 * lda, 2 * lda, o);
+            // a GEMM on the stored T cannot read the stop flag: poll one step behind, not two
+            const int lag = method == TA_STORED ? 1 : kLag;
             // delayed orthogonalisation: the host enqueues steps ahead of the device and a
             // device flag, raised once the rotations have finished every column, ends them
             int32_t* stop = dcgs2 ? s->sync.flag() : nullptr;
@@ -300,14 +447,11 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             int launched = 0;
             done_h.assign(na, 0);
             for (int k = 0; k < m; ++k) {
-                if (stop && k >= kLag && s->sync.stopped(k - kLag)) break;
+                if (stop && k >= lag && s->sync.stopped(k - lag)) break;
                 double2* vk = W.V + k * vstride;
                 tm.mark(k, 0, s->st);
-                if (wide32)
-                    px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32, stop);
-                else
-                    px::tapply_f64(s->g, reinterpret_cast<const double*>(vk), W.Y64, 2 * lda, 2 * lda, s->st,
-                                   W.narrow, W.narrow_bytes, stop);
+                if (wide32) tapply(s, method, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop);
+                else tapply(s, method, false, vk, W.Y64, 2 * lda, 2 * lda, stop);
                 tm.mark(k, 1, s->st);
                 px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
                                W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st, stop);
@@ -361,7 +505,12 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             HC(hipMemcpyAsync(W.map, act.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
             px::scatter_cols(W.xs, lda, s->x, s->ldg, W.map, na, nup, s->st);
             HC(hipStreamSynchronize(s->st));
-            tm.collect(launched, s->ms[wide32 ? 1 : 2], s->ms[3], s->ms[4]);
+            {
+                double t_ap = 0.0;
+                tm.collect(launched, t_ap, s->ms[3], s->ms[4]);
+                s->ms[wide32 ? 1 : 2] += t_ap;
+                s->tms[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += t_ap;
+            }
             // accounting: column q took part in the matvecs of its first M_q steps (the delayed
             // variant learns that a column is done one step after its last useful matvec)
             const double nu = (double)s->g.nu;
@@ -377,10 +526,12 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 s->cycles[act[q]] += 1;
                 s->work[2] += 16.0 * nu * (steps_h[q] + 2);
             }
+            s->tstats[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += executed;
             s->counts[wide32 ? 0 : 3] += executed;
             s->counts[wide32 ? 1 : 4] += (int64_t)executed * 2 * lda;
             s->counts[wide32 ? 2 : 5] += 2 * colsum;
             s->work[wide32 ? 0 : 1] += 2.0 * nu * nu * 2.0 * (double)colsum;
+            s->tflop[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += 2.0 * nu * nu * 2.0 * (double)colsum;
         }
     }
 }
@@ -392,6 +543,7 @@ pxStatus check_options(const pxSolveOptions& o)
     if (!(o.rel_tol > 0.0) || o.max_cycles < 1 || o.max_block_cols < 0 || o.inner_reduction < 0.0 ||
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
         (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) || o.graph_steps < 0 || o.graph_steps > 64 ||
+        (o.t_apply != PX_TAPPLY_AUTO && o.t_apply != PX_TAPPLY_ON_THE_FLY && o.t_apply != PX_TAPPLY_STORED) ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -405,6 +557,9 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     for (double& v : s->ms) v = 0.0;
     for (int64_t& v : s->counts) v = 0;
     for (double& v : s->work) v = 0.0;
+    for (int64_t& v : s->tstats) v = 0;
+    for (double& v : s->tms) v = 0.0;
+    for (double& v : s->tflop) v = 0.0;
     const int ncol = s->ncol;
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
     ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
@@ -458,6 +613,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->block_cols = 0;
     o->ortho = PX_ORTHO_DCGS2;
     o->graph_steps = 8;
+    o->t_apply = PX_TAPPLY_AUTO;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }
@@ -752,6 +908,16 @@ pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns)
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (n_atoms) *n_atoms = s->g.n;
     if (n_unknowns) *n_unknowns = s->g.nu;
+    return PX_OK;
+}
+
+pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double* flop4)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    if (launches4) std::copy(s->tstats, s->tstats + 4, launches4);
+    if (ms4) std::copy(s->tms, s->tms + 4, ms4);
+    if (flop4) std::copy(s->tflop, s->tflop + 4, flop4);
     return PX_OK;
 }
 

@@ -60,6 +60,11 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
                 double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
+// Dense T over the padded unknowns (row-major, nup x nup; ghost rows and
+// columns zero) for the stored-T apply: Y = T X is then one GEMM.
+void tdense_f32(const Geometry& g, float* T, hipStream_t st);
+void tdense_f64(const Geometry& g, double* T, hipStream_t st);
+
 // Grouped T-apply over the segments of a stacked block (each segment one
 // structure's padded rows starting at row_off; real columns ldx, a multiple
 // of 128).  setup() builds and uploads the tile lists; run_* launch one kernel

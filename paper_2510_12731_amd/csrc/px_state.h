@@ -171,6 +171,9 @@ class StepTimer {
     std::vector<hipEvent_t> ev_;
 };
 
+// Destroys a rocBLAS handle made by the stored-T apply (null: nothing).
+void release_blas(void* handle);
+
 // z_q(omega) of Eq. (z_q_wfq) with the Drude weight n/m* (graphene: E_F/(pi t_g)), omega in Hartree
 void shift_q(double drude, double tau, double w, double& zr, double& zi);
 // Eq. (z-mu): z_mu = -1 / alpha_IB
@@ -212,11 +215,21 @@ struct pxStructure_t {
     double work[3] = {0, 0, 0};   // algorithmic FP32 FLOP, FP64 FLOP, HBM bytes of the last solve
     pxs::StepSync sync;           // stop flag of the Arnoldi steps
 
+    // stored-T apply: dense T in FP32 / FP64 (allocated when the tuner or the
+    // options pick it), the rocBLAS handle bound to st, launches per method
+    float* t32 = nullptr;
+    double* t64 = nullptr;
+    void* blas = nullptr;
+    int64_t tstats[4] = {0, 0, 0, 0};   // FP32 on the fly, FP32 stored, FP64 on the fly, FP64 stored
+    double tms[4] = {0, 0, 0, 0};       // their HIP-event milliseconds inside cycles (options.timings)
+    double tflop[4] = {0, 0, 0, 0};     // their algorithmic FLOP inside cycles
+
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, d_perm, d_col_pol, d_omega, x, b};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, d_perm, d_col_pol, d_omega, x, b, t32, t64};
         for (void* p : ps) pxs::dfree(p);
+        pxs::release_blas(blas);
     }
 };
 

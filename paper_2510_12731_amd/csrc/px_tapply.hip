@@ -981,6 +981,77 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit, stop);
 }
 
+// ---- dense T for the stored-T apply ---------------------------------------------
+// T[u][v] over the padded unknowns u, v (row-major, ld = nup; component-major
+// for the dipole model: u = a * np + i), the same formulas and far thresholds
+// as the on-the-fly kernels of the precision; rows and columns of ghost atoms
+// are zero.  One thread per element, 256 columns of one row per workgroup.
+__global__ __launch_bounds__(256) void k_tdense_f32(const float4* __restrict__ xyz, int64_t n, int64_t np, int model,
+                                                    float inv_rqq, float t_self, float r_far2, DipoleConstF kc,
+                                                    float* __restrict__ T)
+{
+    const int64_t nup = model ? 4 * np : np;
+    const int64_t v = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    const int64_t u = blockIdx.x;
+    if (v >= nup) return;
+    const int a = (int)(u / np), c = (int)(v / np);
+    const int64_t i = u - a * np, j = v - c * np;
+    float t = 0.0f;
+    if (i < n && j < n) {
+        const float4 pi = xyz[i], pj = xyz[j];
+        const float dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (!model) {
+            if (i == j) {
+                t = t_self;
+            } else {
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                t = r2 < r_far2 ? erf_as(r2 * rinv * inv_rqq) * rinv : rinv;
+            }
+        } else if (i == j) {
+            t = (a == 0 && c == 0) ? kc.t_self : 0.0f;
+        } else {
+            float b[4][4];
+            pair_block_f32(dx, dy, dz, r2 >= kc.r_far2, kc, b);
+            t = b[a][c];
+        }
+    }
+    T[u * nup + v] = t;
+}
+
+__global__ __launch_bounds__(256) void k_tdense_f64(const double4* __restrict__ xyz, int64_t n, int64_t np, int model,
+                                                    double inv_rqq, double t_self, float r_far2, DipoleConstD kc,
+                                                    double* __restrict__ T)
+{
+    const int64_t nup = model ? 4 * np : np;
+    const int64_t v = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    const int64_t u = blockIdx.x;
+    if (v >= nup) return;
+    const int a = (int)(u / np), c = (int)(v / np);
+    const int64_t i = u - a * np, j = v - c * np;
+    double t = 0.0;
+    if (i < n && j < n) {
+        const double4 pi = xyz[i], pj = xyz[j];
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        if (!model) {
+            if (i == j) {
+                t = t_self;
+            } else {
+                const double rinv = rsqrt(r2);
+                t = r2 < (double)r_far2 ? erf(r2 * rinv * inv_rqq) * rinv : rinv;
+            }
+        } else if (i == j) {
+            t = (a == 0 && c == 0) ? kc.t_self : 0.0;
+        } else {
+            double b[4][4];
+            pair_block_f64(dx, dy, dz, r2 >= (double)kc.r_far2, kc, b);
+            t = b[a][c];
+        }
+    }
+    T[u * nup + v] = t;
+}
+
 // Resident 512-thread FP32 workgroups: two per CU (LDS and registers allow
 // two), counted once per device.
 int sk_slots()
@@ -1221,6 +1292,34 @@ void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st, const in
     if (impl->n64d > 0)
         hipLaunchKernelGGL(k_tapply_wfqfmu_f64_grouped, dim3(impl->n64d), dim3(256), 0, st, impl->d_gc, impl->d_t64d,
                            X, Y, impl->ldx, stop);
+}
+
+void tdense_f32(const Geometry& g, float* T, hipStream_t st)
+{
+    const double rqq = std::sqrt(2.0) * g.r_q;
+    const float rf = (float)(XFAR_Q32 * rqq);
+    DipoleConstF k{};
+    if (g.model == 1) {
+        const DipoleConstD d = dipole_const_d(g);
+        k.inv_rqq = (float)d.inv_rqq;
+        k.inv_rqm = (float)d.inv_rqm;
+        k.inv_rmm = (float)d.inv_rmm;
+        k.gauss_pref = (float)d.gauss_pref;
+        k.t_self = (float)d.t_self;
+        const double rmax = 1.0 / std::fmin(d.inv_rqq, std::fmin(d.inv_rqm, d.inv_rmm));
+        k.r_far2 = (float)((XFAR_D32 * rmax) * (XFAR_D32 * rmax));
+    }
+    hipLaunchKernelGGL(k_tdense_f32, dim3((unsigned)g.nup, (unsigned)((g.nup + 255) / 256)), dim3(256), 0, st, g.xyz32,
+                       g.n, g.np, g.model, (float)(1.0 / rqq), (float)(TWO_OVER_SQRTPI / rqq), rf * rf, k, T);
+}
+
+void tdense_f64(const Geometry& g, double* T, hipStream_t st)
+{
+    const double rqq = std::sqrt(2.0) * g.r_q;
+    const float rf = (float)(XFAR_Q64 * rqq);
+    const DipoleConstD k = dipole_const_d(g);
+    hipLaunchKernelGGL(k_tdense_f64, dim3((unsigned)g.nup, (unsigned)((g.nup + 255) / 256)), dim3(256), 0, st, g.xyz64,
+                       g.n, g.np, g.model, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf * rf, k, T);
 }
 
 }  // namespace px

@@ -182,6 +182,39 @@ def test_orthogonalisation_variants_agree(precision, tol, bound):
         s.close()
 
 
+@pytest.mark.parametrize("precision,tol,bound", [(px.PX_FP64, 1e-12, 1e-10), (px.PX_MIXED, 1e-8, 1e-5)])
+def test_stored_t_apply_matches_oracle(precision, tol, bound):
+    """The stored-T apply (dense T built once per structure, one GEMM per
+    apply) reaches the oracle's spectrum on both models, forced and under the
+    autotuner, and agrees with the on-the-fly kernels."""
+    xyz = G.fcc_rod_n(300, seed=31)
+    p = M.load("au_wfqfmu")
+    om = np.linspace(1.6, 3.4, 7)
+    aib = M.interband_alpha(p, om)
+    ref = O.solve_spectrum(1, xyz, M.param_vector(p), om, 0b101, 1e-4, aib)
+    c = C.small_sphere()
+    ref_s = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
+    for mode in (px.PX_TAPPLY_STORED, px.PX_TAPPLY_AUTO, px.PX_TAPPLY_ON_THE_FLY):
+        s, st, alpha, sig_r, it, rr = _solve(1, xyz, p, om, 0b101, aib, precision, tol, t_apply=mode)
+        ts = s.tapply_stats()
+        e = rel_err(sig_r, ref["sigma"])
+        say(f"[t_apply {mode}] rod: status {st} iters max {it.max()} rel_err {e:.2e} launches {ts}")
+        assert st == px.PX_OK and e <= bound
+        if mode == px.PX_TAPPLY_STORED:
+            assert ts["f64_stored"] > 0 and ts["f64_on_the_fly"] == 0
+            if precision == px.PX_MIXED:
+                assert ts["f32_stored"] > 0 and ts["f32_on_the_fly"] == 0
+        if mode == px.PX_TAPPLY_ON_THE_FLY:
+            assert ts["f32_stored"] == 0 and ts["f64_stored"] == 0
+        s.close()
+        s, st, alpha, sig_s, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
+                                             tol, t_apply=mode)
+        e = rel_err(sig_s, ref_s["sigma"])
+        say(f"[t_apply {mode}] sphere: status {st} iters max {it.max()} rel_err {e:.2e} launches {s.tapply_stats()}")
+        assert st == px.PX_OK and e <= bound
+        s.close()
+
+
 def test_gap_dimer_conserves_charge_per_fragment():
     xyz = G.gap_dimer(600, gap=5.0, seed=41)
     p = M.load("ag_wfq")
