@@ -73,17 +73,39 @@ def tapply_roofline(runs, n, traffic, traffic_cols):
     nl = sum(r["tapply"][dom] for r in runs)
     achieved = fl / (ms[dom] * 1e-3) / 1e12 if ms[dom] > 0 else 0.0
     fly = dom == "f32_on_the_fly"
+    note = None
+    if fly and traffic is not None:
+        note = (f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
+                f"algorithmic {2 * 4 * n * traffic_cols} B (X read once, Y written once)")
+    if not fly:
+        traffic, traffic_cols, kname = measured_traffic_stored("tapply_f32_stored_sgemm_sphere20k_hbm_counters.md")
+        if traffic is not None:
+            nup = ((n + 255) // 256) * 256
+            note = (f"HBM bytes per launch at {traffic_cols} real columns (counter runs, {kname}); "
+                    f"algorithmic {4 * nup * nup + 2 * 4 * nup * traffic_cols} B (stored T read once, X, Y)")
     return dict(bound="mfma", achieved=round(achieved, 2), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
-                traffic=traffic if fly else None,
-                traffic_note=(f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
-                              f"algorithmic {2 * 4 * n * traffic_cols} B" if fly and traffic is not None else None),
+                traffic=traffic,
+                traffic_note=note,
                 kernel=("k_tapply_wfq_f32 (+ k_sk_fixup), T generated on the fly" if fly else
                         "rocBLAS sgemm on the stored T (autotuner's choice for this width)"),
                 launches=int(nl), avg_launch_ms=round(ms[dom] / max(nl, 1), 4),
                 avg_algorithmic_gflop_per_launch=round(fl / max(nl, 1) / 1e9, 2),
                 method_ms={k: round(v, 1) for k, v in ms.items()},
                 method_launches={k: int(sum(r["tapply"][k] for r in runs)) for k in keys})
+
+
+def measured_traffic_stored(summary):
+    """HBM bytes per full-width stored-T GEMM launch from the committed counter
+    summary (a library kernel: keyed by the kernel name recorded there)."""
+    try:
+        text = open(os.path.join(ROOT, "profiles", summary)).read()
+    except OSError:
+        return None, None, None
+    kv = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("-", "#")))
+    if "traffic_bytes_per_launch" not in kv:
+        return None, None, None
+    return int(kv["traffic_bytes_per_launch"]), int(kv["traffic_launch_real_columns"]), kv.get("kernel_name")
 
 
 def measured_traffic(kernel_src, summary):
@@ -266,7 +288,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lu-steps", type=int, default=4)
     ap.add_argument("--kernel-sample", action="store_true",
-                    help="one restart cycle of 4 steps on the full workload, T on the fly (hardware-counter runs)")
+                    help="one restart cycle of 4 steps on the full workload with --t-apply (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
     ap.add_argument("--workload", default="sphere",
@@ -275,6 +297,8 @@ def main():
                          "serving mix, printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
     ap.add_argument("--no-on-the-fly", action="store_true", help="skip the on-the-fly-only comparison step")
+    ap.add_argument("--t-apply", default="auto", choices=["auto", "on-the-fly", "stored"],
+                    help="T-apply method of the timed steps (auto: the autotuner's choice per width)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box here has a single MI355X and the solver does not shard; "
@@ -323,16 +347,19 @@ def main():
     if args.kernel_sample:
         s = pxm.Structure(case["model"], case["xyz"], case["params"], pxm.default_stream())
         s.set_frequencies(case["omega_ev"], case["pol_mask"], case["e0"])
-        st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True,
-                     t_apply=pxm.PX_TAPPLY_ON_THE_FLY)
+        ta = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
+              "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
+        st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True, t_apply=ta)
         tm = s.timings()
         s.close()
         print(json.dumps({"kernel_sample": True, "status": int(st), "tapply_f32_launches": int(tm["n_tapply_f32"]),
                           "cols_f32_padded": int(tm["cols_f32_padded"])}), flush=True)
         return
 
+    ta_mode = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
+               "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
     for w in range(args.warmup):
-        r = one_step(pxm, case, pxm.PX_MIXED, True)
+        r = one_step(pxm, case, pxm.PX_MIXED, True, t_apply=ta_mode)
         log(f"[bench] warmup {w}: status {r['status']} max iters {r['iters'].max()} "
             f"{r['timings']['ms_total'] / 1e3:.2f} s")
 
@@ -342,7 +369,7 @@ def main():
     step_s = []
     for k in range(args.steps):
         ta = time.perf_counter()
-        runs.append(one_step(pxm, case, pxm.PX_MIXED, True))
+        runs.append(one_step(pxm, case, pxm.PX_MIXED, True, t_apply=ta_mode))
         step_s.append(time.perf_counter() - ta)
         log(f"[bench] step {k}: status {runs[-1]['status']} {runs[-1]['timings']['ms_total'] / 1e3:.2f} s")
     torch.cuda.synchronize()
@@ -457,7 +484,7 @@ def main():
         "dtype": "f32/f64",
         "data": "synthetic",
         "config": {"workload": case["name"], "n_atoms": n, "n_omega": int(len(case["omega_ev"])),
-                   "polarizations": 3, "columns": ncol, "restart_m": 50, "rel_tol": 1e-8},
+                   "polarizations": 3, "columns": ncol, "restart_m": 50, "rel_tol": 1e-8, "t_apply": args.t_apply},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,
