@@ -38,7 +38,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build()
     lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -63,6 +63,13 @@ def _load():
     lib.or_tapply_rows.argtypes = [ctypes.c_int, i64, dp, dp, i64, lp, i64, dp, dp]
     lib.or_assemble.argtypes = [ctypes.c_int, i64, dp, dp, ctypes.c_double, dp, dp]
     lib.or_constants.argtypes = [dp]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.or_solve_spectrum_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, i64, dp, ctypes.c_uint32,
+                                          ctypes.c_double, dp, dp, dp, dp, dp]
+    lib.or_solve_spectrum_het.restype = i64
+    lib.or_apply_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, i64, dp, dp, dp, dp, dp]
+    lib.or_rhs_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                               dp]
     _lib = lib
     return lib
 
@@ -195,6 +202,62 @@ def rhs(model, xyz, p, pol, e0):
     nu = 4 * n if model == 1 else n
     b = np.zeros(nu, dtype=np.complex128)
     _load().or_rhs(int(model), n, _d(xyz), _d(_pv(p)), int(pol), float(e0), _d(b.view(np.float64)))
+    return b
+
+
+def _types(types, n):
+    t = np.ascontiguousarray(types, dtype=np.int32)
+    assert t.shape == (n,) and np.all((t == 0) | (t == 1))
+    return t
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def solve_spectrum_het(model, xyz, types, pa, pb, omega_ev, pol_mask, e0, alpha_ib_a=None, alpha_ib_b=None):
+    """Direct-solve spectrum of a two-type structure (Eq. wfqfmu-leghe; model 0
+    is its charge block).  types[i] in {0: A, 1: B}; returns as solve_spectrum."""
+    xyz = _xyz(xyz)
+    n = len(xyz)
+    t = _types(types, n)
+    nu = 4 * n if model == 1 else n
+    om = np.ascontiguousarray(omega_ev, dtype=np.float64)
+    nw = len(om)
+    npol = bin(pol_mask & 7).count("1")
+    q = np.zeros((nw, npol, nu), dtype=np.complex128)
+    alpha = np.zeros((nw, 3, 3), dtype=np.complex128)
+    sigma = np.zeros(nw)
+    aa, ab = _alpha_ib_arr(alpha_ib_a, nw), _alpha_ib_arr(alpha_ib_b, nw)
+    st = _load().or_solve_spectrum_het(int(model), n, _d(xyz), _i(t), _d(_pv(pa)), _d(_pv(pb)), nw, _d(om),
+                                       int(pol_mask), float(e0), _d(aa), _d(ab), _d(q.view(np.float64)),
+                                       _d(alpha.view(np.float64)), _d(sigma))
+    return dict(q=q, alpha=alpha, sigma=sigma, status=int(st))
+
+
+def apply_het(model, xyz, types, pa, pb, omega_ev, x, alpha_ib_a=None, alpha_ib_b=None):
+    """y = A(w_c) x_c of a two-type structure; x: [ncol, nu] complex."""
+    xyz = _xyz(xyz)
+    n = len(xyz)
+    t = _types(types, n)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    ncol = x.shape[0]
+    om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega_ev, dtype=np.float64), (ncol,)))
+    y = np.zeros_like(x)
+    aa, ab = _alpha_ib_arr(alpha_ib_a, ncol), _alpha_ib_arr(alpha_ib_b, ncol)
+    _load().or_apply_het(int(model), n, _d(xyz), _i(t), _d(_pv(pa)), _d(_pv(pb)), ncol, _d(om), _d(aa), _d(ab),
+                         _d(x.view(np.float64)), _d(y.view(np.float64)))
+    return y
+
+
+def rhs_het(model, xyz, types, pa, pb, omega_ev, pol, e0):
+    xyz = _xyz(xyz)
+    n = len(xyz)
+    t = _types(types, n)
+    nu = 4 * n if model == 1 else n
+    b = np.zeros(nu, dtype=np.complex128)
+    _load().or_rhs_het(int(model), n, _d(xyz), _i(t), _d(_pv(pa)), _d(_pv(pb)), float(omega_ev), int(pol),
+                       float(e0), _d(b.view(np.float64)))
     return b
 
 

@@ -16,6 +16,7 @@
  *   Eq. (z-mu)        z_mu(w) = -1 / alpha_IB(w)
  *   Eq. (wfq-system)  [Kbar T - z_q I] q = -Kbar V
  *   Eq. (wfqfmu-system) for charges and dipoles
+ *   Eq. (wfqfmu-leghe), Eq. (polar-finale): two atom types (the *_het functions)
  *   Section 6, "inversion": LU with partial pivoting, then forward/back solves
  *   Section 7: d = sum_i q_i r_i (+ mu_i), alpha_kl = d_k / E_l, sigma_abs.
  *
@@ -592,6 +593,313 @@ void or_assemble(int model, int64_t n, const double* xyz_ang, const double* p, d
     }
     system_matrix(model, n, kt, zq, zmu, a);
     free(kbar); free(kt);
+}
+
+/* ---- heterogeneous systems: two atom types (Section 2.2, Eqs. wfqfmu-leghe,
+ * polar-finale) ----
+ * Atom i has type t_i = 0 (A) or 1 (B) with parameter vectors pa, pb.  The
+ * system is [diag(S(w), I) T - diag(z_q,i, z_mu,i)] x = diag(S(w), I) (-V; E)
+ * with S = (Kbar + Hbar(w)) / 2, Hbar_ij = H_ij - delta_ij sum_k H_ik and
+ * H_ij = (n_j tau_j / n_i tau_i) (1 - i w tau_i) / (1 - i w tau_j) K_ji.
+ * Readings (also in the design notes):
+ *   - unlike pairs exchange with the mean of the two types' A, r0, d, s and
+ *     cutoff in Eqs. (fermi), (kappa);
+ *   - n_i is the Drude weight n/m* of atom i's type;
+ *   - z_q is per atom, z_q,i = z_q of atom i's type (Eq. z_q_wfq): the
+ *     equation is the charge exchange through the mean of the two atoms' Drude
+ *     factors sigma_i = 2 n_i tau_i / (1 - i w tau_i), with row i divided by
+ *     sigma_i, which gives exactly the (Kbar + Hbar)/2 form and z_q,i;
+ *   - both types share R_q and R_mu (T is that of the homogeneous model);
+ *   - the neighbours of Eq. (polar-finale) are the atoms within the exchange
+ *     cutoff; for an atom of type B the roles of A and B swap;
+ *   - model 0 is the charge block alone (omegaFQ with two types). */
+
+static material pair_material(const material* ma, const material* mb, int ti, int tj)
+{
+    if (ti == tj) return ti == 0 ? *ma : *mb;
+    material m = *ma;
+    m.a_eff = 0.5 * (ma->a_eff + mb->a_eff);
+    m.r0 = 0.5 * (ma->r0 + mb->r0);
+    m.fd = 0.5 * (ma->fd + mb->fd);
+    m.fs = 0.5 * (ma->fs + mb->fs);
+    m.rc = 0.5 * (ma->rc + mb->rc);
+    return m;
+}
+
+/* Dense K (not Kbar) for two atom types, row-major N x N, zero diagonal. */
+static void build_k_het(int64_t n, const double* xyz, const int32_t* types, const material* ma,
+                        const material* mb, double* k)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            k[i * n + j] = 0.0;
+            if (j == i) continue;
+            material m = pair_material(ma, mb, types[i], types[j]);
+            k[i * n + j] = kappa(&m, dist(xyz, i, j, NULL));
+        }
+}
+
+/* S(w) = (Kbar + Hbar(w)) / 2, dense complex interleaved N x N, from K. */
+static void build_s_het(int64_t n, const double* k, const int32_t* types, const double* pa, const double* pb,
+                        double w, double* sm)
+{
+    const double* pt[2] = {pa, pb};
+    double dt[2], tau[2];
+    for (int t = 0; t < 2; ++t) {
+        dt[t] = or_drude_weight(pt[t]);
+        tau[t] = unpack(pt[t]).tau;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double kr = 0.0, hr = 0.0, hi = 0.0;
+        const int ti = types[i];
+        for (int64_t j = 0; j < n; ++j) {
+            double* e = sm + 2 * (i * n + j);
+            if (j == i) continue;
+            const int tj = types[j];
+            const double kij = k[i * n + j], kji = k[j * n + i];
+            /* H_ij = (n_j tau_j / n_i tau_i) (1 - i w tau_i) / (1 - i w tau_j) K_ji */
+            const double ratio = dt[tj] * tau[tj] / (dt[ti] * tau[ti]);
+            const double ar = 1.0, ai = -w * tau[ti];        /* 1 - i w tau_i */
+            const double br = 1.0, bi = -w * tau[tj];        /* 1 - i w tau_j */
+            const double den = br * br + bi * bi;
+            const double fr = (ar * br + ai * bi) / den, fi = (ai * br - ar * bi) / den;
+            const double h_r = ratio * fr * kji, h_i = ratio * fi * kji;
+            e[0] = 0.5 * (kij + h_r);
+            e[1] = 0.5 * h_i;
+            kr += kij;
+            hr += h_r;
+            hi += h_i;
+        }
+        /* diagonal: Kbar_ii = -sum_k K_ik, Hbar_ii = -sum_k H_ik */
+        sm[2 * (i * n + i)] = -0.5 * (kr + hr);
+        sm[2 * (i * n + i) + 1] = -0.5 * hi;
+    }
+}
+
+/* Eq. (polar-finale): per-atom interband polarizability from the numbers of
+ * neighbours of each type; aib_t = alpha_IB of type t at this frequency. */
+static void alpha_ib_het(int64_t n, const double* k, const int32_t* types, const double* aib_a, const double* aib_b,
+                         double* out)
+{
+    const double* ab[2] = {aib_a, aib_b};
+    double inv[2][2];
+    for (int t = 0; t < 2; ++t) {
+        double den = ab[t][0] * ab[t][0] + ab[t][1] * ab[t][1];
+        inv[t][0] = ab[t][0] / den;
+        inv[t][1] = -ab[t][1] / den;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int cnt[2] = {0, 0};
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && k[i * n + j] != 0.0) cnt[types[j]] += 1;
+        const int own = types[i], oth = 1 - own;
+        const double m = (double)(cnt[0] + cnt[1] + 1);
+        const double sr = ((cnt[own] + 1) * inv[own][0] + cnt[oth] * inv[oth][0]) / m;
+        const double si = ((cnt[own] + 1) * inv[own][1] + cnt[oth] * inv[oth][1]) / m;
+        const double den = sr * sr + si * si;
+        out[2 * i] = sr / den;      /* alpha_i = 1 / (mean of inverses) */
+        out[2 * i + 1] = -si / den;
+    }
+}
+
+/*
+ * Spectrum of a two-type structure by direct solves (arguments as
+ * or_solve_spectrum; types[n] in {0, 1}; aib_a, aib_b: 2*n_omega interleaved
+ * alpha_IB of the two types, model 1 only).  Returns 0, a zero-pivot code, or
+ * -1 if the two types' Gaussian widths differ.
+ */
+int64_t or_solve_spectrum_het(int model, int64_t n, const double* xyz_ang, const int32_t* types, const double* pa,
+                              const double* pb, int64_t n_omega, const double* omega_ev, uint32_t pol_mask,
+                              double e0, const double* aib_a, const double* aib_b, double* q_out,
+                              double* alpha_out, double* sigma_out)
+{
+    material ma = unpack(pa), mb = unpack(pb);
+    if (ma.r_q != mb.r_q || (model == 1 && ma.r_mu != mb.r_mu)) return -1;
+    int64_t nu = n_unknowns(model, n);
+    int npol = popcount3(pol_mask);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    double* k = (double*)malloc(sizeof(double) * n * n);
+    double* sm = (double*)malloc(sizeof(double) * 2 * n * n);
+    double* t = (double*)malloc(sizeof(double) * nu * nu);
+    double* a = (double*)malloc(sizeof(double) * 2 * nu * nu);
+    double* aib = (double*)malloc(sizeof(double) * 2 * n);
+    int64_t* piv = (int64_t*)malloc(sizeof(int64_t) * nu);
+    int64_t status = 0;
+    to_bohr(n, xyz_ang, xyz);
+    build_k_het(n, xyz, types, &ma, &mb, k);
+    if (model == 1) or_build_tfull(n, xyz_ang, pa, t);
+    else or_build_tqq(n, xyz_ang, pa, t);
+    int pols[3], ip = 0;
+    for (int l = 0; l < 3; ++l)
+        if (pol_mask & (1u << l)) pols[ip++] = l;
+    for (int64_t w = 0; w < n_omega; ++w) {
+        const double om = omega_ev[w] / EV_PER_HARTREE;
+        build_s_het(n, k, types, pa, pb, om, sm);
+        if (model == 1) alpha_ib_het(n, k, types, aib_a + 2 * w, aib_b + 2 * w, aib);
+        /* A = diag(S, I) T - diag(z_q,i, z_mu,i) */
+        for (int64_t i = 0; i < n; ++i) {
+            double* row = a + 2 * i * nu;
+            memset(row, 0, sizeof(double) * 2 * nu);
+            for (int64_t kk = 0; kk < n; ++kk) {
+                const double sr = sm[2 * (i * n + kk)], si = sm[2 * (i * n + kk) + 1];
+                if (sr == 0.0 && si == 0.0) continue;
+                const double* tk = t + kk * nu;
+                for (int64_t j = 0; j < nu; ++j) {
+                    row[2 * j] += sr * tk[j];
+                    row[2 * j + 1] += si * tk[j];
+                }
+            }
+        }
+        for (int64_t i = n; i < nu; ++i)
+            for (int64_t j = 0; j < nu; ++j) {
+                a[2 * (i * nu + j)] = t[i * nu + j];
+                a[2 * (i * nu + j) + 1] = 0.0;
+            }
+        const double* pt[2] = {pa, pb};
+        for (int64_t i = 0; i < nu; ++i) {
+            double z[2];
+            const int64_t ai = i % n;
+            if (i < n) {
+                or_zq(pt[types[ai]], om, z);
+            } else {        /* Eq. (z-mu) with the atom's mixed alpha_IB */
+                const double ar = aib[2 * ai], aim = aib[2 * ai + 1];
+                const double den = ar * ar + aim * aim;
+                z[0] = -ar / den;
+                z[1] = aim / den;
+            }
+            a[2 * (i * nu + i)] -= z[0];
+            a[2 * (i * nu + i) + 1] -= z[1];
+        }
+        int64_t rc = or_lu_factor(nu, a, piv);
+        if (rc != 0 && status == 0) status = rc;
+        double* al = alpha_out + 18 * w;
+        memset(al, 0, sizeof(double) * 18);
+        double im_sum = 0.0;
+        for (int ip2 = 0; ip2 < npol; ++ip2) {
+            const int l = pols[ip2];
+            double* q = q_out + 2 * nu * (w * npol + ip2);
+            memset(q, 0, sizeof(double) * 2 * nu);
+            /* b = diag(S, I) (-V; E), -V_j = E0 x_j,l */
+            for (int64_t i = 0; i < n; ++i) {
+                double br = 0.0, bi = 0.0;
+                for (int64_t j = 0; j < n; ++j) {
+                    const double v = e0 * xyz[3 * j + l];
+                    br += sm[2 * (i * n + j)] * v;
+                    bi += sm[2 * (i * n + j) + 1] * v;
+                }
+                q[2 * i] = br;
+                q[2 * i + 1] = bi;
+            }
+            if (model == 1)
+                for (int64_t i = 0; i < n; ++i) q[2 * ((1 + l) * n + i)] = e0;
+            if (rc == 0) or_lu_solve(nu, a, piv, q);
+            for (int kk = 0; kk < 3; ++kk) {
+                double dr = 0.0, di = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    dr += q[2 * i] * xyz[3 * i + kk];
+                    di += q[2 * i + 1] * xyz[3 * i + kk];
+                }
+                if (model == 1)
+                    for (int64_t i = 0; i < n; ++i) {
+                        dr += q[2 * ((1 + kk) * n + i)];
+                        di += q[2 * ((1 + kk) * n + i) + 1];
+                    }
+                al[2 * (3 * kk + l)] = dr / e0;
+                al[2 * (3 * kk + l) + 1] = di / e0;
+            }
+            im_sum += al[2 * (3 * l + l) + 1];
+        }
+        sigma_out[w] = 4.0 * PI * om / C_LIGHT_AU * (im_sum / npol);
+    }
+    free(xyz); free(k); free(sm); free(t); free(a); free(aib); free(piv);
+    return status;
+}
+
+/* Matrix-free y = A(w) x of a two-type structure for ncol columns (layout as
+ * or_apply; aib_a/aib_b per column). */
+void or_apply_het(int model, int64_t n, const double* xyz_ang, const int32_t* types, const double* pa,
+                  const double* pb, int64_t ncol, const double* omega_ev, const double* aib_a, const double* aib_b,
+                  const double* x, double* y)
+{
+    material ma = unpack(pa), mb = unpack(pb);
+    int64_t nu = n_unknowns(model, n);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    double* k = (double*)malloc(sizeof(double) * n * n);
+    double* sm = (double*)malloc(sizeof(double) * 2 * n * n);
+    double* aib = (double*)malloc(sizeof(double) * 2 * n);
+    double* u = (double*)malloc(sizeof(double) * 2 * nu * ncol);
+    to_bohr(n, xyz_ang, xyz);
+    build_k_het(n, xyz, types, &ma, &mb, k);
+    memset(u, 0, sizeof(double) * 2 * nu * ncol);
+    for (int64_t i = 0; i < n; ++i)        /* u = T x */
+        for (int64_t j = 0; j < n; ++j) {
+            double rv[3] = {0, 0, 0};
+            double r = (i == j) ? 0.0 : dist(xyz, i, j, rv);
+            double blk[4][4];
+            if (model == 1) pair_block(&ma, rv, r, i == j, blk);
+            else blk[0][0] = tqq(r, ma.r_q, ma.r_q);
+            const int nb = model == 1 ? 4 : 1;
+            for (int64_t c = 0; c < ncol; ++c)
+                for (int aa = 0; aa < nb; ++aa)
+                    for (int b = 0; b < nb; ++b) {
+                        u[2 * (c * nu + aa * n + i)] += blk[aa][b] * x[2 * (c * nu + b * n + j)];
+                        u[2 * (c * nu + aa * n + i) + 1] += blk[aa][b] * x[2 * (c * nu + b * n + j) + 1];
+                    }
+        }
+    const double* pt[2] = {pa, pb};
+    for (int64_t c = 0; c < ncol; ++c) {
+        const double om = omega_ev[c] / EV_PER_HARTREE;
+        build_s_het(n, k, types, pa, pb, om, sm);
+        if (model == 1) alpha_ib_het(n, k, types, aib_a + 2 * c, aib_b + 2 * c, aib);
+        const double* uc = u + 2 * c * nu;
+        const double* xc = x + 2 * c * nu;
+        double* yc = y + 2 * c * nu;
+        for (int64_t i = 0; i < n; ++i) {    /* y = S u - z_q,i x */
+            double sr = 0.0, si = 0.0, z[2];
+            for (int64_t j = 0; j < n; ++j) {
+                const double er = sm[2 * (i * n + j)], ei = sm[2 * (i * n + j) + 1];
+                sr += er * uc[2 * j] - ei * uc[2 * j + 1];
+                si += er * uc[2 * j + 1] + ei * uc[2 * j];
+            }
+            or_zq(pt[types[i]], om, z);
+            yc[2 * i] = sr - (z[0] * xc[2 * i] - z[1] * xc[2 * i + 1]);
+            yc[2 * i + 1] = si - (z[0] * xc[2 * i + 1] + z[1] * xc[2 * i]);
+        }
+        for (int64_t i = n; i < nu; ++i) {  /* y = u - z_mu,i x */
+            const int64_t ai = i % n;
+            const double ar = aib[2 * ai], aim = aib[2 * ai + 1];
+            const double den = ar * ar + aim * aim;
+            const double z0 = -ar / den, z1 = aim / den;
+            yc[2 * i] = uc[2 * i] - (z0 * xc[2 * i] - z1 * xc[2 * i + 1]);
+            yc[2 * i + 1] = uc[2 * i + 1] - (z0 * xc[2 * i + 1] + z1 * xc[2 * i]);
+        }
+    }
+    free(xyz); free(k); free(sm); free(aib); free(u);
+}
+
+/* Right-hand side of a two-type structure at one frequency for polarization l:
+ * diag(S(w), I) (-V; E), [nu] interleaved complex. */
+void or_rhs_het(int model, int64_t n, const double* xyz_ang, const int32_t* types, const double* pa,
+                const double* pb, double omega_ev, int l, double e0, double* b)
+{
+    material ma = unpack(pa), mb = unpack(pb);
+    int64_t nu = n_unknowns(model, n);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * n);
+    double* k = (double*)malloc(sizeof(double) * n * n);
+    double* sm = (double*)malloc(sizeof(double) * 2 * n * n);
+    to_bohr(n, xyz_ang, xyz);
+    build_k_het(n, xyz, types, &ma, &mb, k);
+    build_s_het(n, k, types, pa, pb, omega_ev / EV_PER_HARTREE, sm);
+    memset(b, 0, sizeof(double) * 2 * nu);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            const double v = e0 * xyz[3 * j + l];
+            b[2 * i] += sm[2 * (i * n + j)] * v;
+            b[2 * i + 1] += sm[2 * (i * n + j) + 1] * v;
+        }
+    if (model == 1)
+        for (int64_t i = 0; i < n; ++i) b[2 * ((1 + l) * n + i)] = e0;
+    free(xyz); free(k); free(sm);
 }
 
 /* Unit constants as used by this oracle (so tests can check them). */

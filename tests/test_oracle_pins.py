@@ -416,3 +416,113 @@ def test_sigma_is_textbook_absorption_cross_section():
     out3 = O.solve_spectrum(0, c["xyz"], pv(c["params"]), c["omega_ev"][:5], 0b111, 1e-4)
     tr = np.trace(out3["alpha"], axis1=1, axis2=2).imag
     assert np.allclose(out3["sigma"], 4 * np.pi * k[:5] * tr / 3, rtol=1e-8)
+
+
+# ---------------------------------------------------------------- two atom types (Eqs. wfqfmu-leghe, polar-finale)
+
+AG_MU = M.load("ag_wfqfmu")
+
+
+def test_two_type_system_reduces_to_the_homogeneous_model():
+    """Eq. (wfqfmu-leghe) reduces to Eq. (wfqfmu-system) for one atom type: all
+    atoms A, all atoms B, and random types with identical parameter sets all
+    give the homogeneous spectrum (charges and dipoles)."""
+    xyz = G.fcc_sphere_n(43, seed=3)
+    om = np.array([2.2, 3.1, 3.9])
+    pa, pb = pv(AG_MU), pv(AU)
+    aa, ab = M.interband_alpha(AG_MU, om), M.interband_alpha(AU, om)
+    rand = G.alloy_types(len(xyz), 0.4, seed=2)
+    cases = [(np.zeros(len(xyz)), pa, aa), (np.ones(len(xyz)), pb, ab)]
+    for types, p, aib in cases:
+        ref = O.solve_spectrum(1, xyz, p, om, 0b011, 1e-4, aib)
+        het = O.solve_spectrum_het(1, xyz, types, pa, pb, om, 0b011, 1e-4, aa, ab)
+        assert np.abs(het["alpha"] - ref["alpha"]).max() <= 1e-11 * np.abs(ref["alpha"]).max()
+    ref = O.solve_spectrum(1, xyz, pa, om, 0b011, 1e-4, aa)
+    het = O.solve_spectrum_het(1, xyz, rand, pa, pa, om, 0b011, 1e-4, aa, aa)
+    assert np.abs(het["q"] - ref["q"]).max() <= 1e-11 * np.abs(ref["q"]).max()
+
+
+def test_unlike_pair_closed_form():
+    """Charges only, an A-B pair at distance l along x: the exchange current
+    through the mean Drude factor sigma = (sigma_A + sigma_B)/2,
+    sigma_t = 2 n_t tau_t / (1 - i w tau_t), gives (derived by hand)
+    alpha_xx = sigma K l^2 / (sigma K eta - i w),  eta = T_11 + T_22 - 2 T_12."""
+    l_ang = 2.95
+    xyz = G.two_atoms(l_ang)
+    pa, pb = pv(AG_MU), pv(AU)
+    k = O.kbar(xyz, pa)[0, 1]             # the two types share A, r0, d, s here
+    t = O.tqq(xyz, pa)
+    eta = t[0, 0] + t[1, 1] - 2 * t[0, 1]
+    l = l_ang / BOHR
+    om = np.array([0.7, 2.5, 3.4, 6.0])
+    out = O.solve_spectrum_het(0, xyz, [0, 1], pa, pb, om, 0b001, 1e-4)
+    for i, wev in enumerate(om):
+        w = wev / HARTREE_EV
+        sig = [2 * (p["density_au"] / p["eff_mass_au"]) * p["tau_au"] / (1 - 1j * w * p["tau_au"]) for p in (AG_MU, AU)]
+        s = 0.5 * (sig[0] + sig[1])
+        axx = s * k * l * l / (s * k * eta - 1j * w)
+        assert out["alpha"][i, 0, 0] == pytest.approx(axx, rel=1e-11)
+
+
+def test_two_type_reciprocity_passivity_conservation():
+    """A random Ag-Au alloy (dipole model): alpha symmetric (the exchange matrix
+    diag(sigma) (Kbar + Hbar) / 2 is symmetric), Im alpha_ll > 0, and the
+    charges of every column sum to zero."""
+    xyz = G.fcc_sphere_n(55, seed=4)
+    types = G.alloy_types(len(xyz), 0.5, seed=5)
+    om = np.array([2.0, 3.0, 3.6, 4.4])
+    out = O.solve_spectrum_het(1, xyz, types, pv(AG_MU), pv(AU), om, 0b111, 1e-4,
+                               M.interband_alpha(AG_MU, om), M.interband_alpha(AU, om))
+    n = len(xyz)
+    for a in out["alpha"]:
+        assert np.abs(a - a.T).max() <= 1e-10 * np.abs(a).max()
+        assert np.all(np.diagonal(a).imag > 0)
+    q = out["q"][:, :, :n]
+    assert np.abs(q.sum(axis=2)).max() <= 1e-10 * np.abs(q).sum(axis=2).max()
+
+
+def test_isolated_atom_of_type_b_has_its_own_interband_polarizability():
+    """Eq. (polar-finale) with no neighbours gives alpha_i = alpha_IB of the
+    atom's own type: a lone B atom's alpha is alpha_IB,B I."""
+    om = np.array([2.0, 3.5])
+    ab = M.interband_alpha(AU, om)
+    out = O.solve_spectrum_het(1, np.zeros((1, 3)), [1], pv(AG_MU), pv(AU), om, 0b111, 1e-4,
+                               M.interband_alpha(AG_MU, om), ab)
+    for i in range(2):
+        assert np.allclose(out["alpha"][i], ab[i] * np.eye(3), rtol=1e-12, atol=0)
+
+
+def test_two_type_apply_and_rhs_satisfy_the_direct_solution():
+    """The matrix-free apply and the right-hand side agree with the dense
+    direct solve: A(w) q = b for the solved charges and dipoles."""
+    xyz = G.fcc_sphere_n(38, seed=8)
+    types = G.alloy_types(len(xyz), 0.3, seed=9)
+    pa, pb = pv(AG_MU), pv(AU)
+    om = np.array([2.6, 3.3])
+    aa, ab = M.interband_alpha(AG_MU, om), M.interband_alpha(AU, om)
+    out = O.solve_spectrum_het(1, xyz, types, pa, pb, om, 0b100, 1e-4, aa, ab)
+    for i in range(len(om)):
+        q = out["q"][i, 0]
+        y = O.apply_het(1, xyz, types, pa, pb, om[i:i + 1], q[None, :], aa[i:i + 1], ab[i:i + 1])[0]
+        b = O.rhs_het(1, xyz, types, pa, pb, om[i], 2, 1e-4)
+        assert np.abs(y - b).max() <= 1e-10 * np.abs(b).max()
+
+
+def test_alloy_plasmon_red_shifts_and_weakens_with_gold_fraction():
+    """The paper's nanoalloy trend (its Ag-Au alloy example): the plasmon peak
+    of an Ag-Au sphere moves to lower energy and loses intensity as the Au
+    fraction grows (peak searched in the plasmon window 1.5-3.5 eV, below the
+    interband absorption)."""
+    xyz = G.fcc_sphere_n(135, seed=10)
+    om = np.linspace(1.5, 3.5, 81)
+    peaks, heights = [], []
+    for frac in (0.0, 0.5, 1.0):
+        types = G.alloy_types(len(xyz), frac, seed=11)
+        out = O.solve_spectrum_het(1, xyz, types, pv(AG_MU), pv(AU), om, 0b001, 1e-4,
+                                   M.interband_alpha(AG_MU, om), M.interband_alpha(AU, om))
+        i = int(np.argmax(out["sigma"]))
+        assert 0 < i < len(om) - 1          # an interior maximum
+        peaks.append(om[i])
+        heights.append(out["sigma"][i])
+    assert peaks[0] > peaks[1] > peaks[2]
+    assert heights[0] > heights[1] > heights[2]

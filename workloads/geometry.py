@@ -143,3 +143,18 @@ def two_atoms(distance: float, axis: int = 0) -> np.ndarray:
     p = np.zeros((2, 3))
     p[1, axis] = distance
     return p
+
+
+def alloy_types(n: int, frac_b: float, seed: int = 6) -> np.ndarray:
+    """Random substitutional alloy: exactly round(frac_b * n) atoms of type B (1),
+    chosen by a seeded permutation, the rest type A (0)."""
+    nb = int(round(frac_b * n))
+    t = np.zeros(n, dtype=np.int32)
+    t[np.random.default_rng(seed).permutation(n)[:nb]] = 1
+    return t
+
+
+def core_shell_types(xyz: np.ndarray, core_radius: float) -> np.ndarray:
+    """Core (type A, 0) within core_radius of the centroid, shell (type B, 1) outside."""
+    c = xyz.mean(axis=0)
+    return (np.linalg.norm(xyz - c, axis=1) > core_radius).astype(np.int32)
