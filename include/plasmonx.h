@@ -166,12 +166,32 @@ void pxDefaultSolveOptions(pxSolveOptions* opt);
 pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang, const pxMaterial* mat,
                            void* hip_stream, pxStructure* out);
 
+/* Creates a structure of two atom types (Section 2.2, Eqs. wfqfmu-leghe and
+ * polar-finale: alloys, core-shell particles): types[n_atoms] (copied) holds 0
+ * for an atom of mat_a and 1 for one of mat_b.  The charge rows solve
+ * S(w) T q - z_q,i q_i = -S(w) V with S = (Kbar + Hbar(w)) / 2, where Hbar
+ * carries the exchange back through the ratio of the two atoms' Drude factors
+ * 2 n tau / (1 - i w tau); z_q,i is the z_q of atom i's type.  Like pairs
+ * exchange with their material's A, r0, d, s and cutoff, unlike pairs with
+ * the mean of the two; the dipole rows use the per-atom interband
+ * polarizability of Eq. (polar-finale) with the neighbours within the
+ * exchange cutoff.  Both materials must have the same r_q (and r_mu for
+ * PX_WFQFMU): T is that of one material.  Such a structure is solved with
+ * pxSolveSpectrum; pxSolveBatch and the server refuse it (PX_E_INVALID).
+ * Errors as pxCreateStructure, and PX_E_INVALID for a type other than 0 or 1
+ * or for different widths. */
+pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* xyz_ang, const uint8_t* types,
+                                 const pxMaterial* mat_a, const pxMaterial* mat_b, void* hip_stream,
+                                 pxStructure* out);
+
 /* Sets the frequency grid (omega_ev[n_omega], > 0, copied), the polarizations
  * (pol_mask bit0 = x, bit1 = y, bit2 = z; one column per set bit and
  * frequency, frequency-major) and the field amplitude e0_au (> 0; the paper
  * uses 1e-4).  alpha_ib: 2*n_omega interleaved complex interband
  * polarizabilities alpha^IB(omega) (bohr^3) of Eq. (z-mu), required for
- * PX_WFQFMU and ignored for PX_WFQ.  Discards previous results. */
+ * PX_WFQFMU and ignored for PX_WFQ.  For a two-type structure alpha_ib holds
+ * 4*n_omega doubles: per frequency alpha^IB of mat_a, then of mat_b (each
+ * interleaved complex).  Discards previous results. */
 pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask,
                           double e0_au, const double* alpha_ib);
 
@@ -243,8 +263,10 @@ pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, do
 
 /* Applies the operator of the solved system, y_c = A(omega_c) x_c, to ncol
  * complex columns (x, y: [ncol][n_unknowns] interleaved complex, caller atom
- * order), column c at frequency omega_ev[c] (and alpha_ib[c] for PX_WFQFMU),
- * in the requested precision, with the same kernels the solver uses. */
+ * order), column c at frequency omega_ev[c] (and alpha_ib[c] for PX_WFQFMU:
+ * 2 doubles per column, 4 for a two-type structure as in pxSetFrequencies),
+ * in the requested precision, with the same kernels the solver uses.  The
+ * dipole rows are those of Eq. (wfqfmu-system), not negated. */
 pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const double* omega_ev,
                          const double* alpha_ib, const double* x, double* y);
 

@@ -24,7 +24,7 @@ PX_ORTHO_CGS2, PX_ORTHO_DCGS2 = 0, 1
 PX_TAPPLY_AUTO, PX_TAPPLY_ON_THE_FLY, PX_TAPPLY_STORED = 0, 1, 2
 STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV", 4: "PX_E_DEVICE", 5: "PX_E_STATE"}
 
-EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
+EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHetero", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy"]
@@ -74,6 +74,9 @@ def load(path: str = LIB_PATH):
     lib.pxDefaultSolveOptions.argtypes = [ctypes.POINTER(pxSolveOptions)]
     lib.pxDefaultSolveOptions.restype = None
     lib.pxCreateStructure.argtypes = [ctypes.c_int, i64, _dp, ctypes.POINTER(pxMaterial), _vp, ctypes.POINTER(_vp)]
+    lib.pxCreateStructureHetero.argtypes = [ctypes.c_int, i64, _dp, ctypes.POINTER(ctypes.c_uint8),
+                                            ctypes.POINTER(pxMaterial), ctypes.POINTER(pxMaterial), _vp,
+                                            ctypes.POINTER(_vp)]
     lib.pxSetFrequencies.argtypes = [_vp, i32, _dp, u32, ctypes.c_double, _dp]
     lib.pxSolveSpectrum.argtypes = [_vp, ctypes.POINTER(pxSolveOptions)]
     lib.pxSolveBatch.argtypes = [ctypes.POINTER(_vp), i32, ctypes.POINTER(pxSolveOptions)]
@@ -151,6 +154,20 @@ def pxCreateStructure(model, xyz_ang, mat, hip_stream=None):
     return h
 
 
+def pxCreateStructureHetero(model, xyz_ang, types, mat_a, mat_b, hip_stream=None):
+    """Two atom types: types[i] = 0 for mat_a, 1 for mat_b."""
+    xyz = np.ascontiguousarray(xyz_ang, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+    if len(t) != len(xyz):
+        raise PxError(PX_E_INVALID, "types and coordinates differ in length")
+    h = _vp()
+    ma = mat_a if isinstance(mat_a, pxMaterial) else material(mat_a)
+    mb = mat_b if isinstance(mat_b, pxMaterial) else material(mat_b)
+    _check(load().pxCreateStructureHetero(int(model), len(xyz), _ptr(xyz), t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                          ctypes.byref(ma), ctypes.byref(mb), hip_stream, ctypes.byref(h)))
+    return h
+
+
 def pxSetFrequencies(h, omega_ev, pol_mask, e0_au, alpha_ib=None):
     om = np.ascontiguousarray(omega_ev, dtype=np.float64)
     aib = None if alpha_ib is None else np.ascontiguousarray(np.asarray(alpha_ib, dtype=np.complex128)).view(np.float64)
@@ -197,13 +214,15 @@ def pxGetSolveStats(h, ncol):
     return np.array(it[:]), np.array(cy[:]), rr
 
 
-def pxApplyOperator(h, precision, omega_ev, x, alpha_ib=None):
+def pxApplyOperator(h, precision, omega_ev, x, alpha_ib=None, het=False):
     x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
     ncol = x.shape[0]
     om = np.ascontiguousarray(np.broadcast_to(np.asarray(omega_ev, dtype=np.float64), (ncol,)))
     aib = None
     if alpha_ib is not None:
-        aib = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha_ib, dtype=np.complex128), (ncol,))).view(np.float64)
+        a = np.asarray(alpha_ib, dtype=np.complex128)
+        # two-type structures: alpha_IB of type A and of type B per column
+        aib = np.ascontiguousarray(np.broadcast_to(a, (ncol, 2) if het else (ncol,))).view(np.float64)
     y = np.zeros_like(x)
     _check(load().pxApplyOperator(h, int(precision), ncol, _ptr(om), _ptr(aib), _ptr(x.view(np.float64)),
                                   _ptr(y.view(np.float64))))
@@ -336,11 +355,18 @@ class Server:
 
 
 class Structure:
-    """One nanostructure on the GPU (see include/plasmonx.h)."""
+    """One nanostructure on the GPU (see include/plasmonx.h).  With `types`
+    and `params_b` it is a two-type structure (pxCreateStructureHetero); its
+    alpha_ib arguments then hold (alpha_IB of A, alpha_IB of B) per frequency
+    or column, shape (n, 2)."""
 
-    def __init__(self, model, xyz_ang, params, hip_stream=None):
+    def __init__(self, model, xyz_ang, params, hip_stream=None, types=None, params_b=None):
         self.model = int(model)
-        self.h = pxCreateStructure(model, xyz_ang, params, hip_stream)
+        self.het = types is not None
+        if self.het:
+            self.h = pxCreateStructureHetero(model, xyz_ang, types, params, params_b, hip_stream)
+        else:
+            self.h = pxCreateStructure(model, xyz_ang, params, hip_stream)
         self.n, self.nu = pxGetSize(self.h)
         self.n_omega = 0
         self.ncol = 0
@@ -364,7 +390,7 @@ class Structure:
         return pxGetSolveStats(self.h, self.ncol)
 
     def apply(self, precision, omega_ev, x, alpha_ib=None):
-        return pxApplyOperator(self.h, precision, omega_ev, x, alpha_ib)
+        return pxApplyOperator(self.h, precision, omega_ev, x, alpha_ib, self.het)
 
     def timings(self):
         return pxGetTimings(self.h)

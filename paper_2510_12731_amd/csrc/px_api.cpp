@@ -67,11 +67,50 @@ void release_blas(void* handle)
     if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
+void het_factors(const pxStructure_t* s, double w, const double* aib4, double2 out[6])
+{
+    const double dr[2] = {s->drude, s->drude_b};
+    const double tau[2] = {s->mat.tau, s->mat_b.tau};
+    for (int t = 0; t < 2; ++t) {
+        const int o = 1 - t;
+        double zr, zi;
+        shift_q(dr[t], tau[t], w, zr, zi);
+        out[t] = make_double2(zr, zi);
+        // rho_t phi_t = (n_o tau_o / n_t tau_t) (1 - i w tau_t) / (1 - i w tau_o)
+        const double rho = dr[o] * tau[o] / (dr[t] * tau[t]);
+        const double ai = -w * tau[t], bi = -w * tau[o];
+        const double den = 1.0 + bi * bi;
+        const double fr = (1.0 + ai * bi) / den, fi = (ai - bi) / den;
+        out[2 + t] = make_double2(0.5 * (1.0 + rho * fr), 0.5 * rho * fi);
+        out[4 + t] = make_double2(0.0, 0.0);
+        if (aib4) {
+            const double ar = aib4[2 * t], aim = aib4[2 * t + 1];
+            const double d = ar * ar + aim * aim;
+            out[4 + t] = make_double2(ar / d, -aim / d);
+        }
+    }
+}
+
 void prepare_solve(pxStructure_t* s)
 {
     const int ncol = s->ncol;
     const int64_t nup = s->g.nup;
-    px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    double2* d_gam = nullptr;
+    if (s->het) {
+        // gamma_A, gamma_B of every column's frequency
+        std::vector<double2> gam((size_t)2 * s->ldg, make_double2(0.0, 0.0));
+        for (int c = 0; c < ncol; ++c) {
+            double2 f[6];
+            het_factors(s, s->omega_au[c / s->npol], nullptr, f);
+            gam[c] = f[2];
+            gam[s->ldg + c] = f[3];
+        }
+        d_gam = dalloc<double2>((size_t)2 * s->ldg);
+        HC(hipMemcpyAsync(d_gam, gam.data(), sizeof(double2) * 2 * s->ldg, hipMemcpyHostToDevice, s->st));
+        px::build_rhs_het(s->g, s->d_col_pol, d_gam, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    } else {
+        px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    }
     px::fill_zero(s->x, sizeof(double2) * (size_t)nup * s->ldg, s->st);
     s->bnorm.assign(ncol, 0.0);
     const int nchunk = px::arnoldi_chunks(nup);
@@ -83,6 +122,7 @@ void prepare_solve(pxStructure_t* s)
     HC(hipStreamSynchronize(s->st));
     dfree(part);
     dfree(nr);
+    dfree(d_gam);
     s->iters.assign(ncol, 0);
     s->cycles.assign(ncol, 0);
     s->stall.assign(ncol, 0);
@@ -154,6 +194,7 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.map = dalloc<int32_t>(lda);
     W.zq = dalloc<double2>(lda);
     W.zmu = dalloc<double2>(lda);
+    W.het = dalloc<double2>((size_t)6 * lda);
     W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, 8);
     W.narrow = dalloc<double>(W.narrow_bytes / sizeof(double) + 1);
     W.split32 = dalloc<float>(px::tapply_f32_scratch_bytes(s->g, 2 * lda) / sizeof(float) + 1);
@@ -299,6 +340,16 @@ void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int 
     else apply_fly(s, f32, X, Y, ldx, ncols, stop);
 }
 
+// The sparse part of the operator on the active block, Y = T X given: the
+// homogeneous Kbar apply with per-column shifts, or the two-type S(w) apply.
+void sparse_apply(pxStructure_t* s, const void* Y, bool f32, int ldy, const double2* X, const double2* B,
+                  double2* out, int na, int lda, double mu_sign, const int32_t* stop = nullptr)
+{
+    Workspace& W = s->ws;
+    if (s->het) px::spmm_het(s->g, Y, f32, ldy, X, W.het, B, out, na, lda, mu_sign, s->st, stop);
+    else px::spmm_shift(s->g, Y, f32, ldy, X, W.zq, W.zmu, B, out, na, lda, mu_sign, s->st, stop);
+}
+
 // r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
 void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda,
               const pxSolveOptions& o)
@@ -313,7 +364,7 @@ void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* r
     const double nu = (double)s->g.nu;
     s->work[1] += 2.0 * nu * nu * 2.0 * na;
     s->work[2] += 80.0 * nu * na;
-    px::spmm_shift(s->g, W.Y64, false, 2 * lda, xs, W.zq, W.zmu, bs, rs, na, lda, SOLVER_MU_SIGN, s->st);
+    sparse_apply(s, W.Y64, false, 2 * lda, xs, bs, rs, na, lda, SOLVER_MU_SIGN);
 }
 
 void col_norms(pxStructure_t* s, const double2* v, int na, int lda, std::vector<double>& out)
@@ -329,6 +380,17 @@ void col_norms(pxStructure_t* s, const double2* v, int na, int lda, std::vector<
 
 void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
 {
+    if (s->het) {
+        std::vector<double2> h((size_t)6 * lda, make_double2(0, 0));
+        for (size_t k = 0; k < act.size(); ++k) {
+            const int w = act[k] / s->npol;
+            double2 f[6];
+            het_factors(s, s->omega_au[w], s->model == PX_WFQFMU ? &s->aib[4 * w] : nullptr, f);
+            for (int q = 0; q < 6; ++q) h[(size_t)q * lda + k] = f[q];
+        }
+        HC(hipMemcpyAsync(s->ws.het, h.data(), sizeof(double2) * 6 * lda, hipMemcpyHostToDevice, s->st));
+        return;
+    }
     std::vector<double2> zq(lda, make_double2(0, 0)), zm(lda, make_double2(0, 0));
     for (size_t k = 0; k < act.size(); ++k) {
         const int c = act[k];
@@ -453,8 +515,8 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
                 if (wide32) tapply(s, method, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop);
                 else tapply(s, method, false, vk, W.Y64, 2 * lda, 2 * lda, stop);
                 tm.mark(k, 1, s->st);
-                px::spmm_shift(s->g, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, W.zq,
-                               W.zmu, nullptr, W.w, na, lda, SOLVER_MU_SIGN, s->st, stop);
+                sparse_apply(s, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, nullptr, W.w,
+                             na, lda, SOLVER_MU_SIGN, stop);
                 tm.mark(k, 2, s->st);
                 if (dcgs2) {
                     // one dot pass and one update pass; column k-1 is finished here
@@ -618,8 +680,28 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
 
 const char* pxLastError(void) { return g_err.c_str(); }
 
-pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang, const pxMaterial* mat,
-                           void* hip_stream, pxStructure* out)
+namespace {
+
+// Drude weight n/m* of a material (graphene: E_F / (pi t_g)); the checks of
+// pxCreateStructure on its parameters.
+double drude_of(const pxMaterial& m)
+{
+    return m.fermi_energy_ev > 0.0 ? (m.fermi_energy_ev / EV_PER_HARTREE) / (PI * m.sheet_thickness)
+                                   : m.density / m.eff_mass;
+}
+
+pxStatus check_material(const pxMaterial& m, pxModel model)
+{
+    const double drude = drude_of(m);
+    if (!(m.a_eff > 0) || !(m.r_q > 0) || !(m.tau > 0) || !(drude > 0) || !std::isfinite(drude) || !(m.r0_ang > 0) ||
+        !(m.cutoff_ang > 0) || !(m.fermi_s > 0) || !std::isfinite(m.fermi_d))
+        return fail(PX_E_INVALID, "invalid material parameters");
+    if (model == PX_WFQFMU && !(m.r_mu > 0)) return fail(PX_E_INVALID, "r_mu must be > 0 for the dipole model");
+    return PX_OK;
+}
+
+pxStatus create_impl(pxModel model, int64_t n_atoms, const double* xyz_ang, const uint8_t* types,
+                     const pxMaterial* mat, const pxMaterial* mat_b, void* hip_stream, pxStructure* out)
 {
     g_err.clear();
     if (!out || !xyz_ang || !mat) return fail(PX_E_INVALID, "null argument");
@@ -629,12 +711,14 @@ pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang
     for (int64_t i = 0; i < n_atoms; ++i)
         if (!finite3(xyz_ang + 3 * i)) return fail(PX_E_INVALID, "non-finite coordinate");
     const pxMaterial& m = *mat;
-    double drude = m.fermi_energy_ev > 0.0 ? (m.fermi_energy_ev / EV_PER_HARTREE) / (PI * m.sheet_thickness)
-                                           : m.density / m.eff_mass;
-    if (!(m.a_eff > 0) || !(m.r_q > 0) || !(m.tau > 0) || !(drude > 0) || !std::isfinite(drude) || !(m.r0_ang > 0) ||
-        !(m.cutoff_ang > 0) || !(m.fermi_s > 0) || !std::isfinite(m.fermi_d))
-        return fail(PX_E_INVALID, "invalid material parameters");
-    if (model == PX_WFQFMU && !(m.r_mu > 0)) return fail(PX_E_INVALID, "r_mu must be > 0 for the dipole model");
+    if (check_material(m, model) != PX_OK) return PX_E_INVALID;
+    if (types) {
+        if (check_material(*mat_b, model) != PX_OK) return PX_E_INVALID;
+        if (mat_b->r_q != m.r_q || (model == PX_WFQFMU && mat_b->r_mu != m.r_mu))
+            return fail(PX_E_INVALID, "the two materials must share r_q (and r_mu)");
+        for (int64_t i = 0; i < n_atoms; ++i)
+            if (types[i] > 1) return fail(PX_E_INVALID, "atom types must be 0 or 1");
+    }
     return guarded([&]() -> pxStatus {
         int dev = 0;
         hipDeviceProp_t prop;
@@ -645,7 +729,12 @@ pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang
         auto* s = new pxStructure_t();
         s->model = model;
         s->mat = m;
-        s->drude = drude;
+        s->drude = drude_of(m);
+        if (types) {
+            s->het = true;
+            s->mat_b = *mat_b;
+            s->drude_b = drude_of(*mat_b);
+        }
         s->st = static_cast<hipStream_t>(hip_stream);
         s->g.model = (int)model;
         s->g.n = n_atoms;
@@ -658,7 +747,7 @@ pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang
         for (int64_t i = 0; i < 3 * n_atoms; ++i) xb[i] = xyz_ang[i] / ANG_PER_BOHR;
         int bad = 0;
         hipError_t e = px::build_geometry(s->g, xb.data(), m.cutoff_ang / ANG_PER_BOHR, m, m.r0_ang / ANG_PER_BOHR,
-                                          s->perm, &bad, s->st);
+                                          s->perm, &bad, s->st, types, types ? mat_b : nullptr);
         if (e != hipSuccess) {
             delete s;
             throw HipError{e, "build_geometry"};
@@ -680,6 +769,26 @@ pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang
     });
 }
 
+}  // namespace
+
+pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang, const pxMaterial* mat,
+                           void* hip_stream, pxStructure* out)
+{
+    return create_impl(model, n_atoms, xyz_ang, nullptr, mat, nullptr, hip_stream, out);
+}
+
+pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* xyz_ang, const uint8_t* types,
+                                 const pxMaterial* mat_a, const pxMaterial* mat_b, void* hip_stream,
+                                 pxStructure* out)
+{
+    if (!types || !mat_b) {
+        g_err.clear();
+        if (out) *out = nullptr;
+        return fail(PX_E_INVALID, "null argument");
+    }
+    return create_impl(model, n_atoms, xyz_ang, types, mat_a, mat_b, hip_stream, out);
+}
+
 pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask, double e0_au,
                           const double* alpha_ib)
 {
@@ -692,7 +801,8 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
         if (!(omega_ev[w] > 0) || !std::isfinite(omega_ev[w])) return fail(PX_E_INVALID, "frequencies must be > 0");
     if (s->model == PX_WFQFMU) {
         if (!alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
-        for (int w = 0; w < n_omega; ++w)
+        const int na = s->het ? 2 * n_omega : n_omega;
+        for (int w = 0; w < na; ++w)
             if (!std::isfinite(alpha_ib[2 * w]) || !std::isfinite(alpha_ib[2 * w + 1]) ||
                 (alpha_ib[2 * w] == 0.0 && alpha_ib[2 * w + 1] == 0.0))
                 return fail(PX_E_INVALID, "alpha_ib must be finite and non-zero");
@@ -707,8 +817,9 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
         s->e0 = e0_au;
         s->omega_au.resize(n_omega);
         for (int w = 0; w < n_omega; ++w) s->omega_au[w] = omega_ev[w] / EV_PER_HARTREE;
-        s->aib.assign(2 * n_omega, 0.0);
-        if (s->model == PX_WFQFMU) std::copy(alpha_ib, alpha_ib + 2 * n_omega, s->aib.begin());
+        const int naib = s->het ? 4 : 2;
+        s->aib.assign((size_t)naib * n_omega, 0.0);
+        if (s->model == PX_WFQFMU) std::copy(alpha_ib, alpha_ib + naib * n_omega, s->aib.begin());
         s->col_pol.clear();
         for (int w = 0; w < n_omega; ++w)
             for (int l = 0; l < 3; ++l)
@@ -754,6 +865,7 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
         if (!ss[k]) return fail(PX_E_INVALID, "null structure");
         if (ss[k]->ncol == 0) return fail(PX_E_STATE, "pxSolveBatch: every structure needs pxSetFrequencies");
         if (ss[k]->st != ss[0]->st) return fail(PX_E_INVALID, "pxSolveBatch: structures use different streams");
+        if (ss[k]->het) return fail(PX_E_INVALID, "pxSolveBatch: two-type structures are solved with pxSolveSpectrum");
     }
     return guarded([&]() -> pxStatus {
         auto t0 = std::chrono::steady_clock::now();
@@ -860,6 +972,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
     if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
     for (int c = 0; c < ncol; ++c)
         if (!(omega_ev[c] > 0)) return fail(PX_E_INVALID, "frequencies must be > 0");
+    const int naib = s->het ? 4 : 2;
     return guarded([&]() -> pxStatus {
         const bool mixed = precision == PX_MIXED;
         const int lda = pad_cols(ncol, !mixed);
@@ -870,25 +983,35 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
         HC(hipMemcpyAsync(din, x, sizeof(double2) * ncol * nu, hipMemcpyHostToDevice, s->st));
         px::permute_in(s->g, din, ncol, s->d_perm, W.xs, lda, s->st);
         std::vector<double2> zq(lda, make_double2(0, 0)), zm(lda, make_double2(0, 0));
+        std::vector<double2> h((size_t)6 * lda, make_double2(0, 0));
         for (int c = 0; c < ncol; ++c) {
+            const double w = omega_ev[c] / EV_PER_HARTREE;
+            const double* a = s->model == PX_WFQFMU ? alpha_ib + naib * c : nullptr;
+            if (s->het) {
+                double2 f[6];
+                het_factors(s, w, a, f);
+                for (int q = 0; q < 6; ++q) h[(size_t)q * lda + c] = f[q];
+                continue;
+            }
             double zr, zi;
-            shift_q(s->drude, s->mat.tau, omega_ev[c] / EV_PER_HARTREE, zr, zi);
+            shift_q(s->drude, s->mat.tau, w, zr, zi);
             zq[c] = make_double2(zr, zi);
-            if (s->model == PX_WFQFMU) {
-                shift_mu(alpha_ib[2 * c], alpha_ib[2 * c + 1], zr, zi);
+            if (a) {
+                shift_mu(a[0], a[1], zr, zi);
                 zm[c] = make_double2(zr, zi);
             }
         }
         HC(hipMemcpyAsync(W.zq, zq.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
         HC(hipMemcpyAsync(W.zmu, zm.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
+        HC(hipMemcpyAsync(W.het, h.data(), sizeof(double2) * 6 * lda, hipMemcpyHostToDevice, s->st));
         if (mixed) {
             px::to_f32(W.xs, W.X32, ncol, lda, nup, s->st);
             px::tapply_f32(s->g, W.X32, W.Y32, 2 * lda, 2 * lda, s->st, W.split32);
-            px::spmm_shift(s->g, W.Y32, true, 2 * lda, W.xs, W.zq, W.zmu, nullptr, W.w, ncol, lda, 1.0, s->st);
+            sparse_apply(s, W.Y32, true, 2 * lda, W.xs, nullptr, W.w, ncol, lda, 1.0);
         } else {
             px::tapply_f64(s->g, reinterpret_cast<const double*>(W.xs), W.Y64, 2 * lda, 2 * lda, s->st, W.narrow,
                            W.narrow_bytes);
-            px::spmm_shift(s->g, W.Y64, false, 2 * lda, W.xs, W.zq, W.zmu, nullptr, W.w, ncol, lda, 1.0, s->st);
+            sparse_apply(s, W.Y64, false, 2 * lda, W.xs, nullptr, W.w, ncol, lda, 1.0);
         }
         const int ncomp = s->model == PX_WFQFMU ? 4 : 1;
         double2* dout = dalloc<double2>((size_t)ncol * nu);
@@ -990,6 +1113,7 @@ pxStatus pxServerSubmit(pxServer sv, pxStructure s)
     if (!sv || !s) return fail(PX_E_INVALID, "null argument");
     if (s->ncol == 0) return fail(PX_E_STATE, "pxServerSubmit: call pxSetFrequencies first");
     if (s->st != sv->st) return fail(PX_E_INVALID, "pxServerSubmit: structure uses another stream");
+    if (s->het) return fail(PX_E_INVALID, "pxServerSubmit: two-type structures are solved with pxSolveSpectrum");
     if (sv->eng->rows_for(s) > sv->eng->rows_capacity())
         return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");
     return guarded([&]() -> pxStatus {

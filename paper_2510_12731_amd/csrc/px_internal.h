@@ -47,6 +47,11 @@ struct Geometry {
     int64_t nnz = 0;
     // kernel constants (bohr)
     double r_q = 0, r_mu = 0;
+    // two atom types (null for homogeneous structures): type per atom in
+    // Morton order, and per real atom (same-type K row sum, other-type K row
+    // sum, same-type and other-type neighbour counts)
+    uint8_t* type = nullptr;
+    double4* hrow = nullptr;
 };
 
 // ---- T-apply launchers (px_tapply.hip) -------------------------------------
@@ -91,8 +96,19 @@ class GroupedTApply {
 };
 
 // ---- other kernels (px_kernels.hip) ----------------------------------------
+// types_host (n atoms, 0/1, may be null) with mb: a two-type structure; unlike
+// pairs exchange with the mean of the two materials' A, r0, d, s and cutoff.
 hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
-                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st);
+                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st,
+                          const uint8_t* types_host = nullptr, const pxMaterial* mb = nullptr);
+// Two-type sparse apply and right-hand side (the structure must have types):
+// het [6][lda] per column: z_q,A, z_q,B, gamma_A, gamma_B, 1/alpha_IB,A, 1/alpha_IB,B;
+// gam [2][ldb]: gamma_A, gamma_B per column.
+void spmm_het(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* het,
+              const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st,
+              const int32_t* stop = nullptr);
+void build_rhs_het(const Geometry& g, const int32_t* col_pol, const double2* gam, double e0, double2* b, int ncol,
+                   int ldb, double mu_sign, hipStream_t st);
 
 struct Shifts {            // per active slot
     double2* zq = nullptr;

@@ -113,6 +113,13 @@ struct KappaConst {
     double a_eff, fd, s_r0, rc, rc2, min_r;
 };
 
+// Exchange constants of the pair types AA, AB (= BA), BB; homogeneous
+// structures use k[0] only (type == nullptr).
+struct KappaSet {
+    KappaConst k[3];
+    double rc_max;
+};
+
 // Eqs. (fermi), (kappa): K_ij = [1 - f(r)] A / r for r <= cutoff.
 __device__ __forceinline__ double kappa_val(double r, const KappaConst& k)
 {
@@ -134,7 +141,8 @@ __device__ __forceinline__ float gap2(float4 alo, float4 ahi, float4 blo, float4
 template <int PASS>
 __global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
                                                    const float4* __restrict__ ghi, int64_t n, int64_t np,
-                                                   KappaConst kc, int32_t* __restrict__ cnt,
+                                                   KappaSet ks, const uint8_t* __restrict__ type,
+                                                   int32_t* __restrict__ cnt,
                                                    const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                    double* __restrict__ val, int* __restrict__ bad)
 {
@@ -150,7 +158,8 @@ __global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x
         bhi = make_float4(fmaxf(bhi.x, b.x), fmaxf(bhi.y, b.y), fmaxf(bhi.z, b.z), 0.f);
     }
     const double4 pi = x64[i];
-    const float lim = (float)(kc.rc * 1.0001 + 1e-3);
+    const float lim = (float)(ks.rc_max * 1.0001 + 1e-3);
+    const int ti = (type && i < n) ? type[i] : 0;
     const int64_t ngroups = (n + GROUP - 1) / GROUP;
     int count = 0;
     double ksum = 0.0;
@@ -167,6 +176,7 @@ __global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x
                 double4 pj = x64[j];
                 double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
                 double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
                 if (r <= kc.rc) ksum += kappa_val(r, kc);
             }
         }
@@ -190,6 +200,7 @@ __global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x
             double4 pj = sp[k];
             double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
             double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
             if (PASS == 0 && r < kc.min_r) *bad = 1;
             if (r <= kc.rc) {
                 if (PASS == 0) {
@@ -236,6 +247,40 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ cnt, 
         __syncthreads();
     }
     if (threadIdx.x == 0) row_ptr[n] = carry;
+}
+
+// Atom types in Morton order (ghost atoms type A).
+__global__ void k_gather_types(const uint8_t* __restrict__ types, const int32_t* __restrict__ perm, int64_t n,
+                               int64_t np, uint8_t* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    out[i] = i < n ? types[perm[i]] : 0;
+}
+
+// Per row of a two-type structure: the exchange K summed over same-type and
+// over other-type neighbours, and the two neighbour counts (Eq. polar-finale).
+__global__ void k_het_rows(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           const double* __restrict__ cv, const uint8_t* __restrict__ type, int64_t n,
+                           double4* __restrict__ hrow)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ti = type[i];
+    double ks = 0.0, ko = 0.0;
+    int ns = 0, no = 0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t j = ci[e];
+        if (j == i) continue;
+        if (type[j] == ti) {
+            ks += cv[e];
+            ++ns;
+        } else {
+            ko += cv[e];
+            ++no;
+        }
+    }
+    hrow[i] = make_double4(ks, ko, (double)ns, (double)no);
 }
 
 // ---------------------------------------------------------------- sparse
@@ -324,6 +369,120 @@ __global__ __launch_bounds__(256) void k_rhs(const int32_t* __restrict__ rp, con
         v = (comp - 1 == l) ? mu_sign * e0 : 0.0;
     }
     b[o] = make_double2(v, 0.0);
+}
+
+// Two atom types (Eq. wfqfmu-leghe): the charge rows apply
+// S(w) = (Kbar + Hbar(w)) / 2, whose off-diagonal entries are K_ij for like
+// pairs and gamma_{t_i}(w) K_ij for unlike ones, gamma_t = (1 + rho_t phi_t) / 2,
+// and whose diagonal is -(Ks_i + gamma_{t_i} Ko_i) (hrow: same-type and
+// other-type row sums of K).  Shifts per atom: z_q of the atom's type, and
+// z_mu,i = -[(N_same + 1) / alpha_t + N_other / alpha_o] / (N + 1)
+// (Eq. polar-finale).  het: [6][lda] complex per column: z_q,A, z_q,B,
+// gamma_A, gamma_B, 1/alpha_IB,A, 1/alpha_IB,B.  Otherwise as k_spmm_shift.
+template <typename TY>
+__global__ __launch_bounds__(256) void k_spmm_het(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                  const double* __restrict__ cv, const uint8_t* __restrict__ type,
+                                                  const double4* __restrict__ hrow, const TY* __restrict__ Y,
+                                                  int ldy, const double2* __restrict__ X,
+                                                  const double2* __restrict__ het, const double2* __restrict__ B,
+                                                  double2* __restrict__ W, int64_t n, int64_t np, int64_t nup,
+                                                  int na, int lda, double mu_sign, const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;   // every column of the block is done
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= lda) return;
+    const size_t o = (size_t)r * lda + c;
+    const int64_t comp = r / np, i = r - comp * np;
+    if (c >= na || i >= n) {
+        W[o] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int ti = type[i];
+    double ar = 0.0, ai = 0.0;
+    double2 z;
+    if (comp == 0) {
+        const double2 g = het[(2 + ti) * (size_t)lda + c];
+        double lr = 0.0, li = 0.0, ur = 0.0, ui = 0.0;   // like and unlike neighbour sums
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t j = ci[e];
+            if (j == i) continue;
+            const double k = cv[e];
+            const TY* yr = Y + (size_t)j * ldy + 2 * c;
+            if (type[j] == ti) {
+                lr = fma(k, (double)yr[0], lr);
+                li = fma(k, (double)yr[1], li);
+            } else {
+                ur = fma(k, (double)yr[0], ur);
+                ui = fma(k, (double)yr[1], ui);
+            }
+        }
+        const double4 h = hrow[i];
+        const TY* yi = Y + (size_t)i * ldy + 2 * c;
+        const double dr = -(h.x + g.x * h.y), di = -(g.y * h.y);          // S_ii
+        const double y0 = (double)yi[0], y1 = (double)yi[1];
+        ar = lr + (g.x * ur - g.y * ui) + (dr * y0 - di * y1);
+        ai = li + (g.x * ui + g.y * ur) + (dr * y1 + di * y0);
+        z = het[(size_t)ti * lda + c];
+    } else {
+        const TY* yr = Y + (size_t)r * ldy + 2 * c;
+        ar = (double)yr[0];
+        ai = (double)yr[1];
+        const double4 h = hrow[i];
+        const double2 own = het[(4 + ti) * (size_t)lda + c], oth = het[(5 - ti) * (size_t)lda + c];
+        const double inv = 1.0 / (h.z + h.w + 1.0);
+        z = make_double2(-((h.z + 1.0) * own.x + h.w * oth.x) * inv, -((h.z + 1.0) * own.y + h.w * oth.y) * inv);
+    }
+    const double2 x = X[o];
+    double2 w = make_double2(ar - (z.x * x.x - z.y * x.y), ai - (z.x * x.y + z.y * x.x));
+    if (comp != 0) w = make_double2(mu_sign * w.x, mu_sign * w.y);
+    if (B != nullptr) {
+        const double2 b = B[o];
+        w = make_double2(b.x - w.x, b.y - w.y);
+    }
+    W[o] = w;
+}
+
+// Right-hand side of a two-type structure: diag(S(w_c), I) (-V; E) per
+// column, -V_j = E0 r_j.l; gam: [2][ldg] gamma_A, gamma_B of each column.
+__global__ __launch_bounds__(256) void k_rhs_het(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ cv, const uint8_t* __restrict__ type,
+                                                 const double4* __restrict__ hrow, const double4* __restrict__ x64,
+                                                 const int32_t* __restrict__ col_pol, const double2* __restrict__ gam,
+                                                 double e0, double2* __restrict__ b, int64_t n, int64_t np,
+                                                 int64_t nup, int ncol, int ldb, double mu_sign)
+{
+    const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= nup || c >= ldb) return;
+    const size_t o = (size_t)r * ldb + c;
+    const int64_t comp = r / np, i = r - comp * np;
+    if (c >= ncol || i >= n) {
+        b[o] = make_double2(0.0, 0.0);
+        return;
+    }
+    const int l = col_pol[c];
+    if (comp != 0) {
+        b[o] = make_double2((comp - 1 == l) ? mu_sign * e0 : 0.0, 0.0);
+        return;
+    }
+    const int ti = type[i];
+    const double2 g = gam[(size_t)ti * ldb + c];
+    double lv = 0.0, uv = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t j = ci[e];
+        if (j == i) continue;
+        const double4 p = x64[j];
+        const double coord = (l == 0) ? p.x : (l == 1) ? p.y : p.z;
+        if (type[j] == ti) lv = fma(cv[e], coord, lv);
+        else uv = fma(cv[e], coord, uv);
+    }
+    const double4 h = hrow[i];
+    const double4 p = x64[i];
+    const double xi = (l == 0) ? p.x : (l == 1) ? p.y : p.z;
+    const double vr = lv + g.x * uv - (h.x + g.x * h.y) * xi;
+    const double vi = g.y * uv - g.y * h.y * xi;
+    b[o] = make_double2(e0 * vr, e0 * vi);
 }
 
 // ---------------------------------------------------------------- Arnoldi
@@ -1234,7 +1393,8 @@ inline int arn_chunks(int64_t rows) { return (int)((rows + ARN_ROWS - 1) / ARN_R
 // ============================================================== launchers
 
 hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
-                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st)
+                          double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st,
+                          const uint8_t* types_host, const pxMaterial* mb)
 {
     const int64_t n = g.n, np = g.np;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -1251,6 +1411,7 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
     uint64_t* d_keys = nullptr;
     int32_t *d_cnt = nullptr, *d_perm = nullptr;
     int* d_bad = nullptr;
+    uint8_t* d_types = nullptr;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
     PXCHK(hipMalloc(&d_xyz, sizeof(double) * 3 * n));
@@ -1279,15 +1440,40 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
     hipLaunchKernelGGL(k_group_bbox, dim3((unsigned)((np / GROUP + 255) / 256)), dim3(256), 0, st, g.xyz64,
                        np / GROUP, g.glo, g.ghi);
     {
-        KappaConst kc;
+        KappaSet ks;
+        KappaConst& kc = ks.k[0];
         kc.a_eff = m.a_eff;
         kc.fd = m.fermi_d;
         kc.s_r0 = m.fermi_s * r0_bohr;
         kc.rc = cutoff_bohr;
         kc.rc2 = cutoff_bohr * cutoff_bohr;
         kc.min_r = 1e-6 / ANG;
+        ks.k[1] = ks.k[2] = kc;
+        ks.rc_max = kc.rc;
+        if (types_host && mb) {
+            // type B, and unlike pairs with the mean of the two types' A, r0, d, s and cutoff
+            const double r0b = mb->r0_ang / ANG, rcb = mb->cutoff_ang / ANG;
+            KappaConst& kb = ks.k[2];
+            kb.a_eff = mb->a_eff;
+            kb.fd = mb->fermi_d;
+            kb.s_r0 = mb->fermi_s * r0b;
+            kb.rc = rcb;
+            kb.rc2 = rcb * rcb;
+            KappaConst& kab = ks.k[1];
+            kab.a_eff = 0.5 * (m.a_eff + mb->a_eff);
+            kab.fd = 0.5 * (m.fermi_d + mb->fermi_d);
+            kab.s_r0 = 0.5 * (m.fermi_s + mb->fermi_s) * 0.5 * (r0_bohr + r0b);
+            kab.rc = 0.5 * (cutoff_bohr + rcb);
+            kab.rc2 = kab.rc * kab.rc;
+            ks.rc_max = std::max(kc.rc, std::max(kb.rc, kab.rc));
+            PXCHK(hipMalloc(&d_types, n));
+            PXCHK(hipMalloc(&g.type, np));
+            PXCHK(hipMemcpyAsync(d_types, types_host, n, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_gather_types, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d_types, d_perm, n,
+                               np, g.type);
+        }
         hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
-                           np, kc, d_cnt, nullptr, nullptr, nullptr, d_bad);
+                           np, ks, g.type, d_cnt, nullptr, nullptr, nullptr, d_bad);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cnt, n, g.row_ptr);
         int32_t nnz = 0;
         PXCHK(hipMemcpyAsync(&nnz, g.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1297,7 +1483,12 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
         PXCHK(hipMalloc(&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
         PXCHK(hipMalloc(&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
         hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
-                           np, kc, nullptr, g.row_ptr, g.col, g.val, d_bad);
+                           np, ks, g.type, nullptr, g.row_ptr, g.col, g.val, d_bad);
+        if (g.type) {
+            PXCHK(hipMalloc(&g.hrow, sizeof(double4) * n));
+            hipLaunchKernelGGL(k_het_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.row_ptr, g.col, g.val,
+                               g.type, n, g.hrow);
+        }
     }
     perm_host.resize(n);
     PXCHK(hipMemcpyAsync(perm_host.data(), d_perm, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
@@ -1310,6 +1501,7 @@ fail:
     (void)hipFree(d_cnt);
     (void)hipFree(d_perm);
     (void)hipFree(d_bad);
+    (void)hipFree(d_types);
     return e;
 }
 
@@ -1547,6 +1739,26 @@ void dcgs2_update(double2* V, int64_t vstride, int k, const double2* coefQ, cons
 {
     hipLaunchKernelGGL(k_dcgs2_update, dim3(update_chunks(nup), (unsigned)((na + 63) / 64)), dim3(256), 0, st, V,
                        vstride, k, coefQ, coefV, w, norm_partial, na, lda, nup, chunk_seg, chunk_seg ? ldc : lda, stop);
+}
+
+void spmm_het(const Geometry& g, const void* Y, bool y_is_f32, int ldy, const double2* X, const double2* het,
+              const double2* B, double2* W, int na, int lda, double mu_sign, hipStream_t st, const int32_t* stop)
+{
+    const dim3 grid((unsigned)((g.nup + 3) / 4), (unsigned)((lda + 63) / 64));
+    if (y_is_f32)
+        hipLaunchKernelGGL(k_spmm_het<float>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val, g.type, g.hrow,
+                           static_cast<const float*>(Y), ldy, X, het, B, W, g.n, g.np, g.nup, na, lda, mu_sign, stop);
+    else
+        hipLaunchKernelGGL(k_spmm_het<double>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val, g.type, g.hrow,
+                           static_cast<const double*>(Y), ldy, X, het, B, W, g.n, g.np, g.nup, na, lda, mu_sign, stop);
+}
+
+void build_rhs_het(const Geometry& g, const int32_t* col_pol, const double2* gam, double e0, double2* b, int ncol,
+                   int ldb, double mu_sign, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rhs_het, dim3((unsigned)((g.nup + 3) / 4), (unsigned)((ldb + 63) / 64)), dim3(256), 0, st,
+                       g.row_ptr, g.col, g.val, g.type, g.hrow, g.xyz64, col_pol, gam, e0, b, g.n, g.np, g.nup, ncol,
+                       ldb, mu_sign);
 }
 
 }  // namespace px

@@ -61,6 +61,7 @@ struct Workspace {
     double *cs = nullptr, *nrm = nullptr, *target = nullptr;
     int32_t *done = nullptr, *steps = nullptr, *map = nullptr;
     double2 *zq = nullptr, *zmu = nullptr;
+    double2* het = nullptr;   // two-type shifts and factors, [6][lda]
     double* narrow = nullptr;
     size_t narrow_bytes = 0;
     float* split32 = nullptr;
@@ -68,7 +69,7 @@ struct Workspace {
     void release()
     {
         void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, H, G, coefQ, coefV, aux, sn, gv, y, cs, nrm, target,
-                      done, steps, map, zq, zmu, narrow, split32};
+                      done, steps, map, zq, zmu, het, narrow, split32};
         for (void* p : ps) dfree(p);
         *this = Workspace();
     }
@@ -186,13 +187,17 @@ struct pxStructure_t {
     pxModel model = PX_WFQ;
     pxMaterial mat{};
     double drude = 0.0;
+    // two atom types: the second material, its Drude weight (types live in g)
+    bool het = false;
+    pxMaterial mat_b{};
+    double drude_b = 0.0;
     hipStream_t st = nullptr;
     std::vector<int32_t> perm;
     int32_t* d_perm = nullptr;
     // frequencies and columns (frequency-major: column = w * npol + p)
     int n_omega = 0, npol = 0, ncol = 0, ldg = 0;
     std::vector<double> omega_au;
-    std::vector<double> aib;   // 2 * n_omega
+    std::vector<double> aib;   // 2 * n_omega (4 * n_omega for two types)
     std::vector<int32_t> col_pol;
     uint32_t pol_mask = 0;
     double e0 = 0.0;
@@ -227,7 +232,7 @@ struct pxStructure_t {
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, d_perm, d_col_pol, d_omega, x, b, t32, t64};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, d_perm, d_col_pol, d_omega, x, b, t32, t64};
         for (void* p : ps) pxs::dfree(p);
         pxs::release_blas(blas);
     }

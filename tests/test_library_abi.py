@@ -100,3 +100,36 @@ def test_null_handles_rejected(lib):
     assert lib.pxGetSpectrum(None, None, None) == px.PX_E_INVALID
     assert lib.pxGetSize(None, None, None) == px.PX_E_INVALID
     lib.pxDestroyStructure(None)
+
+
+@pytest.mark.parametrize("case", ["null_types", "null_mat_b", "bad_type", "r_q_differs", "r_mu_differs",
+                                  "bad_tau_b"])
+def test_invalid_two_type_inputs_rejected_on_host(lib, case):
+    from workloads import materials as M
+    xyz = np.zeros((3, 3))
+    xyz[1, 0] = 2.9
+    xyz[2, 1] = 2.9
+    ma, mb = px.material(M.load("ag_wfqfmu")), px.material(M.load("au_wfqfmu"))
+    types = np.array([0, 1, 0], dtype=np.uint8)
+    model = px.PX_WFQFMU
+    tp = types.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    mbp = ctypes.byref(mb)
+    if case == "null_types":
+        tp = None
+    elif case == "null_mat_b":
+        mbp = None
+    elif case == "bad_type":
+        types[2] = 2
+    elif case == "r_q_differs":
+        mb.r_q = 1.01 * ma.r_q
+    elif case == "r_mu_differs":
+        mb.r_mu = 0.9 * ma.r_mu
+    elif case == "bad_tau_b":
+        mb.tau = -1.0
+    h = ctypes.c_void_p()
+    xp = np.ascontiguousarray(xyz)
+    st = lib.pxCreateStructureHetero(model, 3, xp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), tp,
+                                     ctypes.byref(ma), mbp, None, ctypes.byref(h))
+    assert st == px.PX_E_INVALID
+    assert h.value is None
+    assert len(px.pxLastError()) > 0
