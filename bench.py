@@ -270,6 +270,75 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
                 sigma_rel_err_mix_vs_alone=err)
 
 
+HC_EV_NM = 1239.84198   # h c in eV nm
+
+
+def alloy_solve(pxm, c, precision):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pxm.Structure(c["model"], c["xyz"], c["params_a"], pxm.default_stream(), types=c["types"],
+                      params_b=c["params_b"])
+    s.set_frequencies(c["omega_ev"], c["pol_mask"], c["e0"], np.stack([c["alpha_ib_a"], c["alpha_ib_b"]], axis=1))
+    st = s.solve(precision=precision, rel_tol=1e-8)
+    sigma = s.spectrum()[1]
+    it, cyc, rr = s.stats()
+    s.close()
+    torch.cuda.synchronize()
+    return dict(seconds=time.perf_counter() - t0, status=int(st), sigma=sigma, iters=it, relres=rr)
+
+
+def alloy_extra(pxm, step_ev=0.01, fp64_fracs=(0.5,)):
+    """The Ag-Au nanoalloy series: 1289-atom spheres with 0-100 % Au in steps
+    of 10 %, two-type omegaFQFmu, 2.0-4.5 eV, x/y/z.  Reports the solve rate,
+    the plasmon resonance (peak of sigma_abs) per composition with the linear
+    fit of its wavelength against the Au fraction and the exponential fit of
+    its height, and the mixed path against the FP64 path on some fractions."""
+    from workloads import configs as C
+    fracs = [k / 10 for k in range(11)]
+    cols = 0
+    secs = 0.0
+    prf_ev, peak, status, it_max = [], [], [], []
+    sig = {}
+    for f in fracs:
+        c = C.alloy_sphere(f, step_ev=step_ev)
+        r = alloy_solve(pxm, c, pxm.PX_MIXED)
+        ncol = len(c["omega_ev"]) * 3
+        cols += ncol
+        secs += r["seconds"]
+        k = int(np.argmax(r["sigma"]))
+        prf_ev.append(float(c["omega_ev"][k]))
+        peak.append(float(r["sigma"][k]))
+        status.append(r["status"])
+        it_max.append(int(r["iters"].max()))
+        sig[f] = r["sigma"]
+        log(f"[bench] alloy {int(round(100 * f))}% Au: {r['seconds']:.2f} s, PRF {prf_ev[-1]:.2f} eV, "
+            f"iters max {it_max[-1]}")
+    x = 100.0 * np.array(fracs)
+    lam = HC_EV_NM / np.array(prf_ev)
+    slope, icpt = np.polyfit(x, lam, 1)
+    r2 = 1.0 - np.sum((lam - (slope * x + icpt)) ** 2) / np.sum((lam - lam.mean()) ** 2)
+    lslope, licpt = np.polyfit(x, np.log(peak), 1)
+    lp = np.log(peak)
+    r2_int = 1.0 - np.sum((lp - (lslope * x + licpt)) ** 2) / np.sum((lp - lp.mean()) ** 2)
+    out = dict(structures=len(fracs), n_atoms=1289, n_omega=len(c["omega_ev"]), columns=cols,
+               mixed_seconds=round(secs, 2), mixed_solves_per_s=round(cols / secs, 2), status=status,
+               iterations_max=it_max, prf_ev=prf_ev, prf_nm=[round(v, 1) for v in lam.tolist()],
+               prf_slope_nm_per_pct_au=round(float(slope), 3), prf_linear_r2=round(float(r2), 4),
+               peak_sigma_bohr2=[round(v, 2) for v in peak],
+               peak_log_slope_per_pct_au=round(float(lslope), 5), peak_exponential_r2=round(float(r2_int), 4))
+    fp = []
+    for f in fp64_fracs:
+        c = C.alloy_sphere(f, step_ev=step_ev)
+        r64 = alloy_solve(pxm, c, pxm.PX_FP64)
+        ncol = len(c["omega_ev"]) * 3
+        fp.append(dict(frac_au=f, fp64_solves_per_s=round(ncol / r64["seconds"], 2), status=r64["status"],
+                       sigma_rel_err_mixed_vs_fp64=float(np.max(np.abs(sig[f] - r64["sigma"])) /
+                                                         np.max(np.abs(r64["sigma"])))))
+    out["fp64"] = fp
+    return out
+
+
 def torch_free_bytes():
     import torch
     free, total = torch.cuda.mem_get_info()
@@ -292,7 +361,7 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
     ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "batch-full", "serving-full"],
+                    choices=["sphere", "batch-full", "serving-full", "alloys"],
                     help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
                          "serving mix, printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
@@ -335,6 +404,10 @@ def main():
         print(json.dumps({"workload": "graphene_batch_64", "fp64_per_structure_s": round(t64, 2),
                           "fp64_per_structure_solves_per_s": round(cols / t64, 2),
                           "speedup": round(t64 / rb["seconds"], 2), "sigma_rel_err_vs_fp64": err}), flush=True)
+        return
+    if args.workload == "alloys":
+        print(json.dumps({"workload": "agau_alloys_1289", **alloy_extra(pxm, fp64_fracs=(0.0, 0.5, 1.0))}),
+              flush=True)
         return
     if args.workload == "serving-full":
         out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75)
@@ -434,8 +507,9 @@ def main():
                                                "hand-written FP64 kernels (T on the fly)",
                                         iterations=r64["iters"].tolist(), seconds=round(tb - ta, 2))
         extra["speedup_vs_fp64_one_column"] = round(value / v64, 2)
-        sig_ref = r64["sigma"]
-        extra["sigma_mixed_vs_fp64_sample_rel"] = None
+        ax = last["alpha"][idx, 0, 0]
+        a64 = r64["alpha"][:, 0, 0]
+        extra["alpha_xx_mixed_vs_fp64_sample_rel"] = float(np.max(np.abs(ax - a64)) / np.max(np.abs(a64)))
     if not args.no_fp64_blocked:
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -464,6 +538,8 @@ def main():
                                                         for a, b in zip(rb["sigma"], seq)))
         log("[bench] serving extra ...")
         extra["serving"] = serving_extra(pxm, 16, 1000, 4000, 5, 0.75)
+        log("[bench] alloy series extra ...")
+        extra["alloys"] = alloy_extra(pxm)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -134,6 +134,19 @@ typedef struct {
  *                    faster; PX_TAPPLY_ON_THE_FLY / PX_TAPPLY_STORED force one
  *                    (STORED fails with PX_E_OOM if T does not fit).
  *                    pxSolveBatch and the server always generate T on the fly.
+ *   shifted          pxSolveSpectrum on a one-material PX_WFQ structure: 1
+ *                    (default) first runs one real Arnoldi process on Kbar T
+ *                    per polarization, in FP64, and takes every frequency's
+ *                    GMRES iterate from it (the right-hand side does not depend
+ *                    on the frequency and the frequency only shifts the
+ *                    operator, so all frequencies share one Krylov space);
+ *                    columns it leaves above rel_tol continue in the blocked
+ *                    solver from its iterate.  0 = blocked solver only.
+ *                    Ignored for PX_WFQFMU, two-type structures, pxSolveBatch
+ *                    and the server.
+ *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 20000]
+ *                    (3000; lowered to keep its basis within a quarter of the
+ *                    free device memory)
  */
 typedef struct {
     int32_t precision;
@@ -149,6 +162,8 @@ typedef struct {
     int32_t ortho;
     int32_t graph_steps;
     int32_t t_apply;
+    int32_t shifted;
+    int32_t shifted_max_steps;
 } pxSolveOptions;
 
 typedef struct pxStructure_t* pxStructure;

@@ -47,7 +47,8 @@ class pxSolveOptions(ctypes.Structure):
                 ("max_cycles", ctypes.c_int32), ("max_block_cols", ctypes.c_int32),
                 ("inner_reduction", ctypes.c_double), ("timings", ctypes.c_int32), ("stall_cycles", ctypes.c_int32),
                 ("max_restart_m", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("ortho", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("t_apply", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("t_apply", ctypes.c_int32), ("shifted", ctypes.c_int32),
+                ("shifted_max_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -269,7 +270,7 @@ def pxLastError():
 
 def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
                   inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
-                  ortho=None, graph_steps=None, t_apply=None):
+                  ortho=None, graph_steps=None, t_apply=None, shifted=None, shifted_max_steps=None):
     o = pxDefaultSolveOptions()
     o.precision = int(precision)
     o.restart_m = int(restart_m)
@@ -287,6 +288,10 @@ def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400
         o.graph_steps = int(graph_steps)
     if t_apply is not None:
         o.t_apply = int(t_apply)
+    if shifted is not None:
+        o.shifted = int(shifted)
+    if shifted_max_steps is not None:
+        o.shifted_max_steps = int(shifted_max_steps)
     return o
 
 

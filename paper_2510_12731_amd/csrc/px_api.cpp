@@ -598,6 +598,138 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
     }
 }
 
+// ---- shared-Krylov phase: every frequency of a one-material omegaFQ structure
+// from one real Arnoldi process per polarization (px_shifted.hip) ----------
+
+// Device buffers that live for one call.
+struct Scratch {
+    std::vector<void*> ps;
+    template <typename T>
+    T* get(size_t count)
+    {
+        T* p = dalloc<T>(count);
+        ps.push_back(p);
+        return p;
+    }
+    ~Scratch()
+    {
+        for (void* p : ps) dfree(p);
+    }
+};
+
+bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
+{
+    return o.shifted == 1 && s->model == PX_WFQ && !s->het;
+}
+
+void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
+{
+    const int npol = s->npol, R = npol == 3 ? 4 : 2, P = s->ncol;
+    const int64_t nup = s->g.nup;
+    hipStream_t st = s->st;
+    // basis and per-step storage within a quarter of the free device memory
+    size_t fr = 0, tot = 0;
+    HC(hipMemGetInfo(&fr, &tot));
+    int kcap = o.shifted_max_steps;
+    auto bytes_for = [&](double k) {
+        return (k + 1) * (double)nup * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16 + 16) +
+               (k + 2) * (k + 3) / 2 * R * 8.0 + (double)px::ms_part2_doubles(R, nup, (int)k + 1) * 8.0;
+    };
+    while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
+    const int64_t vstride = nup * R;
+    Scratch sc;
+    double* V = sc.get<double>((size_t)(kcap + 1) * vstride);
+    double* Y = sc.get<double>((size_t)vstride);
+    double* w = sc.get<double>((size_t)vstride);
+    double* part = sc.get<double>(px::ms_part_doubles(R, nup, kcap + 1));
+    double* part2 = sc.get<double>(px::ms_part2_doubles(R, nup, kcap + 1));
+    double* S1 = sc.get<double>((size_t)(kcap + 1) * R);
+    double* S2 = sc.get<double>((size_t)(kcap + 1) * R);
+    double* nrm2 = sc.get<double>(R);
+    double* hpk = sc.get<double>((size_t)(kcap + 1) * (kcap + 4) / 2 * R);
+    double2* z = sc.get<double2>(P);
+    double* cs = sc.get<double>((size_t)kcap * P);
+    double2* sn = sc.get<double2>((size_t)kcap * P);
+    double2* g = sc.get<double2>((size_t)(kcap + 1) * P);
+    double2* colscr = sc.get<double2>((size_t)kcap * P);
+    double2* ycoef = sc.get<double2>((size_t)kcap * P);
+    double* target = sc.get<double>(P);
+    double* resid = sc.get<double>(P);
+    double* bn = sc.get<double>(npol);
+    int32_t* done = sc.get<int32_t>(P);
+
+    std::vector<double2> zh(P), g0(P);
+    std::vector<double> th(P);
+    for (int p = 0; p < P; ++p) {
+        double zr, zi;
+        shift_q(s->drude, s->mat.tau, s->omega_au[p / npol], zr, zi);
+        zh[p] = make_double2(zr, zi);
+        g0[p] = make_double2(s->bnorm[p % npol], 0.0);
+        th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+    }
+    HC(hipMemcpyAsync(z, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+    HC(hipMemcpyAsync(g, g0.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+    HC(hipMemcpyAsync(target, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
+    HC(hipMemcpyAsync(bn, s->bnorm.data(), sizeof(double) * npol, hipMemcpyHostToDevice, st));
+    px::fill_zero(done, sizeof(int32_t) * P, st);
+    px::ms_init(R, s->b, s->ldg, npol, bn, V, nup, st);
+
+    const int method = tapply_method(s, false, V, Y, R, R, o);
+    const int lag = method == TA_STORED ? 1 : kLag;
+    s->sync.ensure(kcap + 1);
+    int32_t* stop = s->sync.flag();
+    s->sync.reset(st);
+    StepTimer tm(o.timings != 0);
+    tm.ensure(kcap);
+    int launched = 0;
+    for (int k = 0; k < kcap; ++k) {
+        if (k >= lag && s->sync.stopped(k - lag)) break;
+        const double* vk = V + (size_t)k * vstride;
+        double* hk = hpk + (size_t)k * (k + 3) / 2 * R;
+        tm.mark(k, 0, st);
+        tapply(s, method, false, vk, Y, R, R, stop);
+        tm.mark(k, 1, st);
+        px::ms_spmv(R, s->g, Y, w, st, stop);
+        tm.mark(k, 2, st);
+        // classical Gram-Schmidt twice; column k of Hbar = both passes' coefficients
+        px::ms_dots(R, V, vstride, k + 1, w, part, nup, S1, nullptr, nullptr, st, stop);
+        px::ms_update(R, V, vstride, k + 1, S1, w, part2, nup, st, stop);
+        px::ms_dots(R, V, vstride, k + 1, w, part, nup, S2, S1, hk, st, stop);
+        px::ms_update(R, V, vstride, k + 1, S2, w, part2, nup, st, stop);
+        px::ms_dots(R, w, 0, 1, w, part, nup, nrm2, nullptr, nullptr, st, stop);
+        px::ms_normalize(R, w, nrm2, V + (size_t)(k + 1) * vstride, hk + (size_t)(k + 1) * R, nup, st, stop);
+        px::ms_givens(hk, R, npol, P, k, z, cs, sn, g, target, done, resid, stop, st);
+        tm.mark(k, 3, st);
+        s->sync.publish(k, st);
+        ++launched;
+    }
+    px::ms_backsub(hpk, R, npol, P, launched, z, cs, sn, g, done, colscr, ycoef, st);
+    px::ms_xcombine(R, V, vstride, launched, ycoef, npol, P, s->x, s->ldg, nup, st);
+    std::vector<int32_t> dh(P);
+    std::vector<double> rh(P);
+    HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
+    HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+    HC(hipStreamSynchronize(st));
+    int executed = 0;
+    for (int p = 0; p < P; ++p) {
+        s->iters[p] = dh[p] ? dh[p] : launched;
+        s->cycles[p] = 1;
+        s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
+        executed = std::max(executed, s->iters[p]);
+    }
+    tm.collect(executed, s->ms[2], s->ms[3], s->ms[4]);
+    // accounting over the steps the device executed
+    const double nu = (double)s->g.nu;
+    s->tstats[method == TA_STORED ? 3 : 2] += executed;
+    s->counts[3] += executed;
+    s->counts[4] += (int64_t)executed * R;
+    s->counts[5] += (int64_t)executed * npol;
+    s->tflop[method == TA_STORED ? 3 : 2] += 2.0 * nu * nu * npol * executed;
+    s->work[1] += 2.0 * nu * nu * npol * executed;
+    // four passes over the basis per step (two dot, two update)
+    s->work[2] += 4.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
+}
+
 pxStatus check_options(const pxSolveOptions& o)
 {
     if (o.restart_m < 1 || o.restart_m > 1000 || o.max_restart_m > 1000)
@@ -606,6 +738,7 @@ pxStatus check_options(const pxSolveOptions& o)
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
         (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) || o.graph_steps < 0 || o.graph_steps > 64 ||
         (o.t_apply != PX_TAPPLY_AUTO && o.t_apply != PX_TAPPLY_ON_THE_FLY && o.t_apply != PX_TAPPLY_STORED) ||
+        (o.shifted != 0 && o.shifted != 1) || o.shifted_max_steps < 1 || o.shifted_max_steps > 20000 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -626,6 +759,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
     ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
     prepare_solve(s);
+    if (shifted_applies(s, o)) shifted_phase(s, o);
     for (int c0 = 0; c0 < ncol; c0 += blk) {
         std::vector<int> cols;
         for (int c = c0; c < std::min(ncol, c0 + blk); ++c) cols.push_back(c);
@@ -676,6 +810,8 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->ortho = PX_ORTHO_DCGS2;
     o->graph_steps = 8;
     o->t_apply = PX_TAPPLY_AUTO;
+    o->shifted = 1;
+    o->shifted_max_steps = 3000;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }

@@ -203,4 +203,24 @@ void normalize_seg(const double2* w, const double* nrm, const int32_t* done, con
 void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
                   double2* x, int Bc, int nseg, int64_t rows, hipStream_t st);
 
+// ---- shared-Krylov solve (px_shifted.hip) ----------------------------------
+// R real slots per row (2 or 4), one per polarization; see px_shifted.hip.
+void ms_init(int R, const double2* b, int ldb, int npol, const double* bnorm, double* V0, int64_t nup, hipStream_t st);
+void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop);
+// dots of w with V_0..V_{nvec-1} per slot into out[nvec][R] (and base + dots into out2)
+void ms_dots(int R, const double* V, int64_t vstride, int nvec, const double* w, double* part, int64_t nup,
+             double* out, const double* base, double* out2, hipStream_t st, const int32_t* stop);
+void ms_update(int R, const double* V, int64_t vstride, int nvec, const double* s, double* w, double* part2,
+               int64_t nup, hipStream_t st, const int32_t* stop);
+size_t ms_part_doubles(int R, int64_t nup, int nvec_max);
+size_t ms_part2_doubles(int R, int64_t nup, int nvec_max);
+void ms_normalize(int R, const double* w, const double* nrm2, double* vnext, double* hnext, int64_t nup,
+                  hipStream_t st, const int32_t* stop);
+void ms_givens(const double* hcol, int R, int npol, int P, int k, const double2* z, double* cs, double2* sn,
+               double2* g, const double* target, int32_t* done, double* resid, int32_t* stop, hipStream_t st);
+void ms_backsub(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
+                const double2* sn, double2* g, const int32_t* done, double2* colscr, double2* y, hipStream_t st);
+void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int npol, int P, double2* x,
+                 int ldx, int64_t nup, hipStream_t st);
+
 }  // namespace px

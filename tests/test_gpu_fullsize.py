@@ -38,14 +38,17 @@ def lib():
     return px.load()
 
 
-def test_sphere_20k_full_spectrum():
+@pytest.mark.parametrize("shifted", [1, 0])
+def test_sphere_20k_full_spectrum(shifted):
+    """The benchmark's solve (shared-Krylov phase on, the default) and the
+    blocked solver alone."""
     case = C.sphere_20k()
     pv = M.param_vector(case["params"])
     om = case["omega_ev"]
-    say("[full size] Ag sphere N=20000, 128 w x 3 pol, mixed, rel_tol 1e-8")
+    say(f"[full size] Ag sphere N=20000, 128 w x 3 pol, mixed, rel_tol 1e-8, shifted={shifted}")
     s = px.Structure(0, case["xyz"], case["params"], px.default_stream())
     s.set_frequencies(om, case["pol_mask"], case["e0"])
-    st = s.solve(precision=px.PX_MIXED, restart_m=50, rel_tol=1e-8)
+    st = s.solve(precision=px.PX_MIXED, restart_m=50, rel_tol=1e-8, shifted=shifted)
     it, cyc, rr = s.stats()
     alpha, sigma = s.spectrum()
     say(f"   status {st} iters max {it.max()} relres max {rr.max():.2e}")

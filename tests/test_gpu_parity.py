@@ -82,13 +82,15 @@ def _solve(model, xyz, params, om, pol, aib, precision, rel_tol, max_block_cols=
     return s, st, alpha, sigma, it, rr
 
 
+@pytest.mark.parametrize("shifted", [0, 1])
 @pytest.mark.parametrize("precision,tol,bound", [(px.PX_FP64, 1e-12, 1e-10), (px.PX_MIXED, 1e-8, 1e-5)])
-def test_small_sphere_spectrum_matches_oracle(precision, tol, bound):
+def test_small_sphere_spectrum_matches_oracle(precision, tol, bound, shifted):
+    """Blocked solver (shifted = 0) and the shared-Krylov phase (shifted = 1)."""
     c = C.small_sphere()
-    say(f"[solve small sphere] precision={precision} tol={tol}")
+    say(f"[solve small sphere] precision={precision} tol={tol} shifted={shifted}")
     ref = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
     s, st, alpha, sigma, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
-                                         tol)
+                                         tol, shifted=shifted)
     say(f"   status {st} iters max {it.max()} mean {it.mean():.1f} relres max {rr.max():.2e}")
     assert st == px.PX_OK
     assert np.all(rr <= tol)
@@ -103,15 +105,16 @@ def test_small_sphere_spectrum_matches_oracle(precision, tol, bound):
     s.close()
 
 
+@pytest.mark.parametrize("shifted", [0, 1])
 @pytest.mark.parametrize("precision,tol,bound", [(px.PX_FP64, 1e-12, 1e-10), (px.PX_MIXED, 1e-8, 1e-5)])
-def test_mid_size_sphere_three_polarizations(precision, tol, bound):
+def test_mid_size_sphere_three_polarizations(precision, tol, bound, shifted):
     """~1000 atoms (several row tiles and a ragged tail), x/y/z columns."""
     xyz = G.fcc_sphere_n(1000, seed=21)
     p = M.load("ag_wfq")
     om = np.array([2.3, 3.4, 4.6])
-    say(f"[solve mid sphere] precision={precision}")
+    say(f"[solve mid sphere] precision={precision} shifted={shifted}")
     ref = O.solve_spectrum(0, xyz, M.param_vector(p), om, 0b111, 1e-4)
-    s, st, alpha, sigma, it, rr = _solve(0, xyz, p, om, 0b111, None, precision, tol)
+    s, st, alpha, sigma, it, rr = _solve(0, xyz, p, om, 0b111, None, precision, tol, shifted=shifted)
     say(f"   status {st} iters max {it.max()} relres max {rr.max():.2e}")
     assert st == px.PX_OK
     e = rel_err(sigma, ref["sigma"])
@@ -146,8 +149,9 @@ def test_one_column_solver_matches_blocked_solver():
     c = C.small_sphere()
     om = c["omega_ev"][::5]
     say("[one-column vs blocked]")
-    _, st1, _, s1, it1, _ = _solve(0, c["xyz"], c["params"], om, 0b001, None, px.PX_FP64, 1e-12, max_block_cols=1)
-    _, st2, _, s2, it2, _ = _solve(0, c["xyz"], c["params"], om, 0b001, None, px.PX_FP64, 1e-12)
+    _, st1, _, s1, it1, _ = _solve(0, c["xyz"], c["params"], om, 0b001, None, px.PX_FP64, 1e-12, max_block_cols=1,
+                                   shifted=0)
+    _, st2, _, s2, it2, _ = _solve(0, c["xyz"], c["params"], om, 0b001, None, px.PX_FP64, 1e-12, shifted=0)
     assert st1 == px.PX_OK and st2 == px.PX_OK
     assert rel_err(s1, s2) <= 1e-9
 
@@ -175,7 +179,8 @@ def test_orthogonalisation_variants_agree(precision, tol, bound):
         assert st == px.PX_OK and e <= bound
         s.close()
         s, st, alpha, sigma, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
-                                             tol, ortho=ortho, restart_m=12, max_restart_m=12, stall_cycles=0)
+                                             tol, ortho=ortho, restart_m=12, max_restart_m=12, stall_cycles=0,
+                                             shifted=0)
         e = rel_err(sigma, ref_s["sigma"])
         say(f"   sphere: status {st} iters max {it.max()} relres max {rr.max():.2e} rel_err {e:.2e}")
         assert st == px.PX_OK and e <= bound
@@ -208,7 +213,7 @@ def test_stored_t_apply_matches_oracle(precision, tol, bound):
             assert ts["f32_stored"] == 0 and ts["f64_stored"] == 0
         s.close()
         s, st, alpha, sig_s, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
-                                             tol, t_apply=mode)
+                                             tol, t_apply=mode, shifted=0)
         e = rel_err(sig_s, ref_s["sigma"])
         say(f"[t_apply {mode}] sphere: status {st} iters max {it.max()} rel_err {e:.2e} launches {s.tapply_stats()}")
         assert st == px.PX_OK and e <= bound
@@ -279,7 +284,7 @@ def test_not_converged_is_reported():
     c = C.small_sphere()
     s = make(0, c["xyz"], c["params"])
     s.set_frequencies([3.5], 0b001)
-    st = s.solve(precision=px.PX_FP64, rel_tol=1e-13, restart_m=5, max_cycles=1)
+    st = s.solve(precision=px.PX_FP64, rel_tol=1e-13, restart_m=5, max_cycles=1, shifted=0)
     assert st == px.PX_E_NOTCONV
     it, cyc, rr = s.stats()
     assert cyc[0] == 1 and rr[0] > 1e-13

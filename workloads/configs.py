@@ -98,13 +98,14 @@ def serving_request(rng, n_min=1000, n_max=100000):
     return _case(model, xyz, params, grid, pol, f"{metal}_{shape}_{n}_m{model}_{n_omega}w")
 
 
-def alloy_sphere(frac_au, n=1289, n_omega=60, seed=7):
-    """Ag-Au nanoalloy sphere of n atoms (the paper's 3.5 nm, 1289-atom alloys),
-    Au atoms substituted at random with fraction frac_au, omegaFQFmu with two
-    atom types, 60 frequencies 2.5-4.5 eV, x polarization."""
+def alloy_sphere(frac_au, n=1289, step_ev=0.01, seed=7):
+    """Ag-Au nanoalloy sphere of n atoms (the paper's D = 3.5 nm, 1289-atom
+    alloys), Au atoms substituted at random with fraction frac_au (the same Ag
+    sphere for every fraction), omegaFQFmu with two atom types, frequencies
+    2.0-4.5 eV in steps of step_ev (251 at 0.01 eV), x, y and z polarizations."""
     xyz = G.fcc_sphere_n(n, jitter=0.01, seed=seed)
     ag, au = M.load("ag_wfqfmu"), M.load("au_wfqfmu")
-    om = np.linspace(2.5, 4.5, n_omega)
+    om = np.round(np.arange(2.0, 4.5 + 0.5 * step_ev, step_ev), 10)
     return dict(model=1, xyz=xyz, types=G.alloy_types(n, frac_au, seed=seed + 1), params_a=ag, params_b=au,
-                omega_ev=om, pol_mask=0b001, e0=E0, alpha_ib_a=M.interband_alpha(ag, om),
+                omega_ev=om, pol_mask=0b111, e0=E0, alpha_ib_a=M.interband_alpha(ag, om),
                 alpha_ib_b=M.interband_alpha(au, om), name=f"agau_alloy_{n}_{int(round(100 * frac_au))}au_wfqfmu")
