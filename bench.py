@@ -46,13 +46,13 @@ def ensure_built():
     return px.load()
 
 
-def one_step(px, case, precision, timings, max_block_cols=0, t_apply=None):
+def one_step(px, case, precision, timings, max_block_cols=0, t_apply=None, shifted=None):
     om = case["omega_ev"]
     s = px.Structure(case["model"], case["xyz"], case["params"], px.default_stream())
     pol = case["pol_mask"]
     s.set_frequencies(om, pol, case["e0"], case["alpha_ib"])
     st = s.solve(precision=precision, restart_m=50, rel_tol=1e-8, max_block_cols=max_block_cols, timings=timings,
-                 t_apply=t_apply)
+                 t_apply=t_apply, shifted=shifted)
     alpha, sigma = s.spectrum()
     it, cyc, rr = s.stats()
     tm = s.timings()
@@ -498,7 +498,7 @@ def main():
         sub["pol_mask"] = 0b001
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        r64 = one_step(pxm, sub, pxm.PX_FP64, False, max_block_cols=1, t_apply=pxm.PX_TAPPLY_ON_THE_FLY)
+        r64 = one_step(pxm, sub, pxm.PX_FP64, False, max_block_cols=1, t_apply=pxm.PX_TAPPLY_ON_THE_FLY, shifted=0)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         v64 = len(idx) / (tb - ta)

@@ -141,12 +141,13 @@ typedef struct {
  *                    on the frequency and the frequency only shifts the
  *                    operator, so all frequencies share one Krylov space);
  *                    columns it leaves above rel_tol continue in the blocked
- *                    solver from its iterate.  0 = blocked solver only.
- *                    Ignored for PX_WFQFMU, two-type structures, pxSolveBatch
- *                    and the server.
- *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 20000]
- *                    (3000; lowered to keep its basis within a quarter of the
- *                    free device memory)
+ *                    solver from its iterate (the phase counts as one cycle).
+ *                    0 = blocked solver only.  Ignored for PX_WFQFMU,
+ *                    two-type structures, pxSolveBatch and the server.
+ *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 4000]
+ *                    (2000; lowered to keep its basis and the frequencies'
+ *                    triangular factors, k^2/2 x 16 B per column, within a
+ *                    quarter of the free device memory)
  */
 typedef struct {
     int32_t precision;

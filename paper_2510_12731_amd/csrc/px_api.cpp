@@ -632,7 +632,7 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipMemGetInfo(&fr, &tot));
     int kcap = o.shifted_max_steps;
     auto bytes_for = [&](double k) {
-        return (k + 1) * (double)nup * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16 + 16) +
+        return (k + 1) * (double)nup * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) + k * (k + 1) / 2 * P * 16.0 +
                (k + 2) * (k + 3) / 2 * R * 8.0 + (double)px::ms_part2_doubles(R, nup, (int)k + 1) * 8.0;
     };
     while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
@@ -651,12 +651,14 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     double* cs = sc.get<double>((size_t)kcap * P);
     double2* sn = sc.get<double2>((size_t)kcap * P);
     double2* g = sc.get<double2>((size_t)(kcap + 1) * P);
-    double2* colscr = sc.get<double2>((size_t)kcap * P);
+    const int GB = px::ms_givens_batch();
+    double2* rst = sc.get<double2>(px::ms_rst_elems(P, kcap));
     double2* ycoef = sc.get<double2>((size_t)kcap * P);
     double* target = sc.get<double>(P);
     double* resid = sc.get<double>(P);
     double* bn = sc.get<double>(npol);
     int32_t* done = sc.get<int32_t>(P);
+    int32_t* ndone = sc.get<int32_t>(1);
 
     std::vector<double2> zh(P), g0(P);
     std::vector<double> th(P);
@@ -672,6 +674,7 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipMemcpyAsync(target, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
     HC(hipMemcpyAsync(bn, s->bnorm.data(), sizeof(double) * npol, hipMemcpyHostToDevice, st));
     px::fill_zero(done, sizeof(int32_t) * P, st);
+    px::fill_zero(ndone, sizeof(int32_t), st);
     px::ms_init(R, s->b, s->ldg, npol, bn, V, nup, st);
 
     const int method = tapply_method(s, false, V, Y, R, R, o);
@@ -698,12 +701,19 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
         px::ms_update(R, V, vstride, k + 1, S2, w, part2, nup, st, stop);
         px::ms_dots(R, w, 0, 1, w, part, nup, nrm2, nullptr, nullptr, st, stop);
         px::ms_normalize(R, w, nrm2, V + (size_t)(k + 1) * vstride, hk + (size_t)(k + 1) * R, nup, st, stop);
-        px::ms_givens(hk, R, npol, P, k, z, cs, sn, g, target, done, resid, stop, st);
+        // the shifted Givens QRs take GB Hessenberg columns per launch
+        if ((k + 1) % GB == 0 || k + 1 == kcap)
+            px::ms_givens(hpk, R, npol, P, (k / GB) * GB, k % GB + 1, z, cs, sn, g, target, done, resid, ndone, stop,
+                          st);
         tm.mark(k, 3, st);
         s->sync.publish(k, st);
         ++launched;
     }
-    px::ms_backsub(hpk, R, npol, P, launched, z, cs, sn, g, done, colscr, ycoef, st);
+    if (launched % GB != 0 && launched < kcap)   // stopped early: the last partial batch (a no-op once all converged)
+        px::ms_givens(hpk, R, npol, P, (launched / GB) * GB, launched % GB, z, cs, sn, g, target, done, resid, ndone,
+                      stop, st);
+    px::ms_rfactor(hpk, R, npol, P, launched, z, cs, sn, done, rst, st);
+    px::ms_backsub(rst, P, launched, done, g, ycoef, st);
     px::ms_xcombine(R, V, vstride, launched, ycoef, npol, P, s->x, s->ldg, nup, st);
     std::vector<int32_t> dh(P);
     std::vector<double> rh(P);
@@ -738,7 +748,7 @@ pxStatus check_options(const pxSolveOptions& o)
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
         (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) || o.graph_steps < 0 || o.graph_steps > 64 ||
         (o.t_apply != PX_TAPPLY_AUTO && o.t_apply != PX_TAPPLY_ON_THE_FLY && o.t_apply != PX_TAPPLY_STORED) ||
-        (o.shifted != 0 && o.shifted != 1) || o.shifted_max_steps < 1 || o.shifted_max_steps > 20000 ||
+        (o.shifted != 0 && o.shifted != 1) || o.shifted_max_steps < 1 || o.shifted_max_steps > 4000 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -811,7 +821,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->graph_steps = 8;
     o->t_apply = PX_TAPPLY_AUTO;
     o->shifted = 1;
-    o->shifted_max_steps = 3000;
+    o->shifted_max_steps = 2000;
 }
 
 const char* pxLastError(void) { return g_err.c_str(); }

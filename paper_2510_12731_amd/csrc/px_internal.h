@@ -216,10 +216,17 @@ size_t ms_part_doubles(int R, int64_t nup, int nvec_max);
 size_t ms_part2_doubles(int R, int64_t nup, int nvec_max);
 void ms_normalize(int R, const double* w, const double* nrm2, double* vnext, double* hnext, int64_t nup,
                   hipStream_t st, const int32_t* stop);
-void ms_givens(const double* hcol, int R, int npol, int P, int k, const double2* z, double* cs, double2* sn,
-               double2* g, const double* target, int32_t* done, double* resid, int32_t* stop, hipStream_t st);
-void ms_backsub(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
-                const double2* sn, double2* g, const int32_t* done, double2* colscr, double2* y, hipStream_t st);
+// Hessenberg columns k0 .. k0+kn-1 (kn <= ms_givens_batch()) for every (frequency, polarization) pair
+int ms_givens_batch();
+void ms_givens(const double* hpk, int R, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
+               double2* g, const double* target, int32_t* done, double* resid, int32_t* ndone, int32_t* stop,
+               hipStream_t st);
+// every pair's triangular factor, packed, into rst (ms_rst_elems(P, kcap) complex)
+size_t ms_rst_elems(int P, int kcap);
+void ms_rfactor(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
+                const double2* sn, const int32_t* done, double2* rst, hipStream_t st);
+// y = R^-1 g per pair (kmax <= 4000: g is staged in LDS)
+void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const double2* g, double2* y, hipStream_t st);
 void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int npol, int P, double2* x,
                  int ldx, int64_t nup, hipStream_t st);
 

@@ -196,38 +196,120 @@ __global__ void k_ms_normalize(const double* __restrict__ w, const double* __res
     vnext[t] = b > 0.0 ? w[t] / b : 0.0;
 }
 
-// Column k of every shifted Hessenberg matrix Hbar - z_p I~: the rotations of
-// steps 0..k-1 are applied, the new rotation annihilates the subdiagonal, and
-// the rotated right-hand side gives the GMRES residual norm |g[k+1][p]|.
-// One workgroup; raises *stop once every pair has converged.
-__global__ __launch_bounds__(1024) void k_ms_givens(const double* __restrict__ hcol, int R, int npol, int P, int k,
-                                                    const double2* __restrict__ z, double* __restrict__ cs,
-                                                    double2* __restrict__ sn, double2* __restrict__ g,
-                                                    const double* __restrict__ target, int32_t* __restrict__ done,
-                                                    double* __restrict__ resid, int32_t* __restrict__ stop)
+// Hessenberg column K of polarization c, entry j, with the shift on the diagonal.
+__device__ __forceinline__ double2 hs(const double* __restrict__ hpk, int R, int c, int K, int j, double2 zp)
+{
+    const double h = hpk[((size_t)K * (K + 3) / 2 + j) * R + c];
+    return j == K ? make_double2(h - zp.x, -zp.y) : make_double2(h, 0.0);
+}
+
+// (a, b) <- (c a + s b, -conj(s) a + c b): returns the first, carries the second in a.
+__device__ __forceinline__ double2 rotate(double cj, double2 sj, double2& a, double2 b)
+{
+    const double2 sb = cmul(sj, b);
+    const double2 first = make_double2(cj * a.x + sb.x, cj * a.y + sb.y);
+    const double2 sa = cmul(make_double2(sj.x, -sj.y), a);
+    a = make_double2(cj * b.x - sa.x, cj * b.y - sa.y);
+    return first;
+}
+
+// The rotations 0..k0-1 of pair p applied to the carried entries a[q] of the
+// nb new columns k0 + q; each output R[j][k0 + q] goes to the packed factor.
+// Two register buffers alternate: the loads of the next GU rotations are in
+// flight while the current GU are applied to nb independent chains.
+constexpr int GB = 8, GU = 4;
+
+struct RotBatch {
+    double c[GU];
+    double2 s[GU];
+    double h[GU][GB];
+};
+
+__device__ __forceinline__ size_t rpk(int l, int j) { return (size_t)l * (l + 1) / 2 + j; }
+
+__device__ __forceinline__ void load_rots(RotBatch& b, const double* __restrict__ cs, const double2* __restrict__ sn,
+                                          const double* __restrict__ hpk, int R, int c, int P, int p, int k0, int nb,
+                                          int j0)
+{
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+        const int j = j0 + u;
+        if (j < k0) {
+            b.c[u] = cs[(size_t)j * P + p];
+            b.s[u] = sn[(size_t)j * P + p];
+#pragma unroll
+            for (int q = 0; q < GB; ++q) {
+                const int l = k0 + q;
+                if (q < nb) b.h[u][q] = hpk[((size_t)l * (l + 3) / 2 + j + 1) * R + c];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void apply_rots(const RotBatch& b, double2 (&a)[GB], int k0, int nb, int j0, double2 zp)
+{
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+        const int j = j0 + u;
+        if (j < k0) {
+#pragma unroll
+            for (int q = 0; q < GB; ++q) {
+                const int l = k0 + q;
+                if (q < nb) {
+                    const double hv = b.h[u][q];
+                    const double2 bb = j + 1 == l ? make_double2(hv - zp.x, -zp.y) : make_double2(hv, 0.0);
+                    (void)rotate(b.c[u], b.s[u], a[q], bb);
+                }
+            }
+        }
+    }
+}
+
+// Columns k0 .. k0+kn-1 (kn <= GB) of every shifted Hessenberg matrix
+// Hbar - z_p I~: the rotations of earlier columns are applied to all kn
+// columns in one pass (each rotation loaded once, kn independent chains),
+// then each column takes the batch's new rotations and its own, which
+// annihilates its subdiagonal; the rotated right-hand side gives the GMRES
+// residual norm |g[K+1][p]|.  One thread per (frequency, polarization) pair;
+// the thread that finishes the last pair raises *stop.  Nothing is stored
+// inside the chains (stores and loads share one completion counter here).
+__global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ hpk, int R, int npol, int P, int k0,
+                                                  int kn, const double2* __restrict__ z, double* __restrict__ cs,
+                                                  double2* __restrict__ sn, double2* __restrict__ g,
+                                                  const double* __restrict__ target,
+                                                  int32_t* __restrict__ done, double* __restrict__ resid,
+                                                  int32_t* __restrict__ ndone, int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
-    __shared__ int all_done;
-    if (threadIdx.x == 0) all_done = 1;
-    __syncthreads();
-    int mine = 1;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        if (done[p]) continue;
-        const int c = p % npol;
-        const double2 zp = z[p];
-        double2 a = make_double2(hcol[c], 0.0);
-        if (k == 0) a = make_double2(a.x - zp.x, -zp.y);
-        for (int j = 0; j < k; ++j) {
-            double2 b = make_double2(hcol[(j + 1) * R + c], 0.0);
-            if (j + 1 == k) b = make_double2(b.x - zp.x, -zp.y);
-            const double cj = cs[(size_t)j * P + p];
-            const double2 sj = sn[(size_t)j * P + p];
-            // (a, b) <- (c a + s b, -conj(s) a + c b); only the second is carried
-            const double2 sa = cmul(make_double2(sj.x, -sj.y), a);
-            a = make_double2(cj * b.x - sa.x, cj * b.y - sa.y);
-        }
-        const double beta = hcol[(k + 1) * R + c];
-        const double aa = sqrt(a.x * a.x + a.y * a.y);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P || done[p]) return;
+    const int c = p % npol;
+    const double2 zp = z[p];
+    double2 a[GB];
+#pragma unroll
+    for (int q = 0; q < GB; ++q)
+        if (q < kn) a[q] = hs(hpk, R, c, k0 + q, 0, zp);
+    RotBatch b0, b1;
+    load_rots(b0, cs, sn, hpk, R, c, P, p, k0, kn, 0);
+    for (int j0 = 0; j0 < k0; j0 += 2 * GU) {
+        load_rots(b1, cs, sn, hpk, R, c, P, p, k0, kn, j0 + GU);
+        apply_rots(b0, a, k0, kn, j0, zp);
+        load_rots(b0, cs, sn, hpk, R, c, P, p, k0, kn, j0 + 2 * GU);
+        apply_rots(b1, a, k0, kn, j0 + GU, zp);
+    }
+    double rc[GB];
+    double2 rs[GB];
+    double2 gk = g[(size_t)k0 * P + p];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+        if (q >= kn) break;
+        const int K = k0 + q;
+        double2 u = a[q];
+#pragma unroll
+        for (int t = 0; t < GB; ++t)
+            if (t < q) (void)rotate(rc[t], rs[t], u, hs(hpk, R, c, K, k0 + t + 1, zp));
+        const double beta = hpk[((size_t)K * (K + 3) / 2 + K + 1) * R + c];
+        const double aa = sqrt(u.x * u.x + u.y * u.y);
         double ck;
         double2 sk;
         if (aa == 0.0) {
@@ -236,68 +318,82 @@ __global__ __launch_bounds__(1024) void k_ms_givens(const double* __restrict__ h
         } else {
             const double rr = sqrt(aa * aa + beta * beta);
             ck = aa / rr;
-            sk = make_double2(a.x / aa * beta / rr, a.y / aa * beta / rr);
+            sk = make_double2(u.x / aa * beta / rr, u.y / aa * beta / rr);
         }
-        cs[(size_t)k * P + p] = ck;
-        sn[(size_t)k * P + p] = sk;
-        const double2 gk = g[(size_t)k * P + p];
-        g[(size_t)k * P + p] = make_double2(ck * gk.x, ck * gk.y);
-        const double2 gn = cmul(make_double2(-sk.x, sk.y), gk);
-        g[(size_t)(k + 1) * P + p] = gn;
-        const double res = sqrt(gn.x * gn.x + gn.y * gn.y);
+        rc[q] = ck;
+        rs[q] = sk;
+        cs[(size_t)K * P + p] = ck;
+        sn[(size_t)K * P + p] = sk;
+        g[(size_t)K * P + p] = make_double2(ck * gk.x, ck * gk.y);
+        gk = cmul(make_double2(-sk.x, sk.y), gk);
+        g[(size_t)(K + 1) * P + p] = gk;
+        const double res = sqrt(gk.x * gk.x + gk.y * gk.y);
         resid[p] = res;
-        if (res <= target[p]) done[p] = k + 1;
-        else mine = 0;
+        if (res <= target[p]) {
+            done[p] = K + 1;
+            if (atomicAdd(ndone, 1) + 1 == P && stop) *stop = 1;
+            break;
+        }
     }
-    if (!mine) atomicAnd(&all_done, 0);
-    __syncthreads();
-    if (threadIdx.x == 0 && all_done && stop) *stop = 1;
 }
 
-// Least-squares solution y_p of every pair over its own number of steps K_p
-// (done[p], else kmax): back substitution with R_p, whose column l is rebuilt
-// by replaying rotations 0..l-1 on column l of Hbar - z_p I~.  g is
-// overwritten; colscr holds one rebuilt column per pair.
-__global__ __launch_bounds__(64) void k_ms_backsub(const double* __restrict__ hpk, int R, int npol, int P, int kmax,
+// Column l = blockIdx.y of every pair's triangular factor R_p (pairs with
+// K_p <= l skip), rebuilt by the same chain of rotations as k_ms_givens:
+// rst[(l (l + 1) / 2 + j) P + p] = R_p[j][l].  One thread per pair; the many
+// columns in flight hide the chains' memory latency.
+__global__ __launch_bounds__(64) void k_ms_rfactor(const double* __restrict__ hpk, int R, int npol, int P, int kmax,
                                                    const double2* __restrict__ z, const double* __restrict__ cs,
-                                                   const double2* __restrict__ sn, double2* __restrict__ g,
-                                                   const int32_t* __restrict__ done, double2* __restrict__ colscr,
-                                                   double2* __restrict__ y)
+                                                   const double2* __restrict__ sn, const int32_t* __restrict__ done,
+                                                   double2* __restrict__ rst)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
     if (p >= P) return;
     const int K = done[p] ? done[p] : kmax;
+    if (l >= K) return;
     const int c = p % npol;
     const double2 zp = z[p];
-    for (int j = K; j < kmax; ++j) y[(size_t)j * P + p] = make_double2(0.0, 0.0);
+    double2 a = hs(hpk, R, c, l, 0, zp);
+    const double* hl = hpk + (size_t)l * (l + 3) / 2 * R;
+#pragma unroll 4
+    for (int j = 0; j < l; ++j) {
+        const double hv = hl[(j + 1) * R + c];
+        const double2 b = j + 1 == l ? make_double2(hv - zp.x, -zp.y) : make_double2(hv, 0.0);
+        rst[rpk(l, j) * P + p] = rotate(cs[(size_t)j * P + p], sn[(size_t)j * P + p], a, b);
+    }
+    const double cl = cs[(size_t)l * P + p];
+    const double2 sl = sn[(size_t)l * P + p];
+    const double beta = hl[(l + 1) * R + c];
+    rst[rpk(l, l) * P + p] = make_double2(cl * a.x + sl.x * beta, cl * a.y + sl.y * beta);
+}
+
+// Least-squares solution y_p = R_p^-1 g_p of every pair over its own number
+// of steps K_p (done[p], else kmax), one workgroup per pair: column-oriented
+// back substitution with g in LDS, the rows of each column spread over the
+// threads.  y[j][p] = 0 for j >= K_p.
+__global__ __launch_bounds__(256) void k_ms_backsub(const double2* __restrict__ rst, int P, int kmax,
+                                                    const int32_t* __restrict__ done, const double2* __restrict__ g,
+                                                    double2* __restrict__ y)
+{
+    extern __shared__ double2 gl[];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int K = done[p] ? done[p] : kmax;
+    for (int j = tid; j < kmax; j += blockDim.x) {
+        if (j < K) gl[j] = g[(size_t)j * P + p];
+        else y[(size_t)j * P + p] = make_double2(0.0, 0.0);
+    }
     for (int l = K - 1; l >= 0; --l) {
-        const double* hl = hpk + (size_t)l * (l + 3) / 2 * R;
-        double2 a = make_double2(hl[c], 0.0);
-        if (l == 0) a = make_double2(a.x - zp.x, -zp.y);
-        for (int j = 0; j < l; ++j) {
-            double2 b = make_double2(hl[(j + 1) * R + c], 0.0);
-            if (j + 1 == l) b = make_double2(b.x - zp.x, -zp.y);
-            const double cj = cs[(size_t)j * P + p];
-            const double2 sj = sn[(size_t)j * P + p];
-            const double2 sb = cmul(sj, b);
-            colscr[(size_t)j * P + p] = make_double2(cj * a.x + sb.x, cj * a.y + sb.y);
-            const double2 sa = cmul(make_double2(sj.x, -sj.y), a);
-            a = make_double2(cj * b.x - sa.x, cj * b.y - sa.y);
-        }
-        const double cl = cs[(size_t)l * P + p];
-        const double2 sl = sn[(size_t)l * P + p];
-        const double beta = hl[(l + 1) * R + c];
-        const double2 rll = make_double2(cl * a.x + sl.x * beta, cl * a.y + sl.y * beta);
-        const double2 gl = g[(size_t)l * P + p];
+        __syncthreads();
+        const double2 rll = rst[rpk(l, l) * P + p];
+        const double2 gv = gl[l];
         const double den = rll.x * rll.x + rll.y * rll.y;
-        const double2 yl = den > 0.0 ? make_double2((gl.x * rll.x + gl.y * rll.y) / den,
-                                                    (gl.y * rll.x - gl.x * rll.y) / den)
+        const double2 yl = den > 0.0 ? make_double2((gv.x * rll.x + gv.y * rll.y) / den,
+                                                    (gv.y * rll.x - gv.x * rll.y) / den)
                                      : make_double2(0.0, 0.0);
-        y[(size_t)l * P + p] = yl;
-        for (int j = 0; j < l; ++j) {
-            const double2 rj = cmul(colscr[(size_t)j * P + p], yl);
-            double2& gj = g[(size_t)j * P + p];
-            gj = make_double2(gj.x - rj.x, gj.y - rj.y);
+        if (tid == 0) y[(size_t)l * P + p] = yl;
+        for (int j = tid; j < l; j += blockDim.x) {
+            const double2 r = cmul(rst[rpk(l, j) * P + p], yl);
+            gl[j] = make_double2(gl[j].x - r.x, gl[j].y - r.y);
         }
     }
 }
@@ -450,19 +546,30 @@ void ms_normalize(int R, const double* w, const double* nrm2, double* vnext, dou
     else hipLaunchKernelGGL(k_ms_normalize<4>, grid, dim3(256), 0, st, w, nrm2, vnext, hnext, nup, stop);
 }
 
-void ms_givens(const double* hcol, int R, int npol, int P, int k, const double2* z, double* cs, double2* sn,
-               double2* g, const double* target, int32_t* done, double* resid, int32_t* stop, hipStream_t st)
+int ms_givens_batch() { return GB; }
+
+void ms_givens(const double* hpk, int R, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
+               double2* g, const double* target, int32_t* done, double* resid, int32_t* ndone, int32_t* stop,
+               hipStream_t st)
 {
-    const int threads = P >= 1024 ? 1024 : ((P + 63) / 64) * 64;
-    hipLaunchKernelGGL(k_ms_givens, dim3(1), dim3(threads), 0, st, hcol, R, npol, P, k, z, cs, sn, g, target, done,
-                       resid, stop);
+    hipLaunchKernelGGL(k_ms_givens, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, hpk, R, npol, P, k0, kn, z, cs,
+                       sn, g, target, done, resid, ndone, stop);
 }
 
-void ms_backsub(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
-                const double2* sn, double2* g, const int32_t* done, double2* colscr, double2* y, hipStream_t st)
+void ms_rfactor(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
+                const double2* sn, const int32_t* done, double2* rst, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ms_backsub, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, hpk, R, npol, P, kmax, z, cs,
-                       sn, g, done, colscr, y);
+    if (kmax < 1) return;
+    hipLaunchKernelGGL(k_ms_rfactor, dim3((unsigned)((P + 63) / 64), (unsigned)kmax), dim3(64), 0, st, hpk, R, npol,
+                       P, kmax, z, cs, sn, done, rst);
+}
+
+size_t ms_rst_elems(int P, int kcap) { return (size_t)kcap * (kcap + 1) / 2 * P; }
+
+void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const double2* g, double2* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ms_backsub, dim3((unsigned)P), dim3(256), sizeof(double2) * kmax, st, rst, P, kmax, done, g,
+                       y);
 }
 
 void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int npol, int P, double2* x,
