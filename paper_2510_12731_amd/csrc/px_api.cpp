@@ -198,6 +198,8 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, 8);
     W.narrow = dalloc<double>(W.narrow_bytes / sizeof(double) + 1);
     W.split32 = dalloc<float>(px::tapply_f32_scratch_bytes(s->g, 2 * lda) / sizeof(float) + 1);
+    // the omegaFQ narrow FP64 T-apply takes its near field from a stored list
+    HC(px::ensure_near_f64(s->g, s->st));
     W.lda_cap = lda;
     W.m_cap = m;
     s->sync.ensure(m + 1);
@@ -624,34 +626,36 @@ bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
 
 void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
 {
-    const int npol = s->npol, R = npol == 3 ? 4 : 2, P = s->ncol;
+    const int npol = s->npol, R = npol, P = s->ncol;
     const int64_t nup = s->g.nup;
     hipStream_t st = s->st;
-    // basis and per-step storage within a quarter of the free device memory
+    // basis, Hessenberg matrices and triangular factors within a quarter of the free device memory
     size_t fr = 0, tot = 0;
     HC(hipMemGetInfo(&fr, &tot));
     int kcap = o.shifted_max_steps;
     auto bytes_for = [&](double k) {
-        return (k + 1) * (double)nup * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) + k * (k + 1) / 2 * P * 16.0 +
-               (k + 2) * (k + 3) / 2 * R * 8.0 + (double)px::ms_part2_doubles(R, nup, (int)k + 1) * 8.0;
+        return (k + 1) * (double)nup * R * 8.0 + (k + 1) * k * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) +
+               k * (k + 1) / 2 * P * 16.0 + (double)px::ms_part2_doubles(R, nup, (int)k) * 8.0;
     };
     while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
     const int64_t vstride = nup * R;
+    const int GB = px::ms_givens_batch();
     Scratch sc;
     double* V = sc.get<double>((size_t)(kcap + 1) * vstride);
+    double* u = sc.get<double>((size_t)vstride);
     double* Y = sc.get<double>((size_t)vstride);
-    double* w = sc.get<double>((size_t)vstride);
-    double* part = sc.get<double>(px::ms_part_doubles(R, nup, kcap + 1));
-    double* part2 = sc.get<double>(px::ms_part2_doubles(R, nup, kcap + 1));
-    double* S1 = sc.get<double>((size_t)(kcap + 1) * R);
-    double* S2 = sc.get<double>((size_t)(kcap + 1) * R);
-    double* nrm2 = sc.get<double>(R);
-    double* hpk = sc.get<double>((size_t)(kcap + 1) * (kcap + 4) / 2 * R);
+    double* wt = sc.get<double>((size_t)vstride);
+    double* part = sc.get<double>(px::ms_part_doubles(R, nup, kcap));
+    double* part2 = sc.get<double>(px::ms_part2_doubles(R, nup, kcap));
+    double* G = sc.get<double>((size_t)(kcap + 1) * 2 * R);
+    double* H = sc.get<double>((size_t)(kcap + 1) * kcap * R);
+    double* coefv = sc.get<double>((size_t)kcap * R);
+    double* coefu = sc.get<double>((size_t)kcap * R);
+    double* scal = sc.get<double>((size_t)3 * R);
     double2* z = sc.get<double2>(P);
     double* cs = sc.get<double>((size_t)kcap * P);
     double2* sn = sc.get<double2>((size_t)kcap * P);
     double2* g = sc.get<double2>((size_t)(kcap + 1) * P);
-    const int GB = px::ms_givens_batch();
     double2* rst = sc.get<double2>(px::ms_rst_elems(P, kcap));
     double2* ycoef = sc.get<double2>((size_t)kcap * P);
     double* target = sc.get<double>(P);
@@ -675,46 +679,45 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipMemcpyAsync(bn, s->bnorm.data(), sizeof(double) * npol, hipMemcpyHostToDevice, st));
     px::fill_zero(done, sizeof(int32_t) * P, st);
     px::fill_zero(ndone, sizeof(int32_t), st);
-    px::ms_init(R, s->b, s->ldg, npol, bn, V, nup, st);
+    px::ms_init(R, s->b, s->ldg, bn, u, nup, st);
 
-    const int method = tapply_method(s, false, V, Y, R, R, o);
+    const int method = tapply_method(s, false, u, Y, R, R, o);
     const int lag = method == TA_STORED ? 1 : kLag;
     s->sync.ensure(kcap + 1);
     int32_t* stop = s->sync.flag();
     s->sync.reset(st);
     StepTimer tm(o.timings != 0);
     tm.ensure(kcap);
-    int launched = 0;
+    int launched = 0, gnext = 0;
     for (int k = 0; k < kcap; ++k) {
         if (k >= lag && s->sync.stopped(k - lag)) break;
-        const double* vk = V + (size_t)k * vstride;
-        double* hk = hpk + (size_t)k * (k + 3) / 2 * R;
         tm.mark(k, 0, st);
-        tapply(s, method, false, vk, Y, R, R, stop);
+        // wt = Kbar T u for the candidate u of v_k
+        tapply(s, method, false, u, Y, R, R, stop);
         tm.mark(k, 1, st);
-        px::ms_spmv(R, s->g, Y, w, st, stop);
+        px::ms_spmv(R, s->g, Y, wt, st, stop);
         tm.mark(k, 2, st);
-        // classical Gram-Schmidt twice; column k of Hbar = both passes' coefficients
-        px::ms_dots(R, V, vstride, k + 1, w, part, nup, S1, nullptr, nullptr, st, stop);
-        px::ms_update(R, V, vstride, k + 1, S1, w, part2, nup, st, stop);
-        px::ms_dots(R, V, vstride, k + 1, w, part, nup, S2, S1, hk, st, stop);
-        px::ms_update(R, V, vstride, k + 1, S2, w, part2, nup, st, stop);
-        px::ms_dots(R, w, 0, 1, w, part, nup, nrm2, nullptr, nullptr, st, stop);
-        px::ms_normalize(R, w, nrm2, V + (size_t)(k + 1) * vstride, hk + (size_t)(k + 1) * R, nup, st, stop);
-        // the shifted Givens QRs take GB Hessenberg columns per launch
-        if ((k + 1) % GB == 0 || k + 1 == kcap)
-            px::ms_givens(hpk, R, npol, P, (k / GB) * GB, k % GB + 1, z, cs, sn, g, target, done, resid, ndone, stop,
-                          st);
+        // one dot and one update pass: v_k final, column k-1 of Hbar final
+        px::ms_step(R, V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup, false, st, stop);
+        // the shifted Givens QRs take GB finished Hessenberg columns per launch
+        if (k - gnext >= GB) {
+            px::ms_givens(H, kcap, npol, P, gnext, GB, z, cs, sn, g, target, done, resid, ndone, stop, st);
+            gnext += GB;
+        }
         tm.mark(k, 3, st);
         s->sync.publish(k, st);
         ++launched;
     }
-    if (launched % GB != 0 && launched < kcap)   // stopped early: the last partial batch (a no-op once all converged)
-        px::ms_givens(hpk, R, npol, P, (launched / GB) * GB, launched % GB, z, cs, sn, g, target, done, resid, ndone,
-                      stop, st);
-    px::ms_rfactor(hpk, R, npol, P, launched, z, cs, sn, done, rst, st);
+    // the last column's correction (a no-op once every pair converged), then its rotations
+    px::ms_step(R, V, vstride, launched, u, u, part, part2, G, H, kcap, coefv, coefu, scal, nup, true, st, stop);
+    while (gnext < launched) {
+        const int kn = std::min(GB, launched - gnext);
+        px::ms_givens(H, kcap, npol, P, gnext, kn, z, cs, sn, g, target, done, resid, ndone, stop, st);
+        gnext += kn;
+    }
+    px::ms_rfactor(H, kcap, npol, P, launched, z, cs, sn, done, rst, st);
     px::ms_backsub(rst, P, launched, done, g, ycoef, st);
-    px::ms_xcombine(R, V, vstride, launched, ycoef, npol, P, s->x, s->ldg, nup, st);
+    px::ms_xcombine(R, V, vstride, launched, ycoef, P, s->x, s->ldg, nup, st);
     std::vector<int32_t> dh(P);
     std::vector<double> rh(P);
     HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
@@ -727,8 +730,9 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
         s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
         executed = std::max(executed, s->iters[p]);
     }
+    // the device ran one step past the last column it needed (that column's correction)
+    executed = std::min(launched, executed + 1);
     tm.collect(executed, s->ms[2], s->ms[3], s->ms[4]);
-    // accounting over the steps the device executed
     const double nu = (double)s->g.nu;
     s->tstats[method == TA_STORED ? 3 : 2] += executed;
     s->counts[3] += executed;
@@ -736,8 +740,8 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     s->counts[5] += (int64_t)executed * npol;
     s->tflop[method == TA_STORED ? 3 : 2] += 2.0 * nu * nu * npol * executed;
     s->work[1] += 2.0 * nu * nu * npol * executed;
-    // four passes over the basis per step (two dot, two update)
-    s->work[2] += 4.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
+    // one dot and one update pass over the basis per step
+    s->work[2] += 2.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
 }
 
 pxStatus check_options(const pxSolveOptions& o)

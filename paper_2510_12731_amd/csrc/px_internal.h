@@ -52,7 +52,20 @@ struct Geometry {
     // sum, same-type and other-type neighbour counts)
     uint8_t* type = nullptr;
     double4* hrow = nullptr;
+    // omegaFQ near field in FP64 (built by ensure_near_f64): CSR over the real
+    // atoms of T - T_point for the pairs closer than the FP64 far threshold,
+    // -erfc(r/R)/r off the diagonal and the self term on it
+    int32_t* near_ptr = nullptr;
+    int32_t* near_col = nullptr;
+    double* near_val = nullptr;
+    int64_t near_nnz = 0;
 };
+
+// Exclusive scan of cnt[0..n) into row_ptr[0..n] (one workgroup).
+void scan_counts(const int32_t* cnt, int64_t n, int32_t* row_ptr, hipStream_t st);
+// Builds g's FP64 near-field list for the omegaFQ narrow T-apply once
+// (a no-op when built or for the dipole model); synchronises st.
+hipError_t ensure_near_f64(Geometry& g, hipStream_t st);
 
 // ---- T-apply launchers (px_tapply.hip) -------------------------------------
 // Y = T X over real columns: X, Y are [nup][ldx] (row-major, component-major
@@ -204,30 +217,30 @@ void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int
                   double2* x, int Bc, int nseg, int64_t rows, hipStream_t st);
 
 // ---- shared-Krylov solve (px_shifted.hip) ----------------------------------
-// R real slots per row (2 or 4), one per polarization; see px_shifted.hip.
-void ms_init(int R, const double2* b, int ldb, int npol, const double* bnorm, double* V0, int64_t nup, hipStream_t st);
+// R = npol real slots per row (1..3), one per polarization; Hbar row-major per
+// slot with row stride kcap; see px_shifted.hip.
+void ms_init(int R, const double2* b, int ldb, const double* bnorm, double* u, int64_t nup, hipStream_t st);
 void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop);
-// dots of w with V_0..V_{nvec-1} per slot into out[nvec][R] (and base + dots into out2)
-void ms_dots(int R, const double* V, int64_t vstride, int nvec, const double* w, double* part, int64_t nup,
-             double* out, const double* base, double* out2, hipStream_t st, const int32_t* stop);
-void ms_update(int R, const double* V, int64_t vstride, int nvec, const double* s, double* w, double* part2,
-               int64_t nup, hipStream_t st, const int32_t* stop);
-size_t ms_part_doubles(int R, int64_t nup, int nvec_max);
-size_t ms_part2_doubles(int R, int64_t nup, int nvec_max);
-void ms_normalize(int R, const double* w, const double* nrm2, double* vnext, double* hnext, int64_t nup,
-                  hipStream_t st, const int32_t* stop);
+// One DCGS2 step k: dots of [V_{<k}, u] with u and wt, the coefficients (column
+// k-1 corrected, column k first pass) and the update pass writing V_k and the
+// next candidate u; fix_only: the last column's correction alone.
+void ms_step(int R, double* V, int64_t vstride, int k, double* u, const double* wt, double* part, double* part2,
+             double* G, double* H, int kcap, double* coefv, double* coefu, double* scal, int64_t nup, bool fix_only,
+             hipStream_t st, const int32_t* stop);
+size_t ms_part_doubles(int R, int64_t nup, int kcap);
+size_t ms_part2_doubles(int R, int64_t nup, int kcap);
 // Hessenberg columns k0 .. k0+kn-1 (kn <= ms_givens_batch()) for every (frequency, polarization) pair
 int ms_givens_batch();
-void ms_givens(const double* hpk, int R, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
+void ms_givens(const double* H, int kcap, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
                double2* g, const double* target, int32_t* done, double* resid, int32_t* ndone, int32_t* stop,
                hipStream_t st);
 // every pair's triangular factor, packed, into rst (ms_rst_elems(P, kcap) complex)
 size_t ms_rst_elems(int P, int kcap);
-void ms_rfactor(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
+void ms_rfactor(const double* H, int kcap, int npol, int P, int kmax, const double2* z, const double* cs,
                 const double2* sn, const int32_t* done, double2* rst, hipStream_t st);
 // y = R^-1 g per pair (kmax <= 4000: g is staged in LDS)
 void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const double2* g, double2* y, hipStream_t st);
-void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int npol, int P, double2* x,
-                 int ldx, int64_t nup, hipStream_t st);
+void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
+                 int64_t nup, hipStream_t st);
 
 }  // namespace px

@@ -1635,6 +1635,11 @@ void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* p
                        perm, x, ldx);
 }
 
+void scan_counts(const int32_t* cnt, int64_t n, int32_t* row_ptr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, n, row_ptr);
+}
+
 void fill_zero(void* p, size_t bytes, hipStream_t st)
 {
     size_t words = bytes / 4;

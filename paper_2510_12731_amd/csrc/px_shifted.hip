@@ -10,14 +10,13 @@
 // (Section 6, "iterative on the fly"): each shift only adds its own Givens QR
 // of the small shifted Hessenberg matrix.
 //
-// Layout: the basis of the npol polarizations is interleaved, V[k][row][slot]
-// (R = 2 or 4 real slots per row, slot = polarization index, unused slots
-// zero), so the narrow FP64 T-apply reads one basis vector of every
-// polarization in one pass over the atom pairs.  Per (frequency,
+// Layout: the basis of the R = npol polarizations is interleaved,
+// V[k][row][slot], so the narrow FP64 T-apply reads one basis vector of every
+// polarization in one pass over the atom pairs.  Hbar is stored row-major per
+// polarization, H[(slot (kcap + 1) + row) kcap + column].  Per (frequency,
 // polarization) pair p = w * npol + slot (the solver's column index): the
 // rotations cs[k][p], sn[k][p] and the rotated right-hand side g[k][p],
-// coalesced over p.  Hessenberg columns are stored packed: column k has rows
-// 0..k+1 at row offset k (k + 3) / 2.
+// coalesced over p.
 #include "px_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -36,38 +35,44 @@ __device__ __forceinline__ double2 cfma_real(double v, double2 y, double2 acc)
     return make_double2(fma(v, y.x, acc.x), fma(v, y.y, acc.y));
 }
 
-// Block sum of R values over 256 threads in a fixed order; thread 0 returns it.
-template <int R>
-__device__ __forceinline__ void block_sum(double (&v)[R], double (*lds)[R])
+// Block sum of W values over 256 threads in a fixed order; thread 0 returns it.
+template <int W>
+__device__ __forceinline__ void block_sum(double (&v)[W], double (*lds)[W])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-    for (int c = 0; c < R; ++c)
+    for (int c = 0; c < W; ++c)
         for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
     if (lane == 0)
 #pragma unroll
-        for (int c = 0; c < R; ++c) lds[wave][c] = v[c];
+        for (int c = 0; c < W; ++c) lds[wave][c] = v[c];
     __syncthreads();
     if (tid == 0)
 #pragma unroll
-        for (int c = 0; c < R; ++c) v[c] = (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]);
+        for (int c = 0; c < W; ++c) v[c] = (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
 }  // namespace
 
-// V0[row][c] = b[row][c].x / bnorm[c] for c < npol (the right-hand sides of
-// the first frequency's columns), 0 otherwise.
+// u[row][c] = b[row][c].x / bnorm[c] (the right-hand sides of the first
+// frequency's columns, normalised).
 template <int R>
-__global__ void k_ms_init(const double2* __restrict__ b, int ldb, int npol, const double* __restrict__ bnorm,
-                          double* __restrict__ V0, int64_t nup)
+__global__ void k_ms_init(const double2* __restrict__ b, int ldb, const double* __restrict__ bnorm,
+                          double* __restrict__ u, int64_t nup)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nup) return;
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         double v = 0.0;
-        if (c < npol && bnorm[c] > 0.0) v = b[(size_t)r * ldb + c].x / bnorm[c];
-        V0[(size_t)r * R + c] = v;
+        if (bnorm[c] > 0.0) v = b[(size_t)r * ldb + c].x / bnorm[c];
+        u[(size_t)r * R + c] = v;
     }
 }
 
@@ -96,53 +101,133 @@ __global__ __launch_bounds__(256) void k_ms_spmv(const int32_t* __restrict__ rp,
     for (int c = 0; c < R; ++c) w[(size_t)i * R + c] = acc[c];
 }
 
-// part[(j * nslab + slab)][c] = sum over the slab's rows of V_j[row][c] w[row][c]
+// ---- delayed classical Gram-Schmidt (DCGS2) --------------------------------
+// Step k holds u, the candidate for v_k orthogonalised once against V_{<k} in
+// step k-1, and wt = M u.  One dot pass gives s = V_{<k}^T u, c = V_{<k}^T wt,
+// <u,u> and <u,wt>.  Then rho = sqrt(<u,u> - |s|^2) and v_k = (u - V_{<k} s)
+// / rho; column k-1 of Hbar gains s (rows < k) and rho (row k); with
+// c_k = (<u,wt> - s.c) / rho and t = Hbar_{(k+1) x k} s, the first-pass
+// column k is h_j = (c_j - t_j) / rho (j < k), h_k = (c_k - t_k) / rho, and
+// the next candidate is u' = M v_k - V_{<=k} h = wt / rho - (c_k / rho^2) u
+// - V_{<k} d with d = (c - (c_k / rho) s) / rho: one update pass over V_{<k}
+// writes v_k and u'.
+
+// part[(j * nslab + slab)][c] = sum over the slab's rows of x_j[row][c] u[row][c]
+// and part[..][R + c] the same with wt, where x_j = V_j (j < k) or u (j = k).
 template <int R>
-__global__ __launch_bounds__(256) void k_ms_dots(const double* __restrict__ V, int64_t vstride,
-                                                 const double* __restrict__ w, double* __restrict__ part,
-                                                 int64_t nup, int64_t rows_per_slab, const int32_t* __restrict__ stop)
+__global__ __launch_bounds__(256) void k_ms_dots(const double* __restrict__ V, int64_t vstride, int k,
+                                                 const double* __restrict__ u, const double* __restrict__ wt,
+                                                 double* __restrict__ part, int64_t nup, int64_t rows_per_slab,
+                                                 const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
-    __shared__ double lds[4][R];
+    constexpr int W = 2 * R;
+    __shared__ double lds[4][W];
     const int j = blockIdx.y, slab = blockIdx.x, nslab = gridDim.x;
     const int64_t r0 = (int64_t)slab * rows_per_slab;
     const int64_t r1 = r0 + rows_per_slab < nup ? r0 + rows_per_slab : nup;
-    const double* vj = V + (size_t)j * vstride;
-    double acc[R];
+    const double* xj = j < k ? V + (size_t)j * vstride : u;
+    double acc[W];
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+    for (int c = 0; c < W; ++c) acc[c] = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = fma(vj[(size_t)r * R + c], w[(size_t)r * R + c], acc[c]);
+        for (int c = 0; c < R; ++c) {
+            const double x = xj[(size_t)r * R + c];
+            acc[c] = fma(x, u[(size_t)r * R + c], acc[c]);
+            acc[R + c] = fma(x, wt[(size_t)r * R + c], acc[R + c]);
+        }
     }
-    block_sum<R>(acc, lds);
+    block_sum<W>(acc, lds);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int c = 0; c < R; ++c) part[((size_t)j * nslab + slab) * R + c] = acc[c];
+        for (int c = 0; c < W; ++c) part[((size_t)j * nslab + slab) * W + c] = acc[c];
 }
 
-// s[j][c] = sum over slabs of part (fixed order); out[j][c] = s, and
-// out2[j][c] = base[j][c] + s when out2 is given.
-template <int R>
-__global__ void k_ms_reduce(const double* __restrict__ part, int nslab, int nvec, double* __restrict__ out,
-                            const double* __restrict__ base, double* __restrict__ out2,
+// G[j][c] = sum over slabs of part[j][slab][c] (fixed order), W values per j.
+template <int W>
+__global__ void k_ms_reduce(const double* __restrict__ part, int nslab, int nvec, double* __restrict__ G,
                             const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nvec * R) return;
-    const int j = t / R, c = t - j * R;
+    if (t >= nvec * W) return;
+    const int j = t / W, c = t - j * W;
     double s = 0.0;
-    for (int q = 0; q < nslab; ++q) s += part[((size_t)j * nslab + q) * R + c];
-    out[t] = s;
-    if (out2) out2[t] = base[t] + s;
+    for (int q = 0; q < nslab; ++q) s += part[((size_t)j * nslab + q) * W + c];
+    G[t] = s;
 }
 
-// w -= sum_j V_j s[j] over the vectors of split blockIdx.y; with one split the
-// result goes to w, else the split's sum goes to part2[split] for k_ms_combine.
+// The coefficients of step k from G (layout of k_ms_dots), one wave per row j
+// of Hbar (j = 0..k) and slot c = blockIdx.y: corrects column k-1, writes the
+// first-pass column k (rows 0..k), coefv[j][c] = s_j / rho and coefu[j][c] =
+// d_j, and scal[c] = {1 / rho, 1 / rho, -c_k / rho^2}.  fix_only: the last
+// column's correction alone.  A zero rho (an invariant subspace) zeroes v_k
+// and u'.
 template <int R>
-__global__ __launch_bounds__(256) void k_ms_update(const double* __restrict__ V, int64_t vstride, int nvec,
-                                                   const double* __restrict__ s, double* __restrict__ w,
+__global__ __launch_bounds__(256) void k_ms_coef(const double* __restrict__ G, double* __restrict__ H, int kcap,
+                                                 int k, int fix_only, double* __restrict__ coefv,
+                                                 double* __restrict__ coefu, double* __restrict__ scal,
+                                                 const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;
+    constexpr int W = 2 * R;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = blockIdx.y;
+    if (j > k) return;
+    double ss = 0.0, sc = 0.0;
+    for (int i = lane; i < k; i += 64) {
+        const double si = G[i * W + c];
+        ss = fma(si, si, ss);
+        sc = fma(si, G[i * W + R + c], sc);
+    }
+    ss = wave_sum(ss);
+    sc = wave_sum(sc);
+    const double rho2 = G[k * W + c] - ss;
+    const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
+    const double ck = (G[k * W + R + c] - sc) * inv;
+    double* hrow = H + ((size_t)c * (kcap + 1) + j) * kcap;
+    const double sj = j < k ? G[j * W + c] : 0.0;
+    double hfix = 0.0;
+    if (k >= 1) hfix = j < k ? hrow[k - 1] + sj : rho;
+    if (fix_only) {
+        if (lane == 0 && k >= 1) hrow[k - 1] = hfix;
+        return;
+    }
+    // t_j = sum_{i >= j-1, i < k} Hbar[j][i] s_i with the corrected column k-1
+    double t = 0.0;
+    for (int i = (j > 0 ? j - 1 : 0) + lane; i < k; i += 64) {
+        const double h = i == k - 1 ? hfix : hrow[i];
+        t = fma(h, G[i * W + c], t);
+    }
+    t = wave_sum(t);
+    if (lane == 0) {
+        if (k >= 1) hrow[k - 1] = hfix;
+        const double cj = j < k ? G[j * W + R + c] : ck;
+        hrow[k] = (cj - t) * inv;
+        if (j < k) {
+            coefv[j * R + c] = sj * inv;
+            coefu[j * R + c] = (cj - ck * inv * sj) * inv;
+        }
+        if (j == 0) {
+            scal[c * 3 + 0] = inv;
+            scal[c * 3 + 1] = inv;
+            scal[c * 3 + 2] = -ck * inv * inv;
+        }
+    }
+}
+
+// One pass over V_{<k}: v_k = scal0 u - V coefv and u' = scal1 wt + scal2 u -
+// V coefu (in place).  The vectors are split over blockIdx.y; with one split
+// the results are written directly, else the split sums go to part2 and
+// k_ms_finish adds them in a fixed order.
+template <int R>
+__global__ __launch_bounds__(256) void k_ms_update(const double* __restrict__ V, int64_t vstride, int k,
+                                                   const double* __restrict__ coefv, const double* __restrict__ coefu,
+                                                   const double* __restrict__ scal, double* __restrict__ u,
+                                                   const double* __restrict__ wt, double* __restrict__ vk,
                                                    double* __restrict__ part2, int64_t nup, int vecs_per_split,
                                                    const int32_t* __restrict__ stop)
 {
@@ -150,56 +235,66 @@ __global__ __launch_bounds__(256) void k_ms_update(const double* __restrict__ V,
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nup) return;
     const int j0 = blockIdx.y * vecs_per_split;
-    const int j1 = j0 + vecs_per_split < nvec ? j0 + vecs_per_split : nvec;
-    double acc[R];
+    const int j1 = j0 + vecs_per_split < k ? j0 + vecs_per_split : k;
+    double av[R], au[R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) acc[c] = 0.0;
+    for (int c = 0; c < R; ++c) av[c] = au[c] = 0.0;
     for (int j = j0; j < j1; ++j) {
         const double* vj = V + (size_t)j * vstride + (size_t)r * R;
 #pragma unroll
-        for (int c = 0; c < R; ++c) acc[c] = fma(vj[c], s[j * R + c], acc[c]);
+        for (int c = 0; c < R; ++c) {
+            const double x = vj[c];
+            av[c] = fma(x, coefv[j * R + c], av[c]);
+            au[c] = fma(x, coefu[j * R + c], au[c]);
+        }
     }
     if (gridDim.y == 1) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) w[(size_t)r * R + c] -= acc[c];
+        for (int c = 0; c < R; ++c) {
+            const size_t o = (size_t)r * R + c;
+            const double uo = u[o];
+            vk[o] = scal[c * 3] * uo - av[c];
+            u[o] = scal[c * 3 + 1] * wt[o] + scal[c * 3 + 2] * uo - au[c];
+        }
     } else {
 #pragma unroll
-        for (int c = 0; c < R; ++c) part2[((size_t)blockIdx.y * nup + r) * R + c] = acc[c];
+        for (int c = 0; c < R; ++c) {
+            part2[((size_t)blockIdx.y * nup + r) * 2 * R + c] = av[c];
+            part2[((size_t)blockIdx.y * nup + r) * 2 * R + R + c] = au[c];
+        }
     }
 }
 
 template <int R>
-__global__ void k_ms_combine(const double* __restrict__ part2, int nsplit, double* __restrict__ w, int64_t nup,
-                             const int32_t* __restrict__ stop)
+__global__ void k_ms_finish(const double* __restrict__ part2, int nsplit, const double* __restrict__ scal,
+                            double* __restrict__ u, const double* __restrict__ wt, double* __restrict__ vk,
+                            int64_t nup, const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nup * R) return;
-    double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += part2[(size_t)q * nup * R + t];
-    w[t] -= s;
+    const int64_t r = t / R;
+    const int c = (int)(t - r * R);
+    double av = 0.0, au = 0.0;
+    for (int q = 0; q < nsplit; ++q) {
+        av += part2[((size_t)q * nup + r) * 2 * R + c];
+        au += part2[((size_t)q * nup + r) * 2 * R + R + c];
+    }
+    const double uo = u[t];
+    vk[t] = scal[c * 3] * uo - av;
+    u[t] = scal[c * 3 + 1] * wt[t] + scal[c * 3 + 2] * uo - au;
 }
 
-// V_next = w / ||w|| per slot (zero for a zero norm: an invariant subspace,
-// where every shift of that polarization has converged); hnext[c] = ||w||.
-template <int R>
-__global__ void k_ms_normalize(const double* __restrict__ w, const double* __restrict__ nrm2,
-                               double* __restrict__ vnext, double* __restrict__ hnext, int64_t nup,
-                               const int32_t* __restrict__ stop)
+// Entry (j, K) of Hbar for polarization c.
+__device__ __forceinline__ double hget(const double* __restrict__ H, int kcap, int c, int j, int K)
 {
-    if (stop && *stop) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < R) hnext[t] = sqrt(nrm2[t]);
-    if (t >= nup * R) return;
-    const int c = (int)(t % R);
-    const double b = sqrt(nrm2[c]);
-    vnext[t] = b > 0.0 ? w[t] / b : 0.0;
+    return H[((size_t)c * (kcap + 1) + j) * kcap + K];
 }
 
-// Hessenberg column K of polarization c, entry j, with the shift on the diagonal.
-__device__ __forceinline__ double2 hs(const double* __restrict__ hpk, int R, int c, int K, int j, double2 zp)
+// Entry (j, K) of Hbar - z I~ (the shift on the diagonal).
+__device__ __forceinline__ double2 hs(const double* __restrict__ H, int kcap, int c, int K, int j, double2 zp)
 {
-    const double h = hpk[((size_t)K * (K + 3) / 2 + j) * R + c];
+    const double h = hget(H, kcap, c, j, K);
     return j == K ? make_double2(h - zp.x, -zp.y) : make_double2(h, 0.0);
 }
 
@@ -228,7 +323,7 @@ struct RotBatch {
 __device__ __forceinline__ size_t rpk(int l, int j) { return (size_t)l * (l + 1) / 2 + j; }
 
 __device__ __forceinline__ void load_rots(RotBatch& b, const double* __restrict__ cs, const double2* __restrict__ sn,
-                                          const double* __restrict__ hpk, int R, int c, int P, int p, int k0, int nb,
+                                          const double* __restrict__ H, int kcap, int c, int P, int p, int k0, int nb,
                                           int j0)
 {
 #pragma unroll
@@ -240,7 +335,7 @@ __device__ __forceinline__ void load_rots(RotBatch& b, const double* __restrict_
 #pragma unroll
             for (int q = 0; q < GB; ++q) {
                 const int l = k0 + q;
-                if (q < nb) b.h[u][q] = hpk[((size_t)l * (l + 3) / 2 + j + 1) * R + c];
+                if (q < nb) b.h[u][q] = hget(H, kcap, c, j + 1, l);
             }
         }
     }
@@ -273,7 +368,7 @@ __device__ __forceinline__ void apply_rots(const RotBatch& b, double2 (&a)[GB], 
 // residual norm |g[K+1][p]|.  One thread per (frequency, polarization) pair;
 // the thread that finishes the last pair raises *stop.  Nothing is stored
 // inside the chains (stores and loads share one completion counter here).
-__global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ hpk, int R, int npol, int P, int k0,
+__global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ H, int kcap, int npol, int P, int k0,
                                                   int kn, const double2* __restrict__ z, double* __restrict__ cs,
                                                   double2* __restrict__ sn, double2* __restrict__ g,
                                                   const double* __restrict__ target,
@@ -288,13 +383,13 @@ __global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ hpk
     double2 a[GB];
 #pragma unroll
     for (int q = 0; q < GB; ++q)
-        if (q < kn) a[q] = hs(hpk, R, c, k0 + q, 0, zp);
+        if (q < kn) a[q] = hs(H, kcap, c, k0 + q, 0, zp);
     RotBatch b0, b1;
-    load_rots(b0, cs, sn, hpk, R, c, P, p, k0, kn, 0);
+    load_rots(b0, cs, sn, H, kcap, c, P, p, k0, kn, 0);
     for (int j0 = 0; j0 < k0; j0 += 2 * GU) {
-        load_rots(b1, cs, sn, hpk, R, c, P, p, k0, kn, j0 + GU);
+        load_rots(b1, cs, sn, H, kcap, c, P, p, k0, kn, j0 + GU);
         apply_rots(b0, a, k0, kn, j0, zp);
-        load_rots(b0, cs, sn, hpk, R, c, P, p, k0, kn, j0 + 2 * GU);
+        load_rots(b0, cs, sn, H, kcap, c, P, p, k0, kn, j0 + 2 * GU);
         apply_rots(b1, a, k0, kn, j0 + GU, zp);
     }
     double rc[GB];
@@ -307,8 +402,8 @@ __global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ hpk
         double2 u = a[q];
 #pragma unroll
         for (int t = 0; t < GB; ++t)
-            if (t < q) (void)rotate(rc[t], rs[t], u, hs(hpk, R, c, K, k0 + t + 1, zp));
-        const double beta = hpk[((size_t)K * (K + 3) / 2 + K + 1) * R + c];
+            if (t < q) (void)rotate(rc[t], rs[t], u, hs(H, kcap, c, K, k0 + t + 1, zp));
+        const double beta = hget(H, kcap, c, K + 1, K);
         const double aa = sqrt(u.x * u.x + u.y * u.y);
         double ck;
         double2 sk;
@@ -341,7 +436,7 @@ __global__ __launch_bounds__(64) void k_ms_givens(const double* __restrict__ hpk
 // K_p <= l skip), rebuilt by the same chain of rotations as k_ms_givens:
 // rst[(l (l + 1) / 2 + j) P + p] = R_p[j][l].  One thread per pair; the many
 // columns in flight hide the chains' memory latency.
-__global__ __launch_bounds__(64) void k_ms_rfactor(const double* __restrict__ hpk, int R, int npol, int P, int kmax,
+__global__ __launch_bounds__(64) void k_ms_rfactor(const double* __restrict__ H, int kcap, int npol, int P, int kmax,
                                                    const double2* __restrict__ z, const double* __restrict__ cs,
                                                    const double2* __restrict__ sn, const int32_t* __restrict__ done,
                                                    double2* __restrict__ rst)
@@ -353,17 +448,16 @@ __global__ __launch_bounds__(64) void k_ms_rfactor(const double* __restrict__ hp
     if (l >= K) return;
     const int c = p % npol;
     const double2 zp = z[p];
-    double2 a = hs(hpk, R, c, l, 0, zp);
-    const double* hl = hpk + (size_t)l * (l + 3) / 2 * R;
+    double2 a = hs(H, kcap, c, l, 0, zp);
 #pragma unroll 4
     for (int j = 0; j < l; ++j) {
-        const double hv = hl[(j + 1) * R + c];
+        const double hv = hget(H, kcap, c, j + 1, l);
         const double2 b = j + 1 == l ? make_double2(hv - zp.x, -zp.y) : make_double2(hv, 0.0);
         rst[rpk(l, j) * P + p] = rotate(cs[(size_t)j * P + p], sn[(size_t)j * P + p], a, b);
     }
     const double cl = cs[(size_t)l * P + p];
     const double2 sl = sn[(size_t)l * P + p];
-    const double beta = hl[(l + 1) * R + c];
+    const double beta = hget(H, kcap, c, l + 1, l);
     rst[rpk(l, l) * P + p] = make_double2(cl * a.x + sl.x * beta, cl * a.y + sl.y * beta);
 }
 
@@ -446,6 +540,16 @@ __global__ __launch_bounds__(256) void k_ms_xcombine(const double* __restrict__ 
 
 // ---------------------------------------------------------------- launchers
 
+namespace {
+
+template <template <int> class F, typename... A>
+void with_r(int R, A... a)
+{
+    if (R == 1) F<1>::run(a...);
+    else if (R == 2) F<2>::run(a...);
+    else F<3>::run(a...);
+}
+
 int ms_slabs(int64_t nup, int nvec)
 {
     int64_t maxs = (nup + 255) / 256;
@@ -455,112 +559,131 @@ int ms_slabs(int64_t nup, int nvec)
     return (int)want;
 }
 
-int ms_update_splits(int64_t nup, int nvec)
+// vectors per split and number of splits of the update pass over k vectors
+void ms_update_split(int64_t nup, int k, int& vps, int& nsp)
 {
+    if (k <= 0) {
+        vps = 0;
+        nsp = 1;
+        return;
+    }
     const int64_t rb = (nup + 255) / 256;
     int64_t want = (1024 + rb - 1) / rb;
-    const int64_t maxs = (nvec + 15) / 16;
+    const int64_t maxs = (k + 15) / 16;
     if (want > maxs) want = maxs;
     if (want < 1) want = 1;
-    return (int)want;
+    vps = (int)((k + want - 1) / want);
+    nsp = (k + vps - 1) / vps;
 }
 
-void ms_init(int R, const double2* b, int ldb, int npol, const double* bnorm, double* V0, int64_t nup, hipStream_t st)
+template <int R>
+struct InitL {
+    static void run(const double2* b, int ldb, const double* bn, double* u, int64_t nup, hipStream_t st)
+    {
+        hipLaunchKernelGGL(k_ms_init<R>, dim3((unsigned)((nup + 255) / 256)), dim3(256), 0, st, b, ldb, bn, u, nup);
+    }
+};
+
+template <int R>
+struct SpmvL {
+    static void run(const Geometry* g, const double* Y, double* w, hipStream_t st, const int32_t* stop)
+    {
+        hipLaunchKernelGGL(k_ms_spmv<R>, dim3((unsigned)((g->np + 255) / 256)), dim3(256), 0, st, g->row_ptr, g->col,
+                           g->val, Y, w, g->n, g->np, stop);
+    }
+};
+
+template <int R>
+struct StepL {
+    static void run(const double* V, int64_t vstride, int k, double* u, const double* wt, double* part,
+                    double* part2, double* G, double* H, int kcap, double* coefv, double* coefu, double* scal,
+                    int64_t nup, int fix_only, hipStream_t st, const int32_t* stop)
+    {
+        constexpr int W = 2 * R;
+        const int nvec = k + 1;
+        const int nslab = ms_slabs(nup, nvec);
+        const int64_t rps = (nup + nslab - 1) / nslab;
+        hipLaunchKernelGGL(k_ms_dots<R>, dim3((unsigned)nslab, (unsigned)nvec), dim3(256), 0, st, V, vstride, k, u,
+                           wt, part, nup, rps, stop);
+        hipLaunchKernelGGL(k_ms_reduce<W>, dim3((unsigned)((nvec * W + 255) / 256)), dim3(256), 0, st, part, nslab,
+                           nvec, G, stop);
+        hipLaunchKernelGGL(k_ms_coef<R>, dim3((unsigned)((k + 1 + 3) / 4), (unsigned)R), dim3(256), 0, st, G, H,
+                           kcap, k, fix_only, coefv, coefu, scal, stop);
+        if (fix_only) return;
+        int vps, nsp;
+        ms_update_split(nup, k, vps, nsp);
+        double* vk = const_cast<double*>(V) + (size_t)k * vstride;
+        hipLaunchKernelGGL(k_ms_update<R>, dim3((unsigned)((nup + 255) / 256), (unsigned)nsp), dim3(256), 0, st, V,
+                           vstride, k, coefv, coefu, scal, u, wt, vk, part2, nup, vps, stop);
+        if (nsp > 1)
+            hipLaunchKernelGGL(k_ms_finish<R>, dim3((unsigned)((nup * R + 255) / 256)), dim3(256), 0, st, part2, nsp,
+                               scal, u, wt, vk, nup, stop);
+    }
+};
+
+template <int R>
+struct XcombL {
+    static void run(const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
+                    int64_t nup, hipStream_t st)
+    {
+        const dim3 grid((unsigned)((nup + 31) / 32), (unsigned)((P + 63) / 64));
+        hipLaunchKernelGGL(k_ms_xcombine<R>, grid, dim3(256), 0, st, V, vstride, K, y, R, P, x, ldx, nup);
+    }
+};
+
+}  // namespace
+
+void ms_init(int R, const double2* b, int ldb, const double* bnorm, double* u, int64_t nup, hipStream_t st)
 {
-    const dim3 grid((unsigned)((nup + 255) / 256));
-    if (R == 2) hipLaunchKernelGGL(k_ms_init<2>, grid, dim3(256), 0, st, b, ldb, npol, bnorm, V0, nup);
-    else hipLaunchKernelGGL(k_ms_init<4>, grid, dim3(256), 0, st, b, ldb, npol, bnorm, V0, nup);
+    with_r<InitL>(R, b, ldb, bnorm, u, nup, st);
 }
 
 void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop)
 {
-    const dim3 grid((unsigned)((g.np + 255) / 256));
-    if (R == 2)
-        hipLaunchKernelGGL(k_ms_spmv<2>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val, Y, w, g.n, g.np, stop);
-    else
-        hipLaunchKernelGGL(k_ms_spmv<4>, grid, dim3(256), 0, st, g.row_ptr, g.col, g.val, Y, w, g.n, g.np, stop);
+    with_r<SpmvL>(R, &g, Y, w, st, stop);
 }
 
-void ms_dots(int R, const double* V, int64_t vstride, int nvec, const double* w, double* part, int64_t nup,
-             double* out, const double* base, double* out2, hipStream_t st, const int32_t* stop)
+void ms_step(int R, double* V, int64_t vstride, int k, double* u, const double* wt, double* part, double* part2,
+             double* G, double* H, int kcap, double* coefv, double* coefu, double* scal, int64_t nup, bool fix_only,
+             hipStream_t st, const int32_t* stop)
 {
-    const int nslab = ms_slabs(nup, nvec);
-    const int64_t rps = (nup + nslab - 1) / nslab;
-    const dim3 grid((unsigned)nslab, (unsigned)nvec);
-    const dim3 rg((unsigned)((nvec * R + 255) / 256));
-    if (R == 2) {
-        hipLaunchKernelGGL(k_ms_dots<2>, grid, dim3(256), 0, st, V, vstride, w, part, nup, rps, stop);
-        hipLaunchKernelGGL(k_ms_reduce<2>, rg, dim3(256), 0, st, part, nslab, nvec, out, base, out2, stop);
-    } else {
-        hipLaunchKernelGGL(k_ms_dots<4>, grid, dim3(256), 0, st, V, vstride, w, part, nup, rps, stop);
-        hipLaunchKernelGGL(k_ms_reduce<4>, rg, dim3(256), 0, st, part, nslab, nvec, out, base, out2, stop);
-    }
+    with_r<StepL>(R, (const double*)V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup,
+                  fix_only ? 1 : 0, st, stop);
 }
 
-void ms_update(int R, const double* V, int64_t vstride, int nvec, const double* s, double* w, double* part2,
-               int64_t nup, hipStream_t st, const int32_t* stop)
+size_t ms_part_doubles(int R, int64_t nup, int kcap)
 {
-    const int nsplit = ms_update_splits(nup, nvec);
-    const int vps = (nvec + nsplit - 1) / nsplit;
-    const int nsp = (nvec + vps - 1) / vps;
-    const dim3 grid((unsigned)((nup + 255) / 256), (unsigned)nsp);
-    const dim3 cg((unsigned)((nup * R + 255) / 256));
-    if (R == 2) {
-        hipLaunchKernelGGL(k_ms_update<2>, grid, dim3(256), 0, st, V, vstride, nvec, s, w, part2, nup, vps, stop);
-        if (nsp > 1) hipLaunchKernelGGL(k_ms_combine<2>, cg, dim3(256), 0, st, part2, nsp, w, nup, stop);
-    } else {
-        hipLaunchKernelGGL(k_ms_update<4>, grid, dim3(256), 0, st, V, vstride, nvec, s, w, part2, nup, vps, stop);
-        if (nsp > 1) hipLaunchKernelGGL(k_ms_combine<4>, cg, dim3(256), 0, st, part2, nsp, w, nup, stop);
-    }
+    // ms_slabs(nup, nv) * nv <= 2048 + nv for every nv <= kcap + 1
+    (void)nup;
+    return (size_t)(2048 + kcap + 1) * 2 * R;
 }
 
-size_t ms_part_doubles(int R, int64_t nup, int nvec_max)
-{
-    size_t a = 0;
-    for (int nv : {1, nvec_max}) {
-        const size_t s = (size_t)ms_slabs(nup, nv) * nv * R;
-        if (s > a) a = s;
-    }
-    // ms_slabs(nup, nv) * nv is at most max(nv, 2048 + nv) over nv
-    const size_t b = (size_t)(2048 + nvec_max) * R;
-    return a > b ? a : b;
-}
-
-size_t ms_part2_doubles(int R, int64_t nup, int nvec_max)
+size_t ms_part2_doubles(int R, int64_t nup, int kcap)
 {
     int mx = 1;
-    for (int nv = 1; nv <= nvec_max; ++nv) {
-        const int nsplit = ms_update_splits(nup, nv);
-        const int vps = (nv + nsplit - 1) / nsplit;
-        const int nsp = (nv + vps - 1) / vps;
+    for (int k = 1; k <= kcap; ++k) {
+        int vps, nsp;
+        ms_update_split(nup, k, vps, nsp);
         if (nsp > mx) mx = nsp;
     }
-    return (size_t)mx * nup * R;
-}
-
-void ms_normalize(int R, const double* w, const double* nrm2, double* vnext, double* hnext, int64_t nup,
-                  hipStream_t st, const int32_t* stop)
-{
-    const dim3 grid((unsigned)((nup * R + 255) / 256));
-    if (R == 2) hipLaunchKernelGGL(k_ms_normalize<2>, grid, dim3(256), 0, st, w, nrm2, vnext, hnext, nup, stop);
-    else hipLaunchKernelGGL(k_ms_normalize<4>, grid, dim3(256), 0, st, w, nrm2, vnext, hnext, nup, stop);
+    return (size_t)mx * nup * 2 * R;
 }
 
 int ms_givens_batch() { return GB; }
 
-void ms_givens(const double* hpk, int R, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
+void ms_givens(const double* H, int kcap, int npol, int P, int k0, int kn, const double2* z, double* cs, double2* sn,
                double2* g, const double* target, int32_t* done, double* resid, int32_t* ndone, int32_t* stop,
                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ms_givens, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, hpk, R, npol, P, k0, kn, z, cs,
+    hipLaunchKernelGGL(k_ms_givens, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, H, kcap, npol, P, k0, kn, z, cs,
                        sn, g, target, done, resid, ndone, stop);
 }
 
-void ms_rfactor(const double* hpk, int R, int npol, int P, int kmax, const double2* z, const double* cs,
+void ms_rfactor(const double* H, int kcap, int npol, int P, int kmax, const double2* z, const double* cs,
                 const double2* sn, const int32_t* done, double2* rst, hipStream_t st)
 {
     if (kmax < 1) return;
-    hipLaunchKernelGGL(k_ms_rfactor, dim3((unsigned)((P + 63) / 64), (unsigned)kmax), dim3(64), 0, st, hpk, R, npol,
+    hipLaunchKernelGGL(k_ms_rfactor, dim3((unsigned)((P + 63) / 64), (unsigned)kmax), dim3(64), 0, st, H, kcap, npol,
                        P, kmax, z, cs, sn, done, rst);
 }
 
@@ -572,14 +695,10 @@ void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const 
                        y);
 }
 
-void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int npol, int P, double2* x,
-                 int ldx, int64_t nup, hipStream_t st)
+void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
+                 int64_t nup, hipStream_t st)
 {
-    const dim3 grid((unsigned)((nup + 31) / 32), (unsigned)((P + 63) / 64));
-    if (R == 2)
-        hipLaunchKernelGGL(k_ms_xcombine<2>, grid, dim3(256), 0, st, V, vstride, K, y, npol, P, x, ldx, nup);
-    else
-        hipLaunchKernelGGL(k_ms_xcombine<4>, grid, dim3(256), 0, st, V, vstride, K, y, npol, P, x, ldx, nup);
+    with_r<XcombL>(R, V, vstride, K, y, P, x, ldx, nup, st);
 }
 
 }  // namespace px

@@ -59,6 +59,11 @@ __device__ __forceinline__ float box_gap2(float4 alo, float4 ahi, float4 blo, fl
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Far-field thresholds x_far = r / R beyond which the Gaussian factors equal
+// their point limits to working precision (erfc(4) < 2^-25; erfc(6) < 2^-54;
+// for the dipole kernels the extra x^3 exp(-x^2) terms need 5 and 7).
+constexpr double XFAR_Q32 = 4.0, XFAR_Q64 = 6.0, XFAR_D32 = 5.0, XFAR_D64 = 7.0;
+
 // ============================ omegaFQ, FP32 MFMA ============================
 // Workgroup: 8 waves, 256 rows x 128 real columns; the X tile of each source
 // chunk is staged once in LDS for all eight.  Wave w: rows [row0, row0 + 32)
@@ -755,9 +760,10 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
         for (int c = 0; c < NC; ++c) acc[a][c] = 0.0;
 
     const int nchunk = np / NW_CHUNK;
-    const int cbeg = blockIdx.y * chunks_per_split;
-    const int cend = min(nchunk, cbeg + chunks_per_split);
-    for (int ch = cbeg; ch < cend; ++ch) {
+    // split y takes chunks y, y + nsplit, ...: the near-field chunks, which lie
+    // close together in Morton order, spread over the splits
+    (void)chunks_per_split;
+    for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y) {
         const int j0 = ch * NW_CHUNK;
         __syncthreads();
         sxyz[tid] = xyz[j0 + tid];
@@ -812,6 +818,80 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
         for (int c = 0; c < NC; ++c) out[a * cstride + (size_t)i * NC + c] = acc[a][c];
 }
 
+// 1/sqrt(x) for finite x > 0: the hardware estimate refined by one
+// third-order step y (1 + e/2 + 3e^2/8), e = 1 - x y^2, which takes the
+// estimate's relative error eps to O(eps^3), below FP64 rounding; the library
+// call adds only the special-input handling, which a pair distance never needs.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// The omegaFQ narrow blocks, T = T_point + C: this kernel applies the point
+// part 1/r to every pair (the self pair excluded), branch-free; the stored
+// near-field correction C (k_near_rows) is added by k_sum_splits_near.  The
+// source atoms are read by wave-uniform loads (through the scalar cache)
+// instead of LDS: every lane of a wave needs the same source atom at each
+// step, so one scalar load serves the whole wave and the LDS pipe, which the
+// CU's waves share, leaves the inner loop.
+template <int NC>
+__global__ __launch_bounds__(256) void k_tapply_f64_narrow_q(const double4* __restrict__ xyz,
+                                                             const float4* __restrict__ glo,
+                                                             const float4* __restrict__ ghi,
+                                                             const double* __restrict__ X,
+                                                             double* __restrict__ part, int np, int chunks_per_split,
+                                                             double inv_rqq, double t_self, float r_far2,
+                                                             const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x * 256 + tid;
+    const int wave_row0 = blockIdx.x * 256 + (tid & ~63);
+    const double4 pi = xyz[i];
+    const float4 g0lo = glo[wave_row0 >> 5], g1lo = glo[(wave_row0 >> 5) + 1];
+    const float4 g0hi = ghi[wave_row0 >> 5], g1hi = ghi[(wave_row0 >> 5) + 1];
+    const float4 rlo = make_float4(fminf(g0lo.x, g1lo.x), fminf(g0lo.y, g1lo.y), fminf(g0lo.z, g1lo.z), 0.f);
+    const float4 rhi = make_float4(fmaxf(g0hi.x, g1hi.x), fmaxf(g0hi.y, g1hi.y), fmaxf(g0hi.z, g1hi.z), 0.f);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    const int nchunk = np / NW_CHUNK;
+    // split y takes chunks y, y + nsplit, ... (near-field work spread over the splits)
+    (void)chunks_per_split;
+    for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y)
+    for (int gq = ch * (NW_CHUNK / GROUP); gq < (ch + 1) * (NW_CHUNK / GROUP); ++gq) {
+        const int j0 = uniform(gq * GROUP);
+        const int far = uniform(box_gap2(rlo, rhi, glo[gq], ghi[gq]) >= r_far2);
+        if (far) {
+#pragma unroll 4
+            for (int jj = 0; jj < GROUP; ++jj) {
+                const double4 pj = xyz[j0 + jj];
+                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const double rinv = rsqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = fma(rinv, X[(size_t)(j0 + jj) * NC + c], acc[c]);
+            }
+        } else {
+            // the point-charge part only (the self pair excluded); the near
+            // field comes from the stored correction in k_sum_splits_near
+#pragma unroll 4
+            for (int jj = 0; jj < GROUP; ++jj) {
+                const double4 pj = xyz[j0 + jj];
+                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const double rinv = rsqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
+                const double t = (i == j0 + jj) ? 0.0 : rinv;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[c]);
+            }
+        }
+    }
+    double* out = part + (size_t)blockIdx.y * np * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
+}
+
 __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict__ Y, size_t len, int nsplit,
     const int32_t* __restrict__ stop)
 {
@@ -821,6 +901,104 @@ __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + t];
     Y[t] = s;
+}
+
+// Y = sum of the split partial sums + C X over the near-field list, one wave
+// per row (lanes over the row's entries, fixed-order wave reduction).
+template <int NC>
+__global__ __launch_bounds__(256) void k_sum_splits_near(const double* __restrict__ part, int nsplit,
+                                                         double* __restrict__ Y, int64_t n, int64_t np,
+                                                         const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const double* __restrict__ X,
+                                                         const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= np) return;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    if (i < n) {
+        for (int32_t e = rp[i] + lane; e < rp[i + 1]; e += 64) {
+            const double v = val[e];
+            const double* x = X + (size_t)col[e] * NC;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] = fma(v, x[c], acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (lane < NC) {
+        double s = 0.0;
+        for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * np * NC + (size_t)i * NC + lane];
+        double a = acc[0];
+#pragma unroll
+        for (int c = 1; c < NC; ++c)
+            if (lane == c) a = acc[c];
+        Y[(size_t)i * NC + lane] = s + a;
+    }
+}
+
+// Near-field list of the omegaFQ T in FP64 over the real atoms: for every
+// pair closer than r_far (erfc(x) < 2^-54 beyond), C_ij = -erfc(r/R_qq)/r,
+// and C_ii = sqrt(2/pi)/R_q (the self term, Eq. tqq); columns increasing.
+// Pass 0 counts, pass 1 fills.  One thread per row atom; the 256 rows of a
+// block skip source groups whose bounding box is farther than r_far.
+template <int PASS>
+__global__ __launch_bounds__(256) void k_near_rows(const double4* __restrict__ xyz, const float4* __restrict__ glo,
+                                                   const float4* __restrict__ ghi, int64_t n, double r_far,
+                                                   double inv_rqq, double t_self, int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                   double* __restrict__ val)
+{
+    __shared__ double4 sp[GROUP];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    const int64_t g0 = ((int64_t)blockIdx.x * 256) / GROUP;
+    float4 blo = glo[g0], bhi = ghi[g0];
+    for (int q = 1; q < 256 / GROUP; ++q) {
+        const float4 a = glo[g0 + q], b = ghi[g0 + q];
+        blo = make_float4(fminf(blo.x, a.x), fminf(blo.y, a.y), fminf(blo.z, a.z), 0.f);
+        bhi = make_float4(fmaxf(bhi.x, b.x), fmaxf(bhi.y, b.y), fmaxf(bhi.z, b.z), 0.f);
+    }
+    const double4 pi = xyz[i];
+    const float lim = (float)(r_far * 1.0001 + 1e-3);
+    const double rf2 = r_far * r_far;
+    const int64_t ngroups = (n + GROUP - 1) / GROUP;
+    int count = 0;
+    int64_t out = (PASS == 1 && i < n) ? rp[i] : 0;
+    for (int64_t gq = 0; gq < ngroups; ++gq) {
+        if (box_gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;   // uniform over the block
+        __syncthreads();
+        if (tid < GROUP) sp[tid] = xyz[gq * GROUP + tid];
+        __syncthreads();
+        if (i >= n) continue;
+        for (int k = 0; k < GROUP; ++k) {
+            const int64_t j = gq * GROUP + k;
+            if (j >= n) break;
+            const double4 pj = sp[k];
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            if (j != i && !(r2 < rf2)) continue;
+            if (PASS == 0) {
+                ++count;
+            } else {
+                double v = t_self;
+                if (j != i) {
+                    const double r = sqrt(r2);
+                    v = -erfc(r * inv_rqq) / r;
+                }
+                col[out] = (int32_t)j;
+                val[out] = v;
+                ++out;
+            }
+        }
+    }
+    if (PASS == 0 && i < n) cnt[i] = count;
 }
 
 // ====================== grouped launches (many segments) ====================
@@ -933,10 +1111,6 @@ __global__ __launch_bounds__(256) void k_tapply_wfqfmu_f64_grouped(const GroupCo
 }
 
 
-// Far-field thresholds x_far = r / R beyond which the Gaussian factors equal
-// their point limits to working precision (erfc(4) < 2^-25; erfc(6) < 2^-54;
-// for the dipole kernels the extra x^3 exp(-x^2) terms need 5 and 7).
-constexpr double XFAR_Q32 = 4.0, XFAR_Q64 = 6.0, XFAR_D32 = 5.0, XFAR_D64 = 7.0;
 
 DipoleConstD dipole_const_d(const Geometry& g)
 {
@@ -954,11 +1128,23 @@ DipoleConstD dipole_const_d(const Geometry& g)
     return k;
 }
 
+// Source splits of the narrow kernels: about 16 workgroups per CU (several
+// rounds), which balances the rows' unequal near-field work better than one
+// round of long workgroups (measured on the 20k-atom sphere).
 int narrow_splits(const Geometry& g)
 {
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            ncu = v;
+        else
+            ncu = 256;
+    }
     int rb = (int)(g.np / 256);
     int nchunk = (int)(g.np / NW_CHUNK);
-    int want = (2048 + rb - 1) / rb;
+    int want = (16 * ncu + rb - 1) / rb;
     if (want < 1) want = 1;
     if (want > nchunk) want = nchunk;
     int cps = (nchunk + want - 1) / want;
@@ -975,8 +1161,16 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     double rqq = std::sqrt(2.0) * g.r_q;
     DipoleConstD kc = dipole_const_d(g);
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
-    hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi,
-                       X, scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc, stop);
+    if (MODEL == 0 && g.near_ptr) {
+        // point part on the fly, near-field correction from the stored list
+        hipLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X,
+                           scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, stop);
+        hipLaunchKernelGGL(k_sum_splits_near<NC>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, st, scratch, nsplit, Y,
+                           g.n, g.np, g.near_ptr, g.near_col, g.near_val, X, stop);
+        return;
+    }
+    hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X,
+                       scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc, stop);
     size_t len = (size_t)(MODEL ? 4 : 1) * g.np * NC;
     hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit, stop);
 }
@@ -1073,6 +1267,44 @@ int sk_workgroups(int64_t total) { return (int)std::max<int64_t>(1, std::min<int
 
 }  // namespace
 
+hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
+{
+    if (g.model != 0 || g.near_ptr) return hipSuccess;
+    const double rqq = std::sqrt(2.0) * g.r_q;
+    const double r_far = XFAR_Q64 * rqq;
+    int32_t* cnt = nullptr;
+    int32_t nnz = 0;
+    hipError_t e;
+#define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
+    PXCHK(hipMalloc(&cnt, sizeof(int32_t) * (g.n + 1)));
+    PXCHK(hipMalloc(&g.near_ptr, sizeof(int32_t) * (g.n + 1)));
+    hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, g.n,
+                       r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, cnt, nullptr, nullptr, nullptr);
+    scan_counts(cnt, g.n, g.near_ptr, st);
+    PXCHK(hipMemcpyAsync(&nnz, g.near_ptr + g.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PXCHK(hipStreamSynchronize(st));
+    g.near_nnz = nnz;
+    PXCHK(hipMalloc(&g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+    PXCHK(hipMalloc(&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+    hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, g.n,
+                       r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, nullptr, g.near_ptr, g.near_col, g.near_val);
+    PXCHK(hipStreamSynchronize(st));
+    PXCHK(hipGetLastError());
+    (void)hipFree(cnt);
+    return hipSuccess;
+fail:
+#undef PXCHK
+    (void)hipFree(cnt);
+    (void)hipFree(g.near_ptr);
+    (void)hipFree(g.near_col);
+    (void)hipFree(g.near_val);
+    g.near_ptr = g.near_col = nullptr;
+    g.near_val = nullptr;
+    g.near_nnz = 0;
+    return e;
+}
+
+
 size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols)
 {
     (void)ncols;
@@ -1124,7 +1356,9 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
         // narrow layout: ldx == ncols
         if (g.model == 0) {
             switch (ncols) {
+            case 1: launch_narrow<1, 0>(g, X, Y, st, scratch, stop); break;
             case 2: launch_narrow<2, 0>(g, X, Y, st, scratch, stop); break;
+            case 3: launch_narrow<3, 0>(g, X, Y, st, scratch, stop); break;
             case 4: launch_narrow<4, 0>(g, X, Y, st, scratch, stop); break;
             case 6: launch_narrow<6, 0>(g, X, Y, st, scratch, stop); break;
             default: launch_narrow<8, 0>(g, X, Y, st, scratch, stop); break;
