@@ -142,8 +142,11 @@ typedef struct {
  *                    operator, so all frequencies share one Krylov space);
  *                    columns it leaves above rel_tol continue in the blocked
  *                    solver from its iterate (the phase counts as one cycle).
- *                    0 = blocked solver only.  Ignored for PX_WFQFMU,
- *                    two-type structures, pxSolveBatch and the server.
+ *                    0 = blocked solver only.  Ignored for PX_WFQFMU and
+ *                    two-type structures.  pxSolveBatch and the server solve
+ *                    the structures it applies to whole (as pxSolveSpectrum
+ *                    does) on a pool of host threads with their own streams,
+ *                    beside the stacked block that takes the others.
  *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 4000]
  *                    (2000; lowered to keep its basis and the frequencies'
  *                    triangular factors, k^2/2 x 16 B per column, within a
@@ -217,12 +220,15 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
 pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt);
 
 /* Solves several structures together (all must use the same HIP stream and
- * have their frequencies set).  Every structure's columns are cut into
- * segments of opt->block_cols columns; the segments of all structures form one
- * stacked block whose Arnoldi steps run as single grouped launches (one
- * T-apply over a tile list covering every structure, one sparse apply, one
- * pass of each orthogonalisation kernel), with segments retiring at restart
- * boundaries.  Results are read per structure with pxGet*.  Returns
+ * have their frequencies set).  With opt->shifted = 1 (default) one-material
+ * PX_WFQ structures are solved whole, each as by pxSolveSpectrum, by up to
+ * four host threads with their own HIP streams (default priority), so that
+ * their solves overlap on the device.  Every other structure's columns are
+ * cut into segments of opt->block_cols columns; the segments of all of them
+ * form one stacked block whose Arnoldi steps run as single grouped launches
+ * (one T-apply over a tile list covering every structure, one sparse apply,
+ * one pass of each orthogonalisation kernel), with segments retiring at
+ * restart boundaries.  Results are read per structure with pxGet*.  Returns
  * PX_E_NOTCONV if any column of any structure missed rel_tol. */
 pxStatus pxSolveBatch(const pxStructure* s, int32_t n, const pxSolveOptions* opt);
 
@@ -244,7 +250,10 @@ typedef struct pxServer_t* pxServer;
 pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out);
 
 /* Queues a structure whose frequencies are set.  PX_E_OOM if it can never fit
- * the budget; PX_E_INVALID for a different stream. */
+ * the budget; PX_E_INVALID for a different stream.  With opt->shifted = 1 a
+ * one-material PX_WFQ structure starts solving at once, whole, on one of up to
+ * four worker threads with their own streams (it is returned by
+ * pxServerStep when done); the others join the stacked block. */
 pxStatus pxServerSubmit(pxServer sv, pxStructure s);
 
 /* Admits queued structures that fit, runs one restart cycle, and writes up to

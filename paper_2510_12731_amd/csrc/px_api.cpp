@@ -14,9 +14,12 @@
 #include "px_state.h"
 #include "px_engine.h"
 
+#include <condition_variable>
+#include <memory>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 
 #include <hip/hip_runtime.h>
@@ -156,15 +159,16 @@ void finish_solve(pxStructure_t* s)
 
 namespace {
 
-void ensure_workspace(pxStructure_t* s, int lda, int m)
+// The active block's vectors and the T-apply scratch: everything a true
+// residual and an operator apply need (lda columns).
+void ensure_vectors(pxStructure_t* s, int lda)
 {
     Workspace& W = s->ws;
     const int64_t nup = s->g.nup;
-    if (W.lda_cap >= lda && W.m_cap >= m && W.nup == nup) return;
+    if (W.lda_cap >= lda && W.nup == nup) return;
     W.release();
     const size_t vec = (size_t)nup * lda;
     const int nchunk = px::arnoldi_chunks(nup);
-    W.V = dalloc<double2>((size_t)(m + 1) * vec);
     W.w = dalloc<double2>(vec);
     W.xs = dalloc<double2>(vec);
     W.rs = dalloc<double2>(vec);
@@ -173,20 +177,7 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     W.X32 = dalloc<float>(2 * vec);
     W.Y32 = dalloc<float>(2 * vec);
     W.Y64 = dalloc<double>(2 * vec);
-    W.partial = dalloc<double2>(std::max((size_t)nchunk * (m + 1), px::dot_partial_slabs(nup, m + 1)) * 2 * lda);
     W.npart = dalloc<double>((size_t)std::max(nchunk, px::update_chunks(nup)) * lda);
-    W.h1 = dalloc<double2>((size_t)(m + 1) * lda);
-    W.h2 = dalloc<double2>((size_t)(m + 1) * lda);
-    W.R = dalloc<double2>((size_t)m * (m + 1) * lda);
-    W.H = dalloc<double2>((size_t)m * (m + 1) * lda);
-    W.G = dalloc<double2>((size_t)(m + 1) * 2 * lda);
-    W.coefQ = dalloc<double2>((size_t)m * 2 * lda);
-    W.coefV = dalloc<double2>((size_t)2 * lda);
-    W.aux = dalloc<double2>((size_t)2 * lda);
-    W.sn = dalloc<double2>((size_t)m * lda);
-    W.gv = dalloc<double2>((size_t)(m + 1) * lda);
-    W.y = dalloc<double2>((size_t)m * lda);
-    W.cs = dalloc<double>((size_t)m * lda);
     W.nrm = dalloc<double>(lda);
     W.target = dalloc<double>(lda);
     W.done = dalloc<int32_t>(lda);
@@ -201,11 +192,41 @@ void ensure_workspace(pxStructure_t* s, int lda, int m)
     // the omegaFQ narrow FP64 T-apply takes its near field from a stored list
     HC(px::ensure_near_f64(s->g, s->st));
     W.lda_cap = lda;
+    W.m_cap = 0;
+    W.nup = nup;
+    px::fill_zero(W.X32, sizeof(float) * 2 * vec, s->st);
+}
+
+// The Krylov basis and the per-column Arnoldi state of restart length m, for
+// the vectors' lda, allocated the first time a restart cycle needs them (a
+// solve that the shared-Krylov phase finishes never does).
+void ensure_basis(pxStructure_t* s, int m)
+{
+    Workspace& W = s->ws;
+    if (W.m_cap >= m) return;
+    const int64_t nup = s->g.nup;
+    const int lda = W.lda_cap;
+    const size_t vec = (size_t)nup * lda;
+    const int nchunk = px::arnoldi_chunks(nup);
+    void* old[] = {W.V, W.partial, W.h1, W.h2, W.R, W.H, W.G, W.coefQ, W.coefV, W.aux, W.sn, W.gv, W.y, W.cs};
+    for (void* p : old) dfree(p);
+    W.V = dalloc<double2>((size_t)(m + 1) * vec);
+    W.partial = dalloc<double2>(std::max((size_t)nchunk * (m + 1), px::dot_partial_slabs(nup, m + 1)) * 2 * lda);
+    W.h1 = dalloc<double2>((size_t)(m + 1) * lda);
+    W.h2 = dalloc<double2>((size_t)(m + 1) * lda);
+    W.R = dalloc<double2>((size_t)m * (m + 1) * lda);
+    W.H = dalloc<double2>((size_t)m * (m + 1) * lda);
+    W.G = dalloc<double2>((size_t)(m + 1) * 2 * lda);
+    W.coefQ = dalloc<double2>((size_t)m * 2 * lda);
+    W.coefV = dalloc<double2>((size_t)2 * lda);
+    W.aux = dalloc<double2>((size_t)2 * lda);
+    W.sn = dalloc<double2>((size_t)m * lda);
+    W.gv = dalloc<double2>((size_t)(m + 1) * lda);
+    W.y = dalloc<double2>((size_t)m * lda);
+    W.cs = dalloc<double>((size_t)m * lda);
     W.m_cap = m;
     s->sync.ensure(m + 1);
-    W.nup = nup;
     px::fill_zero(W.V, sizeof(double2) * (size_t)(m + 1) * vec, s->st);
-    px::fill_zero(W.X32, sizeof(float) * 2 * vec, s->st);
 }
 
 
@@ -482,6 +503,7 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
             upload_shifts(s, act, lda);
         }
         // ---- one restart cycle ----
+        ensure_basis(s, m_max);
         {
             std::vector<double> tgt(lda, 0.0);
             std::vector<double2> g0(lda, make_double2(0, 0));
@@ -686,6 +708,25 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     s->sync.ensure(kcap + 1);
     int32_t* stop = s->sync.flag();
     s->sync.reset(st);
+    // the shifted Givens QRs (a few waves) run on a second stream of the same
+    // priority, beside the next steps' T-applies; each batch waits for the step
+    // that finished its columns, and the batches keep their order on that stream
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        ~Side()
+        {
+            if (e) (void)hipEventDestroy(e);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } side;
+    HC(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+    HC(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
+    auto givens_side = [&](int k0, int kn) {
+        HC(hipEventRecord(side.e, st));
+        HC(hipStreamWaitEvent(side.s, side.e, 0));
+        px::ms_givens(H, kcap, npol, P, k0, kn, z, cs, sn, g, target, done, resid, ndone, stop, side.s);
+    };
     StepTimer tm(o.timings != 0);
     tm.ensure(kcap);
     int launched = 0, gnext = 0;
@@ -701,7 +742,7 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
         px::ms_step(R, V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup, false, st, stop);
         // the shifted Givens QRs take GB finished Hessenberg columns per launch
         if (k - gnext >= GB) {
-            px::ms_givens(H, kcap, npol, P, gnext, GB, z, cs, sn, g, target, done, resid, ndone, stop, st);
+            givens_side(gnext, GB);
             gnext += GB;
         }
         tm.mark(k, 3, st);
@@ -712,9 +753,11 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     px::ms_step(R, V, vstride, launched, u, u, part, part2, G, H, kcap, coefv, coefu, scal, nup, true, st, stop);
     while (gnext < launched) {
         const int kn = std::min(GB, launched - gnext);
-        px::ms_givens(H, kcap, npol, P, gnext, kn, z, cs, sn, g, target, done, resid, ndone, stop, st);
+        givens_side(gnext, kn);
         gnext += kn;
     }
+    HC(hipEventRecord(side.e, side.s));
+    HC(hipStreamWaitEvent(st, side.e, 0));
     px::ms_rfactor(H, kcap, npol, P, launched, z, cs, sn, done, rst, st);
     px::ms_backsub(rst, P, launched, done, g, ycoef, st);
     px::ms_xcombine(R, V, vstride, launched, ycoef, P, s->x, s->ldg, nup, st);
@@ -732,7 +775,10 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     }
     // the device ran one step past the last column it needed (that column's correction)
     executed = std::min(launched, executed + 1);
-    tm.collect(executed, s->ms[2], s->ms[3], s->ms[4]);
+    double t_ap = 0.0;
+    tm.collect(executed, t_ap, s->ms[3], s->ms[4]);
+    s->ms[2] += t_ap;
+    s->tms[method == TA_STORED ? 3 : 2] += t_ap;
     const double nu = (double)s->g.nu;
     s->tstats[method == TA_STORED ? 3 : 2] += executed;
     s->counts[3] += executed;
@@ -771,7 +817,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     for (double& v : s->tflop) v = 0.0;
     const int ncol = s->ncol;
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
-    ensure_workspace(s, pad_cols(blk, true), std::max(o.restart_m, o.max_restart_m));
+    ensure_vectors(s, pad_cols(blk, true));
     prepare_solve(s);
     if (shifted_applies(s, o)) shifted_phase(s, o);
     for (int c0 = 0; c0 < ncol; c0 += blk) {
@@ -803,6 +849,100 @@ pxStatus guarded(F&& f)
         return fail(PX_E_DEVICE, "unexpected exception");
     }
 }
+
+// ---- concurrent single-structure solves (batch and server) -----------------
+// One-material omegaFQ structures are solved whole, shared-Krylov phase first,
+// by a small pool of host threads, each driving its own HIP stream of the
+// default priority, so that the solves of several structures (small ones
+// leave most of the GPU idle) and the stacked engine's cycles overlap on the
+// device.  A structure is moved to its worker's stream for the solve and
+// handed back on its own stream.
+class SolvePool {
+  public:
+    SolvePool(int nworkers, const pxSolveOptions& o) : o_(o)
+    {
+        HC(hipGetDevice(&dev_));
+        for (int w = 0; w < nworkers; ++w) threads_.emplace_back([this] { work(); });
+    }
+    ~SolvePool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        for (auto& t : threads_) t.join();
+    }
+    void submit(pxStructure_t* s)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            jobs_.push_back(s);
+            ++pending_;
+        }
+        cv_.notify_one();
+    }
+    // finished solves (structure, status); with wait, blocks until at least one
+    // is there or nothing is pending
+    std::vector<std::pair<pxStructure_t*, pxStatus>> collect(bool wait)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        if (wait) done_cv_.wait(lk, [this] { return !done_.empty() || pending_ == 0; });
+        std::vector<std::pair<pxStructure_t*, pxStatus>> out(done_.begin(), done_.end());
+        done_.clear();
+        return out;
+    }
+    int pending()
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return pending_;
+    }
+
+  private:
+    void work()
+    {
+        (void)hipSetDevice(dev_);
+        hipStream_t ws = nullptr;
+        const bool have = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess;
+        while (true) {
+            pxStructure_t* s = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [this] { return quit_ || !jobs_.empty(); });
+                if (jobs_.empty()) break;
+                s = jobs_.front();
+                jobs_.pop_front();
+            }
+            pxStatus st = PX_E_DEVICE;
+            if (have) {
+                hipStream_t own = s->st;
+                s->st = ws;
+                st = guarded([&]() -> pxStatus { return solve_impl(s, o_); });
+                (void)hipStreamSynchronize(ws);
+                s->st = own;
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                done_.emplace_back(s, st);
+                --pending_;
+            }
+            done_cv_.notify_all();
+        }
+        if (have) (void)hipStreamDestroy(ws);
+    }
+    pxSolveOptions o_;
+    int dev_ = 0;
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<pxStructure_t*> jobs_;
+    std::vector<std::pair<pxStructure_t*, pxStatus>> done_;
+    int pending_ = 0;
+    bool quit_ = false;
+};
+
+constexpr int kPoolWorkers = 4;   // GPU_MAX_HW_QUEUES is 4 by default
+
 
 }  // namespace
 
@@ -1022,27 +1162,55 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
         const int Bc = o.block_cols > 0 ? o.block_cols : 64;
         const int m_max = std::max(o.restart_m, o.max_restart_m);
         hipStream_t st = ss[0]->st;
+        // one-material omegaFQ structures: whole solves on the worker pool,
+        // beside the stacked engine that takes the others
+        std::vector<pxStructure_t*> pooled, stacked;
+        for (int32_t k = 0; k < n; ++k) (shifted_applies(ss[k], o) ? pooled : stacked).push_back(ss[k]);
+        std::unique_ptr<SolvePool> pool;
+        if (!pooled.empty()) {
+            HC(hipStreamSynchronize(st));
+            pool.reset(new SolvePool(std::min<int>(kPoolWorkers, (int)pooled.size()), o));
+            for (pxStructure_t* p : pooled) pool->submit(p);
+        }
+        pxStatus worst = PX_OK;
+        auto finish_pool = [&]() {
+            if (!pool) return;
+            while (pool->pending() > 0)
+                for (auto& r : pool->collect(true))
+                    if (r.second != PX_OK && worst == PX_OK) worst = r.second;
+            for (auto& r : pool->collect(false))
+                if (r.second != PX_OK && worst == PX_OK) worst = r.second;
+            pool.reset();
+        };
+        if (stacked.empty()) {
+            finish_pool();
+            if (worst != PX_OK) return fail(worst, "some columns did not reach rel_tol");
+            return PX_OK;
+        }
         int64_t rows = 0;
         int nseg = 0;
-        for (int32_t k = 0; k < n; ++k) {
-            nseg += (ss[k]->ncol + Bc - 1) / Bc;
-            rows += (int64_t)((ss[k]->ncol + Bc - 1) / Bc) * ss[k]->g.nup;
+        for (pxStructure_t* p : stacked) {
+            nseg += (p->ncol + Bc - 1) / Bc;
+            rows += (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup;
         }
         size_t free_b = 0, total_b = 0;
         HC(hipMemGetInfo(&free_b, &total_b));
         const int64_t fit = (int64_t)(0.8 * (double)free_b / (double)Engine::bytes_per_row(Bc, m_max));
         const int64_t cap = std::min(rows, fit);
         int64_t biggest = 0;
-        for (int32_t k = 0; k < n; ++k)
-            biggest = std::max<int64_t>(biggest, (int64_t)((ss[k]->ncol + Bc - 1) / Bc) * ss[k]->g.nup);
-        if (cap < biggest) return fail(PX_E_OOM, "pxSolveBatch: the largest structure does not fit in device memory");
+        for (pxStructure_t* p : stacked)
+            biggest = std::max<int64_t>(biggest, (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup);
+        if (cap < biggest) {
+            finish_pool();
+            return fail(PX_E_OOM, "pxSolveBatch: the largest structure does not fit in device memory");
+        }
         Engine eng(st, Bc, o, std::max(cap, biggest), nseg);
         std::deque<pxStructure_t*> queue;
-        for (int32_t k = 0; k < n; ++k) {
-            for (double& v : ss[k]->ms) v = 0.0;
-            for (int64_t& v : ss[k]->counts) v = 0;
-            prepare_solve(ss[k]);
-            queue.push_back(ss[k]);
+        for (pxStructure_t* p : stacked) {
+            for (double& v : p->ms) v = 0.0;
+            for (int64_t& v : p->counts) v = 0;
+            prepare_solve(p);
+            queue.push_back(p);
         }
         while (!queue.empty() || !eng.idle()) {
             while (!queue.empty() && eng.can_admit(queue.front())) {
@@ -1052,14 +1220,14 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
             eng.cycle();
         }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        pxStatus worst = PX_OK;
-        for (int32_t k = 0; k < n; ++k) {
-            ss[k]->ms[0] = ms;
-            ss[k]->ms[5] = ms;
-            ss[k]->counts[0] = eng.stats().tapply_f32;
-            ss[k]->counts[3] = eng.stats().tapply_f64 + eng.stats().residuals;
-            for (int c = 0; c < ss[k]->ncol; ++c)
-                if (!(ss[k]->relres[c] <= o.rel_tol)) worst = PX_E_NOTCONV;
+        finish_pool();
+        for (pxStructure_t* p : stacked) {
+            p->ms[0] = ms;
+            p->ms[5] = ms;
+            p->counts[0] = eng.stats().tapply_f32;
+            p->counts[3] = eng.stats().tapply_f64 + eng.stats().residuals;
+            for (int c = 0; c < p->ncol; ++c)
+                if (!(p->relres[c] <= o.rel_tol)) worst = PX_E_NOTCONV;
         }
         if (worst != PX_OK) return fail(worst, "some columns did not reach rel_tol");
         return PX_OK;
@@ -1126,7 +1294,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
     return guarded([&]() -> pxStatus {
         const bool mixed = precision == PX_MIXED;
         const int lda = pad_cols(ncol, !mixed);
-        ensure_workspace(s, std::max(lda, s->ws.lda_cap), std::max(1, s->ws.m_cap));
+        ensure_vectors(s, std::max(lda, s->ws.lda_cap));
         Workspace& W = s->ws;
         const int64_t nu = s->g.nu, nup = s->g.nup;
         double2* din = dalloc<double2>((size_t)ncol * nu);
@@ -1221,6 +1389,7 @@ void pxDestroyStructure(pxStructure s)
 
 struct pxServer_t {
     pxs::Engine* eng = nullptr;
+    std::unique_ptr<SolvePool> pool;   // one-material omegaFQ requests, solved whole
     std::deque<pxStructure_t*> queue;
     std::deque<pxStructure_t*> done;
     hipStream_t st = nullptr;
@@ -1267,6 +1436,13 @@ pxStatus pxServerSubmit(pxServer sv, pxStructure s)
     if (sv->eng->rows_for(s) > sv->eng->rows_capacity())
         return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");
     return guarded([&]() -> pxStatus {
+        if (shifted_applies(s, sv->o)) {
+            // solved whole on a worker stream, beside the engine's cycles
+            if (!sv->pool) sv->pool.reset(new SolvePool(kPoolWorkers, sv->o));
+            HC(hipStreamSynchronize(s->st));
+            sv->pool->submit(s);
+            return PX_OK;
+        }
         for (double& v : s->ms) v = 0.0;
         for (int64_t& v : s->counts) v = 0;
         prepare_solve(s);
@@ -1284,8 +1460,14 @@ pxStatus pxServerStep(pxServer sv, pxStructure* finished, int32_t max_finished, 
             sv->eng->admit(sv->queue.front());
             sv->queue.pop_front();
         }
-        if (!sv->eng->idle())
+        const bool cycled = !sv->eng->idle();
+        if (cycled)
             for (pxStructure_t* s : sv->eng->cycle()) sv->done.push_back(s);
+        if (sv->pool) {
+            // without an engine cycle to run, wait for a worker rather than spin
+            const bool wait = !cycled && sv->done.empty() && sv->pool->pending() > 0;
+            for (auto& r : sv->pool->collect(wait)) sv->done.push_back(r.first);
+        }
         int32_t k = 0;
         while (k < max_finished && !sv->done.empty()) {
             finished[k++] = sv->done.front();
@@ -1302,7 +1484,7 @@ pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_
     g_err.clear();
     if (!sv) return fail(PX_E_INVALID, "null server");
     if (n_queued) *n_queued = (int32_t)sv->queue.size();
-    if (n_active) *n_active = sv->eng->n_structures();
+    if (n_active) *n_active = sv->eng->n_structures() + (sv->pool ? sv->pool->pending() : 0);
     if (rows_in_use) *rows_in_use = sv->eng->rows_in_use();
     if (rows_capacity) *rows_capacity = sv->eng->rows_capacity();
     return PX_OK;
@@ -1311,6 +1493,7 @@ pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_
 void pxServerDestroy(pxServer sv)
 {
     if (!sv) return;
+    sv->pool.reset();   // joins the workers (their solves finish first)
     if (sv->st) (void)hipStreamSynchronize(sv->st);
     else (void)hipDeviceSynchronize();
     delete sv->eng;

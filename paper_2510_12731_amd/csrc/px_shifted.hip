@@ -114,6 +114,9 @@ __global__ __launch_bounds__(256) void k_ms_spmv(const int32_t* __restrict__ rp,
 
 // part[(j * nslab + slab)][c] = sum over the slab's rows of x_j[row][c] u[row][c]
 // and part[..][R + c] the same with wt, where x_j = V_j (j < k) or u (j = k).
+// A block takes MJ consecutive vectors, so u and wt are read once for MJ of them.
+constexpr int MJ = 2;
+
 template <int R>
 __global__ __launch_bounds__(256) void k_ms_dots(const double* __restrict__ V, int64_t vstride, int k,
                                                  const double* __restrict__ u, const double* __restrict__ wt,
@@ -122,26 +125,42 @@ __global__ __launch_bounds__(256) void k_ms_dots(const double* __restrict__ V, i
 {
     if (stop && *stop) return;
     constexpr int W = 2 * R;
-    __shared__ double lds[4][W];
-    const int j = blockIdx.y, slab = blockIdx.x, nslab = gridDim.x;
+    __shared__ double lds[4][MJ * W];
+    const int j0 = blockIdx.y * MJ, slab = blockIdx.x, nslab = gridDim.x;
+    const int nj = k + 1 - j0 < MJ ? k + 1 - j0 : MJ;
     const int64_t r0 = (int64_t)slab * rows_per_slab;
     const int64_t r1 = r0 + rows_per_slab < nup ? r0 + rows_per_slab : nup;
-    const double* xj = j < k ? V + (size_t)j * vstride : u;
-    double acc[W];
+    double acc[MJ * W];
 #pragma unroll
-    for (int c = 0; c < W; ++c) acc[c] = 0.0;
+    for (int c = 0; c < MJ * W; ++c) acc[c] = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+        double uu[R], ww[R];
 #pragma unroll
         for (int c = 0; c < R; ++c) {
-            const double x = xj[(size_t)r * R + c];
-            acc[c] = fma(x, u[(size_t)r * R + c], acc[c]);
-            acc[R + c] = fma(x, wt[(size_t)r * R + c], acc[R + c]);
+            uu[c] = u[(size_t)r * R + c];
+            ww[c] = wt[(size_t)r * R + c];
+        }
+#pragma unroll
+        for (int jj = 0; jj < MJ; ++jj) {
+            if (jj < nj) {
+                const int j = j0 + jj;
+                const double* xj = V + (size_t)(j < k ? j : 0) * vstride + (size_t)r * R;
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const double x = j < k ? xj[c] : uu[c];
+                    acc[jj * W + c] = fma(x, uu[c], acc[jj * W + c]);
+                    acc[jj * W + R + c] = fma(x, ww[c], acc[jj * W + R + c]);
+                }
+            }
         }
     }
-    block_sum<W>(acc, lds);
+    block_sum<MJ * W>(acc, lds);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int c = 0; c < W; ++c) part[((size_t)j * nslab + slab) * W + c] = acc[c];
+        for (int jj = 0; jj < MJ; ++jj)
+            if (jj < nj)
+#pragma unroll
+                for (int c = 0; c < W; ++c) part[((size_t)(j0 + jj) * nslab + slab) * W + c] = acc[jj * W + c];
 }
 
 // G[j][c] = sum over slabs of part[j][slab][c] (fixed order), W values per j.
@@ -550,10 +569,13 @@ void with_r(int R, A... a)
     else F<3>::run(a...);
 }
 
-int ms_slabs(int64_t nup, int nvec)
+// row slabs of the dot pass over ngroups vector groups: about 2048 blocks
+// (two vectors per block measured fastest: 47 us against 54 us for one and
+// 73 us for four at step 800 of the 20k-atom sphere)
+int ms_slabs(int64_t nup, int ngroups)
 {
     int64_t maxs = (nup + 255) / 256;
-    int64_t want = (2048 + nvec - 1) / nvec;
+    int64_t want = (2048 + ngroups - 1) / ngroups;
     if (want < 1) want = 1;
     if (want > maxs) want = maxs;
     return (int)want;
@@ -601,10 +623,11 @@ struct StepL {
     {
         constexpr int W = 2 * R;
         const int nvec = k + 1;
-        const int nslab = ms_slabs(nup, nvec);
+        const int ngroups = (nvec + MJ - 1) / MJ;
+        const int nslab = ms_slabs(nup, ngroups);
         const int64_t rps = (nup + nslab - 1) / nslab;
-        hipLaunchKernelGGL(k_ms_dots<R>, dim3((unsigned)nslab, (unsigned)nvec), dim3(256), 0, st, V, vstride, k, u,
-                           wt, part, nup, rps, stop);
+        hipLaunchKernelGGL(k_ms_dots<R>, dim3((unsigned)nslab, (unsigned)ngroups), dim3(256), 0, st, V, vstride, k,
+                           u, wt, part, nup, rps, stop);
         hipLaunchKernelGGL(k_ms_reduce<W>, dim3((unsigned)((nvec * W + 255) / 256)), dim3(256), 0, st, part, nslab,
                            nvec, G, stop);
         hipLaunchKernelGGL(k_ms_coef<R>, dim3((unsigned)((k + 1 + 3) / 4), (unsigned)R), dim3(256), 0, st, G, H,
@@ -653,9 +676,9 @@ void ms_step(int R, double* V, int64_t vstride, int k, double* u, const double* 
 
 size_t ms_part_doubles(int R, int64_t nup, int kcap)
 {
-    // ms_slabs(nup, nv) * nv <= 2048 + nv for every nv <= kcap + 1
+    // slabs x (vectors rounded up to MJ) <= (2048 + groups) x MJ for every length up to kcap + 1
     (void)nup;
-    return (size_t)(2048 + kcap + 1) * 2 * R;
+    return (size_t)(2048 + (kcap + 1 + MJ - 1) / MJ) * MJ * 2 * R;
 }
 
 size_t ms_part2_doubles(int R, int64_t nup, int kcap)

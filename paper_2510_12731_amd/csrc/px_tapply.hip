@@ -921,6 +921,12 @@ __global__ __launch_bounds__(256) void k_sum_splits_near(const double* __restric
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    // the split partial sums, spread over the lanes
+    for (int k = lane; k < nsplit; k += 64) {
+        const double* pk = part + (size_t)k * np * NC + (size_t)i * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += pk[c];
+    }
     if (i < n) {
         for (int32_t e = rp[i] + lane; e < rp[i + 1]; e += 64) {
             const double v = val[e];
@@ -932,15 +938,9 @@ __global__ __launch_bounds__(256) void k_sum_splits_near(const double* __restric
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-    if (lane < NC) {
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * np * NC + (size_t)i * NC + lane];
-        double a = acc[0];
+    if (lane == 0)
 #pragma unroll
-        for (int c = 1; c < NC; ++c)
-            if (lane == c) a = acc[c];
-        Y[(size_t)i * NC + lane] = s + a;
-    }
+        for (int c = 0; c < NC; ++c) Y[(size_t)i * NC + c] = acc[c];
 }
 
 // Near-field list of the omegaFQ T in FP64 over the real atoms: for every
@@ -1133,15 +1133,13 @@ DipoleConstD dipole_const_d(const Geometry& g)
 // round of long workgroups (measured on the 20k-atom sphere).
 int narrow_splits(const Geometry& g)
 {
-    static int ncu = 0;
-    if (ncu == 0) {
+    static const int ncu = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            ncu = v;
-        else
-            ncu = 256;
-    }
+            return v;
+        return 256;
+    }();
     int rb = (int)(g.np / 256);
     int nchunk = (int)(g.np / NW_CHUNK);
     int want = (16 * ncu + rb - 1) / rb;

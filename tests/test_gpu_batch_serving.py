@@ -55,11 +55,14 @@ def make(c):
     return s
 
 
-def test_batch_matches_solo_and_oracle():
+@pytest.mark.parametrize("shifted", [0, 1])
+def test_batch_matches_solo_and_oracle(shifted):
+    """shifted = 0: all three in the stacked block; 1: the omegaFQ two solved
+    whole on worker streams beside the block that takes the rod."""
     cs = cases()
-    say("[batch] 3 structures (graphene 600 / Ag sphere 400 / Au rod 240 dipole)")
+    say(f"[batch] 3 structures (graphene 600 / Ag sphere 400 / Au rod 240 dipole), shifted={shifted}")
     batch = [make(c) for c in cs]
-    st = px.solve_batch(batch, precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64)
+    st = px.solve_batch(batch, precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64, shifted=shifted)
     assert st == px.PX_OK
     for c, s in zip(cs, batch):
         _, sig_b = s.spectrum()
@@ -105,7 +108,7 @@ def test_batch_graph_replays_match_eager_launches():
     for gs in (0, 3, 8):
         batch = [make(c) for c in cs]
         st = px.solve_batch(batch, precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64, restart_m=20,
-                            max_restart_m=40, graph_steps=gs)
+                            max_restart_m=40, graph_steps=gs, shifted=0)
         assert st == px.PX_OK
         sig = [s.spectrum()[1] for s in batch]
         cyc = max(int(s.stats()[1].max()) for s in batch)
@@ -120,12 +123,17 @@ def test_batch_graph_replays_match_eager_launches():
             s.close()
 
 
-def test_server_alone_vs_mix_and_admission():
+@pytest.mark.parametrize("shifted", [0, 1])
+def test_server_alone_vs_mix_and_admission(shifted):
+    """shifted = 0: every request joins the stacked block; 1: the omegaFQ
+    requests are solved whole on worker streams while the rod cycles in the
+    block."""
     cs = cases()
     # rows: graphene 2 x 768, sphere 512, rod 4 x 256; a budget of ~2600 rows
     # holds the first two together but not all three
     per_row = 64 * 16 * (200 + 1 + 7) + 64 * 32
-    sv = px.Server(2600 * per_row, px.default_stream(), precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64)
+    sv = px.Server(2600 * per_row, px.default_stream(), precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64,
+                   shifted=shifted)
     cap = sv.query()["rows_capacity"]
     say(f"[server] capacity {cap} rows")
     assert 2560 <= cap < 3072
@@ -152,7 +160,7 @@ def test_server_alone_vs_mix_and_admission():
         assert r.h.value in done
         _, sig_mix = r.spectrum()
         solo = make(c)
-        assert solo.solve(precision=px.PX_MIXED, rel_tol=1e-8) == px.PX_OK
+        assert solo.solve(precision=px.PX_MIXED, rel_tol=1e-8, shifted=shifted) == px.PX_OK
         e = rel_err(sig_mix, solo.spectrum()[1])
         say(f"   model {c['model']} N={len(c['xyz'])}: mix vs alone {e:.1e}")
         assert e <= 1e-6
