@@ -64,11 +64,12 @@ def one_step(px, case, precision, timings, max_block_cols=0, t_apply=None, shift
 
 
 # FP64 arithmetic per atom pair of the narrow omegaFQ T-apply besides the
-# products with the columns: the three coordinate differences (3), r^2 (one
-# multiply and two fused multiply-adds, 5), the reciprocal square root estimate
-# (1) and its third-order refinement to FP64 accuracy (two multiplies and
-# three fused multiply-adds, 8); each column adds one fused multiply-add (2).
-PAIR_FLOP = 17
+# products with the columns: r^2 = |p_i|^2 + |p_j|^2 - 2 p_i.p_j over centred
+# positions (one add and three fused multiply-adds, 7; the per-atom -2 p_i and
+# |p|^2 are computed once), the reciprocal square root estimate (1) and one
+# Newton step to FP64 accuracy (two multiplies and a fused multiply-add, 4);
+# each column adds one fused multiply-add (2).
+PAIR_FLOP = 12
 
 
 def tapply_roofline(runs, n, npol, traffic, traffic_note):
@@ -84,7 +85,7 @@ def tapply_roofline(runs, n, npol, traffic, traffic_note):
     if dom == "f64_on_the_fly":
         fl = float(n) * n * (PAIR_FLOP + 2 * npol) * nl[dom]
         peak, bound, kname = FP64_VECTOR_PEAK_TFLOPS, "alu", \
-            "k_tapply_f64_narrow_q (point part) + k_sum_splits_near (near-field correction), FP64"
+            "k_tapply_f64_narrow_q (point part and stored near-field correction) + k_sum_splits (split sum), FP64"
         flop_note = (f"{PAIR_FLOP} + 2 x {npol} FP64 FLOP per atom pair (N^2 pairs; the near-field list adds "
                      f"< 1 %), peak = FP64 vector")
     else:

@@ -52,13 +52,19 @@ struct Geometry {
     // sum, same-type and other-type neighbour counts)
     uint8_t* type = nullptr;
     double4* hrow = nullptr;
-    // omegaFQ near field in FP64 (built by ensure_near_f64): CSR over the real
-    // atoms of T - T_point for the pairs closer than the FP64 far threshold,
-    // -erfc(r/R)/r off the diagonal and the self term on it
-    int32_t* near_ptr = nullptr;
+    // omegaFQ near field in FP64 (built by ensure_near_f64): T - T_point over
+    // the real atoms for the pairs closer than the FP64 far threshold,
+    // -erfc(r/R)/r off the diagonal and the self term on it, in ELL layout per
+    // block of 256 rows: near_off[b] is block b's first entry ([np/256 + 1]),
+    // slot k of row i at near_off[i/256] + 256 k + i % 256, unused slots zero
+    int64_t* near_off = nullptr;
     int32_t* near_col = nullptr;
     double* near_val = nullptr;
-    int64_t near_nnz = 0;
+    int64_t near_nnz = 0;   // entries including the unused slots
+    // centre of the real atoms' bounding box (bohr), and for the point-charge
+    // kernel every atom's position relative to it with its squared norm in w
+    double cx = 0, cy = 0, cz = 0;
+    double4* xyzc = nullptr;   // [np], built with the near-field list
 };
 
 // Exclusive scan of cnt[0..n) into row_ptr[0..n] (one workgroup).

@@ -135,89 +135,94 @@ __device__ __forceinline__ float gap2(float4 alo, float4 ahi, float4 blo, float4
     return dx * dx + dy * dy + dz * dz;
 }
 
-// Neighbour search over the real atoms, one thread per row atom.  Pass 0
-// counts (row length incl. the diagonal) and flags coincident atoms; pass 1
-// fills columns in increasing order with Kbar_ii = -sum_k K_ik in place.
-template <int PASS>
-__global__ __launch_bounds__(256) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
-                                                   const float4* __restrict__ ghi, int64_t n, int64_t np,
-                                                   KappaSet ks, const uint8_t* __restrict__ type,
-                                                   int32_t* __restrict__ cnt,
-                                                   const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
-                                                   double* __restrict__ val, int* __restrict__ bad)
+// Calls f(gq) for every source group gq < ngroups whose bounding box lies
+// within sqrt(lim2) of the box (blo, bhi), in increasing order, wave-uniform:
+// the lanes test 64 groups at a time and the wave walks the set bits.
+template <typename F>
+__device__ __forceinline__ void for_groups_near(float4 blo, float4 bhi, const float4* __restrict__ glo,
+                                                const float4* __restrict__ ghi, int64_t ngroups, float lim2, F&& f)
 {
-    __shared__ double4 sp[GROUP];
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-    const int64_t g0 = ((int64_t)blockIdx.x * 256) / GROUP;
-    // box of this block's 256 rows (8 groups)
-    float4 blo = glo[g0], bhi = ghi[g0];
-    for (int q = 1; q < 256 / GROUP; ++q) {
-        float4 a = glo[g0 + q], b = ghi[g0 + q];
-        blo = make_float4(fminf(blo.x, a.x), fminf(blo.y, a.y), fminf(blo.z, a.z), 0.f);
-        bhi = make_float4(fmaxf(bhi.x, b.x), fmaxf(bhi.y, b.y), fmaxf(bhi.z, b.z), 0.f);
-    }
-    const double4 pi = x64[i];
-    const float lim = (float)(ks.rc_max * 1.0001 + 1e-3);
-    const int ti = (type && i < n) ? type[i] : 0;
-    const int64_t ngroups = (n + GROUP - 1) / GROUP;
-    int count = 0;
-    double ksum = 0.0;
-    int64_t out = 0;
-    bool diag_done = false;
-    if (PASS == 1 && i < n) {
-        out = row_ptr[i];
-        // Kbar_ii needs the full row sum first
-        for (int64_t gq = 0; gq < ngroups; ++gq) {
-            if (gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;
-            for (int k = 0; k < GROUP; ++k) {
-                int64_t j = gq * GROUP + k;
-                if (j >= n || j == i) continue;
-                double4 pj = x64[j];
-                double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                double r = sqrt(dx * dx + dy * dy + dz * dz);
-                const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
-                if (r <= kc.rc) ksum += kappa_val(r, kc);
-            }
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = 0; base < ngroups; base += 64) {
+        const int64_t gq = base + lane;
+        const bool hit = gq < ngroups && gap2(blo, bhi, glo[gq], ghi[gq]) <= lim2;
+        uint64_t mask = __ballot(hit);
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            f(base + b);
         }
     }
-    for (int64_t gq = 0; gq < ngroups; ++gq) {
-        if (gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;   // uniform over the block
-        __syncthreads();
-        if (tid < GROUP) sp[tid] = x64[gq * GROUP + tid];
-        __syncthreads();
-        if (i >= n) continue;
+}
+
+// Bounding box of the 64 rows (two groups) of a one-wave workgroup.
+__device__ __forceinline__ void wave_box(const float4* __restrict__ glo, const float4* __restrict__ ghi,
+                                         int64_t g0, float4& blo, float4& bhi)
+{
+    const float4 a0 = glo[g0], a1 = glo[g0 + 1], b0 = ghi[g0], b1 = ghi[g0 + 1];
+    blo = make_float4(fminf(a0.x, a1.x), fminf(a0.y, a1.y), fminf(a0.z, a1.z), 0.f);
+    bhi = make_float4(fmaxf(b0.x, b1.x), fmaxf(b0.y, b1.y), fmaxf(b0.z, b1.z), 0.f);
+}
+
+// Neighbour search over the real atoms, one thread per row atom, 64 rows per
+// (one-wave) workgroup; source atoms are read wave-uniform.  Pass 0 counts
+// (row length incl. the diagonal) and flags coincident atoms; pass 1 fills
+// columns in increasing order, the diagonal slot kept where the columns pass
+// i and filled with Kbar_ii = -sum_k K_ik once the row is summed.
+template <int PASS>
+__global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
+                                                  const float4* __restrict__ ghi, int64_t n, int64_t np,
+                                                  KappaSet ks, const uint8_t* __restrict__ type,
+                                                  int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                  double* __restrict__ val, int* __restrict__ bad)
+{
+    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    float4 blo, bhi;
+    wave_box(glo, ghi, (int64_t)blockIdx.x * (64 / GROUP), blo, bhi);
+    const double4 pi = x64[i];
+    const bool row = i < n;
+    const float lim = (float)(ks.rc_max * 1.0001 + 1e-3);
+    const double lim2 = (double)lim * (double)lim;   // r^2 prefilter, above every pair type's cutoff
+    const int ti = (type && row) ? type[i] : 0;
+    int count = 0;
+    double ksum = 0.0;
+    int64_t out = (PASS == 1 && row) ? row_ptr[i] : 0;
+    int64_t diag = -1;
+    for_groups_near(blo, bhi, glo, ghi, (n + GROUP - 1) / GROUP, lim * lim, [&](int64_t gq) {
         for (int k = 0; k < GROUP; ++k) {
-            int64_t j = gq * GROUP + k;
+            const int64_t j = gq * GROUP + k;
             if (j >= n) break;
-            if (PASS == 1 && !diag_done && j > i) {
-                col[out] = (int32_t)i;
-                val[out] = -ksum;
-                ++out;
-                diag_done = true;
-            }
+            const double4 pj = x64[j];
+            if (!row) continue;
+            if (PASS == 1 && diag < 0 && j > i) diag = out++;
             if (j == i) continue;
-            double4 pj = sp[k];
-            double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 > lim2) continue;
+            const double r = sqrt(r2);
             const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
             if (PASS == 0 && r < kc.min_r) *bad = 1;
             if (r <= kc.rc) {
                 if (PASS == 0) {
                     ++count;
                 } else {
+                    const double v = kappa_val(r, kc);
                     col[out] = (int32_t)j;
-                    val[out] = kappa_val(r, kc);
+                    val[out] = v;
+                    ksum += v;
                     ++out;
                 }
             }
         }
-    }
-    if (i < n) {
-        if (PASS == 0) cnt[i] = count + 1;
-        if (PASS == 1 && !diag_done) {
-            col[out] = (int32_t)i;
-            val[out] = -ksum;
+    });
+    if (row) {
+        if (PASS == 0) {
+            cnt[i] = count + 1;
+        } else {
+            if (diag < 0) diag = out;
+            col[diag] = (int32_t)i;
+            val[diag] = -ksum;
         }
     }
 }
@@ -1405,6 +1410,9 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
         }
     double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
     double sc = ext > 0 ? 1023.0 / ext : 1.0;
+    g.cx = n > 0 ? 0.5 * (lo[0] + hi[0]) : 0.0;
+    g.cy = n > 0 ? 0.5 * (lo[1] + hi[1]) : 0.0;
+    g.cz = n > 0 ? 0.5 * (lo[2] + hi[2]) : 0.0;
     int64_t npow = 1;
     while (npow < n) npow <<= 1;
     double* d_xyz = nullptr;
@@ -1472,7 +1480,7 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
             hipLaunchKernelGGL(k_gather_types, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d_types, d_perm, n,
                                np, g.type);
         }
-        hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
+        hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, n,
                            np, ks, g.type, d_cnt, nullptr, nullptr, nullptr, d_bad);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cnt, n, g.row_ptr);
         int32_t nnz = 0;
@@ -1482,7 +1490,7 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
         g.nnz = nnz;
         PXCHK(hipMalloc(&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
         PXCHK(hipMalloc(&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
-        hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, n,
+        hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, n,
                            np, ks, g.type, nullptr, g.row_ptr, g.col, g.val, d_bad);
         if (g.type) {
             PXCHK(hipMalloc(&g.hrow, sizeof(double4) * n));

@@ -232,7 +232,7 @@ struct pxStructure_t {
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_ptr, g.near_col, g.near_val, d_perm, d_col_pol, d_omega, x, b, t32, t64};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, d_perm, d_col_pol, d_omega, x, b, t32, t64};
         for (void* p : ps) pxs::dfree(p);
         pxs::release_blas(blas);
     }

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
 namespace px {
 namespace {
@@ -822,70 +823,80 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow(const double4* __rest
 // third-order step y (1 + e/2 + 3e^2/8), e = 1 - x y^2, which takes the
 // estimate's relative error eps to O(eps^3), below FP64 rounding; the library
 // call adds only the special-input handling, which a pair distance never needs.
-__device__ __forceinline__ double rsqrt_pos(double x)
+// Twice 1/sqrt(q) for q > 0: the hardware estimate y0 (about 23 correct bits)
+// and one Newton step, y0 (3 - q y0^2), whose factor 1/2 the caller applies
+// once to its sums.  Relative error below 1e-13 (the Newton step squares the
+// estimate's error, times 3/2), in three instructions instead of the five of
+// rsqrt_pos.
+__device__ __forceinline__ double rsqrt_pos_x2(double q)
 {
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-x * y, y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
+    const double y = __builtin_amdgcn_rsq(q);
+    return y * fma(-q, y * y, 3.0);
 }
 
-// The omegaFQ narrow blocks, T = T_point + C: this kernel applies the point
-// part 1/r to every pair (the self pair excluded), branch-free; the stored
-// near-field correction C (k_near_rows) is added by k_sum_splits_near.  The
-// source atoms are read by wave-uniform loads (through the scalar cache)
-// instead of LDS: every lane of a wave needs the same source atom at each
-// step, so one scalar load serves the whole wave and the LDS pipe, which the
-// CU's waves share, leaves the inner loop.
+// The omegaFQ narrow blocks, T = T_point + C.  Split y of a row block applies
+// the point part 1/r over the source chunks y, y + nsplit, ... (the self pair
+// excluded) and the slots y, y + nsplit, ... of the row block's stored
+// near-field correction C (ELL layout, k_near_rows); k_sum_splits adds the
+// splits.  The source atoms are read by wave-uniform loads (through the
+// scalar cache) instead of LDS: every lane of a wave needs the same source
+// atom at each step, so one scalar load serves the whole wave and the LDS
+// pipe, which the CU's waves share, leaves the inner loop.  Positions are
+// relative to the structure's centre with |p|^2 in w, so that r^2 = |p_i|^2 +
+// |p_j|^2 - 2 p_i.p_j takes four instructions; its rounding error, a few
+// units of FP64 rounding times the squared radius of the structure, is below
+// 1e-12 of r^2 for the nearest pairs of a 100k-atom sphere.  Only the source
+// groups that hold one of the wave's own rows need the self pair masked.  The
+// correction list is read in the shadow of the ALU-bound pair loop.
 template <int NC>
-__global__ __launch_bounds__(256) void k_tapply_f64_narrow_q(const double4* __restrict__ xyz,
-                                                             const float4* __restrict__ glo,
-                                                             const float4* __restrict__ ghi,
+__global__ __launch_bounds__(256) void k_tapply_f64_narrow_q(const double4* __restrict__ xyzc,
                                                              const double* __restrict__ X,
-                                                             double* __restrict__ part, int np, int chunks_per_split,
-                                                             double inv_rqq, double t_self, float r_far2,
+                                                             double* __restrict__ part, int np,
+                                                             const int64_t* __restrict__ ell_off,
+                                                             const int32_t* __restrict__ ell_col,
+                                                             const double* __restrict__ ell_val,
                                                              const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
     const int tid = threadIdx.x;
     const int i = blockIdx.x * 256 + tid;
-    const int wave_row0 = blockIdx.x * 256 + (tid & ~63);
-    const double4 pi = xyz[i];
-    const float4 g0lo = glo[wave_row0 >> 5], g1lo = glo[(wave_row0 >> 5) + 1];
-    const float4 g0hi = ghi[wave_row0 >> 5], g1hi = ghi[(wave_row0 >> 5) + 1];
-    const float4 rlo = make_float4(fminf(g0lo.x, g1lo.x), fminf(g0lo.y, g1lo.y), fminf(g0lo.z, g1lo.z), 0.f);
-    const float4 rhi = make_float4(fmaxf(g0hi.x, g1hi.x), fmaxf(g0hi.y, g1hi.y), fmaxf(g0hi.z, g1hi.z), 0.f);
+    const int wave_row0 = uniform(blockIdx.x * 256 + (tid & ~63));
+    const double4 pi = xyzc[i];
+    const double ax = -2.0 * pi.x, ay = -2.0 * pi.y, az = -2.0 * pi.z;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     const int nchunk = np / NW_CHUNK;
-    // split y takes chunks y, y + nsplit, ... (near-field work spread over the splits)
-    (void)chunks_per_split;
     for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y)
     for (int gq = ch * (NW_CHUNK / GROUP); gq < (ch + 1) * (NW_CHUNK / GROUP); ++gq) {
         const int j0 = uniform(gq * GROUP);
-        const int far = uniform(box_gap2(rlo, rhi, glo[gq], ghi[gq]) >= r_far2);
-        if (far) {
+        if (j0 + GROUP <= wave_row0 || j0 >= wave_row0 + 64) {
 #pragma unroll 4
             for (int jj = 0; jj < GROUP; ++jj) {
-                const double4 pj = xyz[j0 + jj];
-                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const double rinv = rsqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
+                const double4 pj = xyzc[j0 + jj];
+                const double t = rsqrt_pos_x2(fma(ax, pj.x, fma(ay, pj.y, fma(az, pj.z, pi.w))) + pj.w);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] = fma(rinv, X[(size_t)(j0 + jj) * NC + c], acc[c]);
+                for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[c]);
             }
         } else {
-            // the point-charge part only (the self pair excluded); the near
-            // field comes from the stored correction in k_sum_splits_near
 #pragma unroll 4
             for (int jj = 0; jj < GROUP; ++jj) {
-                const double4 pj = xyz[j0 + jj];
-                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const double rinv = rsqrt_pos(fma(dx, dx, fma(dy, dy, dz * dz)));
-                const double t = (i == j0 + jj) ? 0.0 : rinv;
+                const double4 pj = xyzc[j0 + jj];
+                const double r2 = fma(ax, pj.x, fma(ay, pj.y, fma(az, pj.z, pi.w))) + pj.w;
+                const double t = (i == j0 + jj) ? 0.0 : rsqrt_pos_x2(r2);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[c]);
             }
         }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] *= 0.5;
+    const int64_t e0 = ell_off[blockIdx.x], e1 = ell_off[blockIdx.x + 1];
+    for (int64_t e = e0 + (int64_t)blockIdx.y * 256 + tid; e < e1; e += (int64_t)gridDim.y * 256) {
+        const double v = ell_val[e];
+        const double* x = X + (size_t)ell_col[e] * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = fma(v, x[c], acc[c]);
     }
     double* out = part + (size_t)blockIdx.y * np * NC;
 #pragma unroll
@@ -903,102 +914,89 @@ __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict
     Y[t] = s;
 }
 
-// Y = sum of the split partial sums + C X over the near-field list, one wave
-// per row (lanes over the row's entries, fixed-order wave reduction).
-template <int NC>
-__global__ __launch_bounds__(256) void k_sum_splits_near(const double* __restrict__ part, int nsplit,
-                                                         double* __restrict__ Y, int64_t n, int64_t np,
-                                                         const int32_t* __restrict__ rp,
-                                                         const int32_t* __restrict__ col,
-                                                         const double* __restrict__ val,
-                                                         const double* __restrict__ X,
-                                                         const int32_t* __restrict__ stop)
-{
-    if (stop && *stop) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= np) return;
-    double acc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
-    // the split partial sums, spread over the lanes
-    for (int k = lane; k < nsplit; k += 64) {
-        const double* pk = part + (size_t)k * np * NC + (size_t)i * NC;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += pk[c];
-    }
-    if (i < n) {
-        for (int32_t e = rp[i] + lane; e < rp[i + 1]; e += 64) {
-            const double v = val[e];
-            const double* x = X + (size_t)col[e] * NC;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] = fma(v, x[c], acc[c]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-        for (int off = 32; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 64);
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) Y[(size_t)i * NC + c] = acc[c];
-}
-
 // Near-field list of the omegaFQ T in FP64 over the real atoms: for every
 // pair closer than r_far (erfc(x) < 2^-54 beyond), C_ij = -erfc(r/R_qq)/r,
-// and C_ii = sqrt(2/pi)/R_q (the self term, Eq. tqq); columns increasing.
-// Pass 0 counts, pass 1 fills.  One thread per row atom; the 256 rows of a
-// block skip source groups whose bounding box is farther than r_far.
+// and C_ii = sqrt(2/pi)/R_q (the self term, Eq. tqq).  Pass 0 counts each
+// row's entries; pass 1 fills the ELL layout: row block b (256 rows) holds
+// width_b = (off[b+1] - off[b]) / 256 slots, entry k of row i at off[b] +
+// k * 256 + (i - 256 b), columns increasing along the slots, unused slots left
+// as cleared (column 0, value 0).  One thread per row atom, 64 rows per
+// (one-wave) workgroup; the wave visits only the source groups whose bounding
+// box lies within r_far of its rows' box (64 groups tested at a time, one per
+// lane) and reads their atoms wave-uniform.
 template <int PASS>
-__global__ __launch_bounds__(256) void k_near_rows(const double4* __restrict__ xyz, const float4* __restrict__ glo,
-                                                   const float4* __restrict__ ghi, int64_t n, double r_far,
-                                                   double inv_rqq, double t_self, int32_t* __restrict__ cnt,
-                                                   const int32_t* __restrict__ rp, int32_t* __restrict__ col,
-                                                   double* __restrict__ val)
+__global__ __launch_bounds__(64) void k_near_rows(const double4* __restrict__ xyz, const float4* __restrict__ glo,
+                                                  const float4* __restrict__ ghi, int64_t n, double r_far,
+                                                  double inv_rqq, double t_self, int32_t* __restrict__ cnt,
+                                                  const int64_t* __restrict__ off, int32_t* __restrict__ col,
+                                                  double* __restrict__ val)
 {
-    __shared__ double4 sp[GROUP];
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-    const int64_t g0 = ((int64_t)blockIdx.x * 256) / GROUP;
-    float4 blo = glo[g0], bhi = ghi[g0];
-    for (int q = 1; q < 256 / GROUP; ++q) {
-        const float4 a = glo[g0 + q], b = ghi[g0 + q];
-        blo = make_float4(fminf(blo.x, a.x), fminf(blo.y, a.y), fminf(blo.z, a.z), 0.f);
-        bhi = make_float4(fmaxf(bhi.x, b.x), fmaxf(bhi.y, b.y), fmaxf(bhi.z, b.z), 0.f);
-    }
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t g0 = (int64_t)blockIdx.x * (64 / GROUP);
+    const float4 a0 = glo[g0], a1 = glo[g0 + 1], b0 = ghi[g0], b1 = ghi[g0 + 1];
+    const float4 blo = make_float4(fminf(a0.x, a1.x), fminf(a0.y, a1.y), fminf(a0.z, a1.z), 0.f);
+    const float4 bhi = make_float4(fmaxf(b0.x, b1.x), fmaxf(b0.y, b1.y), fmaxf(b0.z, b1.z), 0.f);
     const double4 pi = xyz[i];
+    const bool row = i < n;
     const float lim = (float)(r_far * 1.0001 + 1e-3);
     const double rf2 = r_far * r_far;
     const int64_t ngroups = (n + GROUP - 1) / GROUP;
     int count = 0;
-    int64_t out = (PASS == 1 && i < n) ? rp[i] : 0;
-    for (int64_t gq = 0; gq < ngroups; ++gq) {
-        if (box_gap2(blo, bhi, glo[gq], ghi[gq]) > lim * lim) continue;   // uniform over the block
-        __syncthreads();
-        if (tid < GROUP) sp[tid] = xyz[gq * GROUP + tid];
-        __syncthreads();
-        if (i >= n) continue;
-        for (int k = 0; k < GROUP; ++k) {
-            const int64_t j = gq * GROUP + k;
-            if (j >= n) break;
-            const double4 pj = sp[k];
-            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            if (j != i && !(r2 < rf2)) continue;
-            if (PASS == 0) {
-                ++count;
-            } else {
-                double v = t_self;
-                if (j != i) {
-                    const double r = sqrt(r2);
-                    v = -erfc(r * inv_rqq) / r;
+    int64_t out = PASS == 1 ? off[i / 256] + (i % 256) : 0;
+    for (int64_t base = 0; base < ngroups; base += 64) {
+        const int64_t gl = base + lane;
+        const bool hit = gl < ngroups && box_gap2(blo, bhi, glo[gl], ghi[gl]) <= lim * lim;
+        uint64_t mask = __ballot(hit);
+        while (mask) {
+            const int64_t gq = base + __builtin_ctzll(mask);
+            mask &= mask - 1;
+            for (int k = 0; k < GROUP; ++k) {
+                const int64_t j = gq * GROUP + k;
+                if (j >= n) break;
+                const double4 pj = xyz[j];
+                if (!row) continue;
+                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                if (j != i && !(r2 < rf2)) continue;
+                if (PASS == 0) {
+                    ++count;
+                } else {
+                    double v = t_self;
+                    if (j != i) {
+                        const double r = sqrt(r2);
+                        v = -erfc(r * inv_rqq) / r;
+                    }
+                    col[out] = (int32_t)j;
+                    val[out] = v;
+                    out += 256;
                 }
-                col[out] = (int32_t)j;
-                val[out] = v;
-                ++out;
             }
         }
     }
-    if (PASS == 0 && i < n) cnt[i] = count;
+    if (PASS == 0 && row) cnt[i] = count;
+}
+
+// ELL slot counts: wid[b] = 256 * (the longest row of row block b), b < nb;
+// with the exclusive scan of wid, off[b] is block b's first entry.
+__global__ void k_near_widths(const int32_t* __restrict__ cnt, int64_t n, int64_t nb, int64_t* __restrict__ wid)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int32_t w = 0;
+    for (int64_t i = b * 256; i < (b + 1) * 256 && i < n; ++i) w = cnt[i] > w ? cnt[i] : w;
+    wid[b] = 256 * (int64_t)w;
+}
+
+// Positions relative to the centre c, |p - c|^2 in w.
+__global__ void k_centred(const double4* __restrict__ xyz, int64_t np, double cx, double cy, double cz,
+                          double4* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const double4 p = xyz[i];
+    const double x = p.x - cx, y = p.y - cy, z = p.z - cz;
+    out[i] = make_double4(x, y, z, fma(x, x, fma(y, y, z * z)));
 }
 
 // ====================== grouped launches (many segments) ====================
@@ -1159,12 +1157,13 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     double rqq = std::sqrt(2.0) * g.r_q;
     DipoleConstD kc = dipole_const_d(g);
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
-    if (MODEL == 0 && g.near_ptr) {
+    if (MODEL == 0 && g.near_off) {
         // point part on the fly, near-field correction from the stored list
-        hipLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X,
-                           scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, stop);
-        hipLaunchKernelGGL(k_sum_splits_near<NC>, dim3((unsigned)((g.np + 3) / 4)), dim3(256), 0, st, scratch, nsplit, Y,
-                           g.n, g.np, g.near_ptr, g.near_col, g.near_val, X, stop);
+        hipLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, g.xyzc, X, scratch,
+                           (int)g.np, g.near_off, g.near_col, g.near_val, stop);
+        const size_t len = (size_t)g.np * NC;
+        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit,
+                           stop);
         return;
     }
     hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X,
@@ -1267,37 +1266,59 @@ int sk_workgroups(int64_t total) { return (int)std::max<int64_t>(1, std::min<int
 
 hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
 {
-    if (g.model != 0 || g.near_ptr) return hipSuccess;
+    if (g.model != 0 || g.near_off) return hipSuccess;
     const double rqq = std::sqrt(2.0) * g.r_q;
     const double r_far = XFAR_Q64 * rqq;
+    const int64_t nb = g.np / 256;
     int32_t* cnt = nullptr;
-    int32_t nnz = 0;
+    int64_t* wid = nullptr;
+    int64_t nnz = 0;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
-    PXCHK(hipMalloc(&cnt, sizeof(int32_t) * (g.n + 1)));
-    PXCHK(hipMalloc(&g.near_ptr, sizeof(int32_t) * (g.n + 1)));
-    hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, g.n,
+    PXCHK(hipMalloc(&cnt, sizeof(int32_t) * g.np));
+    PXCHK(hipMalloc(&wid, sizeof(int64_t) * nb));
+    PXCHK(hipMalloc(&g.near_off, sizeof(int64_t) * (nb + 1)));
+    PXCHK(hipMalloc(&g.xyzc, sizeof(double4) * g.np));
+    hipLaunchKernelGGL(k_centred, dim3((unsigned)((g.np + 255) / 256)), dim3(256), 0, st, g.xyz64, g.np, g.cx, g.cy,
+                       g.cz, g.xyzc);
+    hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, g.n,
                        r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, cnt, nullptr, nullptr, nullptr);
-    scan_counts(cnt, g.n, g.near_ptr, st);
-    PXCHK(hipMemcpyAsync(&nnz, g.near_ptr + g.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    PXCHK(hipStreamSynchronize(st));
-    g.near_nnz = nnz;
-    PXCHK(hipMalloc(&g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-    PXCHK(hipMalloc(&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
-    hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 256)), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, g.n,
-                       r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, nullptr, g.near_ptr, g.near_col, g.near_val);
-    PXCHK(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_near_widths, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, cnt, g.n, nb, wid);
     PXCHK(hipGetLastError());
+    {
+        // block offsets on the host (one value per 256 atoms)
+        std::vector<int64_t> w((size_t)nb), o((size_t)nb + 1);
+        PXCHK(hipMemcpyAsync(w.data(), wid, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, st));
+        PXCHK(hipStreamSynchronize(st));
+        o[0] = 0;
+        for (int64_t b = 0; b < nb; ++b) o[b + 1] = o[b] + w[b];
+        nnz = o[nb];
+        PXCHK(hipMemcpyAsync(g.near_off, o.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, st));
+        g.near_nnz = nnz;
+        PXCHK(hipMalloc(&g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+        PXCHK(hipMalloc(&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+        fill_zero(g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), st);
+        fill_zero(g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1), st);
+        hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, g.n,
+                           r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, nullptr, g.near_off, g.near_col, g.near_val);
+        PXCHK(hipStreamSynchronize(st));
+        PXCHK(hipGetLastError());
+    }
     (void)hipFree(cnt);
+    (void)hipFree(wid);
     return hipSuccess;
 fail:
 #undef PXCHK
     (void)hipFree(cnt);
-    (void)hipFree(g.near_ptr);
+    (void)hipFree(wid);
+    (void)hipFree(g.near_off);
     (void)hipFree(g.near_col);
     (void)hipFree(g.near_val);
-    g.near_ptr = g.near_col = nullptr;
+    (void)hipFree(g.xyzc);
+    g.near_off = nullptr;
+    g.near_col = nullptr;
     g.near_val = nullptr;
+    g.xyzc = nullptr;
     g.near_nnz = 0;
     return e;
 }
