@@ -7,6 +7,7 @@
 // and a fixed summation order, so a column's arithmetic never depends on which
 // other columns share the block.
 #include "px_internal.h"
+#include "px_neighbors.h"
 
 #include <hip/hip_runtime.h>
 
@@ -127,48 +128,11 @@ __device__ __forceinline__ double kappa_val(double r, const KappaConst& k)
     return (1.0 - f) * k.a_eff / r;
 }
 
-__device__ __forceinline__ float gap2(float4 alo, float4 ahi, float4 blo, float4 bhi)
-{
-    float dx = fmaxf(0.0f, fmaxf(blo.x - ahi.x, alo.x - bhi.x));
-    float dy = fmaxf(0.0f, fmaxf(blo.y - ahi.y, alo.y - bhi.y));
-    float dz = fmaxf(0.0f, fmaxf(blo.z - ahi.z, alo.z - bhi.z));
-    return dx * dx + dy * dy + dz * dz;
-}
-
-// Calls f(gq) for every source group gq < ngroups whose bounding box lies
-// within sqrt(lim2) of the box (blo, bhi), in increasing order, wave-uniform:
-// the lanes test 64 groups at a time and the wave walks the set bits.
-template <typename F>
-__device__ __forceinline__ void for_groups_near(float4 blo, float4 bhi, const float4* __restrict__ glo,
-                                                const float4* __restrict__ ghi, int64_t ngroups, float lim2, F&& f)
-{
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = 0; base < ngroups; base += 64) {
-        const int64_t gq = base + lane;
-        const bool hit = gq < ngroups && gap2(blo, bhi, glo[gq], ghi[gq]) <= lim2;
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-            const int b = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            f(base + b);
-        }
-    }
-}
-
-// Bounding box of the 64 rows (two groups) of a one-wave workgroup.
-__device__ __forceinline__ void wave_box(const float4* __restrict__ glo, const float4* __restrict__ ghi,
-                                         int64_t g0, float4& blo, float4& bhi)
-{
-    const float4 a0 = glo[g0], a1 = glo[g0 + 1], b0 = ghi[g0], b1 = ghi[g0 + 1];
-    blo = make_float4(fminf(a0.x, a1.x), fminf(a0.y, a1.y), fminf(a0.z, a1.z), 0.f);
-    bhi = make_float4(fmaxf(b0.x, b1.x), fmaxf(b0.y, b1.y), fmaxf(b0.z, b1.z), 0.f);
-}
-
 // Neighbour search over the real atoms, one thread per row atom, 64 rows per
-// (one-wave) workgroup; source atoms are read wave-uniform.  Pass 0 counts
-// (row length incl. the diagonal) and flags coincident atoms; pass 1 fills
-// columns in increasing order, the diagonal slot kept where the columns pass
-// i and filled with Kbar_ii = -sum_k K_ik once the row is summed.
+// (one-wave) workgroup (px_neighbors.h).  Pass 0 counts (row length incl. the
+// diagonal) and flags coincident atoms; pass 1 fills columns in increasing
+// order, the diagonal slot kept where the columns pass i and filled with
+// Kbar_ii = -sum_k K_ik once the row is summed.
 template <int PASS>
 __global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
                                                   const float4* __restrict__ ghi, int64_t n, int64_t np,
@@ -178,8 +142,6 @@ __global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x6
                                                   double* __restrict__ val, int* __restrict__ bad)
 {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    float4 blo, bhi;
-    wave_box(glo, ghi, (int64_t)blockIdx.x * (64 / GROUP), blo, bhi);
     const double4 pi = x64[i];
     const bool row = i < n;
     const float lim = (float)(ks.rc_max * 1.0001 + 1e-3);
@@ -189,30 +151,25 @@ __global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x6
     double ksum = 0.0;
     int64_t out = (PASS == 1 && row) ? row_ptr[i] : 0;
     int64_t diag = -1;
-    for_groups_near(blo, bhi, glo, ghi, (n + GROUP - 1) / GROUP, lim * lim, [&](int64_t gq) {
-        for (int k = 0; k < GROUP; ++k) {
-            const int64_t j = gq * GROUP + k;
-            if (j >= n) break;
-            const double4 pj = x64[j];
-            if (!row) continue;
-            if (PASS == 1 && diag < 0 && j > i) diag = out++;
-            if (j == i) continue;
-            const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 > lim2) continue;
-            const double r = sqrt(r2);
-            const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
-            if (PASS == 0 && r < kc.min_r) *bad = 1;
-            if (r <= kc.rc) {
-                if (PASS == 0) {
-                    ++count;
-                } else {
-                    const double v = kappa_val(r, kc);
-                    col[out] = (int32_t)j;
-                    val[out] = v;
-                    ksum += v;
-                    ++out;
-                }
+    nbr::for_near_atoms(x64, n, glo, ghi, lim, [&](int64_t j, const double4& pj) {
+        if (!row) return;
+        if (PASS == 1 && diag < 0 && j > i) diag = out++;
+        if (j == i) return;
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > lim2) return;
+        const double r = sqrt(r2);
+        const KappaConst& kc = ks.k[type ? ti + type[j] : 0];
+        if (PASS == 0 && r < kc.min_r) *bad = 1;
+        if (r <= kc.rc) {
+            if (PASS == 0) {
+                ++count;
+            } else {
+                const double v = kappa_val(r, kc);
+                col[out] = (int32_t)j;
+                val[out] = v;
+                ksum += v;
+                ++out;
             }
         }
     });

@@ -22,6 +22,7 @@
 // uniform per wave.  The diagonal T_ii is the Gaussian self-interaction
 // sqrt(2/pi)/R_q; the dipole self blocks are zero.
 #include "px_internal.h"
+#include "px_neighbors.h"
 
 #include <hip/hip_runtime.h>
 
@@ -903,15 +904,21 @@ __global__ __launch_bounds__(256) void k_tapply_f64_narrow_q(const double4* __re
     for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
 }
 
+// Y[t] = sum over the splits of part[k][t], in four interleaved chains so that
+// several loads of a thread are in flight (the launches have few waves).
 __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict__ Y, size_t len, int nsplit,
     const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;   // every column of the block is done
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= len) return;
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * len + t];
-    Y[t] = s;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 4 <= nsplit; k += 4)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += part[(size_t)(k + q) * len + t];
+    for (; k < nsplit; ++k) s[0] += part[(size_t)k * len + t];
+    Y[t] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // Near-field list of the omegaFQ T in FP64 over the real atoms: for every
@@ -921,9 +928,7 @@ __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict
 // width_b = (off[b+1] - off[b]) / 256 slots, entry k of row i at off[b] +
 // k * 256 + (i - 256 b), columns increasing along the slots, unused slots left
 // as cleared (column 0, value 0).  One thread per row atom, 64 rows per
-// (one-wave) workgroup; the wave visits only the source groups whose bounding
-// box lies within r_far of its rows' box (64 groups tested at a time, one per
-// lane) and reads their atoms wave-uniform.
+// (one-wave) workgroup (px_neighbors.h).
 template <int PASS>
 __global__ __launch_bounds__(64) void k_near_rows(const double4* __restrict__ xyz, const float4* __restrict__ glo,
                                                   const float4* __restrict__ ghi, int64_t n, double r_far,
@@ -931,49 +936,30 @@ __global__ __launch_bounds__(64) void k_near_rows(const double4* __restrict__ xy
                                                   const int64_t* __restrict__ off, int32_t* __restrict__ col,
                                                   double* __restrict__ val)
 {
-    const int lane = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t g0 = (int64_t)blockIdx.x * (64 / GROUP);
-    const float4 a0 = glo[g0], a1 = glo[g0 + 1], b0 = ghi[g0], b1 = ghi[g0 + 1];
-    const float4 blo = make_float4(fminf(a0.x, a1.x), fminf(a0.y, a1.y), fminf(a0.z, a1.z), 0.f);
-    const float4 bhi = make_float4(fmaxf(b0.x, b1.x), fmaxf(b0.y, b1.y), fmaxf(b0.z, b1.z), 0.f);
+    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const double4 pi = xyz[i];
     const bool row = i < n;
-    const float lim = (float)(r_far * 1.0001 + 1e-3);
     const double rf2 = r_far * r_far;
-    const int64_t ngroups = (n + GROUP - 1) / GROUP;
     int count = 0;
     int64_t out = PASS == 1 ? off[i / 256] + (i % 256) : 0;
-    for (int64_t base = 0; base < ngroups; base += 64) {
-        const int64_t gl = base + lane;
-        const bool hit = gl < ngroups && box_gap2(blo, bhi, glo[gl], ghi[gl]) <= lim * lim;
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-            const int64_t gq = base + __builtin_ctzll(mask);
-            mask &= mask - 1;
-            for (int k = 0; k < GROUP; ++k) {
-                const int64_t j = gq * GROUP + k;
-                if (j >= n) break;
-                const double4 pj = xyz[j];
-                if (!row) continue;
-                const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                if (j != i && !(r2 < rf2)) continue;
-                if (PASS == 0) {
-                    ++count;
-                } else {
-                    double v = t_self;
-                    if (j != i) {
-                        const double r = sqrt(r2);
-                        v = -erfc(r * inv_rqq) / r;
-                    }
-                    col[out] = (int32_t)j;
-                    val[out] = v;
-                    out += 256;
-                }
+    nbr::for_near_atoms(xyz, n, glo, ghi, (float)(r_far * 1.0001 + 1e-3), [&](int64_t j, const double4& pj) {
+        if (!row) return;
+        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        if (j != i && !(r2 < rf2)) return;
+        if (PASS == 0) {
+            ++count;
+        } else {
+            double v = t_self;
+            if (j != i) {
+                const double r = sqrt(r2);
+                v = -erfc(r * inv_rqq) / r;
             }
+            col[out] = (int32_t)j;
+            val[out] = v;
+            out += 256;
         }
-    }
+    });
     if (PASS == 0 && row) cnt[i] = count;
 }
 
@@ -1162,7 +1148,7 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
         hipLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, g.xyzc, X, scratch,
                            (int)g.np, g.near_off, g.near_col, g.near_val, stop);
         const size_t len = (size_t)g.np * NC;
-        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit,
+        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 63) / 64)), dim3(64), 0, st, scratch, Y, len, nsplit,
                            stop);
         return;
     }
