@@ -106,7 +106,8 @@ typedef struct {
  *   inner_reduction  mixed precision: a cycle stops for a column once its
  *                    estimated residual fell by this factor (1e-5); 0 = only
  *                    the rel_tol target stops it
- *   timings          1 = time each phase with HIP events (pxGetTimings) (0)
+ *   timings          1 = time each phase with HIP events, sampled
+ *                    (pxGetTimings) (0)
  *   block_cols       columns per segment of the stacked multi-structure block
  *                    used by pxSolveBatch and the server (multiple of 64;
  *                    0 = 64)
@@ -303,7 +304,11 @@ pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns);
  * HIP-event times summed over all Arnoldi steps of [1] the FP32 T-apply, [2]
  * the FP64 T-apply inside cycles, [3] the sparse Kbar apply, [4] the
  * orthogonalisation/Givens kernels, and [5] the remainder (residuals,
- * updates, host work); zeros otherwise.
+ * updates, host work); zeros otherwise.  Only every 16th Arnoldi step of a
+ * cycle or of the shared-Krylov phase is timed (an event costs a few
+ * microseconds of stream time) and the sampled steps' mean is scaled to all
+ * steps; the shared phase's Givens kernels run on a second stream and count in
+ * [5] only where they delay the main stream.
  * counts6 (may be NULL): [0] FP32 T-apply launches, [1] real columns they
  * processed including padding, [2] real columns without padding; [3..5] the
  * same for the FP64 T-apply (inside cycles and true residuals). */

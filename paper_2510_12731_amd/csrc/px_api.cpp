@@ -294,15 +294,19 @@ void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, i
     if (e != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas gemm"};
 }
 
-void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop)
+void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop,
+               const hipEvent_t* ev = nullptr)
 {
     Workspace& W = s->ws;
-    if (f32)
+    if (f32) {
+        if (ev) HC(hipEventRecord(ev[0], s->st));
         px::tapply_f32(s->g, static_cast<const float*>(X), static_cast<float*>(Y), ldx, ncols, s->st, W.split32,
                        stop);
-    else
+        if (ev) HC(hipEventRecord(ev[1], s->st));
+    } else {
         px::tapply_f64(s->g, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st, W.narrow,
-                       W.narrow_bytes, stop);
+                       W.narrow_bytes, stop, ev);
+    }
 }
 
 float time_apply(pxStructure_t* s, bool f32, int method, const void* X, void* Y, int ldx, int ncols)
@@ -357,10 +361,18 @@ int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, i
     return m;
 }
 
-void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop)
+// ev (optional): start/stop events around the apply (carried by the launches
+// of the on-the-fly FP64 kernels, recorded on the stream otherwise).
+void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop,
+            const hipEvent_t* ev = nullptr)
 {
-    if (method == TA_STORED) apply_stored(s, f32, X, Y, ldx, ncols);
-    else apply_fly(s, f32, X, Y, ldx, ncols, stop);
+    if (method == TA_STORED) {
+        if (ev) HC(hipEventRecord(ev[0], s->st));
+        apply_stored(s, f32, X, Y, ldx, ncols);
+        if (ev) HC(hipEventRecord(ev[1], s->st));
+    } else {
+        apply_fly(s, f32, X, Y, ldx, ncols, stop, ev);
+    }
 }
 
 // The sparse part of the operator on the active block, Y = T X given: the
@@ -704,8 +716,12 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     px::ms_init(R, s->b, s->ldg, bn, u, nup, st);
 
     const int method = tapply_method(s, false, u, Y, R, R, o);
-    const int lag = method == TA_STORED ? 1 : kLag;
-    s->sync.ensure(kcap + 1);
+    // a stored-T GEMM cannot read the stop flag, so it polls as soon as possible;
+    // the on-the-fly kernels return at once once it is set, and a longer lag
+    // keeps the host from waiting on a Givens batch the main stream has not
+    // overtaken yet
+    const int lag = method == TA_STORED ? 1 : 2 * kLag;
+    s->sync.ensure(kcap / GB + 2);
     int32_t* stop = s->sync.flag();
     s->sync.reset(st);
     // the shifted Givens QRs (a few waves) run on a second stream of the same
@@ -722,38 +738,47 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     } side;
     HC(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
     HC(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
-    auto givens_side = [&](int k0, int kn) {
+    // Only the Givens batches can raise the stop flag, so it is published (copied
+    // to the host) once per batch, on the second stream; the host polls the
+    // batch whose publication was enqueued at least lag steps earlier.
+    std::vector<int> batch_step;
+    int polled = 0;
+    auto givens_side = [&](int k0, int kn, int at_step) {
         HC(hipEventRecord(side.e, st));
         HC(hipStreamWaitEvent(side.s, side.e, 0));
         px::ms_givens(H, kcap, npol, P, k0, kn, z, cs, sn, g, target, done, resid, ndone, stop, side.s);
+        s->sync.publish((int)batch_step.size(), side.s);
+        batch_step.push_back(at_step);
     };
-    StepTimer tm(o.timings != 0);
-    tm.ensure(kcap);
+    LaunchTimer tm(o.timings != 0);
     int launched = 0, gnext = 0;
-    for (int k = 0; k < kcap; ++k) {
-        if (k >= lag && s->sync.stopped(k - lag)) break;
-        tm.mark(k, 0, st);
+    bool stopped = false;
+    for (int k = 0; k < kcap && !stopped; ++k) {
+        while (polled < (int)batch_step.size() && batch_step[polled] <= k - lag) {
+            if (s->sync.stopped(polled++)) {
+                stopped = true;
+                break;
+            }
+        }
+        if (stopped) break;
         // wt = Kbar T u for the candidate u of v_k
-        tapply(s, method, false, u, Y, R, R, stop);
-        tm.mark(k, 1, st);
-        px::ms_spmv(R, s->g, Y, wt, st, stop);
-        tm.mark(k, 2, st);
+        tapply(s, method, false, u, Y, R, R, stop, tm.events(k, 0));
+        px::ms_spmv(R, s->g, Y, wt, st, stop, tm.events(k, 1));
         // one dot and one update pass: v_k final, column k-1 of Hbar final
-        px::ms_step(R, V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup, false, st, stop);
+        px::ms_step(R, V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup, false, st, stop,
+                    tm.events(k, 2));
         // the shifted Givens QRs take GB finished Hessenberg columns per launch
         if (k - gnext >= GB) {
-            givens_side(gnext, GB);
+            givens_side(gnext, GB, k);
             gnext += GB;
         }
-        tm.mark(k, 3, st);
-        s->sync.publish(k, st);
         ++launched;
     }
     // the last column's correction (a no-op once every pair converged), then its rotations
     px::ms_step(R, V, vstride, launched, u, u, part, part2, G, H, kcap, coefv, coefu, scal, nup, true, st, stop);
     while (gnext < launched) {
         const int kn = std::min(GB, launched - gnext);
-        givens_side(gnext, kn);
+        givens_side(gnext, kn, launched);
         gnext += kn;
     }
     HC(hipEventRecord(side.e, side.s));

@@ -80,8 +80,10 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st);
 // scratch: tapply_f32_scratch_bytes(g, ncols) bytes (split-K partial sums).
 void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols, hipStream_t st, float* scratch, const int32_t* stop = nullptr);
 size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols);
+// ev: optional start/stop events carried by the first and last launch (timing
+// without extra stream packets).
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr);
+                double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
 // Dense T over the padded unknowns (row-major, nup x nup; ghost rows and
@@ -226,13 +228,15 @@ void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int
 // R = npol real slots per row (1..3), one per polarization; Hbar row-major per
 // slot with row stride kcap; see px_shifted.hip.
 void ms_init(int R, const double2* b, int ldb, const double* bnorm, double* u, int64_t nup, hipStream_t st);
-void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop);
+// ev (optional): start and stop events carried by the first and last launch.
+void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop,
+             const hipEvent_t* ev = nullptr);
 // One DCGS2 step k: dots of [V_{<k}, u] with u and wt, the coefficients (column
 // k-1 corrected, column k first pass) and the update pass writing V_k and the
 // next candidate u; fix_only: the last column's correction alone.
 void ms_step(int R, double* V, int64_t vstride, int k, double* u, const double* wt, double* part, double* part2,
              double* G, double* H, int kcap, double* coefv, double* coefu, double* scal, int64_t nup, bool fix_only,
-             hipStream_t st, const int32_t* stop);
+             hipStream_t st, const int32_t* stop, const hipEvent_t* ev = nullptr);
 size_t ms_part_doubles(int R, int64_t nup, int kcap);
 size_t ms_part2_doubles(int R, int64_t nup, int kcap);
 // Hessenberg columns k0 .. k0+kn-1 (kn <= ms_givens_batch()) for every (frequency, polarization) pair

@@ -19,6 +19,7 @@
 // coalesced over p.
 #include "px_internal.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace px {
@@ -569,13 +570,14 @@ void with_r(int R, A... a)
     else F<3>::run(a...);
 }
 
-// row slabs of the dot pass over ngroups vector groups: about 2048 blocks
+// row slabs of the dot pass over ngroups vector groups: about 1024 blocks
 // (two vectors per block measured fastest: 47 us against 54 us for one and
-// 73 us for four at step 800 of the 20k-atom sphere)
+// 73 us for four at step 800 of the 20k-atom sphere; 1024 blocks 1 ms per
+// solve faster than 2048 there, 4096 5 ms slower)
 int ms_slabs(int64_t nup, int ngroups)
 {
     int64_t maxs = (nup + 255) / 256;
-    int64_t want = (2048 + ngroups - 1) / ngroups;
+    int64_t want = (1024 + ngroups - 1) / ngroups;
     if (want < 1) want = 1;
     if (want > maxs) want = maxs;
     return (int)want;
@@ -608,10 +610,12 @@ struct InitL {
 
 template <int R>
 struct SpmvL {
-    static void run(const Geometry* g, const double* Y, double* w, hipStream_t st, const int32_t* stop)
+    static void run(const Geometry* g, const double* Y, double* w, hipStream_t st, const int32_t* stop,
+                    hipEvent_t e0, hipEvent_t e1)
     {
-        hipLaunchKernelGGL(k_ms_spmv<R>, dim3((unsigned)((g->np + 255) / 256)), dim3(256), 0, st, g->row_ptr, g->col,
-                           g->val, Y, w, g->n, g->np, stop);
+        hipExtLaunchKernelGGL(k_ms_spmv<R>, dim3((unsigned)((g->np + 255) / 256)), dim3(256), 0, st, e0, e1, 0,
+                              (const int32_t*)g->row_ptr, (const int32_t*)g->col, (const double*)g->val, Y, w, g->n,
+                              g->np, stop);
     }
 };
 
@@ -619,28 +623,33 @@ template <int R>
 struct StepL {
     static void run(const double* V, int64_t vstride, int k, double* u, const double* wt, double* part,
                     double* part2, double* G, double* H, int kcap, double* coefv, double* coefu, double* scal,
-                    int64_t nup, int fix_only, hipStream_t st, const int32_t* stop)
+                    int64_t nup, int fix_only, hipStream_t st, const int32_t* stop, hipEvent_t e0, hipEvent_t e1)
     {
         constexpr int W = 2 * R;
         const int nvec = k + 1;
         const int ngroups = (nvec + MJ - 1) / MJ;
         const int nslab = ms_slabs(nup, ngroups);
         const int64_t rps = (nup + nslab - 1) / nslab;
-        hipLaunchKernelGGL(k_ms_dots<R>, dim3((unsigned)nslab, (unsigned)ngroups), dim3(256), 0, st, V, vstride, k,
-                           u, wt, part, nup, rps, stop);
+        hipExtLaunchKernelGGL(k_ms_dots<R>, dim3((unsigned)nslab, (unsigned)ngroups), dim3(256), 0, st, e0, nullptr, 0,
+                              V, vstride, k, (const double*)u, wt, part, nup, rps, stop);
         hipLaunchKernelGGL(k_ms_reduce<W>, dim3((unsigned)((nvec * W + 255) / 256)), dim3(256), 0, st, part, nslab,
                            nvec, G, stop);
+        if (fix_only) {
+            hipExtLaunchKernelGGL(k_ms_coef<R>, dim3((unsigned)((k + 1 + 3) / 4), (unsigned)R), dim3(256), 0, st,
+                                  nullptr, e1, 0, (const double*)G, H, kcap, k, fix_only, coefv, coefu, scal, stop);
+            return;
+        }
         hipLaunchKernelGGL(k_ms_coef<R>, dim3((unsigned)((k + 1 + 3) / 4), (unsigned)R), dim3(256), 0, st, G, H,
                            kcap, k, fix_only, coefv, coefu, scal, stop);
-        if (fix_only) return;
         int vps, nsp;
         ms_update_split(nup, k, vps, nsp);
         double* vk = const_cast<double*>(V) + (size_t)k * vstride;
-        hipLaunchKernelGGL(k_ms_update<R>, dim3((unsigned)((nup + 255) / 256), (unsigned)nsp), dim3(256), 0, st, V,
-                           vstride, k, coefv, coefu, scal, u, wt, vk, part2, nup, vps, stop);
+        hipExtLaunchKernelGGL(k_ms_update<R>, dim3((unsigned)((nup + 255) / 256), (unsigned)nsp), dim3(256), 0, st,
+                              nullptr, nsp > 1 ? nullptr : e1, 0, V, vstride, k, (const double*)coefv,
+                              (const double*)coefu, (const double*)scal, u, wt, vk, part2, nup, vps, stop);
         if (nsp > 1)
-            hipLaunchKernelGGL(k_ms_finish<R>, dim3((unsigned)((nup * R + 255) / 256)), dim3(256), 0, st, part2, nsp,
-                               scal, u, wt, vk, nup, stop);
+            hipExtLaunchKernelGGL(k_ms_finish<R>, dim3((unsigned)((nup * R + 255) / 256)), dim3(256), 0, st, nullptr,
+                                  e1, 0, (const double*)part2, nsp, (const double*)scal, u, wt, vk, nup, stop);
     }
 };
 
@@ -661,24 +670,25 @@ void ms_init(int R, const double2* b, int ldb, const double* bnorm, double* u, i
     with_r<InitL>(R, b, ldb, bnorm, u, nup, st);
 }
 
-void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop)
+void ms_spmv(int R, const Geometry& g, const double* Y, double* w, hipStream_t st, const int32_t* stop,
+             const hipEvent_t* ev)
 {
-    with_r<SpmvL>(R, &g, Y, w, st, stop);
+    with_r<SpmvL>(R, &g, Y, w, st, stop, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
 
 void ms_step(int R, double* V, int64_t vstride, int k, double* u, const double* wt, double* part, double* part2,
              double* G, double* H, int kcap, double* coefv, double* coefu, double* scal, int64_t nup, bool fix_only,
-             hipStream_t st, const int32_t* stop)
+             hipStream_t st, const int32_t* stop, const hipEvent_t* ev)
 {
     with_r<StepL>(R, (const double*)V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup,
-                  fix_only ? 1 : 0, st, stop);
+                  fix_only ? 1 : 0, st, stop, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
 }
 
 size_t ms_part_doubles(int R, int64_t nup, int kcap)
 {
-    // slabs x (vectors rounded up to MJ) <= (2048 + groups) x MJ for every length up to kcap + 1
+    // slabs x (vectors rounded up to MJ) <= (1024 + groups) x MJ for every length up to kcap + 1
     (void)nup;
-    return (size_t)(2048 + (kcap + 1 + MJ - 1) / MJ) * MJ * 2 * R;
+    return (size_t)(1024 + (kcap + 1 + MJ - 1) / MJ) * MJ * 2 * R;
 }
 
 size_t ms_part2_doubles(int R, int64_t nup, int kcap)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <array>
 #include <vector>
 
 #include "plasmonx.h"
@@ -129,8 +130,12 @@ class StepSync {
 };
 
 // Per-step phase timing with HIP events, read after the cycle's final sync.
+// An event costs a few microseconds of stream time, so only every kStride-th
+// step of a cycle is marked and collect() scales the sampled steps' mean to
+// all steps.
 class StepTimer {
   public:
+    static constexpr int kStride = 16;
     explicit StepTimer(bool on) : on_(on) {}
     StepTimer(const StepTimer&) = delete;
     StepTimer& operator=(const StepTimer&) = delete;
@@ -141,7 +146,8 @@ class StepTimer {
     void ensure(int steps)
     {
         if (!on_) return;
-        while ((int)ev_.size() < 4 * steps) {
+        const int slots = (steps + kStride - 1) / kStride;
+        while ((int)ev_.size() < 4 * slots) {
             hipEvent_t e;
             HC(hipEventCreate(&e));
             ev_.push_back(e);
@@ -149,27 +155,102 @@ class StepTimer {
     }
     void mark(int k, int i, hipStream_t st)
     {
-        if (on_) HC(hipEventRecord(ev_[4 * k + i], st));
+        if (on_ && k % kStride == 0) HC(hipEventRecord(ev_[4 * (k / kStride) + i], st));
     }
-    // adds the phase times of steps [0, nsteps) to ms[1..4] style slots: t01 -> a, t12 -> b, t23 -> c
+    // adds the estimated phase times of steps [0, nsteps) to a, b, c (t01, t12, t23)
     void collect(int nsteps, double& a, double& b, double& c)
     {
-        if (!on_) return;
-        for (int k = 0; k < nsteps; ++k) {
+        if (!on_ || nsteps <= 0) return;
+        const int m = (nsteps + kStride - 1) / kStride;
+        double sa = 0.0, sb = 0.0, sc = 0.0;
+        for (int q = 0; q < m; ++q) {
             float t = 0.f;
-            HC(hipEventElapsedTime(&t, ev_[4 * k], ev_[4 * k + 1]));
-            a += t;
-            HC(hipEventElapsedTime(&t, ev_[4 * k + 1], ev_[4 * k + 2]));
-            b += t;
-            HC(hipEventElapsedTime(&t, ev_[4 * k + 2], ev_[4 * k + 3]));
-            c += t;
+            HC(hipEventElapsedTime(&t, ev_[4 * q], ev_[4 * q + 1]));
+            sa += t;
+            HC(hipEventElapsedTime(&t, ev_[4 * q + 1], ev_[4 * q + 2]));
+            sb += t;
+            HC(hipEventElapsedTime(&t, ev_[4 * q + 2], ev_[4 * q + 3]));
+            sc += t;
         }
+        a += sa * nsteps / m;
+        b += sb * nsteps / m;
+        c += sc * nsteps / m;
     }
     bool on() const { return on_; }
 
   private:
     bool on_;
     std::vector<hipEvent_t> ev_;
+};
+
+// Sampled per-step kernel timing for the shared-Krylov phase.  An event costs
+// a few microseconds of stream time, so only every kStride-th step is timed
+// (its phases' first and last launches carry start and stop events); the
+// sampled event sets form a ring of kRing, read on the host when a slot comes
+// round again (the host has waited for later steps by then) or at the end, and
+// the totals are scaled from the sampled steps to all steps.
+class LaunchTimer {
+  public:
+    static constexpr int kStride = 16, kRing = 16, kPhases = 3;
+    explicit LaunchTimer(bool on) : on_(on)
+    {
+        if (!on_) return;
+        ev_.resize((size_t)kRing * kPhases * 2);
+        for (auto& e : ev_) HC(hipEventCreate(&e));
+    }
+    LaunchTimer(const LaunchTimer&) = delete;
+    LaunchTimer& operator=(const LaunchTimer&) = delete;
+    ~LaunchTimer()
+    {
+        for (auto& e : ev_) (void)hipEventDestroy(e);
+    }
+    // start/stop events of phase i for step k, or null when step k is not
+    // timed; call for phase 0 of step k before its other phases
+    const hipEvent_t* events(int k, int i)
+    {
+        if (!on_ || k % kStride != 0) return nullptr;
+        const int q = k / kStride;
+        if (i == 0) {
+            if (q >= kRing) read(q - kRing);
+            if ((int)ms_.size() < q + 1) ms_.resize((size_t)q + 1, {0.0, 0.0, 0.0});
+            recorded_ = q + 1;
+        }
+        return &ev_[((size_t)(q % kRing) * kPhases + i) * 2];
+    }
+    // adds the estimated phase times of steps [0, nsteps) to a, b, c: the
+    // sampled steps' mean times nsteps
+    void collect(int nsteps, double& a, double& b, double& c)
+    {
+        if (!on_ || nsteps <= 0) return;
+        for (int q = recorded_ - kRing > 0 ? recorded_ - kRing : 0; q < recorded_; ++q) read(q);
+        int m = 0;
+        double sa = 0.0, sb = 0.0, sc = 0.0;
+        for (int q = 0; q < recorded_ && q * kStride < nsteps; ++q, ++m) {
+            sa += ms_[q][0];
+            sb += ms_[q][1];
+            sc += ms_[q][2];
+        }
+        if (m == 0) return;
+        a += sa * nsteps / m;
+        b += sb * nsteps / m;
+        c += sc * nsteps / m;
+    }
+
+  private:
+    void read(int q)
+    {
+        for (int i = 0; i < kPhases; ++i) {
+            const hipEvent_t* e = &ev_[((size_t)(q % kRing) * kPhases + i) * 2];
+            HC(hipEventSynchronize(e[1]));
+            float t = 0.f;
+            HC(hipEventElapsedTime(&t, e[0], e[1]));
+            ms_[q][i] = t;
+        }
+    }
+    bool on_;
+    int recorded_ = 0;
+    std::vector<hipEvent_t> ev_;
+    std::vector<std::array<double, 3>> ms_;
 };
 
 // Destroys a rocBLAS handle made by the stored-T apply (null: nothing).

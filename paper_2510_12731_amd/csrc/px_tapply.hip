@@ -24,6 +24,7 @@
 #include "px_internal.h"
 #include "px_neighbors.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1134,7 +1135,8 @@ int narrow_splits(const Geometry& g)
 }
 
 template <int NC, int MODEL>
-void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch, const int32_t* stop)
+void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch, const int32_t* stop,
+                   hipEvent_t ev0, hipEvent_t ev1)
 {
     int rb = (int)(g.np / 256);
     int nchunk = (int)(g.np / NW_CHUNK);
@@ -1145,17 +1147,20 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
     if (MODEL == 0 && g.near_off) {
         // point part on the fly, near-field correction from the stored list
-        hipLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, g.xyzc, X, scratch,
-                           (int)g.np, g.near_off, g.near_col, g.near_val, stop);
+        hipExtLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, ev0, nullptr, 0,
+                              (const double4*)g.xyzc, X, scratch, (int)g.np, (const int64_t*)g.near_off,
+                              (const int32_t*)g.near_col, (const double*)g.near_val, stop);
         const size_t len = (size_t)g.np * NC;
-        hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 63) / 64)), dim3(64), 0, st, scratch, Y, len, nsplit,
-                           stop);
+        hipExtLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 63) / 64)), dim3(64), 0, st, nullptr, ev1, 0,
+                              (const double*)scratch, Y, len, nsplit, stop);
         return;
     }
-    hipLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X,
-                       scratch, (int)g.np, cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc, stop);
+    hipExtLaunchKernelGGL((k_tapply_f64_narrow<NC, MODEL>), dim3(rb, nsplit), dim3(256), 0, st, ev0, nullptr, 0,
+                          (const double4*)g.xyz64, (const float4*)g.glo, (const float4*)g.ghi, X, scratch, (int)g.np,
+                          cps, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf2, kc, stop);
     size_t len = (size_t)(MODEL ? 4 : 1) * g.np * NC;
-    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, scratch, Y, len, nsplit, stop);
+    hipExtLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, nullptr, ev1, 0,
+                          (const double*)scratch, Y, len, nsplit, stop);
 }
 
 // ---- dense T for the stored-T apply ---------------------------------------------
@@ -1354,26 +1359,27 @@ size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 }
 
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes, const int32_t* stop)
+                double* scratch, size_t scratch_bytes, const int32_t* stop, const hipEvent_t* ev)
 {
     (void)scratch_bytes;
+    hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
     if (ncols <= 8) {
         // narrow layout: ldx == ncols
         if (g.model == 0) {
             switch (ncols) {
-            case 1: launch_narrow<1, 0>(g, X, Y, st, scratch, stop); break;
-            case 2: launch_narrow<2, 0>(g, X, Y, st, scratch, stop); break;
-            case 3: launch_narrow<3, 0>(g, X, Y, st, scratch, stop); break;
-            case 4: launch_narrow<4, 0>(g, X, Y, st, scratch, stop); break;
-            case 6: launch_narrow<6, 0>(g, X, Y, st, scratch, stop); break;
-            default: launch_narrow<8, 0>(g, X, Y, st, scratch, stop); break;
+            case 1: launch_narrow<1, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 2: launch_narrow<2, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 3: launch_narrow<3, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 4: launch_narrow<4, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 6: launch_narrow<6, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
+            default: launch_narrow<8, 0>(g, X, Y, st, scratch, stop, e0, e1); break;
             }
         } else {
             switch (ncols) {
-            case 2: launch_narrow<2, 1>(g, X, Y, st, scratch, stop); break;
-            case 4: launch_narrow<4, 1>(g, X, Y, st, scratch, stop); break;
-            case 6: launch_narrow<6, 1>(g, X, Y, st, scratch, stop); break;
-            default: launch_narrow<8, 1>(g, X, Y, st, scratch, stop); break;
+            case 2: launch_narrow<2, 1>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 4: launch_narrow<4, 1>(g, X, Y, st, scratch, stop, e0, e1); break;
+            case 6: launch_narrow<6, 1>(g, X, Y, st, scratch, stop, e0, e1); break;
+            default: launch_narrow<8, 1>(g, X, Y, st, scratch, stop, e0, e1); break;
             }
         }
         return;
@@ -1381,13 +1387,14 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
     if (g.model == 0) {
         double rqq = std::sqrt(2.0) * g.r_q;
         float rf = (float)(XFAR_Q64 * rqq);
-        hipLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)(ncols / Q64_COLS)), dim3(256),
-                           0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, 1.0 / rqq, TWO_OVER_SQRTPI / rqq,
-                           rf * rf, stop);
+        hipExtLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)(ncols / Q64_COLS)), dim3(256),
+                              0, st, e0, e1, 0, (const double4*)g.xyz64, (const float4*)g.glo, (const float4*)g.ghi, X,
+                              Y, (int)g.np, ldx, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf * rf, stop);
     } else {
         DipoleConstD k = dipole_const_d(g);
-        hipLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
-                           dim3(256), 0, st, g.xyz64, g.glo, g.ghi, X, Y, (int)g.np, ldx, k, stop);
+        hipExtLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
+                              dim3(256), 0, st, e0, e1, 0, (const double4*)g.xyz64, (const float4*)g.glo,
+                              (const float4*)g.ghi, X, Y, (int)g.np, ldx, k, stop);
     }
 }
 
