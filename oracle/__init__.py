@@ -70,6 +70,7 @@ def _load():
     lib.or_apply_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, i64, dp, dp, dp, dp, dp]
     lib.or_rhs_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                dp]
+    lib.or_probe.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, i64, dp, dp, dp, dp]
     _lib = lib
     return lib
 
@@ -280,3 +281,24 @@ def assemble(model, xyz, p, omega_ev, alpha_ib=None):
     aib = _alpha_ib_arr(alpha_ib, 1)
     _load().or_assemble(int(model), n, _d(xyz), _d(_pv(p)), float(omega_ev), _d(aib), _d(a.view(np.float64)))
     return a
+
+
+def probe(model, xyz, p, q, mu, pts):
+    """Potential, field and density of Gaussian charges q [n] (and dipoles mu
+    [3, n], model 1) on the atoms at points pts [npts, 3] (Angstrom).  Returns
+    dict(phi=[npts], field=[npts, 3], rho=[npts]) complex, atomic units."""
+    xyz = _xyz(xyz)
+    n = len(xyz)
+    q = np.ascontiguousarray(q, dtype=np.complex128).reshape(n)
+    mu_arr = None
+    if model == 1 and mu is not None:
+        mu_arr = np.ascontiguousarray(mu, dtype=np.complex128).reshape(3 * n)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    npts = len(pts)
+    phi = np.zeros(npts, dtype=np.complex128)
+    field = np.zeros((npts, 3), dtype=np.complex128)
+    rho = np.zeros(npts, dtype=np.complex128)
+    _load().or_probe(int(model), n, _d(xyz), _d(_pv(p)), _d(q.view(np.float64)),
+                     _d(mu_arr.view(np.float64)) if mu_arr is not None else None, npts, _d(pts),
+                     _d(phi.view(np.float64)), _d(field.view(np.float64)), _d(rho.view(np.float64)))
+    return dict(phi=phi, field=field, rho=rho)

@@ -19,6 +19,8 @@
  *   Eq. (wfqfmu-leghe), Eq. (polar-finale): two atom types (the *_het functions)
  *   Section 6, "inversion": LU with partial pivoting, then forward/back solves
  *   Section 7: d = sum_i q_i r_i (+ mu_i), alpha_kl = d_k / E_l, sigma_abs.
+ *   Section "Post-process Analysis": potential, field and density of the
+ *   induced Gaussian charges and dipoles at probe points (or_probe)
  *
  * Readings of points the paper leaves open (each listed in the design notes):
  *   - T^qq diagonal = lim_{r->0} erf(r/R_ii)/r = sqrt(2/pi)/R_q (the Gaussian
@@ -908,4 +910,108 @@ void or_constants(double* out3)
     out3[0] = ANG_PER_BOHR;
     out3[1] = EV_PER_HARTREE;
     out3[2] = C_LIGHT_AU;
+}
+
+/* ---- post-processing: induced potential, field and density at probe points
+ * (Section "Post-process Analysis"; the charges and dipoles are the Gaussian
+ * distributions of Section 2: width R_q for a charge, R_mu for a dipole).
+ *
+ * A Gaussian charge q at r_i has density q G(r; R), G = exp(-r^2/R^2) /
+ * (pi^{3/2} R^3), and potential q erf(r/R) / r, r = |p - r_i|.  A Gaussian
+ * dipole mu is the limit of a charge pair: density -mu . grad G (= (2/R^2)
+ * (mu . d) G, d = p - r_i) and potential mu . d g(r; R) / r^3.  The field is
+ * minus the gradient of the potential:
+ *   charge:  E = q g(r; R_q) d / r^3
+ *   dipole:  E = -mu g / r^3 + (mu . d) d [3 g / r^5 - (4/sqrt(pi)) exp(-x^2) / (R^3 r^2)],  x = r/R_mu.
+ * Near the centre (x < 1/2) g / r^3 and the bracket are evaluated from the
+ * Taylor series of erf and exp (the differences cancel there):
+ *   g / x^3 = (2/sqrt(pi)) sum_{k>=1} (-1)^{k+1} (2k / (2k+1)) x^{2k-2} / k!
+ *   [3 g / x^3 - (4/sqrt(pi)) e^{-x^2}] / x^2 = (2/sqrt(pi)) sum_{k>=2} (-1)^k 4 x^{2k-4} / ((2k+1) (k-2)!)
+ * At r = 0 the potential takes its limit 2 q / (sqrt(pi) R) and the series
+ * their value at x = 0.  Atomic units: bohr, e, Hartree / (e bohr). */
+
+/* g(r; R) / r^3 and [3 g / r^5 - (4/sqrt(pi)) exp(-x^2) / (R^3 r^2)], x = r/R. */
+static void probe_radial(double r, double rr, double* g_r3, double* brk)
+{
+    double x = r / rr;
+    if (x < 0.5) {
+        double s1 = 0.0, s2 = 0.0, fact = 1.0;
+        /* k-th terms: x^{2k-2} / k! for the first, x^{2k-4} / (k-2)! for the second */
+        for (int k = 1; k <= 20; ++k) {
+            fact *= k;                                  /* k! */
+            double xp = pow(x, 2.0 * k - 2.0);
+            double sgn = (k % 2 == 1) ? 1.0 : -1.0;     /* (-1)^{k+1} */
+            s1 += sgn * (2.0 * k / (2.0 * k + 1.0)) * xp / fact;
+            if (k >= 2) {
+                double f2 = 1.0;
+                for (int t = 2; t <= k - 2; ++t) f2 *= t;   /* (k-2)! */
+                s2 += (-sgn) * 4.0 * pow(x, 2.0 * k - 4.0) / ((2.0 * k + 1.0) * f2);
+            }
+        }
+        double c = 2.0 / sqrt(PI);
+        *g_r3 = c * s1 / (rr * rr * rr);
+        *brk = c * s2 / (rr * rr * rr * rr * rr);
+        return;
+    }
+    double g = gfun(r, rr);
+    *g_r3 = g / (r * r * r);
+    *brk = 3.0 * g / (r * r * r * r * r) - 4.0 / sqrt(PI) * exp(-x * x) / (rr * rr * rr * r * r);
+}
+
+/* q: [n] complex charges; mu: [3n] complex dipoles, component-major (model 1
+ * only; NULL otherwise); points pts_ang [npts][3] in Angstrom.  Outputs (any
+ * may be NULL): phi [npts] complex, field [npts][3] complex, rho [npts]
+ * complex (interleaved re, im). */
+void or_probe(int model, int64_t n, const double* xyz_ang, const double* p, const double* q, const double* mu,
+              int64_t npts, const double* pts_ang, double* phi, double* field, double* rho)
+{
+    material m = unpack(p);
+    double* xyz = (double*)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    to_bohr(n, xyz_ang, xyz);
+    const double c = 2.0 / sqrt(PI);
+    for (int64_t t = 0; t < npts; ++t) {
+        double pt[3];
+        for (int a = 0; a < 3; ++a) pt[a] = pts_ang[3 * t + a] / ANG_PER_BOHR;
+        double ph[2] = {0, 0}, e[3][2] = {{0, 0}, {0, 0}, {0, 0}}, de[2] = {0, 0};
+        for (int64_t i = 0; i < n; ++i) {
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = pt[a] - xyz[3 * i + a];
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            /* charge */
+            double rq = m.r_q;
+            double gq, bq;
+            probe_radial(r, rq, &gq, &bq);
+            double pot = r > 0.0 ? erf(r / rq) / r : c / rq;
+            double dens = exp(-(r / rq) * (r / rq)) / (pow(PI, 1.5) * rq * rq * rq);
+            for (int s = 0; s < 2; ++s) {
+                double qs = q[2 * i + s];
+                ph[s] += qs * pot;
+                de[s] += qs * dens;
+                for (int a = 0; a < 3; ++a) e[a][s] += qs * gq * d[a];
+            }
+            if (model == 1 && mu) {
+                double rm = m.r_mu;
+                double gm, bm;
+                probe_radial(r, rm, &gm, &bm);
+                double gauss = exp(-(r / rm) * (r / rm)) / (pow(PI, 1.5) * rm * rm * rm);
+                for (int s = 0; s < 2; ++s) {
+                    double mv[3], md = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        mv[a] = mu[2 * (a * n + i) + s];
+                        md += mv[a] * d[a];
+                    }
+                    ph[s] += md * gm;
+                    de[s] += 2.0 / (rm * rm) * md * gauss;
+                    for (int a = 0; a < 3; ++a) e[a][s] += -mv[a] * gm + md * d[a] * bm;
+                }
+            }
+        }
+        for (int s = 0; s < 2; ++s) {
+            if (phi) phi[2 * t + s] = ph[s];
+            if (rho) rho[2 * t + s] = de[s];
+            if (field)
+                for (int a = 0; a < 3; ++a) field[2 * (3 * t + a) + s] = e[a][s];
+        }
+    }
+    free(xyz);
 }

@@ -526,3 +526,111 @@ def test_alloy_plasmon_red_shifts_and_weakens_with_gold_fraction():
         heights.append(out["sigma"][i])
     assert peaks[0] > peaks[1] > peaks[2]
     assert heights[0] > heights[1] > heights[2]
+
+
+# ------------------------------------------------ probe fields (post-processing)
+
+def _probe_case(model, n=6, seed=3):
+    """A few atoms with seeded complex charges (and dipoles)."""
+    rng = np.random.default_rng(seed)
+    xyz = G.fcc_sphere_n(n)
+    q = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    mu = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n)) if model == 1 else None
+    return xyz, pv(AU if model else AG), q, mu
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_probe_field_is_minus_gradient_of_potential(model):
+    """E = -grad phi by central differences, at points in the Taylor-series
+    region of an atom (x < 1/2), at moderate and at large distance."""
+    xyz, p, q, mu = _probe_case(model)
+    pts = np.array([xyz[0] + [0.3, -0.2, 0.25], xyz[1] + [0.05, 0.02, -0.04], xyz[2] + [1.7, 0.9, -1.1],
+                    [6.0, -4.0, 3.0], [30.0, 12.0, -20.0]])
+    r = O.probe(model, xyz, p, q, mu, pts)
+    h = 1e-4   # Angstrom
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fp = O.probe(model, xyz, p, q, mu, pts + e)["phi"]
+        fm = O.probe(model, xyz, p, q, mu, pts - e)["phi"]
+        grad = (fp - fm) / (2 * h / BOHR)
+        assert np.allclose(-grad, r["field"][:, a], rtol=1e-6, atol=1e-8 * np.abs(r["field"]).max())
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_probe_gauss_law(model):
+    """div E = 4 pi rho (atomic units), by central differences of the field
+    at points inside the atoms' Gaussians."""
+    xyz, p, q, mu = _probe_case(model)
+    pts = np.array([xyz[0] + [0.4, 0.1, -0.3], xyz[3] + [-0.2, 0.6, 0.1], xyz[5] + [0.05, -0.05, 0.1]])
+    h = 2e-3   # Angstrom
+    div = np.zeros(len(pts), dtype=complex)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        div += (O.probe(model, xyz, p, q, mu, pts + e)["field"][:, a] -
+                O.probe(model, xyz, p, q, mu, pts - e)["field"][:, a]) / (2 * h / BOHR)
+    rho = O.probe(model, xyz, p, q, mu, pts)["rho"]
+    assert np.allclose(div, 4 * np.pi * rho, rtol=1e-5, atol=1e-7 * np.abs(rho).max())
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_probe_density_moments(model):
+    """The density integrates to the total charge and its first moment to
+    sum q_i r_i + sum mu_i (midpoint rule on a fine grid, spectrally accurate
+    for Gaussians)."""
+    xyz, p, q, mu = _probe_case(model, n=3)
+    lo, hi = xyz.min(0) - 6.0, xyz.max(0) + 6.0
+    hstep = 0.12
+    axes = [np.arange(lo[a], hi[a], hstep) + hstep / 2 for a in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    rho = O.probe(model, xyz, p, q, mu, pts)["rho"]
+    dv = (hstep / BOHR) ** 3
+    assert abs(rho.sum() * dv - q.sum()) <= 1e-8 * np.abs(q).sum()
+    dip = (rho[:, None] * (pts / BOHR)).sum(0) * dv
+    ref = (q[None, :] * (xyz.T / BOHR)).sum(1)
+    if model == 1:
+        ref = ref + mu.sum(1)
+    assert np.allclose(dip, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_probe_far_field_is_point_multipoles(model):
+    """Far from the atoms the Gaussians act as point charges and point
+    dipoles: phi = q / r + mu . d / r^3 and E = q d / r^3 + (3 (mu . d) d / r^2 - mu) / r^3."""
+    xyz, p, q, mu = _probe_case(model)
+    pts = np.array([[80.0, 10.0, -30.0], [-50.0, 60.0, 45.0]])
+    r = O.probe(model, xyz, p, q, mu, pts)
+    for t, pt in enumerate(pts / BOHR):
+        d = pt[None, :] - xyz / BOHR
+        rr = np.linalg.norm(d, axis=1)
+        phi = (q / rr).sum()
+        e = (q[:, None] * d / rr[:, None] ** 3).sum(0)
+        if model == 1:
+            md = (mu.T * d).sum(1)
+            phi += (md / rr ** 3).sum()
+            e += ((3 * md[:, None] * d / rr[:, None] ** 2 - mu.T) / rr[:, None] ** 3).sum(0)
+        assert abs(r["phi"][t] - phi) <= 1e-13 * np.abs(q).sum()
+        assert np.allclose(r["field"][t], e, rtol=1e-12, atol=1e-15)
+        assert abs(r["rho"][t]) < 1e-300
+
+
+def test_probe_at_an_atom_centre_and_series_boundary():
+    """At a charge's own centre: zero field, potential 2 q / (sqrt(pi) R_q),
+    density q / (pi^1.5 R_q^3); the series (x < 1/2) and the closed form agree
+    across x = 1/2 for a charge and a dipole."""
+    p = pv(AU)
+    rq, rmu = M.load("au_wfqfmu")["r_q_bohr"], M.load("au_wfqfmu")["r_mu_bohr"]
+    xyz = np.zeros((1, 3))
+    r = O.probe(0, xyz, p, np.array([1.0 + 0.5j]), None, xyz)
+    assert abs(r["field"]).max() == 0.0
+    assert abs(r["phi"][0] - (1 + 0.5j) * 2 / (np.sqrt(np.pi) * rq)) < 1e-15
+    assert abs(r["rho"][0] - (1 + 0.5j) / (np.pi ** 1.5 * rq ** 3)) < 1e-15
+    for R, model, mu in ((rq, 0, None), (rmu, 1, np.array([[0.3], [-0.7], [0.4]], dtype=complex))):
+        d = np.array([0.6, -0.3, 0.2])
+        d = d / np.linalg.norm(d)
+        x = 0.5 * R * BOHR
+        lo = O.probe(model, xyz, p, np.array([0.8]), mu, (x * (1 - 1e-9)) * d[None, :])["field"]
+        hi = O.probe(model, xyz, p, np.array([0.8]), mu, (x * (1 + 1e-9)) * d[None, :])["field"]
+        assert np.allclose(lo, hi, rtol=1e-8)
