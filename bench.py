@@ -395,6 +395,89 @@ def alloy_extra(pxm, step_ev=0.01, fp64_fracs=(0.5,)):
     return out
 
 
+# FP64 arithmetic per (point, atom) pair of the probe kernel's point-source
+# path: the differences (3), r^2 (5), the reciprocal square root estimate, its
+# Newton step and the halving (6), r^-2 and r^-3 (2), the charge's two parts
+# times r^-3 (2) and six fused multiply-adds into the complex field (12); a
+# dipole adds 3 r^-5 (2), mu . d r^-5 for both parts (12) and twelve fused
+# multiply-adds (24).
+PROBE_PAIR_FLOP = {0: 30, 1: 68}
+
+
+def probe_roofline(st, model):
+    fl = PROBE_PAIR_FLOP[model] * st["pairs"]
+    ach = fl / (st["ms_kernel"] * 1e-3) / 1e12 if st["ms_kernel"] > 0 else 0.0
+    return dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), kernel="k_probe (+ k_probe_sum)",
+                flop_note=f"{PROBE_PAIR_FLOP[model]} FP64 FLOP per (point, atom) pair of the point-source path; "
+                          "pairs within 7 Gaussian widths cost more and count the same")
+
+
+def probe_extra(pxm):
+    """Post-processing: the induced density and field of the plasmon resonance.
+    The paper's example (an Au dimer of 1122 atoms with a 5 A gap along x,
+    omegaFQFmu, 2.28 eV, x polarization: density on a CUBE grid and the field in
+    the xy plane) with a synthetic fcc dimer, and the 20,000-atom Ag sphere
+    (omegaFQ, 3.6 eV) on a 128^3 grid; the probe kernel times come from HIP
+    events around its launches."""
+    from workloads import configs as C
+    from workloads import geometry as G
+    from workloads import materials as M
+    out = {}
+    au = M.load("au_wfqfmu")
+    xyz = G.gap_dimer(1122, 5.0)
+    s = pxm.Structure(1, xyz, au, pxm.default_stream())
+    om = np.array([2.28])
+    s.set_frequencies(om, 0b001, 1e-4, M.interband_alpha(au, om))
+    s.solve(precision=pxm.PX_MIXED, rel_tol=1e-8)
+    lo, hi = xyz.min(0) - 4.0, xyz.max(0) + 4.0
+    ax = [np.linspace(lo[a], hi[a], 80) for a in range(3)]
+    X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    cube = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    t0 = time.perf_counter()
+    _, rho = s.induced_field(0, 0, cube)
+    t_cube = time.perf_counter() - t0
+    st_cube = s.probe_stats()
+    px_ = np.linspace(lo[0], hi[0], 400)
+    py_ = np.linspace(lo[1], hi[1], 400)
+    PX, PY = np.meshgrid(px_, py_, indexing="ij")
+    plane = np.stack([PX.ravel(), PY.ravel(), np.full(PX.size, xyz[:, 2].mean())], 1)
+    t0 = time.perf_counter()
+    f, _ = s.induced_field(0, 0, plane)
+    t_plane = time.perf_counter() - t0
+    st_plane = s.probe_stats()
+    e0 = 1e-4
+    enh = np.sqrt((np.abs(f[:, 0] + e0) ** 2 + np.abs(f[:, 1]) ** 2 + np.abs(f[:, 2]) ** 2)) / e0
+    gap_pt = np.argmin(np.linalg.norm(plane[:, :2] - xyz[:, :2].mean(0), axis=1))
+    s.close()
+    out["au_dimer_1122_wfqfmu"] = dict(
+        cube_points=len(cube), cube_seconds=round(t_cube, 4), cube_kernel_ms=round(st_cube["ms_kernel"], 3),
+        plane_points=len(plane), plane_seconds=round(t_plane, 4), plane_kernel_ms=round(st_plane["ms_kernel"], 3),
+        max_field_enhancement=round(float(enh.max()), 1), gap_centre_enhancement=round(float(enh[gap_pt]), 1),
+        roofline=probe_roofline(st_plane, 1))
+    case = C.sphere_20k()
+    s = pxm.Structure(0, case["xyz"], case["params"], pxm.default_stream())
+    s.set_frequencies(np.array([3.6]), 0b001, case["e0"])
+    s.solve(precision=pxm.PX_MIXED, rel_tol=1e-8)
+    xyz = case["xyz"]
+    lo, hi = xyz.min(0) - 5.0, xyz.max(0) + 5.0
+    ax = [np.linspace(lo[a], hi[a], 128) for a in range(3)]
+    X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    grid = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    s.induced_field(0, 0, grid[:65536])   # warm-up
+    t0 = time.perf_counter()
+    s.induced_field(0, 0, grid)
+    t_grid = time.perf_counter() - t0
+    st = s.probe_stats()
+    s.close()
+    out["ag_sphere_20000_wfq_grid128"] = dict(
+        points=len(grid), seconds=round(t_grid, 3), kernel_ms=round(st["ms_kernel"], 2),
+        points_per_s=round(len(grid) / (st["ms_kernel"] * 1e-3), 1),
+        pair_evaluations_per_s=round(st["pairs"] / (st["ms_kernel"] * 1e-3), 1), roofline=probe_roofline(st, 0),
+        note="seconds include the host conversion of the points and the copies; kernel_ms the probe kernels")
+    return out
+
+
 def torch_free_bytes():
     import torch
     free, total = torch.cuda.mem_get_info()
@@ -634,6 +717,8 @@ def main():
         extra["serving"] = serving_extra(pxm, 16, 1000, 4000, 5, 0.75)
         log("[bench] alloy series extra ...")
         extra["alloys"] = alloy_extra(pxm)
+        log("[bench] induced field extra ...")
+        extra["induced_field"] = probe_extra(pxm)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -10,6 +10,8 @@
  *                         (frequency, polarization) column by blocked GMRES
  *                         (Section 6, "iterative on the fly")
  *   pxGetCharges / pxGetSpectrum / pxGetSolveStats -> results (Section 7)
+ *   pxInducedField / pxProbeField -> induced field and density at probe points
+ *                         (Section "Post-process Analysis")
  *   pxDestroyStructure
  *
  * Conventions
@@ -335,6 +337,39 @@ pxStatus pxGetWork(pxStructure s, double* work3);
  * their algorithmic FLOP inside cycles (2 N_u^2 per real column of a column
  * that was still iterating). */
 pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double* flop4);
+
+/* Post-processing (Section "Post-process Analysis"): the electric field and
+ * the charge density of induced charges (and, for PX_WFQFMU, dipoles) at
+ * probe points, for CUBE grids and plane maps.  The charges are the model's
+ * Gaussians (Section 2): a charge q at r_i contributes the density
+ * q exp(-r^2/R_q^2) / (pi^{3/2} R_q^3) and the field q g(r) d / r^3, with
+ * d = p - r_i, r = |d|, g(r) = erf(r/R_q) - (2/sqrt(pi)) (r/R_q)
+ * exp(-(r/R_q)^2); a dipole mu (width R_mu) the density -mu . grad of its
+ * Gaussian and the field -grad [mu . d g(r; R_mu) / r^3].  Points may lie
+ * anywhere, atom centres included.
+ *   pxInducedField: the sources of the solved column (i_omega, pol) of s
+ *     (after pxSolveSpectrum; the field per E0 of pxSetFrequencies).
+ *   pxProbeField: caller-given sources on s's atoms, caller's atom order:
+ *     q [n_atoms] complex; mu [3 n_atoms] complex, component-major
+ *     ([mu_x | mu_y | mu_z], the layout of pxGetCharges), PX_WFQFMU only
+ *     (NULL there leaves the dipoles out; must be NULL for PX_WFQ).
+ * pts_ang: [npts][3] host, Angstrom.  field (may be NULL): [npts][3] complex
+ * (E_x, E_y, E_z), Hartree / (e bohr); density (may be NULL): [npts] complex,
+ * e / bohr^3.  The work is npts x n_atoms pair evaluations; points in spatial
+ * order (grid lines, planes) run fastest.  Device buffers for the points and
+ * results are allocated and released inside the call (points in batches of
+ * 2^20); synchronises s's stream.  Errors: PX_E_INVALID (null s, pts with
+ * npts > 0 or q; npts < 0; a column outside the solved set; mu for PX_WFQ),
+ * PX_E_STATE (pxInducedField before a solve), PX_E_OOM, PX_E_DEVICE. */
+pxStatus pxInducedField(pxStructure s, int32_t i_omega, int32_t pol, int64_t npts, const double* pts_ang,
+                        double* field, double* density);
+pxStatus pxProbeField(pxStructure s, const double* q, const double* mu, int64_t npts, const double* pts_ang,
+                      double* field, double* density);
+
+/* The last pxInducedField / pxProbeField call of s: out2[0] HIP-event
+ * milliseconds of its probe kernels (the field and density sums, without the
+ * copies), out2[1] its pair evaluations (npts x n_atoms). */
+pxStatus pxGetProbeStats(pxStructure s, double* out2);
 
 void pxDestroyStructure(pxStructure s);
 

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV",
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHetero", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
-            "pxServerQuery", "pxServerDestroy"]
+            "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats"]
 
 
 class PxError(RuntimeError):
@@ -89,6 +89,9 @@ def load(path: str = LIB_PATH):
     lib.pxGetTimings.argtypes = [_vp, _dp, ctypes.POINTER(i64)]
     lib.pxGetWork.argtypes = [_vp, _dp]
     lib.pxGetTApplyStats.argtypes = [_vp, ctypes.POINTER(i64), _dp, _dp]
+    lib.pxInducedField.argtypes = [_vp, i32, i32, i64, _dp, _dp, _dp]
+    lib.pxProbeField.argtypes = [_vp, _dp, _dp, i64, _dp, _dp, _dp]
+    lib.pxGetProbeStats.argtypes = [_vp, _dp]
     lib.pxServerCreate.argtypes = [ctypes.c_double, ctypes.POINTER(pxSolveOptions), _vp, ctypes.POINTER(_vp)]
     lib.pxServerSubmit.argtypes = [_vp, _vp]
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
@@ -198,6 +201,39 @@ def pxGetCharges(h, i_omega, pol, with_dipoles=False):
     _check(load().pxGetCharges(h, int(i_omega), int(pol), _ptr(q.view(np.float64)),
                                None if mu is None else _ptr(mu.view(np.float64))))
     return (q, mu) if with_dipoles else q
+
+
+def _probe_out(pts):
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    field = np.zeros((len(pts), 3), dtype=np.complex128)
+    rho = np.zeros(len(pts), dtype=np.complex128)
+    return pts, field, rho
+
+
+def pxInducedField(h, i_omega, pol, pts):
+    """Field [npts, 3] and density [npts] (complex, atomic units) of the solved
+    column (i_omega, pol) at points pts [npts, 3] (Angstrom)."""
+    pts, field, rho = _probe_out(pts)
+    _check(load().pxInducedField(h, int(i_omega), int(pol), len(pts), _ptr(pts), _ptr(field.view(np.float64)),
+                                 _ptr(rho.view(np.float64))))
+    return field, rho
+
+
+def pxProbeField(h, q, mu, pts):
+    """Field and density of caller-given charges q [n] (and dipoles mu [3, n])
+    on the structure's atoms (caller's atom order) at points pts (Angstrom)."""
+    pts, field, rho = _probe_out(pts)
+    q = np.ascontiguousarray(q, dtype=np.complex128).ravel()
+    mu_a = None if mu is None else np.ascontiguousarray(mu, dtype=np.complex128).ravel()
+    _check(load().pxProbeField(h, _ptr(q.view(np.float64)), None if mu_a is None else _ptr(mu_a.view(np.float64)),
+                               len(pts), _ptr(pts), _ptr(field.view(np.float64)), _ptr(rho.view(np.float64))))
+    return field, rho
+
+
+def pxGetProbeStats(h):
+    out = np.zeros(2)
+    _check(load().pxGetProbeStats(h, _ptr(out)))
+    return dict(ms_kernel=out[0], pairs=out[1])
 
 
 def pxGetSpectrum(h, n_omega):
@@ -393,6 +429,15 @@ class Structure:
 
     def stats(self):
         return pxGetSolveStats(self.h, self.ncol)
+
+    def induced_field(self, i_omega, pol, pts):
+        return pxInducedField(self.h, i_omega, pol, pts)
+
+    def probe_field(self, q, mu, pts):
+        return pxProbeField(self.h, q, mu, pts)
+
+    def probe_stats(self):
+        return pxGetProbeStats(self.h)
 
     def apply(self, precision, omega_ev, x, alpha_ib=None):
         return pxApplyOperator(self.h, precision, omega_ev, x, alpha_ib, self.het)

@@ -1284,6 +1284,121 @@ pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, do
     });
 }
 
+// ---- post-processing: field and density at probe points --------------------
+
+namespace {
+
+// Field and density at npts points (Angstrom, host) from the per-atom sources
+// src (device, Morton order, np x 2 or np x 8), in batches of 2^20 points.
+pxStatus probe_run(pxStructure_t* s, const double* src, int64_t npts, const double* pts_ang, double* field,
+                   double* density)
+{
+    constexpr int64_t kBatch = int64_t(1) << 20;
+    s->probe[0] = 0.0;
+    s->probe[1] = (double)npts * (double)s->g.n;
+    if (npts == 0) return PX_OK;
+    const int64_t nb0 = std::min(npts, kBatch);
+    const int64_t npad0 = (nb0 + 255) / 256 * 256;
+    Scratch sc;
+    double4* pts = sc.get<double4>((size_t)npad0);
+    // split counts differ between a full batch and the last one
+    const int64_t nlast = npts - (npts - 1) / kBatch * kBatch;
+    const size_t nparts = std::max(px::probe_part_doubles(s->g, npad0),
+                                   px::probe_part_doubles(s->g, (nlast + 255) / 256 * 256));
+    double* part = sc.get<double>(nparts);
+    double* f_d = sc.get<double>((size_t)nb0 * 6);
+    double* r_d = sc.get<double>((size_t)nb0 * 2);
+    std::vector<double4> ph((size_t)npad0);
+    std::vector<double> fh((size_t)nb0 * 6), rh((size_t)nb0 * 2);
+    hipEvent_t ev[2];
+    HC(hipEventCreate(&ev[0]));
+    HC(hipEventCreate(&ev[1]));
+    const double ang = ANG_PER_BOHR;
+    for (int64_t b0 = 0; b0 < npts; b0 += kBatch) {
+        const int64_t nb = std::min(kBatch, npts - b0);
+        const int64_t npad = (nb + 255) / 256 * 256;
+        for (int64_t t = 0; t < npad; ++t) {
+            const double* p = pts_ang + 3 * (b0 + std::min(t, nb - 1));
+            ph[(size_t)t] = make_double4(p[0] / ang, p[1] / ang, p[2] / ang, 0.0);
+        }
+        HC(hipMemcpyAsync(pts, ph.data(), sizeof(double4) * npad, hipMemcpyHostToDevice, s->st));
+        HC(hipEventRecord(ev[0], s->st));
+        px::probe_field(s->g, src, pts, nb, npad, part, f_d, r_d, s->st);
+        HC(hipEventRecord(ev[1], s->st));
+        HC(hipGetLastError());
+        HC(hipMemcpyAsync(fh.data(), f_d, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, s->st));
+        HC(hipMemcpyAsync(rh.data(), r_d, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s->st));
+        HC(hipStreamSynchronize(s->st));
+        float ms = 0.f;
+        HC(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        s->probe[0] += ms;
+        if (field) std::copy(fh.begin(), fh.begin() + 6 * nb, field + 6 * b0);
+        if (density) std::copy(rh.begin(), rh.begin() + 2 * nb, density + 2 * b0);
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return PX_OK;
+}
+
+}  // namespace
+
+pxStatus pxInducedField(pxStructure s, int32_t i_omega, int32_t pol, int64_t npts, const double* pts_ang,
+                        double* field, double* density)
+{
+    g_err.clear();
+    if (!s || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxInducedField: invalid argument");
+    if (!s->solved) return fail(PX_E_STATE, "pxInducedField: no solved spectrum");
+    if (i_omega < 0 || i_omega >= s->n_omega || pol < 0 || pol > 2 || !(s->pol_mask & (1u << pol)))
+        return fail(PX_E_INVALID, "pxInducedField: column not in the solved set");
+    int p = 0;
+    for (int l = 0; l < pol; ++l)
+        if (s->pol_mask & (1u << l)) ++p;
+    const int col = i_omega * s->npol + p;
+    return guarded([&]() -> pxStatus {
+        Scratch sc;
+        const int S = s->model == PX_WFQFMU ? 8 : 2;
+        double* src = sc.get<double>((size_t)S * s->g.np);
+        px::probe_sources(s->g, s->x, s->ldg, col, src, s->st);
+        return probe_run(s, src, npts, pts_ang, field, density);
+    });
+}
+
+pxStatus pxProbeField(pxStructure s, const double* q, const double* mu, int64_t npts, const double* pts_ang,
+                      double* field, double* density)
+{
+    g_err.clear();
+    if (!s || !q || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxProbeField: invalid argument");
+    if (mu && s->model != PX_WFQFMU) return fail(PX_E_INVALID, "pxProbeField: dipoles given for an omegaFQ structure");
+    return guarded([&]() -> pxStatus {
+        const int S = s->model == PX_WFQFMU ? 8 : 2;
+        const int64_t n = s->g.n, np = s->g.np;
+        std::vector<double> h((size_t)S * np, 0.0);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t o = s->perm[(size_t)i];
+            h[(size_t)S * i] = q[2 * o];
+            h[(size_t)S * i + 1] = q[2 * o + 1];
+            if (mu)
+                for (int a = 0; a < 3; ++a) {
+                    h[(size_t)S * i + 2 + 2 * a] = mu[2 * (a * n + o)];
+                    h[(size_t)S * i + 3 + 2 * a] = mu[2 * (a * n + o) + 1];
+                }
+        }
+        Scratch sc;
+        double* src = sc.get<double>((size_t)S * np);
+        HC(hipMemcpyAsync(src, h.data(), sizeof(double) * S * np, hipMemcpyHostToDevice, s->st));
+        return probe_run(s, src, npts, pts_ang, field, density);
+    });
+}
+
+pxStatus pxGetProbeStats(pxStructure s, double* out2)
+{
+    g_err.clear();
+    if (!s || !out2) return fail(PX_E_INVALID, "null argument");
+    out2[0] = s->probe[0];
+    out2[1] = s->probe[1];
+    return PX_OK;
+}
+
 pxStatus pxGetSpectrum(pxStructure s, double* alpha, double* sigma_abs)
 {
     g_err.clear();

@@ -224,6 +224,17 @@ void normalize_seg(const double2* w, const double* nrm, const int32_t* done, con
 void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int32_t* steps, const int32_t* chunk_seg,
                   double2* x, int Bc, int nseg, int64_t rows, hipStream_t st);
 
+// ---- post-processing: field and density at probe points (px_probe.hip) ------
+// Sources of one column (charge, and for the dipole model the dipole, per atom
+// in Morton order; np x 2 or np x 8 doubles) from the solution x.
+void probe_sources(const Geometry& g, const double2* x, int ldx, int col, double* src, hipStream_t st);
+// Partial-sum scratch (doubles) for npad points (a multiple of 256).
+size_t probe_part_doubles(const Geometry& g, int64_t npad);
+// field [npts][3] complex and rho [npts] complex at pts [npad] (bohr, the
+// points past npts copies of a real one).
+void probe_field(const Geometry& g, const double* src, const double4* pts, int64_t npts, int64_t npad, double* part,
+                 double* field, double* rho, hipStream_t st);
+
 // ---- shared-Krylov solve (px_shifted.hip) ----------------------------------
 // R = npol real slots per row (1..3), one per polarization; Hbar row-major per
 // slot with row stride kcap; see px_shifted.hip.

@@ -309,6 +309,7 @@ struct pxStructure_t {
     int64_t tstats[4] = {0, 0, 0, 0};   // FP32 on the fly, FP32 stored, FP64 on the fly, FP64 stored
     double tms[4] = {0, 0, 0, 0};       // their HIP-event milliseconds inside cycles (options.timings)
     double tflop[4] = {0, 0, 0, 0};     // their algorithmic FLOP inside cycles
+    double probe[2] = {0, 0};           // last probe call: kernel milliseconds, pair evaluations
 
     ~pxStructure_t()
     {

@@ -133,3 +133,10 @@ def test_invalid_two_type_inputs_rejected_on_host(lib, case):
     assert st == px.PX_E_INVALID
     assert h.value is None
     assert len(px.pxLastError()) > 0
+
+
+def test_probe_rejections_on_host(lib):
+    """Invalid probe calls fail on the host before any GPU work."""
+    assert lib.pxInducedField(None, 0, 0, 0, None, None, None) == px.PX_E_INVALID
+    assert lib.pxProbeField(None, None, None, 0, None, None, None) == px.PX_E_INVALID
+    assert lib.pxGetProbeStats(None, None) == px.PX_E_INVALID
