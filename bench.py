@@ -501,9 +501,10 @@ def main():
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
     ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "batch-full", "serving-full", "alloys"],
+                    choices=["sphere", "batch-full", "serving-full", "alloys", "probe"],
                     help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
-                         "serving mix, printed as their own JSON lines")
+                         "serving mix, alloys: the Ag-Au series, probe: the induced-field evaluation, "
+                         "printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked mixed-precision comparison step")
     ap.add_argument("--no-shifted", action="store_true",
@@ -546,6 +547,9 @@ def main():
         print(json.dumps({"workload": "graphene_batch_64", "fp64_per_structure_s": round(t64, 2),
                           "fp64_per_structure_solves_per_s": round(cols / t64, 2),
                           "speedup": round(t64 / rb["seconds"], 2), "sigma_rel_err_vs_fp64": err}), flush=True)
+        return
+    if args.workload == "probe":
+        print(json.dumps({"workload": "induced_field", **probe_extra(pxm)}), flush=True)
         return
     if args.workload == "alloys":
         print(json.dumps({"workload": "agau_alloys_1289", **alloy_extra(pxm, fp64_fracs=(0.0, 0.5, 1.0))}),
