@@ -134,26 +134,34 @@ __global__ __launch_bounds__(256) void k_ms_dots(const double* __restrict__ V, i
     double acc[MJ * W];
 #pragma unroll
     for (int c = 0; c < MJ * W; ++c) acc[c] = 0.0;
+    // the block's vectors (u itself for j = k, and in place of the missing
+    // ones of a short last group, whose sums are not written): chosen once, so
+    // that the row loop has no branch and its loads overlap across rows
+    const double* xp[MJ];
+#pragma unroll
+    for (int jj = 0; jj < MJ; ++jj) {
+        const int j = j0 + jj;
+        xp[jj] = (jj < nj && j < k) ? V + (size_t)j * vstride : u;
+    }
+#pragma unroll 2
     for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
-        double uu[R], ww[R];
+        double uu[R], ww[R], xx[MJ][R];
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             uu[c] = u[(size_t)r * R + c];
             ww[c] = wt[(size_t)r * R + c];
         }
 #pragma unroll
-        for (int jj = 0; jj < MJ; ++jj) {
-            if (jj < nj) {
-                const int j = j0 + jj;
-                const double* xj = V + (size_t)(j < k ? j : 0) * vstride + (size_t)r * R;
+        for (int jj = 0; jj < MJ; ++jj)
 #pragma unroll
-                for (int c = 0; c < R; ++c) {
-                    const double x = j < k ? xj[c] : uu[c];
-                    acc[jj * W + c] = fma(x, uu[c], acc[jj * W + c]);
-                    acc[jj * W + R + c] = fma(x, ww[c], acc[jj * W + R + c]);
-                }
+            for (int c = 0; c < R; ++c) xx[jj][c] = xp[jj][(size_t)r * R + c];
+#pragma unroll
+        for (int jj = 0; jj < MJ; ++jj)
+#pragma unroll
+            for (int c = 0; c < R; ++c) {
+                acc[jj * W + c] = fma(xx[jj][c], uu[c], acc[jj * W + c]);
+                acc[jj * W + R + c] = fma(xx[jj][c], ww[c], acc[jj * W + R + c]);
             }
-        }
     }
     block_sum<MJ * W>(acc, lds);
     if (threadIdx.x == 0)
