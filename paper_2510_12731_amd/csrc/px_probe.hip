@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_probe(const double4* __restrict__ xyz, 
         const int j0 = uniform_i(gq * GROUP);
         if (uniform_i(nbr::box_gap2(blo, bhi, glo[gq], ghi[gq]) >= k.near2)) {
             // point charges (and point dipoles)
-#pragma unroll 2
+#pragma unroll 8
             for (int jj = 0; jj < GROUP; ++jj) {
                 const double4 a = xyz[j0 + jj];
                 const double* s = src + (size_t)(j0 + jj) * S;
