@@ -358,8 +358,11 @@ pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double
  * e / bohr^3.  The work is npts x n_atoms pair evaluations; points in spatial
  * order (grid lines, planes) run fastest.  Device buffers for the points and
  * results are allocated and released inside the call (points in batches of
- * 2^20); synchronises s's stream.  Errors: PX_E_INVALID (null s, pts with
- * npts > 0 or q; npts < 0; a column outside the solved set; mu for PX_WFQ),
+ * 2^20; for 4096 atoms or more each batch is evaluated in Morton order and
+ * returned in the caller's order);
+ * synchronises s's stream.  Errors: PX_E_INVALID (null s, pts with npts > 0
+ * or q; npts < 0; a non-finite point; a column outside the solved set; mu for
+ * PX_WFQ),
  * PX_E_STATE (pxInducedField before a solve), PX_E_OOM, PX_E_DEVICE. */
 pxStatus pxInducedField(pxStructure s, int32_t i_omega, int32_t pol, int64_t npts, const double* pts_ang,
                         double* field, double* density);

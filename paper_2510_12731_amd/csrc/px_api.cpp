@@ -1297,18 +1297,18 @@ pxStatus probe_run(pxStructure_t* s, const double* src, int64_t npts, const doub
     s->probe[0] = 0.0;
     s->probe[1] = (double)npts * (double)s->g.n;
     if (npts == 0) return PX_OK;
+    for (int64_t t = 0; t < 3 * npts; ++t)
+        if (!std::isfinite(pts_ang[t])) return fail(PX_E_INVALID, "probe points must be finite");
     const int64_t nb0 = std::min(npts, kBatch);
-    const int64_t npad0 = (nb0 + 255) / 256 * 256;
-    Scratch sc;
-    double4* pts = sc.get<double4>((size_t)npad0);
     // split counts differ between a full batch and the last one
     const int64_t nlast = npts - (npts - 1) / kBatch * kBatch;
-    const size_t nparts = std::max(px::probe_part_doubles(s->g, npad0),
-                                   px::probe_part_doubles(s->g, (nlast + 255) / 256 * 256));
-    double* part = sc.get<double>(nparts);
+    Scratch sc;
+    double4* pts = sc.get<double4>((size_t)nb0);
+    double* part = sc.get<double>(std::max(px::probe_part_doubles(s->g, nb0), px::probe_part_doubles(s->g, nlast)));
+    void* order = sc.get<uint8_t>(px::probe_order_bytes(nb0));
     double* f_d = sc.get<double>((size_t)nb0 * 6);
     double* r_d = sc.get<double>((size_t)nb0 * 2);
-    std::vector<double4> ph((size_t)npad0);
+    std::vector<double4> ph((size_t)nb0);
     std::vector<double> fh((size_t)nb0 * 6), rh((size_t)nb0 * 2);
     hipEvent_t ev[2];
     HC(hipEventCreate(&ev[0]));
@@ -1316,14 +1316,19 @@ pxStatus probe_run(pxStructure_t* s, const double* src, int64_t npts, const doub
     const double ang = ANG_PER_BOHR;
     for (int64_t b0 = 0; b0 < npts; b0 += kBatch) {
         const int64_t nb = std::min(kBatch, npts - b0);
-        const int64_t npad = (nb + 255) / 256 * 256;
-        for (int64_t t = 0; t < npad; ++t) {
-            const double* p = pts_ang + 3 * (b0 + std::min(t, nb - 1));
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t t = 0; t < nb; ++t) {
+            const double* p = pts_ang + 3 * (b0 + t);
             ph[(size_t)t] = make_double4(p[0] / ang, p[1] / ang, p[2] / ang, 0.0);
+            const double v[3] = {ph[(size_t)t].x, ph[(size_t)t].y, ph[(size_t)t].z};
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], v[a]);
+                hi[a] = std::max(hi[a], v[a]);
+            }
         }
-        HC(hipMemcpyAsync(pts, ph.data(), sizeof(double4) * npad, hipMemcpyHostToDevice, s->st));
+        HC(hipMemcpyAsync(pts, ph.data(), sizeof(double4) * nb, hipMemcpyHostToDevice, s->st));
         HC(hipEventRecord(ev[0], s->st));
-        px::probe_field(s->g, src, pts, nb, npad, part, f_d, r_d, s->st);
+        px::probe_field(s->g, src, pts, nb, lo, hi, order, part, f_d, r_d, s->st);
         HC(hipEventRecord(ev[1], s->st));
         HC(hipGetLastError());
         HC(hipMemcpyAsync(fh.data(), f_d, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, s->st));

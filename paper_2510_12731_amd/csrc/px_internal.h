@@ -67,6 +67,8 @@ struct Geometry {
     double4* xyzc = nullptr;   // [np], built with the near-field list
 };
 
+// Ascending bitonic sort of npow (a power of two) 64-bit keys in place.
+void sort_keys(uint64_t* keys, int64_t npow, hipStream_t st);
 // Exclusive scan of cnt[0..n) into row_ptr[0..n] (one workgroup).
 void scan_counts(const int32_t* cnt, int64_t n, int32_t* row_ptr, hipStream_t st);
 // Builds g's FP64 near-field list for the omegaFQ narrow T-apply once
@@ -228,12 +230,17 @@ void x_update_seg(const double2* V, int64_t vstride, const double2* y, const int
 // Sources of one column (charge, and for the dipole model the dipole, per atom
 // in Morton order; np x 2 or np x 8 doubles) from the solution x.
 void probe_sources(const Geometry& g, const double2* x, int ldx, int col, double* src, hipStream_t st);
-// Partial-sum scratch (doubles) for npad points (a multiple of 256).
-size_t probe_part_doubles(const Geometry& g, int64_t npad);
-// field [npts][3] complex and rho [npts] complex at pts [npad] (bohr, the
-// points past npts copies of a real one).
-void probe_field(const Geometry& g, const double* src, const double4* pts, int64_t npts, int64_t npad, double* part,
-                 double* field, double* rho, hipStream_t st);
+// Partial-sum scratch (doubles) for npts points.
+size_t probe_part_doubles(const Geometry& g, int64_t npts);
+// Scratch of probe_field for npts points: keys (npow = the power of two >=
+// npad), sorted points (npad) and their order (npad), in bytes.
+size_t probe_order_bytes(int64_t npts);
+// field [npts][3] complex and rho [npts] complex at pts [npts] (bohr, w
+// unused), in the caller's order; lo/hi: the points' bounding box (bohr).  The
+// points are evaluated in Morton order (compact waves) and the results
+// scattered back.  order: probe_order_bytes(npts) bytes of scratch.
+void probe_field(const Geometry& g, const double* src, const double4* pts, int64_t npts, const double lo[3],
+                 const double hi[3], void* order, double* part, double* field, double* rho, hipStream_t st);
 
 // ---- shared-Krylov solve (px_shifted.hip) ----------------------------------
 // R = npol real slots per row (1..3), one per polarization; Hbar row-major per

@@ -1600,6 +1600,14 @@ void permute_in(const Geometry& g, const double2* in, int ncol, const int32_t* p
                        perm, x, ldx);
 }
 
+void sort_keys(uint64_t* keys, int64_t npow, hipStream_t st)
+{
+    for (uint32_t k = 2; k <= (uint32_t)npow; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, st, keys, j, k,
+                               (uint32_t)npow);
+}
+
 void scan_counts(const int32_t* cnt, int64_t n, int32_t* row_ptr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, n, row_ptr);

@@ -9,11 +9,14 @@
 // widths the Gaussian corrections are below FP64 rounding and a source acts
 // as a point charge or point dipole.
 //
-// One thread per probe point, the source atoms (Morton order) read
-// wave-uniform through the scalar cache; a group of 32 atoms whose bounding
-// box lies farther than 7 widths from the box of the wave's 64 points takes
-// the branch-free point path, the others the Gaussian formulas.  With few
-// points the atoms are split over blockIdx.y and k_probe_sum adds the splits.
+// For structures of 4096 atoms or more the points are sorted by their Morton
+// code first (so that a wave's 64 points are close together) and the results
+// scattered back.  One thread per
+// probe point, the source atoms (Morton order) read wave-uniform through the
+// scalar cache; a group of 32 atoms whose bounding box lies farther than 7
+// widths from the box of the wave's 64 points takes the branch-free point
+// path, the others the Gaussian formulas.  With few points the atoms are
+// split over blockIdx.y and k_probe_sum adds the splits.
 
 #include "px_internal.h"
 #include "px_neighbors.h"
@@ -213,10 +216,56 @@ __global__ __launch_bounds__(256) void k_probe(const double4* __restrict__ xyz, 
     out[7] = rho[1];
 }
 
-// field[t] = {E_x, E_y, E_z} complex (interleaved), rho[t] complex: the sum of
-// the splits for the first npts points.
+__device__ __forceinline__ uint32_t spread_bits10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// keys[t] = 30-bit Morton code of point t in the box (lo, lo + 1023 / sc)
+// above its index (morton = 0: the index alone, the caller's order); the
+// padding up to npow sorts last.
+__global__ void k_probe_keys(const double4* __restrict__ pts, int64_t npts, int64_t npow, double3 lo, double sc,
+                             int morton, uint64_t* __restrict__ keys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npow) return;
+    if (t >= npts) {
+        keys[t] = ~0ull;
+        return;
+    }
+    if (!morton) {
+        keys[t] = (uint64_t)t;
+        return;
+    }
+    const double4 p = pts[t];
+    const uint32_t qx = (uint32_t)fmin(1023.0, fmax(0.0, (p.x - lo.x) * sc));
+    const uint32_t qy = (uint32_t)fmin(1023.0, fmax(0.0, (p.y - lo.y) * sc));
+    const uint32_t qz = (uint32_t)fmin(1023.0, fmax(0.0, (p.z - lo.z) * sc));
+    const uint32_t code = spread_bits10(qx) | (spread_bits10(qy) << 1) | (spread_bits10(qz) << 2);
+    keys[t] = ((uint64_t)code << 32) | (uint64_t)t;
+}
+
+// Points in key order (padding: copies of the last real point) and their
+// original indices.
+__global__ void k_probe_order(const uint64_t* __restrict__ keys, const double4* __restrict__ pts, int64_t npts,
+                              int64_t npad, double4* __restrict__ spts, int32_t* __restrict__ order)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npad) return;
+    const int64_t s = t < npts ? (int64_t)(keys[t] & 0xffffffffull) : (int64_t)(keys[npts - 1] & 0xffffffffull);
+    spts[t] = pts[s];
+    order[t] = (int32_t)s;
+}
+
+// field[order[t]] = {E_x, E_y, E_z} complex (interleaved), rho[order[t]]
+// complex: the sum of the splits of sorted point t < npts.
 __global__ void k_probe_sum(const double* __restrict__ part, int nsplit, int64_t npad, int64_t npts,
-                            double* __restrict__ field, double* __restrict__ rho)
+                            const int32_t* __restrict__ order, double* __restrict__ field, double* __restrict__ rho)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npts) return;
@@ -224,13 +273,21 @@ __global__ void k_probe_sum(const double* __restrict__ part, int nsplit, int64_t
     for (int s = 0; s < nsplit; ++s)
 #pragma unroll
         for (int c = 0; c < 8; ++c) v[c] += part[((size_t)s * npad + t) * 8 + c];
+    const int64_t o = order[t];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        field[(size_t)t * 6 + 2 * a] = v[a];
-        field[(size_t)t * 6 + 2 * a + 1] = v[3 + a];
+        field[(size_t)o * 6 + 2 * a] = v[a];
+        field[(size_t)o * 6 + 2 * a + 1] = v[3 + a];
     }
-    rho[(size_t)t * 2] = v[6];
-    rho[(size_t)t * 2 + 1] = v[7];
+    rho[(size_t)o * 2] = v[6];
+    rho[(size_t)o * 2 + 1] = v[7];
+}
+
+int64_t pow2_at_least(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
 }
 
 }  // namespace
@@ -245,11 +302,37 @@ void probe_sources(const Geometry& g, const double2* x, int ldx, int col, double
                            g.np, src);
 }
 
-size_t probe_part_doubles(const Geometry& g, int64_t npad) { return (size_t)probe_splits(npad, g.np) * npad * 8; }
-
-void probe_field(const Geometry& g, const double* src, const double4* pts, int64_t npts, int64_t npad, double* part,
-                 double* field, double* rho, hipStream_t st)
+size_t probe_part_doubles(const Geometry& g, int64_t npts)
 {
+    const int64_t npad = (npts + 255) / 256 * 256;
+    return (size_t)probe_splits(npad, g.np) * npad * 8;
+}
+
+size_t probe_order_bytes(int64_t npts)
+{
+    const int64_t npad = (npts + 255) / 256 * 256;
+    return (size_t)pow2_at_least(npad) * sizeof(uint64_t) + (size_t)npad * (sizeof(double4) + sizeof(int32_t));
+}
+
+void probe_field(const Geometry& g, const double* src, const double4* pts, int64_t npts, const double lo[3],
+                 const double hi[3], void* order, double* part, double* field, double* rho, hipStream_t st)
+{
+    const int64_t npad = (npts + 255) / 256 * 256;
+    const int64_t npow = pow2_at_least(npad);
+    uint64_t* keys = static_cast<uint64_t*>(order);
+    double4* spts = reinterpret_cast<double4*>(keys + npow);
+    int32_t* perm = reinterpret_cast<int32_t*>(spts + npad);
+    const double ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+    const double sc = ext > 0 ? 1023.0 / ext : 1.0;
+    // sorting pays once the atoms are many (its ~log^2 npts launches against
+    // the n_atoms-long loop of every point): 20k-atom sphere on a 128^3 grid
+    // 50.5 -> 46.5 ms, 1122-atom dimer on 160k points 1.22 -> 1.55 ms
+    const int morton = g.n >= 4096 ? 1 : 0;
+    hipLaunchKernelGGL(k_probe_keys, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, st, pts, npts, npow,
+                       make_double3(lo[0], lo[1], lo[2]), sc, morton, keys);
+    if (morton) sort_keys(keys, npow, st);
+    hipLaunchKernelGGL(k_probe_order, dim3((unsigned)(npad / 256)), dim3(256), 0, st, (const uint64_t*)keys, pts, npts,
+                       npad, spts, perm);
     ProbeConst k;
     k.rq = g.r_q;
     k.rmu = g.model ? g.r_mu : g.r_q;
@@ -261,11 +344,13 @@ void probe_field(const Geometry& g, const double* src, const double4* pts, int64
     const int nsplit = probe_splits(npad, g.np);
     const dim3 grid((unsigned)(npad / 256), (unsigned)nsplit);
     if (g.model == 0)
-        hipLaunchKernelGGL(k_probe<0>, grid, dim3(256), 0, st, g.xyz64, src, g.glo, g.ghi, g.np, pts, part, npad, k);
+        hipLaunchKernelGGL(k_probe<0>, grid, dim3(256), 0, st, g.xyz64, src, g.glo, g.ghi, g.np, (const double4*)spts,
+                           part, npad, k);
     else
-        hipLaunchKernelGGL(k_probe<1>, grid, dim3(256), 0, st, g.xyz64, src, g.glo, g.ghi, g.np, pts, part, npad, k);
+        hipLaunchKernelGGL(k_probe<1>, grid, dim3(256), 0, st, g.xyz64, src, g.glo, g.ghi, g.np, (const double4*)spts,
+                           part, npad, k);
     hipLaunchKernelGGL(k_probe_sum, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, part, nsplit, npad, npts,
-                       field, rho);
+                       (const int32_t*)perm, field, rho);
 }
 
 }  // namespace px

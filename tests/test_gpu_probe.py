@@ -143,6 +143,12 @@ def test_probe_many_points_in_batches_and_empty():
     assert rel(f[idx], ref["field"]) <= 1e-11 and rel(rho[idx], ref["rho"]) <= 1e-11
     f0, r0 = s.probe_field(q, None, np.zeros((0, 3)))
     assert f0.shape == (0, 3) and r0.shape == (0,) and s.probe_stats()["pairs"] == 0
+    bad = pts[:10].copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(px.PxError):
+        s.probe_field(q, None, bad)
+    with pytest.raises(px.PxError):
+        s.probe_field(q, np.zeros((3, n)), pts[:4])   # dipoles for an omegaFQ structure
     s.close()
 
 
