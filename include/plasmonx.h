@@ -147,9 +147,10 @@ typedef struct {
  *                    solver from its iterate (the phase counts as one cycle).
  *                    0 = blocked solver only.  Ignored for PX_WFQFMU and
  *                    two-type structures.  pxSolveBatch and the server solve
- *                    the structures it applies to whole (as pxSolveSpectrum
- *                    does) on a pool of host threads with their own streams,
- *                    beside the stacked block that takes the others.
+ *                    the structures it applies to, and every structure of
+ *                    1024 atoms or more, whole (as pxSolveSpectrum does) on a
+ *                    pool of host threads with their own streams, beside the
+ *                    stacked block that takes the others.
  *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 4000]
  *                    (2000; lowered to keep its basis and the frequencies'
  *                    triangular factors, k^2/2 x 16 B per column, within a
@@ -253,10 +254,11 @@ typedef struct pxServer_t* pxServer;
 pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out);
 
 /* Queues a structure whose frequencies are set.  PX_E_OOM if it can never fit
- * the budget; PX_E_INVALID for a different stream.  With opt->shifted = 1 a
- * one-material PX_WFQ structure starts solving at once, whole, on one of up to
- * four worker threads with their own streams (it is returned by
- * pxServerStep when done); the others join the stacked block. */
+ * the budget; PX_E_INVALID for a different stream.  A structure of 1024
+ * atoms or more, or (opt->shifted = 1) a one-material PX_WFQ structure, starts
+ * solving at once, whole, on one of up to four worker threads with their own
+ * streams (it is returned by pxServerStep when done); the others join the
+ * stacked block. */
 pxStatus pxServerSubmit(pxServer sv, pxStructure s);
 
 /* Admits queued structures that fit, runs one restart cycle, and writes up to

@@ -658,6 +658,18 @@ bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
     return o.shifted == 1 && s->model == PX_WFQ && !s->het;
 }
 
+// Structures that pxSolveBatch and the server solve whole on the worker pool
+// instead of in the stacked block: those of the shared-Krylov phase, and
+// structures of kPoolMinAtoms atoms or more, whose own launches fill the GPU
+// and whose restart escalation would otherwise hold every segment of the
+// block (dipole-model requests of 1k-4k atoms ran 1.7x slower stacked than
+// alone).
+constexpr int64_t kPoolMinAtoms = 1024;
+bool pooled_solve(const pxStructure_t* s, const pxSolveOptions& o)
+{
+    return shifted_applies(s, o) || s->g.n >= kPoolMinAtoms;
+}
+
 void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
 {
     const int npol = s->npol, R = npol, P = s->ncol;
@@ -1187,10 +1199,10 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
         const int Bc = o.block_cols > 0 ? o.block_cols : 64;
         const int m_max = std::max(o.restart_m, o.max_restart_m);
         hipStream_t st = ss[0]->st;
-        // one-material omegaFQ structures: whole solves on the worker pool,
-        // beside the stacked engine that takes the others
+        // whole solves on the worker pool, beside the stacked engine that
+        // takes the small structures
         std::vector<pxStructure_t*> pooled, stacked;
-        for (int32_t k = 0; k < n; ++k) (shifted_applies(ss[k], o) ? pooled : stacked).push_back(ss[k]);
+        for (int32_t k = 0; k < n; ++k) (pooled_solve(ss[k], o) ? pooled : stacked).push_back(ss[k]);
         std::unique_ptr<SolvePool> pool;
         if (!pooled.empty()) {
             HC(hipStreamSynchronize(st));
@@ -1581,7 +1593,7 @@ pxStatus pxServerSubmit(pxServer sv, pxStructure s)
     if (sv->eng->rows_for(s) > sv->eng->rows_capacity())
         return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");
     return guarded([&]() -> pxStatus {
-        if (shifted_applies(s, sv->o)) {
+        if (pooled_solve(s, sv->o)) {
             // solved whole on a worker stream, beside the engine's cycles
             if (!sv->pool) sv->pool.reset(new SolvePool(kPoolWorkers, sv->o));
             HC(hipStreamSynchronize(s->st));

@@ -176,3 +176,42 @@ def test_server_alone_vs_mix_and_admission(shifted):
     sv.close()
     for r in reqs:
         r.close()
+
+
+def test_large_structures_solved_whole_beside_the_block():
+    """A 1100-atom dipole-model rod (1024 atoms or more: solved whole on a
+    worker stream) with a 240-atom rod (stacked block), in a batch and through
+    the server: each spectrum as solved alone."""
+    au = M.load("au_wfqfmu")
+    om = np.linspace(1.6, 3.2, 6)
+    cs = [dict(model=1, xyz=G.fcc_rod_n(1100, seed=21), params=au, om=om, pol=0b100, aib=M.interband_alpha(au, om)),
+          dict(model=1, xyz=G.fcc_rod_n(240, seed=13), params=au, om=om, pol=0b001, aib=M.interband_alpha(au, om))]
+    solo = []
+    for c in cs:
+        s = make(c)
+        assert s.solve(precision=px.PX_MIXED, rel_tol=1e-8) == px.PX_OK
+        solo.append(s.spectrum()[1])
+        s.close()
+    batch = [make(c) for c in cs]
+    assert px.solve_batch(batch, precision=px.PX_MIXED, rel_tol=1e-8) == px.PX_OK
+    for c, s, ref in zip(cs, batch, solo):
+        e = rel_err(s.spectrum()[1], ref)
+        say(f"[pooled batch] N={len(c['xyz'])}: vs alone {e:.1e}")
+        assert e <= 1e-6 and s.stats()[2].max() <= 1e-8
+        s.close()
+    per_row = 64 * 16 * (200 + 1 + 7) + 64 * 32
+    sv = px.Server(40000 * per_row, px.default_stream(), precision=px.PX_MIXED, rel_tol=1e-8, block_cols=64)
+    reqs = [make(c) for c in cs]
+    for r in reqs:
+        sv.submit(r)
+    done, steps = set(), 0
+    while len(done) < len(reqs):
+        done.update(sv.step())
+        steps += 1
+        assert steps < 5000
+    for c, r, ref in zip(cs, reqs, solo):
+        e = rel_err(r.spectrum()[1], ref)
+        say(f"[pooled server] N={len(c['xyz'])}: vs alone {e:.1e}")
+        assert e <= 1e-6 and r.stats()[2].max() <= 1e-8
+        r.close()
+    sv.close()
