@@ -850,61 +850,87 @@ __device__ __forceinline__ double rsqrt_pos_x2(double q)
 // 1e-12 of r^2 for the nearest pairs of a 100k-atom sphere.  Only the source
 // groups that hold one of the wave's own rows need the self pair masked.  The
 // correction list is read in the shadow of the ALU-bound pair loop.
-template <int NC>
-__global__ __launch_bounds__(256) void k_tapply_f64_narrow_q(const double4* __restrict__ xyzc,
-                                                             const double* __restrict__ X,
-                                                             double* __restrict__ part, int np,
-                                                             const int64_t* __restrict__ ell_off,
-                                                             const int32_t* __restrict__ ell_col,
-                                                             const double* __restrict__ ell_val,
-                                                             const int32_t* __restrict__ stop)
+template <int NC, int RPT>
+__global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4* __restrict__ xyzc,
+                                                                   const double* __restrict__ X,
+                                                                   double* __restrict__ part, int np,
+                                                                   const int64_t* __restrict__ ell_off,
+                                                                   const int32_t* __restrict__ ell_col,
+                                                                   const double* __restrict__ ell_val,
+                                                                   const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
+    // a block covers 256 rows with 256 / RPT threads: thread t holds rows
+    // t, t + 256 / RPT, ... of the block, so every source load feeds RPT rows
+    constexpr int BT = 256 / RPT;
     const int tid = threadIdx.x;
-    const int i = blockIdx.x * 256 + tid;
-    const int wave_row0 = uniform(blockIdx.x * 256 + (tid & ~63));
-    const double4 pi = xyzc[i];
-    const double ax = -2.0 * pi.x, ay = -2.0 * pi.y, az = -2.0 * pi.z;
-    double acc[NC];
+    const int base = blockIdx.x * 256;
+    const int wave_row0 = uniform(base + (tid & ~63));
+    double px_[RPT], py_[RPT], pz_[RPT], pw_[RPT];
+    double acc[RPT][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int r = 0; r < RPT; ++r) {
+        const double4 pi = xyzc[base + tid + r * BT];
+        px_[r] = -2.0 * pi.x;
+        py_[r] = -2.0 * pi.y;
+        pz_[r] = -2.0 * pi.z;
+        pw_[r] = pi.w;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+    }
     const int nchunk = np / NW_CHUNK;
     for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y)
     for (int gq = ch * (NW_CHUNK / GROUP); gq < (ch + 1) * (NW_CHUNK / GROUP); ++gq) {
         const int j0 = uniform(gq * GROUP);
-        if (j0 + GROUP <= wave_row0 || j0 >= wave_row0 + 64) {
+        bool self = false;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) self = self || (j0 + GROUP > wave_row0 + r * BT && j0 < wave_row0 + r * BT + 64);
+        if (!self) {
             // eight pairs per iteration: the next iteration's scalar loads are
             // in flight under this one's arithmetic (2: +15 %, 4: +4 % time)
 #pragma unroll 8
             for (int jj = 0; jj < GROUP; ++jj) {
                 const double4 pj = xyzc[j0 + jj];
-                const double t = rsqrt_pos_x2(fma(ax, pj.x, fma(ay, pj.y, fma(az, pj.z, pi.w))) + pj.w);
+                double xj[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[c]);
+                for (int c = 0; c < NC; ++c) xj[c] = X[(size_t)(j0 + jj) * NC + c];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const double t = rsqrt_pos_x2(fma(px_[r], pj.x, fma(py_[r], pj.y, fma(pz_[r], pj.z, pw_[r]))) + pj.w);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[r][c] = fma(t, xj[c], acc[r][c]);
+                }
             }
         } else {
 #pragma unroll 4
             for (int jj = 0; jj < GROUP; ++jj) {
                 const double4 pj = xyzc[j0 + jj];
-                const double r2 = fma(ax, pj.x, fma(ay, pj.y, fma(az, pj.z, pi.w))) + pj.w;
-                const double t = (i == j0 + jj) ? 0.0 : rsqrt_pos_x2(r2);
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[c]);
+                for (int r = 0; r < RPT; ++r) {
+                    const double r2 = fma(px_[r], pj.x, fma(py_[r], pj.y, fma(pz_[r], pj.z, pw_[r]))) + pj.w;
+                    const double t = (base + tid + r * BT == j0 + jj) ? 0.0 : rsqrt_pos_x2(r2);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[r][c] = fma(t, X[(size_t)(j0 + jj) * NC + c], acc[r][c]);
+                }
             }
         }
     }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] *= 0.5;
     const int64_t e0 = ell_off[blockIdx.x], e1 = ell_off[blockIdx.x + 1];
-    for (int64_t e = e0 + (int64_t)blockIdx.y * 256 + tid; e < e1; e += (int64_t)gridDim.y * 256) {
-        const double v = ell_val[e];
-        const double* x = X + (size_t)ell_col[e] * NC;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] = fma(v, x[c], acc[c]);
-    }
     double* out = part + (size_t)blockIdx.y * np * NC;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
+    for (int r = 0; r < RPT; ++r) {
+        const int lr = tid + r * BT;   // row within the block
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] *= 0.5;
+        for (int64_t e = e0 + (int64_t)blockIdx.y * 256 + lr; e < e1; e += (int64_t)gridDim.y * 256) {
+            const double v = ell_val[e];
+            const double* x = X + (size_t)ell_col[e] * NC;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[r][c] = fma(v, x[c], acc[r][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[(size_t)(base + lr) * NC + c] = acc[r][c];
+    }
 }
 
 // Y[t] = sum over the splits of part[k][t], in four interleaved chains so that
@@ -1136,6 +1162,10 @@ int narrow_splits(const Geometry& g)
     return (nchunk + cps - 1) / cps;
 }
 
+// rows per thread of the point-charge kernel (2: +12 %, 4: +43 % time on the
+// 20k-atom sphere: the extra registers cut the waves per SIMD from 8 to 3)
+constexpr int kNarrowRpt = 1;
+
 template <int NC, int MODEL>
 void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch, const int32_t* stop,
                    hipEvent_t ev0, hipEvent_t ev1)
@@ -1149,7 +1179,8 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
     if (MODEL == 0 && g.near_off) {
         // point part on the fly, near-field correction from the stored list
-        hipExtLaunchKernelGGL((k_tapply_f64_narrow_q<NC>), dim3(rb, nsplit), dim3(256), 0, st, ev0, nullptr, 0,
+        hipExtLaunchKernelGGL((k_tapply_f64_narrow_q<NC, kNarrowRpt>), dim3(rb, nsplit), dim3(256 / kNarrowRpt), 0, st,
+                              ev0, nullptr, 0,
                               (const double4*)g.xyzc, X, scratch, (int)g.np, (const int64_t*)g.near_off,
                               (const int32_t*)g.near_col, (const double*)g.near_val, stop);
         const size_t len = (size_t)g.np * NC;
