@@ -218,7 +218,8 @@ def ncols(case):
 
 
 def batch_run(pxm, cases, precision, block_cols=64):
-    """All structures in one stacked block (pxSolveBatch); returns timing and statuses."""
+    """All structures in one pxSolveBatch call (solved whole on the worker pool
+    or stacked in the block); returns timing and statuses."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -232,12 +233,14 @@ def batch_run(pxm, cases, precision, block_cols=64):
     return dict(seconds=time.perf_counter() - t0, status=int(st), relres_max=rr, sigma=sig)
 
 
-def sequential_run(pxm, cases, precision, max_block_cols=0, shifted=None):
+def sequential_run(pxm, cases, precision, max_block_cols=0, shifted=None, progress=False):
     """One structure after the other, each with pxSolveSpectrum (shifted = 0:
     the blocked solver alone, the plain FP64 baseline with PX_FP64)."""
     import torch
     out = []
-    for c in cases:
+    for k, c in enumerate(cases):
+        if progress:
+            log(f"[bench]   structure {k + 1}/{len(cases)}: N={len(c['xyz'])}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = make_structure(pxm, c)
@@ -500,6 +503,8 @@ def main():
                          "with --no-shifted one blocked restart cycle of 4 steps (with --t-apply)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
+    ap.add_argument("--fp64-every", type=int, default=4,
+                    help="batch-full: the plain FP64 baseline on every k-th structure")
     ap.add_argument("--workload", default="sphere",
                     choices=["sphere", "batch-full", "serving-full", "alloys", "probe"],
                     help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
@@ -541,12 +546,20 @@ def main():
         print(json.dumps({"workload": "graphene_batch_64", "columns": cols, "batched_s": round(rb["seconds"], 2),
                           "batched_solves_per_s": round(cols / rb["seconds"], 2), "status": rb["status"],
                           "relres_max": rb["relres_max"]}), flush=True)
-        seq = sequential_run(pxm, cases, pxm.PX_FP64, shifted=0)
+        # the plain FP64 solver on every fp64_every-th structure (a seeded sample
+        # of the same size distribution; all 64 would take about a quarter hour)
+        pick = list(range(0, len(cases), args.fp64_every))
+        sub = [cases[k] for k in pick]
+        seq = sequential_run(pxm, sub, pxm.PX_FP64, shifted=0, progress=True)
         t64 = sum(r["seconds"] for r in seq)
-        err = max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"]))) for a, b in zip(rb["sigma"], seq))
-        print(json.dumps({"workload": "graphene_batch_64", "fp64_per_structure_s": round(t64, 2),
-                          "fp64_per_structure_solves_per_s": round(cols / t64, 2),
-                          "speedup": round(t64 / rb["seconds"], 2), "sigma_rel_err_vs_fp64": err}), flush=True)
+        cols64 = sum(ncols(c) for c in sub)
+        err = max(float(np.max(np.abs(rb["sigma"][k] - r["sigma"])) / np.max(np.abs(r["sigma"])))
+                  for k, r in zip(pick, seq))
+        print(json.dumps({"workload": "graphene_batch_64", "fp64_sample": f"every {args.fp64_every}th structure "
+                          f"({len(sub)} of {len(cases)}, {cols64} columns)", "fp64_per_structure_s": round(t64, 2),
+                          "fp64_per_structure_solves_per_s": round(cols64 / t64, 2),
+                          "speedup": round((cols / rb["seconds"]) / (cols64 / t64), 2),
+                          "sigma_rel_err_vs_fp64": err}), flush=True)
         return
     if args.workload == "probe":
         print(json.dumps({"workload": "induced_field", **probe_extra(pxm)}), flush=True)
