@@ -506,7 +506,7 @@ def main():
     ap.add_argument("--fp64-every", type=int, default=4,
                     help="batch-full: the plain FP64 baseline on every k-th structure")
     ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "batch-full", "serving-full", "alloys", "probe"],
+                    choices=["sphere", "batch-full", "serving-full", "alloys", "probe", "rod"],
                     help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
                          "serving mix, alloys: the Ag-Au series, probe: the induced-field evaluation, "
                          "printed as their own JSON lines")
@@ -560,6 +560,28 @@ def main():
                           "fp64_per_structure_solves_per_s": round(cols64 / t64, 2),
                           "speedup": round((cols / rb["seconds"]) / (cols64 / t64), 2),
                           "sigma_rel_err_vs_fp64": err}), flush=True)
+        return
+    if args.workload == "rod":
+        # the omegaFQFmu Au nanorod: 10,000 atoms (40,000 unknowns), 96 frequencies, z
+        c = C.rod_10k()
+        ncol = len(c["omega_ev"])
+        runs = {}
+        for label, prec in (("mixed", pxm.PX_MIXED), ("fp64", pxm.PX_FP64)):
+            log(f"[bench] rod 10k {label} ...")
+            one_step(pxm, c, prec, False)   # warm-up: the T-apply tuner times its shapes once per process
+            t0 = time.perf_counter()
+            r = one_step(pxm, c, prec, True)
+            runs[label] = (time.perf_counter() - t0, r)
+        (tm, rm), (t64, r64) = runs["mixed"], runs["fp64"]
+        print(json.dumps({"workload": "au_rod_10000_wfqfmu_96w_z", "columns": ncol,
+                          "mixed_s": round(tm, 2), "mixed_solves_per_s": round(ncol / tm, 2),
+                          "fp64_s": round(t64, 2), "fp64_solves_per_s": round(ncol / t64, 2),
+                          "speedup": round(t64 / tm, 2), "mixed_iterations_max": int(rm["iters"].max()),
+                          "fp64_iterations_max": int(r64["iters"].max()), "status": [rm["status"], r64["status"]],
+                          "relres_max": [float(rm["relres"].max()), float(r64["relres"].max())],
+                          "sigma_rel_err_mixed_vs_fp64": float(np.max(np.abs(rm["sigma"] - r64["sigma"])) /
+                                                               np.max(np.abs(r64["sigma"]))),
+                          "tapply": {k: v for k, v in rm["tapply"].items()}}), flush=True)
         return
     if args.workload == "probe":
         print(json.dumps({"workload": "induced_field", **probe_extra(pxm)}), flush=True)
