@@ -850,8 +850,8 @@ __device__ __forceinline__ double rsqrt_pos_x2(double q)
 // 1e-12 of r^2 for the nearest pairs of a 100k-atom sphere.  Only the source
 // groups that hold one of the wave's own rows need the self pair masked.  The
 // correction list is read in the shadow of the ALU-bound pair loop.
-template <int NC, int RPT>
-__global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4* __restrict__ xyzc,
+template <int NC, int RPT, int RB, int SU>
+__global__ __launch_bounds__(RB / RPT) void k_tapply_f64_narrow_q(const double4* __restrict__ xyzc,
                                                                    const double* __restrict__ X,
                                                                    double* __restrict__ part, int np,
                                                                    const int64_t* __restrict__ ell_off,
@@ -860,11 +860,12 @@ __global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4
                                                                    const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
-    // a block covers 256 rows with 256 / RPT threads: thread t holds rows
-    // t, t + 256 / RPT, ... of the block, so every source load feeds RPT rows
-    constexpr int BT = 256 / RPT;
+    // a block covers RB rows with RB / RPT threads: thread t holds rows
+    // t, t + RB / RPT, ... of the block, so every source load feeds RPT rows
+    static_assert(256 % RB == 0 && SU % GROUP == 0, "row blocks within the 256-row ELL blocks");
+    constexpr int BT = RB / RPT;
     const int tid = threadIdx.x;
-    const int base = blockIdx.x * 256;
+    const int base = blockIdx.x * RB;
     const int wave_row0 = uniform(base + (tid & ~63));
     double px_[RPT], py_[RPT], pz_[RPT], pw_[RPT];
     double acc[RPT][NC];
@@ -878,9 +879,9 @@ __global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
     }
-    const int nchunk = np / NW_CHUNK;
-    for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y)
-    for (int gq = ch * (NW_CHUNK / GROUP); gq < (ch + 1) * (NW_CHUNK / GROUP); ++gq) {
+    const int nunit = np / SU;
+    for (int ch = blockIdx.y; ch < nunit; ch += gridDim.y)
+    for (int gq = ch * (SU / GROUP); gq < (ch + 1) * (SU / GROUP); ++gq) {
         const int j0 = uniform(gq * GROUP);
         bool self = false;
 #pragma unroll
@@ -915,11 +916,11 @@ __global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4
             }
         }
     }
-    const int64_t e0 = ell_off[blockIdx.x], e1 = ell_off[blockIdx.x + 1];
+    const int64_t e0 = ell_off[base / 256], e1 = ell_off[base / 256 + 1];
     double* out = part + (size_t)blockIdx.y * np * NC;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int lr = tid + r * BT;   // row within the block
+        const int lr = base % 256 + tid + r * BT;   // row within the 256-row ELL block
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[r][c] *= 0.5;
         for (int64_t e = e0 + (int64_t)blockIdx.y * 256 + lr; e < e1; e += (int64_t)gridDim.y * 256) {
@@ -929,7 +930,7 @@ __global__ __launch_bounds__(256 / RPT) void k_tapply_f64_narrow_q(const double4
             for (int c = 0; c < NC; ++c) acc[r][c] = fma(v, x[c], acc[r][c]);
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[(size_t)(base + lr) * NC + c] = acc[r][c];
+        for (int c = 0; c < NC; ++c) out[(size_t)(base + tid + r * BT) * NC + c] = acc[r][c];
     }
 }
 
@@ -1141,10 +1142,7 @@ DipoleConstD dipole_const_d(const Geometry& g)
     return k;
 }
 
-// Source splits of the narrow kernels: about 16 workgroups per CU (several
-// rounds), which balances the rows' unequal near-field work better than one
-// round of long workgroups (measured on the 20k-atom sphere).
-int narrow_splits(const Geometry& g)
+int device_cus()
 {
     static const int ncu = [] {
         int dev = 0, v = 0;
@@ -1153,6 +1151,15 @@ int narrow_splits(const Geometry& g)
             return v;
         return 256;
     }();
+    return ncu;
+}
+
+// Source splits of the narrow kernels: about 16 workgroups per CU (several
+// rounds), which balances the rows' unequal near-field work better than one
+// round of long workgroups (measured on the 20k-atom sphere).
+int narrow_splits(const Geometry& g)
+{
+    const int ncu = device_cus();
     int rb = (int)(g.np / 256);
     int nchunk = (int)(g.np / NW_CHUNK);
     int want = (16 * ncu + rb - 1) / rb;
@@ -1165,6 +1172,25 @@ int narrow_splits(const Geometry& g)
 // rows per thread of the point-charge kernel (2: +12 %, 4: +43 % time on the
 // 20k-atom sphere: the extra registers cut the waves per SIMD from 8 to 3)
 constexpr int kNarrowRpt = 1;
+// rows per workgroup, source atoms per split unit and 256-row blocks x splits
+// per CU aimed at by the point-charge kernel.  On the 20k-atom sphere (79
+// splits of one unit each): 3 % less time than 40 splits of two units, while
+// 64- or 128-row workgroups change nothing and 128-atom units (158 splits) or
+// fewer splits cost 2-12 % (the split sum grows, resp. the last round of
+// workgroups runs the CUs part empty).
+constexpr int kQRows = 256;
+constexpr int kQUnit = 256;
+constexpr int kQWant = 32;
+
+int narrow_q_splits(const Geometry& g)
+{
+    const int nunit = (int)(g.np / kQUnit);
+    const int rb = (int)(g.np / 256);
+    int want = (kQWant * device_cus() + rb - 1) / rb;
+    want = std::max(1, std::min(want, nunit));
+    const int ups = (nunit + want - 1) / want;
+    return (nunit + ups - 1) / ups;
+}
 
 template <int NC, int MODEL>
 void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st, double* scratch, const int32_t* stop,
@@ -1179,7 +1205,9 @@ void launch_narrow(const Geometry& g, const double* X, double* Y, hipStream_t st
     float rf2 = MODEL ? kc.r_far2 : (float)((XFAR_Q64 * rqq) * (XFAR_Q64 * rqq));
     if (MODEL == 0 && g.near_off) {
         // point part on the fly, near-field correction from the stored list
-        hipExtLaunchKernelGGL((k_tapply_f64_narrow_q<NC, kNarrowRpt>), dim3(rb, nsplit), dim3(256 / kNarrowRpt), 0, st,
+        nsplit = narrow_q_splits(g);
+        hipExtLaunchKernelGGL((k_tapply_f64_narrow_q<NC, kNarrowRpt, kQRows, kQUnit>),
+                              dim3((unsigned)(g.np / kQRows), nsplit), dim3(kQRows / kNarrowRpt), 0, st,
                               ev0, nullptr, 0,
                               (const double4*)g.xyzc, X, scratch, (int)g.np, (const int64_t*)g.near_off,
                               (const int32_t*)g.near_col, (const double*)g.near_val, stop);
@@ -1388,7 +1416,8 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 {
     if (ncols > 8) return 0;
-    return (size_t)narrow_splits(g) * (g.model ? 4 : 1) * g.np * ncols * sizeof(double);
+    const int ns = g.model ? narrow_splits(g) : std::max(narrow_splits(g), narrow_q_splits(g));
+    return (size_t)ns * (g.model ? 4 : 1) * g.np * ncols * sizeof(double);
 }
 
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
