@@ -145,6 +145,15 @@ typedef struct {
  *                    operator, so all frequencies share one Krylov space);
  *                    columns it leaves above rel_tol continue in the blocked
  *                    solver from its iterate (the phase counts as one cycle).
+ *                    2: one block Arnoldi process over the polarizations
+ *                    instead (2 or 3 polarizations with non-zero right-hand
+ *                    sides, else as 1): the block Krylov space of all
+ *                    right-hand sides holds each polarization's own space, so
+ *                    every pair minimises its residual over all of it (fewer
+ *                    steps for the same tolerance, each one T-apply of the
+ *                    same vectors); one banded QR per frequency serves its
+ *                    polarizations; steps at most min(shifted_max_steps,
+ *                    4096 / npol).
  *                    0 = blocked solver only.  Ignored for PX_WFQFMU and
  *                    two-type structures.  pxSolveBatch and the server solve
  *                    the structures it applies to, and every structure of

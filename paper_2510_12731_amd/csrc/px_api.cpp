@@ -655,7 +655,7 @@ struct Scratch {
 
 bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
 {
-    return o.shifted == 1 && s->model == PX_WFQ && !s->het;
+    return o.shifted >= 1 && s->model == PX_WFQ && !s->het;
 }
 
 // Structures that pxSolveBatch and the server solve whole on the worker pool
@@ -797,7 +797,7 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipStreamWaitEvent(st, side.e, 0));
     px::ms_rfactor(H, kcap, npol, P, launched, z, cs, sn, done, rst, st);
     px::ms_backsub(rst, P, launched, done, g, ycoef, st);
-    px::ms_xcombine(R, V, vstride, launched, ycoef, P, s->x, s->ldg, nup, st);
+    px::ms_xcombine(R, V, vstride, launched, done, ycoef, P, s->x, s->ldg, nup, st);
     std::vector<int32_t> dh(P);
     std::vector<double> rh(P);
     HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
@@ -827,6 +827,167 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     s->work[2] += 2.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
 }
 
+// The shared-Krylov phase over a block of polarizations: one block Arnoldi
+// process for the npol right-hand sides (px_shifted_block.hip), for 2 or 3
+// polarizations whose right-hand sides are all non-zero.
+bool block_applies(const pxStructure_t* s, const pxSolveOptions& o)
+{
+    if (o.shifted != 2 || s->npol < 2 || s->npol > 3) return false;
+    for (int l = 0; l < s->npol; ++l)
+        if (!(s->bnorm[l] > 0.0)) return false;
+    return true;
+}
+
+void shifted_phase_block(pxStructure_t* s, const pxSolveOptions& o)
+{
+    const int R = s->npol, P = s->ncol, NW = P / R;
+    const int64_t nup = s->g.nup;
+    hipStream_t st = s->st;
+    size_t fr = 0, tot = 0;
+    HC(hipMemGetInfo(&fr, &tot));
+    // the back substitution holds a frequency's kcap R rows of its right-hand
+    // sides in registers (at most 4096)
+    int kcap = std::min(o.shifted_max_steps, 4096 / R);
+    auto bytes_for = [&](double k) {
+        const double kc = k * R;
+        return (k + 1) * (double)nup * R * 8.0 + (kc + R) * kc * 8.0 + kc * R * NW * 24.0 + (kc + R) * NW * R * 16.0 +
+               kc * (kc + 1) / 2 * NW * 16.0 + kc * P * 16.0 + (double)px::msb_part2_doubles(R, nup, (int)k) * 8.0;
+    };
+    while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
+    const int RR = R * R;
+    const int ldh = kcap * R;
+    const int64_t vstride = nup * R;
+    Scratch sc;
+    double* V = sc.get<double>((size_t)(kcap + 1) * vstride);
+    double* u = sc.get<double>((size_t)vstride);
+    double* Y = sc.get<double>((size_t)vstride);
+    double* wt = sc.get<double>((size_t)vstride);
+    double* part = sc.get<double>(px::msb_part_doubles(R, kcap));
+    double* part2 = sc.get<double>(px::msb_part2_doubles(R, nup, kcap));
+    double* G = sc.get<double>((size_t)(kcap + 1) * 2 * RR);
+    double* Hb = sc.get<double>((size_t)(kcap + 1) * R * ldh);
+    double* coefv = sc.get<double>((size_t)kcap * RR);
+    double* coefu = sc.get<double>((size_t)kcap * RR);
+    double* scal = sc.get<double>((size_t)2 * RR);
+    double* rho0 = sc.get<double>((size_t)RR);
+    double2* z = sc.get<double2>(P);
+    double* rc = sc.get<double>((size_t)kcap * R * R * NW);
+    double2* rs = sc.get<double2>((size_t)kcap * R * R * NW);
+    double2* g = sc.get<double2>((size_t)(kcap + 1) * R * NW * R);
+    double* target = sc.get<double>(P);
+    double* resid = sc.get<double>(P);
+    int32_t* done = sc.get<int32_t>(P);
+    int32_t* ndone = sc.get<int32_t>(1);
+
+    std::vector<double2> zh(P);
+    std::vector<double> th(P);
+    for (int p = 0; p < P; ++p) {
+        double zr, zi;
+        shift_q(s->drude, s->mat.tau, s->omega_au[p / R], zr, zi);
+        zh[p] = make_double2(zr, zi);
+        th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+    }
+    HC(hipMemcpyAsync(z, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+    HC(hipMemcpyAsync(target, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
+    px::fill_zero(Hb, sizeof(double) * (size_t)(kcap + 1) * R * ldh, st);
+    px::fill_zero(g, sizeof(double2) * (size_t)(kcap + 1) * R * NW * R, st);
+    px::fill_zero(done, sizeof(int32_t) * P, st);
+    px::fill_zero(ndone, sizeof(int32_t), st);
+    px::msb_init(R, s->b, s->ldg, u, nup, st);
+
+    const int method = tapply_method(s, false, u, Y, R, R, o);
+    const int lag = method == TA_STORED ? 1 : 2 * kLag;
+    const int GBB = px::msb_givens_cols() / R;   // block steps per banded-QR launch
+    s->sync.ensure(kcap / GBB + 2);
+    int32_t* stop = s->sync.flag();
+    s->sync.reset(st);
+    // the banded QRs run on a second stream of the same priority, beside the
+    // next steps' T-applies, and publish the stop flag once per launch
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        ~Side()
+        {
+            if (e) (void)hipEventDestroy(e);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } side;
+    HC(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+    HC(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
+    std::vector<int> batch_step;
+    int polled = 0;
+    auto givens_side = [&](int kb0, int nkb, int at_step) {
+        HC(hipEventRecord(side.e, st));
+        HC(hipStreamWaitEvent(side.s, side.e, 0));
+        px::msb_givens(R, Hb, ldh, NW, kb0 * R, nkb * R, z, rc, rs, g, rho0, target, done, resid, ndone, stop, side.s);
+        s->sync.publish((int)batch_step.size(), side.s);
+        batch_step.push_back(at_step);
+    };
+    LaunchTimer tm(o.timings != 0);
+    int launched = 0, gnext = 0;
+    bool stopped = false;
+    for (int k = 0; k < kcap && !stopped; ++k) {
+        while (polled < (int)batch_step.size() && batch_step[polled] <= k - lag) {
+            if (s->sync.stopped(polled++)) {
+                stopped = true;
+                break;
+            }
+        }
+        if (stopped) break;
+        // Wt = Kbar T U for the candidate block U of V_k
+        tapply(s, method, false, u, Y, R, R, stop, tm.events(k, 0));
+        px::ms_spmv(R, s->g, Y, wt, st, stop, tm.events(k, 1));
+        px::msb_step(R, V, vstride, k, u, wt, part, part2, G, Hb, ldh, coefv, coefu, scal, rho0, nup, false, st, stop,
+                     tm.events(k, 2));
+        // block columns < k are final after step k
+        if (k - gnext >= GBB) {
+            givens_side(gnext, GBB, k);
+            gnext += GBB;
+        }
+        ++launched;
+    }
+    px::msb_step(R, V, vstride, launched, u, u, part, part2, G, Hb, ldh, coefv, coefu, scal, rho0, nup, true, st,
+                 stop);
+    while (gnext < launched) {
+        const int kn = std::min(GBB, launched - gnext);
+        givens_side(gnext, kn, launched);
+        gnext += kn;
+    }
+    HC(hipEventRecord(side.e, side.s));
+    HC(hipStreamWaitEvent(st, side.e, 0));
+    const int kcols = launched * R;
+    double2* rst = sc.get<double2>(std::max<size_t>(1, px::msb_rst_elems(NW, kcols)));
+    double2* ycoef = sc.get<double2>(std::max<size_t>(1, (size_t)kcols * P));
+    px::msb_finish_solve(R, Hb, ldh, NW, kcols, z, rc, rs, done, rst, g, ycoef, V, vstride, s->x, s->ldg, nup, st);
+    std::vector<int32_t> dh(P);
+    std::vector<double> rh(P);
+    HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
+    HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+    HC(hipStreamSynchronize(st));
+    int executed = 0;
+    for (int p = 0; p < P; ++p) {
+        s->iters[p] = dh[p] ? (dh[p] + R - 1) / R : launched;
+        s->cycles[p] = 1;
+        s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
+        executed = std::max(executed, s->iters[p]);
+    }
+    executed = std::min(launched, executed + 1);
+    double t_ap = 0.0;
+    tm.collect(executed, t_ap, s->ms[3], s->ms[4]);
+    s->ms[2] += t_ap;
+    s->tms[method == TA_STORED ? 3 : 2] += t_ap;
+    const double nu = (double)s->g.nu;
+    s->tstats[method == TA_STORED ? 3 : 2] += executed;
+    s->counts[3] += executed;
+    s->counts[4] += (int64_t)executed * R;
+    s->counts[5] += (int64_t)executed * R;
+    s->tflop[method == TA_STORED ? 3 : 2] += 2.0 * nu * nu * R * executed;
+    s->work[1] += 2.0 * nu * nu * R * executed;
+    // one dot pass (2 R^2 products per basis block and row) and one update
+    // pass (2 R^2) per step
+    s->work[2] += 2.0 * 2.0 * 2.0 * R * R * (double)s->g.n * (double)executed * (executed + 1) / 2.0;
+}
+
 pxStatus check_options(const pxSolveOptions& o)
 {
     if (o.restart_m < 1 || o.restart_m > 1000 || o.max_restart_m > 1000)
@@ -835,7 +996,7 @@ pxStatus check_options(const pxSolveOptions& o)
         o.stall_cycles < 0 || o.block_cols < 0 || o.block_cols % 64 != 0 || o.block_cols > 1024 ||
         (o.ortho != PX_ORTHO_CGS2 && o.ortho != PX_ORTHO_DCGS2) || o.graph_steps < 0 || o.graph_steps > 64 ||
         (o.t_apply != PX_TAPPLY_AUTO && o.t_apply != PX_TAPPLY_ON_THE_FLY && o.t_apply != PX_TAPPLY_STORED) ||
-        (o.shifted != 0 && o.shifted != 1) || o.shifted_max_steps < 1 || o.shifted_max_steps > 4000 ||
+        (o.shifted < 0 || o.shifted > 2) || o.shifted_max_steps < 1 || o.shifted_max_steps > 4000 ||
         (o.precision != PX_FP64 && o.precision != PX_MIXED))
         return fail(PX_E_INVALID, "invalid solve options");
     return PX_OK;
@@ -856,7 +1017,10 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
     ensure_vectors(s, pad_cols(blk, true));
     prepare_solve(s);
-    if (shifted_applies(s, o)) shifted_phase(s, o);
+    if (shifted_applies(s, o)) {
+        if (block_applies(s, o)) shifted_phase_block(s, o);
+        else shifted_phase(s, o);
+    }
     for (int c0 = 0; c0 < ncol; c0 += blk) {
         std::vector<int> cols;
         for (int c = c0; c < std::min(ncol, c0 + blk); ++c) cols.push_back(c);

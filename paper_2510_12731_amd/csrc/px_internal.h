@@ -268,7 +268,32 @@ void ms_rfactor(const double* H, int kcap, int npol, int P, int kmax, const doub
                 const double2* sn, const int32_t* done, double2* rst, hipStream_t st);
 // y = R^-1 g per pair (kmax <= 4000: g is staged in LDS)
 void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const double2* g, double2* y, hipStream_t st);
-void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
-                 int64_t nup, hipStream_t st);
+// x = V y per pair over its done[p] (else K) basis vectors
+void ms_xcombine(int R, const double* V, int64_t vstride, int K, const int32_t* done, const double2* y, int P,
+                 double2* x, int ldx, int64_t nup, hipStream_t st);
+
+// ---- shared-Krylov solve over a block of polarizations (px_shifted_block.hip)
+// One block Arnoldi process for R = npol in {2, 3} right-hand sides; Hbar
+// dense row-major with ldh = kcap R; pairs p = w R + l; see px_shifted_block.hip.
+void msb_init(int R, const double2* b, int ldb, double* u, int64_t nup, hipStream_t st);
+// One delayed block CGS2 step k (block column k-1 corrected, block column k
+// first pass, V_k and the next candidate block u written); rho0 receives
+// rho_0 (R x R) at k = 0; fix_only: the last block column's correction alone.
+void msb_step(int R, double* V, int64_t vstride, int k, double* u, const double* wt, double* part, double* part2,
+              double* G, double* Hb, int ldh, double* coefv, double* coefu, double* scal, double* rho0, int64_t nup,
+              bool fix_only, hipStream_t st, const int32_t* stop, const hipEvent_t* ev = nullptr);
+size_t msb_part_doubles(int R, int kcap);
+size_t msb_part2_doubles(int R, int64_t nup, int kcap);
+// banded QR columns K0 .. K0+nc-1 (nc <= msb_givens_cols()) of every frequency
+int msb_givens_cols();
+void msb_givens(int R, const double* Hb, int ldh, int NW, int K0, int nc, const double2* z, double* rc, double2* rs,
+                double2* g, const double* rho0, const double* target, int32_t* done, double* resid, int32_t* ndone,
+                int32_t* stop, hipStream_t st);
+// triangular factors (rst: msb_rst_elems(NW, kcols) complex), back
+// substitution (kcols <= 4096) and x = V y over kcols columns
+size_t msb_rst_elems(int NW, int kcols);
+void msb_finish_solve(int R, const double* Hb, int ldh, int NW, int kcols, const double2* z, const double* rc,
+                      const double2* rs, const int32_t* done, double2* rst, const double2* g, double2* y,
+                      const double* V, int64_t vstride, double2* x, int ldx, int64_t nup, hipStream_t st);
 
 }  // namespace px

@@ -520,21 +520,30 @@ __global__ __launch_bounds__(256) void k_ms_backsub(const double2* __restrict__ 
     }
 }
 
-// x[row][p] = sum_j V_j[row][slot(p)] y[j][p] for K basis vectors: tiles of
-// 32 rows x 64 pairs, 16 basis vectors per LDS stage.
+// x[row][p] = sum_j V_j[row][slot(p)] y[j][p] over the pair's K_p = done[p]
+// (else kmax) basis vectors: tiles of 32 rows x 64 pairs, 16 basis vectors per
+// LDS stage, up to the tile's largest K_p (vectors of steps issued after every
+// pair finished were skipped and are never read).
 template <int R>
-__global__ __launch_bounds__(256) void k_ms_xcombine(const double* __restrict__ V, int64_t vstride, int K,
+__global__ __launch_bounds__(256) void k_ms_xcombine(const double* __restrict__ V, int64_t vstride, int kmax,
+                                                     const int32_t* __restrict__ done,
                                                      const double2* __restrict__ y, int npol, int P,
                                                      double2* __restrict__ x, int ldx, int64_t nup)
 {
     constexpr int TR = 32, TP = 64, TJ = 16;
     __shared__ double sv[TJ][TR][R];
     __shared__ double2 sy[TJ][TP];
+    __shared__ int kt;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * TR;
     const int p0 = blockIdx.y * TP;
     const int p = p0 + tx;
     const int c = p % npol;
+    if (tid == 0) kt = 0;
+    __syncthreads();
+    if (ty == 0 && p < P) atomicMax(&kt, done[p] ? done[p] : kmax);
+    __syncthreads();
+    const int K = kt;
     double2 acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
@@ -663,11 +672,11 @@ struct StepL {
 
 template <int R>
 struct XcombL {
-    static void run(const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
-                    int64_t nup, hipStream_t st)
+    static void run(const double* V, int64_t vstride, int K, const int32_t* done, const double2* y, int P, double2* x,
+                    int ldx, int64_t nup, hipStream_t st)
     {
         const dim3 grid((unsigned)((nup + 31) / 32), (unsigned)((P + 63) / 64));
-        hipLaunchKernelGGL(k_ms_xcombine<R>, grid, dim3(256), 0, st, V, vstride, K, y, R, P, x, ldx, nup);
+        hipLaunchKernelGGL(k_ms_xcombine<R>, grid, dim3(256), 0, st, V, vstride, K, done, y, R, P, x, ldx, nup);
     }
 };
 
@@ -736,10 +745,10 @@ void ms_backsub(const double2* rst, int P, int kmax, const int32_t* done, const 
                        y);
 }
 
-void ms_xcombine(int R, const double* V, int64_t vstride, int K, const double2* y, int P, double2* x, int ldx,
-                 int64_t nup, hipStream_t st)
+void ms_xcombine(int R, const double* V, int64_t vstride, int K, const int32_t* done, const double2* y, int P,
+                 double2* x, int ldx, int64_t nup, hipStream_t st)
 {
-    with_r<XcombL>(R, V, vstride, K, y, P, x, ldx, nup, st);
+    with_r<XcombL>(R, V, vstride, K, done, y, P, x, ldx, nup, st);
 }
 
 }  // namespace px
