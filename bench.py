@@ -620,7 +620,7 @@ def main():
 
     ta_mode = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
                "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
-    shifted = 0 if args.no_shifted else 1
+    shifted = 0 if args.no_shifted else 2
     for w in range(args.warmup):
         r = one_step(pxm, case, pxm.PX_MIXED, True, t_apply=ta_mode, shifted=shifted)
         log(f"[bench] warmup {w}: status {r['status']} max iters {r['iters'].max()} "
@@ -675,6 +675,20 @@ def main():
                       sparse=round(tm["ms_spmm"], 1), arnoldi_givens=round(tm["ms_arnoldi"], 1),
                       rest=round(tm["ms_other"], 1)))
     extra["tapply_launches"] = {k: int(v) for k, v in last["tapply"].items() if not k.startswith(("ms_", "flop_"))}
+
+    # the shared-Krylov phase with one Arnoldi process per polarization instead
+    if shifted and not args.no_blocked:
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rpp = one_step(pxm, case, pxm.PX_MIXED, True, t_apply=ta_mode, shifted=1)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        extra["per_polarization_phase"] = dict(
+            value=round(ncol / (tb - ta), 3), unit="freq-solves/s", seconds=round(tb - ta, 3),
+            status=int(rpp["status"]), steps_max=int(rpp["iters"].max()),
+            note="shifted = 1: one Arnoldi process per polarization (the default takes one block process)",
+            sigma_rel_err_vs_default=float(np.max(np.abs(rpp["sigma"] - last["sigma"])) /
+                                           np.max(np.abs(last["sigma"]))))
 
     # the blocked mixed-precision solver alone: FP32 MFMA T-apply, FP64 refinement
     if not args.no_blocked:
@@ -779,8 +793,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": case["name"], "n_atoms": n, "n_omega": int(len(case["omega_ev"])),
                    "polarizations": 3, "columns": ncol, "rel_tol": 1e-8, "t_apply": args.t_apply,
-                   "solver": ("shared-Krylov phase (one FP64 Arnoldi process per polarization for all frequencies), "
-                              "blocked GMRES(50) for any column left" if shifted else
+                   "solver": ("shared-Krylov phase (one FP64 block Arnoldi process over the three polarizations for "
+                              "all frequencies), blocked GMRES(50) for any column left" if shifted else
                               "blocked GMRES(50), FP32 T-apply, FP64 refinement")},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -138,14 +138,14 @@ typedef struct {
  *                    (STORED fails with PX_E_OOM if T does not fit).
  *                    pxSolveBatch and the server always generate T on the fly.
  *   shifted          pxSolveSpectrum on a one-material PX_WFQ structure: 1
- *                    (default) first runs one real Arnoldi process on Kbar T
+ *                    first runs one real Arnoldi process on Kbar T
  *                    per polarization, in FP64, and takes every frequency's
  *                    GMRES iterate from it (the right-hand side does not depend
  *                    on the frequency and the frequency only shifts the
  *                    operator, so all frequencies share one Krylov space);
  *                    columns it leaves above rel_tol continue in the blocked
  *                    solver from its iterate (the phase counts as one cycle).
- *                    2: one block Arnoldi process over the polarizations
+ *                    2 (default): one block Arnoldi process over the polarizations
  *                    instead (2 or 3 polarizations with non-zero right-hand
  *                    sides, else as 1): the block Krylov space of all
  *                    right-hand sides holds each polarization's own space, so

@@ -1165,7 +1165,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
     o->ortho = PX_ORTHO_DCGS2;
     o->graph_steps = 8;
     o->t_apply = PX_TAPPLY_AUTO;
-    o->shifted = 1;
+    o->shifted = 2;
     o->shifted_max_steps = 2000;
 }
 

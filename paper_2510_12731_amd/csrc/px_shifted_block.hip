@@ -190,7 +190,7 @@ __global__ void k_msb_init(const double2* __restrict__ b, int ldb, double* __res
 // part[(j * nslab + slab)][.]: over the slab's rows, S_j[a][b] = sum x_j[row][a]
 // u[row][b] at a R + b and C_j[a][b] (wt in place of u) at R^2 + a R + b, with
 // x_j = V_j (j < k) or u (j = k).  A block takes MJB consecutive vectors.
-constexpr int MJB = 2;
+constexpr int MJB = 1;
 
 template <int R>
 __global__ __launch_bounds__(256) void k_msb_dots(const double* __restrict__ V, int64_t vstride, int k,
@@ -258,26 +258,30 @@ __global__ void k_msb_reduce(const double* __restrict__ part, int nslab, int nve
     G[t] = s;
 }
 
-// The coefficients of step k, one wave per block row j = 0..k of Hbar:
+// The coefficients of step k, one wave per block row j = 0..k of Hbar
+// (CWPB waves per workgroup, which form sum S_i^T S_i and S_i^T C_i together):
 // corrects block column k-1, writes the first-pass block column k (block rows
 // 0..k), coefv_j = S_j rho^-1 and coefu_j = (C_j - S_j rho^-1 Ck) rho^-1 (j < k),
 // scal = {rho^-1, -rho^-1 Ck rho^-1} and, at k = 0, rho0 = rho_0.
 // fix_only: the last block column's correction alone.
+constexpr int CWPB = 4;
+
 template <int R>
-__global__ __launch_bounds__(256) void k_msb_coef(const double* __restrict__ G, double* __restrict__ Hb, int ldh,
-                                                  int k, int fix_only, double* __restrict__ coefv,
-                                                  double* __restrict__ coefu, double* __restrict__ scal,
-                                                  double* __restrict__ rho0, const int32_t* __restrict__ stop)
+__global__ __launch_bounds__(64 * CWPB) void k_msb_coef(const double* __restrict__ G, double* __restrict__ Hb,
+                                                        int ldh, int k, int fix_only, double* __restrict__ coefv,
+                                                        double* __restrict__ coefu, double* __restrict__ scal,
+                                                        double* __restrict__ rho0,
+                                                        const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
     constexpr int RR = R * R, W = 2 * RR;
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j > k) return;
+    __shared__ double red[CWPB][2 * RR];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = blockIdx.x * CWPB + wave;
     double ss[RR], sc[RR];
 #pragma unroll
     for (int e = 0; e < RR; ++e) ss[e] = sc[e] = 0.0;
-    for (int i = lane; i < k; i += 64) {
+    for (int i = threadIdx.x; i < k; i += 64 * CWPB) {
         const double* Si = G + (size_t)i * W;
 #pragma unroll
         for (int a = 0; a < R; ++a)
@@ -294,6 +298,25 @@ __global__ __launch_bounds__(256) void k_msb_coef(const double* __restrict__ G, 
         ss[e] = wave_sum(ss[e]);
         sc[e] = wave_sum(sc[e]);
     }
+    if (lane == 0)
+#pragma unroll
+        for (int e = 0; e < RR; ++e) {
+            red[wave][e] = ss[e];
+            red[wave][RR + e] = sc[e];
+        }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < RR; ++e) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int q = 0; q < CWPB; ++q) {
+            a += red[q][e];
+            b += red[q][RR + e];
+        }
+        ss[e] = a;
+        sc[e] = b;
+    }
+    if (j > k) return;
     const double* Gk = G + (size_t)k * W;
     double X[RR], ref[R], rho[RR], ri[RR], ck[RR];
 #pragma unroll
@@ -498,6 +521,53 @@ __global__ void k_msb_finish(const double* __restrict__ part2, int nsplit, const
     msb_finish_row<R>(r, av, au, scal, u, wt, vk);
 }
 
+// A batch of RFB columns' rotations and the fresh Hessenberg entries that
+// enter the window of column l after each of them.
+constexpr int RFB = 4;
+
+template <int R>
+struct RotBatchB {
+    double c[RFB][R], h[RFB];
+    double2 s[RFB][R];
+
+    __device__ __forceinline__ void load(const double* __restrict__ rc, const double2* __restrict__ rs,
+                                         const double* __restrict__ Hb, int ldh, int NW, int w, int l, int j0, int jn)
+    {
+#pragma unroll
+        for (int u = 0; u < RFB; ++u) {
+            const int j = j0 + u;
+            if (j < jn) {
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    c[u][i] = rc[(size_t)(j * R + i) * NW + w];
+                    s[u][i] = rs[(size_t)(j * R + i) * NW + w];
+                }
+                h[u] = Hb[(size_t)(j + R + 1) * ldh + l];
+            }
+        }
+    }
+
+    // columns j0 .. j0+RFB-1 (< jn) applied to the window a of column l; row j
+    // of the factor goes to out[rpk(l, j)] (STORE)
+    template <bool STORE>
+    __device__ __forceinline__ void apply(double2 (&a)[R + 1], double2* __restrict__ out, int l, int j0, int jn,
+                                          double2 zw) const
+    {
+#pragma unroll
+        for (int u = 0; u < RFB; ++u) {
+            const int j = j0 + u;
+            if (j < jn) {
+#pragma unroll
+                for (int i = 0; i < R; ++i) rot(c[u][i], s[u][i], a[0], a[i + 1]);
+                if (STORE) out[rpk(l, j)] = a[0];
+#pragma unroll
+                for (int m = 0; m < R; ++m) a[m] = a[m + 1];
+                a[R] = j + R + 1 == l ? make_double2(h[u] - zw.x, -zw.y) : make_double2(h[u], 0.0);
+            }
+        }
+    }
+};
+
 // ---- banded QR of every frequency's shifted block Hessenberg matrix --------
 // Columns K0 .. K0+nc-1 (nc <= GBC) per launch.  Phase 1, one lane per
 // (frequency, new column): the rotations of the columns before K0 are applied
@@ -510,7 +580,7 @@ __global__ void k_msb_finish(const double* __restrict__ part2, int nsplit, const
 // the residual norms after K+1 columns.  A pair whose residual reaches its
 // target is done with done[p] = K + 1 columns; the thread that finishes the
 // last pair raises *stop.
-constexpr int GBC = 12, LPW = 16, GU_B = 4;
+constexpr int GBC = 12, LPW = 16;
 
 template <int R>
 __global__ __launch_bounds__(64) void k_msb_givens(const double* __restrict__ Hb, int ldh, int NW, int K0, int nc,
@@ -546,32 +616,12 @@ __global__ __launch_bounds__(64) void k_msb_givens(const double* __restrict__ Hb
         double2 a[R + 1];
 #pragma unroll
         for (int m = 0; m <= R; ++m) a[m] = hsb(Hb, ldh, m, K, zw);
-        for (int j0 = 0; j0 < K0; j0 += GU_B) {
-            double c[GU_B][R], fr[GU_B];
-            double2 s[GU_B][R];
-#pragma unroll
-            for (int uu = 0; uu < GU_B; ++uu) {
-                const int j = j0 + uu;
-                if (j < K0) {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        c[uu][i] = rc[(size_t)(j * R + i) * NW + w];
-                        s[uu][i] = rs[(size_t)(j * R + i) * NW + w];
-                    }
-                    fr[uu] = Hb[(size_t)(j + R + 1) * ldh + K];
-                }
-            }
-#pragma unroll
-            for (int uu = 0; uu < GU_B; ++uu) {
-                const int j = j0 + uu;
-                if (j < K0) {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) rot(c[uu][i], s[uu][i], a[0], a[i + 1]);
-#pragma unroll
-                    for (int m = 0; m < R; ++m) a[m] = a[m + 1];
-                    a[R] = j + R + 1 == K ? make_double2(fr[uu] - zw.x, -zw.y) : make_double2(fr[uu], 0.0);
-                }
-            }
+        // batches of RFB earlier columns (a double-buffered variant measured
+        // 1.8x slower here)
+        for (int j0 = 0; j0 < K0; j0 += RFB) {
+            RotBatchB<R> b;
+            b.load(rc, rs, Hb, ldh, NW, w, K, j0, K0);
+            b.template apply<false>(a, nullptr, K, j0, K0, zw);
         }
 #pragma unroll
         for (int m = 0; m <= R; ++m) win[wl][q][m] = a[m];
@@ -675,15 +725,15 @@ __global__ __launch_bounds__(64) void k_msb_rfactor(const double* __restrict__ H
     double2 a[R + 1];
 #pragma unroll
     for (int m = 0; m <= R; ++m) a[m] = hsb(Hb, ldh, m, l, zw);
-#pragma unroll 2
-    for (int j = 0; j < l; ++j) {
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-            rot(rc[(size_t)(j * R + i) * NW + w], rs[(size_t)(j * R + i) * NW + w], a[0], a[i + 1]);
-        out[rpk(l, j)] = a[0];
-#pragma unroll
-        for (int m = 0; m < R; ++m) a[m] = a[m + 1];
-        a[R] = hsb(Hb, ldh, j + R + 1, l, zw);
+    // batches of RFB earlier columns, the next batch's loads in flight while
+    // the current one is applied
+    RotBatchB<R> b0, b1;
+    b0.load(rc, rs, Hb, ldh, NW, w, l, 0, l);
+    for (int j0 = 0; j0 < l; j0 += 2 * RFB) {
+        b1.load(rc, rs, Hb, ldh, NW, w, l, j0 + RFB, l);
+        b0.template apply<true>(a, out, l, j0, l, zw);
+        b0.load(rc, rs, Hb, ldh, NW, w, l, j0 + 2 * RFB, l);
+        b1.template apply<true>(a, out, l, j0 + RFB, l, zw);
     }
 #pragma unroll
     for (int i = 0; i < R; ++i)
@@ -692,15 +742,26 @@ __global__ __launch_bounds__(64) void k_msb_rfactor(const double* __restrict__ H
 }
 
 // y_p = R_w^-1 g_p for the R pairs p = w R + l of frequency w = blockIdx.x
-// together, each over its own K_p columns (done[p], else kcols <= 256 MBS):
-// column-oriented back substitution, thread t holding rows t + 256 m of the R
+// together, each over its own K_p columns (done[p], else kcols <= BST MBS):
+// column-oriented back substitution, thread t holding rows t + BST m of the R
 // right-hand sides in registers; column c of R_w is read once (contiguous)
-// for all of them, the next column's entries while this one is applied.
-// y[j][p] = 0 for j >= K_p.
-constexpr int MBS = 16;
+// for all of them, PD columns ahead of its use.  y[j][p] = 0 for j >= K_p.
+constexpr int BST = 512, MBS = 8, PD = 3;
 
 template <int R>
-__global__ __launch_bounds__(256) void k_msb_backsub(const double2* __restrict__ rst, int NW, int kcols,
+__device__ __forceinline__ void bs_load(const double2* __restrict__ Rw, int c, double2 (&v)[MBS])
+{
+    if (c < 0) return;
+    const double2* col = Rw + rpk(c, 0);
+#pragma unroll
+    for (int m = 0; m < MBS; ++m) {
+        const int j = threadIdx.x + BST * m;
+        if (j <= c) v[m] = col[j];
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(BST) void k_msb_backsub(const double2* __restrict__ rst, int NW, int kcols,
                                                      const int32_t* __restrict__ done,
                                                      const double2* __restrict__ g, double2* __restrict__ y)
 {
@@ -714,68 +775,67 @@ __global__ __launch_bounds__(256) void k_msb_backsub(const double2* __restrict__
         K[l] = d ? d : kcols;
         Kw = std::max(Kw, K[l]);
     }
-    double2 gr[MBS][R], nx[MBS];
+    double2 gr[MBS][R], ring[PD][MBS];
 #pragma unroll
     for (int m = 0; m < MBS; ++m) {
-        const int j = tid + 256 * m;
+        const int j = tid + BST * m;
 #pragma unroll
         for (int l = 0; l < R; ++l) {
             gr[m][l] = j < K[l] ? g[((size_t)j * NW + w) * R + l] : make_double2(0.0, 0.0);
             if (j >= K[l] && j < kcols) y[(size_t)j * P + w * R + l] = make_double2(0.0, 0.0);
         }
-        nx[m] = (Kw > 0 && j <= Kw - 1) ? Rw[rpk(Kw - 1, 0) + j] : make_double2(0.0, 0.0);
     }
-    for (int c = Kw - 1; c >= 0; --c) {
-        double2 cur[MBS];
 #pragma unroll
-        for (int m = 0; m < MBS; ++m) cur[m] = nx[m];
-        // the next column's entries, in flight during this step
-        if (c > 0) {
-            const double2* nc = Rw + rpk(c - 1, 0);
+    for (int u = 0; u < PD; ++u) bs_load<R>(Rw, Kw - 1 - u, ring[u]);
+    for (int cb = Kw - 1; cb >= 0; cb -= PD) {
 #pragma unroll
-            for (int m = 0; m < MBS; ++m) {
-                const int j = tid + 256 * m;
-                if (j <= c - 1) nx[m] = nc[j];
-            }
-        }
-        if (tid == (c & 255)) {
-            const int mo = c >> 8;
-            double2 rcc = make_double2(0.0, 0.0);
-            double2 gv[R];
+        for (int u = 0; u < PD; ++u) {
+            const int c = cb - u;
+            if (c < 0) break;
+            double2 cur[MBS];
 #pragma unroll
-            for (int l = 0; l < R; ++l) gv[l] = make_double2(0.0, 0.0);
+            for (int m = 0; m < MBS; ++m) cur[m] = ring[u][m];
+            bs_load<R>(Rw, c - PD, ring[u]);
+            if (tid == (c % BST)) {
+                const int mo = c / BST;
+                double2 rcc = make_double2(0.0, 0.0);
+                double2 gv[R];
 #pragma unroll
-            for (int m = 0; m < MBS; ++m)
-                if (m == mo) {
-                    rcc = cur[m];
+                for (int l = 0; l < R; ++l) gv[l] = make_double2(0.0, 0.0);
 #pragma unroll
-                    for (int l = 0; l < R; ++l) gv[l] = gr[m][l];
-                }
-            const double den = cabs2(rcc);
+                for (int m = 0; m < MBS; ++m)
+                    if (m == mo) {
+                        rcc = cur[m];
 #pragma unroll
-            for (int l = 0; l < R; ++l) {
-                const double2 v = (c < K[l] && den > 0.0) ? make_double2((gv[l].x * rcc.x + gv[l].y * rcc.y) / den,
-                                                                         (gv[l].y * rcc.x - gv[l].x * rcc.y) / den)
-                                                          : make_double2(0.0, 0.0);
-                ys[l] = v;
-                if (c < K[l]) y[(size_t)c * P + w * R + l] = v;
-            }
-        }
-        __syncthreads();
-        double2 yc[R];
-#pragma unroll
-        for (int l = 0; l < R; ++l) yc[l] = ys[l];
-#pragma unroll
-        for (int m = 0; m < MBS; ++m) {
-            const int j = tid + 256 * m;
-            if (j < c)
+                        for (int l = 0; l < R; ++l) gv[l] = gr[m][l];
+                    }
+                const double den = cabs2(rcc);
 #pragma unroll
                 for (int l = 0; l < R; ++l) {
-                    const double2 t = cmul(cur[m], yc[l]);
-                    gr[m][l] = make_double2(gr[m][l].x - t.x, gr[m][l].y - t.y);
+                    const double2 v = (c < K[l] && den > 0.0)
+                                          ? make_double2((gv[l].x * rcc.x + gv[l].y * rcc.y) / den,
+                                                         (gv[l].y * rcc.x - gv[l].x * rcc.y) / den)
+                                          : make_double2(0.0, 0.0);
+                    ys[l] = v;
+                    if (c < K[l]) y[(size_t)c * P + w * R + l] = v;
                 }
+            }
+            __syncthreads();
+            double2 yc[R];
+#pragma unroll
+            for (int l = 0; l < R; ++l) yc[l] = ys[l];
+#pragma unroll
+            for (int m = 0; m < MBS; ++m) {
+                const int j = tid + BST * m;
+                if (j < c)
+#pragma unroll
+                    for (int l = 0; l < R; ++l) {
+                        const double2 t = cmul(cur[m], yc[l]);
+                        gr[m][l] = make_double2(gr[m][l].x - t.x, gr[m][l].y - t.y);
+                    }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -880,14 +940,13 @@ void step_r(const double* V, int64_t vstride, int k, double* u, const double* wt
                           V, vstride, k, (const double*)u, wt, part, nup, rps, stop);
     hipLaunchKernelGGL(k_msb_reduce<W>, dim3((unsigned)((nvec * W + 255) / 256)), dim3(256), 0, st, (const double*)part,
                        nslab, nvec, G, stop);
-    const dim3 cg((unsigned)((k + 1 + 3) / 4));
+    const dim3 cg((unsigned)((k + CWPB) / CWPB)), cb(64 * CWPB);
     if (fix_only) {
-        hipExtLaunchKernelGGL(k_msb_coef<R>, cg, dim3(256), 0, st, nullptr, e1, 0, (const double*)G, Hb, ldh, k, 1,
-                              coefv, coefu, scal, rho0, stop);
+        hipExtLaunchKernelGGL(k_msb_coef<R>, cg, cb, 0, st, nullptr, e1, 0, (const double*)G, Hb, ldh, k, 1, coefv,
+                              coefu, scal, rho0, stop);
         return;
     }
-    hipLaunchKernelGGL(k_msb_coef<R>, cg, dim3(256), 0, st, (const double*)G, Hb, ldh, k, 0, coefv, coefu, scal, rho0,
-                       stop);
+    hipLaunchKernelGGL(k_msb_coef<R>, cg, cb, 0, st, (const double*)G, Hb, ldh, k, 0, coefv, coefu, scal, rho0, stop);
     int vps, nsp;
     msb_update_split(nup, k, vps, nsp);
     double* vk = const_cast<double*>(V) + (size_t)k * vstride;
@@ -964,13 +1023,13 @@ void msb_finish_solve(int R, const double* Hb, int ldh, int NW, int kcols, const
     const dim3 gx((unsigned)((nup + 31) / 32), (unsigned)((P + 63) / 64));
     if (R == 2) {
         hipLaunchKernelGGL(k_msb_rfactor<2>, gr, dim3(64), 0, st, Hb, ldh, NW, kcols, z, rc, rs, done, rst);
-        hipLaunchKernelGGL(k_msb_backsub<2>, dim3((unsigned)NW), dim3(256), 0, st, (const double2*)rst, NW, kcols,
+        hipLaunchKernelGGL(k_msb_backsub<2>, dim3((unsigned)NW), dim3(BST), 0, st, (const double2*)rst, NW, kcols,
                            done, g, y);
         hipLaunchKernelGGL(k_msb_xcombine<2>, gx, dim3(256), 0, st, V, vstride, kcols, done, (const double2*)y, P, x,
                            ldx, nup);
     } else {
         hipLaunchKernelGGL(k_msb_rfactor<3>, gr, dim3(64), 0, st, Hb, ldh, NW, kcols, z, rc, rs, done, rst);
-        hipLaunchKernelGGL(k_msb_backsub<3>, dim3((unsigned)NW), dim3(256), 0, st, (const double2*)rst, NW, kcols,
+        hipLaunchKernelGGL(k_msb_backsub<3>, dim3((unsigned)NW), dim3(BST), 0, st, (const double2*)rst, NW, kcols,
                            done, g, y);
         hipLaunchKernelGGL(k_msb_xcombine<3>, gx, dim3(256), 0, st, V, vstride, kcols, done, (const double2*)y, P, x,
                            ldx, nup);

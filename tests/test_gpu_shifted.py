@@ -39,6 +39,7 @@ def lib():
 
 
 def solve(xyz, params, om, pol, precision, tol, **kw):
+    kw.setdefault("shifted", 1)
     s = px.Structure(0, xyz, params, px.default_stream())
     s.set_frequencies(om, pol, 1e-4)
     st = s.solve(precision=precision, rel_tol=tol, **kw)
@@ -122,7 +123,7 @@ def test_step_cap_reports_not_converged():
     c = C.small_sphere()
     s = px.Structure(0, c["xyz"], c["params"], px.default_stream())
     s.set_frequencies([3.5], 0b001)
-    st = s.solve(precision=px.PX_FP64, rel_tol=1e-12, shifted_max_steps=3, max_cycles=1)
+    st = s.solve(precision=px.PX_FP64, rel_tol=1e-12, shifted=1, shifted_max_steps=3, max_cycles=1)
     assert st == px.PX_E_NOTCONV
     it, cyc, rr = s.stats()
     assert it[0] == 3 and cyc[0] == 1 and rr[0] > 1e-12
