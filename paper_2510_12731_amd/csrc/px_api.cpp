@@ -266,11 +266,11 @@ void ensure_stored(pxStructure_t* s, bool f32)
 {
     const size_t n2 = (size_t)s->g.nup * (size_t)s->g.nup;
     if (f32 && !s->t32) {
-        s->t32 = dalloc<float>(n2);
+        s->t32 = static_cast<float*>(pxs::BlockCache::get().take(n2 * sizeof(float)));
         px::tdense_f32(s->g, s->t32, s->st);
     }
     if (!f32 && !s->t64) {
-        s->t64 = dalloc<double>(n2);
+        s->t64 = static_cast<double*>(pxs::BlockCache::get().take(n2 * sizeof(double)));
         px::tdense_f64(s->g, s->t64, s->st);
     }
 }
@@ -637,19 +637,24 @@ void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
 // ---- shared-Krylov phase: every frequency of a one-material omegaFQ structure
 // from one real Arnoldi process per polarization (px_shifted.hip) ----------
 
-// Device buffers that live for one call.
+// Device buffers that live for one call, from the block cache: given back to
+// it once the call has marked them idle (its streams synchronised), else freed.
 struct Scratch {
     std::vector<void*> ps;
+    bool idle = false;
     template <typename T>
     T* get(size_t count)
     {
-        T* p = dalloc<T>(count);
+        T* p = static_cast<T*>(pxs::BlockCache::get().take(std::max<size_t>(count, 1) * sizeof(T)));
         ps.push_back(p);
         return p;
     }
     ~Scratch()
     {
-        for (void* p : ps) dfree(p);
+        for (void* p : ps) {
+            if (idle) pxs::BlockCache::get().give(p);
+            else pxs::BlockCache::get().drop(p);
+        }
     }
 };
 
@@ -803,6 +808,7 @@ void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
     HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
     HC(hipStreamSynchronize(st));
+    sc.idle = true;   // nothing on either stream uses the scratch any more
     int executed = 0;
     for (int p = 0; p < P; ++p) {
         s->iters[p] = dh[p] ? dh[p] : launched;
@@ -964,6 +970,7 @@ void shifted_phase_block(pxStructure_t* s, const pxSolveOptions& o)
     HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
     HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
     HC(hipStreamSynchronize(st));
+    sc.idle = true;   // nothing on either stream uses the scratch any more
     int executed = 0;
     for (int p = 0; p < P; ++p) {
         s->iters[p] = dh[p] ? (dh[p] + R - 1) / R : launched;
@@ -1703,8 +1710,8 @@ pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6)
 void pxDestroyStructure(pxStructure s)
 {
     if (!s) return;
-    if (s->st) (void)hipStreamSynchronize(s->st);
-    else (void)hipDeviceSynchronize();
+    const hipError_t e = s->st ? hipStreamSynchronize(s->st) : hipDeviceSynchronize();
+    s->idle = e == hipSuccess;
     delete s;
 }
 

@@ -6,6 +6,9 @@
 
 #include <string>
 #include <array>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "plasmonx.h"
@@ -48,6 +51,109 @@ inline void dfree(void* p)
 {
     if (p) (void)hipFree(p);
 }
+
+// Device blocks kept for the next allocation of a similar size (the shared
+// phases' scratch and the stored T: hipMalloc and hipFree of several GB cost
+// milliseconds of host time per solve).  A block is given back only once no
+// stream uses it any more (its user has synchronised); a block of at least
+// kMinBytes serves a request of at least half its size on the same device;
+// at most kCacheBytes are kept, and a failed hipMalloc releases them and
+// tries again.  The blocks are never freed at process exit.
+class BlockCache {
+  public:
+    static constexpr size_t kMinBytes = size_t(1) << 24, kCacheBytes = size_t(24) << 30;
+
+    static BlockCache& get()
+    {
+        static BlockCache* c = new BlockCache();
+        return *c;
+    }
+
+    void* take(size_t bytes)
+    {
+        if (bytes == 0) bytes = 1;
+        int dev = 0;
+        hcheck(hipGetDevice(&dev), "hipGetDevice");
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto it = blocks_.lower_bound(bytes); it != blocks_.end() && it->first <= 2 * bytes; ++it)
+                if (it->second.dev == dev) {
+                    void* p = it->second.p;
+                    live_[p] = Live{it->first, dev};
+                    held_ -= it->first;
+                    blocks_.erase(it);
+                    return p;
+                }
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            release();
+            e = hipMalloc(&p, bytes);
+        }
+        if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+        std::lock_guard<std::mutex> lk(mu_);
+        live_[p] = Live{bytes, dev};
+        return p;
+    }
+
+    // p came from take() and no stream uses it any more
+    void give(void* p)
+    {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = live_.find(p);
+            if (it != live_.end()) {
+                const Live l = it->second;
+                live_.erase(it);
+                if (l.bytes >= kMinBytes && held_ + l.bytes <= kCacheBytes) {
+                    blocks_.emplace(l.bytes, Block{p, l.dev});
+                    held_ += l.bytes;
+                    return;
+                }
+            }
+        }
+        (void)hipFree(p);
+    }
+
+    // p came from take() but may still be in use: freed (hipFree waits for the device)
+    void drop(void* p)
+    {
+        if (!p) return;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            live_.erase(p);
+        }
+        (void)hipFree(p);
+    }
+
+    void release()
+    {
+        std::multimap<size_t, Block> b;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            b.swap(blocks_);
+            held_ = 0;
+        }
+        for (auto& e : b) (void)hipFree(e.second.p);
+    }
+
+  private:
+    struct Block {
+        void* p;
+        int dev;
+    };
+    struct Live {
+        size_t bytes;
+        int dev;
+    };
+    std::mutex mu_;
+    std::multimap<size_t, Block> blocks_;
+    std::unordered_map<void*, Live> live_;
+    size_t held_ = 0;
+};
 
 struct Workspace {
     int lda_cap = 0, m_cap = 0;
@@ -311,11 +417,18 @@ struct pxStructure_t {
     double tflop[4] = {0, 0, 0, 0};     // their algorithmic FLOP inside cycles
     double probe[2] = {0, 0};           // last probe call: kernel milliseconds, pair evaluations
 
+    bool idle = false;   // set once the structure's stream has been synchronised for destruction
+
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, d_perm, d_col_pol, d_omega, x, b, t32, t64};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, d_perm, d_col_pol, d_omega, x, b};
         for (void* p : ps) pxs::dfree(p);
+        // the stored T came from the block cache
+        for (void* p : {(void*)t32, (void*)t64}) {
+            if (idle) pxs::BlockCache::get().give(p);
+            else pxs::BlockCache::get().drop(p);
+        }
         pxs::release_blas(blas);
     }
 };
