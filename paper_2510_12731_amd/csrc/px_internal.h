@@ -69,6 +69,10 @@ struct Geometry {
 
 // Ascending bitonic sort of npow (a power of two) 64-bit keys in place.
 void sort_keys(uint64_t* keys, int64_t npow, hipStream_t st);
+// Candidate subsets per 64-row block of the neighbour builders (px_neighbors.h)
+int neighbor_subsets(int64_t np);
+// cnt[i] = add + sum over nsub subsets of cntw[s][i] (row stride np), i < n
+void count_sum(const int32_t* cntw, int nsub, int64_t np, int64_t n, int32_t add, int32_t* cnt, hipStream_t st);
 // Exclusive scan of cnt[0..n) into row_ptr[0..n] (one workgroup).
 void scan_counts(const int32_t* cnt, int64_t n, int32_t* row_ptr, hipStream_t st);
 // Builds g's FP64 near-field list for the omegaFQ narrow T-apply once

@@ -129,31 +129,34 @@ __device__ __forceinline__ double kappa_val(double r, const KappaConst& k)
 }
 
 // Neighbour search over the real atoms, one thread per row atom, 64 rows per
-// (one-wave) workgroup (px_neighbors.h).  Pass 0 counts (row length incl. the
-// diagonal) and flags coincident atoms; pass 1 fills columns in increasing
-// order, the diagonal slot kept where the columns pass i and filled with
-// Kbar_ii = -sum_k K_ik once the row is summed.
+// (one-wave) workgroup x = blockIdx.x, the row block's candidate source
+// groups shared out over gridDim.y subsets (px_neighbors.h).  Pass 0 counts
+// each subset's off-diagonal entries of the row (cntw[sub][i]) and flags
+// coincident atoms; pass 1 fills them, subset after subset (columns
+// increasing within a subset), leaving the row's last slot to k_kbar_diag.
 template <int PASS>
 __global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x64, const float4* __restrict__ glo,
                                                   const float4* __restrict__ ghi, int64_t n, int64_t np,
                                                   KappaSet ks, const uint8_t* __restrict__ type,
-                                                  int32_t* __restrict__ cnt,
+                                                  int32_t* __restrict__ cntw,
                                                   const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                   double* __restrict__ val, int* __restrict__ bad)
 {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int sub = blockIdx.y, nsub = gridDim.y;
     const double4 pi = x64[i];
     const bool row = i < n;
     const float lim = (float)(ks.rc_max * 1.0001 + 1e-3);
     const double lim2 = (double)lim * (double)lim;   // r^2 prefilter, above every pair type's cutoff
     const int ti = (type && row) ? type[i] : 0;
     int count = 0;
-    double ksum = 0.0;
-    int64_t out = (PASS == 1 && row) ? row_ptr[i] : 0;
-    int64_t diag = -1;
-    nbr::for_near_atoms(x64, n, glo, ghi, lim, [&](int64_t j, const double4& pj) {
+    int64_t out = 0;
+    if (PASS == 1 && row) {
+        out = row_ptr[i];
+        for (int t = 0; t < sub; ++t) out += cntw[(size_t)t * np + i];
+    }
+    nbr::for_near_atoms(x64, n, glo, ghi, lim, (int64_t)blockIdx.x, sub, nsub, [&](int64_t j, const double4& pj) {
         if (!row) return;
-        if (PASS == 1 && diag < 0 && j > i) diag = out++;
         if (j == i) return;
         const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
         const double r2 = dx * dx + dy * dy + dz * dz;
@@ -165,23 +168,38 @@ __global__ __launch_bounds__(64) void k_kbar_rows(const double4* __restrict__ x6
             if (PASS == 0) {
                 ++count;
             } else {
-                const double v = kappa_val(r, kc);
                 col[out] = (int32_t)j;
-                val[out] = v;
-                ksum += v;
+                val[out] = kappa_val(r, kc);
                 ++out;
             }
         }
     });
-    if (row) {
-        if (PASS == 0) {
-            cnt[i] = count + 1;
-        } else {
-            if (diag < 0) diag = out;
-            col[diag] = (int32_t)i;
-            val[diag] = -ksum;
-        }
-    }
+    if (PASS == 0 && row) cntw[(size_t)sub * np + i] = count;
+}
+
+// cnt[i] = add + sum over the nsub subsets of cntw[s][i], i < n.
+__global__ void k_count_sum(const int32_t* __restrict__ cntw, int nsub, int64_t np, int64_t n, int32_t add,
+                            int32_t* __restrict__ cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t c = add;
+    for (int s = 0; s < nsub; ++s) c += cntw[(size_t)s * np + i];
+    cnt[i] = c;
+}
+
+// The diagonal of each row of Kbar in its last slot: Kbar_ii = -sum_k K_ik
+// over the row's other entries, in slot order.
+__global__ void k_kbar_diag(const int32_t* __restrict__ row_ptr, int64_t n, int32_t* __restrict__ col,
+                            double* __restrict__ val)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t d = row_ptr[i + 1] - 1;
+    double s = 0.0;
+    for (int32_t e = row_ptr[i]; e < d; ++e) s += val[e];
+    col[d] = (int32_t)i;
+    val[d] = -s;
 }
 
 // Exclusive scan of cnt[0..n) into row_ptr[0..n], single workgroup.
@@ -1354,6 +1372,21 @@ inline int arn_chunks(int64_t rows) { return (int)((rows + ARN_ROWS - 1) / ARN_R
 
 // ============================================================== launchers
 
+// Candidate subsets per row block of the neighbour builders: about 1024
+// one-wave workgroups in all, at most 8 subsets.
+void count_sum(const int32_t* cntw, int nsub, int64_t np, int64_t n, int32_t add, int32_t* cnt, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_count_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cntw, nsub, np, n, add,
+                           cnt);
+}
+
+int neighbor_subsets(int64_t np)
+{
+    const int64_t rb = std::max<int64_t>(1, np / 64);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8, (1024 + rb - 1) / rb));
+}
+
 hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutoff_bohr, const pxMaterial& m,
                           double r0_bohr, std::vector<int32_t>& perm_host, int* bad_pair, hipStream_t st,
                           const uint8_t* types_host, const pxMaterial* mb)
@@ -1374,7 +1407,7 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
     while (npow < n) npow <<= 1;
     double* d_xyz = nullptr;
     uint64_t* d_keys = nullptr;
-    int32_t *d_cnt = nullptr, *d_perm = nullptr;
+    int32_t *d_cnt = nullptr, *d_perm = nullptr, *d_cntw = nullptr;
     int* d_bad = nullptr;
     uint8_t* d_types = nullptr;
     hipError_t e;
@@ -1437,8 +1470,13 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
             hipLaunchKernelGGL(k_gather_types, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d_types, d_perm, n,
                                np, g.type);
         }
-        hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, n,
-                           np, ks, g.type, d_cnt, nullptr, nullptr, nullptr, d_bad);
+        const int nsub = neighbor_subsets(np);
+        PXCHK(hipMalloc(&d_cntw, sizeof(int32_t) * (size_t)nsub * np));
+        hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
+                           g.ghi, n, np, ks, g.type, d_cntw, nullptr, nullptr, nullptr, d_bad);
+        // row lengths with the diagonal
+        hipLaunchKernelGGL(k_count_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const int32_t*)d_cntw,
+                           nsub, np, n, 1, d_cnt);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d_cnt, n, g.row_ptr);
         int32_t nnz = 0;
         PXCHK(hipMemcpyAsync(&nnz, g.row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1447,8 +1485,10 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
         g.nnz = nnz;
         PXCHK(hipMalloc(&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
         PXCHK(hipMalloc(&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
-        hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, n,
-                           np, ks, g.type, nullptr, g.row_ptr, g.col, g.val, d_bad);
+        hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
+                           g.ghi, n, np, ks, g.type, d_cntw, g.row_ptr, g.col, g.val, d_bad);
+        hipLaunchKernelGGL(k_kbar_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                           (const int32_t*)g.row_ptr, n, g.col, g.val);
         if (g.type) {
             PXCHK(hipMalloc(&g.hrow, sizeof(double4) * n));
             hipLaunchKernelGGL(k_het_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.row_ptr, g.col, g.val,
@@ -1464,6 +1504,7 @@ fail:
     (void)hipFree(d_xyz);
     (void)hipFree(d_keys);
     (void)hipFree(d_cnt);
+    (void)hipFree(d_cntw);
     (void)hipFree(d_perm);
     (void)hipFree(d_bad);
     (void)hipFree(d_types);

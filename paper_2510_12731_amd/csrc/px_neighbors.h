@@ -2,7 +2,9 @@
 // workgroup owns 64 row atoms (two groups of GROUP) and visits the source
 // groups whose bounding box lies within a distance of its rows' box, in
 // increasing order, with each group's atoms fetched by one vector load while
-// the previous group is being processed.
+// the previous group is being processed.  The candidate groups of a row block
+// can be shared out over nsub workgroups: subset s takes candidates s,
+// s + nsub, ... of the sequence (every subset still tests all the boxes).
 #pragma once
 
 #include "px_internal.h"
@@ -56,29 +58,35 @@ struct GroupWalk {
     }
 };
 
-// Calls f(j, p_j) for every real atom j (< n) of every source group whose box
-// lies within lim of the box of the workgroup's 64 rows, j increasing,
-// wave-uniform.  Lane k < GROUP loads atom k of a group (the next group's load
-// is issued before the current group is processed) and the atoms are
-// broadcast from LDS.  For one-wave workgroups (64 threads).
+// Calls f(j, p_j) for every real atom j (< n) of the source groups of subset
+// sub (of nsub) among those whose box lies within lim of the box of row block
+// rb (64 rows), j increasing, wave-uniform.  Lane k < GROUP loads atom k of a
+// group (the next group's load is issued before the current group is
+// processed) and the atoms are broadcast from LDS.  For one-wave workgroups
+// (64 threads).
 template <typename F>
 __device__ __forceinline__ void for_near_atoms(const double4* __restrict__ xyz, int64_t n,
                                                const float4* __restrict__ glo, const float4* __restrict__ ghi,
-                                               float lim, F&& f)
+                                               float lim, int64_t rb, int sub, int nsub, F&& f)
 {
     __shared__ double4 sp[GROUP];
     const int lane = threadIdx.x & 63;
     GroupWalk w;
-    wave_box(glo, ghi, (int64_t)blockIdx.x * (64 / GROUP), w.lo, w.hi);
+    wave_box(glo, ghi, rb * (64 / GROUP), w.lo, w.hi);
     w.glo = glo;
     w.ghi = ghi;
     w.ngroups = (n + GROUP - 1) / GROUP;
     w.lim2 = lim * lim;
+    // candidate sub, then every nsub-th
+    for (int t = 0; t < sub; ++t)
+        if (w.next() < 0) break;
     int64_t g = w.next();
     double4 cur = make_double4(0.0, 0.0, 0.0, 0.0);
     if (g >= 0) cur = xyz[g * GROUP + (lane & (GROUP - 1))];
     while (g >= 0) {
-        const int64_t gn = w.next();
+        int64_t gn = -1;
+        for (int t = 0; t < nsub; ++t)
+            if ((gn = w.next()) < 0) break;
         double4 nxt = cur;
         if (gn >= 0) nxt = xyz[gn * GROUP + (lane & (GROUP - 1))];
         __syncthreads();

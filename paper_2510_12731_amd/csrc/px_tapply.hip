@@ -954,25 +954,34 @@ __global__ void k_sum_splits(const double* __restrict__ part, double* __restrict
 // Near-field list of the omegaFQ T in FP64 over the real atoms: for every
 // pair closer than r_far (erfc(x) < 2^-54 beyond), C_ij = -erfc(r/R_qq)/r,
 // and C_ii = sqrt(2/pi)/R_q (the self term, Eq. tqq).  Pass 0 counts each
-// row's entries; pass 1 fills the ELL layout: row block b (256 rows) holds
-// width_b = (off[b+1] - off[b]) / 256 slots, entry k of row i at off[b] +
-// k * 256 + (i - 256 b), columns increasing along the slots, unused slots left
-// as cleared (column 0, value 0).  One thread per row atom, 64 rows per
-// (one-wave) workgroup (px_neighbors.h).
+// row's entries per candidate subset (cntw[sub][i]); pass 1 fills the ELL
+// layout: row block b (256 rows) holds width_b = (off[b+1] - off[b]) / 256
+// slots, entry k of row i at off[b] + k * 256 + (i - 256 b), subset after
+// subset (columns increasing within a subset), unused slots left as cleared
+// (column 0, value 0).  One thread per row atom, 64 rows per (one-wave)
+// workgroup x = blockIdx.x, the row block's candidate source groups shared out
+// over gridDim.y subsets (px_neighbors.h).
 template <int PASS>
 __global__ __launch_bounds__(64) void k_near_rows(const double4* __restrict__ xyz, const float4* __restrict__ glo,
-                                                  const float4* __restrict__ ghi, int64_t n, double r_far,
-                                                  double inv_rqq, double t_self, int32_t* __restrict__ cnt,
-                                                  const int64_t* __restrict__ off, int32_t* __restrict__ col,
-                                                  double* __restrict__ val)
+                                                  const float4* __restrict__ ghi, int64_t n, int64_t np,
+                                                  double r_far, double inv_rqq, double t_self,
+                                                  int32_t* __restrict__ cntw, const int64_t* __restrict__ off,
+                                                  int32_t* __restrict__ col, double* __restrict__ val)
 {
     const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int sub = blockIdx.y, nsub = gridDim.y;
     const double4 pi = xyz[i];
     const bool row = i < n;
     const double rf2 = r_far * r_far;
     int count = 0;
-    int64_t out = PASS == 1 ? off[i / 256] + (i % 256) : 0;
-    nbr::for_near_atoms(xyz, n, glo, ghi, (float)(r_far * 1.0001 + 1e-3), [&](int64_t j, const double4& pj) {
+    int64_t out = 0;
+    if (PASS == 1 && row) {
+        int64_t before = 0;
+        for (int t = 0; t < sub; ++t) before += cntw[(size_t)t * np + i];
+        out = off[i / 256] + (i % 256) + 256 * before;
+    }
+    nbr::for_near_atoms(xyz, n, glo, ghi, (float)(r_far * 1.0001 + 1e-3), (int64_t)blockIdx.x, sub, nsub,
+                        [&](int64_t j, const double4& pj) {
         if (!row) return;
         const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -990,7 +999,7 @@ __global__ __launch_bounds__(64) void k_near_rows(const double4* __restrict__ xy
             out += 256;
         }
     });
-    if (PASS == 0 && row) cnt[i] = count;
+    if (PASS == 0 && row) cntw[(size_t)sub * np + i] = count;
 }
 
 // ELL slot counts: wid[b] = 256 * (the longest row of row block b), b < nb;
@@ -1322,19 +1331,22 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
     const double rqq = std::sqrt(2.0) * g.r_q;
     const double r_far = XFAR_Q64 * rqq;
     const int64_t nb = g.np / 256;
-    int32_t* cnt = nullptr;
+    int32_t *cnt = nullptr, *cntw = nullptr;
     int64_t* wid = nullptr;
+    const int nsub = neighbor_subsets(g.np);
     int64_t nnz = 0;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
     PXCHK(hipMalloc(&cnt, sizeof(int32_t) * g.np));
+    PXCHK(hipMalloc(&cntw, sizeof(int32_t) * (size_t)nsub * g.np));
     PXCHK(hipMalloc(&wid, sizeof(int64_t) * nb));
     PXCHK(hipMalloc(&g.near_off, sizeof(int64_t) * (nb + 1)));
     PXCHK(hipMalloc(&g.xyzc, sizeof(double4) * g.np));
     hipLaunchKernelGGL(k_centred, dim3((unsigned)((g.np + 255) / 256)), dim3(256), 0, st, g.xyz64, g.np, g.cx, g.cy,
                        g.cz, g.xyzc);
-    hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, g.n,
-                       r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, cnt, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
+                       g.ghi, g.n, g.np, r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, cntw, nullptr, nullptr, nullptr);
+    count_sum(cntw, nsub, g.np, g.n, 0, cnt, st);
     hipLaunchKernelGGL(k_near_widths, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, cnt, g.n, nb, wid);
     PXCHK(hipGetLastError());
     {
@@ -1351,17 +1363,20 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
         PXCHK(hipMalloc(&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
         fill_zero(g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), st);
         fill_zero(g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1), st);
-        hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 64)), dim3(64), 0, st, g.xyz64, g.glo, g.ghi, g.n,
-                           r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, nullptr, g.near_off, g.near_col, g.near_val);
+        hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64,
+                           g.glo, g.ghi, g.n, g.np, r_far, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, cntw, g.near_off,
+                           g.near_col, g.near_val);
         PXCHK(hipStreamSynchronize(st));
         PXCHK(hipGetLastError());
     }
     (void)hipFree(cnt);
+    (void)hipFree(cntw);
     (void)hipFree(wid);
     return hipSuccess;
 fail:
 #undef PXCHK
     (void)hipFree(cnt);
+    (void)hipFree(cntw);
     (void)hipFree(wid);
     (void)hipFree(g.near_off);
     (void)hipFree(g.near_col);
