@@ -9,7 +9,8 @@ Parity with the oracle at the bounds of test_gpu_parity (FP64 at rel_tol
 polarizations, with the phase capped so that the blocked solver finishes from
 its iterate; a flat structure whose z right-hand side is zero falls back to one
 process per polarization; against the per-polarization phase on a 1,500-atom
-sphere (same spectrum, fewer steps).
+sphere (same spectrum, fewer steps); identical right-hand sides (a block
+deflated at step 0) and a single frequency.
 """
 import sys
 
@@ -140,4 +141,31 @@ def test_block_step_cap_reports_not_converged():
     it, cyc, rr = s.stats()
     assert (it == 3).all() and (cyc == 1).all() and (rr > 1e-12).all()
     assert np.isfinite(s.spectrum()[1]).all()
+    s.close()
+
+
+def test_block_deflates_identical_right_hand_sides():
+    """A chain along (1, 1, 0) has x_i = y_i, so b_x = b_y: the block of step 0
+    is rank-deficient, its second column is deflated at once and both
+    polarizations share one Krylov space.  Also one frequency with three
+    polarizations (a single banded QR)."""
+    d = 2.9
+    t = np.arange(60, dtype=float)
+    xyz = np.stack([d * t / np.sqrt(2.0), d * t / np.sqrt(2.0), np.zeros_like(t)], 1)
+    p = M.load("ag_wfq")
+    om = np.linspace(1.5, 5.0, 9)
+    ref = O.solve_spectrum(0, xyz, M.param_vector(p), om, 0b011, 1e-4)
+    s, st, alpha, sigma, it, cyc, rr = solve(xyz, p, om, 0b011, px.PX_FP64, 1e-11, shifted=2)
+    e = rel_err(sigma, ref["sigma"])
+    say(f"[block deflation] chain 60: status {st} steps {it.max()} cycles {cyc.max()} relres {rr.max():.1e} sigma {e:.2e}")
+    assert st == px.PX_OK and cyc.max() == 1 and e <= 1e-10
+    for w in (0, 8):
+        qx, qy = s.charges(w, 0), s.charges(w, 1)
+        assert rel_err(qx, ref["q"][w, 0]) <= 1e-8 and rel_err(qy, ref["q"][w, 1]) <= 1e-8
+    s.close()
+    c = C.small_sphere()
+    ref = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), [3.3], 0b111, 1e-4)
+    s, st, alpha, sigma, it, cyc, rr = solve(c["xyz"], c["params"], [3.3], 0b111, px.PX_FP64, 1e-12, shifted=2)
+    say(f"[block one frequency] status {st} steps {it.max()} sigma {rel_err(sigma, ref['sigma']):.2e}")
+    assert st == px.PX_OK and cyc.max() == 1 and rel_err(sigma, ref["sigma"]) <= 1e-10
     s.close()
