@@ -508,6 +508,95 @@ def test_two_type_apply_and_rhs_satisfy_the_direct_solution():
         assert np.abs(y - b).max() <= 1e-10 * np.abs(b).max()
 
 
+# --------------------------- matrix-free operator, right-hand side, sampled rows
+# These three are the checkers of the GPU operator-apply and full-size tests.
+# Each is pinned to the dense, separately pinned pieces: K-bar (Laplacian
+# structure, Fermi damping), T (quadrature, finite differences) and z_q (the
+# two-atom Drude-Lorentz closed form), composed here as Eqs. (wfq-system) and
+# (wfqfmu-system) state them, and to the oracle's own dense LU solution.
+
+def _dense_operator(model, xyz, p, om_ev, aib):
+    """A(w) of Eq. (wfq-system) / (wfqfmu-system) from the pinned dense pieces:
+    charge rows Kbar (T x)_q - z_q x_q, dipole rows (T x)_mu - z_mu x_mu."""
+    n = len(xyz)
+    kb = O.kbar(xyz, p)
+    z = O.zq(p, om_ev / HARTREE_EV)
+    if model == 0:
+        return kb @ O.tqq(xyz, p) - z * np.eye(n)
+    t = O.tfull(xyz, p)
+    a = t.astype(np.complex128)
+    a[:n] = kb @ t[:n]
+    zmu = -1.0 / aib
+    return a - np.diag(np.r_[np.full(n, z), np.full(3 * n, zmu)])
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_matrix_free_apply_is_the_dense_operator(model):
+    """or_apply(x) = A(w) x column by column, each column at its own frequency,
+    with A built from the pinned K-bar, T and z_q (and z_mu = -1/alpha_IB)."""
+    p = AG if model == 0 else AU
+    xyz = G.fcc_sphere_n(60, seed=31) if model == 0 else G.fcc_rod_n(48, seed=32)
+    n = len(xyz)
+    nu = n if model == 0 else 4 * n
+    om = np.array([1.7, 2.9, 4.1])
+    aib = M.interband_alpha(p, om) if model == 1 else None
+    rng = np.random.default_rng(33)
+    x = rng.standard_normal((3, nu)) + 1j * rng.standard_normal((3, nu))
+    y = O.apply(model, xyz, pv(p), om, x, aib)
+    for c in range(3):
+        a = _dense_operator(model, xyz, pv(p), om[c], None if aib is None else aib[c])
+        ref = a @ x[c]
+        assert np.abs(y[c] - ref).max() <= 1e-12 * np.abs(ref).max()
+        # and the oracle's own dense assembly agrees
+        a2 = O.assemble(model, xyz, pv(p), om[c], None if aib is None else aib[c:c + 1])
+        assert np.abs(a2 @ x[c] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_rhs_is_minus_kbar_v_and_the_direct_solution_satisfies_it(model):
+    """or_rhs(l) = -Kbar V with V_i = -E0 r_{i,l} (and E0 on the dipole rows of
+    component l), built from the pinned K-bar; and A(w) q = b holds for the
+    charges (and dipoles) of the oracle's dense LU solve."""
+    p = AG if model == 0 else AU
+    xyz = G.fcc_sphere_n(60, seed=34) if model == 0 else G.fcc_rod_n(48, seed=35)
+    n = len(xyz)
+    nu = n if model == 0 else 4 * n
+    e0 = 1e-4
+    rb = np.asarray(xyz) / BOHR
+    kb = O.kbar(xyz, pv(p))
+    om = np.array([2.2, 3.6])
+    aib = M.interband_alpha(p, om) if model == 1 else None
+    out = O.solve_spectrum(model, xyz, pv(p), om, 0b111, e0, aib)
+    for l in range(3):
+        b = O.rhs(model, xyz, pv(p), l, e0)
+        ref = np.zeros(nu, dtype=np.complex128)
+        ref[:n] = -kb @ (-e0 * rb[:, l])
+        if model == 1:
+            ref[(1 + l) * n:(2 + l) * n] = e0
+        assert np.abs(b - ref).max() <= 1e-13 * np.abs(ref).max()
+        for i in range(len(om)):
+            a = _dense_operator(model, xyz, pv(p), om[i], None if aib is None else aib[i])
+            assert np.abs(a @ out["q"][i, l] - b).max() <= 1e-10 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_tapply_rows_are_rows_of_the_dense_t(model):
+    """or_tapply_rows gives the requested rows of T X (T^qq, or the 4N x 4N
+    dipole-model T in [q | mu_x | mu_y | mu_z] order), including the first and
+    last unknown and a row of every component block."""
+    p = AG if model == 0 else AU
+    xyz = G.fcc_sphere_n(60, seed=36) if model == 0 else G.fcc_rod_n(48, seed=37)
+    n = len(xyz)
+    nu = n if model == 0 else 4 * n
+    t = O.tqq(xyz, pv(p)) if model == 0 else O.tfull(xyz, pv(p))
+    rows = np.array(sorted({0, nu - 1, 5, n - 1} | ({n, n + 7, 2 * n + 3, 3 * n + 11} if model == 1 else set())))
+    x = np.random.default_rng(38).standard_normal((4, nu))
+    y = O.tapply_rows(model, xyz, pv(p), rows, x)
+    ref = (t @ x.T)[rows].T
+    assert y.shape == ref.shape
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_alloy_plasmon_red_shifts_and_weakens_with_gold_fraction():
     """The paper's nanoalloy trend (its Ag-Au alloy example): the plasmon peak
     of an Ag-Au sphere moves to lower energy and loses intensity as the Au
