@@ -232,55 +232,87 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
  * missed rel_tol within max_cycles (results stay readable). */
 pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt);
 
-/* Solves several structures together (all must use the same HIP stream and
- * have their frequencies set).  With opt->shifted = 1 (default) one-material
- * PX_WFQ structures are solved whole, each as by pxSolveSpectrum, by up to
- * four host threads with their own HIP streams (default priority), so that
- * their solves overlap on the device.  Every other structure's columns are
- * cut into segments of opt->block_cols columns; the segments of all of them
- * form one stacked block whose Arnoldi steps run as single grouped launches
- * (one T-apply over a tile list covering every structure, one sparse apply,
- * one pass of each orthogonalisation kernel), with segments retiring at
- * restart boundaries.  Results are read per structure with pxGet*.  Returns
- * PX_E_NOTCONV if any column of any structure missed rel_tol. */
+/* Solves several structures together (all must use the same HIP stream, have
+ * their frequencies set, and appear once).  One-material PX_WFQ structures
+ * with opt->shifted >= 1 (default 2), and every structure of 1024 atoms or
+ * more, are solved whole, each as by pxSolveSpectrum, up to four at a time,
+ * each on a HIP stream of its own (default priority, ordered after the
+ * structures' stream): the calling thread enqueues a few steps of each in
+ * turn without waiting for the device, so their launches overlap; the library
+ * starts no host threads.  Every other structure's columns are cut into
+ * segments of opt->block_cols columns; the segments of all of them form one
+ * stacked block whose Arnoldi steps run as single grouped launches (one
+ * T-apply over a tile list covering every structure, one sparse apply, one
+ * pass of each orthogonalisation kernel), with segments retiring at restart
+ * boundaries.  Results are read per structure with pxGet*; each structure's
+ * own status and message with pxGetSolveStatus.  Returns the worst status
+ * (a device or memory failure before PX_E_NOTCONV) with the first failing
+ * structure's message; the other structures' results stay valid. */
 pxStatus pxSolveBatch(const pxStructure* s, int32_t n, const pxSolveOptions* opt);
 
 /* ---- continuous batching ----------------------------------------------------
  * A server keeps one stacked block resident on the device and runs restart
- * cycles over it.  Structures submitted while others are being solved join
- * the block at the next cycle boundary if their segments fit the memory
- * budget (first come, first served); finished structures leave at cycle
- * boundaries, so requests of different sizes overlap on the device.
- * Structures stay owned by the caller and must outlive their time in the
- * server; their results are read with pxGet* once pxServerStep returned them.
- * Calls on one server are not thread-safe. */
+ * cycles over it, and beside it solves up to four larger requests whole, each
+ * on a stream of its own, a few steps per pxServerStep.  Requests submitted
+ * while others are being solved are admitted by HBM footprint as memory
+ * frees up (first come, first served within each kind); finished stacked
+ * requests leave at cycle boundaries, so requests of different sizes overlap
+ * on the device.  Structures stay owned by the caller and must outlive their
+ * time in the server; their results are read with pxGet* once pxServerStep
+ * returned them, their status with pxGetSolveStatus.  Calls on one server are
+ * not thread-safe; the library starts no host threads. */
 typedef struct pxServer_t* pxServer;
 
-/* memory_budget_bytes bounds the server's resident Krylov storage (the basis
- * of the largest restart length and the block's vectors); opt as for
- * pxSolveSpectrum (may be NULL), including block_cols.  The stream is the
- * one every submitted structure must use. */
+/* memory_budget_bytes bounds the resident storage of the admitted requests:
+ * the stacked block's rows in use times its bytes per row (the basis of the
+ * largest restart length and the block's vectors) plus the footprints of the
+ * whole solves in flight (pxSolveFootprint).  The stacked block's storage for
+ * its full row capacity (the budget over the bytes per row) is allocated at
+ * creation; the whole solves allocate theirs when admitted, so the device
+ * holds at most about twice the budget.  opt as for pxSolveSpectrum (may be
+ * NULL), including block_cols.  The stream is the one every submitted
+ * structure must use. */
 pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out);
 
 /* Queues a structure whose frequencies are set.  PX_E_OOM if it can never fit
  * the budget; PX_E_INVALID for a different stream.  A structure of 1024
- * atoms or more, or (opt->shifted = 1) a one-material PX_WFQ structure, starts
- * solving at once, whole, on one of up to four worker threads with their own
- * streams (it is returned by pxServerStep when done); the others join the
- * stacked block. */
+ * atoms or more, or (opt->shifted >= 1) a one-material PX_WFQ structure, is
+ * solved whole once admitted; the others join the stacked block. */
 pxStatus pxServerSubmit(pxServer sv, pxStructure s);
 
-/* Admits queued structures that fit, runs one restart cycle, and writes up to
- * max_finished structures that completed into finished[] (*n_finished of
- * them; more are returned by later calls).  With nothing queued or active it
- * returns at once with *n_finished = 0. */
+/* Admits queued structures that fit the budget, advances the whole solves by
+ * a few steps each, runs one restart cycle of the stacked block, and writes up
+ * to max_finished structures that completed (converged or not, or failed:
+ * see pxGetSolveStatus) into finished[] (*n_finished of them; more are
+ * returned by later calls).  With only whole solves in flight and none
+ * finished it waits for the device instead of returning at once. */
 pxStatus pxServerStep(pxServer sv, pxStructure* finished, int32_t max_finished, int32_t* n_finished);
 
-/* Queue length, structures in the block, rows in use and row capacity. */
+/* Queue length (both kinds), structures in flight (stacked block and whole
+ * solves), rows of the stacked block in use and its row capacity. */
 pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_t* rows_in_use,
                        int64_t* rows_capacity);
 
+/* Bytes charged against the budget (stacked rows in use times bytes per row
+ * plus the admitted whole solves' footprints), the budget, and the number of
+ * whole solves in flight.  Any pointer may be NULL. */
+pxStatus pxServerMemory(pxServer sv, double* bytes_in_use, double* budget_bytes, int32_t* n_whole);
+
 void pxServerDestroy(pxServer sv);
+
+/* HBM footprint (bytes) of solving s whole with the options opt (NULL:
+ * defaults): the active column block's vectors and T-apply scratch, the
+ * near-field list, and the shared-Krylov phase's basis and factors at
+ * opt->shifted_max_steps or the blocked solver's basis at max_restart_m; the
+ * figure the server admits whole solves by.  PX_E_STATE before
+ * pxSetFrequencies. */
+pxStatus pxSolveFootprint(pxStructure s, const pxSolveOptions* opt, double* bytes);
+
+/* Status of the structure's last solve (pxSolveSpectrum, pxSolveBatch or the
+ * server: PX_OK, PX_E_NOTCONV, PX_E_OOM, PX_E_DEVICE; PX_E_STATE while not
+ * solved) and its message, copied into message[message_len] (NUL-terminated,
+ * truncated; message may be NULL). */
+pxStatus pxGetSolveStatus(pxStructure s, int32_t* status, char* message, int32_t message_len);
 
 /* Induced charges q (2*n_atoms doubles) and, for PX_WFQFMU, dipoles mu
  * (6*n_atoms doubles: mu_x, mu_y, mu_z blocks) of column (i_omega, pol) in

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "PX_OK", 1: "PX_E_INVALID", 2: "PX_E_OOM", 3: "PX_E_NOTCONV",
 EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHetero", "pxSetFrequencies", "pxSolveSpectrum", "pxSolveBatch",
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
-            "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats"]
+            "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
+            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus"]
 
 
 class PxError(RuntimeError):
@@ -97,6 +98,9 @@ def load(path: str = LIB_PATH):
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
     lib.pxServerQuery.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]
+    lib.pxServerMemory.argtypes = [_vp, _dp, _dp, ctypes.POINTER(i32)]
+    lib.pxSolveFootprint.argtypes = [_vp, ctypes.POINTER(pxSolveOptions), _dp]
+    lib.pxGetSolveStatus.argtypes = [_vp, ctypes.POINTER(i32), ctypes.c_char_p, i32]
     lib.pxServerDestroy.argtypes = [_vp]
     lib.pxServerDestroy.restype = None
     lib.pxDestroyStructure.argtypes = [_vp]
@@ -356,6 +360,25 @@ def pxServerQuery(sv):
     return dict(queued=q.value, active=a.value, rows_in_use=r.value, rows_capacity=c.value)
 
 
+def pxServerMemory(sv):
+    used, budget, nw = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(load().pxServerMemory(sv, ctypes.byref(used), ctypes.byref(budget), ctypes.byref(nw)))
+    return dict(bytes_in_use=used.value, budget=budget.value, whole_solves=nw.value)
+
+
+def pxSolveFootprint(h, opt: pxSolveOptions | None = None):
+    b = ctypes.c_double()
+    _check(load().pxSolveFootprint(h, None if opt is None else ctypes.byref(opt), ctypes.byref(b)))
+    return b.value
+
+
+def pxGetSolveStatus(h):
+    st = ctypes.c_int32()
+    buf = ctypes.create_string_buffer(512)
+    _check(load().pxGetSolveStatus(h, ctypes.byref(st), buf, len(buf)))
+    return st.value, buf.value.decode()
+
+
 def pxServerDestroy(sv):
     if sv is not None:
         load().pxServerDestroy(sv)
@@ -382,6 +405,9 @@ class Server:
 
     def query(self):
         return pxServerQuery(self.h)
+
+    def memory(self):
+        return pxServerMemory(self.h)
 
     def close(self):
         if self.h is not None:
@@ -429,6 +455,13 @@ class Structure:
 
     def stats(self):
         return pxGetSolveStats(self.h, self.ncol)
+
+    def status(self):
+        """(status, message) of the last solve."""
+        return pxGetSolveStatus(self.h)
+
+    def footprint(self, **kw):
+        return pxSolveFootprint(self.h, solve_options(**kw))
 
     def induced_field(self, i_omega, pol, pts):
         return pxInducedField(self.h, i_omega, pol, pts)

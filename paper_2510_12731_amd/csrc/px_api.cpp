@@ -448,197 +448,288 @@ void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
 // Steps the host enqueues ahead of the last stop flag it looked at.
 constexpr int kLag = 2;
 
-// Solves the columns in `cols` (global indices) as one block.
-void run_block(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
-{
-    Workspace& W = s->ws;
-    int m = o.restart_m;
-    const int m_max = std::max(o.restart_m, o.max_restart_m);
-    const int64_t nup = s->g.nup;
-    const bool mixed = o.precision == PX_MIXED;
-    const bool dcgs2 = o.ortho == PX_ORTHO_DCGS2;
-    const int nchunk = px::arnoldi_chunks(nup);
-    StepTimer tm(o.timings != 0);
-    std::vector<int32_t> done_h, steps_h;
-    std::vector<double> beta;
+// ---- blocked GMRES over a set of columns, advanced step by step -------------
+// Solves the columns `act` (global indices) of a structure as one block: the
+// true FP64 residual of every column, then a restart cycle of m Arnoldi steps,
+// repeated until every column reached rel_tol (or gave up).  advance()
+// enqueues work without waiting for the device wherever it can (the steps run
+// ahead of the host and a device flag ends them), so one host thread can keep
+// several solves busy on their own streams.
+class BlockRun {
+  public:
+    BlockRun(pxStructure_t* s, std::vector<int> act, const pxSolveOptions& o)
+        : s_(s), o_(o), act_(std::move(act)), tm_(o.timings != 0)
+    {
+        Workspace& W = s->ws;
+        m_ = o.restart_m;
+        m_max_ = std::max(o.restart_m, o.max_restart_m);
+        mixed_ = o.precision == PX_MIXED;
+        dcgs2_ = o.ortho == PX_ORTHO_DCGS2;
+        na_ = (int)act_.size();
+        lda_ = pad_cols(na_, true);
+        const int64_t nup = s->g.nup;
+        std::vector<int32_t> map(act_.begin(), act_.end());
+        HC(hipMemcpyAsync(W.map, map.data(), sizeof(int32_t) * na_, hipMemcpyHostToDevice, s->st));
+        px::gather_cols(s->x, s->ldg, W.xs, lda_, W.map, na_, nup, s->st);
+        px::gather_cols(s->b, s->ldg, W.bs, lda_, W.map, na_, nup, s->st);
+        upload_shifts(s, act_, lda_);
+    }
+    bool finished() const { return state_ == DONE; }
+    // Enqueues at most max_steps Arnoldi steps (a residual pass counts as
+    // one).  Without `wait` it returns instead of waiting for a step still on
+    // the device.  Returns the work enqueued (0: it would have had to wait).
+    int advance(int max_steps, bool wait)
+    {
+        int did = 0;
+        while (state_ != DONE && did < max_steps) {
+            if (state_ == RESIDUAL) {
+                begin_cycle();
+                ++did;
+                continue;
+            }
+            bool blocked = false;
+            did += steps(max_steps - did, wait, blocked);
+            if (blocked) break;
+        }
+        return did;
+    }
 
-    int na = (int)act.size();
-    int lda = pad_cols(na, true);
-    std::vector<int32_t> map(act.begin(), act.end());
-    HC(hipMemcpyAsync(W.map, map.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
-    px::gather_cols(s->x, s->ldg, W.xs, lda, W.map, na, nup, s->st);
-    px::gather_cols(s->b, s->ldg, W.bs, lda, W.map, na, nup, s->st);
-    upload_shifts(s, act, lda);
+  private:
+    enum State { RESIDUAL, STEPS, DONE };
 
-    while (true) {
-        residual(s, W.xs, W.bs, W.rs, na, lda, o);
-        col_norms(s, W.rs, na, lda, beta);
+    // True residual, retirement of finished columns, then the set-up of one
+    // restart cycle (or DONE when no column is left).
+    void begin_cycle()
+    {
+        pxStructure_t* s = s_;
+        Workspace& W = s->ws;
+        const int64_t nup = s->g.nup;
+        residual(s, W.xs, W.bs, W.rs, na_, lda_, o_);
+        col_norms(s, W.rs, na_, lda_, beta_);
         std::vector<int> keep;
         bool slow = false;
-        for (int k = 0; k < na; ++k) {
-            const int c = act[k];
+        for (int k = 0; k < na_; ++k) {
+            const int c = act_[k];
             const double prev = s->relres[c];
-            s->relres[c] = s->bnorm[c] > 0.0 ? beta[k] / s->bnorm[c] : 0.0;
+            s->relres[c] = s->bnorm[c] > 0.0 ? beta_[k] / s->bnorm[c] : 0.0;
             if (s->cycles[c] > 0 && s->relres[c] > 0.98 * prev) s->stall[c] += 1;
             else s->stall[c] = 0;
-            if (s->relres[c] > o.rel_tol && s->cycles[c] < o.max_cycles &&
-                (o.stall_cycles == 0 || s->stall[c] < o.stall_cycles)) {
+            if (s->relres[c] > o_.rel_tol && s->cycles[c] < o_.max_cycles &&
+                (o_.stall_cycles == 0 || s->stall[c] < o_.stall_cycles)) {
                 keep.push_back(k);
                 if (s->cycles[c] > 0 && s->relres[c] > 0.7 * prev) slow = true;
             }
         }
-        if (slow && m < m_max) {
+        if (slow && m_ < m_max_) {
             // a longer Krylov space for every remaining column of the block
-            m = std::min(2 * m, m_max);
-            for (int k : keep) s->stall[act[k]] = 0;
+            m_ = std::min(2 * m_, m_max_);
+            for (int k : keep) s->stall[act_[k]] = 0;
         }
-        if (keep.empty()) break;
-        if ((int)keep.size() < na) {
+        if (keep.empty()) {
+            state_ = DONE;
+            return;
+        }
+        if ((int)keep.size() < na_) {
             // retire finished columns: compact the slot layout
             const int na2 = (int)keep.size();
             const int lda2 = pad_cols(na2, true);
             std::vector<int32_t> smap(keep.begin(), keep.end());
             HC(hipMemcpyAsync(W.map, smap.data(), sizeof(int32_t) * na2, hipMemcpyHostToDevice, s->st));
-            px::gather_cols(W.xs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            px::gather_cols(W.xs, lda_, W.tmp, lda2, W.map, na2, nup, s->st);
             std::swap(W.xs, W.tmp);
-            px::gather_cols(W.rs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            px::gather_cols(W.rs, lda_, W.tmp, lda2, W.map, na2, nup, s->st);
             std::swap(W.rs, W.tmp);
-            px::gather_cols(W.bs, lda, W.tmp, lda2, W.map, na2, nup, s->st);
+            px::gather_cols(W.bs, lda_, W.tmp, lda2, W.map, na2, nup, s->st);
             std::swap(W.bs, W.tmp);
             std::vector<int> act2;
             std::vector<double> beta2;
             for (int k : keep) {
-                act2.push_back(act[k]);
-                beta2.push_back(beta[k]);
+                act2.push_back(act_[k]);
+                beta2.push_back(beta_[k]);
             }
-            act.swap(act2);
-            beta.swap(beta2);
-            na = na2;
-            lda = lda2;
-            upload_shifts(s, act, lda);
+            act_.swap(act2);
+            beta_.swap(beta2);
+            na_ = na2;
+            lda_ = lda2;
+            upload_shifts(s, act_, lda_);
         }
-        // ---- one restart cycle ----
-        ensure_basis(s, m_max);
-        {
-            std::vector<double> tgt(lda, 0.0);
-            std::vector<double2> g0(lda, make_double2(0, 0));
-            for (int k = 0; k < na; ++k) {
-                const int c = act[k];
-                tgt[k] = std::max(0.5 * o.rel_tol * s->bnorm[c], mixed ? beta[k] * o.inner_reduction : 0.0);
-                g0[k] = make_double2(beta[k], 0.0);
-            }
-            HC(hipMemcpyAsync(W.target, tgt.data(), sizeof(double) * lda, hipMemcpyHostToDevice, s->st));
-            px::fill_zero(W.gv, sizeof(double2) * (size_t)(m + 1) * lda, s->st);
-            HC(hipMemcpyAsync(W.gv, g0.data(), sizeof(double2) * lda, hipMemcpyHostToDevice, s->st));
-            px::fill_zero(W.done, sizeof(int32_t) * lda, s->st);
-            px::fill_zero(W.steps, sizeof(int32_t) * lda, s->st);
-            HC(hipMemcpyAsync(W.nrm, beta.data(), sizeof(double) * na, hipMemcpyHostToDevice, s->st));
-            const int64_t vstride = nup * lda;
-            px::normalize(W.rs, W.nrm, nullptr, W.V, mixed ? W.X32 : nullptr, na, lda, nup, s->st);
-            const bool wide32 = mixed && lda > 4;
-            const int method = wide32 ? tapply_method(s, true, W.X32, W.Y32, 2 * lda, 2 * lda, o)
-                                      : tapply_method(s, false, W.V, W.Y64, 2 * lda, 2 * lda, o);
-            // a GEMM on the stored T cannot read the stop flag: poll one step behind, not two
-            const int lag = method == TA_STORED ? 1 : kLag;
-            // delayed orthogonalisation: the host enqueues steps ahead of the device and a
-            // device flag, raised once the rotations have finished every column, ends them
-            int32_t* stop = dcgs2 ? s->sync.flag() : nullptr;
-            if (stop) s->sync.reset(s->st);
-            tm.ensure(m);
-            int launched = 0;
-            done_h.assign(na, 0);
-            for (int k = 0; k < m; ++k) {
-                if (stop && k >= lag && s->sync.stopped(k - lag)) break;
-                double2* vk = W.V + k * vstride;
-                tm.mark(k, 0, s->st);
-                if (wide32) tapply(s, method, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop);
-                else tapply(s, method, false, vk, W.Y64, 2 * lda, 2 * lda, stop);
-                tm.mark(k, 1, s->st);
-                sparse_apply(s, wide32 ? (const void*)W.Y32 : (const void*)W.Y64, wide32, 2 * lda, vk, nullptr, W.w,
-                             na, lda, SOLVER_MU_SIGN, stop);
-                tm.mark(k, 2, s->st);
-                if (dcgs2) {
-                    // one dot pass and one update pass; column k-1 is finished here
-                    px::dots2(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st, stop);
-                    px::reduce_dots2(W.partial, nup, k + 1, W.G, na, lda, s->st, nullptr, 1, stop);
-                    px::dcgs2_coef(k, m, false, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
-                                   W.aux, W.coefQ, W.coefV, na, lda, s->st, stop);
-                    px::dcgs2_update(W.V, vstride, k, W.coefQ, W.coefV, W.w, W.npart, na, lda, nup, s->st, nullptr,
-                                     0, stop);
-                } else {
-                    // CGS2 against v_0..v_k
-                    px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
-                    px::reduce_dots(W.partial, nchunk, k + 1, W.h1, na, lda, false, s->st);
-                    px::col_update(W.V, vstride, k + 1, W.h1, W.w, nullptr, na, lda, nup, s->st);
-                    px::col_dots(W.V, vstride, k + 1, W.w, W.partial, na, lda, nup, s->st);
-                    px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
-                    px::col_update(W.V, vstride, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
-                }
-                px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st, stop);
-                if (!dcgs2)
-                    px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
-                                    nullptr, na, lda, s->st);
-                px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride, mixed ? W.X32 : nullptr, na, lda, nup,
-                              s->st, stop);
-                if (dcgs2 && k == m - 1) {
-                    // the last basis vector's correction finishes column m-1
-                    px::dots2(W.V, vstride, m + 1, W.V + m * vstride, W.partial, na, lda, nup, s->st, stop);
-                    px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st, nullptr, 1, stop);
-                    px::dcgs2_coef(m, m, true, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps,
-                                   W.aux, W.coefQ, W.coefV, na, lda, s->st, stop);
-                }
-                tm.mark(k, 3, s->st);
-                ++launched;
-                if (stop) {
-                    s->sync.publish(k, s->st);
-                } else {
-                    HC(hipMemcpyAsync(done_h.data(), W.done, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
-                    HC(hipStreamSynchronize(s->st));
-                    bool all = true;
-                    for (int q = 0; q < na; ++q) all = all && done_h[q];
-                    if (all) break;
-                }
-            }
-            px::lsq_solve(m, W.R, W.gv, W.steps, W.y, na, lda, s->st);
-            px::x_update(W.V, vstride, W.y, W.steps, m, W.xs, na, lda, nup, s->st);
-            steps_h.assign(na, 0);
-            HC(hipMemcpyAsync(steps_h.data(), W.steps, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
-            HC(hipMemcpyAsync(W.map, act.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
-            px::scatter_cols(W.xs, lda, s->x, s->ldg, W.map, na, nup, s->st);
-            HC(hipStreamSynchronize(s->st));
-            {
-                double t_ap = 0.0;
-                tm.collect(launched, t_ap, s->ms[3], s->ms[4]);
-                s->ms[wide32 ? 1 : 2] += t_ap;
-                s->tms[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += t_ap;
-            }
-            // accounting: column q took part in the matvecs of its first M_q steps (the delayed
-            // variant learns that a column is done one step after its last useful matvec)
-            const double nu = (double)s->g.nu;
-            int executed = 0;
-            int64_t colsum = 0;
-            for (int q = 0; q < na; ++q) {
-                const int mq = dcgs2 ? std::min(steps_h[q] + 1, m) : steps_h[q];
-                executed = std::max(executed, mq);
-                colsum += mq;
-                for (int k = 0; k < mq; ++k) s->work[2] += nu * (80.0 + 16.0 * (dcgs2 ? 2.0 * k + 6.0 : 4.0 * k + 10.0));
-                if (dcgs2 && steps_h[q] == m) s->work[2] += nu * 16.0 * (m + 2);   // final correction pass
-                s->iters[act[q]] += steps_h[q];
-                s->cycles[act[q]] += 1;
-                s->work[2] += 16.0 * nu * (steps_h[q] + 2);
-            }
-            s->tstats[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += executed;
-            s->counts[wide32 ? 0 : 3] += executed;
-            s->counts[wide32 ? 1 : 4] += (int64_t)executed * 2 * lda;
-            s->counts[wide32 ? 2 : 5] += 2 * colsum;
-            s->work[wide32 ? 0 : 1] += 2.0 * nu * nu * 2.0 * (double)colsum;
-            s->tflop[(wide32 ? 0 : 2) + (method == TA_STORED ? 1 : 0)] += 2.0 * nu * nu * 2.0 * (double)colsum;
+        // ---- set-up of one restart cycle
+        ensure_basis(s, m_max_);
+        const int m = m_;
+        std::vector<double> tgt(lda_, 0.0);
+        std::vector<double2> g0(lda_, make_double2(0, 0));
+        for (int k = 0; k < na_; ++k) {
+            const int c = act_[k];
+            tgt[k] = std::max(0.5 * o_.rel_tol * s->bnorm[c], mixed_ ? beta_[k] * o_.inner_reduction : 0.0);
+            g0[k] = make_double2(beta_[k], 0.0);
         }
+        HC(hipMemcpyAsync(W.target, tgt.data(), sizeof(double) * lda_, hipMemcpyHostToDevice, s->st));
+        px::fill_zero(W.gv, sizeof(double2) * (size_t)(m + 1) * lda_, s->st);
+        HC(hipMemcpyAsync(W.gv, g0.data(), sizeof(double2) * lda_, hipMemcpyHostToDevice, s->st));
+        px::fill_zero(W.done, sizeof(int32_t) * lda_, s->st);
+        px::fill_zero(W.steps, sizeof(int32_t) * lda_, s->st);
+        HC(hipMemcpyAsync(W.nrm, beta_.data(), sizeof(double) * na_, hipMemcpyHostToDevice, s->st));
+        vstride_ = nup * lda_;
+        px::normalize(W.rs, W.nrm, nullptr, W.V, mixed_ ? W.X32 : nullptr, na_, lda_, nup, s->st);
+        wide32_ = mixed_ && lda_ > 4;
+        method_ = wide32_ ? tapply_method(s, true, W.X32, W.Y32, 2 * lda_, 2 * lda_, o_)
+                          : tapply_method(s, false, W.V, W.Y64, 2 * lda_, 2 * lda_, o_);
+        // a GEMM on the stored T cannot read the stop flag: poll one step behind, not two
+        lag_ = method_ == TA_STORED ? 1 : kLag;
+        // delayed orthogonalisation: the host enqueues steps ahead of the device and a
+        // device flag, raised once the rotations have finished every column, ends them
+        stop_ = dcgs2_ ? s->sync.flag() : nullptr;
+        if (stop_) s->sync.reset(s->st);
+        tm_.ensure(m);
+        launched_ = 0;
+        k_ = 0;
+        done_h_.assign(na_, 0);
+        state_ = STEPS;
     }
-}
+
+    // Steps of the current cycle; ends the cycle when its loop is over.
+    int steps(int max_steps, bool wait, bool& blocked)
+    {
+        pxStructure_t* s = s_;
+        Workspace& W = s->ws;
+        const int64_t nup = s->g.nup;
+        const int m = m_, na = na_, lda = lda_;
+        const int nchunk = px::arnoldi_chunks(nup);
+        int did = 0;
+        while (did < max_steps) {
+            const int k = k_;
+            bool end = k >= m;
+            if (!end && stop_ && k >= lag_) {
+                if (!wait && !s->sync.ready(k - lag_)) {
+                    blocked = true;
+                    return did;
+                }
+                end = s->sync.stopped(k - lag_);
+            }
+            if (end) {
+                end_cycle();
+                return did;
+            }
+            double2* vk = W.V + k * vstride_;
+            tm_.mark(k, 0, s->st);
+            if (wide32_) tapply(s, method_, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop_);
+            else tapply(s, method_, false, vk, W.Y64, 2 * lda, 2 * lda, stop_);
+            tm_.mark(k, 1, s->st);
+            sparse_apply(s, wide32_ ? (const void*)W.Y32 : (const void*)W.Y64, wide32_, 2 * lda, vk, nullptr, W.w, na,
+                         lda, SOLVER_MU_SIGN, stop_);
+            tm_.mark(k, 2, s->st);
+            if (dcgs2_) {
+                // one dot pass and one update pass; column k-1 is finished here
+                px::dots2(W.V, vstride_, k + 1, W.w, W.partial, na, lda, nup, s->st, stop_);
+                px::reduce_dots2(W.partial, nup, k + 1, W.G, na, lda, s->st, nullptr, 1, stop_);
+                px::dcgs2_coef(k, m, false, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, W.aux,
+                               W.coefQ, W.coefV, na, lda, s->st, stop_);
+                px::dcgs2_update(W.V, vstride_, k, W.coefQ, W.coefV, W.w, W.npart, na, lda, nup, s->st, nullptr, 0,
+                                 stop_);
+            } else {
+                // CGS2 against v_0..v_k
+                px::col_dots(W.V, vstride_, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                px::reduce_dots(W.partial, nchunk, k + 1, W.h1, na, lda, false, s->st);
+                px::col_update(W.V, vstride_, k + 1, W.h1, W.w, nullptr, na, lda, nup, s->st);
+                px::col_dots(W.V, vstride_, k + 1, W.w, W.partial, na, lda, nup, s->st);
+                px::reduce_dots(W.partial, nchunk, k + 1, W.h2, na, lda, false, s->st);
+                px::col_update(W.V, vstride_, k + 1, W.h2, W.w, W.npart, na, lda, nup, s->st);
+            }
+            px::reduce_norms(W.npart, px::update_chunks(nup), W.nrm, na, lda, s->st, stop_);
+            if (!dcgs2_)
+                px::givens_step(k, m, W.h1, W.h2, W.nrm, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, nullptr,
+                                na, lda, s->st);
+            px::normalize(W.w, W.nrm, W.done, W.V + (k + 1) * vstride_, mixed_ ? W.X32 : nullptr, na, lda, nup, s->st,
+                          stop_);
+            if (dcgs2_ && k == m - 1) {
+                // the last basis vector's correction finishes column m-1
+                px::dots2(W.V, vstride_, m + 1, W.V + m * vstride_, W.partial, na, lda, nup, s->st, stop_);
+                px::reduce_dots2(W.partial, nup, m + 1, W.G, na, lda, s->st, nullptr, 1, stop_);
+                px::dcgs2_coef(m, m, true, W.G, W.nrm, W.H, W.R, W.cs, W.sn, W.gv, W.target, W.done, W.steps, W.aux,
+                               W.coefQ, W.coefV, na, lda, s->st, stop_);
+            }
+            tm_.mark(k, 3, s->st);
+            ++launched_;
+            ++k_;
+            ++did;
+            if (stop_) {
+                s->sync.publish(k, s->st);
+            } else {
+                HC(hipMemcpyAsync(done_h_.data(), W.done, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
+                HC(hipStreamSynchronize(s->st));
+                bool all = true;
+                for (int q = 0; q < na; ++q) all = all && done_h_[q];
+                if (all) {
+                    end_cycle();
+                    return did;
+                }
+            }
+        }
+        return did;
+    }
+
+    // Least squares, x update, statistics of the finished cycle.
+    void end_cycle()
+    {
+        pxStructure_t* s = s_;
+        Workspace& W = s->ws;
+        const int64_t nup = s->g.nup;
+        const int m = m_, na = na_, lda = lda_;
+        px::lsq_solve(m, W.R, W.gv, W.steps, W.y, na, lda, s->st);
+        px::x_update(W.V, vstride_, W.y, W.steps, m, W.xs, na, lda, nup, s->st);
+        std::vector<int32_t> steps_h(na, 0);
+        HC(hipMemcpyAsync(steps_h.data(), W.steps, sizeof(int32_t) * na, hipMemcpyDeviceToHost, s->st));
+        HC(hipMemcpyAsync(W.map, act_.data(), sizeof(int32_t) * na, hipMemcpyHostToDevice, s->st));
+        px::scatter_cols(W.xs, lda, s->x, s->ldg, W.map, na, nup, s->st);
+        HC(hipStreamSynchronize(s->st));
+        const bool stored = method_ == TA_STORED;
+        {
+            double t_ap = 0.0;
+            tm_.collect(launched_, t_ap, s->ms[3], s->ms[4]);
+            s->ms[wide32_ ? 1 : 2] += t_ap;
+            s->tms[(wide32_ ? 0 : 2) + (stored ? 1 : 0)] += t_ap;
+        }
+        // accounting: column q took part in the matvecs of its first M_q steps (the delayed
+        // variant learns that a column is done one step after its last useful matvec)
+        const double nu = (double)s->g.nu;
+        int executed = 0;
+        int64_t colsum = 0;
+        for (int q = 0; q < na; ++q) {
+            const int mq = dcgs2_ ? std::min(steps_h[q] + 1, m) : steps_h[q];
+            executed = std::max(executed, mq);
+            colsum += mq;
+            for (int k = 0; k < mq; ++k) s->work[2] += nu * (80.0 + 16.0 * (dcgs2_ ? 2.0 * k + 6.0 : 4.0 * k + 10.0));
+            if (dcgs2_ && steps_h[q] == m) s->work[2] += nu * 16.0 * (m + 2);   // final correction pass
+            s->iters[act_[q]] += steps_h[q];
+            s->cycles[act_[q]] += 1;
+            s->work[2] += 16.0 * nu * (steps_h[q] + 2);
+        }
+        s->tstats[(wide32_ ? 0 : 2) + (stored ? 1 : 0)] += executed;
+        s->counts[wide32_ ? 0 : 3] += executed;
+        s->counts[wide32_ ? 1 : 4] += (int64_t)executed * 2 * lda;
+        s->counts[wide32_ ? 2 : 5] += 2 * colsum;
+        s->work[wide32_ ? 0 : 1] += 2.0 * nu * nu * 2.0 * (double)colsum;
+        s->tflop[(wide32_ ? 0 : 2) + (stored ? 1 : 0)] += 2.0 * nu * nu * 2.0 * (double)colsum;
+        state_ = RESIDUAL;
+    }
+
+    pxStructure_t* s_;
+    pxSolveOptions o_;
+    std::vector<int> act_;
+    StepTimer tm_;
+    State state_ = RESIDUAL;
+    int m_ = 0, m_max_ = 0, na_ = 0, lda_ = 0;
+    bool mixed_ = false, dcgs2_ = false, wide32_ = false;
+    std::vector<double> beta_;
+    std::vector<int32_t> done_h_;
+    int64_t vstride_ = 0;
+    int method_ = TA_FLY, lag_ = kLag, launched_ = 0, k_ = 0;
+    int32_t* stop_ = nullptr;
+};
 
 // ---- shared-Krylov phase: every frequency of a one-material omegaFQ structure
-// from one real Arnoldi process per polarization (px_shifted.hip) ----------
+// from one real Arnoldi process per polarization (px_shifted.hip) or one block
+// Arnoldi process over the polarizations (px_shifted_block.hip) ----------------
 
 // Device buffers that live for one call, from the block cache: given back to
 // it once the call has marked them idle (its streams synchronised), else freed.
@@ -666,175 +757,267 @@ bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
     return o.shifted >= 1 && s->model == PX_WFQ && !s->het;
 }
 
-// Structures that pxSolveBatch and the server solve whole on the worker pool
-// instead of in the stacked block: those of the shared-Krylov phase, and
-// structures of kPoolMinAtoms atoms or more, whose own launches fill the GPU
-// and whose restart escalation would otherwise hold every segment of the
-// block (dipole-model requests of 1k-4k atoms ran 1.7x slower stacked than
-// alone).
+// Structures that pxSolveBatch and the server solve whole (each on a stream of
+// its own, several at a time) instead of in the stacked block: those of the
+// shared-Krylov phase, and structures of kPoolMinAtoms atoms or more, whose
+// own launches fill the GPU and whose restart escalation would otherwise hold
+// every segment of the block (dipole-model requests of 1k-4k atoms ran 1.7x
+// slower stacked than alone).
 constexpr int64_t kPoolMinAtoms = 1024;
 bool pooled_solve(const pxStructure_t* s, const pxSolveOptions& o)
 {
     return shifted_applies(s, o) || s->g.n >= kPoolMinAtoms;
 }
 
-void shifted_phase(pxStructure_t* s, const pxSolveOptions& o)
-{
-    const int npol = s->npol, R = npol, P = s->ncol;
-    const int64_t nup = s->g.nup;
-    hipStream_t st = s->st;
-    // basis, Hessenberg matrices and triangular factors within a quarter of the free device memory
-    size_t fr = 0, tot = 0;
-    HC(hipMemGetInfo(&fr, &tot));
-    int kcap = o.shifted_max_steps;
-    auto bytes_for = [&](double k) {
-        return (k + 1) * (double)nup * R * 8.0 + (k + 1) * k * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) +
-               k * (k + 1) / 2 * P * 16.0 + (double)px::ms_part2_doubles(R, nup, (int)k) * 8.0;
-    };
-    while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
-    const int64_t vstride = nup * R;
-    const int GB = px::ms_givens_batch();
-    Scratch sc;
-    double* V = sc.get<double>((size_t)(kcap + 1) * vstride);
-    double* u = sc.get<double>((size_t)vstride);
-    double* Y = sc.get<double>((size_t)vstride);
-    double* wt = sc.get<double>((size_t)vstride);
-    double* part = sc.get<double>(px::ms_part_doubles(R, nup, kcap));
-    double* part2 = sc.get<double>(px::ms_part2_doubles(R, nup, kcap));
-    double* G = sc.get<double>((size_t)(kcap + 1) * 2 * R);
-    double* H = sc.get<double>((size_t)(kcap + 1) * kcap * R);
-    double* coefv = sc.get<double>((size_t)kcap * R);
-    double* coefu = sc.get<double>((size_t)kcap * R);
-    double* scal = sc.get<double>((size_t)3 * R);
-    double2* z = sc.get<double2>(P);
-    double* cs = sc.get<double>((size_t)kcap * P);
-    double2* sn = sc.get<double2>((size_t)kcap * P);
-    double2* g = sc.get<double2>((size_t)(kcap + 1) * P);
-    double2* rst = sc.get<double2>(px::ms_rst_elems(P, kcap));
-    double2* ycoef = sc.get<double2>((size_t)kcap * P);
-    double* target = sc.get<double>(P);
-    double* resid = sc.get<double>(P);
-    double* bn = sc.get<double>(npol);
-    int32_t* done = sc.get<int32_t>(P);
-    int32_t* ndone = sc.get<int32_t>(1);
-
-    std::vector<double2> zh(P), g0(P);
-    std::vector<double> th(P);
-    for (int p = 0; p < P; ++p) {
-        double zr, zi;
-        shift_q(s->drude, s->mat.tau, s->omega_au[p / npol], zr, zi);
-        zh[p] = make_double2(zr, zi);
-        g0[p] = make_double2(s->bnorm[p % npol], 0.0);
-        th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+// The step loop of a shared-Krylov phase: steps on the structure's stream, the
+// frequencies' Givens QRs in batches on a second stream of the same priority
+// (beside the next steps' T-applies), the stop flag published once per batch
+// and polled by the host a few steps behind.
+class PhaseRun {
+  public:
+    virtual ~PhaseRun()
+    {
+        if (side_e_) (void)hipEventDestroy(side_e_);
+        if (side_s_) (void)hipStreamDestroy(side_s_);
     }
-    HC(hipMemcpyAsync(z, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
-    HC(hipMemcpyAsync(g, g0.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
-    HC(hipMemcpyAsync(target, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
-    HC(hipMemcpyAsync(bn, s->bnorm.data(), sizeof(double) * npol, hipMemcpyHostToDevice, st));
-    px::fill_zero(done, sizeof(int32_t) * P, st);
-    px::fill_zero(ndone, sizeof(int32_t), st);
-    px::ms_init(R, s->b, s->ldg, bn, u, nup, st);
-
-    const int method = tapply_method(s, false, u, Y, R, R, o);
-    // a stored-T GEMM cannot read the stop flag, so it polls as soon as possible;
-    // the on-the-fly kernels return at once once it is set, and a longer lag
-    // keeps the host from waiting on a Givens batch the main stream has not
-    // overtaken yet
-    const int lag = method == TA_STORED ? 1 : 2 * kLag;
-    s->sync.ensure(kcap / GB + 2);
-    int32_t* stop = s->sync.flag();
-    s->sync.reset(st);
-    // the shifted Givens QRs (a few waves) run on a second stream of the same
-    // priority, beside the next steps' T-applies; each batch waits for the step
-    // that finished its columns, and the batches keep their order on that stream
-    struct Side {
-        hipStream_t s = nullptr;
-        hipEvent_t e = nullptr;
-        ~Side()
-        {
-            if (e) (void)hipEventDestroy(e);
-            if (s) (void)hipStreamDestroy(s);
-        }
-    } side;
-    HC(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
-    HC(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
-    // Only the Givens batches can raise the stop flag, so it is published (copied
-    // to the host) once per batch, on the second stream; the host polls the
-    // batch whose publication was enqueued at least lag steps earlier.
-    std::vector<int> batch_step;
-    int polled = 0;
-    auto givens_side = [&](int k0, int kn, int at_step) {
-        HC(hipEventRecord(side.e, st));
-        HC(hipStreamWaitEvent(side.s, side.e, 0));
-        px::ms_givens(H, kcap, npol, P, k0, kn, z, cs, sn, g, target, done, resid, ndone, stop, side.s);
-        s->sync.publish((int)batch_step.size(), side.s);
-        batch_step.push_back(at_step);
-    };
-    LaunchTimer tm(o.timings != 0);
-    int launched = 0, gnext = 0;
-    bool stopped = false;
-    for (int k = 0; k < kcap && !stopped; ++k) {
-        while (polled < (int)batch_step.size() && batch_step[polled] <= k - lag) {
-            if (s->sync.stopped(polled++)) {
-                stopped = true;
+    bool ended() const { return ended_; }
+    // Enqueues at most max_steps steps; without `wait`, returns (blocked set)
+    // rather than wait for a Givens batch still on the device.
+    int advance(int max_steps, bool wait, bool& blocked)
+    {
+        int did = 0;
+        while (!ended_ && did < max_steps) {
+            const int k = launched_;
+            if (k >= kcap_) {
+                end_loop();
                 break;
             }
+            bool stopped = false;
+            while (polled_ < (int)batch_step_.size() && batch_step_[polled_] <= k - lag_) {
+                if (!wait && !s_->sync.ready(polled_)) {
+                    blocked = true;
+                    return did;
+                }
+                if (s_->sync.stopped(polled_++)) {
+                    stopped = true;
+                    break;
+                }
+            }
+            if (stopped) {
+                end_loop();
+                break;
+            }
+            step(k);
+            if (k - gnext_ >= gb_) {
+                givens_side(gnext_, gb_, k);
+                gnext_ += gb_;
+            }
+            ++launched_;
+            ++did;
         }
-        if (stopped) break;
+        return did;
+    }
+    // Finishing kernels (factors, back substitution, x = V y), a wait for the
+    // structure's stream, statistics.
+    void finish()
+    {
+        bool blocked = false;
+        while (!ended_) advance(1 << 30, true, blocked);
+        finish_kernels(launched_);
+    }
+
+  protected:
+    PhaseRun(pxStructure_t* s, const pxSolveOptions& o) : s_(s), o_(o), tm_(o.timings != 0) {}
+    // after the buffers: the stop flag, the side stream
+    void start(int kcap, int lag, int gb)
+    {
+        kcap_ = kcap;
+        lag_ = lag;
+        gb_ = gb;
+        s_->sync.ensure(kcap / gb + 2);
+        stop_ = s_->sync.flag();
+        s_->sync.reset(s_->st);
+        HC(hipStreamCreateWithFlags(&side_s_, hipStreamNonBlocking));
+        HC(hipEventCreateWithFlags(&side_e_, hipEventDisableTiming));
+    }
+    virtual void step(int k) = 0;
+    virtual void givens(int k0, int kn) = 0;   // on side_s_
+    virtual void last_step(int launched) = 0;
+    virtual void finish_kernels(int launched) = 0;
+
+    pxStructure_t* s_;
+    pxSolveOptions o_;
+    LaunchTimer tm_;
+    Scratch sc_;
+    int32_t* stop_ = nullptr;
+    hipStream_t side_s_ = nullptr;
+    hipEvent_t side_e_ = nullptr;
+    int method_ = TA_FLY;
+
+  private:
+    void givens_side(int k0, int kn, int at_step)
+    {
+        HC(hipEventRecord(side_e_, s_->st));
+        HC(hipStreamWaitEvent(side_s_, side_e_, 0));
+        givens(k0, kn);
+        s_->sync.publish((int)batch_step_.size(), side_s_);
+        batch_step_.push_back(at_step);
+    }
+    // the last column's correction (a no-op once every pair converged), the
+    // remaining Givens batches, the side stream joined into the main one
+    void end_loop()
+    {
+        last_step(launched_);
+        while (gnext_ < launched_) {
+            const int kn = std::min(gb_, launched_ - gnext_);
+            givens_side(gnext_, kn, launched_);
+            gnext_ += kn;
+        }
+        HC(hipEventRecord(side_e_, side_s_));
+        HC(hipStreamWaitEvent(s_->st, side_e_, 0));
+        ended_ = true;
+    }
+    int kcap_ = 0, lag_ = 0, gb_ = 1;
+    int launched_ = 0, gnext_ = 0, polled_ = 0;
+    bool ended_ = false;
+    std::vector<int> batch_step_;
+};
+
+// One real Arnoldi process per polarization (shifted = 1, and the fallback for
+// one polarization or a zero right-hand side).
+class ShiftedRun : public PhaseRun {
+  public:
+    ShiftedRun(pxStructure_t* s, const pxSolveOptions& o) : PhaseRun(s, o)
+    {
+        npol_ = s->npol;
+        R_ = npol_;
+        P_ = s->ncol;
+        const int R = R_, P = P_;
+        const int64_t nup = s->g.nup;
+        hipStream_t st = s->st;
+        // basis, Hessenberg matrices and triangular factors within a quarter of the free device memory
+        size_t fr = 0, tot = 0;
+        HC(hipMemGetInfo(&fr, &tot));
+        int kcap = o.shifted_max_steps;
+        auto bytes_for = [&](double k) {
+            return (k + 1) * (double)nup * R * 8.0 + (k + 1) * k * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) +
+                   k * (k + 1) / 2 * P * 16.0 + (double)px::ms_part2_doubles(R, nup, (int)k) * 8.0;
+        };
+        while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
+        kc_ = kcap;
+        vstride_ = nup * R;
+        V_ = sc_.get<double>((size_t)(kcap + 1) * vstride_);
+        u_ = sc_.get<double>((size_t)vstride_);
+        Y_ = sc_.get<double>((size_t)vstride_);
+        wt_ = sc_.get<double>((size_t)vstride_);
+        part_ = sc_.get<double>(px::ms_part_doubles(R, nup, kcap));
+        part2_ = sc_.get<double>(px::ms_part2_doubles(R, nup, kcap));
+        G_ = sc_.get<double>((size_t)(kcap + 1) * 2 * R);
+        H_ = sc_.get<double>((size_t)(kcap + 1) * kcap * R);
+        coefv_ = sc_.get<double>((size_t)kcap * R);
+        coefu_ = sc_.get<double>((size_t)kcap * R);
+        scal_ = sc_.get<double>((size_t)3 * R);
+        z_ = sc_.get<double2>(P);
+        cs_ = sc_.get<double>((size_t)kcap * P);
+        sn_ = sc_.get<double2>((size_t)kcap * P);
+        g_ = sc_.get<double2>((size_t)(kcap + 1) * P);
+        rst_ = sc_.get<double2>(px::ms_rst_elems(P, kcap));
+        ycoef_ = sc_.get<double2>((size_t)kcap * P);
+        target_ = sc_.get<double>(P);
+        resid_ = sc_.get<double>(P);
+        double* bn = sc_.get<double>(npol_);
+        done_ = sc_.get<int32_t>(P);
+        ndone_ = sc_.get<int32_t>(1);
+
+        std::vector<double2> zh(P), g0(P);
+        std::vector<double> th(P);
+        for (int p = 0; p < P; ++p) {
+            double zr, zi;
+            shift_q(s->drude, s->mat.tau, s->omega_au[p / npol_], zr, zi);
+            zh[p] = make_double2(zr, zi);
+            g0[p] = make_double2(s->bnorm[p % npol_], 0.0);
+            th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+        }
+        HC(hipMemcpyAsync(z_, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+        HC(hipMemcpyAsync(g_, g0.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+        HC(hipMemcpyAsync(target_, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
+        HC(hipMemcpyAsync(bn, s->bnorm.data(), sizeof(double) * npol_, hipMemcpyHostToDevice, st));
+        px::fill_zero(done_, sizeof(int32_t) * P, st);
+        px::fill_zero(ndone_, sizeof(int32_t), st);
+        px::ms_init(R, s->b, s->ldg, bn, u_, nup, st);
+        method_ = tapply_method(s, false, u_, Y_, R, R, o);
+        // a stored-T GEMM cannot read the stop flag, so it polls as soon as possible;
+        // the on-the-fly kernels return at once once it is set, and a longer lag
+        // keeps the host from waiting on a Givens batch the main stream has not
+        // overtaken yet
+        start(kcap, method_ == TA_STORED ? 1 : 2 * kLag, px::ms_givens_batch());
+    }
+
+  protected:
+    void step(int k) override
+    {
+        pxStructure_t* s = s_;
         // wt = Kbar T u for the candidate u of v_k
-        tapply(s, method, false, u, Y, R, R, stop, tm.events(k, 0));
-        px::ms_spmv(R, s->g, Y, wt, st, stop, tm.events(k, 1));
+        tapply(s, method_, false, u_, Y_, R_, R_, stop_, tm_.events(k, 0));
+        px::ms_spmv(R_, s->g, Y_, wt_, s->st, stop_, tm_.events(k, 1));
         // one dot and one update pass: v_k final, column k-1 of Hbar final
-        px::ms_step(R, V, vstride, k, u, wt, part, part2, G, H, kcap, coefv, coefu, scal, nup, false, st, stop,
-                    tm.events(k, 2));
-        // the shifted Givens QRs take GB finished Hessenberg columns per launch
-        if (k - gnext >= GB) {
-            givens_side(gnext, GB, k);
-            gnext += GB;
+        px::ms_step(R_, V_, vstride_, k, u_, wt_, part_, part2_, G_, H_, kc_, coefv_, coefu_, scal_, s->g.nup, false,
+                    s->st, stop_, tm_.events(k, 2));
+    }
+    void givens(int k0, int kn) override
+    {
+        px::ms_givens(H_, kc_, npol_, P_, k0, kn, z_, cs_, sn_, g_, target_, done_, resid_, ndone_, stop_, side_s_);
+    }
+    void last_step(int launched) override
+    {
+        px::ms_step(R_, V_, vstride_, launched, u_, u_, part_, part2_, G_, H_, kc_, coefv_, coefu_, scal_, s_->g.nup,
+                    true, s_->st, stop_);
+    }
+    void finish_kernels(int launched) override
+    {
+        pxStructure_t* s = s_;
+        hipStream_t st = s->st;
+        const int P = P_, npol = npol_, R = R_;
+        px::ms_rfactor(H_, kc_, npol, P, launched, z_, cs_, sn_, done_, rst_, st);
+        px::ms_backsub(rst_, P, launched, done_, g_, ycoef_, st);
+        px::ms_xcombine(R, V_, vstride_, launched, done_, ycoef_, P, s->x, s->ldg, s->g.nup, st);
+        std::vector<int32_t> dh(P);
+        std::vector<double> rh(P);
+        HC(hipMemcpyAsync(dh.data(), done_, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
+        HC(hipMemcpyAsync(rh.data(), resid_, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+        HC(hipStreamSynchronize(st));
+        sc_.idle = true;   // nothing on either stream uses the scratch any more
+        int executed = 0;
+        for (int p = 0; p < P; ++p) {
+            s->iters[p] = dh[p] ? dh[p] : launched;
+            s->cycles[p] = 1;
+            s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
+            executed = std::max(executed, s->iters[p]);
         }
-        ++launched;
+        // the device ran one step past the last column it needed (that column's correction)
+        executed = std::min(launched, executed + 1);
+        double t_ap = 0.0;
+        tm_.collect(executed, t_ap, s->ms[3], s->ms[4]);
+        s->ms[2] += t_ap;
+        s->tms[method_ == TA_STORED ? 3 : 2] += t_ap;
+        const double nu = (double)s->g.nu;
+        s->tstats[method_ == TA_STORED ? 3 : 2] += executed;
+        s->counts[3] += executed;
+        s->counts[4] += (int64_t)executed * R;
+        s->counts[5] += (int64_t)executed * npol;
+        s->tflop[method_ == TA_STORED ? 3 : 2] += 2.0 * nu * nu * npol * executed;
+        s->work[1] += 2.0 * nu * nu * npol * executed;
+        // one dot and one update pass over the basis per step
+        s->work[2] += 2.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
     }
-    // the last column's correction (a no-op once every pair converged), then its rotations
-    px::ms_step(R, V, vstride, launched, u, u, part, part2, G, H, kcap, coefv, coefu, scal, nup, true, st, stop);
-    while (gnext < launched) {
-        const int kn = std::min(GB, launched - gnext);
-        givens_side(gnext, kn, launched);
-        gnext += kn;
-    }
-    HC(hipEventRecord(side.e, side.s));
-    HC(hipStreamWaitEvent(st, side.e, 0));
-    px::ms_rfactor(H, kcap, npol, P, launched, z, cs, sn, done, rst, st);
-    px::ms_backsub(rst, P, launched, done, g, ycoef, st);
-    px::ms_xcombine(R, V, vstride, launched, done, ycoef, P, s->x, s->ldg, nup, st);
-    std::vector<int32_t> dh(P);
-    std::vector<double> rh(P);
-    HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
-    HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
-    HC(hipStreamSynchronize(st));
-    sc.idle = true;   // nothing on either stream uses the scratch any more
-    int executed = 0;
-    for (int p = 0; p < P; ++p) {
-        s->iters[p] = dh[p] ? dh[p] : launched;
-        s->cycles[p] = 1;
-        s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
-        executed = std::max(executed, s->iters[p]);
-    }
-    // the device ran one step past the last column it needed (that column's correction)
-    executed = std::min(launched, executed + 1);
-    double t_ap = 0.0;
-    tm.collect(executed, t_ap, s->ms[3], s->ms[4]);
-    s->ms[2] += t_ap;
-    s->tms[method == TA_STORED ? 3 : 2] += t_ap;
-    const double nu = (double)s->g.nu;
-    s->tstats[method == TA_STORED ? 3 : 2] += executed;
-    s->counts[3] += executed;
-    s->counts[4] += (int64_t)executed * R;
-    s->counts[5] += (int64_t)executed * npol;
-    s->tflop[method == TA_STORED ? 3 : 2] += 2.0 * nu * nu * npol * executed;
-    s->work[1] += 2.0 * nu * nu * npol * executed;
-    // one dot and one update pass over the basis per step
-    s->work[2] += 2.0 * 8.0 * (double)s->g.n * npol * (double)executed * (executed + 1) / 2.0;
-}
+
+  private:
+    int npol_ = 0, R_ = 0, P_ = 0, kc_ = 0;
+    int64_t vstride_ = 0;
+    double *V_, *u_, *Y_, *wt_, *part_, *part2_, *G_, *H_, *coefv_, *coefu_, *scal_, *cs_, *target_, *resid_;
+    double2 *z_, *sn_, *g_, *rst_, *ycoef_;
+    int32_t *done_, *ndone_;
+};
 
 // The shared-Krylov phase over a block of polarizations: one block Arnoldi
 // process for the npol right-hand sides (px_shifted_block.hip), for 2 or 3
@@ -847,156 +1030,139 @@ bool block_applies(const pxStructure_t* s, const pxSolveOptions& o)
     return true;
 }
 
-void shifted_phase_block(pxStructure_t* s, const pxSolveOptions& o)
-{
-    const int R = s->npol, P = s->ncol, NW = P / R;
-    const int64_t nup = s->g.nup;
-    hipStream_t st = s->st;
-    size_t fr = 0, tot = 0;
-    HC(hipMemGetInfo(&fr, &tot));
-    // the back substitution holds a frequency's kcap R rows of its right-hand
-    // sides in registers (at most 4096)
-    int kcap = std::min(o.shifted_max_steps, 4096 / R);
-    auto bytes_for = [&](double k) {
-        const double kc = k * R;
-        return (k + 1) * (double)nup * R * 8.0 + (kc + R) * kc * 8.0 + kc * R * NW * 24.0 + (kc + R) * NW * R * 16.0 +
-               kc * (kc + 1) / 2 * NW * 16.0 + kc * P * 16.0 + (double)px::msb_part2_doubles(R, nup, (int)k) * 8.0;
-    };
-    while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
-    const int RR = R * R;
-    const int ldh = kcap * R;
-    const int64_t vstride = nup * R;
-    Scratch sc;
-    double* V = sc.get<double>((size_t)(kcap + 1) * vstride);
-    double* u = sc.get<double>((size_t)vstride);
-    double* Y = sc.get<double>((size_t)vstride);
-    double* wt = sc.get<double>((size_t)vstride);
-    double* part = sc.get<double>(px::msb_part_doubles(R, kcap));
-    double* part2 = sc.get<double>(px::msb_part2_doubles(R, nup, kcap));
-    double* G = sc.get<double>((size_t)(kcap + 1) * 2 * RR);
-    double* Hb = sc.get<double>((size_t)(kcap + 1) * R * ldh);
-    double* coefv = sc.get<double>((size_t)kcap * RR);
-    double* coefu = sc.get<double>((size_t)kcap * RR);
-    double* scal = sc.get<double>((size_t)2 * RR);
-    double* rho0 = sc.get<double>((size_t)RR);
-    double2* z = sc.get<double2>(P);
-    double* rc = sc.get<double>((size_t)kcap * R * R * NW);
-    double2* rs = sc.get<double2>((size_t)kcap * R * R * NW);
-    double2* g = sc.get<double2>((size_t)(kcap + 1) * R * NW * R);
-    double* target = sc.get<double>(P);
-    double* resid = sc.get<double>(P);
-    int32_t* done = sc.get<int32_t>(P);
-    int32_t* ndone = sc.get<int32_t>(1);
+class BlockShiftedRun : public PhaseRun {
+  public:
+    BlockShiftedRun(pxStructure_t* s, const pxSolveOptions& o) : PhaseRun(s, o)
+    {
+        R_ = s->npol;
+        P_ = s->ncol;
+        NW_ = P_ / R_;
+        const int R = R_, P = P_, NW = NW_;
+        const int64_t nup = s->g.nup;
+        hipStream_t st = s->st;
+        size_t fr = 0, tot = 0;
+        HC(hipMemGetInfo(&fr, &tot));
+        // the back substitution holds a frequency's kcap R rows of its right-hand
+        // sides in registers (at most 4096)
+        int kcap = std::min(o.shifted_max_steps, 4096 / R);
+        auto bytes_for = [&](double k) {
+            const double kc = k * R;
+            return (k + 1) * (double)nup * R * 8.0 + (kc + R) * kc * 8.0 + kc * R * NW * 24.0 +
+                   (kc + R) * NW * R * 16.0 + kc * (kc + 1) / 2 * NW * 16.0 + kc * P * 16.0 +
+                   (double)px::msb_part2_doubles(R, nup, (int)k) * 8.0;
+        };
+        while (kcap > 8 && bytes_for(kcap) > 0.25 * (double)fr) kcap = kcap * 3 / 4;
+        const int RR = R * R;
+        ldh_ = kcap * R;
+        vstride_ = nup * R;
+        V_ = sc_.get<double>((size_t)(kcap + 1) * vstride_);
+        u_ = sc_.get<double>((size_t)vstride_);
+        Y_ = sc_.get<double>((size_t)vstride_);
+        wt_ = sc_.get<double>((size_t)vstride_);
+        part_ = sc_.get<double>(px::msb_part_doubles(R, kcap));
+        part2_ = sc_.get<double>(px::msb_part2_doubles(R, nup, kcap));
+        G_ = sc_.get<double>((size_t)(kcap + 1) * 2 * RR);
+        Hb_ = sc_.get<double>((size_t)(kcap + 1) * R * ldh_);
+        coefv_ = sc_.get<double>((size_t)kcap * RR);
+        coefu_ = sc_.get<double>((size_t)kcap * RR);
+        scal_ = sc_.get<double>((size_t)2 * RR);
+        rho0_ = sc_.get<double>((size_t)RR);
+        z_ = sc_.get<double2>(P);
+        rc_ = sc_.get<double>((size_t)kcap * R * R * NW);
+        rs_ = sc_.get<double2>((size_t)kcap * R * R * NW);
+        g_ = sc_.get<double2>((size_t)(kcap + 1) * R * NW * R);
+        target_ = sc_.get<double>(P);
+        resid_ = sc_.get<double>(P);
+        done_ = sc_.get<int32_t>(P);
+        ndone_ = sc_.get<int32_t>(1);
 
-    std::vector<double2> zh(P);
-    std::vector<double> th(P);
-    for (int p = 0; p < P; ++p) {
-        double zr, zi;
-        shift_q(s->drude, s->mat.tau, s->omega_au[p / R], zr, zi);
-        zh[p] = make_double2(zr, zi);
-        th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+        std::vector<double2> zh(P);
+        std::vector<double> th(P);
+        for (int p = 0; p < P; ++p) {
+            double zr, zi;
+            shift_q(s->drude, s->mat.tau, s->omega_au[p / R], zr, zi);
+            zh[p] = make_double2(zr, zi);
+            th[p] = 0.5 * o.rel_tol * s->bnorm[p];
+        }
+        HC(hipMemcpyAsync(z_, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
+        HC(hipMemcpyAsync(target_, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
+        px::fill_zero(Hb_, sizeof(double) * (size_t)(kcap + 1) * R * ldh_, st);
+        px::fill_zero(g_, sizeof(double2) * (size_t)(kcap + 1) * R * NW * R, st);
+        px::fill_zero(done_, sizeof(int32_t) * P, st);
+        px::fill_zero(ndone_, sizeof(int32_t), st);
+        px::msb_init(R, s->b, s->ldg, u_, nup, st);
+        method_ = tapply_method(s, false, u_, Y_, R, R, o);
+        // the banded QRs run on the side stream, a launch every GBB block steps
+        start(kcap, method_ == TA_STORED ? 1 : 2 * kLag, px::msb_givens_cols() / R);
     }
-    HC(hipMemcpyAsync(z, zh.data(), sizeof(double2) * P, hipMemcpyHostToDevice, st));
-    HC(hipMemcpyAsync(target, th.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
-    px::fill_zero(Hb, sizeof(double) * (size_t)(kcap + 1) * R * ldh, st);
-    px::fill_zero(g, sizeof(double2) * (size_t)(kcap + 1) * R * NW * R, st);
-    px::fill_zero(done, sizeof(int32_t) * P, st);
-    px::fill_zero(ndone, sizeof(int32_t), st);
-    px::msb_init(R, s->b, s->ldg, u, nup, st);
 
-    const int method = tapply_method(s, false, u, Y, R, R, o);
-    const int lag = method == TA_STORED ? 1 : 2 * kLag;
-    const int GBB = px::msb_givens_cols() / R;   // block steps per banded-QR launch
-    s->sync.ensure(kcap / GBB + 2);
-    int32_t* stop = s->sync.flag();
-    s->sync.reset(st);
-    // the banded QRs run on a second stream of the same priority, beside the
-    // next steps' T-applies, and publish the stop flag once per launch
-    struct Side {
-        hipStream_t s = nullptr;
-        hipEvent_t e = nullptr;
-        ~Side()
-        {
-            if (e) (void)hipEventDestroy(e);
-            if (s) (void)hipStreamDestroy(s);
-        }
-    } side;
-    HC(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
-    HC(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
-    std::vector<int> batch_step;
-    int polled = 0;
-    auto givens_side = [&](int kb0, int nkb, int at_step) {
-        HC(hipEventRecord(side.e, st));
-        HC(hipStreamWaitEvent(side.s, side.e, 0));
-        px::msb_givens(R, Hb, ldh, NW, kb0 * R, nkb * R, z, rc, rs, g, rho0, target, done, resid, ndone, stop, side.s);
-        s->sync.publish((int)batch_step.size(), side.s);
-        batch_step.push_back(at_step);
-    };
-    LaunchTimer tm(o.timings != 0);
-    int launched = 0, gnext = 0;
-    bool stopped = false;
-    for (int k = 0; k < kcap && !stopped; ++k) {
-        while (polled < (int)batch_step.size() && batch_step[polled] <= k - lag) {
-            if (s->sync.stopped(polled++)) {
-                stopped = true;
-                break;
-            }
-        }
-        if (stopped) break;
+  protected:
+    void step(int k) override
+    {
+        pxStructure_t* s = s_;
         // Wt = Kbar T U for the candidate block U of V_k
-        tapply(s, method, false, u, Y, R, R, stop, tm.events(k, 0));
-        px::ms_spmv(R, s->g, Y, wt, st, stop, tm.events(k, 1));
-        px::msb_step(R, V, vstride, k, u, wt, part, part2, G, Hb, ldh, coefv, coefu, scal, rho0, nup, false, st, stop,
-                     tm.events(k, 2));
-        // block columns < k are final after step k
-        if (k - gnext >= GBB) {
-            givens_side(gnext, GBB, k);
-            gnext += GBB;
+        tapply(s, method_, false, u_, Y_, R_, R_, stop_, tm_.events(k, 0));
+        px::ms_spmv(R_, s->g, Y_, wt_, s->st, stop_, tm_.events(k, 1));
+        px::msb_step(R_, V_, vstride_, k, u_, wt_, part_, part2_, G_, Hb_, ldh_, coefv_, coefu_, scal_, rho0_,
+                     s->g.nup, false, s->st, stop_, tm_.events(k, 2));
+    }
+    void givens(int kb0, int nkb) override
+    {
+        px::msb_givens(R_, Hb_, ldh_, NW_, kb0 * R_, nkb * R_, z_, rc_, rs_, g_, rho0_, target_, done_, resid_, ndone_,
+                       stop_, side_s_);
+    }
+    void last_step(int launched) override
+    {
+        px::msb_step(R_, V_, vstride_, launched, u_, u_, part_, part2_, G_, Hb_, ldh_, coefv_, coefu_, scal_, rho0_,
+                     s_->g.nup, true, s_->st, stop_);
+    }
+    void finish_kernels(int launched) override
+    {
+        pxStructure_t* s = s_;
+        hipStream_t st = s->st;
+        const int R = R_, P = P_, NW = NW_;
+        const int kcols = launched * R;
+        double2* rst = sc_.get<double2>(std::max<size_t>(1, px::msb_rst_elems(NW, kcols)));
+        double2* ycoef = sc_.get<double2>(std::max<size_t>(1, (size_t)kcols * P));
+        px::msb_finish_solve(R, Hb_, ldh_, NW, kcols, z_, rc_, rs_, done_, rst, g_, ycoef, V_, vstride_, s->x, s->ldg,
+                             s->g.nup, st);
+        std::vector<int32_t> dh(P);
+        std::vector<double> rh(P);
+        HC(hipMemcpyAsync(dh.data(), done_, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
+        HC(hipMemcpyAsync(rh.data(), resid_, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+        HC(hipStreamSynchronize(st));
+        sc_.idle = true;   // nothing on either stream uses the scratch any more
+        int executed = 0;
+        for (int p = 0; p < P; ++p) {
+            s->iters[p] = dh[p] ? (dh[p] + R - 1) / R : launched;
+            s->cycles[p] = 1;
+            s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
+            executed = std::max(executed, s->iters[p]);
         }
-        ++launched;
+        executed = std::min(launched, executed + 1);
+        double t_ap = 0.0;
+        tm_.collect(executed, t_ap, s->ms[3], s->ms[4]);
+        s->ms[2] += t_ap;
+        s->tms[method_ == TA_STORED ? 3 : 2] += t_ap;
+        const double nu = (double)s->g.nu;
+        s->tstats[method_ == TA_STORED ? 3 : 2] += executed;
+        s->counts[3] += executed;
+        s->counts[4] += (int64_t)executed * R;
+        s->counts[5] += (int64_t)executed * R;
+        s->tflop[method_ == TA_STORED ? 3 : 2] += 2.0 * nu * nu * R * executed;
+        s->work[1] += 2.0 * nu * nu * R * executed;
+        // one dot pass (2 R^2 products per basis block and row) and one update
+        // pass (2 R^2) per step
+        s->work[2] += 2.0 * 2.0 * 2.0 * R * R * (double)s->g.n * (double)executed * (executed + 1) / 2.0;
     }
-    px::msb_step(R, V, vstride, launched, u, u, part, part2, G, Hb, ldh, coefv, coefu, scal, rho0, nup, true, st,
-                 stop);
-    while (gnext < launched) {
-        const int kn = std::min(GBB, launched - gnext);
-        givens_side(gnext, kn, launched);
-        gnext += kn;
-    }
-    HC(hipEventRecord(side.e, side.s));
-    HC(hipStreamWaitEvent(st, side.e, 0));
-    const int kcols = launched * R;
-    double2* rst = sc.get<double2>(std::max<size_t>(1, px::msb_rst_elems(NW, kcols)));
-    double2* ycoef = sc.get<double2>(std::max<size_t>(1, (size_t)kcols * P));
-    px::msb_finish_solve(R, Hb, ldh, NW, kcols, z, rc, rs, done, rst, g, ycoef, V, vstride, s->x, s->ldg, nup, st);
-    std::vector<int32_t> dh(P);
-    std::vector<double> rh(P);
-    HC(hipMemcpyAsync(dh.data(), done, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
-    HC(hipMemcpyAsync(rh.data(), resid, sizeof(double) * P, hipMemcpyDeviceToHost, st));
-    HC(hipStreamSynchronize(st));
-    sc.idle = true;   // nothing on either stream uses the scratch any more
-    int executed = 0;
-    for (int p = 0; p < P; ++p) {
-        s->iters[p] = dh[p] ? (dh[p] + R - 1) / R : launched;
-        s->cycles[p] = 1;
-        s->relres[p] = s->bnorm[p] > 0.0 ? rh[p] / s->bnorm[p] : 0.0;
-        executed = std::max(executed, s->iters[p]);
-    }
-    executed = std::min(launched, executed + 1);
-    double t_ap = 0.0;
-    tm.collect(executed, t_ap, s->ms[3], s->ms[4]);
-    s->ms[2] += t_ap;
-    s->tms[method == TA_STORED ? 3 : 2] += t_ap;
-    const double nu = (double)s->g.nu;
-    s->tstats[method == TA_STORED ? 3 : 2] += executed;
-    s->counts[3] += executed;
-    s->counts[4] += (int64_t)executed * R;
-    s->counts[5] += (int64_t)executed * R;
-    s->tflop[method == TA_STORED ? 3 : 2] += 2.0 * nu * nu * R * executed;
-    s->work[1] += 2.0 * nu * nu * R * executed;
-    // one dot pass (2 R^2 products per basis block and row) and one update
-    // pass (2 R^2) per step
-    s->work[2] += 2.0 * 2.0 * 2.0 * R * R * (double)s->g.n * (double)executed * (executed + 1) / 2.0;
-}
+
+  private:
+    int R_ = 0, P_ = 0, NW_ = 0, ldh_ = 0;
+    int64_t vstride_ = 0;
+    double *V_, *u_, *Y_, *wt_, *part_, *part2_, *G_, *Hb_, *coefv_, *coefu_, *scal_, *rho0_, *rc_, *target_, *resid_;
+    double2 *z_, *rs_, *g_;
+    int32_t *done_, *ndone_;
+};
 
 pxStatus check_options(const pxSolveOptions& o)
 {
@@ -1012,39 +1178,178 @@ pxStatus check_options(const pxSolveOptions& o)
     return PX_OK;
 }
 
+// Status of a structure the stacked engine finished.
+void set_engine_status(pxStructure_t* s, const pxSolveOptions& o)
+{
+    s->last_status = PX_OK;
+    s->last_error.clear();
+    for (int c = 0; c < s->ncol; ++c)
+        if (!(s->relres[c] <= o.rel_tol)) {
+            s->last_status = PX_E_NOTCONV;
+            s->last_error = "some columns did not reach rel_tol";
+        }
+}
+
+// The stored-T GEMMs' library handle follows the structure's stream.
+void rebind_blas(pxStructure_t* s)
+{
+    if (s->blas) (void)rocblas_set_stream(static_cast<rocblas_handle>(s->blas), s->st);
+}
+
+// ---- one structure's whole solve, advanced step by step ----------------------
+// Right-hand sides and norms, the shared-Krylov phase where it applies, the
+// blocked solver over every column block (the true FP64 residual of every
+// column, restart cycles for any column above rel_tol), the observables.
+// pxSolveSpectrum drives it to the end on the structure's stream; the batch
+// and the server drive several at once from the calling thread, each on a
+// stream of its own (ordered after the structure's stream when it starts, and
+// the structure's stream after it when it ends), so their launches overlap on
+// the device without host threads.
+class WholeSolve {
+  public:
+    WholeSolve(pxStructure_t* s, const pxSolveOptions& o, bool own_stream) : s_(s), o_(o)
+    {
+        t0_ = std::chrono::steady_clock::now();
+        for (double& v : s->ms) v = 0.0;
+        for (int64_t& v : s->counts) v = 0;
+        for (double& v : s->work) v = 0.0;
+        for (int64_t& v : s->tstats) v = 0;
+        for (double& v : s->tms) v = 0.0;
+        for (double& v : s->tflop) v = 0.0;
+        s->last_status = PX_E_STATE;
+        s->last_error = "solve in progress";
+        if (own_stream) {
+            HC(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+            HC(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+            HC(hipEventRecord(ev_, s->st));
+            HC(hipStreamWaitEvent(st_, ev_, 0));
+            home_ = s->st;
+            s->st = st_;
+            moved_ = true;
+        }
+        try {
+            blk_ = o.max_block_cols > 0 ? std::min(o.max_block_cols, s->ncol) : s->ncol;
+            ensure_vectors(s, pad_cols(blk_, true));
+            prepare_solve(s);
+            if (shifted_applies(s, o)) {
+                if (block_applies(s, o)) phase_.reset(new BlockShiftedRun(s, o));
+                else phase_.reset(new ShiftedRun(s, o));
+            } else {
+                next_block();
+            }
+        } catch (...) {
+            phase_.reset();
+            block_.reset();
+            hand_back();
+            if (ev_) (void)hipEventDestroy(ev_);
+            if (st_) (void)hipStreamDestroy(st_);
+            throw;
+        }
+    }
+    ~WholeSolve()
+    {
+        phase_.reset();
+        block_.reset();
+        hand_back();
+        if (ev_) (void)hipEventDestroy(ev_);
+        if (st_) (void)hipStreamDestroy(st_);
+    }
+    WholeSolve(const WholeSolve&) = delete;
+    WholeSolve& operator=(const WholeSolve&) = delete;
+
+    bool finished() const { return fin_; }
+    pxStructure_t* structure() const { return s_; }
+    // Enqueues at most about max_steps steps; without `wait` it returns
+    // rather than wait for work still on the device.  Returns the work done
+    // (0: it would have had to wait).
+    int advance(int max_steps, bool wait)
+    {
+        int did = 0;
+        while (!fin_ && did < max_steps) {
+            if (phase_) {
+                bool blocked = false;
+                did += phase_->advance(max_steps - did, wait, blocked);
+                if (phase_->ended()) {
+                    phase_->finish();
+                    phase_.reset();
+                    next_block();
+                    ++did;
+                } else if (blocked) {
+                    break;
+                }
+                continue;
+            }
+            const int n = block_->advance(max_steps - did, wait);
+            did += n;
+            if (block_->finished()) {
+                block_.reset();
+                next_block();
+                ++did;
+            } else if (n == 0) {
+                break;
+            }
+        }
+        return did;
+    }
+
+  private:
+    void next_block()
+    {
+        if (c0_ < s_->ncol) {
+            std::vector<int> cols;
+            for (int c = c0_; c < std::min(s_->ncol, c0_ + blk_); ++c) cols.push_back(c);
+            c0_ += blk_;
+            block_.reset(new BlockRun(s_, cols, o_));
+            return;
+        }
+        finish_solve(s_);
+        hand_back();
+        s_->ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0_).count();
+        s_->ms[5] = s_->ms[0] - s_->ms[1] - s_->ms[2] - s_->ms[3] - s_->ms[4];
+        s_->last_status = PX_OK;
+        s_->last_error.clear();
+        for (int c = 0; c < s_->ncol; ++c)
+            if (!(s_->relres[c] <= o_.rel_tol)) {
+                s_->last_status = PX_E_NOTCONV;
+                s_->last_error = "some columns did not reach rel_tol";
+            }
+        fin_ = true;
+    }
+    // the structure back on its own stream, ordered after everything this solve enqueued
+    void hand_back()
+    {
+        if (!moved_) return;
+        moved_ = false;
+        if (hipEventRecord(ev_, st_) == hipSuccess) (void)hipStreamWaitEvent(home_, ev_, 0);
+        (void)hipStreamSynchronize(st_);
+        s_->st = home_;
+        rebind_blas(s_);
+    }
+
+    pxStructure_t* s_;
+    pxSolveOptions o_;
+    std::chrono::steady_clock::time_point t0_;
+    hipStream_t st_ = nullptr, home_ = nullptr;
+    hipEvent_t ev_ = nullptr;
+    bool moved_ = false, fin_ = false;
+    int blk_ = 0, c0_ = 0;
+    std::unique_ptr<PhaseRun> phase_;
+    std::unique_ptr<BlockRun> block_;
+};
+
 pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
 {
     if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrum: call pxSetFrequencies first");
     if (check_options(o) != PX_OK) return PX_E_INVALID;
-    auto t0 = std::chrono::steady_clock::now();
-    for (double& v : s->ms) v = 0.0;
-    for (int64_t& v : s->counts) v = 0;
-    for (double& v : s->work) v = 0.0;
-    for (int64_t& v : s->tstats) v = 0;
-    for (double& v : s->tms) v = 0.0;
-    for (double& v : s->tflop) v = 0.0;
-    const int ncol = s->ncol;
-    const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, ncol) : ncol;
-    ensure_vectors(s, pad_cols(blk, true));
-    prepare_solve(s);
-    if (shifted_applies(s, o)) {
-        if (block_applies(s, o)) shifted_phase_block(s, o);
-        else shifted_phase(s, o);
-    }
-    for (int c0 = 0; c0 < ncol; c0 += blk) {
-        std::vector<int> cols;
-        for (int c = c0; c < std::min(ncol, c0 + blk); ++c) cols.push_back(c);
-        run_block(s, cols, o);
-    }
-    finish_solve(s);
-    s->ms[0] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    s->ms[5] = s->ms[0] - s->ms[1] - s->ms[2] - s->ms[3] - s->ms[4];
-    for (int c = 0; c < ncol; ++c)
-        if (!(s->relres[c] <= o.rel_tol)) return fail(PX_E_NOTCONV, "some columns did not reach rel_tol");
+    WholeSolve w(s, o, false);
+    while (!w.finished()) w.advance(1 << 30, true);
+    if (s->last_status != PX_OK) return fail(s->last_status, s->last_error);
     return PX_OK;
 }
 
 bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+pxStatus status_of(const HipError& h) { return h.e == hipErrorOutOfMemory ? PX_E_OOM : PX_E_DEVICE; }
 
 template <typename F>
 pxStatus guarded(F&& f)
@@ -1052,8 +1357,7 @@ pxStatus guarded(F&& f)
     try {
         return f();
     } catch (const HipError& h) {
-        return fail(h.e == hipErrorOutOfMemory ? PX_E_OOM : PX_E_DEVICE,
-                    std::string(h.where) + ": " + hipGetErrorString(h.e));
+        return fail(status_of(h), std::string(h.where) + ": " + hipGetErrorString(h.e));
     } catch (const std::bad_alloc&) {
         return fail(PX_E_OOM, "host allocation failed");
     } catch (...) {
@@ -1061,98 +1365,115 @@ pxStatus guarded(F&& f)
     }
 }
 
-// ---- concurrent single-structure solves (batch and server) -----------------
-// One-material omegaFQ structures are solved whole, shared-Krylov phase first,
-// by a small pool of host threads, each driving its own HIP stream of the
-// default priority, so that the solves of several structures (small ones
-// leave most of the GPU idle) and the stacked engine's cycles overlap on the
-// device.  A structure is moved to its worker's stream for the solve and
-// handed back on its own stream.
-class SolvePool {
+// ---- several whole solves at once from one host thread (batch and server) ----
+// Each structure runs as a WholeSolve on a stream of its own; the driver
+// enqueues a few steps of each in turn without waiting for the device, and
+// only waits (on the oldest) when none of them can go on.  A solve that
+// throws is ended on its own: its structure records the status and the
+// message, the others go on.
+constexpr int kConcurrentSolves = 4;   // GPU_MAX_HW_QUEUES is 4 by default
+constexpr int kStepsPerTurn = 8;
+
+class SolveDriver {
   public:
-    SolvePool(int nworkers, const pxSolveOptions& o) : o_(o)
+    explicit SolveDriver(const pxSolveOptions& o) : o_(o) {}
+    ~SolveDriver() { run_.clear(); }
+    bool busy() const { return !run_.empty(); }
+    int running() const { return (int)run_.size(); }
+    bool has_room() const { return (int)run_.size() < kConcurrentSolves; }
+    // starts s (it must have frequencies set); a failure to start is recorded in s
+    void start(pxStructure_t* s)
     {
-        HC(hipGetDevice(&dev_));
-        for (int w = 0; w < nworkers; ++w) threads_.emplace_back([this] { work(); });
-    }
-    ~SolvePool()
-    {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            quit_ = true;
+        try {
+            run_.emplace_back(new WholeSolve(s, o_, true));
+        } catch (const HipError& h) {
+            record(s, status_of(h), std::string(h.where) + ": " + hipGetErrorString(h.e));
+        } catch (const std::bad_alloc&) {
+            record(s, PX_E_OOM, "host allocation failed");
         }
-        cv_.notify_all();
-        for (auto& t : threads_) t.join();
     }
-    void submit(pxStructure_t* s)
+    // One turn over the running solves; returns the structures that finished
+    // (successfully or not).  With `may_wait`, waits for the device when no
+    // solve could go on without waiting.
+    std::vector<pxStructure_t*> turn(bool may_wait)
     {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            jobs_.push_back(s);
-            ++pending_;
-        }
-        cv_.notify_one();
+        int did = 0;
+        for (size_t i = 0; i < run_.size(); ++i) did += step(i, kStepsPerTurn, false);
+        if (did == 0 && may_wait && !run_.empty()) step(0, 1, true);
+        return collect();
     }
-    // finished solves (structure, status); with wait, blocks until at least one
-    // is there or nothing is pending
-    std::vector<std::pair<pxStructure_t*, pxStatus>> collect(bool wait)
+    std::vector<pxStructure_t*> take_failed_starts()
     {
-        std::unique_lock<std::mutex> lk(mu_);
-        if (wait) done_cv_.wait(lk, [this] { return !done_.empty() || pending_ == 0; });
-        std::vector<std::pair<pxStructure_t*, pxStatus>> out(done_.begin(), done_.end());
-        done_.clear();
+        std::vector<pxStructure_t*> out;
+        out.swap(failed_);
         return out;
-    }
-    int pending()
-    {
-        std::lock_guard<std::mutex> lk(mu_);
-        return pending_;
     }
 
   private:
-    void work()
+    int step(size_t i, int n, bool wait)
     {
-        (void)hipSetDevice(dev_);
-        hipStream_t ws = nullptr;
-        const bool have = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess;
-        while (true) {
-            pxStructure_t* s = nullptr;
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [this] { return quit_ || !jobs_.empty(); });
-                if (jobs_.empty()) break;
-                s = jobs_.front();
-                jobs_.pop_front();
-            }
-            pxStatus st = PX_E_DEVICE;
-            if (have) {
-                hipStream_t own = s->st;
-                s->st = ws;
-                st = guarded([&]() -> pxStatus { return solve_impl(s, o_); });
-                (void)hipStreamSynchronize(ws);
-                s->st = own;
-            }
-            {
-                std::lock_guard<std::mutex> lk(mu_);
-                done_.emplace_back(s, st);
-                --pending_;
-            }
-            done_cv_.notify_all();
+        WholeSolve* w = run_[i].get();
+        if (!w || w->finished()) return 0;
+        try {
+            return w->advance(n, wait);
+        } catch (const HipError& h) {
+            end_failed(i, status_of(h), std::string(h.where) + ": " + hipGetErrorString(h.e));
+        } catch (const std::bad_alloc&) {
+            end_failed(i, PX_E_OOM, "host allocation failed");
         }
-        if (have) (void)hipStreamDestroy(ws);
+        return 1;
+    }
+    void end_failed(size_t i, pxStatus st, const std::string& msg)
+    {
+        pxStructure_t* s = run_[i]->structure();
+        run_[i].reset();   // waits for its stream, hands the structure back
+        record(s, st, msg);
+    }
+    void record(pxStructure_t* s, pxStatus st, const std::string& msg)
+    {
+        s->last_status = st;
+        s->last_error = msg;
+        s->solved = false;
+        failed_.push_back(s);
+    }
+    std::vector<pxStructure_t*> collect()
+    {
+        std::vector<pxStructure_t*> out;
+        out.swap(failed_);
+        for (auto& w : run_)
+            if (w && w->finished()) {
+                out.push_back(w->structure());
+                w.reset();
+            }
+        run_.erase(std::remove_if(run_.begin(), run_.end(), [](const std::unique_ptr<WholeSolve>& w) { return !w; }),
+                   run_.end());
+        return out;
     }
     pxSolveOptions o_;
-    int dev_ = 0;
-    std::vector<std::thread> threads_;
-    std::mutex mu_;
-    std::condition_variable cv_, done_cv_;
-    std::deque<pxStructure_t*> jobs_;
-    std::vector<std::pair<pxStructure_t*, pxStatus>> done_;
-    int pending_ = 0;
-    bool quit_ = false;
+    std::vector<std::unique_ptr<WholeSolve>> run_;
+    std::vector<pxStructure_t*> failed_;
 };
 
-constexpr int kPoolWorkers = 4;   // GPU_MAX_HW_QUEUES is 4 by default
+// HBM bytes of one whole solve (admission of the server's whole solves): the
+// active block's vectors and T-apply scratch, the near-field list, and the
+// shared-Krylov phase's basis and factors or the blocked solver's basis.
+double solve_footprint(const pxStructure_t* s, const pxSolveOptions& o)
+{
+    const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, s->ncol) : s->ncol;
+    const double lda = pad_cols(blk, true);
+    const double nup = (double)s->g.nup, vec = nup * lda;
+    double b = vec * (5 * 16 + 8 + 8 + 16) + (double)px::tapply_f64_scratch_bytes(s->g, 8) +
+               (double)px::tapply_f32_scratch_bytes(s->g, 2 * (int)lda);
+    if (s->model == PX_WFQ) b += 6000.0 * (double)s->g.n;   // near-field list (about 400 entries per atom)
+    const int m_max = std::max(o.restart_m, o.max_restart_m);
+    if (shifted_applies(s, o)) {
+        const double k = o.shifted_max_steps, R = s->npol, P = s->ncol;
+        b += (k + 1) * nup * R * 8.0 + (k + 1) * k * R * R * 8.0 + k * P * 56.0 + k * (k + 1) / 2.0 * P * 16.0;
+    } else {
+        b += (m_max + 1.0) * vec * 16.0 + 2.0 * m_max * (m_max + 1.0) * lda * 16.0;
+    }
+    return b;
+}
 
 
 }  // namespace
@@ -1367,80 +1688,85 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
         if (ss[k]->ncol == 0) return fail(PX_E_STATE, "pxSolveBatch: every structure needs pxSetFrequencies");
         if (ss[k]->st != ss[0]->st) return fail(PX_E_INVALID, "pxSolveBatch: structures use different streams");
         if (ss[k]->het) return fail(PX_E_INVALID, "pxSolveBatch: two-type structures are solved with pxSolveSpectrum");
+        for (int32_t j = 0; j < k; ++j)
+            if (ss[j] == ss[k]) return fail(PX_E_INVALID, "pxSolveBatch: a structure is listed twice");
     }
     return guarded([&]() -> pxStatus {
         auto t0 = std::chrono::steady_clock::now();
         const int Bc = o.block_cols > 0 ? o.block_cols : 64;
         const int m_max = std::max(o.restart_m, o.max_restart_m);
         hipStream_t st = ss[0]->st;
-        // whole solves on the worker pool, beside the stacked engine that
-        // takes the small structures
+        // whole solves (several at once, each on a stream of its own) beside
+        // the stacked engine that takes the small structures
         std::vector<pxStructure_t*> pooled, stacked;
-        for (int32_t k = 0; k < n; ++k) (pooled_solve(ss[k], o) ? pooled : stacked).push_back(ss[k]);
-        std::unique_ptr<SolvePool> pool;
-        if (!pooled.empty()) {
-            HC(hipStreamSynchronize(st));
-            pool.reset(new SolvePool(std::min<int>(kPoolWorkers, (int)pooled.size()), o));
-            for (pxStructure_t* p : pooled) pool->submit(p);
+        for (int32_t k = 0; k < n; ++k) {
+            ss[k]->last_status = PX_E_STATE;
+            ss[k]->last_error = "not solved";
+            (pooled_solve(ss[k], o) ? pooled : stacked).push_back(ss[k]);
         }
-        pxStatus worst = PX_OK;
-        auto finish_pool = [&]() {
-            if (!pool) return;
-            while (pool->pending() > 0)
-                for (auto& r : pool->collect(true))
-                    if (r.second != PX_OK && worst == PX_OK) worst = r.second;
-            for (auto& r : pool->collect(false))
-                if (r.second != PX_OK && worst == PX_OK) worst = r.second;
-            pool.reset();
-        };
-        if (stacked.empty()) {
-            finish_pool();
-            if (worst != PX_OK) return fail(worst, "some columns did not reach rel_tol");
-            return PX_OK;
-        }
-        int64_t rows = 0;
-        int nseg = 0;
-        for (pxStructure_t* p : stacked) {
-            nseg += (p->ncol + Bc - 1) / Bc;
-            rows += (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup;
-        }
-        size_t free_b = 0, total_b = 0;
-        HC(hipMemGetInfo(&free_b, &total_b));
-        const int64_t fit = (int64_t)(0.8 * (double)free_b / (double)Engine::bytes_per_row(Bc, m_max));
-        const int64_t cap = std::min(rows, fit);
-        int64_t biggest = 0;
-        for (pxStructure_t* p : stacked)
-            biggest = std::max<int64_t>(biggest, (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup);
-        if (cap < biggest) {
-            finish_pool();
-            return fail(PX_E_OOM, "pxSolveBatch: the largest structure does not fit in device memory");
-        }
-        Engine eng(st, Bc, o, std::max(cap, biggest), nseg);
+        std::unique_ptr<Engine> eng;
         std::deque<pxStructure_t*> queue;
-        for (pxStructure_t* p : stacked) {
-            for (double& v : p->ms) v = 0.0;
-            for (int64_t& v : p->counts) v = 0;
-            prepare_solve(p);
-            queue.push_back(p);
-        }
-        while (!queue.empty() || !eng.idle()) {
-            while (!queue.empty() && eng.can_admit(queue.front())) {
-                eng.admit(queue.front());
-                queue.pop_front();
+        if (!stacked.empty()) {
+            int64_t rows = 0;
+            int nseg = 0;
+            for (pxStructure_t* p : stacked) {
+                nseg += (p->ncol + Bc - 1) / Bc;
+                rows += (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup;
             }
-            eng.cycle();
+            size_t free_b = 0, total_b = 0;
+            HC(hipMemGetInfo(&free_b, &total_b));
+            const int64_t fit = (int64_t)(0.8 * (double)free_b / (double)Engine::bytes_per_row(Bc, m_max));
+            const int64_t cap = std::min(rows, fit);
+            int64_t biggest = 0;
+            for (pxStructure_t* p : stacked)
+                biggest = std::max<int64_t>(biggest, (int64_t)((p->ncol + Bc - 1) / Bc) * p->g.nup);
+            if (cap < biggest) return fail(PX_E_OOM, "pxSolveBatch: the largest structure does not fit in device memory");
+            eng.reset(new Engine(st, Bc, o, std::max(cap, biggest), nseg));
+            for (pxStructure_t* p : stacked) {
+                for (double& v : p->ms) v = 0.0;
+                for (int64_t& v : p->counts) v = 0;
+                prepare_solve(p);
+                queue.push_back(p);
+            }
+        }
+        SolveDriver drv(o);
+        std::deque<pxStructure_t*> waiting(pooled.begin(), pooled.end());
+        auto engine_work = [&]() { return eng && (!queue.empty() || !eng->idle()); };
+        while (!waiting.empty() || drv.busy() || engine_work()) {
+            while (drv.has_room() && !waiting.empty()) {
+                drv.start(waiting.front());
+                waiting.pop_front();
+            }
+            const bool ew = engine_work();
+            (void)drv.turn(!ew);
+            if (ew) {
+                while (!queue.empty() && eng->can_admit(queue.front())) {
+                    eng->admit(queue.front());
+                    queue.pop_front();
+                }
+                for (pxStructure_t* p : eng->cycle()) set_engine_status(p, o);
+                (void)drv.turn(false);
+            }
         }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        finish_pool();
         for (pxStructure_t* p : stacked) {
             p->ms[0] = ms;
             p->ms[5] = ms;
-            p->counts[0] = eng.stats().tapply_f32;
-            p->counts[3] = eng.stats().tapply_f64 + eng.stats().residuals;
-            for (int c = 0; c < p->ncol; ++c)
-                if (!(p->relres[c] <= o.rel_tol)) worst = PX_E_NOTCONV;
+            p->counts[0] = eng->stats().tapply_f32;
+            p->counts[3] = eng->stats().tapply_f64 + eng->stats().residuals;
         }
-        if (worst != PX_OK) return fail(worst, "some columns did not reach rel_tol");
+        // the worst status: a device or memory failure before a convergence shortfall
+        pxStatus worst = PX_OK;
+        std::string msg;
+        for (int32_t k = 0; k < n; ++k) {
+            const pxStatus sk = ss[k]->last_status;
+            if (sk == PX_OK) continue;
+            if (worst == PX_OK || (worst == PX_E_NOTCONV && sk != PX_E_NOTCONV)) {
+                worst = sk;
+                msg = "structure " + std::to_string(k) + ": " + ss[k]->last_error;
+            }
+        }
+        if (worst != PX_OK) return fail(worst, msg);
         return PX_OK;
     });
 }
@@ -1720,11 +2046,17 @@ void pxDestroyStructure(pxStructure s)
 
 struct pxServer_t {
     pxs::Engine* eng = nullptr;
-    std::unique_ptr<SolvePool> pool;   // one-material omegaFQ requests, solved whole
-    std::deque<pxStructure_t*> queue;
+    std::unique_ptr<SolveDriver> drv;               // whole solves, several at once
+    std::deque<pxStructure_t*> queue;               // stacked-engine requests not yet admitted
+    std::deque<pxStructure_t*> waiting;             // whole-solve requests not yet admitted
+    std::map<pxStructure_t*, double> whole_bytes;   // footprints of the admitted whole solves
+    double whole_in_use = 0.0;
     std::deque<pxStructure_t*> done;
     hipStream_t st = nullptr;
     pxSolveOptions o{};
+    double budget = 0.0;
+    double row_bytes = 0.0;
+    double engine_bytes() const { return (double)eng->rows_in_use() * row_bytes; }
 };
 
 pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, void* hip_stream, pxServer* out)
@@ -1742,17 +2074,15 @@ pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, v
         const int m_max = std::max(o.restart_m, o.max_restart_m);
         const int64_t rows = (int64_t)(memory_budget_bytes / (double)Engine::bytes_per_row(Bc, m_max));
         if (rows < 256) return fail(PX_E_OOM, "memory budget below one segment");
-        auto* sv = new pxServer_t();
+        std::unique_ptr<pxServer_t> sv(new pxServer_t());
         sv->st = static_cast<hipStream_t>(hip_stream);
         sv->o = o;
         sv->o.block_cols = Bc;
-        try {
-            sv->eng = new Engine(sv->st, Bc, o, rows, (int)std::max<int64_t>(1, rows / 256));
-        } catch (...) {
-            delete sv;
-            throw;
-        }
-        *out = sv;
+        sv->budget = memory_budget_bytes;
+        sv->row_bytes = (double)Engine::bytes_per_row(Bc, m_max);
+        sv->eng = new Engine(sv->st, Bc, o, rows, (int)std::max<int64_t>(1, rows / 256));
+        sv->drv.reset(new SolveDriver(sv->o));
+        *out = sv.release();
         return PX_OK;
     });
 }
@@ -1764,14 +2094,15 @@ pxStatus pxServerSubmit(pxServer sv, pxStructure s)
     if (s->ncol == 0) return fail(PX_E_STATE, "pxServerSubmit: call pxSetFrequencies first");
     if (s->st != sv->st) return fail(PX_E_INVALID, "pxServerSubmit: structure uses another stream");
     if (s->het) return fail(PX_E_INVALID, "pxServerSubmit: two-type structures are solved with pxSolveSpectrum");
-    if (sv->eng->rows_for(s) > sv->eng->rows_capacity())
+    const bool whole = pooled_solve(s, sv->o);
+    if (whole ? solve_footprint(s, sv->o) > sv->budget : sv->eng->rows_for(s) > sv->eng->rows_capacity())
         return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");
     return guarded([&]() -> pxStatus {
-        if (pooled_solve(s, sv->o)) {
-            // solved whole on a worker stream, beside the engine's cycles
-            if (!sv->pool) sv->pool.reset(new SolvePool(kPoolWorkers, sv->o));
-            HC(hipStreamSynchronize(s->st));
-            sv->pool->submit(s);
+        s->last_status = PX_E_STATE;
+        s->last_error = "queued";
+        s->solved = false;
+        if (whole) {
+            sv->waiting.push_back(s);
             return PX_OK;
         }
         for (double& v : s->ms) v = 0.0;
@@ -1787,18 +2118,43 @@ pxStatus pxServerStep(pxServer sv, pxStructure* finished, int32_t max_finished, 
     g_err.clear();
     if (!sv || !n_finished || (max_finished > 0 && !finished)) return fail(PX_E_INVALID, "null argument");
     return guarded([&]() -> pxStatus {
-        while (!sv->queue.empty() && sv->eng->can_admit(sv->queue.front())) {
+        // admission by HBM footprint, in arrival order within each kind: the
+        // stacked rows in use and the whole solves' footprints share the budget
+        while (!sv->queue.empty() && sv->eng->can_admit(sv->queue.front()) &&
+               (double)(sv->eng->rows_in_use() + sv->eng->rows_for(sv->queue.front())) * sv->row_bytes +
+                       sv->whole_in_use <= sv->budget) {
             sv->eng->admit(sv->queue.front());
             sv->queue.pop_front();
         }
+        while (!sv->waiting.empty() && sv->drv->has_room()) {
+            pxStructure_t* s = sv->waiting.front();
+            const double fp = solve_footprint(s, sv->o);
+            if (sv->engine_bytes() + sv->whole_in_use + fp > sv->budget) break;
+            sv->waiting.pop_front();
+            sv->whole_bytes[s] = fp;
+            sv->whole_in_use += fp;
+            sv->drv->start(s);
+        }
+        auto take = [&](const std::vector<pxStructure_t*>& fin) {
+            for (pxStructure_t* s : fin) {
+                auto it = sv->whole_bytes.find(s);
+                if (it != sv->whole_bytes.end()) {
+                    sv->whole_in_use -= it->second;
+                    sv->whole_bytes.erase(it);
+                }
+                sv->done.push_back(s);
+            }
+        };
+        take(sv->drv->turn(false));
         const bool cycled = !sv->eng->idle();
         if (cycled)
-            for (pxStructure_t* s : sv->eng->cycle()) sv->done.push_back(s);
-        if (sv->pool) {
-            // without an engine cycle to run, wait for a worker rather than spin
-            const bool wait = !cycled && sv->done.empty() && sv->pool->pending() > 0;
-            for (auto& r : sv->pool->collect(wait)) sv->done.push_back(r.first);
-        }
+            for (pxStructure_t* s : sv->eng->cycle()) {
+                set_engine_status(s, sv->o);
+                sv->done.push_back(s);
+            }
+        // without an engine cycle to run, wait for the device rather than spin
+        take(sv->drv->turn(!cycled && sv->done.empty()));
+        if (sv->whole_bytes.empty()) sv->whole_in_use = 0.0;
         int32_t k = 0;
         while (k < max_finished && !sv->done.empty()) {
             finished[k++] = sv->done.front();
@@ -1814,17 +2170,53 @@ pxStatus pxServerQuery(pxServer sv, int32_t* n_queued, int32_t* n_active, int64_
 {
     g_err.clear();
     if (!sv) return fail(PX_E_INVALID, "null server");
-    if (n_queued) *n_queued = (int32_t)sv->queue.size();
-    if (n_active) *n_active = sv->eng->n_structures() + (sv->pool ? sv->pool->pending() : 0);
+    if (n_queued) *n_queued = (int32_t)(sv->queue.size() + sv->waiting.size());
+    if (n_active) *n_active = sv->eng->n_structures() + sv->drv->running();
     if (rows_in_use) *rows_in_use = sv->eng->rows_in_use();
     if (rows_capacity) *rows_capacity = sv->eng->rows_capacity();
+    return PX_OK;
+}
+
+pxStatus pxServerMemory(pxServer sv, double* bytes_in_use, double* budget_bytes, int32_t* n_whole)
+{
+    g_err.clear();
+    if (!sv) return fail(PX_E_INVALID, "null server");
+    if (bytes_in_use) *bytes_in_use = sv->engine_bytes() + sv->whole_in_use;
+    if (budget_bytes) *budget_bytes = sv->budget;
+    if (n_whole) *n_whole = sv->drv->running();
+    return PX_OK;
+}
+
+pxStatus pxSolveFootprint(pxStructure s, const pxSolveOptions* opt, double* bytes)
+{
+    g_err.clear();
+    if (!s || !bytes) return fail(PX_E_INVALID, "null argument");
+    if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveFootprint: call pxSetFrequencies first");
+    pxSolveOptions o;
+    pxDefaultSolveOptions(&o);
+    if (opt) o = *opt;
+    if (check_options(o) != PX_OK) return PX_E_INVALID;
+    *bytes = solve_footprint(s, o);
+    return PX_OK;
+}
+
+pxStatus pxGetSolveStatus(pxStructure s, int32_t* status, char* message, int32_t message_len)
+{
+    g_err.clear();
+    if (!s || !status) return fail(PX_E_INVALID, "null argument");
+    *status = (int32_t)s->last_status;
+    if (message && message_len > 0) {
+        const size_t n = std::min<size_t>((size_t)message_len - 1, s->last_error.size());
+        std::memcpy(message, s->last_error.data(), n);
+        message[n] = '\0';
+    }
     return PX_OK;
 }
 
 void pxServerDestroy(pxServer sv)
 {
     if (!sv) return;
-    sv->pool.reset();   // joins the workers (their solves finish first)
+    sv->drv.reset();   // waits for the running whole solves' streams
     if (sv->st) (void)hipStreamSynchronize(sv->st);
     else (void)hipDeviceSynchronize();
     delete sv->eng;
@@ -1832,3 +2224,4 @@ void pxServerDestroy(pxServer sv)
 }
 
 }  // extern "C"
+

@@ -212,6 +212,14 @@ class StepSync {
         HC(hipMemcpyAsync(h_flags_ + k, d_flag_, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HC(hipEventRecord(ev_[k], st));
     }
+    // true once the flag published as k has reached the host (never waits)
+    bool ready(int k)
+    {
+        const hipError_t e = hipEventQuery(ev_[k]);
+        if (e == hipSuccess) return true;
+        if (e == hipErrorNotReady) return false;
+        throw HipError{e, "hipEventQuery"};
+    }
     bool stopped(int k)
     {
         HC(hipEventSynchronize(ev_[k]));
@@ -418,6 +426,9 @@ struct pxStructure_t {
     double probe[2] = {0, 0};           // last probe call: kernel milliseconds, pair evaluations
 
     bool idle = false;   // set once the structure's stream has been synchronised for destruction
+    // status and message of the last solve (pxSolveSpectrum, pxSolveBatch, the server)
+    pxStatus last_status = PX_E_STATE;
+    std::string last_error = "not solved";
 
     ~pxStructure_t()
     {
