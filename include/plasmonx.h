@@ -341,6 +341,26 @@ pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, do
 pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const double* omega_ev,
                          const double* alpha_ib, const double* x, double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * pxApplyOperator, y_c = A(omega_c) x_c for 1 <= ncol <= 4 columns, with x
+ * and y in DEVICE memory ([ncol][n_unknowns] interleaved complex, caller atom
+ * order, as pxApplyOperator's host arrays), the same kernels and the same
+ * result as pxApplyOperator with PX_FP64.  Its scratch (the permuted columns,
+ * T x, the operator's result before un-permuting, the narrow T-apply's split
+ * partial sums and the shifts) lives in a fixed 128 MiB device array of the
+ * library, one per GPU, held until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).  Runs on the
+ * structure's stream and returns once y is written.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  Errors: PX_E_INVALID
+ * for a null pointer, ncol outside [1, 4], omega <= 0 or a missing alpha_ib
+ * (PX_WFQFMU); PX_E_OOM, with the sizes in the message, when the structure
+ * needs more scratch than the array holds (e.g. ncol = 4 on a 20k-atom
+ * PX_WFQFMU structure); PX_E_DEVICE. */
+pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega_ev, const double* alpha_ib,
+                                const double* x, double* y);
+
 /* Number of unknowns (n_atoms or 4 n_atoms) and of atoms. */
 pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns);
 

@@ -28,7 +28,7 @@ EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHete
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
-            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus"]
+            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc"]
 
 
 class PxError(RuntimeError):
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
     lib.pxServerQuery.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]
+    lib.pxApplyOperatorNoAlloc.argtypes = [_vp, i32, _dp, _dp, _vp, _vp]
     lib.pxServerMemory.argtypes = [_vp, _dp, _dp, ctypes.POINTER(i32)]
     lib.pxSolveFootprint.argtypes = [_vp, ctypes.POINTER(pxSolveOptions), _dp]
     lib.pxGetSolveStatus.argtypes = [_vp, ctypes.POINTER(i32), ctypes.c_char_p, i32]
@@ -190,6 +191,17 @@ def pxSolveBatch(handles, opt: pxSolveOptions | None = None):
     arr = (_vp * len(handles))(*[h.value if isinstance(h, _vp) else h for h in handles])
     return _check(load().pxSolveBatch(arr, len(handles), None if opt is None else ctypes.byref(opt)),
                   (PX_OK, PX_E_NOTCONV))
+
+
+def pxApplyOperatorNoAlloc(h, omega_ev, x_dev_ptr, y_dev_ptr, alpha_ib=None):
+    """FP64 y = A(w) x with x, y given as device addresses ([ncol][nu] complex
+    interleaved); the library allocates nothing for the call."""
+    om = np.ascontiguousarray(np.atleast_1d(omega_ev), dtype=np.float64)
+    aib = None
+    if alpha_ib is not None:
+        aib = np.ascontiguousarray(np.asarray(alpha_ib, dtype=np.complex128).reshape(len(om), -1)).view(np.float64)
+    _check(load().pxApplyOperatorNoAlloc(h, len(om), _ptr(om), _ptr(aib), ctypes.c_void_p(int(x_dev_ptr)),
+                                         ctypes.c_void_p(int(y_dev_ptr))))
 
 
 def pxGetSize(h):

@@ -1478,6 +1478,37 @@ double solve_footprint(const pxStructure_t* s, const pxSolveOptions& o)
 
 }  // namespace
 
+// ---- device scratch of pxApplyOperatorNoAlloc --------------------------------
+// A fixed array per GPU, held until the process ends, for callers that cannot
+// allocate.  Host code never uses its name as an address: the device address
+// is taken once per device with hipGetSymbolAddress and kept.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64] = {};
+
+// This device's address of the scratch array (looked up on the first call on
+// each device, with that device current).
+char* noalloc_scratch()
+{
+    int dev = 0;
+    HC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw HipError{hipErrorInvalidDevice, "hipGetDevice"};
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError{hipErrorInvalidSymbol, "hipGetSymbolAddress"};
+        g_noalloc_ptr[dev] = p;
+    }
+    return static_cast<char*>(g_noalloc_ptr[dev]);
+}
+
+}  // namespace
+
 extern "C" {
 
 void pxDefaultSolveOptions(pxSolveOptions* o)
@@ -1579,6 +1610,8 @@ pxStatus create_impl(pxModel model, int64_t n_atoms, const double* xyz_ang, cons
             return fail(PX_E_INVALID, "two atoms closer than 1e-6 Angstrom");
         }
         try {
+            // the omegaFQ narrow FP64 T-apply takes its near field from a list built here
+            HC(px::ensure_near_f64(s->g, s->st));
             s->d_perm = dalloc<int32_t>(n_atoms);
             HC(hipMemcpyAsync(s->d_perm, s->perm.data(), sizeof(int32_t) * n_atoms, hipMemcpyHostToDevice, s->st));
             HC(hipStreamSynchronize(s->st));
@@ -1996,6 +2029,77 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
         HC(hipStreamSynchronize(s->st));
         dfree(din);
         dfree(dout);
+        return PX_OK;
+    });
+}
+
+pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega_ev, const double* alpha_ib,
+                                const double* x, double* y)
+{
+    g_err.clear();
+    if (!s || !omega_ev || !x || !y) return fail(PX_E_INVALID, "null argument");
+    if (ncol < 1 || ncol > 4) return fail(PX_E_INVALID, "pxApplyOperatorNoAlloc: ncol must be in [1, 4]");
+    if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
+    for (int c = 0; c < ncol; ++c)
+        if (!(omega_ev[c] > 0) || !std::isfinite(omega_ev[c])) return fail(PX_E_INVALID, "frequencies must be > 0");
+    const int naib = s->het ? 4 : 2;
+    return guarded([&]() -> pxStatus {
+        if (s->model == PX_WFQ && !s->g.near_off) return fail(PX_E_STATE, "near-field list missing");
+        const int64_t nu = s->g.nu, nup = s->g.nup;
+        const int lda = ncol;
+        const size_t vec = (size_t)nup * lda;
+        // the layout in the scratch array: shifts, permuted columns, T x, the
+        // operator's result, the narrow T-apply's split partial sums
+        size_t off = 0;
+        auto carve = [&off](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) / 256 * 256;
+            return o;
+        };
+        const size_t part_bytes = px::tapply_f64_scratch_bytes(s->g, 2 * lda);
+        const size_t o_sh = carve(sizeof(double2) * 8 * lda), o_xs = carve(sizeof(double2) * vec),
+                     o_y = carve(sizeof(double) * 2 * vec), o_w = carve(sizeof(double2) * vec),
+                     o_part = carve(part_bytes);
+        if (off > kNoAllocScratchBytes)
+            return fail(PX_E_OOM, "pxApplyOperatorNoAlloc: needs " + std::to_string(off) +
+                                      " bytes of scratch, the fixed device array holds " +
+                                      std::to_string(kNoAllocScratchBytes));
+        char* base = noalloc_scratch();
+        double2* zq = reinterpret_cast<double2*>(base + o_sh);
+        double2* zm = zq + lda;
+        double2* het = zq + 2 * lda;
+        double2* xs = reinterpret_cast<double2*>(base + o_xs);
+        double* Y64 = reinterpret_cast<double*>(base + o_y);
+        double2* w = reinterpret_cast<double2*>(base + o_w);
+        double* part = reinterpret_cast<double*>(base + o_part);
+        // shifts of every column (host), one copy into the array
+        std::vector<double2> h((size_t)8 * lda, make_double2(0, 0));
+        for (int c = 0; c < ncol; ++c) {
+            const double wv = omega_ev[c] / EV_PER_HARTREE;
+            const double* a = s->model == PX_WFQFMU ? alpha_ib + naib * c : nullptr;
+            if (s->het) {
+                double2 f[6];
+                het_factors(s, wv, a, f);
+                for (int q = 0; q < 6; ++q) h[(size_t)(2 + q) * lda + c] = f[q];
+                continue;
+            }
+            double zr, zi;
+            shift_q(s->drude, s->mat.tau, wv, zr, zi);
+            h[c] = make_double2(zr, zi);
+            if (a) {
+                shift_mu(a[0], a[1], zr, zi);
+                h[(size_t)lda + c] = make_double2(zr, zi);
+            }
+        }
+        HC(hipMemcpyAsync(zq, h.data(), sizeof(double2) * 8 * lda, hipMemcpyHostToDevice, s->st));
+        px::permute_in(s->g, reinterpret_cast<const double2*>(x), ncol, s->d_perm, xs, lda, s->st);
+        px::tapply_f64(s->g, reinterpret_cast<const double*>(xs), Y64, 2 * lda, 2 * lda, s->st, part, part_bytes);
+        if (s->het) px::spmm_het(s->g, Y64, false, 2 * lda, xs, het, nullptr, w, ncol, lda, 1.0, s->st);
+        else px::spmm_shift(s->g, Y64, false, 2 * lda, xs, zq, zm, nullptr, w, ncol, lda, 1.0, s->st);
+        for (int c = 0; c < ncol; ++c)
+            px::unpermute(s->g, w, lda, c, s->d_perm, reinterpret_cast<double2*>(y) + (size_t)c * nu, s->st);
+        HC(hipGetLastError());
+        HC(hipStreamSynchronize(s->st));
         return PX_OK;
     });
 }
