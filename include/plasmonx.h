@@ -129,14 +129,16 @@ typedef struct {
  *                    layout changes at nearly every restart as columns retire).
  *   t_apply          how pxSolveSpectrum applies T in its cycles and true
  *                    residuals: PX_TAPPLY_AUTO (default) times, on the
- *                    structure itself, the on-the-fly kernels and a GEMM
- *                    (rocBLAS) on T stored densely (N_u^2 x 4 B in FP32,
+ *                    structure itself, the on-the-fly kernels and the
+ *                    hand-written products with T stored densely (the
+ *                    paper's in-memory solver; N_u^2 x 4 B in FP32,
  *                    x 8 B in FP64, only when that fits a quarter of the free
  *                    device memory) the first time a (model, atoms, columns,
  *                    precision) shape occurs in the process, and keeps the
  *                    faster; PX_TAPPLY_ON_THE_FLY / PX_TAPPLY_STORED force one
  *                    (STORED fails with PX_E_OOM if T does not fit).
- *                    pxSolveBatch and the server always generate T on the fly.
+ *                    The stacked block of pxSolveBatch and the server always
+ *                    generates T on the fly.
  *   shifted          pxSolveSpectrum on a one-material PX_WFQ structure: 1
  *                    first runs one real Arnoldi process on Kbar T
  *                    per polarization, in FP64, and takes every frequency's

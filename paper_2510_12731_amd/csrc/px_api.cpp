@@ -23,7 +23,6 @@
 #include <tuple>
 
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -63,11 +62,6 @@ void shift_mu(double ar, double ai, double& zr, double& zi)
     const double den = ar * ar + ai * ai;
     zr = -ar / den;
     zi = ai / den;
-}
-
-void release_blas(void* handle)
-{
-    if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
 void het_factors(const pxStructure_t* s, double w, const double* aib4, double2 out[6])
@@ -241,18 +235,6 @@ enum { TA_FLY = 1, TA_STORED = 2 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int, int>, int> g_tune;
 
-rocblas_handle blas_of(pxStructure_t* s)
-{
-    if (!s->blas) {
-        rocblas_handle h = nullptr;
-        if (rocblas_create_handle(&h) != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas_create_handle"};
-        s->blas = h;
-    }
-    rocblas_handle h = static_cast<rocblas_handle>(s->blas);
-    if (rocblas_set_stream(h, s->st) != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas_set_stream"};
-    return h;
-}
-
 bool stored_fits(pxStructure_t* s, bool f32)
 {
     if ((f32 ? (void*)s->t32 : (void*)s->t64) != nullptr) return true;
@@ -269,29 +251,25 @@ void ensure_stored(pxStructure_t* s, bool f32)
         s->t32 = static_cast<float*>(pxs::BlockCache::get().take(n2 * sizeof(float)));
         px::tdense_f32(s->g, s->t32, s->st);
     }
+    if (f32 && !s->ws.sk32) s->ws.sk32 = dalloc<float>(px::tstored_f32_scratch_bytes() / sizeof(float));
     if (!f32 && !s->t64) {
         s->t64 = static_cast<double*>(pxs::BlockCache::get().take(n2 * sizeof(double)));
         px::tdense_f64(s->g, s->t64, s->st);
     }
 }
 
-// Y = T X with X, Y row-major [nup][ldx]: as column-major matrices this is
-// Y^T = X^T T^T, one GEMM with T's row-major buffer as the second operand.
-void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols)
+// Y = T X on the stored T (hand-written kernels: FP32 or FP64 MFMA tiles, or
+// a split pass over T for the narrow FP64 blocks).
+void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop = nullptr,
+                  const hipEvent_t* ev = nullptr)
 {
-    rocblas_handle h = blas_of(s);
-    const rocblas_int m = ncols, n = (rocblas_int)s->g.nup;
-    rocblas_status e;
-    if (f32) {
-        const float one = 1.f, zero = 0.f;
-        e = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, n, &one,
-                          static_cast<const float*>(X), ldx, s->t32, n, &zero, static_cast<float*>(Y), ldx);
-    } else {
-        const double one = 1.0, zero = 0.0;
-        e = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, n, &one,
-                          static_cast<const double*>(X), ldx, s->t64, n, &zero, static_cast<double*>(Y), ldx);
-    }
-    if (e != rocblas_status_success) throw HipError{hipErrorUnknown, "rocblas gemm"};
+    Workspace& W = s->ws;
+    if (f32)
+        px::tstored_f32(s->g, s->t32, static_cast<const float*>(X), static_cast<float*>(Y), ldx, ncols, s->st, W.sk32,
+                        stop, ev);
+    else
+        px::tstored_f64(s->g, s->t64, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st,
+                        W.narrow, stop, ev);
 }
 
 void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop,
@@ -370,9 +348,7 @@ void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int 
             const hipEvent_t* ev = nullptr)
 {
     if (method == TA_STORED) {
-        if (ev) HC(hipEventRecord(ev[0], s->st));
-        apply_stored(s, f32, X, Y, ldx, ncols);
-        if (ev) HC(hipEventRecord(ev[1], s->st));
+        apply_stored(s, f32, X, Y, ldx, ncols, stop, ev);
     } else {
         apply_fly(s, f32, X, Y, ldx, ncols, stop, ev);
     }
@@ -574,8 +550,7 @@ class BlockRun {
         wide32_ = mixed_ && lda_ > 4;
         method_ = wide32_ ? tapply_method(s, true, W.X32, W.Y32, 2 * lda_, 2 * lda_, o_)
                           : tapply_method(s, false, W.V, W.Y64, 2 * lda_, 2 * lda_, o_);
-        // a GEMM on the stored T cannot read the stop flag: poll one step behind, not two
-        lag_ = method_ == TA_STORED ? 1 : kLag;
+        lag_ = kLag;
         // delayed orthogonalisation: the host enqueues steps ahead of the device and a
         // device flag, raised once the rotations have finished every column, ends them
         stop_ = dcgs2_ ? s->sync.flag() : nullptr;
@@ -946,11 +921,10 @@ class ShiftedRun : public PhaseRun {
         px::fill_zero(ndone_, sizeof(int32_t), st);
         px::ms_init(R, s->b, s->ldg, bn, u_, nup, st);
         method_ = tapply_method(s, false, u_, Y_, R, R, o);
-        // a stored-T GEMM cannot read the stop flag, so it polls as soon as possible;
-        // the on-the-fly kernels return at once once it is set, and a longer lag
-        // keeps the host from waiting on a Givens batch the main stream has not
-        // overtaken yet
-        start(kcap, method_ == TA_STORED ? 1 : 2 * kLag, px::ms_givens_batch());
+        // the T-apply kernels return at once once the stop flag is set; a lag
+        // of a few steps keeps the host from waiting on a Givens batch the main
+        // stream has not overtaken yet
+        start(kcap, 2 * kLag, px::ms_givens_batch());
     }
 
   protected:
@@ -1093,7 +1067,7 @@ class BlockShiftedRun : public PhaseRun {
         px::msb_init(R, s->b, s->ldg, u_, nup, st);
         method_ = tapply_method(s, false, u_, Y_, R, R, o);
         // the banded QRs run on the side stream, a launch every GBB block steps
-        start(kcap, method_ == TA_STORED ? 1 : 2 * kLag, px::msb_givens_cols() / R);
+        start(kcap, 2 * kLag, px::msb_givens_cols() / R);
     }
 
   protected:
@@ -1188,12 +1162,6 @@ void set_engine_status(pxStructure_t* s, const pxSolveOptions& o)
             s->last_status = PX_E_NOTCONV;
             s->last_error = "some columns did not reach rel_tol";
         }
-}
-
-// The stored-T GEMMs' library handle follows the structure's stream.
-void rebind_blas(pxStructure_t* s)
-{
-    if (s->blas) (void)rocblas_set_stream(static_cast<rocblas_handle>(s->blas), s->st);
 }
 
 // ---- one structure's whole solve, advanced step by step ----------------------
@@ -1323,7 +1291,6 @@ class WholeSolve {
         if (hipEventRecord(ev_, st_) == hipSuccess) (void)hipStreamWaitEvent(home_, ev_, 0);
         (void)hipStreamSynchronize(st_);
         s_->st = home_;
-        rebind_blas(s_);
     }
 
     pxStructure_t* s_;

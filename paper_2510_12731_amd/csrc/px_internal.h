@@ -94,6 +94,17 @@ size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
 // Dense T over the padded unknowns (row-major, nup x nup; ghost rows and
 // columns zero) for the stored-T apply: Y = T X is then one GEMM.
+// Y = T X with T stored dense (tdense_f32 / tdense_f64: row-major, nup x nup,
+// symmetric), either model: FP32 on MFMA with the stream-K pieces of
+// tapply_f32 (ncols a multiple of 128; scratch of tstored_f32_scratch_bytes());
+// FP64 on MFMA (ncols a multiple of 64), or for 1-8 real columns (ldx ==
+// ncols) a split pass over T with scratch of tapply_f64_scratch_bytes(g, 8).
+// ev: optional start/stop events carried by the first and last launch.
+size_t tstored_f32_scratch_bytes();
+void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, int ldx, int ncols, hipStream_t st,
+                 float* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
+void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
+                 double* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
 void tdense_f32(const Geometry& g, float* T, hipStream_t st);
 void tdense_f64(const Geometry& g, double* T, hipStream_t st);
 

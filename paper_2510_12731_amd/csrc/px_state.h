@@ -172,11 +172,12 @@ struct Workspace {
     double* narrow = nullptr;
     size_t narrow_bytes = 0;
     float* split32 = nullptr;
+    float* sk32 = nullptr;   // stream-K tiles of the stored FP32 apply (allocated with the stored T)
 
     void release()
     {
         void* ps[] = {V, w, xs, rs, bs, tmp, X32, Y32, Y64, partial, npart, h1, h2, R, H, G, coefQ, coefV, aux, sn, gv, y, cs, nrm, target,
-                      done, steps, map, zq, zmu, het, narrow, split32};
+                      done, steps, map, zq, zmu, het, narrow, split32, sk32};
         for (void* p : ps) dfree(p);
         *this = Workspace();
     }
@@ -367,9 +368,6 @@ class LaunchTimer {
     std::vector<std::array<double, 3>> ms_;
 };
 
-// Destroys a rocBLAS handle made by the stored-T apply (null: nothing).
-void release_blas(void* handle);
-
 // z_q(omega) of Eq. (z_q_wfq) with the Drude weight n/m* (graphene: E_F/(pi t_g)), omega in Hartree
 void shift_q(double drude, double tau, double w, double& zr, double& zi);
 // Eq. (z-mu): z_mu = -1 / alpha_IB
@@ -416,10 +414,9 @@ struct pxStructure_t {
     pxs::StepSync sync;           // stop flag of the Arnoldi steps
 
     // stored-T apply: dense T in FP32 / FP64 (allocated when the tuner or the
-    // options pick it), the rocBLAS handle bound to st, launches per method
+    // options pick it), launches per method
     float* t32 = nullptr;
     double* t64 = nullptr;
-    void* blas = nullptr;
     int64_t tstats[4] = {0, 0, 0, 0};   // FP32 on the fly, FP32 stored, FP64 on the fly, FP64 stored
     double tms[4] = {0, 0, 0, 0};       // their HIP-event milliseconds inside cycles (options.timings)
     double tflop[4] = {0, 0, 0, 0};     // their algorithmic FLOP inside cycles
@@ -440,7 +437,6 @@ struct pxStructure_t {
             if (idle) pxs::BlockCache::get().give(p);
             else pxs::BlockCache::get().drop(p);
         }
-        pxs::release_blas(blas);
     }
 };
 

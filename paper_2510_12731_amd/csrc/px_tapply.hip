@@ -271,6 +271,99 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32(const float4* __
     });
 }
 
+// ---- stored T (the paper's in-memory solver), FP32 --------------------------
+// Y = T X with T stored dense (row-major nup x nup, ld = ldt) for either model:
+// the tiles and stream-K pieces of the on-the-fly kernel, the A operand read
+// from memory instead of generated.  T is symmetric (T_ij = T_ji holds bit for
+// bit in the dense builders: swapping i and j negates the components of r
+// exactly), so lane l of k-step kk, which needs T[i][j] for row i = row0 +
+// l%32 and source j = j0 + 2 kk + l/32, reads T[j][i]: the 32 lanes of a
+// half-wave read 128 contiguous bytes.  The next chunk's 16 values per lane
+// are loaded while the current chunk's MFMAs run.
+__device__ __forceinline__ void tstored_f32_body(int bx, int by, int cbeg, int cend, const float* __restrict__ Ts,
+                                                 int ldt, const float* __restrict__ X, float* __restrict__ out,
+                                                 int ldo, int ldx)
+{
+    __shared__ __attribute__((aligned(16))) float sx[2][Q32_JC][Q32_COLS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = uniform(tid >> 6);
+    const int row0 = bx * 256 + wave * 32;
+    const int col0 = by * Q32_COLS;
+    const int ii = row0 + (lane & 31);
+    const int half = lane >> 5;
+    const int col4 = 4 * (lane & 31);
+
+    f32x16 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
+
+    const int lr = tid >> 4;
+    const int lc = (tid & 15) * 8;
+    float tv[Q32_JC / 2];
+    if (cbeg < cend) {
+        const int j0 = cbeg * Q32_JC;
+        const float4* src = reinterpret_cast<const float4*>(X + (size_t)(j0 + lr) * ldx + col0 + lc);
+        float4* dst = reinterpret_cast<float4*>(&sx[0][lr][lc]);
+        dst[0] = src[0];
+        dst[1] = src[1];
+#pragma unroll
+        for (int kk = 0; kk < Q32_JC / 2; ++kk) tv[kk] = Ts[(size_t)(j0 + 2 * kk + half) * ldt + ii];
+    }
+    __syncthreads();
+
+    for (int ch = cbeg; ch < cend; ++ch) {
+        const int buf = (ch - cbeg) & 1;
+        const int j0 = ch * Q32_JC;
+        const bool more = (ch + 1) < cend;
+        const int jn = more ? j0 + Q32_JC : j0;
+        const float4* nsrc = reinterpret_cast<const float4*>(X + (size_t)(jn + lr) * ldx + col0 + lc);
+        const float4 pre0 = nsrc[0];
+        const float4 pre1 = nsrc[1];
+        float tn[Q32_JC / 2];
+#pragma unroll
+        for (int kk = 0; kk < Q32_JC / 2; ++kk) tn[kk] = Ts[(size_t)(jn + 2 * kk + half) * ldt + ii];
+        float4 bq = *reinterpret_cast<const float4*>(&sx[buf][half][col4]);
+#pragma unroll
+        for (int kk = 0; kk < Q32_JC / 2; ++kk) {
+            float4 bqn = bq;
+            if (kk + 1 < Q32_JC / 2) bqn = *reinterpret_cast<const float4*>(&sx[buf][2 * kk + 2 + half][col4]);
+            mfma4(acc, tv[kk], bq);
+            bq = bqn;
+            if (kk == Q32_JC / 4 && more) {
+                float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
+                dst[0] = pre0;
+                dst[1] = pre1;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < Q32_JC / 2; ++kk) tv[kk] = tn[kk];
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = wave * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const float4 o = make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
+        *reinterpret_cast<float4*>(out + (size_t)i * ldo + col4) = o;
+    }
+}
+
+__global__ __launch_bounds__(Q32_THREADS) void k_tstored_f32(const float* __restrict__ Ts, int ldt,
+                                                             const float* __restrict__ X, float* __restrict__ Y,
+                                                             float* __restrict__ partial, int ldx, SkGrid sk,
+                                                             const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;   // every column of the block is done
+    sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
+        const int rb = t % sk.RB, cb = t / sk.RB;
+        float* out = slot < 0 ? Y + (size_t)rb * 256 * ldx + cb * Q32_COLS : partial + (size_t)slot * SK_TILE_FLOATS;
+        tstored_f32_body(rb, cb, c0, c1, Ts, ldt, X, out, slot < 0 ? ldx : Q32_COLS, ldx);
+    });
+}
+
 // ========================== omegaFQFmu, FP32 MFMA ===========================
 // Workgroup: 4 waves x 32 atoms, 32 real columns.  Each lane builds the 4x4
 // pair block of (row atom l%32, source atom 2kk + l/32) once and feeds the 16
@@ -566,6 +659,124 @@ __global__ __launch_bounds__(256) void k_tapply_wfq_f64(const double4* __restric
 {
     if (stop && *stop) return;   // every column of the block is done
     tapply_wfq_f64_body(blockIdx.x, blockIdx.y, blockIdx.z, xyz, glo, ghi, X, Y, np, ldx, inv_rqq, t_self, r_far2);
+}
+
+// ---- stored T, FP64 (either model): the tiles of the on-the-fly FP64 MFMA
+// kernel with the A operand read as T[j][i] (T symmetric): the 16 lanes of a
+// row group read 128 contiguous bytes; the next chunk's 16 values per lane
+// are loaded while the current chunk's MFMAs run.
+__global__ __launch_bounds__(256) void k_tstored_f64(const double* __restrict__ Ts, int ldt,
+                                                     const double* __restrict__ X, double* __restrict__ Y, int nup,
+                                                     int ldx, const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;   // every column of the block is done
+    __shared__ __attribute__((aligned(16))) double sx[2][Q64_JC][Q64_COLS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int row0 = blockIdx.x * 128 + wave * 32;
+    const int col0 = blockIdx.y * Q64_COLS;
+    int ii[2];
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb) ii[sb] = row0 + sb * 16 + (lane & 15);
+    f64x4 acc[2][4];
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[sb][cb][v] = 0.0;
+    const int lr = tid >> 3;
+    const int lc = (tid & 7) * 8;
+    const int nchunk = nup / Q64_JC;
+    double tv[Q64_JC / 4][2];
+    {
+        const double2* src = reinterpret_cast<const double2*>(X + (size_t)lr * ldx + col0 + lc);
+        double2* dst = reinterpret_cast<double2*>(&sx[0][lr][lc]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = src[q];
+#pragma unroll
+        for (int kk = 0; kk < Q64_JC / 4; ++kk)
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) tv[kk][sb] = Ts[(size_t)(4 * kk + (lane >> 4)) * ldt + ii[sb]];
+    }
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        const int j0 = ch * Q64_JC;
+        const bool more = (ch + 1) < nchunk;
+        const int jn = more ? j0 + Q64_JC : j0;
+        double2 pre[4];
+        const double2* src = reinterpret_cast<const double2*>(X + (size_t)(jn + lr) * ldx + col0 + lc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pre[q] = src[q];
+        double tn[Q64_JC / 4][2];
+#pragma unroll
+        for (int kk = 0; kk < Q64_JC / 4; ++kk)
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) tn[kk][sb] = Ts[(size_t)(jn + 4 * kk + (lane >> 4)) * ldt + ii[sb]];
+#pragma unroll
+        for (int kk = 0; kk < Q64_JC / 4; ++kk) {
+            const int jr = 4 * kk + (lane >> 4);
+            const double2* bp = reinterpret_cast<const double2*>(&sx[buf][jr][4 * (lane & 15)]);
+            const double2 b01 = bp[0], b23 = bp[1];
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+                acc[sb][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk][sb], b01.x, acc[sb][0], 0, 0, 0);
+                acc[sb][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk][sb], b01.y, acc[sb][1], 0, 0, 0);
+                acc[sb][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk][sb], b23.x, acc[sb][2], 0, 0, 0);
+                acc[sb][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk][sb], b23.y, acc[sb][3], 0, 0, 0);
+            }
+        }
+        if (more) {
+            double2* dst = reinterpret_cast<double2*>(&sx[buf ^ 1][lr][lc]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = pre[q];
+        }
+#pragma unroll
+        for (int kk = 0; kk < Q64_JC / 4; ++kk)
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) tv[kk][sb] = tn[kk][sb];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = row0 + sb * 16 + 4 * v + (lane >> 4);
+            double2* dst = reinterpret_cast<double2*>(Y + (size_t)i * ldx + col0 + 4 * (lane & 15));
+            dst[0] = make_double2(acc[sb][0][v], acc[sb][1][v]);
+            dst[1] = make_double2(acc[sb][2][v], acc[sb][3][v]);
+        }
+}
+
+// Stored T, FP64, 1-8 real columns (the shared-Krylov phase's matvec on a
+// stored T; a memory-bound pass over T): thread t of row block x takes row
+// i = 256 x + t; split y of the sources sums T[j][i] x_j (T symmetric, so the
+// 64 lanes of a wave read 512 contiguous bytes of row j, and x_j is a
+// wave-uniform load) over its share of the rows j; k_sum_splits adds the
+// splits.
+template <int NC>
+__global__ __launch_bounds__(256) void k_tstored_narrow(const double* __restrict__ Ts, int ldt,
+                                                        const double* __restrict__ X, double* __restrict__ part,
+                                                        int nup, int per_split, const int32_t* __restrict__ stop)
+{
+    if (stop && *stop) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j0 = blockIdx.y * per_split;
+    const int j1 = min(nup, j0 + per_split);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+        const double t = Ts[(size_t)j * ldt + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)j * NC + c], acc[c]);
+    }
+    double* out = part + (size_t)blockIdx.y * nup * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[(size_t)i * NC + c] = acc[c];
 }
 
 // ========================== omegaFQFmu, FP64 MFMA ===========================
@@ -1615,6 +1826,55 @@ void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st, const in
     if (impl->n64d > 0)
         hipLaunchKernelGGL(k_tapply_wfqfmu_f64_grouped, dim3(impl->n64d), dim3(256), 0, st, impl->d_gc, impl->d_t64d,
                            X, Y, impl->ldx, stop);
+}
+
+size_t tstored_f32_scratch_bytes() { return (size_t)2 * sk_slots() * SK_TILE_FLOATS * sizeof(float); }
+
+void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, int ldx, int ncols, hipStream_t st,
+                 float* scratch, const int32_t* stop, const hipEvent_t* ev)
+{
+    SkGrid sk{};
+    sk.RB = (int)(g.nup / 256);
+    sk.C = (int)(g.nup / Q32_JC);
+    sk.T = sk.RB * (ncols / Q32_COLS);
+    sk.total = (int64_t)sk.T * sk.C;
+    sk.G = sk_workgroups(sk.total);
+    hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
+    hipExtLaunchKernelGGL(k_tstored_f32, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, e0, nullptr, 0, T,
+                          (int)g.nup, X, Y, scratch, ldx, sk, stop);
+    hipExtLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * sk.T)), dim3(256), 0, st, nullptr, e1, 0, scratch, Y, ldx,
+                          sk, (const GroupConst*)nullptr, stop);
+}
+
+void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
+                 double* scratch, const int32_t* stop, const hipEvent_t* ev)
+{
+    hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
+    const int nup = (int)g.nup;
+    if (ncols <= 8) {
+        // narrow layout (ldx == ncols): split over the source rows, then the split sum
+        const int nsplit = narrow_splits(g);
+        const int per = (nup + nsplit - 1) / nsplit;
+        const dim3 grid((unsigned)(nup / 256), (unsigned)nsplit);
+#define PX_TSN(NC)                                                                                                   \
+    hipExtLaunchKernelGGL(k_tstored_narrow<NC>, grid, dim3(256), 0, st, e0, nullptr, 0, T, nup, X, scratch, nup, per, stop)
+        switch (ncols) {
+        case 1: PX_TSN(1); break;
+        case 2: PX_TSN(2); break;
+        case 3: PX_TSN(3); break;
+        case 4: PX_TSN(4); break;
+        case 6: PX_TSN(6); break;
+        default: PX_TSN(8); break;
+        }
+#undef PX_TSN
+        const int nc = ncols <= 4 || ncols == 6 ? ncols : 8;
+        const size_t len = (size_t)nup * nc;
+        hipExtLaunchKernelGGL(k_sum_splits, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, nullptr, e1, 0,
+                              (const double*)scratch, Y, len, nsplit, stop);
+        return;
+    }
+    hipExtLaunchKernelGGL(k_tstored_f64, dim3((unsigned)(nup / 128), (unsigned)(ncols / Q64_COLS)), dim3(256), 0, st,
+                          e0, e1, 0, T, nup, X, Y, nup, ldx, stop);
 }
 
 void tdense_f32(const Geometry& g, float* T, hipStream_t st)

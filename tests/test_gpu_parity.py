@@ -189,9 +189,10 @@ def test_orthogonalisation_variants_agree(precision, tol, bound):
 
 @pytest.mark.parametrize("precision,tol,bound", [(px.PX_FP64, 1e-12, 1e-10), (px.PX_MIXED, 1e-8, 1e-5)])
 def test_stored_t_apply_matches_oracle(precision, tol, bound):
-    """The stored-T apply (dense T built once per structure, one GEMM per
-    apply) reaches the oracle's spectrum on both models, forced and under the
-    autotuner, and agrees with the on-the-fly kernels."""
+    """The stored-T apply (dense T built once per structure, the hand-written
+    FP32/FP64 MFMA products and the narrow FP64 pass over T) reaches the
+    oracle's spectrum on both models, forced and under the autotuner, in the
+    blocked solver and in the shared-Krylov phase."""
     xyz = G.fcc_rod_n(300, seed=31)
     p = M.load("au_wfqfmu")
     om = np.linspace(1.6, 3.4, 7)
@@ -217,6 +218,17 @@ def test_stored_t_apply_matches_oracle(precision, tol, bound):
         e = rel_err(sig_s, ref_s["sigma"])
         say(f"[t_apply {mode}] sphere: status {st} iters max {it.max()} rel_err {e:.2e} launches {s.tapply_stats()}")
         assert st == px.PX_OK and e <= bound
+        s.close()
+        # the shared-Krylov phase: its narrow FP64 T-apply (one real column)
+        # on the stored T too, then the true residuals
+        s, st, alpha, sig_s, it, rr = _solve(0, c["xyz"], c["params"], c["omega_ev"], c["pol_mask"], None, precision,
+                                             tol, t_apply=mode)
+        ts = s.tapply_stats()
+        e = rel_err(sig_s, ref_s["sigma"])
+        say(f"[t_apply {mode}] sphere, shared phase: status {st} rel_err {e:.2e} launches {ts}")
+        assert st == px.PX_OK and e <= bound
+        if mode == px.PX_TAPPLY_STORED:
+            assert ts["f64_stored"] > 10 and ts["f64_on_the_fly"] == 0
         s.close()
 
 
