@@ -71,6 +71,12 @@ def _load():
     lib.or_rhs_het.argtypes = [ctypes.c_int, i64, dp, ip, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                dp]
     lib.or_probe.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, i64, dp, dp, dp, dp]
+    lib.or_bem_matrix.argtypes = [i64, dp, dp, dp, ctypes.c_double, dp]
+    lib.or_bem_rhs.argtypes = [i64, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
+    lib.or_bem_apply.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, dp]
+    lib.or_bem_solve_spectrum.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, ctypes.c_uint32,
+                                          ctypes.c_double, dp, dp, dp]
+    lib.or_bem_solve_spectrum.restype = i64
     _lib = lib
     return lib
 
@@ -302,3 +308,60 @@ def probe(model, xyz, p, q, mu, pts):
                      _d(mu_arr.view(np.float64)) if mu_arr is not None else None, npts, _d(pts),
                      _d(phi.view(np.float64)), _d(field.view(np.float64)), _d(rho.view(np.float64)))
     return dict(phi=phi, field=field, rho=rho)
+
+
+# ---- BEM (Section 2.3, Eq. bem-dpcm) ---------------------------------------
+# mesh: a dict from workloads.mesh (cen, nrm, area in Angstrom units, r_enc);
+# eps2: complex metal permittivity per frequency (or per column); eps1: the
+# medium's (complex scalar).
+
+def _mesh(m):
+    cen = np.ascontiguousarray(m["cen"], dtype=np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(m["nrm"], dtype=np.float64).reshape(-1, 3)
+    area = np.ascontiguousarray(m["area"], dtype=np.float64).reshape(-1)
+    return len(area), cen, nrm, area, float(m["r_enc"])
+
+
+def _cplx(a, n):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.complex128), (n,))).view(np.float64).copy()
+
+
+def bem_matrix(m):
+    n, cen, nrm, area, r = _mesh(m)
+    out = np.zeros((n, n))
+    _load().or_bem_matrix(n, _d(cen), _d(nrm), _d(area), r, _d(out))
+    return out
+
+
+def bem_rhs(m, pol, e0):
+    n, cen, nrm, area, r = _mesh(m)
+    b = np.zeros(n, dtype=np.complex128)
+    _load().or_bem_rhs(n, _d(cen), _d(nrm), _d(area), r, int(pol), float(e0), _d(b.view(np.float64)))
+    return b
+
+
+def bem_apply(m, eps2, eps1, x):
+    """y_c = [M - z(eps2_c) I] x_c; x: [ncol, n] complex, eps2: [ncol]."""
+    n, cen, nrm, area, r = _mesh(m)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    ncol = x.shape[0]
+    y = np.zeros_like(x)
+    _load().or_bem_apply(n, _d(cen), _d(nrm), _d(area), r, ncol, _d(_cplx(eps2, ncol)), _d(_cplx(eps1, 1)),
+                         _d(x.view(np.float64)), _d(y.view(np.float64)))
+    return y
+
+
+def bem_solve_spectrum(m, omega_ev, eps2, eps1, pol_mask, e0):
+    """Direct-solve BEM spectrum.  Returns dict(q=[n_omega, n_pol, n] tessera
+    charges, alpha=[n_omega, 3, 3], sigma=[n_omega] bohr^2, status)."""
+    n, cen, nrm, area, r = _mesh(m)
+    om = np.ascontiguousarray(omega_ev, dtype=np.float64)
+    nw = len(om)
+    npol = bin(pol_mask & 7).count("1")
+    q = np.zeros((nw, npol, n), dtype=np.complex128)
+    alpha = np.zeros((nw, 3, 3), dtype=np.complex128)
+    sigma = np.zeros(nw)
+    st = _load().or_bem_solve_spectrum(n, _d(cen), _d(nrm), _d(area), r, nw, _d(om), _d(_cplx(eps2, nw)),
+                                       _d(_cplx(eps1, 1)), int(pol_mask), float(e0), _d(q.view(np.float64)),
+                                       _d(alpha.view(np.float64)), _d(sigma))
+    return dict(q=q, alpha=alpha, sigma=sigma, status=int(st))

@@ -21,6 +21,8 @@
  *   Section 7: d = sum_i q_i r_i (+ mu_i), alpha_kl = d_k / E_l, sigma_abs.
  *   Section "Post-process Analysis": potential, field and density of the
  *   induced Gaussian charges and dipoles at probe points (or_probe)
+ *   Section 2.3, Eq. (bem-dpcm): BEM surface charges of a triangulated
+ *   surface, "approximate" F (the or_bem_* functions)
  *
  * Readings of points the paper leaves open (each listed in the design notes):
  *   - T^qq diagonal = lim_{r->0} erf(r/R_ii)/r = sqrt(2/pi)/R_q (the Gaussian
@@ -1014,4 +1016,183 @@ void or_probe(int model, int64_t n, const double* xyz_ang, const double* p, cons
         }
     }
     free(xyz);
+}
+
+/* ---- BEM in the DPCM formulation (Section 2.3, Eq. bem-dpcm) -------------
+ * The nanostructure is a closed triangulated surface; tessera i has its
+ * barycentre s_i, outward unit normal n_i and area A_i.  Reading of Eq.
+ * (bem-dpcm) (the printed form mixes an area-weighted and a dimensionless
+ * term, and its normal index does not fit its positive diagonal): the unknowns
+ * are the tessera charges q_i (the paper's sigma_i, so that d = sum_i q_i s_i
+ * as in its Section 7), E_n,i = E . n_i, eps2 the metal inside and eps1 the
+ * medium outside, and
+ *     [ M - 2 pi (eps2 + eps1) / (eps2 - eps1) I ] q = -A E_n,
+ *     M_ij = A_i (s_i - s_j) . n_i / |s_i - s_j|^3   (i != j),
+ *     M_ii = 1.0694 sqrt(4 pi A_i) / (2 R)             (the "approximate" F
+ *            diagonal, R the radius of the sphere enclosing the tesserae).
+ * This is the jump condition eps2 dphi/dn(in) = eps1 dphi/dn(out) for the
+ * potential of the surface charge (normal derivative of 1/|s - s'| taken at
+ * the evaluation point) and the applied field, written for the charges: on a
+ * sphere it gives the Clausius-Mossotti polarizability R^3 (eps2 - eps1) /
+ * (eps2 + 2 eps1) as the mesh is refined (pinned).  M is real and the same at
+ * every frequency; the frequency enters through the scalar shift only. */
+
+typedef struct {
+    int64_t n;
+    double* s;    /* [n][3] bohr */
+    double* nv;   /* [n][3] unit normals */
+    double* a;    /* [n] bohr^2 */
+    double r_enc; /* bohr */
+} bem_mesh;
+
+static bem_mesh bem_load(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2, double r_enc_ang)
+{
+    bem_mesh b;
+    b.n = n;
+    b.s = (double*)malloc(sizeof(double) * 3 * n);
+    b.nv = (double*)malloc(sizeof(double) * 3 * n);
+    b.a = (double*)malloc(sizeof(double) * n);
+    to_bohr(n, cen_ang, b.s);
+    for (int64_t i = 0; i < n; ++i) {
+        double l = sqrt(nrm[3 * i] * nrm[3 * i] + nrm[3 * i + 1] * nrm[3 * i + 1] + nrm[3 * i + 2] * nrm[3 * i + 2]);
+        for (int k = 0; k < 3; ++k) b.nv[3 * i + k] = nrm[3 * i + k] / l;
+        b.a[i] = area_ang2[i] / (ANG_PER_BOHR * ANG_PER_BOHR);
+    }
+    b.r_enc = r_enc_ang / ANG_PER_BOHR;
+    return b;
+}
+
+static void bem_free(bem_mesh* b) { free(b->s); free(b->nv); free(b->a); }
+
+/* one element of M (see above) */
+static double bem_m(const bem_mesh* b, int64_t i, int64_t j)
+{
+    if (i == j) return 1.0694 * sqrt(4.0 * PI * b->a[i]) / (2.0 * b->r_enc);
+    double dv[3], r2 = 0.0, dn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        dv[k] = b->s[3 * i + k] - b->s[3 * j + k];
+        r2 += dv[k] * dv[k];
+        dn += dv[k] * b->nv[3 * i + k];
+    }
+    return b->a[i] * dn / (r2 * sqrt(r2));
+}
+
+/* the shift 2 pi (eps2 + eps1) / (eps2 - eps1); eps as (re, im) */
+static void bem_shift(const double* e2, const double* e1, double* z)
+{
+    double nr = e2[0] + e1[0], ni = e2[1] + e1[1];
+    double dr = e2[0] - e1[0], di = e2[1] - e1[1];
+    double den = dr * dr + di * di;
+    z[0] = 2.0 * PI * (nr * dr + ni * di) / den;
+    z[1] = 2.0 * PI * (ni * dr - nr * di) / den;
+}
+
+/* M as a dense row-major n x n matrix (dimensionless). */
+void or_bem_matrix(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2, double r_enc_ang,
+                   double* m_out)
+{
+    bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) m_out[i * n + j] = bem_m(&b, i, j);
+    bem_free(&b);
+}
+
+/* Right-hand side -A_i E0 n_i,l for polarization l, [n] interleaved complex. */
+void or_bem_rhs(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2, double r_enc_ang, int l,
+                double e0, double* b_out)
+{
+    bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    for (int64_t i = 0; i < n; ++i) {
+        b_out[2 * i] = -b.a[i] * e0 * b.nv[3 * i + l];
+        b_out[2 * i + 1] = 0.0;
+    }
+    bem_free(&b);
+}
+
+/* Matrix-free y_c = [M - z(eps2_c) I] x_c for ncol complex columns (x, y:
+ * [ncol][n] interleaved complex), each with its own metal permittivity. */
+void or_bem_apply(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2, double r_enc_ang,
+                  int64_t ncol, const double* eps2, const double* eps1, const double* x, double* y)
+{
+    bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    for (int64_t c = 0; c < ncol; ++c) {
+        double z[2];
+        bem_shift(eps2 + 2 * c, eps1, z);
+        const double* xc = x + 2 * c * n;
+        double* yc = y + 2 * c * n;
+        for (int64_t i = 0; i < n; ++i) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                double mij = bem_m(&b, i, j);
+                sr += mij * xc[2 * j];
+                si += mij * xc[2 * j + 1];
+            }
+            yc[2 * i] = sr - (z[0] * xc[2 * i] - z[1] * xc[2 * i + 1]);
+            yc[2 * i + 1] = si - (z[0] * xc[2 * i + 1] + z[1] * xc[2 * i]);
+        }
+    }
+    bem_free(&b);
+}
+
+/* Direct-solve spectrum of a BEM mesh: for each frequency, LU of
+ * M - z(eps2(w)) I (own LU, partial pivoting), every requested polarization
+ * solved, d = sum_i q_i s_i (Section 7), alpha_kl = d_k / E0, sigma_abs as for
+ * the atomistic models.  q_out [n_omega][npol][n], alpha_out [n_omega][3][3],
+ * complex interleaved; returns 0, or k + 1 if the k-th factorization failed. */
+int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,
+                              double r_enc_ang, int64_t n_omega, const double* omega_ev, const double* eps2,
+                              const double* eps1, uint32_t pol_mask, double e0, double* q_out, double* alpha_out,
+                              double* sigma_out)
+{
+    bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    int npol = 0;
+    for (int l = 0; l < 3; ++l)
+        if (pol_mask & (1u << l)) ++npol;
+    double* m = (double*)malloc(sizeof(double) * n * n);
+    double* a = (double*)malloc(sizeof(double) * 2 * n * n);
+    double* rhs = (double*)malloc(sizeof(double) * 2 * n);
+    int64_t* piv = (int64_t*)malloc(sizeof(int64_t) * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) m[i * n + j] = bem_m(&b, i, j);
+    int64_t status = 0;
+    for (int64_t w = 0; w < n_omega; ++w) {
+        double z[2];
+        bem_shift(eps2 + 2 * w, eps1, z);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                a[2 * (i * n + j)] = m[i * n + j] - (i == j ? z[0] : 0.0);
+                a[2 * (i * n + j) + 1] = i == j ? -z[1] : 0.0;
+            }
+        if (or_lu_factor(n, a, piv) != 0 && status == 0) status = w + 1;
+        double* al = alpha_out + 18 * w;
+        memset(al, 0, sizeof(double) * 18);
+        double im_sum = 0.0;
+        int p = 0;
+        for (int l = 0; l < 3; ++l) {
+            if (!(pol_mask & (1u << l))) continue;
+            for (int64_t i = 0; i < n; ++i) {
+                rhs[2 * i] = -b.a[i] * e0 * b.nv[3 * i + l];
+                rhs[2 * i + 1] = 0.0;
+            }
+            or_lu_solve(n, a, piv, rhs);
+            double* q = q_out + 2 * n * (w * npol + p);
+            memcpy(q, rhs, sizeof(double) * 2 * n);
+            for (int k = 0; k < 3; ++k) {
+                double dr = 0.0, di = 0.0;
+                for (int64_t i = 0; i < n; ++i) {
+                    dr += rhs[2 * i] * b.s[3 * i + k];
+                    di += rhs[2 * i + 1] * b.s[3 * i + k];
+                }
+                al[2 * (3 * k + l)] = dr / e0;
+                al[2 * (3 * k + l) + 1] = di / e0;
+            }
+            im_sum += al[2 * (3 * l + l) + 1];
+            ++p;
+        }
+        double om = omega_ev[w] / EV_PER_HARTREE;
+        sigma_out[w] = 4.0 * PI * om / C_LIGHT_AU * (im_sum / npol);
+    }
+    free(m); free(a); free(rhs); free(piv);
+    bem_free(&b);
+    return status;
 }

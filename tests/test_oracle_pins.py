@@ -723,3 +723,123 @@ def test_probe_at_an_atom_centre_and_series_boundary():
         lo = O.probe(model, xyz, p, np.array([0.8]), mu, (x * (1 - 1e-9)) * d[None, :])["field"]
         hi = O.probe(model, xyz, p, np.array([0.8]), mu, (x * (1 + 1e-9)) * d[None, :])["field"]
         assert np.allclose(lo, hi, rtol=1e-8)
+
+
+# ---------------------------------------------------------------- BEM (DPCM)
+# Section 2.3, Eq. (bem-dpcm), "approximate" F, read for the tessera charges
+# (oracle/px_oracle.c, or_bem_*).  Pinned to the textbook quasistatic sphere
+# (Clausius-Mossotti polarizability, the Frohlich resonance, the eigenvalues
+# 2 pi / (2l + 1) of the adjoint double-layer operator on a sphere), the
+# depolarization-factor closed form of a spheroid, charge neutrality and the
+# icosahedral isotropy of the mesh.
+from workloads import mesh as ME  # noqa: E402
+
+ANG3 = BOHR ** 3
+
+
+def _bem_alpha(m, eps2, pol=0b100):
+    om = np.linspace(2.0, 3.0, len(np.atleast_1d(eps2)))
+    out = O.bem_solve_spectrum(m, om, np.atleast_1d(eps2), 1.0, pol, 1e-4)
+    assert out["status"] == 0
+    return out
+
+
+@pytest.mark.parametrize("eps2", [-1.5 + 0.3j, 5.0 + 0.0j])
+def test_bem_sphere_converges_to_clausius_mossotti(eps2):
+    """A meshed sphere's dipolar polarizability tends to R^3 (e2 - e1) / (e2 + 2 e1)
+    as the mesh is refined (80, 320, 1280 tesserae), at second order."""
+    R = 40.0
+    exact = (R ** 3 / ANG3) * (eps2 - 1.0) / (eps2 + 2.0)
+    errs = []
+    for k in (1, 2, 3):
+        a = _bem_alpha(ME.sphere(R, k), eps2)["alpha"][0, 2, 2]
+        errs.append(abs(a - exact) / abs(exact))
+    assert errs[0] > 2.5 * errs[1] > 2.5 * 2.5 * errs[2]
+    assert errs[2] < 0.02
+
+
+def test_bem_icosphere_is_isotropic_and_neutral():
+    """The icosahedral mesh leaves no preferred axis (alpha = alpha_iso I), and
+    the induced charges of a neutral body sum to zero."""
+    out = _bem_alpha(ME.sphere(30.0, 2), -2.3 + 0.4j, pol=0b111)
+    al = out["alpha"][0]
+    iso = np.trace(al) / 3
+    assert np.abs(al - iso * np.eye(3)).max() <= 1e-11 * abs(iso)
+    for q in out["q"][0]:
+        assert abs(q.sum()) <= 1e-12 * np.abs(q).sum()
+
+
+def test_bem_operator_has_the_sphere_eigenvalues():
+    """On a sphere the kernel A_i (s_i - s_j).n_i / r^3 is the adjoint double
+    layer: charge patterns of degree l are eigenvectors with eigenvalue
+    2 pi / (2l + 1) (l = 0: 2 pi; l = 1: 2 pi / 3; l = 2: 2 pi / 5)."""
+    res = {}
+    for k in (2, 3):
+        m = ME.sphere(25.0, k)
+        M_ = O.bem_matrix(m)
+        c, a = m["cen"], m["area"]
+        u = c / np.linalg.norm(c, axis=1)[:, None]
+        for l, (q, lam) in enumerate(((a, 2 * np.pi), (a * u[:, 2], 2 * np.pi / 3),
+                                      (a * (3 * u[:, 0] * u[:, 1]), 2 * np.pi / 5))):
+            mq = M_ @ q
+            res.setdefault(l, []).append(np.linalg.norm(mq - lam * q) / np.linalg.norm(lam * q))
+            if k == 3:
+                assert abs((q @ mq) / (q @ q) / lam - 1.0) <= 5e-3      # Rayleigh quotient
+    for l in res:
+        assert res[l][1] < res[l][0] and res[l][1] < 0.03
+
+
+def test_bem_spheroid_approaches_depolarization_closed_form():
+    """A prolate spheroid (semi-axes 15, 15, 45 Angstrom) against the textbook
+    alpha_ll = (a a c / 3) (e2 - e1) / (e1 + L_l (e2 - e1)), L from the
+    eccentricity: the error falls as the mesh is refined."""
+    a_, c_ = 15.0, 45.0
+    e = np.sqrt(1 - (a_ / c_) ** 2)
+    Lz = (1 - e * e) / (e * e) * (np.log((1 + e) / (1 - e)) / (2 * e) - 1)
+    Lx = (1 - Lz) / 2
+    eps2 = -1.2 + 0.5j
+    errs = {0: [], 2: []}
+    for k in (2, 3):
+        out = _bem_alpha(ME.spheroid(a_, c_, k), eps2, pol=0b101)
+        for l, L in ((0, Lx), (2, Lz)):
+            exact = (a_ * a_ * c_ / 3.0 / ANG3) * (eps2 - 1.0) / (1.0 + L * (eps2 - 1.0))
+            errs[l].append(abs(out["alpha"][0, l, l] - exact) / abs(exact))
+        for q in out["q"][0]:
+            assert abs(q.sum()) <= 1e-3 * np.abs(q).sum()
+    for l in (0, 2):
+        assert errs[l][1] < errs[l][0] and errs[l][1] < 0.06
+
+
+def test_bem_drude_sphere_resonates_at_the_frohlich_frequency():
+    """A Drude sphere absorbs most where e2 = -2 e1, i.e. at w_p / sqrt(eps_inf + 2)."""
+    p = M.load("ag_bem")
+    b = p["bem"]
+    wf = b["omega_p_ev"] / np.sqrt(b["eps_inf"] + 2.0)
+    om = np.linspace(wf - 0.15, wf + 0.15, 61)
+    out = O.bem_solve_spectrum(ME.sphere(20.0, 2), om, M.drude_permittivity(p, om), 1.0, 0b001, 1e-4)
+    peak = om[int(np.argmax(out["sigma"]))]
+    assert abs(peak - wf) <= 0.01 * wf
+
+
+def test_bem_apply_rhs_and_direct_solution_agree():
+    """The matrix-free apply is (M - z I) x with z = 2 pi (e2 + e1) / (e2 - e1);
+    the right-hand side is -A E0 n_l; the dense LU solution satisfies the system."""
+    m = ME.spheroid(12.0, 30.0, 2)
+    n = len(m["area"])
+    om = np.array([2.5, 3.1])
+    eps2 = np.array([-3.0 + 0.7j, 2.0 + 0.1j])
+    M_ = O.bem_matrix(m)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    y = O.bem_apply(m, eps2, 1.0, x)
+    for c in range(2):
+        z = 2 * np.pi * (eps2[c] + 1.0) / (eps2[c] - 1.0)
+        ref = M_ @ x[c] - z * x[c]
+        assert np.abs(y[c] - ref).max() <= 1e-12 * np.abs(ref).max()
+    out = O.bem_solve_spectrum(m, om, eps2, 1.0, 0b011, 1e-4)
+    for l in (0, 1):
+        b = O.bem_rhs(m, l, 1e-4)
+        assert np.abs(b + 1e-4 * m["area"] / BOHR ** 2 * m["nrm"][:, l]).max() <= 1e-15
+        for w in range(2):
+            r = O.bem_apply(m, eps2[w:w + 1], 1.0, out["q"][w, l][None, :])[0] - b
+            assert np.abs(r).max() <= 1e-11 * np.abs(b).max()

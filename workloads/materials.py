@@ -49,3 +49,17 @@ def interband_alpha(p: dict, omega_ev) -> np.ndarray:
     eps = ib["eps_inf"] + s * w0 ** 2 / (w0 ** 2 - w ** 2 - 1j * g * w)
     vol = ib["volume_per_atom_bohr3"]
     return (3.0 * vol / (4.0 * np.pi)) * (eps - 1.0) / (eps + 2.0)
+
+
+def drude_permittivity(p: dict, omega_ev) -> np.ndarray:
+    """Synthetic metal permittivity for the BEM workloads (complex, on the grid):
+    eps(w) = eps_inf - w_p^2 / (w^2 + i gamma w) plus the material's interband
+    Lorentzian if it has one (the same single-Lorentzian form as interband_alpha)."""
+    w = np.asarray(omega_ev, dtype=np.float64)
+    b = p["bem"]
+    eps = b["eps_inf"] - b["omega_p_ev"] ** 2 / (w * w + 1j * b["gamma_ev"] * w)
+    ib = p.get("interband")
+    if ib is not None and b.get("with_interband", False):
+        w0, g, st = ib["omega0_ev"], ib["gamma_ev"], ib["strength"]
+        eps = eps + st * w0 ** 2 / (w0 ** 2 - w ** 2 - 1j * g * w)
+    return eps
