@@ -47,7 +47,7 @@ typedef enum {
     PX_E_STATE = 5      /* call out of order (e.g. results before a solve) */
 } pxStatus;
 
-typedef enum { PX_WFQ = 0, PX_WFQFMU = 1 } pxModel;
+typedef enum { PX_WFQ = 0, PX_WFQFMU = 1, PX_BEM = 2 } pxModel;
 
 typedef enum {
     PX_FP64 = 0,   /* every step in FP64 */
@@ -217,6 +217,32 @@ pxStatus pxCreateStructure(pxModel model, int64_t n_atoms, const double* xyz_ang
 pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* xyz_ang, const uint8_t* types,
                                  const pxMaterial* mat_a, const pxMaterial* mat_b, void* hip_stream,
                                  pxStructure* out);
+
+/* Creates a BEM structure in the DPCM formulation (Section 2.3, Eq.
+ * bem-dpcm, the "approximate" F): a closed surface mesh of n_tess tesserae
+ * with barycentres cen_ang (n_tess x 3, Angstrom), outward normals normals
+ * (n_tess x 3, normalised here) and areas area_ang2 (Angstrom^2), all copied;
+ * r_enc_ang is the radius of the sphere enclosing the mesh (the R of F's
+ * diagonal); eps_env (2 doubles, complex; NULL = vacuum) is the medium's
+ * permittivity eps1.  The unknowns are the tessera charges q_i (pxGetCharges
+ * returns them in the caller's tessera order) and the solved system is
+ *   [ M - 2 pi (eps2 + eps1) / (eps2 - eps1) I ] q = -A E_n,
+ *   M_ij = A_i (s_i - s_j).n_i / |s_i - s_j|^3, M_ii = 1.0694 sqrt(4 pi A_i) / (2R),
+ * with E_n,i = E0 e_l . n_i; d = sum_i q_i s_i (Section 7) and alpha, sigma_abs
+ * as for the atomistic models.  pxSetFrequencies takes the metal permittivity
+ * eps2(omega_w) per frequency in its alpha_ib argument (2 * n_omega doubles,
+ * interleaved complex, != eps1).  M is real and the same at every frequency,
+ * so pxSolveSpectrum (shifted >= 1) runs the shared-Krylov phase over all
+ * frequencies, then the true FP64 residual of every column; M is generated on
+ * the fly in FP64 (t_apply is ignored; PX_MIXED runs the FP64 apply).
+ * pxApplyOperator (PX_FP64 only) and pxApplyOperatorNoAlloc take eps2 per
+ * column in alpha_ib; pxInducedField and pxProbeField refuse a BEM structure;
+ * pxSolveBatch and the server solve it whole (shifted >= 1, else
+ * PX_E_INVALID).  Errors: PX_E_INVALID for n_tess < 1, non-finite inputs, a
+ * zero normal, an area <= 0 or r_enc <= 0; barycentres must be distinct.
+ * PX_E_OOM; PX_E_DEVICE. */
+pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                     double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out);
 
 /* Sets the frequency grid (omega_ev[n_omega], > 0, copied), the polarizations
  * (pol_mask bit0 = x, bit1 = y, bit2 = z; one column per set bit and

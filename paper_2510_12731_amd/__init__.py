@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libplasmonx_hip.so")
 
 PX_OK, PX_E_INVALID, PX_E_OOM, PX_E_NOTCONV, PX_E_DEVICE, PX_E_STATE = range(6)
-PX_WFQ, PX_WFQFMU = 0, 1
+PX_WFQ, PX_WFQFMU, PX_BEM = 0, 1, 2
 PX_FP64, PX_MIXED = 0, 1
 PX_ORTHO_CGS2, PX_ORTHO_DCGS2 = 0, 1
 PX_TAPPLY_AUTO, PX_TAPPLY_ON_THE_FLY, PX_TAPPLY_STORED = 0, 1, 2
@@ -28,7 +28,7 @@ EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHete
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
-            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc"]
+            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc", "pxCreateBem"]
 
 
 class PxError(RuntimeError):
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.pxServerStep.argtypes = [_vp, ctypes.POINTER(_vp), i32, ctypes.POINTER(i32)]
     lib.pxServerQuery.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]
+    lib.pxCreateBem.argtypes = [i64, _dp, _dp, _dp, ctypes.c_double, _dp, _vp, ctypes.POINTER(_vp)]
     lib.pxApplyOperatorNoAlloc.argtypes = [_vp, i32, _dp, _dp, _vp, _vp]
     lib.pxServerMemory.argtypes = [_vp, _dp, _dp, ctypes.POINTER(i32)]
     lib.pxSolveFootprint.argtypes = [_vp, ctypes.POINTER(pxSolveOptions), _dp]
@@ -174,6 +175,18 @@ def pxCreateStructureHetero(model, xyz_ang, types, mat_a, mat_b, hip_stream=None
     mb = mat_b if isinstance(mat_b, pxMaterial) else material(mat_b)
     _check(load().pxCreateStructureHetero(int(model), len(xyz), _ptr(xyz), t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                           ctypes.byref(ma), ctypes.byref(mb), hip_stream, ctypes.byref(h)))
+    return h
+
+
+def pxCreateBem(mesh, eps_env=1.0, hip_stream=None):
+    """BEM structure from a mesh dict (cen, nrm, area in Angstrom units, r_enc)."""
+    cen = np.ascontiguousarray(mesh["cen"], dtype=np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(mesh["nrm"], dtype=np.float64).reshape(-1, 3)
+    area = np.ascontiguousarray(mesh["area"], dtype=np.float64).reshape(-1)
+    e1 = np.array([complex(eps_env).real, complex(eps_env).imag])
+    h = _vp()
+    _check(load().pxCreateBem(len(area), _ptr(cen), _ptr(nrm), _ptr(area), float(mesh["r_enc"]), _ptr(e1), hip_stream,
+                              ctypes.byref(h)))
     return h
 
 
@@ -439,16 +452,24 @@ class Structure:
     alpha_ib arguments then hold (alpha_IB of A, alpha_IB of B) per frequency
     or column, shape (n, 2)."""
 
-    def __init__(self, model, xyz_ang, params, hip_stream=None, types=None, params_b=None):
+    def __init__(self, model, xyz_ang, params, hip_stream=None, types=None, params_b=None, mesh=None, eps_env=1.0):
         self.model = int(model)
         self.het = types is not None
-        if self.het:
+        if self.model == PX_BEM:
+            self.h = pxCreateBem(mesh, eps_env, hip_stream)
+        elif self.het:
             self.h = pxCreateStructureHetero(model, xyz_ang, types, params, params_b, hip_stream)
         else:
             self.h = pxCreateStructure(model, xyz_ang, params, hip_stream)
         self.n, self.nu = pxGetSize(self.h)
         self.n_omega = 0
         self.ncol = 0
+
+    @classmethod
+    def bem(cls, mesh, eps_env=1.0, hip_stream=None):
+        """A BEM (DPCM) structure on a mesh dict (workloads.mesh); its
+        set_frequencies takes eps2(w) per frequency as alpha_ib."""
+        return cls(PX_BEM, None, None, hip_stream, mesh=mesh, eps_env=eps_env)
 
     def set_frequencies(self, omega_ev, pol_mask, e0_au=1e-4, alpha_ib=None):
         pxSetFrequencies(self.h, omega_ev, pol_mask, e0_au, alpha_ib)

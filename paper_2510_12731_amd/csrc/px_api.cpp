@@ -64,6 +64,23 @@ void shift_mu(double ar, double ai, double& zr, double& zi)
     zi = ai / den;
 }
 
+void shift_bem(double e2r, double e2i, double e1r, double e1i, double& zr, double& zi)
+{
+    const double nr = e2r + e1r, ni = e2i + e1i, dr = e2r - e1r, di = e2i - e1i;
+    const double den = dr * dr + di * di;
+    zr = 2.0 * PI * (nr * dr + ni * di) / den;
+    zi = 2.0 * PI * (ni * dr - nr * di) / den;
+}
+
+// The charge-row shift of frequency w: z_q(w) of Eq. (z_q_wfq), or for a BEM
+// structure the shift of Eq. (bem-dpcm) with the metal permittivity eps2(w)
+// given with the frequencies.
+void shift_of(const pxStructure_t* s, int w, double& zr, double& zi)
+{
+    if (s->model == PX_BEM) shift_bem(s->aib[2 * w], s->aib[2 * w + 1], s->eps1[0], s->eps1[1], zr, zi);
+    else shift_q(s->drude, s->mat.tau, s->omega_au[w], zr, zi);
+}
+
 void het_factors(const pxStructure_t* s, double w, const double* aib4, double2 out[6])
 {
     const double dr[2] = {s->drude, s->drude_b};
@@ -105,6 +122,8 @@ void prepare_solve(pxStructure_t* s)
         d_gam = dalloc<double2>((size_t)2 * s->ldg);
         HC(hipMemcpyAsync(d_gam, gam.data(), sizeof(double2) * 2 * s->ldg, hipMemcpyHostToDevice, s->st));
         px::build_rhs_het(s->g, s->d_col_pol, d_gam, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
+    } else if (s->model == PX_BEM) {
+        px::bem_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, s->st);
     } else {
         px::build_rhs(s->g, s->d_col_pol, s->e0, s->b, ncol, s->ldg, SOLVER_MU_SIGN, s->st);
     }
@@ -307,7 +326,8 @@ float time_apply(pxStructure_t* s, bool f32, int method, const void* X, void* Y,
 // The method for this shape: forced by the options, else the tuner's choice.
 int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const pxSolveOptions& o)
 {
-    if (o.t_apply == PX_TAPPLY_ON_THE_FLY) return TA_FLY;
+    // the BEM operator is generated on the fly only (it is not symmetric)
+    if (o.t_apply == PX_TAPPLY_ON_THE_FLY || s->g.bem) return TA_FLY;
     if (o.t_apply == PX_TAPPLY_STORED) {
         ensure_stored(s, f32);
         return TA_STORED;
@@ -410,7 +430,7 @@ void upload_shifts(pxStructure_t* s, const std::vector<int>& act, int lda)
         const int c = act[k];
         const int w = c / s->npol;
         double zr, zi;
-        shift_q(s->drude, s->mat.tau, s->omega_au[w], zr, zi);
+        shift_of(s, w, zr, zi);
         zq[k] = make_double2(zr, zi);
         if (s->model == PX_WFQFMU) {
             shift_mu(s->aib[2 * w], s->aib[2 * w + 1], zr, zi);
@@ -547,7 +567,8 @@ class BlockRun {
         HC(hipMemcpyAsync(W.nrm, beta_.data(), sizeof(double) * na_, hipMemcpyHostToDevice, s->st));
         vstride_ = nup * lda_;
         px::normalize(W.rs, W.nrm, nullptr, W.V, mixed_ ? W.X32 : nullptr, na_, lda_, nup, s->st);
-        wide32_ = mixed_ && lda_ > 4;
+        // the BEM operator has an FP64 apply only
+        wide32_ = mixed_ && lda_ > 4 && !s->g.bem;
         method_ = wide32_ ? tapply_method(s, true, W.X32, W.Y32, 2 * lda_, 2 * lda_, o_)
                           : tapply_method(s, false, W.V, W.Y64, 2 * lda_, 2 * lda_, o_);
         lag_ = kLag;
@@ -729,7 +750,7 @@ struct Scratch {
 
 bool shifted_applies(const pxStructure_t* s, const pxSolveOptions& o)
 {
-    return o.shifted >= 1 && s->model == PX_WFQ && !s->het;
+    return o.shifted >= 1 && (s->model == PX_WFQ || s->model == PX_BEM) && !s->het;
 }
 
 // Structures that pxSolveBatch and the server solve whole (each on a stream of
@@ -908,7 +929,7 @@ class ShiftedRun : public PhaseRun {
         std::vector<double> th(P);
         for (int p = 0; p < P; ++p) {
             double zr, zi;
-            shift_q(s->drude, s->mat.tau, s->omega_au[p / npol_], zr, zi);
+            shift_of(s, p / npol_, zr, zi);
             zh[p] = make_double2(zr, zi);
             g0[p] = make_double2(s->bnorm[p % npol_], 0.0);
             th[p] = 0.5 * o.rel_tol * s->bnorm[p];
@@ -1054,7 +1075,7 @@ class BlockShiftedRun : public PhaseRun {
         std::vector<double> th(P);
         for (int p = 0; p < P; ++p) {
             double zr, zi;
-            shift_q(s->drude, s->mat.tau, s->omega_au[p / R], zr, zi);
+            shift_of(s, p / R, zr, zi);
             zh[p] = make_double2(zr, zi);
             th[p] = 0.5 * o.rel_tol * s->bnorm[p];
         }
@@ -1526,7 +1547,8 @@ pxStatus create_impl(pxModel model, int64_t n_atoms, const double* xyz_ang, cons
     g_err.clear();
     if (!out || !xyz_ang || !mat) return fail(PX_E_INVALID, "null argument");
     *out = nullptr;
-    if (model != PX_WFQ && model != PX_WFQFMU) return fail(PX_E_INVALID, "unknown model");
+    if (model != PX_WFQ && model != PX_WFQFMU)
+        return fail(PX_E_INVALID, model == PX_BEM ? "a BEM structure is made with pxCreateBem" : "unknown model");
     if (n_atoms < 1 || n_atoms > (int64_t)1 << 28) return fail(PX_E_INVALID, "n_atoms out of range");
     for (int64_t i = 0; i < n_atoms; ++i)
         if (!finite3(xyz_ang + 3 * i)) return fail(PX_E_INVALID, "non-finite coordinate");
@@ -1611,6 +1633,54 @@ pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* x
     return create_impl(model, n_atoms, xyz_ang, types, mat_a, mat_b, hip_stream, out);
 }
 
+pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                     double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out)
+{
+    g_err.clear();
+    if (!out || !cen_ang || !normals || !area_ang2) return fail(PX_E_INVALID, "null argument");
+    *out = nullptr;
+    if (n_tess < 1 || n_tess > (int64_t)1 << 26) return fail(PX_E_INVALID, "n_tess out of range");
+    if (!(r_enc_ang > 0) || !std::isfinite(r_enc_ang)) return fail(PX_E_INVALID, "r_enc must be > 0");
+    const double e1r = eps_env ? eps_env[0] : 1.0, e1i = eps_env ? eps_env[1] : 0.0;
+    if (!std::isfinite(e1r) || !std::isfinite(e1i)) return fail(PX_E_INVALID, "eps_env must be finite");
+    for (int64_t i = 0; i < n_tess; ++i) {
+        const double* v = normals + 3 * i;
+        const double l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        if (!finite3(cen_ang + 3 * i) || !finite3(v) || !(l2 > 0) || !std::isfinite(l2))
+            return fail(PX_E_INVALID, "non-finite barycentre or normal, or a zero normal");
+        if (!(area_ang2[i] > 0) || !std::isfinite(area_ang2[i])) return fail(PX_E_INVALID, "tessera areas must be > 0");
+    }
+    return guarded([&]() -> pxStatus {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        HC(hipGetDevice(&dev));
+        HC(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(PX_E_DEVICE, std::string("built for gfx950, device is ") + prop.gcnArchName);
+        std::unique_ptr<pxStructure_t> s(new pxStructure_t());
+        s->model = PX_BEM;
+        s->eps1[0] = e1r;
+        s->eps1[1] = e1i;
+        s->st = static_cast<hipStream_t>(hip_stream);
+        s->g.model = 0;
+        s->g.n = n_tess;
+        s->g.np = ((n_tess + px::ATOM_PAD - 1) / px::ATOM_PAD) * px::ATOM_PAD;
+        s->g.nu = n_tess;
+        s->g.nup = s->g.np;
+        std::vector<double> cb(3 * n_tess), ab(n_tess);
+        for (int64_t i = 0; i < 3 * n_tess; ++i) cb[i] = cen_ang[i] / ANG_PER_BOHR;
+        for (int64_t i = 0; i < n_tess; ++i) ab[i] = area_ang2[i] / (ANG_PER_BOHR * ANG_PER_BOHR);
+        HC(px::build_bem_geometry(s->g, cb.data(), normals, ab.data(), r_enc_ang / ANG_PER_BOHR, s->st));
+        s->perm.resize(n_tess);
+        for (int64_t i = 0; i < n_tess; ++i) s->perm[i] = (int32_t)i;
+        s->d_perm = dalloc<int32_t>(n_tess);
+        HC(hipMemcpyAsync(s->d_perm, s->perm.data(), sizeof(int32_t) * n_tess, hipMemcpyHostToDevice, s->st));
+        HC(hipStreamSynchronize(s->st));
+        *out = s.release();
+        return PX_OK;
+    });
+}
+
 pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask, double e0_au,
                           const double* alpha_ib)
 {
@@ -1629,6 +1699,14 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
                 (alpha_ib[2 * w] == 0.0 && alpha_ib[2 * w + 1] == 0.0))
                 return fail(PX_E_INVALID, "alpha_ib must be finite and non-zero");
     }
+    if (s->model == PX_BEM) {
+        // eps2(w): the metal permittivity per frequency
+        if (!alpha_ib) return fail(PX_E_INVALID, "a BEM structure needs eps2(w) (alpha_ib argument)");
+        for (int w = 0; w < n_omega; ++w)
+            if (!std::isfinite(alpha_ib[2 * w]) || !std::isfinite(alpha_ib[2 * w + 1]) ||
+                (alpha_ib[2 * w] == s->eps1[0] && alpha_ib[2 * w + 1] == s->eps1[1]))
+                return fail(PX_E_INVALID, "eps2 must be finite and differ from the medium's eps1");
+    }
     return guarded([&]() -> pxStatus {
         s->solved = false;
         s->n_omega = n_omega;
@@ -1641,7 +1719,7 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
         for (int w = 0; w < n_omega; ++w) s->omega_au[w] = omega_ev[w] / EV_PER_HARTREE;
         const int naib = s->het ? 4 : 2;
         s->aib.assign((size_t)naib * n_omega, 0.0);
-        if (s->model == PX_WFQFMU) std::copy(alpha_ib, alpha_ib + naib * n_omega, s->aib.begin());
+        if (s->model != PX_WFQ) std::copy(alpha_ib, alpha_ib + naib * n_omega, s->aib.begin());
         s->col_pol.clear();
         for (int w = 0; w < n_omega; ++w)
             for (int l = 0; l < 3; ++l)
@@ -1688,6 +1766,8 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
         if (ss[k]->ncol == 0) return fail(PX_E_STATE, "pxSolveBatch: every structure needs pxSetFrequencies");
         if (ss[k]->st != ss[0]->st) return fail(PX_E_INVALID, "pxSolveBatch: structures use different streams");
         if (ss[k]->het) return fail(PX_E_INVALID, "pxSolveBatch: two-type structures are solved with pxSolveSpectrum");
+        if (ss[k]->model == PX_BEM && o.shifted < 1)
+            return fail(PX_E_INVALID, "pxSolveBatch: BEM structures are solved whole (shifted >= 1)");
         for (int32_t j = 0; j < k; ++j)
             if (ss[j] == ss[k]) return fail(PX_E_INVALID, "pxSolveBatch: a structure is listed twice");
     }
@@ -1864,6 +1944,7 @@ pxStatus pxInducedField(pxStructure s, int32_t i_omega, int32_t pol, int64_t npt
 {
     g_err.clear();
     if (!s || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxInducedField: invalid argument");
+    if (s->model == PX_BEM) return fail(PX_E_INVALID, "pxInducedField: the Gaussian densities are those of the atomistic models");
     if (!s->solved) return fail(PX_E_STATE, "pxInducedField: no solved spectrum");
     if (i_omega < 0 || i_omega >= s->n_omega || pol < 0 || pol > 2 || !(s->pol_mask & (1u << pol)))
         return fail(PX_E_INVALID, "pxInducedField: column not in the solved set");
@@ -1885,6 +1966,7 @@ pxStatus pxProbeField(pxStructure s, const double* q, const double* mu, int64_t 
 {
     g_err.clear();
     if (!s || !q || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxProbeField: invalid argument");
+    if (s->model == PX_BEM) return fail(PX_E_INVALID, "pxProbeField: the Gaussian densities are those of the atomistic models");
     if (mu && s->model != PX_WFQFMU) return fail(PX_E_INVALID, "pxProbeField: dipoles given for an omegaFQ structure");
     return guarded([&]() -> pxStatus {
         const int S = s->model == PX_WFQFMU ? 8 : 2;
@@ -1945,6 +2027,8 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
     if (ncol < 1) return fail(PX_E_INVALID, "ncol must be >= 1");
     if (precision != PX_FP64 && precision != PX_MIXED) return fail(PX_E_INVALID, "unknown precision");
     if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
+    if (s->model == PX_BEM && (!alpha_ib || precision != PX_FP64))
+        return fail(PX_E_INVALID, "a BEM structure needs eps2 per column (alpha_ib) and PX_FP64");
     for (int c = 0; c < ncol; ++c)
         if (!(omega_ev[c] > 0)) return fail(PX_E_INVALID, "frequencies must be > 0");
     const int naib = s->het ? 4 : 2;
@@ -1969,7 +2053,8 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
                 continue;
             }
             double zr, zi;
-            shift_q(s->drude, s->mat.tau, w, zr, zi);
+            if (s->model == PX_BEM) shift_bem(alpha_ib[2 * c], alpha_ib[2 * c + 1], s->eps1[0], s->eps1[1], zr, zi);
+            else shift_q(s->drude, s->mat.tau, w, zr, zi);
             zq[c] = make_double2(zr, zi);
             if (a) {
                 shift_mu(a[0], a[1], zr, zi);
@@ -2007,11 +2092,12 @@ pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega
     if (!s || !omega_ev || !x || !y) return fail(PX_E_INVALID, "null argument");
     if (ncol < 1 || ncol > 4) return fail(PX_E_INVALID, "pxApplyOperatorNoAlloc: ncol must be in [1, 4]");
     if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
+    if (s->model == PX_BEM && !alpha_ib) return fail(PX_E_INVALID, "a BEM structure needs eps2 per column (alpha_ib)");
     for (int c = 0; c < ncol; ++c)
         if (!(omega_ev[c] > 0) || !std::isfinite(omega_ev[c])) return fail(PX_E_INVALID, "frequencies must be > 0");
     const int naib = s->het ? 4 : 2;
     return guarded([&]() -> pxStatus {
-        if (s->model == PX_WFQ && !s->g.near_off) return fail(PX_E_STATE, "near-field list missing");
+        if (s->model == PX_WFQ && !s->het && !s->g.near_off) return fail(PX_E_STATE, "near-field list missing");
         const int64_t nu = s->g.nu, nup = s->g.nup;
         const int lda = ncol;
         const size_t vec = (size_t)nup * lda;
@@ -2051,7 +2137,8 @@ pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega
                 continue;
             }
             double zr, zi;
-            shift_q(s->drude, s->mat.tau, wv, zr, zi);
+            if (s->model == PX_BEM) shift_bem(alpha_ib[2 * c], alpha_ib[2 * c + 1], s->eps1[0], s->eps1[1], zr, zi);
+            else shift_q(s->drude, s->mat.tau, wv, zr, zi);
             h[c] = make_double2(zr, zi);
             if (a) {
                 shift_mu(a[0], a[1], zr, zi);
@@ -2165,6 +2252,8 @@ pxStatus pxServerSubmit(pxServer sv, pxStructure s)
     if (s->ncol == 0) return fail(PX_E_STATE, "pxServerSubmit: call pxSetFrequencies first");
     if (s->st != sv->st) return fail(PX_E_INVALID, "pxServerSubmit: structure uses another stream");
     if (s->het) return fail(PX_E_INVALID, "pxServerSubmit: two-type structures are solved with pxSolveSpectrum");
+    if (s->model == PX_BEM && sv->o.shifted < 1)
+        return fail(PX_E_INVALID, "pxServerSubmit: BEM structures are solved whole (shifted >= 1)");
     const bool whole = pooled_solve(s, sv->o);
     if (whole ? solve_footprint(s, sv->o) > sv->budget : sv->eng->rows_for(s) > sv->eng->rows_capacity())
         return fail(PX_E_OOM, "pxServerSubmit: the structure can never fit the memory budget");

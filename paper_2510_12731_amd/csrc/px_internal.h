@@ -65,7 +65,25 @@ struct Geometry {
     // kernel every atom's position relative to it with its squared norm in w
     double cx = 0, cy = 0, cz = 0;
     double4* xyzc = nullptr;   // [np], built with the near-field list
+    // BEM (DPCM): the sites are tesserae (barycentres in xyz64), with their
+    // outward unit normal and area in bem_na [np] (ghosts: area 0), the
+    // identity in place of Kbar and the radius enclosing the mesh (bohr)
+    bool bem = false;
+    double4* bem_na = nullptr;
+    double bem_r = 0.0;
 };
+
+// ---- BEM, DPCM (px_bem.hip) ---------------------------------------------------
+// The mesh on the device (caller order; positions and areas in bohr units).
+hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double* nrm, const double* area_bohr2,
+                              double r_enc_bohr, hipStream_t st);
+// Y = M X for ncols real columns (X, Y row-major, ld ldx), M generated on the
+// fly in FP64; scratch of bem_scratch_bytes(g).
+size_t bem_scratch_bytes(const Geometry& g);
+void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st, double* scratch,
+                   const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
+// b = -A E0 n_l per column (complex, imaginary part 0)
+void bem_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, hipStream_t st);
 
 // Ascending bitonic sort of npow (a power of two) 64-bit keys in place.
 void sort_keys(uint64_t* keys, int64_t npow, hipStream_t st);

@@ -372,6 +372,8 @@ class LaunchTimer {
 void shift_q(double drude, double tau, double w, double& zr, double& zi);
 // Eq. (z-mu): z_mu = -1 / alpha_IB
 void shift_mu(double ar, double ai, double& zr, double& zi);
+// Eq. (bem-dpcm): the BEM shift 2 pi (eps2 + eps1) / (eps2 - eps1)
+void shift_bem(double e2r, double e2i, double e1r, double e1i, double& zr, double& zi);
 
 }  // namespace pxs
 
@@ -379,6 +381,7 @@ struct pxStructure_t {
     px::Geometry g;
     pxModel model = PX_WFQ;
     pxMaterial mat{};
+    double eps1[2] = {1.0, 0.0};   // BEM: permittivity of the medium around the mesh
     double drude = 0.0;
     // two atom types: the second material, its Drude weight (types live in g)
     bool het = false;
@@ -430,7 +433,7 @@ struct pxStructure_t {
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, d_perm, d_col_pol, d_omega, x, b};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, d_perm, d_col_pol, d_omega, x, b};
         for (void* p : ps) pxs::dfree(p);
         // the stored T came from the block cache
         for (void* p : {(void*)t32, (void*)t64}) {

@@ -1538,7 +1538,7 @@ int sk_workgroups(int64_t total) { return (int)std::max<int64_t>(1, std::min<int
 
 hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
 {
-    if (g.model != 0 || g.near_off) return hipSuccess;
+    if (g.model != 0 || g.near_off || g.bem) return hipSuccess;
     const double rqq = std::sqrt(2.0) * g.r_q;
     const double r_far = XFAR_Q64 * rqq;
     const int64_t nb = g.np / 256;
@@ -1641,6 +1641,7 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
 
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 {
+    if (g.bem) return bem_scratch_bytes(g);
     if (ncols > 8) return 0;
     const int ns = g.model ? narrow_splits(g) : std::max(narrow_splits(g), narrow_q_splits(g));
     return (size_t)ns * (g.model ? 4 : 1) * g.np * ncols * sizeof(double);
@@ -1650,6 +1651,10 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
                 double* scratch, size_t scratch_bytes, const int32_t* stop, const hipEvent_t* ev)
 {
     (void)scratch_bytes;
+    if (g.bem) {
+        bem_apply_f64(g, X, Y, ldx, ncols, st, scratch, stop, ev);
+        return;
+    }
     hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
     if (ncols <= 8) {
         // narrow layout: ldx == ncols
