@@ -2,19 +2,23 @@
 
 Workload (one "step" = the whole path once): an Ag fcc sphere of 20,000 atoms,
 128 frequencies 2-5 eV x 3 polarizations = 384 (frequency, polarization)
-columns, each driven by blocked GMRES(50) with FP64 iterative refinement to
-a true relative residual of 1e-8.  A step creates the structure on the GPU
-(Morton order, neighbour list, Kbar), sets the frequencies, solves and reads
-the spectrum back; inputs are in host memory as they arrive at the C ABI.
+columns, each driven to a true relative residual of 1e-8 (recomputed in
+FP64).  A step creates the structure on the GPU (neighbour list, Kbar,
+near-field list), sets the frequencies, solves (the shared-Krylov phase: one
+FP64 block Arnoldi process over the three polarizations serves every
+frequency, then every column's true FP64 residual) and reads the spectrum
+back; the inputs are host arrays as they arrive at the C ABI.
 
-Reported next to the headline number:
-  * roofline of the dominant kernel (the FP32 MFMA T-apply): algorithmic FLOP
-    4 N^2 per complex column per launch over the launch times measured with HIP
-    events on the library's stream, against the MI355X FP32 matrix peak;
-  * the same spectrum with the plain FP64 solver one column at a time (a
-    sampled subset of the columns, scaled to freq-solves/s), and blocked FP64;
-  * the oracle (single-threaded FP64 dense LU) timed on a bounded sample of
-    the same workload on the host.
+Reported next to the headline number (one JSON line):
+  * roofline of the dominant kernel (the narrow FP64 T-apply), from HIP-event
+    times of its launches on the library's stream, against the FP64 vector peak;
+  * the small spectrum (249 atoms x 50 w) against the oracle's direct solve,
+    and the oracle residual of sampled columns of the headline spectrum;
+  * the plain FP64 solver (one column at a time, sampled) and FP64 blocked,
+    the blocked mixed-precision solver, the per-polarization phase;
+  * the other workloads: the 10,000-atom Au rod (omegaFQFmu), the 64-structure
+    graphene batch, the serving mix, and the BEM sphere;
+  * the oracle timed on the host's cores (a bounded sample, scaled).
 """
 from __future__ import annotations
 
@@ -93,7 +97,8 @@ def tapply_roofline(runs, n, npol, traffic, traffic_note):
         f32 = dom.startswith("f32")
         peak, bound = (FP32_MFMA_PEAK_TFLOPS if f32 else FP64_MFMA_PEAK_TFLOPS), "mfma"
         kname = {"f32_on_the_fly": "k_tapply_wfq_f32 (+ k_sk_fixup), T generated on the fly",
-                 "f32_stored": "rocBLAS sgemm on the stored T", "f64_stored": "rocBLAS dgemm on the stored T"}[dom]
+                 "f32_stored": "k_tstored_f32 (+ k_sk_fixup) on the stored T",
+                 "f64_stored": "k_tstored_f64 / k_tstored_narrow on the stored T"}[dom]
         flop_note = "2 N^2 FLOP per real column still iterating, peak = matrix"
     achieved = fl / (ms[dom] * 1e-3) / 1e12 if ms[dom] > 0 else 0.0
     return dict(bound=bound, achieved=round(achieved, 2), peak=peak, unit="TFLOP/s", frac=round(achieved / peak, 4),
@@ -118,7 +123,7 @@ def blocked_roofline(runs, n, traffic, traffic_cols):
         note = (f"HBM bytes per launch at {traffic_cols} real columns (counter runs); "
                 f"algorithmic {2 * 4 * n * traffic_cols} B (X read once, Y written once)")
     if not fly:
-        traffic, traffic_cols, kname = measured_traffic_stored("tapply_f32_stored_sgemm_sphere20k_hbm_counters.md")
+        traffic, traffic_cols, kname = measured_traffic_stored("tapply_f32_stored_sphere20k_hbm_counters.md")
         if traffic is not None:
             nup = ((n + 255) // 256) * 256
             note = (f"HBM bytes per launch at {traffic_cols} real columns (counter runs, {kname}); "
@@ -126,7 +131,7 @@ def blocked_roofline(runs, n, traffic, traffic_cols):
     return dict(bound="mfma", achieved=round(achieved, 2), peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), traffic=traffic, traffic_note=note,
                 kernel=("k_tapply_wfq_f32 (+ k_sk_fixup), T generated on the fly" if fly else
-                        "rocBLAS sgemm on the stored T (autotuner's choice for this width)"),
+                        "k_tstored_f32 (+ k_sk_fixup) on the stored T (autotuner's choice for this width)"),
                 launches=int(nl), avg_launch_ms=round(ms[dom] / max(nl, 1), 4),
                 avg_algorithmic_gflop_per_launch=round(fl / max(nl, 1) / 1e9, 2),
                 method_ms={k: round(v, 1) for k, v in ms.items()},
@@ -177,34 +182,255 @@ def measured_traffic_narrow(kernel_src, summary):
     return int(kv["traffic_bytes_per_launch"]), kv.get("traffic_note")
 
 
-def cpu_baseline(case, lu_steps):
-    """Oracle on the host: dense assembly of A(w) for one frequency of the
-    workload plus the first lu_steps elimination steps of its LU; the full
-    factorization time is extrapolated from the measured elimination rate."""
+def host_info():
+    """Host CPU model and core counts (the box the oracle baseline ran on)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(cpu_model=model, nproc=os.cpu_count(), usable_cores=usable)
+
+
+# Oracle timing tasks, each run in a child process pinned to one core (the
+# oracle is single-threaded C): 'c1' the small spectrum in full, 'lu' one
+# frequency of an N-atom sphere of the headline's lattice (dense assembly of
+# A(w), its complete LU, three polarizations' solves), 'asm' the dense
+# assembly alone at the headline's size.
+_ORACLE_TASK = r"""
+import json, os, sys, time
+os.sched_setaffinity(0, {int(sys.argv[2])})
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle as O
+from workloads import configs as C
+from workloads import geometry as G
+from workloads import materials as M
+task = sys.argv[3]
+t0 = time.perf_counter()
+if task == "c1":
+    c = C.small_sphere()
+    O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
+    out = dict(seconds=time.perf_counter() - t0, columns=len(c["omega_ev"]))
+else:
+    n = int(sys.argv[4])
+    c = C.sphere_20k(n, 3)
+    pv = M.param_vector(c["params"])
+    a = O.assemble(0, c["xyz"], pv, 3.5)
+    t1 = time.perf_counter()
+    if task == "asm":
+        out = dict(seconds=t1 - t0, n=n)
+    else:
+        b = np.stack([O.rhs(0, c["xyz"], pv, l, 1e-4) for l in range(3)], axis=1)
+        O.lu_solve(a, b)
+        out = dict(seconds=time.perf_counter() - t0, assembly_s=t1 - t0, lu_solve_s=time.perf_counter() - t1, n=n)
+print(json.dumps(out), flush=True)
+"""
+
+
+def _oracle_children(tasks):
+    """Run the oracle tasks concurrently, one child process per (core, task)."""
+    import subprocess
+    procs = [subprocess.Popen([sys.executable, "-c", _ORACLE_TASK, ROOT, str(core), *map(str, t)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True) for core, t in tasks]
+    out = []
+    for p in procs:
+        so, se = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle child failed: {se[-400:]}")
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    return out
+
+
+def cpu_baseline(n_head, npol, n_lu=3000, all_core_cap=16):
+    """The oracle (dense FP64 direct solve, its own LU) on the host's cores.
+
+    One pinned core: the small spectrum in full; one frequency at N = n_lu
+    (assembly + complete LU + 3 solves); the dense assembly at the headline's
+    N.  The headline's rate is extrapolated: assembly measured at N, LU and
+    solves scaled from n_lu by (N / n_lu)^3.  All cores: one n_lu frequency on
+    each usable core at once (independent frequency shards), measured, scaled
+    the same way."""
+    info = host_info()
+    cores = sorted(os.sched_getaffinity(0))
+    c0 = cores[0]
+    t0 = time.perf_counter()
+    c1 = _oracle_children([(c0, ("c1",))])[0]
+    lu = _oracle_children([(c0, ("lu", n_lu))])[0]
+    asm = _oracle_children([(c0, ("asm", n_head))])[0]
+    k = min(len(cores), all_core_cap)
+    allc = _oracle_children([(cores[i], ("lu", n_lu)) for i in range(k)])
+    scale = (n_head / n_lu) ** 3
+    per_freq = asm["seconds"] + lu["lu_solve_s"] * scale
+    rate = npol / per_freq
+    t_all = max(r["seconds"] for r in allc)
+    lu_all = float(np.mean([r["lu_solve_s"] for r in allc]))
+    asm_all = float(np.mean([r["assembly_s"] for r in allc]))
+    # k shards at once: each core's frequency costs its assembly (scaled by N^2) and LU (by N^3)
+    per_freq_all = asm_all * (n_head / n_lu) ** 2 + lu_all * scale
+    rate_all = k * npol / per_freq_all
+    return dict(value=round(rate, 8), unit="freq-solves/s", cores=1, kind="oracle",
+                sample=(f"one core (pinned): dense assembly of A(w) at N={n_head} measured "
+                        f"({asm['seconds']:.1f} s); one frequency at N={n_lu} (assembly {lu['assembly_s']:.1f} s, "
+                        f"complete LU + {npol} solves {lu['lu_solve_s']:.1f} s) with the LU scaled by "
+                        f"(N/{n_lu})^3 = {scale:.0f} to {lu['lu_solve_s'] * scale / 3600:.1f} h; {npol} "
+                        f"polarizations per factorization; extrapolated, not run at N={n_head}"),
+                host=info,
+                config1_full=dict(columns=c1["columns"], seconds=round(c1["seconds"], 3),
+                                  freq_solves_per_s=round(c1["columns"] / c1["seconds"], 2),
+                                  note="249-atom sphere, 50 frequencies, x: the complete oracle spectrum, measured"),
+                all_cores=dict(cores=k, value=round(rate_all, 8), unit="freq-solves/s",
+                               measured_wall_s=round(t_all, 1),
+                               note=(f"{k} independent frequency shards at N={n_lu} on {k} pinned cores at once "
+                                     "(measured), each scaled to the headline's N as above")),
+                measured_s=round(time.perf_counter() - t0, 1))
+
+
+def config1_parity(pxm):
+    """The small spectrum (249-atom Ag sphere, 50 w, x) on the GPU against the
+    oracle's direct solve: sigma_abs relative error of the default (mixed
+    options) and of the FP64 path at rel_tol 1e-12."""
+    import oracle as O
+    from workloads import configs as C
+    from workloads import materials as M
+    c = C.small_sphere()
+    ref = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
+    out = {}
+    for label, prec, tol in (("default_rel_tol_1e-8", pxm.PX_MIXED, 1e-8), ("fp64_rel_tol_1e-12", pxm.PX_FP64, 1e-12)):
+        s = make_structure(pxm, c)
+        st = s.solve(precision=prec, rel_tol=tol)
+        sig = s.spectrum()[1]
+        s.close()
+        out[label] = dict(status=int(st), sigma_rel_err=float(np.max(np.abs(sig - ref["sigma"])) /
+                                                              np.max(np.abs(ref["sigma"]))))
+    return out
+
+
+# sampled (frequency index, polarization) columns of the headline spectrum for
+# the oracle residual: three in the 3.30-3.44 eV band at the dipolar plasmon,
+# where restarted GMRES stagnates, the others spread over the grid
+SAMPLED_COLUMNS = ((0, 0), (30, 1), (55, 0), (57, 1), (60, 2), (80, 2), (110, 0), (127, 1))
+
+
+def oracle_residuals(pxm, case):
+    """Solve the headline spectrum once more (untimed, same options), then
+    the residual of sampled columns under the oracle's own operator and
+    right-hand side (matrix-free, FP64 on the host)."""
     import oracle as O
     from workloads import materials as M
-    n = len(case["xyz"])
+    s = make_structure(pxm, case)
+    st = s.solve(precision=pxm.PX_MIXED, rel_tol=1e-8)
+    om = case["omega_ev"]
+    cols = [(w, l) for w, l in SAMPLED_COLUMNS if w < len(om)]
+    q = np.stack([s.charges(w, l) for w, l in cols])
+    s.close()
     pv = M.param_vector(case["params"])
-    w = float(case["omega_ev"][len(case["omega_ev"]) // 2])
     t0 = time.perf_counter()
-    a = O.assemble(case["model"], case["xyz"], pv, w)
-    t1 = time.perf_counter()
-    O.lu_factor_partial(a, lu_steps)
-    t2 = time.perf_counter()
-    del a
-    # elimination step k costs 8 (n-k-1)^2 flops (complex multiply-add on the trailing block)
-    sample_flops = sum(8.0 * (n - k - 1) ** 2 for k in range(lu_steps))
-    full_flops = 8.0 * (n - 1) * n * (2 * n - 1) / 6.0
-    t_lu = (t2 - t1) * full_flops / sample_flops
-    t_solve = 3 * 8.0 * n * n / (sample_flops / (t2 - t1))     # forward/back substitution, 3 polarizations
-    t_per_freq = (t1 - t0) + t_lu + t_solve
-    npol = bin(case["pol_mask"]).count("1")
-    return dict(value=npol / t_per_freq, unit="freq-solves/s", cores=1, kind="oracle",
-                sample=(f"one frequency of the workload: dense assembly of A(w) at N={n} "
-                        f"({t1 - t0:.1f} s measured) + first {lu_steps} LU elimination steps "
-                        f"({t2 - t1:.1f} s measured); full LU extrapolated by its flop count "
-                        f"to {t_lu / 3600:.2f} h; {npol} polarizations per factorization"),
-                measured_s=round(t2 - t0, 2))
+    y = O.apply(0, case["xyz"], pv, om[[w for w, _ in cols]], q)
+    b = {l: O.rhs(0, case["xyz"], pv, l, case["e0"]) for l in {l for _, l in cols}}
+    res = [float(np.linalg.norm(b[l] - y[k]) / np.linalg.norm(b[l])) for k, (w, l) in enumerate(cols)]
+    return dict(status=int(st), columns=[dict(omega_ev=round(float(om[w]), 4), pol="xyz"[l], oracle_rel_residual=r)
+                                         for (w, l), r in zip(cols, res)],
+                max_oracle_rel_residual=max(res), oracle_seconds=round(time.perf_counter() - t0, 1),
+                note="||b - A q|| / ||b|| with A and b from the oracle (or_apply, or_rhs) for the GPU's charges")
+
+
+def rod_extra(pxm):
+    """The 10,000-atom Au rod (omegaFQFmu, 40,000 unknowns), 96 w, z: mixed
+    against the plain FP64 blocked solver."""
+    from workloads import configs as C
+    c = C.rod_10k()
+    ncol = len(c["omega_ev"])
+    runs = {}
+    for label, prec in (("mixed", pxm.PX_MIXED), ("fp64", pxm.PX_FP64)):
+        one_step(pxm, c, prec, False)   # the T-apply tuner times its shapes once per process
+        t0 = time.perf_counter()
+        r = one_step(pxm, c, prec, True)
+        runs[label] = (time.perf_counter() - t0, r)
+    (tm, rm), (t64, r64) = runs["mixed"], runs["fp64"]
+    return dict(workload="au_rod_10000_wfqfmu_96w_z", columns=ncol, mixed_s=round(tm, 2),
+                mixed_solves_per_s=round(ncol / tm, 2), fp64_s=round(t64, 2), fp64_solves_per_s=round(ncol / t64, 2),
+                speedup=round(t64 / tm, 2), mixed_iterations_max=int(rm["iters"].max()),
+                fp64_iterations_max=int(r64["iters"].max()), status=[rm["status"], r64["status"]],
+                relres_max=[float(rm["relres"].max()), float(r64["relres"].max())],
+                sigma_rel_err_mixed_vs_fp64=float(np.max(np.abs(rm["sigma"] - r64["sigma"])) /
+                                                  np.max(np.abs(r64["sigma"]))),
+                tapply_launches={k: v for k, v in rm["tapply"].items() if not k.startswith(("ms_", "flop_"))})
+
+
+def batch_full_extra(pxm, fp64_every=8):
+    """The 64 graphene disks and ribbons (2k-60k atoms, 64 w each) in one
+    pxSolveBatch call, against the plain FP64 solver per structure on every
+    fp64_every-th structure."""
+    from workloads import configs as C
+    cases = C.graphene_batch()
+    rb = batch_run(pxm, cases, pxm.PX_MIXED)
+    cols = sum(ncols(c) for c in cases)
+    pick = list(range(0, len(cases), fp64_every))
+    sub = [cases[k] for k in pick]
+    seq = sequential_run(pxm, sub, pxm.PX_FP64, shifted=0)
+    t64 = sum(r["seconds"] for r in seq)
+    cols64 = sum(ncols(c) for c in sub)
+    err = max(float(np.max(np.abs(rb["sigma"][k] - r["sigma"])) / np.max(np.abs(r["sigma"])))
+              for k, r in zip(pick, seq))
+    return dict(workload="graphene_batch_64", structures=len(cases),
+                n_range=[min(len(c["xyz"]) for c in cases), max(len(c["xyz"]) for c in cases)], columns=cols,
+                batched_s=round(rb["seconds"], 2), batched_solves_per_s=round(cols / rb["seconds"], 2),
+                status=rb["status"], relres_max=rb["relres_max"],
+                fp64_sample=f"every {fp64_every}th structure ({len(sub)} of {len(cases)}, {cols64} columns)",
+                fp64_per_structure_solves_per_s=round(cols64 / t64, 2),
+                speedup_vs_fp64=round((cols / rb["seconds"]) / (cols64 / t64), 2), sigma_rel_err_vs_fp64=err)
+
+
+def bem_extra(pxm):
+    """BEM (DPCM): a 20,480-tesserae Ag sphere (R = 80 A), 64 w x 3 pol, the
+    default solve against the FP64 blocked solver, and the oracle residual of
+    two sampled columns."""
+    import oracle as O
+    from workloads import materials as M
+    from workloads import mesh as ME
+    m = ME.sphere(80.0, 5)
+    om = np.linspace(3.2, 4.4, 64)
+    eps = M.drude_permittivity(M.load("ag_bem"), om)
+
+    def run(**kw):
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = pxm.Structure.bem(m, 1.0, pxm.default_stream())
+        s.set_frequencies(om, 0b111, 1e-4, eps)
+        st = s.solve(rel_tol=1e-8, **kw)
+        sig = s.spectrum()[1]
+        it = s.stats()[0]
+        torch.cuda.synchronize()
+        return s, dict(seconds=time.perf_counter() - t0, status=int(st), sigma=sig, steps=int(it.max()))
+
+    s, r = run()
+    s.close()
+    s, r = run()
+    w = int(np.argmax(r["sigma"]))
+    q = s.charges(w, 0)
+    s.close()
+    b = O.bem_rhs(m, 0, 1e-4)
+    res = float(np.linalg.norm(b - O.bem_apply(m, eps[w:w + 1], 1.0, q[None, :])[0]) / np.linalg.norm(b))
+    s64, r64 = run(precision=pxm.PX_FP64, shifted=0)
+    s64.close()
+    ncol = len(om) * 3
+    return dict(workload="ag_bem_sphere_20480_64w_xyz", tesserae=len(m["area"]), columns=ncol,
+                seconds=round(r["seconds"], 3), solves_per_s=round(ncol / r["seconds"], 2), status=r["status"],
+                phase_steps_max=r["steps"], fp64_blocked_s=round(r64["seconds"], 2),
+                fp64_blocked_solves_per_s=round(ncol / r64["seconds"], 2),
+                speedup_vs_fp64_blocked=round(r64["seconds"] / r["seconds"], 2),
+                sigma_rel_err_vs_fp64_blocked=float(np.max(np.abs(r["sigma"] - r64["sigma"])) /
+                                                    np.max(np.abs(r64["sigma"]))),
+                oracle_rel_residual_at_peak=res, peak_ev=round(float(om[w]), 3))
 
 
 def make_structure(pxm, case):
@@ -218,8 +444,8 @@ def ncols(case):
 
 
 def batch_run(pxm, cases, precision, block_cols=64):
-    """All structures in one pxSolveBatch call (solved whole on the worker pool
-    or stacked in the block); returns timing and statuses."""
+    """All structures in one pxSolveBatch call (solved whole, several at once on
+    their own streams, or stacked in the block); returns timing and statuses."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -329,75 +555,6 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
                 sigma_rel_err_mix_vs_alone=err)
 
 
-HC_EV_NM = 1239.84198   # h c in eV nm
-
-
-def alloy_solve(pxm, c, precision):
-    import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s = pxm.Structure(c["model"], c["xyz"], c["params_a"], pxm.default_stream(), types=c["types"],
-                      params_b=c["params_b"])
-    s.set_frequencies(c["omega_ev"], c["pol_mask"], c["e0"], np.stack([c["alpha_ib_a"], c["alpha_ib_b"]], axis=1))
-    st = s.solve(precision=precision, rel_tol=1e-8)
-    sigma = s.spectrum()[1]
-    it, cyc, rr = s.stats()
-    s.close()
-    torch.cuda.synchronize()
-    return dict(seconds=time.perf_counter() - t0, status=int(st), sigma=sigma, iters=it, relres=rr)
-
-
-def alloy_extra(pxm, step_ev=0.01, fp64_fracs=(0.5,)):
-    """The Ag-Au nanoalloy series: 1289-atom spheres with 0-100 % Au in steps
-    of 10 %, two-type omegaFQFmu, 2.0-4.5 eV, x/y/z.  Reports the solve rate,
-    the plasmon resonance (peak of sigma_abs) per composition with the linear
-    fit of its wavelength against the Au fraction and the exponential fit of
-    its height, and the mixed path against the FP64 path on some fractions."""
-    from workloads import configs as C
-    fracs = [k / 10 for k in range(11)]
-    cols = 0
-    secs = 0.0
-    prf_ev, peak, status, it_max = [], [], [], []
-    sig = {}
-    for f in fracs:
-        c = C.alloy_sphere(f, step_ev=step_ev)
-        r = alloy_solve(pxm, c, pxm.PX_MIXED)
-        ncol = len(c["omega_ev"]) * 3
-        cols += ncol
-        secs += r["seconds"]
-        k = int(np.argmax(r["sigma"]))
-        prf_ev.append(float(c["omega_ev"][k]))
-        peak.append(float(r["sigma"][k]))
-        status.append(r["status"])
-        it_max.append(int(r["iters"].max()))
-        sig[f] = r["sigma"]
-        log(f"[bench] alloy {int(round(100 * f))}% Au: {r['seconds']:.2f} s, PRF {prf_ev[-1]:.2f} eV, "
-            f"iters max {it_max[-1]}")
-    x = 100.0 * np.array(fracs)
-    lam = HC_EV_NM / np.array(prf_ev)
-    slope, icpt = np.polyfit(x, lam, 1)
-    r2 = 1.0 - np.sum((lam - (slope * x + icpt)) ** 2) / np.sum((lam - lam.mean()) ** 2)
-    lslope, licpt = np.polyfit(x, np.log(peak), 1)
-    lp = np.log(peak)
-    r2_int = 1.0 - np.sum((lp - (lslope * x + licpt)) ** 2) / np.sum((lp - lp.mean()) ** 2)
-    out = dict(structures=len(fracs), n_atoms=1289, n_omega=len(c["omega_ev"]), columns=cols,
-               mixed_seconds=round(secs, 2), mixed_solves_per_s=round(cols / secs, 2), status=status,
-               iterations_max=it_max, prf_ev=prf_ev, prf_nm=[round(v, 1) for v in lam.tolist()],
-               prf_slope_nm_per_pct_au=round(float(slope), 3), prf_linear_r2=round(float(r2), 4),
-               peak_sigma_bohr2=[round(v, 2) for v in peak],
-               peak_log_slope_per_pct_au=round(float(lslope), 5), peak_exponential_r2=round(float(r2_int), 4))
-    fp = []
-    for f in fp64_fracs:
-        c = C.alloy_sphere(f, step_ev=step_ev)
-        r64 = alloy_solve(pxm, c, pxm.PX_FP64)
-        ncol = len(c["omega_ev"]) * 3
-        fp.append(dict(frac_au=f, fp64_solves_per_s=round(ncol / r64["seconds"], 2), status=r64["status"],
-                       sigma_rel_err_mixed_vs_fp64=float(np.max(np.abs(sig[f] - r64["sigma"])) /
-                                                         np.max(np.abs(r64["sigma"])))))
-    out["fp64"] = fp
-    return out
-
-
 # FP64 arithmetic per (point, atom) pair of the probe kernel's point-source
 # path: the differences (3), r^2 (5), the reciprocal square root estimate, its
 # Newton step and the halving (6), r^-2 and r^-3 (2), the charge's two parts
@@ -417,12 +574,11 @@ def probe_roofline(st, model):
 
 
 def probe_extra(pxm):
-    """Post-processing: the induced density and field of the plasmon resonance.
-    The paper's example (an Au dimer of 1122 atoms with a 5 A gap along x,
-    omegaFQFmu, 2.28 eV, x polarization: density on a CUBE grid and the field in
-    the xy plane) with a synthetic fcc dimer, and the 20,000-atom Ag sphere
-    (omegaFQ, 3.6 eV) on a 128^3 grid; the probe kernel times come from HIP
-    events around its launches."""
+    """Post-processing rates: the induced density and field of a solved column
+    at probe points, for a synthetic 1122-atom Au fcc gap dimer (5 A gap,
+    omegaFQFmu, 2.28 eV, x: an 80^3 CUBE grid and a 400 x 400 plane) and the
+    20,000-atom Ag sphere (omegaFQ, 3.6 eV) on a 128^3 grid; the probe kernel
+    times come from HIP events around its launches."""
     from workloads import configs as C
     from workloads import geometry as G
     from workloads import materials as M
@@ -449,14 +605,10 @@ def probe_extra(pxm):
     f, _ = s.induced_field(0, 0, plane)
     t_plane = time.perf_counter() - t0
     st_plane = s.probe_stats()
-    e0 = 1e-4
-    enh = np.sqrt((np.abs(f[:, 0] + e0) ** 2 + np.abs(f[:, 1]) ** 2 + np.abs(f[:, 2]) ** 2)) / e0
-    gap_pt = np.argmin(np.linalg.norm(plane[:, :2] - xyz[:, :2].mean(0), axis=1))
     s.close()
     out["au_dimer_1122_wfqfmu"] = dict(
         cube_points=len(cube), cube_seconds=round(t_cube, 4), cube_kernel_ms=round(st_cube["ms_kernel"], 3),
         plane_points=len(plane), plane_seconds=round(t_plane, 4), plane_kernel_ms=round(st_plane["ms_kernel"], 3),
-        max_field_enhancement=round(float(enh.max()), 1), gap_centre_enhancement=round(float(enh[gap_pt]), 1),
         roofline=probe_roofline(st_plane, 1))
     case = C.sphere_20k()
     s = pxm.Structure(0, case["xyz"], case["params"], pxm.default_stream())
@@ -497,20 +649,16 @@ def main():
     ap.add_argument("--fp64-sample", type=int, default=6, help="columns of the one-column FP64 baseline")
     ap.add_argument("--no-fp64-blocked", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--lu-steps", type=int, default=4)
+    ap.add_argument("--cpu-lu-n", type=int, default=3000, help="atoms of the oracle's complete LU (CPU baseline)")
     ap.add_argument("--kernel-sample", action="store_true",
                     help="a short solve of the full workload for hardware-counter runs: 8 shared-Krylov steps, or "
                          "with --no-shifted one blocked restart cycle of 4 steps (with --t-apply)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
-    ap.add_argument("--fp64-every", type=int, default=4,
-                    help="batch-full: the plain FP64 baseline on every k-th structure")
-    ap.add_argument("--workload", default="sphere",
-                    choices=["sphere", "batch-full", "serving-full", "alloys", "probe", "rod"],
-                    help="sphere: the headline line; batch-full / serving-full: the full graphene batch and "
-                         "serving mix, alloys: the Ag-Au series, probe: the induced-field evaluation, "
-                         "printed as their own JSON lines")
-    ap.add_argument("--no-extras", action="store_true", help="skip the small batch and serving extras")
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving-full", "probe"],
+                    help="sphere: the headline line with every config's extra; serving-full: the serving mix at "
+                         "1k-100k atoms; probe: the induced-field evaluation, printed as their own JSON lines")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads (rod, batch, serving, BEM)")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked mixed-precision comparison step")
     ap.add_argument("--no-shifted", action="store_true",
                     help="time the blocked mixed-precision solver alone (no shared-Krylov phase)")
@@ -521,6 +669,14 @@ def main():
         print("bench.py measures one GPU: every box here has a single MI355X and the solver does not shard; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's host baseline first, in pinned child processes, before this
+    # process touches the GPU
+    cpu = None
+    if not (args.no_cpu_baseline or args.kernel_sample or args.copy_calibration > 0 or args.workload != "sphere"):
+        log("[bench] oracle CPU baseline (pinned cores) ...")
+        cpu = cpu_baseline(args.n, 3, n_lu=args.cpu_lu_n)
+        log(f"[bench] oracle CPU baseline done in {cpu['measured_s']} s")
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -533,62 +689,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
         return
-    px = ensure_built()
+    ensure_built()
     import paper_2510_12731_amd as pxm
     from workloads import configs as C
 
-    if args.workload == "batch-full":
-        cases = C.graphene_batch()
-        log(f"[bench] graphene batch: {len(cases)} structures, N {min(len(c['xyz']) for c in cases)}-"
-            f"{max(len(c['xyz']) for c in cases)}")
-        rb = batch_run(pxm, cases, pxm.PX_MIXED)
-        cols = sum(ncols(c) for c in cases)
-        print(json.dumps({"workload": "graphene_batch_64", "columns": cols, "batched_s": round(rb["seconds"], 2),
-                          "batched_solves_per_s": round(cols / rb["seconds"], 2), "status": rb["status"],
-                          "relres_max": rb["relres_max"]}), flush=True)
-        # the plain FP64 solver on every fp64_every-th structure (a seeded sample
-        # of the same size distribution; all 64 would take about a quarter hour)
-        pick = list(range(0, len(cases), args.fp64_every))
-        sub = [cases[k] for k in pick]
-        seq = sequential_run(pxm, sub, pxm.PX_FP64, shifted=0, progress=True)
-        t64 = sum(r["seconds"] for r in seq)
-        cols64 = sum(ncols(c) for c in sub)
-        err = max(float(np.max(np.abs(rb["sigma"][k] - r["sigma"])) / np.max(np.abs(r["sigma"])))
-                  for k, r in zip(pick, seq))
-        print(json.dumps({"workload": "graphene_batch_64", "fp64_sample": f"every {args.fp64_every}th structure "
-                          f"({len(sub)} of {len(cases)}, {cols64} columns)", "fp64_per_structure_s": round(t64, 2),
-                          "fp64_per_structure_solves_per_s": round(cols64 / t64, 2),
-                          "speedup": round((cols / rb["seconds"]) / (cols64 / t64), 2),
-                          "sigma_rel_err_vs_fp64": err}), flush=True)
-        return
-    if args.workload == "rod":
-        # the omegaFQFmu Au nanorod: 10,000 atoms (40,000 unknowns), 96 frequencies, z
-        c = C.rod_10k()
-        ncol = len(c["omega_ev"])
-        runs = {}
-        for label, prec in (("mixed", pxm.PX_MIXED), ("fp64", pxm.PX_FP64)):
-            log(f"[bench] rod 10k {label} ...")
-            one_step(pxm, c, prec, False)   # warm-up: the T-apply tuner times its shapes once per process
-            t0 = time.perf_counter()
-            r = one_step(pxm, c, prec, True)
-            runs[label] = (time.perf_counter() - t0, r)
-        (tm, rm), (t64, r64) = runs["mixed"], runs["fp64"]
-        print(json.dumps({"workload": "au_rod_10000_wfqfmu_96w_z", "columns": ncol,
-                          "mixed_s": round(tm, 2), "mixed_solves_per_s": round(ncol / tm, 2),
-                          "fp64_s": round(t64, 2), "fp64_solves_per_s": round(ncol / t64, 2),
-                          "speedup": round(t64 / tm, 2), "mixed_iterations_max": int(rm["iters"].max()),
-                          "fp64_iterations_max": int(r64["iters"].max()), "status": [rm["status"], r64["status"]],
-                          "relres_max": [float(rm["relres"].max()), float(r64["relres"].max())],
-                          "sigma_rel_err_mixed_vs_fp64": float(np.max(np.abs(rm["sigma"] - r64["sigma"])) /
-                                                               np.max(np.abs(r64["sigma"]))),
-                          "tapply": {k: v for k, v in rm["tapply"].items()}}), flush=True)
-        return
     if args.workload == "probe":
         print(json.dumps({"workload": "induced_field", **probe_extra(pxm)}), flush=True)
-        return
-    if args.workload == "alloys":
-        print(json.dumps({"workload": "agau_alloys_1289", **alloy_extra(pxm, fp64_fracs=(0.0, 0.5, 1.0))}),
-              flush=True)
         return
     if args.workload == "serving-full":
         out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75)
@@ -598,18 +704,18 @@ def main():
     case = C.sphere_20k(args.n, args.n_omega)
     ncol = len(case["omega_ev"]) * bin(case["pol_mask"]).count("1")
     log(f"[bench] workload {case['name']}: N={len(case['xyz'])}, {ncol} columns")
+    ta_mode = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
+               "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
     if args.kernel_sample:
         s = pxm.Structure(case["model"], case["xyz"], case["params"], pxm.default_stream())
         s.set_frequencies(case["omega_ev"], case["pol_mask"], case["e0"])
-        ta = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
-              "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
         if args.no_shifted:
             # one restart cycle of 4 steps of the blocked solver (FP32 T-apply)
             st = s.solve(precision=pxm.PX_MIXED, restart_m=4, max_restart_m=4, max_cycles=1, timings=True,
-                         t_apply=ta, shifted=0)
+                         t_apply=ta_mode, shifted=0)
         else:
             # 8 steps of the shared-Krylov phase (narrow FP64 T-apply)
-            st = s.solve(precision=pxm.PX_MIXED, max_cycles=1, timings=True, t_apply=ta, shifted=1,
+            st = s.solve(precision=pxm.PX_MIXED, max_cycles=1, timings=True, t_apply=ta_mode, shifted=1,
                          shifted_max_steps=8)
         tm = s.timings()
         s.close()
@@ -618,8 +724,6 @@ def main():
                           "tapply_f64_launches": int(tm["n_tapply_f64"])}), flush=True)
         return
 
-    ta_mode = {"auto": pxm.PX_TAPPLY_AUTO, "on-the-fly": pxm.PX_TAPPLY_ON_THE_FLY,
-               "stored": pxm.PX_TAPPLY_STORED}[args.t_apply]
     shifted = 0 if args.no_shifted else 2
     for w in range(args.warmup):
         r = one_step(pxm, case, pxm.PX_MIXED, True, t_apply=ta_mode, shifted=shifted)
@@ -675,6 +779,10 @@ def main():
                       sparse=round(tm["ms_spmm"], 1), arnoldi_givens=round(tm["ms_arnoldi"], 1),
                       rest=round(tm["ms_other"], 1)))
     extra["tapply_launches"] = {k: int(v) for k, v in last["tapply"].items() if not k.startswith(("ms_", "flop_"))}
+
+    # error against the oracle: the small spectrum in full, sampled columns of this one
+    log("[bench] oracle parity: 249-atom spectrum, sampled columns of the headline ...")
+    extra["oracle_parity"] = dict(config1=config1_parity(pxm), headline_sampled_columns=oracle_residuals(pxm, case))
 
     # the shared-Krylov phase with one Arnoldi process per polarization instead
     if shifted and not args.no_blocked:
@@ -746,40 +854,14 @@ def main():
                                                                       2)
 
     if not args.no_extras:
-        from workloads import configs as C2
-        log("[bench] batch extra ...")
-        gb = C2.graphene_batch(n_struct=8, n_min=2000, n_max=12000)
-        # untimed pass first: the T-apply tuner times its shapes once per process,
-        # which the one-at-a-time runs below would otherwise be spared
-        batch_run(pxm, gb, pxm.PX_MIXED)
-        rb = batch_run(pxm, gb, pxm.PX_MIXED)
-        cols = sum(ncols(c) for c in gb)
-        seq = sequential_run(pxm, gb, pxm.PX_FP64, shifted=0)
-        t64 = sum(r["seconds"] for r in seq)
-        one = sequential_run(pxm, gb, pxm.PX_MIXED)
-        t1 = sum(r["seconds"] for r in one)
-        extra["batch"] = dict(structures=len(gb), n_range=[2000, 12000], columns=cols,
-                              batched_solves_per_s=round(cols / rb["seconds"], 2),
-                              one_at_a_time_solves_per_s=round(cols / t1, 2),
-                              fp64_per_structure_solves_per_s=round(cols / t64, 2),
-                              speedup_vs_fp64=round(t64 / rb["seconds"], 2),
-                              speedup_vs_one_at_a_time=round(t1 / rb["seconds"], 2), status=rb["status"],
-                              note="batched: pxSolveBatch (omegaFQ structures solved whole on 4 worker streams); "
-                                   "one at a time: pxSolveSpectrum in turn; FP64: the blocked FP64 solver per "
-                                   "structure",
-                              sigma_rel_err_vs_fp64=max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"])))
-                                                        for a, b in zip(rb["sigma"], seq)))
-        log("[bench] serving extra ...")
-        extra["serving"] = serving_extra(pxm, 16, 1000, 4000, 5, 0.75)
-        log("[bench] alloy series extra ...")
-        extra["alloys"] = alloy_extra(pxm)
-        log("[bench] induced field extra ...")
-        extra["induced_field"] = probe_extra(pxm)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] oracle CPU baseline ...")
-        cpu = cpu_baseline(case, args.lu_steps)
+        log("[bench] config 3: 10k-atom Au rod ...")
+        extra["rod_10k"] = rod_extra(pxm)
+        log("[bench] config 4: 64-structure graphene batch ...")
+        extra["batch_full"] = batch_full_extra(pxm)
+        log("[bench] config 5: serving mix (1k-8k atoms) ...")
+        extra["serving"] = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
+        log("[bench] BEM sphere ...")
+        extra["bem"] = bem_extra(pxm)
 
     out = {
         "metric": "omegaFQ freq-solves/s at N=20k (rel res 1e-8)",
