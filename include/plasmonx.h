@@ -21,17 +21,31 @@
  *     everything else in Hartree atomic units unless the field name says so.
  *   - Complex numbers are interleaved (re, im) doubles.
  *   - All caller buffers are host memory, read (inputs) or written (outputs)
- *     before the call returns; the library copies what it keeps.  Device memory
- *     belongs to the library (hipMalloc) and is released by pxDestroyStructure.
+ *     before the call returns; the library copies what it keeps (the device
+ *     arrays of pxApplyOperatorNoAlloc aside).  Device memory comes from
+ *     hipMalloc, or from the caller's allocator once pxSetAllocator installed
+ *     one (the Python binding offers the framework's caching allocator); a
+ *     structure's memory is released by pxDestroyStructure.
  *   - Outputs are in the caller's atom order.
  *   - A handle is not thread-safe; distinct handles may be used concurrently
- *     from different threads.  Work runs on the HIP stream given at creation
- *     (NULL = the default stream); pxGet* synchronise that stream.
+ *     from different threads.
+ *   - Streams: each structure's device work is ordered on the HIP stream given
+ *     at creation (NULL = the default stream): it starts after the work the
+ *     caller queued on that stream before the call, and work the caller
+ *     queues after a call returns sees its results.  A solve drives restart
+ *     cycles and convergence checks from the host, so pxSolveSpectrum,
+ *     pxSolveBatch and pxServerStep return only once their steps are done (a
+ *     solve is not left running on the stream; the server's pxServerStep is
+ *     the way to interleave solves with other host work).  Inside a solve
+ *     the library may also use streams of its own (default priority), joined
+ *     back to the structure's stream before the call returns.  pxGet*
+ *     synchronise the structure's stream.
  *   - Unknown order of the dipole model: [q_0..q_{N-1} | mu_x | mu_y | mu_z].
  */
 #ifndef PLASMONX_H
 #define PLASMONX_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -51,8 +65,12 @@ typedef enum { PX_WFQ = 0, PX_WFQFMU = 1, PX_BEM = 2 } pxModel;
 
 typedef enum {
     PX_FP64 = 0,   /* every step in FP64 */
-    PX_MIXED = 1   /* T-apply in FP32 on MFMA inside GMRES cycles; FP64 Arnoldi,
-                      Givens, solution update and true residual (iterative refinement) */
+    PX_MIXED = 1   /* the blocked GMRES cycles apply T in FP32 on MFMA; FP64
+                      Arnoldi, Givens, solution update and true residual
+                      (iterative refinement).  The shared-Krylov phase
+                      (pxSolveOptions.shifted) is FP64 either way: PX_MIXED
+                      changes only the cycles of the columns that phase leaves
+                      above rel_tol, and every cycle of shifted = 0 */
 } pxPrecision;
 
 typedef enum {
@@ -95,7 +113,7 @@ typedef struct {
 } pxMaterial;
 
 /* Solver options (pxDefaultSolveOptions fills the defaults shown).
- *   precision        PX_MIXED (default) or PX_FP64
+ *   precision        PX_FP64 (default) or PX_MIXED (see pxPrecision)
  *   restart_m        GMRES restart length m at the start (50)
  *   max_restart_m    the restart length doubles, up to this value, whenever
  *                    some column's true residual fell by less than 30 % over
@@ -159,9 +177,9 @@ typedef struct {
  *                    0 = blocked solver only.  Ignored for PX_WFQFMU and
  *                    two-type structures.  pxSolveBatch and the server solve
  *                    the structures it applies to, and every structure of
- *                    1024 atoms or more, whole (as pxSolveSpectrum does) on a
- *                    pool of host threads with their own streams, beside the
- *                    stacked block that takes the others.
+ *                    1024 atoms or more, whole (as pxSolveSpectrum does), a
+ *                    few steps of each in turn on streams of their own,
+ *                    beside the stacked block that takes the others.
  *   shifted_max_steps  Arnoldi steps of that phase at most, in [1, 4000]
  *                    (2000; lowered to keep its basis and the frequencies'
  *                    triangular factors, k^2/2 x 16 B per column, within a
@@ -368,6 +386,31 @@ pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, do
  * dipole rows are those of Eq. (wfqfmu-system), not negated. */
 pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const double* omega_ev,
                          const double* alpha_ib, const double* x, double* y);
+
+/* Device memory.  alloc(bytes, device, user) returns at least bytes of
+ * device memory on that device (the current one), 256-byte aligned, or NULL
+ * when none is left (the library call then fails with PX_E_OOM);
+ * free(ptr, device, user) gives back a block that alloc returned.  The
+ * library waits for the device after alloc returns and before it calls free,
+ * so the allocator may hand out a block whose previous user's work is still
+ * queued on some stream, and may reuse a freed block at once.  Every device
+ * allocation of the library goes through it (structures, solve workspaces,
+ * stored T), except the fixed array of pxApplyOperatorNoAlloc; each block
+ * goes back to the allocator that made it, also after a later
+ * pxSetAllocator.  alloc = free = NULL restores hipMalloc/hipFree.  With an
+ * allocator installed the library keeps no freed blocks of its own: the
+ * blocks it keeps for reuse between solves are released and later ones are
+ * given back at once.  The callbacks run on the thread that made the
+ * library call.  Errors: PX_E_INVALID if exactly one of alloc and free is
+ * NULL. */
+typedef void* (*pxDeviceAllocFn)(size_t bytes, int32_t device, void* user);
+typedef void (*pxDeviceFreeFn)(void* ptr, int32_t device, void* user);
+pxStatus pxSetAllocator(pxDeviceAllocFn alloc, pxDeviceFreeFn free, void* user);
+
+/* Frees the device blocks the library keeps for reuse between solves (solve
+ * workspaces and stored T of at least 16 MiB, up to 24 GiB in all, with
+ * hipMalloc as the allocator).  Blocks in use are not touched. */
+pxStatus pxReleaseCache(void);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64

@@ -28,7 +28,8 @@ EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHete
             "pxGetCharges", "pxGetSpectrum", "pxGetSolveStats", "pxApplyOperator", "pxGetSize", "pxGetTimings", "pxGetWork", "pxGetTApplyStats",
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
-            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc", "pxCreateBem"]
+            "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc", "pxCreateBem",
+            "pxSetAllocator", "pxReleaseCache"]
 
 
 class PxError(RuntimeError):
@@ -55,6 +56,9 @@ class pxSolveOptions(ctypes.Structure):
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
+# pxDeviceAllocFn / pxDeviceFreeFn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
 
 
 def load(path: str = LIB_PATH):
@@ -103,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.pxServerMemory.argtypes = [_vp, _dp, _dp, ctypes.POINTER(i32)]
     lib.pxSolveFootprint.argtypes = [_vp, ctypes.POINTER(pxSolveOptions), _dp]
     lib.pxGetSolveStatus.argtypes = [_vp, ctypes.POINTER(i32), ctypes.c_char_p, i32]
+    lib.pxSetAllocator.argtypes = [ALLOC_FN, FREE_FN, _vp]
+    lib.pxReleaseCache.argtypes = []
     lib.pxServerDestroy.argtypes = [_vp]
     lib.pxServerDestroy.restype = None
     lib.pxDestroyStructure.argtypes = [_vp]
@@ -114,6 +120,51 @@ def load(path: str = LIB_PATH):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+_allocator = None   # the installed callbacks (kept alive while installed)
+
+
+def pxSetAllocator(alloc, free, user=None):
+    """pxSetAllocator with ctypes callbacks (ALLOC_FN, FREE_FN), or None, None."""
+    global _allocator
+    lib = load()
+    if alloc is None and free is None:
+        _check(lib.pxSetAllocator(ALLOC_FN(), FREE_FN(), user))
+    else:
+        _check(lib.pxSetAllocator(alloc, free, user))
+    # blocks made by earlier callbacks still go back through them
+    _allocator = (alloc, free, _allocator)
+
+
+def pxReleaseCache():
+    _check(load().pxReleaseCache())
+
+
+def use_torch_allocator():
+    """Route the library's device memory through torch's caching allocator:
+    torch.cuda.memory_allocated() then counts it, and torch reuses it after
+    pxDestroyStructure."""
+    import torch
+
+    def alloc(nbytes, device, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), int(device))
+        except Exception:   # out of memory: the library reports PX_E_OOM
+            return None
+
+    def free(ptr, device, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:   # interpreter shutting down: the block is leaked
+            pass
+
+    pxSetAllocator(ALLOC_FN(alloc), FREE_FN(free))
+
+
+def use_hip_allocator():
+    """Back to hipMalloc/hipFree (blocks made by torch still go back to it)."""
+    pxSetAllocator(None, None)
 
 
 def _ptr(a):
@@ -333,7 +384,7 @@ def pxLastError():
     return load().pxLastError().decode()
 
 
-def solve_options(precision=PX_MIXED, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
+def solve_options(precision=PX_FP64, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
                   inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
                   ortho=None, graph_steps=None, t_apply=None, shifted=None, shifted_max_steps=None):
     o = pxDefaultSolveOptions()

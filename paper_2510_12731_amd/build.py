@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libplasmonx_hip.so")
-SOURCES = ["px_api.cpp", "px_engine.cpp", "px_kernels.hip", "px_tapply.hip", "px_shifted.hip", "px_shifted_block.hip",
+SOURCES = ["px_api.cpp", "px_alloc.cpp", "px_engine.cpp", "px_kernels.hip", "px_tapply.hip", "px_shifted.hip", "px_shifted_block.hip",
            "px_probe.hip", "px_bem.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

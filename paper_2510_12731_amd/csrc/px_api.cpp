@@ -1499,10 +1499,30 @@ char* noalloc_scratch()
 
 extern "C" {
 
+pxStatus pxSetAllocator(pxDeviceAllocFn alloc, pxDeviceFreeFn free, void* user)
+{
+    if ((alloc == nullptr) != (free == nullptr))
+        return fail(PX_E_INVALID, "pxSetAllocator: give both alloc and free, or neither");
+    return guarded([&]() -> pxStatus {
+        // blocks kept from earlier solves were made by the previous allocator
+        pxs::BlockCache::get().release();
+        px::set_allocator(alloc, free, user);
+        return PX_OK;
+    });
+}
+
+pxStatus pxReleaseCache(void)
+{
+    return guarded([&]() -> pxStatus {
+        pxs::BlockCache::get().release();
+        return PX_OK;
+    });
+}
+
 void pxDefaultSolveOptions(pxSolveOptions* o)
 {
     if (!o) return;
-    o->precision = PX_MIXED;
+    o->precision = PX_FP64;
     o->restart_m = 50;
     o->rel_tol = 1e-8;
     o->max_cycles = 400;

@@ -209,12 +209,12 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     for (int64_t i = 0; i < n; ++i) ci[(size_t)i] = (int32_t)i;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) return e; } while (0)
-    PXCHK(hipMalloc(&g.xyz64, sizeof(double4) * np));
-    PXCHK(hipMalloc(&g.xyz32, sizeof(float4) * np));
-    PXCHK(hipMalloc(&g.bem_na, sizeof(double4) * np));
-    PXCHK(hipMalloc(&g.row_ptr, sizeof(int32_t) * (n + 1)));
-    PXCHK(hipMalloc(&g.col, sizeof(int32_t) * ci.size()));
-    PXCHK(hipMalloc(&g.val, sizeof(double) * cv.size()));
+    PXCHK(px::dev_malloc((void**)&g.xyz64, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.xyz32, sizeof(float4) * np));
+    PXCHK(px::dev_malloc((void**)&g.bem_na, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.row_ptr, sizeof(int32_t) * (n + 1)));
+    PXCHK(px::dev_malloc((void**)&g.col, sizeof(int32_t) * ci.size()));
+    PXCHK(px::dev_malloc((void**)&g.val, sizeof(double) * cv.size()));
     PXCHK(hipMemcpyAsync(g.xyz64, s.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.xyz32, s32.data(), sizeof(float4) * np, hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.bem_na, na.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));

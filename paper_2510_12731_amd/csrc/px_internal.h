@@ -11,6 +11,16 @@
 
 namespace px {
 
+// Device memory of the library.  With no caller allocator installed
+// (pxSetAllocator) these are hipMalloc and hipFree; with one, blocks come from
+// it, and each block goes back to the allocator that made it after the device
+// has finished with it (as hipFree waits for the device).
+hipError_t dev_malloc(void** p, size_t bytes);
+void dev_free(void* p);
+// true while a caller allocator is installed
+bool caller_allocator();
+void set_allocator(pxDeviceAllocFn alloc, pxDeviceFreeFn free, void* user);
+
 // Atom padding: every device vector holds np >= n rows per component; rows
 // n..np-1 belong to ghost atoms parked far away with zero unknowns.
 constexpr int ATOM_PAD = 256;

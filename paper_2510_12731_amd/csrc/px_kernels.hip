@@ -1412,16 +1412,16 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
     uint8_t* d_types = nullptr;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
-    PXCHK(hipMalloc(&d_xyz, sizeof(double) * 3 * n));
-    PXCHK(hipMalloc(&d_keys, sizeof(uint64_t) * npow));
-    PXCHK(hipMalloc(&d_cnt, sizeof(int32_t) * (n + 1)));
-    PXCHK(hipMalloc(&d_perm, sizeof(int32_t) * np));
-    PXCHK(hipMalloc(&d_bad, sizeof(int)));
-    PXCHK(hipMalloc(&g.xyz64, sizeof(double4) * np));
-    PXCHK(hipMalloc(&g.xyz32, sizeof(float4) * np));
-    PXCHK(hipMalloc(&g.glo, sizeof(float4) * (np / GROUP)));
-    PXCHK(hipMalloc(&g.ghi, sizeof(float4) * (np / GROUP)));
-    PXCHK(hipMalloc(&g.row_ptr, sizeof(int32_t) * (n + 1)));
+    PXCHK(px::dev_malloc((void**)&d_xyz, sizeof(double) * 3 * n));
+    PXCHK(px::dev_malloc((void**)&d_keys, sizeof(uint64_t) * npow));
+    PXCHK(px::dev_malloc((void**)&d_cnt, sizeof(int32_t) * (n + 1)));
+    PXCHK(px::dev_malloc((void**)&d_perm, sizeof(int32_t) * np));
+    PXCHK(px::dev_malloc((void**)&d_bad, sizeof(int)));
+    PXCHK(px::dev_malloc((void**)&g.xyz64, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.xyz32, sizeof(float4) * np));
+    PXCHK(px::dev_malloc((void**)&g.glo, sizeof(float4) * (np / GROUP)));
+    PXCHK(px::dev_malloc((void**)&g.ghi, sizeof(float4) * (np / GROUP)));
+    PXCHK(px::dev_malloc((void**)&g.row_ptr, sizeof(int32_t) * (n + 1)));
     PXCHK(hipMemcpyAsync(d_xyz, xyz_bohr_host, sizeof(double) * 3 * n, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(d_bad), (size_t)1);
     hipLaunchKernelGGL(k_morton, dim3((unsigned)((npow + 255) / 256)), dim3(256), 0, st, d_xyz, n, npow,
@@ -1464,14 +1464,14 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
             kab.rc = 0.5 * (cutoff_bohr + rcb);
             kab.rc2 = kab.rc * kab.rc;
             ks.rc_max = std::max(kc.rc, std::max(kb.rc, kab.rc));
-            PXCHK(hipMalloc(&d_types, n));
-            PXCHK(hipMalloc(&g.type, np));
+            PXCHK(px::dev_malloc((void**)&d_types, n));
+            PXCHK(px::dev_malloc((void**)&g.type, np));
             PXCHK(hipMemcpyAsync(d_types, types_host, n, hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL(k_gather_types, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, d_types, d_perm, n,
                                np, g.type);
         }
         const int nsub = neighbor_subsets(np);
-        PXCHK(hipMalloc(&d_cntw, sizeof(int32_t) * (size_t)nsub * np));
+        PXCHK(px::dev_malloc((void**)&d_cntw, sizeof(int32_t) * (size_t)nsub * np));
         hipLaunchKernelGGL(k_kbar_rows<0>, dim3((unsigned)(np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
                            g.ghi, n, np, ks, g.type, d_cntw, nullptr, nullptr, nullptr, d_bad);
         // row lengths with the diagonal
@@ -1483,14 +1483,14 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
         PXCHK(hipMemcpyAsync(bad_pair, d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
         PXCHK(hipStreamSynchronize(st));
         g.nnz = nnz;
-        PXCHK(hipMalloc(&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-        PXCHK(hipMalloc(&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+        PXCHK(px::dev_malloc((void**)&g.col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+        PXCHK(px::dev_malloc((void**)&g.val, sizeof(double) * std::max<int64_t>(nnz, 1)));
         hipLaunchKernelGGL(k_kbar_rows<1>, dim3((unsigned)(np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
                            g.ghi, n, np, ks, g.type, d_cntw, g.row_ptr, g.col, g.val, d_bad);
         hipLaunchKernelGGL(k_kbar_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                            (const int32_t*)g.row_ptr, n, g.col, g.val);
         if (g.type) {
-            PXCHK(hipMalloc(&g.hrow, sizeof(double4) * n));
+            PXCHK(px::dev_malloc((void**)&g.hrow, sizeof(double4) * n));
             hipLaunchKernelGGL(k_het_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.row_ptr, g.col, g.val,
                                g.type, n, g.hrow);
         }
@@ -1501,13 +1501,13 @@ hipError_t build_geometry(Geometry& g, const double* xyz_bohr_host, double cutof
     PXCHK(hipGetLastError());
 fail:
 #undef PXCHK
-    (void)hipFree(d_xyz);
-    (void)hipFree(d_keys);
-    (void)hipFree(d_cnt);
-    (void)hipFree(d_cntw);
-    (void)hipFree(d_perm);
-    (void)hipFree(d_bad);
-    (void)hipFree(d_types);
+    px::dev_free(d_xyz);
+    px::dev_free(d_keys);
+    px::dev_free(d_cnt);
+    px::dev_free(d_cntw);
+    px::dev_free(d_perm);
+    px::dev_free(d_bad);
+    px::dev_free(d_types);
     return e;
 }
 

@@ -23,6 +23,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 
 namespace px {
@@ -105,13 +106,16 @@ __device__ __forceinline__ void probe_radial(double r, double R, double& g_r3, d
 // narrow T-apply), at most one chunk of atoms per split.
 int probe_splits(int64_t npad, int64_t np)
 {
-    static int ncu = 0;
+    // filled on first use; concurrent first calls store the same value
+    static std::atomic<int> ncu_cache{0};
+    int ncu = ncu_cache.load(std::memory_order_relaxed);
     if (ncu == 0) {
         int dev = 0, cu = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cu <= 0)
             cu = 256;
         ncu = cu;
+        ncu_cache.store(ncu, std::memory_order_relaxed);
     }
     const int64_t blocks = npad / 256;
     const int64_t nchunk = (np + PROBE_CHUNK - 1) / PROBE_CHUNK;

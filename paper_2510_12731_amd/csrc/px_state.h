@@ -42,14 +42,14 @@ T* dalloc(size_t count)
 {
     void* p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
-    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    hipError_t e = px::dev_malloc(&p, count * sizeof(T));
+    if (e != hipSuccess) throw HipError{e, "device allocation"};
     return static_cast<T*>(p);
 }
 
 inline void dfree(void* p)
 {
-    if (p) (void)hipFree(p);
+    if (p) px::dev_free(p);
 }
 
 // Device blocks kept for the next allocation of a similar size (the shared
@@ -57,8 +57,10 @@ inline void dfree(void* p)
 // milliseconds of host time per solve).  A block is given back only once no
 // stream uses it any more (its user has synchronised); a block of at least
 // kMinBytes serves a request of at least half its size on the same device;
-// at most kCacheBytes are kept, and a failed hipMalloc releases them and
-// tries again.  The blocks are never freed at process exit.
+// at most kCacheBytes are kept, and a failed allocation releases them and
+// tries again.  The blocks are never freed at process exit.  With a caller
+// allocator installed nothing is kept: the caller's allocator caches instead.
+// Blocks come from px::dev_malloc and go back through px::dev_free.
 class BlockCache {
   public:
     static constexpr size_t kMinBytes = size_t(1) << 24, kCacheBytes = size_t(24) << 30;
@@ -74,7 +76,7 @@ class BlockCache {
         if (bytes == 0) bytes = 1;
         int dev = 0;
         hcheck(hipGetDevice(&dev), "hipGetDevice");
-        {
+        if (!px::caller_allocator()) {
             std::lock_guard<std::mutex> lk(mu_);
             for (auto it = blocks_.lower_bound(bytes); it != blocks_.end() && it->first <= 2 * bytes; ++it)
                 if (it->second.dev == dev) {
@@ -86,13 +88,13 @@ class BlockCache {
                 }
         }
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
+        hipError_t e = px::dev_malloc(&p, bytes);
         if (e == hipErrorOutOfMemory) {
             (void)hipGetLastError();
             release();
-            e = hipMalloc(&p, bytes);
+            e = px::dev_malloc(&p, bytes);
         }
-        if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+        if (e != hipSuccess) throw HipError{e, "device allocation"};
         std::lock_guard<std::mutex> lk(mu_);
         live_[p] = Live{bytes, dev};
         return p;
@@ -108,17 +110,17 @@ class BlockCache {
             if (it != live_.end()) {
                 const Live l = it->second;
                 live_.erase(it);
-                if (l.bytes >= kMinBytes && held_ + l.bytes <= kCacheBytes) {
+                if (l.bytes >= kMinBytes && held_ + l.bytes <= kCacheBytes && !px::caller_allocator()) {
                     blocks_.emplace(l.bytes, Block{p, l.dev});
                     held_ += l.bytes;
                     return;
                 }
             }
         }
-        (void)hipFree(p);
+        px::dev_free(p);
     }
 
-    // p came from take() but may still be in use: freed (hipFree waits for the device)
+    // p came from take() but may still be in use: freed (dev_free waits for the device)
     void drop(void* p)
     {
         if (!p) return;
@@ -126,7 +128,7 @@ class BlockCache {
             std::lock_guard<std::mutex> lk(mu_);
             live_.erase(p);
         }
-        (void)hipFree(p);
+        px::dev_free(p);
     }
 
     void release()
@@ -137,7 +139,7 @@ class BlockCache {
             b.swap(blocks_);
             held_ = 0;
         }
-        for (auto& e : b) (void)hipFree(e.second.p);
+        for (auto& e : b) px::dev_free(e.second.p);
     }
 
   private:

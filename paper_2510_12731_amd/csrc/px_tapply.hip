@@ -27,6 +27,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -1519,15 +1520,19 @@ __global__ __launch_bounds__(256) void k_tdense_f64(const double4* __restrict__ 
 // two), counted once per device.
 int sk_slots()
 {
-    static int slots[64] = {0};
+    // filled on first use per device; callers on several host threads store
+    // the same value, so relaxed atomics suffice
+    static std::atomic<int> slots[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (slots[dev] == 0) {
+    int v = slots[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
         int cu = 0;
         if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
-        slots[dev] = 2 * cu;
+        v = 2 * cu;
+        slots[dev].store(v, std::memory_order_relaxed);
     }
-    return slots[dev];
+    return v;
 }
 
 // Workgroups of a stream-K launch over `total` iterations: every resident
@@ -1548,11 +1553,11 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
     int64_t nnz = 0;
     hipError_t e;
 #define PXCHK(x) do { e = (x); if (e != hipSuccess) goto fail; } while (0)
-    PXCHK(hipMalloc(&cnt, sizeof(int32_t) * g.np));
-    PXCHK(hipMalloc(&cntw, sizeof(int32_t) * (size_t)nsub * g.np));
-    PXCHK(hipMalloc(&wid, sizeof(int64_t) * nb));
-    PXCHK(hipMalloc(&g.near_off, sizeof(int64_t) * (nb + 1)));
-    PXCHK(hipMalloc(&g.xyzc, sizeof(double4) * g.np));
+    PXCHK(px::dev_malloc((void**)&cnt, sizeof(int32_t) * g.np));
+    PXCHK(px::dev_malloc((void**)&cntw, sizeof(int32_t) * (size_t)nsub * g.np));
+    PXCHK(px::dev_malloc((void**)&wid, sizeof(int64_t) * nb));
+    PXCHK(px::dev_malloc((void**)&g.near_off, sizeof(int64_t) * (nb + 1)));
+    PXCHK(px::dev_malloc((void**)&g.xyzc, sizeof(double4) * g.np));
     hipLaunchKernelGGL(k_centred, dim3((unsigned)((g.np + 255) / 256)), dim3(256), 0, st, g.xyz64, g.np, g.cx, g.cy,
                        g.cz, g.xyzc);
     hipLaunchKernelGGL(k_near_rows<0>, dim3((unsigned)(g.np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64, g.glo,
@@ -1570,8 +1575,8 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
         nnz = o[nb];
         PXCHK(hipMemcpyAsync(g.near_off, o.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, st));
         g.near_nnz = nnz;
-        PXCHK(hipMalloc(&g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-        PXCHK(hipMalloc(&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+        PXCHK(px::dev_malloc((void**)&g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+        PXCHK(px::dev_malloc((void**)&g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1)));
         fill_zero(g.near_col, sizeof(int32_t) * std::max<int64_t>(nnz, 1), st);
         fill_zero(g.near_val, sizeof(double) * std::max<int64_t>(nnz, 1), st);
         hipLaunchKernelGGL(k_near_rows<1>, dim3((unsigned)(g.np / 64), (unsigned)nsub), dim3(64), 0, st, g.xyz64,
@@ -1580,19 +1585,19 @@ hipError_t ensure_near_f64(Geometry& g, hipStream_t st)
         PXCHK(hipStreamSynchronize(st));
         PXCHK(hipGetLastError());
     }
-    (void)hipFree(cnt);
-    (void)hipFree(cntw);
-    (void)hipFree(wid);
+    px::dev_free(cnt);
+    px::dev_free(cntw);
+    px::dev_free(wid);
     return hipSuccess;
 fail:
 #undef PXCHK
-    (void)hipFree(cnt);
-    (void)hipFree(cntw);
-    (void)hipFree(wid);
-    (void)hipFree(g.near_off);
-    (void)hipFree(g.near_col);
-    (void)hipFree(g.near_val);
-    (void)hipFree(g.xyzc);
+    px::dev_free(cnt);
+    px::dev_free(cntw);
+    px::dev_free(wid);
+    px::dev_free(g.near_off);
+    px::dev_free(g.near_col);
+    px::dev_free(g.near_val);
+    px::dev_free(g.xyzc);
     g.near_off = nullptr;
     g.near_col = nullptr;
     g.near_val = nullptr;
@@ -1708,7 +1713,7 @@ struct GroupedTApply::Impl {
     {
         void* ps[] = {d_gc, d_t32q, d_t32d, d_t64q, d_t64d, d_pre32q};
         for (void* p : ps)
-            if (p) (void)hipFree(p);
+            if (p) px::dev_free(p);
         d_gc = nullptr;
         d_t32q = d_t32d = d_t64q = d_t64d = nullptr;
         d_pre32q = nullptr;
@@ -1724,7 +1729,7 @@ GroupedTApply::~GroupedTApply()
 
 static hipError_t upload(void** dst, const void* src, size_t bytes, hipStream_t st)
 {
-    hipError_t e = hipMalloc(dst, bytes > 0 ? bytes : 16);
+    hipError_t e = px::dev_malloc(dst, bytes > 0 ? bytes : 16);
     if (e != hipSuccess) return e;
     if (bytes > 0) e = hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, st);
     return e;

@@ -54,9 +54,21 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_default_options(lib):
     o = px.pxDefaultSolveOptions()
-    assert (o.precision, o.restart_m, o.rel_tol, o.max_cycles, o.max_block_cols) == (px.PX_MIXED, 50, 1e-8, 400, 0)
+    assert (o.precision, o.restart_m, o.rel_tol, o.max_cycles, o.max_block_cols) == (px.PX_FP64, 50, 1e-8, 400, 0)
+    assert o.shifted == 2 and o.shifted_max_steps == 2000
     assert o.inner_reduction == 1e-5 and o.timings == 0 and o.stall_cycles == 8
     assert o.max_restart_m == 200 and o.block_cols == 0 and o.ortho == px.PX_ORTHO_DCGS2 and o.graph_steps == 8 and o.t_apply == px.PX_TAPPLY_AUTO
+
+
+def test_set_allocator_argument_errors(lib):
+    """alloc and free come together; NULL/NULL restores hipMalloc (no device
+    call is made)."""
+    a = px.ALLOC_FN(lambda n, d, u: None)
+    assert lib.pxSetAllocator(a, px.FREE_FN(), None) == px.PX_E_INVALID
+    assert b"both" in lib.pxLastError()
+    assert lib.pxSetAllocator(px.ALLOC_FN(), px.FREE_FN(lambda p, d, u: None), None) == px.PX_E_INVALID
+    assert lib.pxSetAllocator(px.ALLOC_FN(), px.FREE_FN(), None) == px.PX_OK
+    assert lib.pxReleaseCache() == px.PX_OK
 
 
 def _mat():
