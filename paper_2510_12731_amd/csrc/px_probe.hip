@@ -15,8 +15,10 @@
 // probe point, the source atoms (Morton order) read wave-uniform through the
 // scalar cache; a group of 32 atoms whose bounding box lies farther than 7
 // widths from the box of the wave's 64 points takes the branch-free point
-// path, the others the Gaussian formulas.  With few points the atoms are
-// split over blockIdx.y and k_probe_sum adds the splits.
+// path; inside the other groups a wave vote per atom takes the Gaussian
+// formulas only where one of the wave's points lies within 7 widths of it.
+// With few points the atoms are split over blockIdx.y and k_probe_sum adds
+// the splits.
 
 #include "px_internal.h"
 #include "px_neighbors.h"
@@ -146,70 +148,81 @@ __global__ __launch_bounds__(256) void k_probe(const double4* __restrict__ xyz, 
     const float4 bhi = make_float4(hi[0], hi[1], hi[2], 0.f);
     double e[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // E_x, E_y, E_z real then imaginary
     double rho[2] = {0.0, 0.0};
+    // one source atom in the point-charge (and point-dipole) form
+    auto point_pair = [&](const double* s, double dx, double dy, double dz, double r2) {
+        const double ir = 0.5 * rsqrt2(r2);
+        const double ir2 = ir * ir, ir3 = ir2 * ir;
+        const double fr = s[0] * ir3, fi = s[1] * ir3;
+        e[0] = fma(fr, dx, e[0]);
+        e[1] = fma(fr, dy, e[1]);
+        e[2] = fma(fr, dz, e[2]);
+        e[3] = fma(fi, dx, e[3]);
+        e[4] = fma(fi, dy, e[4]);
+        e[5] = fma(fi, dz, e[5]);
+        if (MODEL) {
+            const double ir5 = 3.0 * ir3 * ir2;
+            const double mdr = fma(s[2], dx, fma(s[4], dy, s[6] * dz)) * ir5;
+            const double mdi = fma(s[3], dx, fma(s[5], dy, s[7] * dz)) * ir5;
+            e[0] = fma(mdr, dx, fma(-s[2], ir3, e[0]));
+            e[1] = fma(mdr, dy, fma(-s[4], ir3, e[1]));
+            e[2] = fma(mdr, dz, fma(-s[6], ir3, e[2]));
+            e[3] = fma(mdi, dx, fma(-s[3], ir3, e[3]));
+            e[4] = fma(mdi, dy, fma(-s[5], ir3, e[4]));
+            e[5] = fma(mdi, dz, fma(-s[7], ir3, e[5]));
+        }
+    };
+    // one source atom with its Gaussian charge (and dipole): field and density
+    auto gauss_pair = [&](const double* s, double dx, double dy, double dz, double r2) {
+        const double r = sqrt(r2);
+        double g3, brk, ex;
+        probe_radial(r, k.rq, g3, brk, ex);
+        const double fr = s[0] * g3, fi = s[1] * g3;
+        e[0] = fma(fr, dx, e[0]);
+        e[1] = fma(fr, dy, e[1]);
+        e[2] = fma(fr, dz, e[2]);
+        e[3] = fma(fi, dx, e[3]);
+        e[4] = fma(fi, dy, e[4]);
+        e[5] = fma(fi, dz, e[5]);
+        rho[0] = fma(s[0], k.gq * ex, rho[0]);
+        rho[1] = fma(s[1], k.gq * ex, rho[1]);
+        if (MODEL) {
+            probe_radial(r, k.rmu, g3, brk, ex);
+            const double mdr = fma(s[2], dx, fma(s[4], dy, s[6] * dz));
+            const double mdi = fma(s[3], dx, fma(s[5], dy, s[7] * dz));
+            e[0] = fma(mdr * brk, dx, fma(-s[2], g3, e[0]));
+            e[1] = fma(mdr * brk, dy, fma(-s[4], g3, e[1]));
+            e[2] = fma(mdr * brk, dz, fma(-s[6], g3, e[2]));
+            e[3] = fma(mdi * brk, dx, fma(-s[3], g3, e[3]));
+            e[4] = fma(mdi * brk, dy, fma(-s[5], g3, e[4]));
+            e[5] = fma(mdi * brk, dz, fma(-s[7], g3, e[5]));
+            const double w = 2.0 / (k.rmu * k.rmu) * k.gmu * ex;
+            rho[0] = fma(mdr, w, rho[0]);
+            rho[1] = fma(mdi, w, rho[1]);
+        }
+    };
+    const double near2 = (double)k.near2;
     const int nchunk = (int)(np / PROBE_CHUNK);
     for (int ch = blockIdx.y; ch < nchunk; ch += gridDim.y)
     for (int gq = ch * (PROBE_CHUNK / GROUP); gq < (ch + 1) * (PROBE_CHUNK / GROUP); ++gq) {
         const int j0 = uniform_i(gq * GROUP);
         if (uniform_i(nbr::box_gap2(blo, bhi, glo[gq], ghi[gq]) >= k.near2)) {
-            // point charges (and point dipoles)
+            // the whole group beyond the near distance of the wave's box
 #pragma unroll 8
             for (int jj = 0; jj < GROUP; ++jj) {
                 const double4 a = xyz[j0 + jj];
-                const double* s = src + (size_t)(j0 + jj) * S;
                 const double dx = p.x - a.x, dy = p.y - a.y, dz = p.z - a.z;
-                const double ir = 0.5 * rsqrt2(fma(dx, dx, fma(dy, dy, dz * dz)));
-                const double ir2 = ir * ir, ir3 = ir2 * ir;
-                const double fr = s[0] * ir3, fi = s[1] * ir3;
-                e[0] = fma(fr, dx, e[0]);
-                e[1] = fma(fr, dy, e[1]);
-                e[2] = fma(fr, dz, e[2]);
-                e[3] = fma(fi, dx, e[3]);
-                e[4] = fma(fi, dy, e[4]);
-                e[5] = fma(fi, dz, e[5]);
-                if (MODEL) {
-                    const double ir5 = 3.0 * ir3 * ir2;
-                    const double mdr = fma(s[2], dx, fma(s[4], dy, s[6] * dz)) * ir5;
-                    const double mdi = fma(s[3], dx, fma(s[5], dy, s[7] * dz)) * ir5;
-                    e[0] = fma(mdr, dx, fma(-s[2], ir3, e[0]));
-                    e[1] = fma(mdr, dy, fma(-s[4], ir3, e[1]));
-                    e[2] = fma(mdr, dz, fma(-s[6], ir3, e[2]));
-                    e[3] = fma(mdi, dx, fma(-s[3], ir3, e[3]));
-                    e[4] = fma(mdi, dy, fma(-s[5], ir3, e[4]));
-                    e[5] = fma(mdi, dz, fma(-s[7], ir3, e[5]));
-                }
+                point_pair(src + (size_t)(j0 + jj) * S, dx, dy, dz, fma(dx, dx, fma(dy, dy, dz * dz)));
             }
         } else {
-            // Gaussian charges (and dipoles)
+            // per atom: the Gaussian forms only where one of the wave's points
+            // is within the near distance (a wave vote), else the point forms
             for (int jj = 0; jj < GROUP; ++jj) {
                 const double4 a = xyz[j0 + jj];
                 const double* s = src + (size_t)(j0 + jj) * S;
                 const double dx = p.x - a.x, dy = p.y - a.y, dz = p.z - a.z;
-                const double r = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-                double g3, brk, ex;
-                probe_radial(r, k.rq, g3, brk, ex);
-                const double fr = s[0] * g3, fi = s[1] * g3;
-                e[0] = fma(fr, dx, e[0]);
-                e[1] = fma(fr, dy, e[1]);
-                e[2] = fma(fr, dz, e[2]);
-                e[3] = fma(fi, dx, e[3]);
-                e[4] = fma(fi, dy, e[4]);
-                e[5] = fma(fi, dz, e[5]);
-                rho[0] = fma(s[0], k.gq * ex, rho[0]);
-                rho[1] = fma(s[1], k.gq * ex, rho[1]);
-                if (MODEL) {
-                    probe_radial(r, k.rmu, g3, brk, ex);
-                    const double mdr = fma(s[2], dx, fma(s[4], dy, s[6] * dz));
-                    const double mdi = fma(s[3], dx, fma(s[5], dy, s[7] * dz));
-                    e[0] = fma(mdr * brk, dx, fma(-s[2], g3, e[0]));
-                    e[1] = fma(mdr * brk, dy, fma(-s[4], g3, e[1]));
-                    e[2] = fma(mdr * brk, dz, fma(-s[6], g3, e[2]));
-                    e[3] = fma(mdi * brk, dx, fma(-s[3], g3, e[3]));
-                    e[4] = fma(mdi * brk, dy, fma(-s[5], g3, e[4]));
-                    e[5] = fma(mdi * brk, dz, fma(-s[7], g3, e[5]));
-                    const double w = 2.0 / (k.rmu * k.rmu) * k.gmu * ex;
-                    rho[0] = fma(mdr, w, rho[0]);
-                    rho[1] = fma(mdi, w, rho[1]);
-                }
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                if (__ballot(r2 < near2) != 0) gauss_pair(s, dx, dy, dz, r2);
+                else point_pair(s, dx, dy, dz, r2);
             }
         }
     }
