@@ -324,13 +324,42 @@ float time_apply(pxStructure_t* s, bool f32, int method, const void* X, void* Y,
 }
 
 // The method for this shape: forced by the options, else the tuner's choice.
-int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const pxSolveOptions& o)
+// Above this many bytes the stored FP64 T is not tried for the narrow (1-8
+// column) apply: that product streams T from HBM (8 N^2 bytes per apply)
+// while the point-charge kernel is ALU-bound on the same N^2 pairs, about 3x
+// faster (20k atoms: 570 against 182 us); only a T that stays in the
+// last-level cache can compete.
+constexpr double kNarrowStoredMaxBytes = 256.0 * (1 << 20);
+// Largest dense T built to tune a single-use residual shape.
+constexpr double kSingleUseTuneMaxBytes = 4.0 * (1 << 30);
+
+// single_use: the apply is a true residual that the solve may need only once
+// or twice (after the shared phase).  A dense T built for it then costs its
+// generation and a device allocation (and its release) of 8 N_u^2 bytes per
+// structure, more than the one apply saves unless the block cache already
+// holds a block for it (a structure of the same size solved before).
+int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const pxSolveOptions& o,
+                  bool single_use = false)
 {
     // the BEM operator is generated on the fly only (it is not symmetric)
     if (o.t_apply == PX_TAPPLY_ON_THE_FLY || s->g.bem) return TA_FLY;
     if (o.t_apply == PX_TAPPLY_STORED) {
         ensure_stored(s, f32);
         return TA_STORED;
+    }
+    const double t_bytes = (double)s->g.nup * (double)s->g.nup * (f32 ? 4.0 : 8.0);
+    if (!f32 && ncols <= 8 && t_bytes > kNarrowStoredMaxBytes && !s->t64) return TA_FLY;
+    if (single_use && !(f32 ? (void*)s->t32 : (void*)s->t64) &&
+        !pxs::BlockCache::get().can_serve((size_t)t_bytes)) {
+        // the T would need a new allocation: on the fly, except to tune a
+        // new shape whose T is small enough (its block then serves the
+        // structures of that size that follow)
+        bool tuned;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            tuned = g_tune.count(std::make_tuple((int)s->g.model, (int64_t)s->g.n, ncols, f32 ? 32 : 64)) > 0;
+        }
+        if (tuned || t_bytes > kSingleUseTuneMaxBytes) return TA_FLY;
     }
     const auto key = std::make_tuple((int)s->g.model, (int64_t)s->g.n, ncols, f32 ? 32 : 64);
     {
@@ -385,11 +414,12 @@ void sparse_apply(pxStructure_t* s, const void* Y, bool f32, int ldy, const doub
 }
 
 // r = b - A x for the active block (FP64 T-apply and FP64 sparse apply).
+// single_use: the first residual of a solve (see tapply_method).
 void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* rs, int na, int lda,
-              const pxSolveOptions& o)
+              const pxSolveOptions& o, bool single_use = false)
 {
     Workspace& W = s->ws;
-    const int method = tapply_method(s, false, xs, W.Y64, 2 * lda, 2 * lda, o);
+    const int method = tapply_method(s, false, xs, W.Y64, 2 * lda, 2 * lda, o, single_use);
     tapply(s, method, false, xs, W.Y64, 2 * lda, 2 * lda, nullptr);
     s->tstats[method == TA_STORED ? 3 : 2] += 1;
     s->counts[3] += 1;
@@ -500,7 +530,8 @@ class BlockRun {
         pxStructure_t* s = s_;
         Workspace& W = s->ws;
         const int64_t nup = s->g.nup;
-        residual(s, W.xs, W.bs, W.rs, na_, lda_, o_);
+        residual(s, W.xs, W.bs, W.rs, na_, lda_, o_, first_residual_);
+        first_residual_ = false;
         col_norms(s, W.rs, na_, lda_, beta_);
         std::vector<int> keep;
         bool slow = false;
@@ -716,6 +747,7 @@ class BlockRun {
     State state_ = RESIDUAL;
     int m_ = 0, m_max_ = 0, na_ = 0, lda_ = 0;
     bool mixed_ = false, dcgs2_ = false, wide32_ = false;
+    bool first_residual_ = true;
     std::vector<double> beta_;
     std::vector<int32_t> done_h_;
     int64_t vstride_ = 0;

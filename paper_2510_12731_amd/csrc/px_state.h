@@ -100,6 +100,19 @@ class BlockCache {
         return p;
     }
 
+    // a take(bytes) on this device would be served from the kept blocks
+    bool can_serve(size_t bytes)
+    {
+        if (bytes == 0) bytes = 1;
+        if (px::caller_allocator()) return false;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return false;
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto it = blocks_.lower_bound(bytes); it != blocks_.end() && it->first <= 2 * bytes; ++it)
+            if (it->second.dev == dev) return true;
+        return false;
+    }
+
     // p came from take() and no stream uses it any more
     void give(void* p)
     {
