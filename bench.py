@@ -544,6 +544,8 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
     srv = serving_run(pxm, cases, arrivals, budget, block_cols)
     err = max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"]))) for a, b in zip(srv["sigma"], seq))
     lat = np.array(srv["latency"])
+    # saturated: every request queued at once, against the same requests one after the other
+    sat = serving_run(pxm, cases, np.zeros(n_req), budget, block_cols)
     return dict(requests=n_req, columns=cols, n_range=[n_min, n_max], arrival_rate_per_s=round(lam, 3),
                 load=load, solves_per_s=round(cols / srv["makespan"], 2),
                 p50_s=round(float(np.percentile(lat, 50)), 3), p99_s=round(float(np.percentile(lat, 99)), 3),
@@ -556,7 +558,11 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
                 sigma_rel_err_mix_vs_fp64=max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"])))
                                               for a, b in zip(srv["sigma"], seq64)),
                 peak_rows=srv["peak_rows"], rows_capacity=srv["rows_capacity"],
-                sigma_rel_err_mix_vs_alone=err)
+                sigma_rel_err_mix_vs_alone=err,
+                saturated=dict(solves_per_s=round(cols / sat["makespan"], 2),
+                               one_at_a_time_solves_per_s=round(cols / t_seq, 2),
+                               note="all requests queued at t = 0; at 75 % load both serve every request as it "
+                                    "arrives, so their solves/s above follow the arrival rate"))
 
 
 # FP64 arithmetic per (point, atom) pair of the probe kernel's point-source
@@ -659,8 +665,9 @@ def main():
                          "with --no-shifted one blocked restart cycle of 4 steps (with --t-apply)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving-full", "probe", "batch"],
-                    help="sphere: the headline line with every config's extra; serving-full: the serving mix at "
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving", "serving-full", "probe", "batch"],
+                    help="sphere: the headline line with every config's extra; serving: the serving mix alone; "
+                         "serving-full: the serving mix at "
                          "1k-100k atoms; probe: the induced-field evaluation; batch: the 64-structure graphene "
                          "batch alone, first and warm call; printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads (rod, batch, serving, BEM)")
@@ -711,6 +718,10 @@ def main():
             r = batch_run(pxm, cases, pxm.PX_MIXED)
             print(json.dumps({"workload": "graphene_batch_64", "call": label, "seconds": round(r["seconds"], 3),
                               "status": r["status"], "relres_max": r["relres_max"]}), flush=True)
+        return
+    if args.workload == "serving":
+        out = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
+        print(json.dumps({"workload": "serving_mix", **out}), flush=True)
         return
     if args.workload == "serving-full":
         out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75)
