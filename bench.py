@@ -56,7 +56,7 @@ def one_step(px, case, precision, timings, max_block_cols=0, t_apply=None, shift
     s = px.Structure(case["model"], case["xyz"], case["params"], px.default_stream())
     pol = case["pol_mask"]
     s.set_frequencies(om, pol, case["e0"], case["alpha_ib"])
-    st = s.solve(precision=precision, restart_m=50, rel_tol=1e-8, max_block_cols=max_block_cols, timings=timings,
+    st = s.solve(precision=precision, rel_tol=1e-8, max_block_cols=max_block_cols, timings=timings,
                  t_apply=t_apply, shifted=shifted)
     alpha, sigma = s.spectrum()
     it, cyc, rr = s.stats()
@@ -908,8 +908,8 @@ def main():
         "config": {"workload": case["name"], "n_atoms": n, "n_omega": int(len(case["omega_ev"])),
                    "polarizations": 3, "columns": ncol, "rel_tol": 1e-8, "t_apply": args.t_apply,
                    "solver": ("shared-Krylov phase (one FP64 block Arnoldi process over the three polarizations for "
-                              "all frequencies), blocked GMRES(50) for any column left" if shifted else
-                              "blocked GMRES(50), FP32 T-apply, FP64 refinement")},
+                              "all frequencies), blocked GMRES(100) for any column left" if shifted else
+                              "blocked GMRES(100), FP32 T-apply, FP64 refinement")},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -114,7 +114,7 @@ typedef struct {
 
 /* Solver options (pxDefaultSolveOptions fills the defaults shown).
  *   precision        PX_FP64 (default) or PX_MIXED (see pxPrecision)
- *   restart_m        GMRES restart length m at the start (50)
+ *   restart_m        GMRES restart length m at the start (100)
  *   max_restart_m    the restart length doubles, up to this value, whenever
  *                    some column's true residual fell by less than 30 % over
  *                    its last cycle (restarted GMRES stagnates at the sharp

@@ -384,30 +384,23 @@ def pxLastError():
     return load().pxLastError().decode()
 
 
-def solve_options(precision=PX_FP64, restart_m=50, rel_tol=1e-8, max_cycles=400, max_block_cols=0,
-                  inner_reduction=1e-5, timings=False, stall_cycles=8, max_restart_m=200, block_cols=0,
+def solve_options(precision=None, restart_m=None, rel_tol=None, max_cycles=None, max_block_cols=None,
+                  inner_reduction=None, timings=None, stall_cycles=None, max_restart_m=None, block_cols=None,
                   ortho=None, graph_steps=None, t_apply=None, shifted=None, shifted_max_steps=None):
+    """pxSolveOptions: pxDefaultSolveOptions with the given fields replaced."""
     o = pxDefaultSolveOptions()
-    o.precision = int(precision)
-    o.restart_m = int(restart_m)
-    o.rel_tol = float(rel_tol)
-    o.max_cycles = int(max_cycles)
-    o.max_block_cols = int(max_block_cols)
-    o.inner_reduction = float(inner_reduction)
-    o.timings = int(bool(timings))
-    o.stall_cycles = int(stall_cycles)
-    o.max_restart_m = int(max_restart_m)
-    o.block_cols = int(block_cols)
-    if ortho is not None:
-        o.ortho = int(ortho)
-    if graph_steps is not None:
-        o.graph_steps = int(graph_steps)
-    if t_apply is not None:
-        o.t_apply = int(t_apply)
-    if shifted is not None:
-        o.shifted = int(shifted)
-    if shifted_max_steps is not None:
-        o.shifted_max_steps = int(shifted_max_steps)
+    given = dict(precision=precision, restart_m=restart_m, max_cycles=max_cycles, max_block_cols=max_block_cols,
+                 stall_cycles=stall_cycles, max_restart_m=max_restart_m, block_cols=block_cols, ortho=ortho,
+                 graph_steps=graph_steps, t_apply=t_apply, shifted=shifted, shifted_max_steps=shifted_max_steps)
+    for name, v in given.items():
+        if v is not None:
+            setattr(o, name, int(v))
+    if rel_tol is not None:
+        o.rel_tol = float(rel_tol)
+    if inner_reduction is not None:
+        o.inner_reduction = float(inner_reduction)
+    if timings is not None:
+        o.timings = int(bool(timings))
     return o
 
 

@@ -1555,7 +1555,7 @@ void pxDefaultSolveOptions(pxSolveOptions* o)
 {
     if (!o) return;
     o->precision = PX_FP64;
-    o->restart_m = 50;
+    o->restart_m = 100;
     o->rel_tol = 1e-8;
     o->max_cycles = 400;
     o->max_block_cols = 0;

@@ -54,7 +54,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_default_options(lib):
     o = px.pxDefaultSolveOptions()
-    assert (o.precision, o.restart_m, o.rel_tol, o.max_cycles, o.max_block_cols) == (px.PX_FP64, 50, 1e-8, 400, 0)
+    assert (o.precision, o.restart_m, o.rel_tol, o.max_cycles, o.max_block_cols) == (px.PX_FP64, 100, 1e-8, 400, 0)
     assert o.shifted == 2 and o.shifted_max_steps == 2000
     assert o.inner_reduction == 1e-5 and o.timings == 0 and o.stall_cycles == 8
     assert o.max_restart_m == 200 and o.block_cols == 0 and o.ortho == px.PX_ORTHO_DCGS2 and o.graph_steps == 8 and o.t_apply == px.PX_TAPPLY_AUTO
