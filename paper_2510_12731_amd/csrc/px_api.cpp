@@ -279,13 +279,14 @@ void ensure_stored(pxStructure_t* s, bool f32)
 
 // Y = T X on the stored T (hand-written kernels: FP32 or FP64 MFMA tiles, or
 // a split pass over T for the narrow FP64 blocks).
+// active (FP32): the real columns that hold data; 0 = all
 void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop = nullptr,
-                  const hipEvent_t* ev = nullptr)
+                  const hipEvent_t* ev = nullptr, int active = 0)
 {
     Workspace& W = s->ws;
     if (f32)
         px::tstored_f32(s->g, s->t32, static_cast<const float*>(X), static_cast<float*>(Y), ldx, ncols, s->st, W.sk32,
-                        stop, ev);
+                        stop, ev, active);
     else
         px::tstored_f64(s->g, s->t64, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st,
                         W.narrow, stop, ev);
@@ -393,11 +394,13 @@ int tapply_method(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, i
 
 // ev (optional): start/stop events around the apply (carried by the launches
 // of the on-the-fly FP64 kernels, recorded on the stream otherwise).
+// active: the real columns that hold data (columns beyond are not read
+// afterwards, so the stored FP32 product may skip them); 0 = all
 void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop,
-            const hipEvent_t* ev = nullptr)
+            const hipEvent_t* ev = nullptr, int active = 0)
 {
     if (method == TA_STORED) {
-        apply_stored(s, f32, X, Y, ldx, ncols, stop, ev);
+        apply_stored(s, f32, X, Y, ldx, ncols, stop, ev, active);
     } else {
         apply_fly(s, f32, X, Y, ldx, ncols, stop, ev);
     }
@@ -639,7 +642,7 @@ class BlockRun {
             }
             double2* vk = W.V + k * vstride_;
             tm_.mark(k, 0, s->st);
-            if (wide32_) tapply(s, method_, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop_);
+            if (wide32_) tapply(s, method_, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop_, nullptr, 2 * na);
             else tapply(s, method_, false, vk, W.Y64, 2 * lda, 2 * lda, stop_);
             tm_.mark(k, 1, s->st);
             sparse_apply(s, wide32_ ? (const void*)W.Y32 : (const void*)W.Y64, wide32_, 2 * lda, vk, nullptr, W.w, na,

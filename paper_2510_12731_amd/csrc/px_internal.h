@@ -129,8 +129,9 @@ size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 // ncols) a split pass over T with scratch of tapply_f64_scratch_bytes(g, 8).
 // ev: optional start/stop events carried by the first and last launch.
 size_t tstored_f32_scratch_bytes();
+// active: the real columns that hold data (the others are never read); 0 = all
 void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, int ldx, int ncols, hipStream_t st,
-                 float* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
+                 float* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr, int active = 0);
 void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
                  double* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
 void tdense_f32(const Geometry& g, float* T, hipStream_t st);

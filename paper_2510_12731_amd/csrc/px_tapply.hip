@@ -280,11 +280,16 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tapply_wfq_f32(const float4* __
 // exactly), so lane l of k-step kk, which needs T[i][j] for row i = row0 +
 // l%32 and source j = j0 + 2 kk + l/32, reads T[j][i]: the 32 lanes of a
 // half-wave read 128 contiguous bytes.  The next chunk's 16 values per lane
-// are loaded while the current chunk's MFMAs run.
+// are loaded while the current chunk's MFMAs run.  NB = 4 computes all 128
+// columns of a tile (MFMA column n of block cb is tile column 4n + cb); NB = 2
+// only its first 64 (column 2n + cb), for a last column block whose other
+// half holds no active column (the sparse apply never reads those).
+template <int NB>
 __device__ __forceinline__ void tstored_f32_body(int bx, int by, int cbeg, int cend, const float* __restrict__ Ts,
                                                  int ldt, const float* __restrict__ X, float* __restrict__ out,
                                                  int ldo, int ldx)
 {
+    static_assert(NB == 2 || NB == 4, "four or two 32-column MFMA blocks per tile");
     __shared__ __attribute__((aligned(16))) float sx[2][Q32_JC][Q32_COLS];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -293,11 +298,11 @@ __device__ __forceinline__ void tstored_f32_body(int bx, int by, int cbeg, int c
     const int col0 = by * Q32_COLS;
     const int ii = row0 + (lane & 31);
     const int half = lane >> 5;
-    const int col4 = 4 * (lane & 31);
+    const int coln = NB * (lane & 31);
 
-    f32x16 acc[4];
+    f32x16 acc[NB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[cb][v] = 0.0f;
 
@@ -326,17 +331,34 @@ __device__ __forceinline__ void tstored_f32_body(int bx, int by, int cbeg, int c
         float tn[Q32_JC / 2];
 #pragma unroll
         for (int kk = 0; kk < Q32_JC / 2; ++kk) tn[kk] = Ts[(size_t)(jn + 2 * kk + half) * ldt + ii];
-        float4 bq = *reinterpret_cast<const float4*>(&sx[buf][half][col4]);
+        if constexpr (NB == 4) {
+            float4 bq = *reinterpret_cast<const float4*>(&sx[buf][half][coln]);
 #pragma unroll
-        for (int kk = 0; kk < Q32_JC / 2; ++kk) {
-            float4 bqn = bq;
-            if (kk + 1 < Q32_JC / 2) bqn = *reinterpret_cast<const float4*>(&sx[buf][2 * kk + 2 + half][col4]);
-            mfma4(acc, tv[kk], bq);
-            bq = bqn;
-            if (kk == Q32_JC / 4 && more) {
-                float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
-                dst[0] = pre0;
-                dst[1] = pre1;
+            for (int kk = 0; kk < Q32_JC / 2; ++kk) {
+                float4 bqn = bq;
+                if (kk + 1 < Q32_JC / 2) bqn = *reinterpret_cast<const float4*>(&sx[buf][2 * kk + 2 + half][coln]);
+                mfma4(acc, tv[kk], bq);
+                bq = bqn;
+                if (kk == Q32_JC / 4 && more) {
+                    float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
+                    dst[0] = pre0;
+                    dst[1] = pre1;
+                }
+            }
+        } else {
+            float2 bq = *reinterpret_cast<const float2*>(&sx[buf][half][coln]);
+#pragma unroll
+            for (int kk = 0; kk < Q32_JC / 2; ++kk) {
+                float2 bqn = bq;
+                if (kk + 1 < Q32_JC / 2) bqn = *reinterpret_cast<const float2*>(&sx[buf][2 * kk + 2 + half][coln]);
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(tv[kk], bq.x, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(tv[kk], bq.y, acc[1], 0, 0, 0);
+                bq = bqn;
+                if (kk == Q32_JC / 4 && more) {
+                    float4* dst = reinterpret_cast<float4*>(&sx[buf ^ 1][lr][lc]);
+                    dst[0] = pre0;
+                    dst[1] = pre1;
+                }
             }
         }
 #pragma unroll
@@ -347,11 +369,16 @@ __device__ __forceinline__ void tstored_f32_body(int bx, int by, int cbeg, int c
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int i = wave * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        const float4 o = make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
-        *reinterpret_cast<float4*>(out + (size_t)i * ldo + col4) = o;
+        if constexpr (NB == 4) {
+            const float4 o = make_float4(acc[0][v], acc[1][v], acc[2][v], acc[3][v]);
+            *reinterpret_cast<float4*>(out + (size_t)i * ldo + coln) = o;
+        } else {
+            *reinterpret_cast<float2*>(out + (size_t)i * ldo + coln) = make_float2(acc[0][v], acc[1][v]);
+        }
     }
 }
 
+template <int NB>
 __global__ __launch_bounds__(Q32_THREADS) void k_tstored_f32(const float* __restrict__ Ts, int ldt,
                                                              const float* __restrict__ X, float* __restrict__ Y,
                                                              float* __restrict__ partial, int ldx, SkGrid sk,
@@ -361,7 +388,7 @@ __global__ __launch_bounds__(Q32_THREADS) void k_tstored_f32(const float* __rest
     sk_pieces(sk, blockIdx.x, [&](int t, int c0, int c1, int slot) {
         const int rb = t % sk.RB, cb = t / sk.RB;
         float* out = slot < 0 ? Y + (size_t)rb * 256 * ldx + cb * Q32_COLS : partial + (size_t)slot * SK_TILE_FLOATS;
-        tstored_f32_body(rb, cb, c0, c1, Ts, ldt, X, out, slot < 0 ? ldx : Q32_COLS, ldx);
+        tstored_f32_body<NB>(rb, cb, c0, c1, Ts, ldt, X, out, slot < 0 ? ldx : Q32_COLS, ldx);
     });
 }
 
@@ -1841,19 +1868,35 @@ void GroupedTApply::run_f64(const double* X, double* Y, hipStream_t st, const in
 size_t tstored_f32_scratch_bytes() { return (size_t)2 * sk_slots() * SK_TILE_FLOATS * sizeof(float); }
 
 void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, int ldx, int ncols, hipStream_t st,
-                 float* scratch, const int32_t* stop, const hipEvent_t* ev)
+                 float* scratch, const int32_t* stop, const hipEvent_t* ev, int active)
 {
-    SkGrid sk{};
-    sk.RB = (int)(g.nup / 256);
-    sk.C = (int)(g.nup / Q32_JC);
-    sk.T = sk.RB * (ncols / Q32_COLS);
-    sk.total = (int64_t)sk.T * sk.C;
-    sk.G = sk_workgroups(sk.total);
+    // column blocks of 128; the last one as a 64-column tile when its active
+    // columns fit one (a second stream-K launch over that block alone)
+    const int nb = ncols / Q32_COLS;
+    if (active <= 0 || active > ncols) active = ncols;
+    const int last = active - (nb - 1) * Q32_COLS;
+    const bool half = nb >= 1 && last > 0 && last <= Q32_COLS / 2;
+    const int nfull = half ? nb - 1 : nb;
     hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
-    hipExtLaunchKernelGGL(k_tstored_f32, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, e0, nullptr, 0, T,
-                          (int)g.nup, X, Y, scratch, ldx, sk, stop);
-    hipExtLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * sk.T)), dim3(256), 0, st, nullptr, e1, 0, scratch, Y, ldx,
-                          sk, (const GroupConst*)nullptr, stop);
+    auto launch = [&](int nblk, bool halftile, const float* Xb, float* Yb, hipEvent_t a, hipEvent_t b) {
+        SkGrid sk{};
+        sk.RB = (int)(g.nup / 256);
+        sk.C = (int)(g.nup / Q32_JC);
+        sk.T = sk.RB * nblk;
+        sk.total = (int64_t)sk.T * sk.C;
+        sk.G = sk_workgroups(sk.total);
+        if (halftile)
+            hipExtLaunchKernelGGL(k_tstored_f32<2>, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, a, nullptr, 0, T,
+                                  (int)g.nup, Xb, Yb, scratch, ldx, sk, stop);
+        else
+            hipExtLaunchKernelGGL(k_tstored_f32<4>, dim3((unsigned)sk.G), dim3(Q32_THREADS), 0, st, a, nullptr, 0, T,
+                                  (int)g.nup, Xb, Yb, scratch, ldx, sk, stop);
+        hipExtLaunchKernelGGL(k_sk_fixup, dim3((unsigned)(32 * sk.T)), dim3(256), 0, st, nullptr, b, 0, scratch, Yb,
+                              ldx, sk, (const GroupConst*)nullptr, stop);
+    };
+    if (nfull > 0) launch(nfull, false, X, Y, e0, half ? nullptr : e1);
+    if (half)
+        launch(1, true, X + (size_t)nfull * Q32_COLS, Y + (size_t)nfull * Q32_COLS, nfull > 0 ? nullptr : e0, e1);
 }
 
 void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
