@@ -289,11 +289,11 @@ void apply_stored(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, i
                         stop, ev, active);
     else
         px::tstored_f64(s->g, s->t64, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st,
-                        W.narrow, stop, ev);
+                        W.narrow, stop, ev, active);
 }
 
 void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int ncols, const int32_t* stop,
-               const hipEvent_t* ev = nullptr)
+               const hipEvent_t* ev = nullptr, int active = 0)
 {
     Workspace& W = s->ws;
     if (f32) {
@@ -303,7 +303,7 @@ void apply_fly(pxStructure_t* s, bool f32, const void* X, void* Y, int ldx, int 
         if (ev) HC(hipEventRecord(ev[1], s->st));
     } else {
         px::tapply_f64(s->g, static_cast<const double*>(X), static_cast<double*>(Y), ldx, ncols, s->st, W.narrow,
-                       W.narrow_bytes, stop, ev);
+                       W.narrow_bytes, stop, ev, active);
     }
 }
 
@@ -402,7 +402,7 @@ void tapply(pxStructure_t* s, int method, bool f32, const void* X, void* Y, int 
     if (method == TA_STORED) {
         apply_stored(s, f32, X, Y, ldx, ncols, stop, ev, active);
     } else {
-        apply_fly(s, f32, X, Y, ldx, ncols, stop, ev);
+        apply_fly(s, f32, X, Y, ldx, ncols, stop, ev, active);
     }
 }
 
@@ -423,7 +423,7 @@ void residual(pxStructure_t* s, const double2* xs, const double2* bs, double2* r
 {
     Workspace& W = s->ws;
     const int method = tapply_method(s, false, xs, W.Y64, 2 * lda, 2 * lda, o, single_use);
-    tapply(s, method, false, xs, W.Y64, 2 * lda, 2 * lda, nullptr);
+    tapply(s, method, false, xs, W.Y64, 2 * lda, 2 * lda, nullptr, nullptr, 2 * na);
     s->tstats[method == TA_STORED ? 3 : 2] += 1;
     s->counts[3] += 1;
     s->counts[4] += 2 * lda;
@@ -643,7 +643,7 @@ class BlockRun {
             double2* vk = W.V + k * vstride_;
             tm_.mark(k, 0, s->st);
             if (wide32_) tapply(s, method_, true, W.X32, W.Y32, 2 * lda, 2 * lda, stop_, nullptr, 2 * na);
-            else tapply(s, method_, false, vk, W.Y64, 2 * lda, 2 * lda, stop_);
+            else tapply(s, method_, false, vk, W.Y64, 2 * lda, 2 * lda, stop_, nullptr, 2 * na);
             tm_.mark(k, 1, s->st);
             sparse_apply(s, wide32_ ? (const void*)W.Y32 : (const void*)W.Y64, wide32_, 2 * lda, vk, nullptr, W.w, na,
                          lda, SOLVER_MU_SIGN, stop_);

@@ -116,8 +116,11 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
 size_t tapply_f32_scratch_bytes(const Geometry& g, int ncols);
 // ev: optional start/stop events carried by the first and last launch (timing
 // without extra stream packets).
+// active (blocks of more than 8 columns): the real columns that hold data;
+// column blocks past them are skipped (their outputs are not read); 0 = all
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
+                double* scratch, size_t scratch_bytes, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr,
+                int active = 0);
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols);
 
 // Dense T over the padded unknowns (row-major, nup x nup; ghost rows and
@@ -133,7 +136,7 @@ size_t tstored_f32_scratch_bytes();
 void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, int ldx, int ncols, hipStream_t st,
                  float* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr, int active = 0);
 void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                 double* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
+                 double* scratch, const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr, int active = 0);
 void tdense_f32(const Geometry& g, float* T, hipStream_t st);
 void tdense_f64(const Geometry& g, double* T, hipStream_t st);
 

@@ -1680,8 +1680,9 @@ size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 }
 
 void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                double* scratch, size_t scratch_bytes, const int32_t* stop, const hipEvent_t* ev)
+                double* scratch, size_t scratch_bytes, const int32_t* stop, const hipEvent_t* ev, int active)
 {
+    if (active <= 0 || active > ncols) active = ncols;
     (void)scratch_bytes;
     if (g.bem) {
         bem_apply_f64(g, X, Y, ldx, ncols, st, scratch, stop, ev);
@@ -1712,12 +1713,12 @@ void tapply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncol
     if (g.model == 0) {
         double rqq = std::sqrt(2.0) * g.r_q;
         float rf = (float)(XFAR_Q64 * rqq);
-        hipExtLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)(ncols / Q64_COLS)), dim3(256),
+        hipExtLaunchKernelGGL(k_tapply_wfq_f64, dim3((unsigned)(g.np / 128), (unsigned)((active + Q64_COLS - 1) / Q64_COLS)), dim3(256),
                               0, st, e0, e1, 0, (const double4*)g.xyz64, (const float4*)g.glo, (const float4*)g.ghi, X,
                               Y, (int)g.np, ldx, 1.0 / rqq, TWO_OVER_SQRTPI / rqq, rf * rf, stop);
     } else {
         DipoleConstD k = dipole_const_d(g);
-        hipExtLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)(ncols / D64_COLS)),
+        hipExtLaunchKernelGGL(k_tapply_wfqfmu_f64, dim3((unsigned)(g.np / 64), (unsigned)((active + D64_COLS - 1) / D64_COLS)),
                               dim3(256), 0, st, e0, e1, 0, (const double4*)g.xyz64, (const float4*)g.glo,
                               (const float4*)g.ghi, X, Y, (int)g.np, ldx, k, stop);
     }
@@ -1900,8 +1901,9 @@ void tstored_f32(const Geometry& g, const float* T, const float* X, float* Y, in
 }
 
 void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
-                 double* scratch, const int32_t* stop, const hipEvent_t* ev)
+                 double* scratch, const int32_t* stop, const hipEvent_t* ev, int active)
 {
+    if (active <= 0 || active > ncols) active = ncols;
     hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
     const int nup = (int)g.nup;
     if (ncols <= 8) {
@@ -1926,7 +1928,7 @@ void tstored_f64(const Geometry& g, const double* T, const double* X, double* Y,
                               (const double*)scratch, Y, len, nsplit, stop);
         return;
     }
-    hipExtLaunchKernelGGL(k_tstored_f64, dim3((unsigned)(nup / 128), (unsigned)(ncols / Q64_COLS)), dim3(256), 0, st,
+    hipExtLaunchKernelGGL(k_tstored_f64, dim3((unsigned)(nup / 128), (unsigned)((active + Q64_COLS - 1) / Q64_COLS)), dim3(256), 0, st,
                           e0, e1, 0, T, nup, X, Y, nup, ldx, stop);
 }
 
