@@ -138,15 +138,18 @@ def blocked_roofline(runs, n, traffic, traffic_cols):
                 method_launches={k: int(sum(r["tapply"][k] for r in runs)) for k in keys})
 
 
-def measured_traffic_stored(summary):
-    """HBM bytes per full-width stored-T GEMM launch from the committed counter
-    summary (a library kernel: keyed by the kernel name recorded there)."""
+def measured_traffic_stored(summary, kernel_src="paper_2510_12731_amd/csrc/px_tapply.hip"):
+    """HBM bytes per full-width stored-T product launch from the committed
+    counter summary, or None if the kernel source changed since the counters
+    were taken."""
+    import hashlib
     try:
         text = open(os.path.join(ROOT, "profiles", summary)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
     except OSError:
         return None, None, None
     kv = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(("-", "#")))
-    if "traffic_bytes_per_launch" not in kv:
+    if "traffic_bytes_per_launch" not in kv or kv.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None, None, None
     return int(kv["traffic_bytes_per_launch"]), int(kv["traffic_launch_real_columns"]), kv.get("kernel_name")
 
