@@ -232,12 +232,14 @@ def test_stored_t_apply_matches_oracle(precision, tol, bound):
         s.close()
 
 
-def test_stored_t_half_tile_block():
+@pytest.mark.parametrize("precision,tol,bound", [(px.PX_MIXED, 1e-8, 1e-5), (px.PX_FP64, 1e-12, 1e-10)])
+def test_stored_t_half_tile_block(precision, tol, bound):
     """96 columns: the blocked solver pads them to 128, so the stored FP32
     product runs one full 128-column block and, for the next block, whose 64
     active real columns fill half a tile, a 64-column tile; as columns retire
-    the block shrinks to 64 (one half tile).  Mixed precision on the stored T
-    against the oracle, and against the on-the-fly FP32 apply."""
+    the block shrinks to 64 (one half tile).  In FP64 the stored product runs
+    on the 192 active real columns alone.  Against the oracle, and against the
+    on-the-fly apply."""
     xyz = G.fcc_rod_n(100, seed=33)
     p = M.load("au_wfqfmu")
     om = np.linspace(1.6, 3.4, 48)
@@ -245,18 +247,20 @@ def test_stored_t_half_tile_block():
     ref = O.solve_spectrum(1, xyz, M.param_vector(p), om, 0b011, 1e-4, aib)
     out = {}
     for mode in (px.PX_TAPPLY_STORED, px.PX_TAPPLY_ON_THE_FLY):
-        s, st, alpha, sig, it, rr = _solve(1, xyz, p, om, 0b011, aib, px.PX_MIXED, 1e-8, t_apply=mode)
+        s, st, alpha, sig, it, rr = _solve(1, xyz, p, om, 0b011, aib, precision, tol, t_apply=mode)
         ts = s.tapply_stats()
         e = rel_err(sig, ref["sigma"])
-        say(f"[half tile] t_apply {mode}: status {st} iters max {it.max()} rel_err {e:.2e} launches {ts}")
-        assert st == px.PX_OK and rr.max() <= 1e-8 and e <= 1e-5
+        say(f"[half tile] precision {precision} t_apply {mode}: status {st} iters max {it.max()} rel_err {e:.2e} "
+            f"launches {ts}")
+        assert st == px.PX_OK and rr.max() <= tol and e <= bound
         if mode == px.PX_TAPPLY_STORED:
-            assert ts["f32_stored"] > 0 and ts["f32_on_the_fly"] == 0
+            key = "f32" if precision == px.PX_MIXED else "f64"
+            assert ts[key + "_stored"] > 0 and ts[key + "_on_the_fly"] == 0
         out[mode] = sig
         s.close()
     e = rel_err(out[px.PX_TAPPLY_STORED], out[px.PX_TAPPLY_ON_THE_FLY])
     say(f"[half tile] stored vs on the fly: {e:.2e}")
-    assert e <= 1e-6
+    assert e <= (1e-6 if precision == px.PX_MIXED else 1e-10)
 
 
 def test_gap_dimer_conserves_charge_per_fragment():
