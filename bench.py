@@ -522,10 +522,17 @@ def serving_run(pxm, cases, arrivals, budget_bytes, block_cols=64):
     return dict(latency=lat, makespan=makespan, sigma=sig, peak_rows=peak_rows, rows_capacity=cap)
 
 
-def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
+def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64, model=None, fp64=True):
+    """The serving mix: n_req seeded requests (model: only those of that model
+    out of the n_req drawn), served by the server under Poisson arrivals at
+    `load` of the one-at-a-time capacity, against one request at a time (and,
+    with fp64, the plain FP64 solver one at a time), then all queued at once."""
     from workloads import configs as C
     rng = np.random.default_rng(seed)
     cases = [C.serving_request(rng, n_min, n_max) for _ in range(n_req)]
+    if model is not None:
+        cases = [c for c in cases if c["model"] == model]
+        n_req = len(cases)
     cols = sum(ncols(c) for c in cases)
     seq = sequential_run(pxm, cases, pxm.PX_MIXED)
     t_seq = sum(r["seconds"] for r in seq)
@@ -538,7 +545,7 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
         t = max(t, a) + r["seconds"]
         lat_seq.append(t - a)
     # the plain FP64 solver (blocked, no shared-Krylov phase) one request at a time, same arrivals, FIFO
-    seq64 = sequential_run(pxm, cases, pxm.PX_FP64, shifted=0)
+    seq64 = sequential_run(pxm, cases, pxm.PX_FP64, shifted=0) if fp64 else seq
     t64, lat64 = 0.0, []
     for a, r in zip(arrivals, seq64):
         t64 = max(t64, a) + r["seconds"]
@@ -555,11 +562,11 @@ def serving_extra(pxm, n_req, n_min, n_max, seed, load, block_cols=64):
                 one_at_a_time_solves_per_s=round(cols / max(t, 1e-9), 2),
                 one_at_a_time_p50_s=round(float(np.percentile(lat_seq, 50)), 3),
                 one_at_a_time_p99_s=round(float(np.percentile(lat_seq, 99)), 3),
-                fp64_one_at_a_time_solves_per_s=round(cols / max(t64, 1e-9), 2),
-                fp64_one_at_a_time_p50_s=round(float(np.percentile(lat64, 50)), 3),
-                fp64_one_at_a_time_p99_s=round(float(np.percentile(lat64, 99)), 3),
+                fp64_one_at_a_time_solves_per_s=round(cols / max(t64, 1e-9), 2) if fp64 else None,
+                fp64_one_at_a_time_p50_s=round(float(np.percentile(lat64, 50)), 3) if fp64 else None,
+                fp64_one_at_a_time_p99_s=round(float(np.percentile(lat64, 99)), 3) if fp64 else None,
                 sigma_rel_err_mix_vs_fp64=max(float(np.max(np.abs(a - b["sigma"])) / np.max(np.abs(b["sigma"])))
-                                              for a, b in zip(srv["sigma"], seq64)),
+                                              for a, b in zip(srv["sigma"], seq64)) if fp64 else None,
                 peak_rows=srv["peak_rows"], rows_capacity=srv["rows_capacity"],
                 sigma_rel_err_mix_vs_alone=err,
                 saturated=dict(solves_per_s=round(cols / sat["makespan"], 2),
@@ -668,9 +675,9 @@ def main():
                          "with --no-shifted one blocked restart cycle of 4 steps (with --t-apply)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving", "serving-full", "probe", "batch"],
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving", "serving-full", "serving-wfq-full", "probe", "batch"],
                     help="sphere: the headline line with every config's extra; serving: the serving mix alone; "
-                         "serving-full: the serving mix at "
+                         "serving-wfq-full: the omegaFQ requests of the 1k-100k mix; serving-full: the serving mix at "
                          "1k-100k atoms; probe: the induced-field evaluation; batch: the 64-structure graphene "
                          "batch alone, first and warm call; printed as their own JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads (rod, batch, serving, BEM)")
@@ -729,6 +736,12 @@ def main():
     if args.workload == "serving-full":
         out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75)
         print(json.dumps({"workload": "serving_mix_full", **out}), flush=True)
+        return
+    if args.workload == "serving-wfq-full":
+        t0 = time.perf_counter()
+        out = serving_extra(pxm, 40, 1000, 100000, 5, 0.75, model=0, fp64=False)
+        print(json.dumps({"workload": "serving_mix_full_wfq", "seconds": round(time.perf_counter() - t0, 1), **out}),
+              flush=True)
         return
 
     case = C.sphere_20k(args.n, args.n_omega)
