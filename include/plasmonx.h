@@ -76,7 +76,7 @@ typedef enum {
 typedef enum {
     PX_TAPPLY_AUTO = 0,        /* the autotuner times both methods per shape and keeps the faster */
     PX_TAPPLY_ON_THE_FLY = 1,  /* T generated in registers by the hand-written kernels */
-    PX_TAPPLY_STORED = 2       /* dense T stored once per structure, one GEMM per apply */
+    PX_TAPPLY_STORED = 2       /* dense T stored once per structure, one hand-written product per apply */
 } pxTApply;
 
 typedef enum {
@@ -154,7 +154,12 @@ typedef struct {
  *                    device memory) the first time a (model, atoms, columns,
  *                    precision) shape occurs in the process, and keeps the
  *                    faster; PX_TAPPLY_ON_THE_FLY / PX_TAPPLY_STORED force one
- *                    (STORED fails with PX_E_OOM if T does not fit).
+ *                    (STORED fails with PX_E_OOM if T does not fit).  Under
+ *                    AUTO a stored FP64 T above 256 MiB is not tried for the
+ *                    narrow (1-8 column) apply of the shared phase, and a
+ *                    solve's first true residual builds no dense T unless a
+ *                    block kept from an earlier solve serves it (or, once per
+ *                    new shape up to 4 GiB, to tune it).
  *                    The stacked block of pxSolveBatch and the server always
  *                    generates T on the fly.
  *   shifted          pxSolveSpectrum on a one-material PX_WFQ structure: 1
@@ -165,6 +170,8 @@ typedef struct {
  *                    operator, so all frequencies share one Krylov space);
  *                    columns it leaves above rel_tol continue in the blocked
  *                    solver from its iterate (the phase counts as one cycle).
+ *                    A pair stops once its GMRES residual estimate is below
+ *                    0.9 rel_tol.
  *                    2 (default): one block Arnoldi process over the polarizations
  *                    instead (2 or 3 polarizations with non-zero right-hand
  *                    sides, else as 1): the block Krylov space of all
