@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg may import this package; the GPU library and its Python
 binding never do.  The C source, px_oracle.c, follows the paper's equations
-step by step (Sections 2.1, 2.2, 6 and 7) with a dense build and its own LU.
+step by step (Sections 2.1, 2.2, 2.3, 6 and 7) with a dense build and its own LU.
 
 Conventions of this wrapper:
   * coordinates in Angstrom, frequencies in eV, parameters as the flat vector
@@ -77,6 +77,12 @@ def _load():
     lib.or_bem_solve_spectrum.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, ctypes.c_uint32,
                                           ctypes.c_double, dp, dp, dp]
     lib.or_bem_solve_spectrum.restype = i64
+    lib.or_bem_ief_matrices.argtypes = [i64, dp, dp, dp, ctypes.c_double, dp, dp]
+    lib.or_bem_ief_rhs.argtypes = [i64, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
+    lib.or_bem_ief_apply.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, dp]
+    lib.or_bem_ief_solve_spectrum.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, ctypes.c_uint32,
+                                              ctypes.c_double, dp, dp, dp]
+    lib.or_bem_ief_solve_spectrum.restype = i64
     _lib = lib
     return lib
 
@@ -364,4 +370,52 @@ def bem_solve_spectrum(m, omega_ev, eps2, eps1, pol_mask, e0):
     st = _load().or_bem_solve_spectrum(n, _d(cen), _d(nrm), _d(area), r, nw, _d(om), _d(_cplx(eps2, nw)),
                                        _d(_cplx(eps1, 1)), int(pol_mask), float(e0), _d(q.view(np.float64)),
                                        _d(alpha.view(np.float64)), _d(sigma))
+    return dict(q=q, alpha=alpha, sigma=sigma, status=int(st))
+
+
+# ---- BEM, IEFPCM (Section 2.3, Eq. bem-iefpcm) -------------------------------
+# The same mesh dicts; S (bohr) and F (dimensionless) are the paper's matrices
+# (F's diagonal read as the double layer's self patch, -S_ii / 2R).
+
+def bem_ief_matrices(m):
+    """(S, F) as dense [n, n] arrays."""
+    n, cen, nrm, area, r = _mesh(m)
+    s = np.zeros((n, n))
+    f = np.zeros((n, n))
+    _load().or_bem_ief_matrices(n, _d(cen), _d(nrm), _d(area), r, _d(s), _d(f))
+    return s, f
+
+
+def bem_ief_rhs(m, pol, e0):
+    """-(2 pi I + F) V with V_i = -E0 s_i,pol: [n] complex."""
+    n, cen, nrm, area, r = _mesh(m)
+    b = np.zeros(n, dtype=np.complex128)
+    _load().or_bem_ief_rhs(n, _d(cen), _d(nrm), _d(area), r, int(pol), float(e0), _d(b.view(np.float64)))
+    return b
+
+
+def bem_ief_apply(m, eps2, eps1, x):
+    """y_c = [2 pi f(eps2_c) I + F] x_c; x: [ncol, n] complex, eps2: [ncol]."""
+    n, cen, nrm, area, r = _mesh(m)
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.complex128)
+    ncol = x.shape[0]
+    y = np.zeros_like(x)
+    _load().or_bem_ief_apply(n, _d(cen), _d(nrm), _d(area), r, ncol, _d(_cplx(eps2, ncol)), _d(_cplx(eps1, 1)),
+                             _d(x.view(np.float64)), _d(y.view(np.float64)))
+    return y
+
+
+def bem_ief_solve_spectrum(m, omega_ev, eps2, eps1, pol_mask, e0):
+    """Direct-solve IEFPCM spectrum.  Returns dict(q=[n_omega, n_pol, n]
+    tessera charges, alpha=[n_omega, 3, 3], sigma=[n_omega] bohr^2, status)."""
+    n, cen, nrm, area, r = _mesh(m)
+    om = np.ascontiguousarray(omega_ev, dtype=np.float64)
+    nw = len(om)
+    npol = bin(pol_mask & 7).count("1")
+    q = np.zeros((nw, npol, n), dtype=np.complex128)
+    alpha = np.zeros((nw, 3, 3), dtype=np.complex128)
+    sigma = np.zeros(nw)
+    st = _load().or_bem_ief_solve_spectrum(n, _d(cen), _d(nrm), _d(area), r, nw, _d(om), _d(_cplx(eps2, nw)),
+                                           _d(_cplx(eps1, 1)), int(pol_mask), float(e0), _d(q.view(np.float64)),
+                                           _d(alpha.view(np.float64)), _d(sigma))
     return dict(q=q, alpha=alpha, sigma=sigma, status=int(st))
