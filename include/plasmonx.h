@@ -269,6 +269,28 @@ pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* x
 pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
                      double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out);
 
+/* Creates a BEM structure in the IEFPCM formulation (Section 2.3, Eq.
+ * bem-iefpcm, the "approximate" F), with the arguments, ownership and errors
+ * of pxCreateBem.  The paper's matrices, for the tessera charges q:
+ *   [ 2 pi f I + F ] S A^-1 q = -(2 pi I + F) V,  f = (eps2 + eps1) / (eps2 - eps1),
+ *   S_ij = A_j / |s_i - s_j|, S_ii = 1.0694 sqrt(4 pi A_i),
+ *   F_ij = A_j (s_i - s_j).n_j / |s_i - s_j|^3, F_ii = -1.0694 sqrt(4 pi A_i) / (2R),
+ *   V_i = -E0 s_i,l (the applied field's potential; the caller's origin).
+ * F's diagonal is the double layer's self patch on a sphere (negative; the
+ * printed positive value belongs to the DPCM operator).  The solver's unknown
+ * is the potential y = S A^-1 q of every column, from [F - z I] y = b with
+ * z = -2 pi f, so pxSolveSpectrum (shifted >= 1) runs the shared-Krylov
+ * phase as for DPCM, rel_tol and pxGetSolveStats refer to this system, and
+ * pxApplyOperator / pxApplyOperatorNoAlloc apply y -> [F + 2 pi f I] y.  The
+ * creation also solves S A^-1 w_k = s_k (k = x, y, z; conjugate gradients to
+ * 1e-12) so that d_k = w_k . y without the charges (S A^-1 is symmetric);
+ * pxGetCharges solves S A^-1 q = y for its column the same way (one solve per
+ * call, PX_E_NOTCONV if it stalls).  Extra errors: PX_E_NOTCONV if the
+ * creation's solve does not converge, PX_E_INVALID if S A^-1 is not positive
+ * definite on the mesh. */
+pxStatus pxCreateBemIefpcm(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                           double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out);
+
 /* Sets the frequency grid (omega_ev[n_omega], > 0, copied), the polarizations
  * (pol_mask bit0 = x, bit1 = y, bit2 = z; one column per set bit and
  * frequency, frequency-major) and the field amplitude e0_au (> 0; the paper

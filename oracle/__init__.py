@@ -80,6 +80,7 @@ def _load():
     lib.or_bem_ief_matrices.argtypes = [i64, dp, dp, dp, ctypes.c_double, dp, dp]
     lib.or_bem_ief_rhs.argtypes = [i64, dp, dp, dp, ctypes.c_double, ctypes.c_int, ctypes.c_double, dp]
     lib.or_bem_ief_apply.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, dp]
+    lib.or_bem_ief_potential.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp]
     lib.or_bem_ief_solve_spectrum.argtypes = [i64, dp, dp, dp, ctypes.c_double, i64, dp, dp, dp, ctypes.c_uint32,
                                               ctypes.c_double, dp, dp, dp]
     lib.or_bem_ief_solve_spectrum.restype = i64
@@ -402,6 +403,17 @@ def bem_ief_apply(m, eps2, eps1, x):
     y = np.zeros_like(x)
     _load().or_bem_ief_apply(n, _d(cen), _d(nrm), _d(area), r, ncol, _d(_cplx(eps2, ncol)), _d(_cplx(eps1, 1)),
                              _d(x.view(np.float64)), _d(y.view(np.float64)))
+    return y
+
+
+def bem_ief_potential(m, q):
+    """y_c = S A^-1 q_c, the potential of the charges at the barycentres;
+    q: [ncol, n] complex."""
+    n, cen, nrm, area, r = _mesh(m)
+    q = np.ascontiguousarray(np.atleast_2d(q), dtype=np.complex128)
+    y = np.zeros_like(q)
+    _load().or_bem_ief_potential(n, _d(cen), _d(nrm), _d(area), r, q.shape[0], _d(q.view(np.float64)),
+                                 _d(y.view(np.float64)))
     return y
 
 

@@ -1273,6 +1273,29 @@ void or_bem_ief_rhs(int64_t n, const double* cen_ang, const double* nrm, const d
     bem_free(&b);
 }
 
+/* The potential of the charges at the barycentres, y_c = S A^-1 q_c, for ncol
+ * complex columns (q, y: [ncol][n] interleaved complex). */
+void or_bem_ief_potential(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,
+                          double r_enc_ang, int64_t ncol, const double* q, double* y)
+{
+    bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    for (int64_t c = 0; c < ncol; ++c) {
+        const double* qc = q + 2 * c * n;
+        double* yc = y + 2 * c * n;
+        for (int64_t i = 0; i < n; ++i) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                double sij = ief_s(&b, i, j) / b.a[j];
+                sr += sij * qc[2 * j];
+                si += sij * qc[2 * j + 1];
+            }
+            yc[2 * i] = sr;
+            yc[2 * i + 1] = si;
+        }
+    }
+    bem_free(&b);
+}
+
 /* The left factor of Eq. (bem-iefpcm) applied to ncol complex columns:
  * y_c = [2 pi f(eps2_c) I + F] x_c (x, y: [ncol][n] interleaved complex). */
 void or_bem_ief_apply(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,

@@ -29,7 +29,7 @@ EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHete
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
             "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc", "pxCreateBem",
-            "pxSetAllocator", "pxReleaseCache"]
+            "pxCreateBemIefpcm", "pxSetAllocator", "pxReleaseCache"]
 
 
 class PxError(RuntimeError):
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.pxServerQuery.argtypes = [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64),
                                   ctypes.POINTER(i64)]
     lib.pxCreateBem.argtypes = [i64, _dp, _dp, _dp, ctypes.c_double, _dp, _vp, ctypes.POINTER(_vp)]
+    lib.pxCreateBemIefpcm.argtypes = [i64, _dp, _dp, _dp, ctypes.c_double, _dp, _vp, ctypes.POINTER(_vp)]
     lib.pxApplyOperatorNoAlloc.argtypes = [_vp, i32, _dp, _dp, _vp, _vp]
     lib.pxServerMemory.argtypes = [_vp, _dp, _dp, ctypes.POINTER(i32)]
     lib.pxSolveFootprint.argtypes = [_vp, ctypes.POINTER(pxSolveOptions), _dp]
@@ -229,15 +230,30 @@ def pxCreateStructureHetero(model, xyz_ang, types, mat_a, mat_b, hip_stream=None
     return h
 
 
-def pxCreateBem(mesh, eps_env=1.0, hip_stream=None):
-    """BEM structure from a mesh dict (cen, nrm, area in Angstrom units, r_enc)."""
+def _bem_args(mesh, eps_env):
     cen = np.ascontiguousarray(mesh["cen"], dtype=np.float64).reshape(-1, 3)
     nrm = np.ascontiguousarray(mesh["nrm"], dtype=np.float64).reshape(-1, 3)
     area = np.ascontiguousarray(mesh["area"], dtype=np.float64).reshape(-1)
     e1 = np.array([complex(eps_env).real, complex(eps_env).imag])
+    return cen, nrm, area, e1
+
+
+def pxCreateBem(mesh, eps_env=1.0, hip_stream=None):
+    """BEM (DPCM) structure from a mesh dict (cen, nrm, area in Angstrom
+    units, r_enc)."""
+    cen, nrm, area, e1 = _bem_args(mesh, eps_env)
     h = _vp()
     _check(load().pxCreateBem(len(area), _ptr(cen), _ptr(nrm), _ptr(area), float(mesh["r_enc"]), _ptr(e1), hip_stream,
                               ctypes.byref(h)))
+    return h
+
+
+def pxCreateBemIefpcm(mesh, eps_env=1.0, hip_stream=None):
+    """BEM (IEFPCM) structure from a mesh dict, as pxCreateBem."""
+    cen, nrm, area, e1 = _bem_args(mesh, eps_env)
+    h = _vp()
+    _check(load().pxCreateBemIefpcm(len(area), _ptr(cen), _ptr(nrm), _ptr(area), float(mesh["r_enc"]), _ptr(e1),
+                                    hip_stream, ctypes.byref(h)))
     return h
 
 
@@ -496,11 +512,15 @@ class Structure:
     alpha_ib arguments then hold (alpha_IB of A, alpha_IB of B) per frequency
     or column, shape (n, 2)."""
 
-    def __init__(self, model, xyz_ang, params, hip_stream=None, types=None, params_b=None, mesh=None, eps_env=1.0):
+    def __init__(self, model, xyz_ang, params, hip_stream=None, types=None, params_b=None, mesh=None, eps_env=1.0,
+                 bem_form="dpcm"):
         self.model = int(model)
         self.het = types is not None
         if self.model == PX_BEM:
-            self.h = pxCreateBem(mesh, eps_env, hip_stream)
+            if bem_form not in ("dpcm", "iefpcm"):
+                raise ValueError("bem_form is 'dpcm' or 'iefpcm'")
+            create = pxCreateBemIefpcm if bem_form == "iefpcm" else pxCreateBem
+            self.h = create(mesh, eps_env, hip_stream)
         elif self.het:
             self.h = pxCreateStructureHetero(model, xyz_ang, types, params, params_b, hip_stream)
         else:
@@ -510,10 +530,11 @@ class Structure:
         self.ncol = 0
 
     @classmethod
-    def bem(cls, mesh, eps_env=1.0, hip_stream=None):
-        """A BEM (DPCM) structure on a mesh dict (workloads.mesh); its
-        set_frequencies takes eps2(w) per frequency as alpha_ib."""
-        return cls(PX_BEM, None, None, hip_stream, mesh=mesh, eps_env=eps_env)
+    def bem(cls, mesh, eps_env=1.0, hip_stream=None, form="dpcm"):
+        """A BEM structure on a mesh dict (workloads.mesh) in the DPCM or the
+        IEFPCM form; its set_frequencies takes eps2(w) per frequency as
+        alpha_ib."""
+        return cls(PX_BEM, None, None, hip_stream, mesh=mesh, eps_env=eps_env, bem_form=form)
 
     def set_frequencies(self, omega_ev, pol_mask, e0_au=1e-4, alpha_ib=None):
         pxSetFrequencies(self.h, omega_ev, pol_mask, e0_au, alpha_ib)

@@ -40,6 +40,11 @@ thread_local std::string g_err;
 
 int pad_cols(int na, bool narrow_ok) { return (narrow_ok && na <= 4) ? na : ((na + px::COL_PAD - 1) / px::COL_PAD) * px::COL_PAD; }
 
+// An IEFPCM column's charges from its potentials: conjugate gradients on
+// S A^-1 to this relative residual.
+constexpr double kChargeSolveTol = 1e-12;
+constexpr int kChargeSolveMaxIter = 20000;
+
 }  // namespace
 
 namespace pxs {
@@ -72,12 +77,24 @@ void shift_bem(double e2r, double e2i, double e1r, double e1i, double& zr, doubl
     zi = 2.0 * PI * (ni * dr - nr * di) / den;
 }
 
+// The shift z of a BEM structure's operator M - z I (DPCM, Eq. bem-dpcm) or
+// F - z I (IEFPCM, Eq. bem-iefpcm: z = -2 pi (eps2 + eps1) / (eps2 - eps1))
+// for the metal permittivity e2 (interleaved complex).
+void shift_bem_of(const pxStructure_t* s, const double* e2, double& zr, double& zi)
+{
+    shift_bem(e2[0], e2[1], s->eps1[0], s->eps1[1], zr, zi);
+    if (s->g.bem_ief) {
+        zr = -zr;
+        zi = -zi;
+    }
+}
+
 // The charge-row shift of frequency w: z_q(w) of Eq. (z_q_wfq), or for a BEM
-// structure the shift of Eq. (bem-dpcm) with the metal permittivity eps2(w)
-// given with the frequencies.
+// structure the shift above with the metal permittivity eps2(w) given with
+// the frequencies.
 void shift_of(const pxStructure_t* s, int w, double& zr, double& zi)
 {
-    if (s->model == PX_BEM) shift_bem(s->aib[2 * w], s->aib[2 * w + 1], s->eps1[0], s->eps1[1], zr, zi);
+    if (s->model == PX_BEM) shift_bem_of(s, &s->aib[2 * w], zr, zi);
     else shift_q(s->drude, s->mat.tau, s->omega_au[w], zr, zi);
 }
 
@@ -1695,8 +1712,10 @@ pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* x
     return create_impl(model, n_atoms, xyz_ang, types, mat_a, mat_b, hip_stream, out);
 }
 
-pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
-                     double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out)
+namespace {
+
+pxStatus create_bem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                    double r_enc_ang, const double* eps_env, void* hip_stream, bool ief, pxStructure* out)
 {
     g_err.clear();
     if (!out || !cen_ang || !normals || !area_ang2) return fail(PX_E_INVALID, "null argument");
@@ -1732,7 +1751,10 @@ pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normal
         std::vector<double> cb(3 * n_tess), ab(n_tess);
         for (int64_t i = 0; i < 3 * n_tess; ++i) cb[i] = cen_ang[i] / ANG_PER_BOHR;
         for (int64_t i = 0; i < n_tess; ++i) ab[i] = area_ang2[i] / (ANG_PER_BOHR * ANG_PER_BOHR);
-        HC(px::build_bem_geometry(s->g, cb.data(), normals, ab.data(), r_enc_ang / ANG_PER_BOHR, s->st));
+        int cg = 0;
+        HC(px::build_bem_geometry(s->g, cb.data(), normals, ab.data(), r_enc_ang / ANG_PER_BOHR, ief, s->st, &cg));
+        if (cg == 2) return fail(PX_E_INVALID, "S A^-1 is not positive definite on this mesh");
+        if (cg == 1) return fail(PX_E_NOTCONV, "the single-layer solve for the dipole weights did not converge");
         s->perm.resize(n_tess);
         for (int64_t i = 0; i < n_tess; ++i) s->perm[i] = (int32_t)i;
         s->d_perm = dalloc<int32_t>(n_tess);
@@ -1741,6 +1763,20 @@ pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normal
         *out = s.release();
         return PX_OK;
     });
+}
+
+}  // namespace
+
+pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                     double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out)
+{
+    return create_bem(n_tess, cen_ang, normals, area_ang2, r_enc_ang, eps_env, hip_stream, false, out);
+}
+
+pxStatus pxCreateBemIefpcm(int64_t n_tess, const double* cen_ang, const double* normals, const double* area_ang2,
+                           double r_enc_ang, const double* eps_env, void* hip_stream, pxStructure* out)
+{
+    return create_bem(n_tess, cen_ang, normals, area_ang2, r_enc_ang, eps_env, hip_stream, true, out);
 }
 
 pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev, uint32_t pol_mask, double e0_au,
@@ -1924,6 +1960,23 @@ pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, do
     for (int l = 0; l < pol; ++l)
         if (s->pol_mask & (1u << l)) ++p;
     const int col = i_omega * s->npol + p;
+    if (s->g.bem_ief) {
+        // the charges of an IEFPCM column: (S A^-1) q = y, the real and
+        // imaginary parts as two real columns
+        return guarded([&]() -> pxStatus {
+            const int64_t np = s->g.np;
+            double* qd = dalloc<double>((size_t)2 * np);
+            int cg = 0;
+            HC(px::bem_single_layer_solve(s->g, reinterpret_cast<const double*>(s->x) + 2 * col, 2 * s->ldg, 2, qd,
+                                          kChargeSolveTol, kChargeSolveMaxIter, s->st, &cg, nullptr, nullptr));
+            HC(hipMemcpyAsync(q, qd, sizeof(double2) * s->g.n, hipMemcpyDeviceToHost, s->st));
+            HC(hipStreamSynchronize(s->st));
+            dfree(qd);
+            if (cg == 2) return fail(PX_E_INVALID, "S A^-1 is not positive definite on this mesh");
+            if (cg == 1) return fail(PX_E_NOTCONV, "the single-layer solve for the charges did not converge");
+            return PX_OK;
+        });
+    }
     return guarded([&]() -> pxStatus {
         const int ncomp = s->model == PX_WFQFMU ? 4 : 1;
         double2* d = dalloc<double2>((size_t)ncomp * s->g.n);
@@ -2115,7 +2168,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
                 continue;
             }
             double zr, zi;
-            if (s->model == PX_BEM) shift_bem(alpha_ib[2 * c], alpha_ib[2 * c + 1], s->eps1[0], s->eps1[1], zr, zi);
+            if (s->model == PX_BEM) shift_bem_of(s, alpha_ib + 2 * c, zr, zi);
             else shift_q(s->drude, s->mat.tau, w, zr, zi);
             zq[c] = make_double2(zr, zi);
             if (a) {
@@ -2199,7 +2252,7 @@ pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega
                 continue;
             }
             double zr, zi;
-            if (s->model == PX_BEM) shift_bem(alpha_ib[2 * c], alpha_ib[2 * c + 1], s->eps1[0], s->eps1[1], zr, zi);
+            if (s->model == PX_BEM) shift_bem_of(s, alpha_ib + 2 * c, zr, zi);
             else shift_q(s->drude, s->mat.tau, wv, zr, zi);
             h[c] = make_double2(zr, zi);
             if (a) {

@@ -1,19 +1,33 @@
-// BEM in the DPCM formulation (plasmonX paper, Section 2.3, Eq. bem-dpcm, the
-// "approximate" F): the surface of the nanostructure is a mesh of tesserae
-// (barycentre s_i, outward unit normal n_i, area A_i); the unknowns are the
-// tessera charges q_i (Section 7: d = sum_i q_i s_i) and the system is
+// BEM (plasmonX paper, Section 2.3, the "approximate" F): the surface of the
+// nanostructure is a mesh of tesserae (barycentre s_i, outward unit normal
+// n_i, area A_i).
+//
+// DPCM (Eq. bem-dpcm), read for the tessera charges q_i (Section 7:
+// d = sum_i q_i s_i):
 //     [ M - z(w) I ] q = -A E_n,    z(w) = 2 pi (eps2 + eps1) / (eps2 - eps1),
 //     M_ij = A_i (s_i - s_j) . n_i / |s_i - s_j|^3   (i != j),
 //     M_ii = 1.0694 sqrt(4 pi A_i) / (2 R),  R the radius enclosing the mesh.
-// M is real and shared by every frequency, so the structure runs through the
-// omegaFQ solver with the tesserae as its sites, the identity in place of
-// Kbar, M in place of T and z(w) in place of z_q(w): the shared-Krylov phase
-// (one Arnoldi process per polarization for every frequency), the blocked
-// solver's true FP64 residuals and the observables are the same code.
+// IEFPCM (Eq. bem-iefpcm) with the unknown y = S A^-1 q, the potential the
+// charges make at the barycentres:
+//     [ F - z(w) I ] y = -(2 pi I + F) V,   z(w) = -2 pi (eps2 + eps1) / (eps2 - eps1),
+//     F_ij = A_j (s_i - s_j) . n_j / |s_i - s_j|^3   (i != j),
+//     F_ii = -1.0694 sqrt(4 pi A_i) / (2 R)   (the double layer's self patch),
+//     V_i = -E0 s_i,l,  then q = (S A^-1)^-1 y with
+//     (S A^-1)_ij = 1 / |s_i - s_j|,  (S A^-1)_ii = 1.0694 sqrt(4 pi / A_i).
+// S A^-1 is symmetric, so the dipole needs no charges: d_k = s_k . q =
+// w_k . y with w_k = (S A^-1)^-1 s_k, three real solves per mesh.
+// M and F are real and shared by every frequency, so the structure runs
+// through the omegaFQ solver with the tesserae as its sites, the identity in
+// place of Kbar, M or F in place of T and z(w) in place of z_q(w): the
+// shared-Krylov phase (one Arnoldi process per polarization for every
+// frequency), the blocked solver's true FP64 residuals and the observables
+// are the same code.
 //
-// The M-apply is generated on the fly in FP64 (M is not symmetric and not
-// stored): one thread per row i, the source tesserae read wave-uniform
-// (through the scalar cache) in source splits, a deterministic split sum.
+// The operators are generated on the fly in FP64 (M and F are not symmetric
+// and not stored): one thread per row i, the source tesserae read
+// wave-uniform (through the scalar cache) in source splits, a deterministic
+// split sum.  The single-layer solves are Jacobi-preconditioned conjugate
+// gradients with every scalar kept on the device.
 #include "px_internal.h"
 
 #include <hip/hip_ext.h>
@@ -30,6 +44,8 @@ constexpr double BEM_SELF = 1.0694;   // self-patch factor of the approximate F 
 constexpr int BEM_ROWS = 256;         // rows per workgroup
 constexpr int BEM_UNIT = 256;         // sources per split unit
 constexpr int BEM_NC = 8;             // real columns per launch (wider blocks: several launches)
+constexpr double kSingleLayerTol = 1e-12;   // the dipole weights' solve
+constexpr int kSingleLayerMaxIter = 20000;
 
 // 2 / sqrt(q) for q > 0: the hardware estimate and one Newton step (the caller
 // applies the factor 1/2, cubed, to its sums).
@@ -39,11 +55,13 @@ __device__ __forceinline__ double rsqrt2_pos(double q)
     return y * fma(-q, y * y, 3.0);
 }
 
-// Split y of row block x: part[y][i][c] = A_i sum_j (s_i - s_j).n_i / r^3 X[j][c0 + c]
-// over the source units y, y + nsplit, ... (the self pair excluded), plus the
-// diagonal M_ii X[i][c0 + c] in split 0.  s, na: [np] (x, y, z, -) and
-// (n_x, n_y, n_z, A); ghost tesserae have A = 0 and zero columns of X.
-template <int NC>
+// Split y of row block x: part[y][i][c] = sum_j K_ij X[j][c0 + c] over the
+// source units y, y + nsplit, ... (the self pair excluded), plus the diagonal
+// K_ii X[i][c0 + c] in split 0, for K = M (MODE 0), F (MODE 1) or S A^-1
+// (MODE 2).  s, na: [np] (x, y, z, -) and (n_x, n_y, n_z, A); ghost
+// tesserae have A = 0: zero rows and columns of M and F, identity rows and
+// zero columns of S A^-1.
+template <int MODE, int NC>
 __global__ __launch_bounds__(BEM_ROWS) void k_bem_apply(const double4* __restrict__ s, const double4* __restrict__ na,
                                                       const double* __restrict__ X, int ldx, int c0,
                                                       double* __restrict__ part, int np, double inv_2r,
@@ -66,22 +84,42 @@ __global__ __launch_bounds__(BEM_ROWS) void k_bem_apply(const double4* __restric
             const double4 sj = s[j];
             const double dx = si.x - sj.x, dy = si.y - sj.y, dz = si.z - sj.z;
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const double dn = fma(dx, ni.x, fma(dy, ni.y, dz * ni.z));
             const double y = rsqrt2_pos(self && j == i ? 1.0 : r2);
-            double t = dn * (y * y * y);
+            double t;
+            if (MODE == 0) {
+                const double dn = fma(dx, ni.x, fma(dy, ni.y, dz * ni.z));
+                t = dn * (y * y * y);
+            } else if (MODE == 1) {
+                const double4 nj = na[j];
+                const double dn = fma(dx, nj.x, fma(dy, nj.y, dz * nj.z));
+                t = nj.w * dn * (y * y * y);
+            } else {
+                t = na[j].w > 0.0 ? y : 0.0;
+            }
             if (self && j == i) t = 0.0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)j * ldx + c0 + c], acc[c]);
         }
     }
-    // (2 / r)^3 = 8 / r^3: the factor 1/8, the row's area, and the diagonal once
-    const double w = 0.125 * ni.w;
+    // 2 / r: the factor 1/2 (S A^-1), (2 / r)^3 = 8 / r^3: 1/8 (M, F); the
+    // row's area (M) or ghost mask (F, S A^-1), and the diagonal once
+    const bool real_row = ni.w > 0.0;
+    double w, kii;
+    if (MODE == 0) {
+        w = 0.125 * ni.w;
+        kii = BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
+    } else if (MODE == 1) {
+        w = real_row ? 0.125 : 0.0;
+        kii = -BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
+    } else {
+        w = real_row ? 0.5 : 0.0;
+        kii = real_row ? BEM_SELF * sqrt(4.0 * M_PI / ni.w) : 1.0;
+    }
     double* out = part + (size_t)blockIdx.y * np * NC + (size_t)i * NC;
-    const double mii = BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double v = w * acc[c];
-        if (blockIdx.y == 0) v = fma(mii, X[(size_t)i * ldx + c0 + c], v);
+        if (blockIdx.y == 0) v = fma(kii, X[(size_t)i * ldx + c0 + c], v);
         out[c] = v;
     }
 }
@@ -106,21 +144,243 @@ __global__ void k_bem_sum(const double* __restrict__ part, int nsplit, int np, i
     Y[(size_t)i * ldy + c0 + c] = s0 + s1;
 }
 
-// b[i][c] = -A_i E0 n_i,l for column c of polarization l = col_pol[c].
-__global__ void k_bem_rhs(const double4* __restrict__ na, const int32_t* __restrict__ col_pol, double e0,
-                          double2* __restrict__ b, int64_t n, int64_t np, int ncol, int ldb)
+// b[i][c] for column c of polarization l = col_pol[c]: -A_i E0 n_i,l (DPCM,
+// rv = null) or E0 rv_i,l with rv = 2 pi s + F s (IEFPCM: -(2 pi I + F) V
+// for V = -E0 s_l).
+__global__ void k_bem_rhs(const double4* __restrict__ na, const double4* __restrict__ rv,
+                          const int32_t* __restrict__ col_pol, double e0, double2* __restrict__ b, int64_t n,
+                          int64_t np, int ncol, int ldb)
 {
     const int c = blockIdx.y * 64 + (threadIdx.x & 63);
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= np || c >= ldb) return;
     double v = 0.0;
     if (i < n && c < ncol) {
-        const double4 a = na[i];
         const int l = col_pol[c];
-        const double nl = l == 0 ? a.x : (l == 1 ? a.y : a.z);
-        v = -a.w * e0 * nl;
+        if (rv) {
+            const double4 a = rv[i];
+            v = e0 * (l == 0 ? a.x : (l == 1 ? a.y : a.z));
+        } else {
+            const double4 a = na[i];
+            const double nl = l == 0 ? a.x : (l == 1 ? a.y : a.z);
+            v = -a.w * e0 * nl;
+        }
     }
     b[(size_t)i * ldb + c] = make_double2(v, 0.0);
+}
+
+// rv_i = 2 pi s_i + (F s)_i over the real tesserae, 0 for ghosts (fs holds F s).
+__global__ void k_bem_ief_rv(const double4* __restrict__ s, const double4* __restrict__ na, double4* __restrict__ fs,
+                             int64_t np)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const double4 p = s[i], f = fs[i];
+    const double tp = 2.0 * M_PI;
+    fs[i] = na[i].w > 0.0 ? make_double4(fma(tp, p.x, f.x), fma(tp, p.y, f.y), fma(tp, p.z, f.z), 0.0)
+                          : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
+// ---- conjugate gradients on S A^-1 -----------------------------------------
+// Vectors [np][nc] (nc <= CG_NC); per-column scalars on the device; the
+// partial sums of each dot product over blocks of CG_ROWS rows are reduced
+// in a fixed order, so the iteration is deterministic.
+constexpr int CG_NC = 8;
+constexpr int CG_ROWS = 256;
+
+struct CgState {
+    double rz[CG_NC], bb[CG_NC], rr[CG_NC], alpha[CG_NC], beta[CG_NC];
+    int32_t active[CG_NC];
+    int32_t n_active, breakdown;
+};
+
+__device__ __forceinline__ double jacobi_inv(double a)
+{
+    // 1 / (S A^-1)_ii for a real tessera, 1 for a ghost (identity row)
+    return a > 0.0 ? 1.0 / (BEM_SELF * sqrt(4.0 * M_PI / a)) : 1.0;
+}
+
+// Sum of v over the CG_ROWS threads of the block; every thread gets it.
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < CG_ROWS / 64; ++k) s += lds[k];
+    return s;
+}
+
+// r = B - Q (Q = S A^-1 x, or null for x = 0), z = D^-1 r, p = z; partial
+// sums of r.z and r.r per column into part[block][2][CG_NC]; x = 0 when Q is
+// null.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_start(const double* __restrict__ B, int ldb, const double* __restrict__ Q,
+                                                    const double4* __restrict__ na, int64_t np, int nc,
+                                                    double* __restrict__ x, double* __restrict__ r,
+                                                    double* __restrict__ z, double* __restrict__ p,
+                                                    double* __restrict__ part)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    const int64_t i = (int64_t)blockIdx.x * CG_ROWS + threadIdx.x;
+    const double a = na[i].w, dinv = jacobi_inv(a);
+    for (int c = 0; c < nc; ++c) {
+        const size_t o = (size_t)i * nc + c;
+        const double b = a > 0.0 ? B[(size_t)i * ldb + c] : 0.0;
+        const double rv = Q ? b - Q[o] : b;
+        if (!Q) x[o] = 0.0;
+        const double zv = dinv * rv;
+        r[o] = rv;
+        z[o] = zv;
+        p[o] = zv;
+        const double s_rz = block_sum(rv * zv, lds);
+        const double s_rr = block_sum(rv * rv, lds);
+        if (threadIdx.x == 0) {
+            part[((size_t)blockIdx.x * 2 + 0) * CG_NC + c] = s_rz;
+            part[((size_t)blockIdx.x * 2 + 1) * CG_NC + c] = s_rr;
+        }
+    }
+}
+
+// Column c's total of part[.][k][c] over nblk blocks (fixed order), for
+// every thread of the block.
+__device__ double part_total(const double* __restrict__ part, int nblk, int k, int c, double* lds)
+{
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += CG_ROWS) s += part[((size_t)b * 2 + k) * CG_NC + c];
+    return block_sum(s, lds);
+}
+
+// After k_cg_start: rz, rr (and ||B||^2 on the first start), the active set.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_begin(const double* __restrict__ part, int nblk, int nc, double tol2,
+                                                    int first, CgState* __restrict__ cs)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    int na = 0;
+    for (int c = 0; c < nc; ++c) {
+        const double rz = part_total(part, nblk, 0, c, lds);
+        const double rr = part_total(part, nblk, 1, c, lds);
+        if (threadIdx.x == 0) {
+            if (first) cs->bb[c] = rr;
+            cs->rz[c] = rz;
+            cs->rr[c] = rr;
+            cs->alpha[c] = cs->beta[c] = 0.0;
+            const int act = cs->bb[c] > 0.0 && rr > tol2 * cs->bb[c];
+            cs->active[c] = act;
+            na += act;
+        }
+    }
+    if (threadIdx.x == 0) {
+        cs->n_active = na;
+        if (first) cs->breakdown = 0;
+    }
+}
+
+// partial sums of p.q per column into part[block][0][CG_NC]
+__global__ __launch_bounds__(CG_ROWS) void k_cg_pq(const double* __restrict__ p, const double* __restrict__ q, int nc,
+                                                 double* __restrict__ part)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    const int64_t i = (int64_t)blockIdx.x * CG_ROWS + threadIdx.x;
+    for (int c = 0; c < nc; ++c) {
+        const size_t o = (size_t)i * nc + c;
+        const double s = block_sum(p[o] * q[o], lds);
+        if (threadIdx.x == 0) part[((size_t)blockIdx.x * 2) * CG_NC + c] = s;
+    }
+}
+
+// alpha = r.z / p.q for the active columns (0 for the others); a
+// non-positive p.q on an active column flags a breakdown.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_alpha(const double* __restrict__ part, int nblk, int nc,
+                                                    CgState* __restrict__ cs)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    for (int c = 0; c < nc; ++c) {
+        const double pq = part_total(part, nblk, 0, c, lds);
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            if (cs->active[c]) {
+                if (pq > 0.0) a = cs->rz[c] / pq;
+                else cs->breakdown = 1;
+            }
+            cs->alpha[c] = a;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q, z = D^-1 r; partial sums of r.z and r.r.
+__global__ __launch_bounds__(CG_ROWS) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ z, const double* __restrict__ p,
+                                                     const double* __restrict__ q, const double4* __restrict__ na,
+                                                     int nc, const CgState* __restrict__ cs,
+                                                     double* __restrict__ part)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    const int64_t i = (int64_t)blockIdx.x * CG_ROWS + threadIdx.x;
+    const double dinv = jacobi_inv(na[i].w);
+    for (int c = 0; c < nc; ++c) {
+        const size_t o = (size_t)i * nc + c;
+        const double a = cs->alpha[c];
+        x[o] = fma(a, p[o], x[o]);
+        const double rv = fma(-a, q[o], r[o]);
+        const double zv = dinv * rv;
+        r[o] = rv;
+        z[o] = zv;
+        const double s_rz = block_sum(rv * zv, lds);
+        const double s_rr = block_sum(rv * rv, lds);
+        if (threadIdx.x == 0) {
+            part[((size_t)blockIdx.x * 2 + 0) * CG_NC + c] = s_rz;
+            part[((size_t)blockIdx.x * 2 + 1) * CG_NC + c] = s_rr;
+        }
+    }
+}
+
+// beta = new r.z / old r.z; columns whose ||r|| <= tol ||B|| leave the
+// active set (alpha = beta = 0 from then on).
+__global__ __launch_bounds__(CG_ROWS) void k_cg_beta(const double* __restrict__ part, int nblk, int nc, double tol2,
+                                                   CgState* __restrict__ cs)
+{
+    __shared__ double lds[CG_ROWS / 64];
+    int na = 0;
+    for (int c = 0; c < nc; ++c) {
+        const double rz = part_total(part, nblk, 0, c, lds);
+        const double rr = part_total(part, nblk, 1, c, lds);
+        if (threadIdx.x == 0) {
+            double b = 0.0;
+            if (cs->active[c]) {
+                cs->rr[c] = rr;
+                b = rz / cs->rz[c];
+                cs->rz[c] = rz;
+                if (!(rr > tol2 * cs->bb[c])) {
+                    cs->active[c] = 0;
+                    b = 0.0;
+                }
+            }
+            cs->beta[c] = b;
+            na += cs->active[c];
+        }
+    }
+    if (threadIdx.x == 0) cs->n_active = na;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(CG_ROWS) void k_cg_dir(const double* __restrict__ z, double* __restrict__ p, int nc,
+                                                  const CgState* __restrict__ cs)
+{
+    const int64_t i = (int64_t)blockIdx.x * CG_ROWS + threadIdx.x;
+    for (int c = 0; c < nc; ++c) {
+        const size_t o = (size_t)i * nc + c;
+        p[o] = fma(cs->beta[c], p[o], z[o]);
+    }
+}
+
+// w[i] = (w3[i][0], w3[i][1], w3[i][2], 0)
+__global__ void k_bem_pack_w(const double* __restrict__ w3, double4* __restrict__ w, int64_t np)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    w[i] = make_double4(w3[3 * i], w3[3 * i + 1], w3[3 * i + 2], 0.0);
 }
 
 }  // namespace
@@ -144,8 +404,11 @@ int bem_splits(const Geometry& g)
 
 size_t bem_scratch_bytes(const Geometry& g) { return (size_t)bem_splits(g) * g.np * BEM_NC * sizeof(double); }
 
-void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st, double* scratch,
-                   const int32_t* stop, const hipEvent_t* ev)
+namespace {
+
+template <int MODE>
+void bem_apply_mode(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st,
+                    double* scratch, const int32_t* stop, const hipEvent_t* ev)
 {
     const int np = (int)g.np;
     const int nsplit = bem_splits(g);
@@ -156,7 +419,7 @@ void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int n
         const int nc = std::min(BEM_NC, ncols - c0);
         const bool first = c0 == 0, last = c0 + nc >= ncols;
 #define PX_BEM(NC)                                                                                                   \
-    hipExtLaunchKernelGGL(k_bem_apply<NC>, grid, dim3(BEM_ROWS), 0, st, first ? e0 : nullptr, nullptr, 0,           \
+    hipExtLaunchKernelGGL(k_bem_apply<MODE, NC>, grid, dim3(BEM_ROWS), 0, st, first ? e0 : nullptr, nullptr, 0,     \
                           (const double4*)g.xyz64, (const double4*)g.bem_na, X, ldx, c0, scratch, np, inv_2r, stop)
         switch (nc) {
         case 1: PX_BEM(1); break;
@@ -175,16 +438,111 @@ void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int n
     }
 }
 
+}  // namespace
+
+void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st, double* scratch,
+                   const int32_t* stop, const hipEvent_t* ev)
+{
+    if (g.bem_ief) bem_apply_mode<1>(g, X, Y, ldx, ncols, st, scratch, stop, ev);
+    else bem_apply_mode<0>(g, X, Y, ldx, ncols, st, scratch, stop, ev);
+}
+
 void bem_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, hipStream_t st)
 {
     const dim3 grid((unsigned)((g.np + 3) / 4), (unsigned)((ldb + 63) / 64));
-    hipLaunchKernelGGL(k_bem_rhs, grid, dim3(256), 0, st, (const double4*)g.bem_na, col_pol, e0, b, g.n, g.np, ncol,
-                       ldb);
+    hipLaunchKernelGGL(k_bem_rhs, grid, dim3(256), 0, st, (const double4*)g.bem_na,
+                       (const double4*)(g.bem_ief ? g.bem_rv : nullptr), col_pol, e0, b, g.n, g.np, ncol, ldb);
+}
+
+hipError_t bem_single_layer_solve(const Geometry& g, const double* B, int ldb, int nc, double* X, double tol,
+                                  int max_iter, hipStream_t st, int* status, int* iters, double* relres)
+{
+    *status = 1;
+    if (nc < 1 || nc > CG_NC || g.np % CG_ROWS != 0) return hipErrorInvalidValue;
+    const int64_t np = g.np;
+    const int nblk = (int)(np / CG_ROWS);
+    const size_t vec = (size_t)np * nc;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *part = nullptr, *scr = nullptr;
+    CgState* cs = nullptr;
+    hipError_t e = hipSuccess;
+    auto cleanup = [&]() {
+        for (void* v : {(void*)r, (void*)z, (void*)p, (void*)q, (void*)part, (void*)scr, (void*)cs}) px::dev_free(v);
+    };
+#define PXCG(x)            \
+    do {                   \
+        e = (x);           \
+        if (e != hipSuccess) { \
+            cleanup();     \
+            return e;      \
+        }                  \
+    } while (0)
+    PXCG(px::dev_malloc((void**)&r, sizeof(double) * vec));
+    PXCG(px::dev_malloc((void**)&z, sizeof(double) * vec));
+    PXCG(px::dev_malloc((void**)&p, sizeof(double) * vec));
+    PXCG(px::dev_malloc((void**)&q, sizeof(double) * vec));
+    PXCG(px::dev_malloc((void**)&part, sizeof(double) * nblk * 2 * CG_NC));
+    PXCG(px::dev_malloc((void**)&scr, bem_scratch_bytes(g)));
+    PXCG(px::dev_malloc((void**)&cs, sizeof(CgState)));
+    const double4* na = (const double4*)g.bem_na;
+    const double tol2 = tol * tol;
+    const dim3 grid((unsigned)nblk), blk(CG_ROWS);
+    CgState h{};
+    int it = 0;
+    // a restart from the current x when the recursive residual has drifted
+    // from the true one by more than 10 tol
+    for (int start = 0; start < 3; ++start) {
+        if (start == 0) {
+            hipLaunchKernelGGL(k_cg_start, grid, blk, 0, st, B, ldb, (const double*)nullptr, na, np, nc, X, r, z, p,
+                               part);
+        } else {
+            bem_apply_mode<2>(g, X, q, nc, nc, st, scr, nullptr, nullptr);
+            hipLaunchKernelGGL(k_cg_start, grid, blk, 0, st, B, ldb, (const double*)q, na, np, nc, X, r, z, p, part);
+        }
+        hipLaunchKernelGGL(k_cg_begin, dim3(1), blk, 0, st, (const double*)part, nblk, nc, tol2, start == 0 ? 1 : 0,
+                           cs);
+        PXCG(hipGetLastError());
+        PXCG(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, st));
+        PXCG(hipStreamSynchronize(st));
+        if (start > 0 && h.n_active == 0) break;
+        while (h.n_active > 0 && !h.breakdown && it < max_iter) {
+            // a few iterations between looks at the active set
+            for (int k = 0; k < 8 && it < max_iter; ++k, ++it) {
+                bem_apply_mode<2>(g, p, q, nc, nc, st, scr, nullptr, nullptr);
+                hipLaunchKernelGGL(k_cg_pq, grid, blk, 0, st, (const double*)p, (const double*)q, nc, part);
+                hipLaunchKernelGGL(k_cg_alpha, dim3(1), blk, 0, st, (const double*)part, nblk, nc, cs);
+                hipLaunchKernelGGL(k_cg_update, grid, blk, 0, st, X, r, z, (const double*)p, (const double*)q, na, nc,
+                                   (const CgState*)cs, part);
+                hipLaunchKernelGGL(k_cg_beta, dim3(1), blk, 0, st, (const double*)part, nblk, nc, tol2, cs);
+                hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, st, (const double*)z, p, nc, (const CgState*)cs);
+            }
+            PXCG(hipGetLastError());
+            PXCG(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, st));
+            PXCG(hipStreamSynchronize(st));
+        }
+        if (h.breakdown || h.n_active > 0) break;
+    }
+    // the true residual of the final x
+    bem_apply_mode<2>(g, X, q, nc, nc, st, scr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_cg_start, grid, blk, 0, st, B, ldb, (const double*)q, na, np, nc, X, r, z, p, part);
+    hipLaunchKernelGGL(k_cg_begin, dim3(1), blk, 0, st, (const double*)part, nblk, nc, tol2, 0, cs);
+    PXCG(hipGetLastError());
+    PXCG(hipMemcpyAsync(&h, cs, sizeof(CgState), hipMemcpyDeviceToHost, st));
+    PXCG(hipStreamSynchronize(st));
+    double worst = 0.0;
+    for (int c = 0; c < nc; ++c)
+        if (h.bb[c] > 0.0) worst = std::max(worst, std::sqrt(h.rr[c] / h.bb[c]));
+    *status = h.breakdown ? 2 : (worst <= 10.0 * tol ? 0 : 1);
+    if (iters) *iters = it;
+    if (relres) *relres = worst;
+    cleanup();
+#undef PXCG
+    return hipSuccess;
 }
 
 hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double* nrm, const double* area_bohr2,
-                              double r_enc_bohr, hipStream_t st)
+                              double r_enc_bohr, bool ief, hipStream_t st, int* status)
 {
+    *status = 0;
     const int64_t n = g.n, np = g.np;
     std::vector<double4> s((size_t)np), na((size_t)np);
     std::vector<float4> s32((size_t)np);
@@ -222,11 +580,37 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     PXCHK(hipMemcpyAsync(g.col, ci.data(), sizeof(int32_t) * ci.size(), hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.val, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice, st));
     PXCHK(hipStreamSynchronize(st));
-#undef PXCHK
     g.nnz = n;
     g.bem = true;
     g.bem_r = r_enc_bohr;
-    return hipSuccess;
+    if (!ief) return hipSuccess;
+    // IEFPCM: rv = 2 pi s + F s, then the dipole weights w = (S A^-1)^-1 s
+    g.bem_ief = true;
+    PXCHK(px::dev_malloc((void**)&g.bem_rv, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.bem_w, sizeof(double4) * np));
+    PXCHK(hipMemsetAsync(g.bem_rv, 0, sizeof(double4) * np, st));
+    double *scr = nullptr, *w3 = nullptr;
+    e = px::dev_malloc((void**)&scr, bem_scratch_bytes(g));
+    if (e == hipSuccess) e = px::dev_malloc((void**)&w3, sizeof(double) * 3 * np);
+    if (e == hipSuccess) {
+        bem_apply_mode<1>(g, (const double*)g.xyz64, (double*)g.bem_rv, 4, 3, st, scr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_bem_ief_rv, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st,
+                           (const double4*)g.xyz64, (const double4*)g.bem_na, g.bem_rv, np);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = bem_single_layer_solve(g, (const double*)g.xyz64, 4, 3, w3, kSingleLayerTol, kSingleLayerMaxIter, st,
+                                   status, nullptr, nullptr);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_bem_pack_w, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, (const double*)w3,
+                           g.bem_w, np);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    px::dev_free(scr);
+    px::dev_free(w3);
+#undef PXCHK
+    return e;
 }
 
 }  // namespace px

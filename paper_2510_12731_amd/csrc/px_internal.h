@@ -75,24 +75,41 @@ struct Geometry {
     // kernel every atom's position relative to it with its squared norm in w
     double cx = 0, cy = 0, cz = 0;
     double4* xyzc = nullptr;   // [np], built with the near-field list
-    // BEM (DPCM): the sites are tesserae (barycentres in xyz64), with their
-    // outward unit normal and area in bem_na [np] (ghosts: area 0), the
-    // identity in place of Kbar and the radius enclosing the mesh (bohr)
+    // BEM: the sites are tesserae (barycentres in xyz64), with their outward
+    // unit normal and area in bem_na [np] (ghosts: area 0), the identity in
+    // place of Kbar and the radius enclosing the mesh (bohr).  DPCM solves for
+    // the charges; IEFPCM (bem_ief) for the potential y = S A^-1 q they make,
+    // with bem_rv [np] = 2 pi s + F s (the right-hand side per unit field,
+    // component l for polarization l) and bem_w [np] = (S A^-1)^-1 s (the
+    // dipole weights: d_k = w_k . y, S A^-1 being symmetric)
     bool bem = false;
+    bool bem_ief = false;
     double4* bem_na = nullptr;
+    double4* bem_rv = nullptr;
+    double4* bem_w = nullptr;
     double bem_r = 0.0;
 };
 
-// ---- BEM, DPCM (px_bem.hip) ---------------------------------------------------
-// The mesh on the device (caller order; positions and areas in bohr units).
+// ---- BEM, DPCM and IEFPCM (px_bem.hip) -------------------------------------------
+// The mesh on the device (caller order; positions and areas in bohr units);
+// for IEFPCM also bem_rv and bem_w (the latter by bem_single_layer_solve;
+// *status as there).
 hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double* nrm, const double* area_bohr2,
-                              double r_enc_bohr, hipStream_t st);
-// Y = M X for ncols real columns (X, Y row-major, ld ldx), M generated on the
-// fly in FP64; scratch of bem_scratch_bytes(g).
+                              double r_enc_bohr, bool ief, hipStream_t st, int* status);
+// Y = M X (DPCM) or Y = F X (IEFPCM) for ncols real columns (X, Y row-major,
+// ld ldx), generated on the fly in FP64; scratch of bem_scratch_bytes(g).
 size_t bem_scratch_bytes(const Geometry& g);
 void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st, double* scratch,
                    const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
-// b = -A E0 n_l per column (complex, imaginary part 0)
+// Solves (S A^-1) X = B for nc <= 8 real columns (IEFPCM's single layer, ghost
+// rows of B ignored): B rows of stride ldb, X [np][nc] contiguous on return,
+// Jacobi-preconditioned conjugate gradients to ||B - S A^-1 X|| <= tol ||B||
+// per column.  *status: 0 converged, 1 not within max_iter, 2 a direction of
+// non-positive curvature (S A^-1 not positive definite on this mesh).
+hipError_t bem_single_layer_solve(const Geometry& g, const double* B, int ldb, int nc, double* X, double tol,
+                                  int max_iter, hipStream_t st, int* status, int* iters, double* relres);
+// b per column: -A E0 n_l (DPCM) or E0 (2 pi s_l + (F s)_l) (IEFPCM), complex
+// with imaginary part 0
 void bem_rhs(const Geometry& g, const int32_t* col_pol, double e0, double2* b, int ncol, int ldb, hipStream_t st);
 
 // Ascending bitonic sort of npow (a power of two) 64-bit keys in place.

@@ -392,6 +392,13 @@ void shift_bem(double e2r, double e2i, double e1r, double e1i, double& zr, doubl
 
 }  // namespace pxs
 
+struct pxStructure_t;
+namespace pxs {
+// The shift z of a BEM structure's operator (DPCM: the one above; IEFPCM: its
+// negative) for the metal permittivity e2 (interleaved complex)
+void shift_bem_of(const pxStructure_t* s, const double* e2, double& zr, double& zi);
+}  // namespace pxs
+
 struct pxStructure_t {
     px::Geometry g;
     pxModel model = PX_WFQ;
@@ -448,7 +455,7 @@ struct pxStructure_t {
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, d_perm, d_col_pol, d_omega, x, b};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, g.bem_rv, g.bem_w, d_perm, d_col_pol, d_omega, x, b};
         for (void* p : ps) pxs::dfree(p);
         // the stored T came from the block cache
         for (void* p : {(void*)t32, (void*)t64}) {

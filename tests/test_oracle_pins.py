@@ -971,3 +971,23 @@ def test_bem_ief_apply_rhs_and_direct_solution_agree():
             f = (eps2[w] + 1.3) / (eps2[w] - 1.3)
             lhs = (2 * np.pi * f * np.eye(n) + F) @ (S @ (out["q"][w, l] / a))
             assert np.abs(lhs - b).max() <= 1e-10 * np.abs(b).max()
+
+
+def test_bem_ief_potential_is_the_single_layer_over_the_areas():
+    """The matrix-free potential S A^-1 q of the oracle's IEFPCM charges: on a
+    sphere a degree-1 charge pattern q = A u_z makes 4 pi R / 3 u_z (the
+    single layer's eigenvalue), and the direct solution's potential solves
+    the shifted double-layer system [2 pi f I + F] y = b."""
+    m = ME.sphere(25.0, 3)
+    R = 25.0 / BOHR
+    a = m["area"] / BOHR ** 2
+    u = m["cen"] / np.linalg.norm(m["cen"], axis=1)[:, None]
+    y = O.bem_ief_potential(m, (a * u[:, 2]).astype(np.complex128))[0]
+    lam = 4 * np.pi * R / 3
+    assert np.linalg.norm(y - lam * u[:, 2]) / np.linalg.norm(lam * u[:, 2]) < 2e-3
+    m = ME.sphere(20.0, 2)
+    eps2 = np.array([-2.0 + 0.5j])
+    out = O.bem_ief_solve_spectrum(m, np.array([3.0]), eps2, 1.0, 0b001, 1e-4)
+    y = O.bem_ief_potential(m, out["q"][0, 0])[0]
+    r = O.bem_ief_apply(m, eps2, 1.0, y[None, :])[0] - O.bem_ief_rhs(m, 0, 1e-4)
+    assert np.abs(r).max() <= 1e-10 * np.abs(O.bem_ief_rhs(m, 0, 1e-4)).max()
