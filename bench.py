@@ -396,10 +396,20 @@ def batch_full_extra(pxm, fp64_every=8):
                 speedup_vs_fp64=round((cols / rb["seconds"]) / (cols64 / t64), 2), sigma_rel_err_vs_fp64=err)
 
 
-def bem_extra(pxm):
-    """BEM (DPCM): a 20,480-tesserae Ag sphere (R = 80 A), 64 w x 3 pol, the
-    default solve against the FP64 blocked solver, and the oracle residual of
-    two sampled columns."""
+# FP64 arithmetic per tessera pair of the BEM operator kernels besides the
+# products with the columns: s_i - s_j (3), r^2 (a multiply and two fused
+# multiply-adds, 5), d.n (5), the reciprocal square root estimate and one
+# Newton step (5), y^3 (2) and the kernel's value (1); the double layer F
+# multiplies by the source area too.
+BEM_PAIR_FLOP = {"dpcm": 21, "iefpcm": 22}
+
+
+def bem_extra(pxm, form="dpcm"):
+    """BEM (DPCM or IEFPCM): a 20,480-tesserae Ag sphere (R = 80 A), 64 w x 3
+    pol, the default solve against the FP64 blocked solver, and the oracle
+    residual of a sampled column (IEFPCM: its charges in the printed
+    equation).  For IEFPCM also the creation (mesh, F s and the dipole
+    weights' single-layer solve) and one column's charge solve, timed apart."""
     import oracle as O
     from workloads import materials as M
     from workloads import mesh as ME
@@ -411,33 +421,61 @@ def bem_extra(pxm):
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s = pxm.Structure.bem(m, 1.0, pxm.default_stream())
+        s = pxm.Structure.bem(m, 1.0, pxm.default_stream(), form=form)
+        t_create = time.perf_counter() - t0
         s.set_frequencies(om, 0b111, 1e-4, eps)
         st = s.solve(rel_tol=1e-8, **kw)
         sig = s.spectrum()[1]
         it = s.stats()[0]
         torch.cuda.synchronize()
-        return s, dict(seconds=time.perf_counter() - t0, status=int(st), sigma=sig, steps=int(it.max()))
+        return s, dict(seconds=time.perf_counter() - t0, create_s=t_create, status=int(st), sigma=sig,
+                       steps=int(it.max()), tapply=s.tapply_stats())
 
     s, r = run()
     s.close()
     s, r = run()
+    # the shared phase's operator applies (one k_bem_apply over the three
+    # real basis columns + k_bem_sum per step), timed by the library's HIP
+    # events on its stream in a third solve with timings on
+    s_t, r_t = run(timings=True)
+    s_t.close()
+    ta = r_t["tapply"]
+    n = len(m["area"])
+    pair_flop = BEM_PAIR_FLOP[form] + 2 * 3
+    launches = int(ta["f64_on_the_fly"])
+    ms_ap = float(ta["ms_f64_on_the_fly"])
+    ach = n * n * pair_flop * launches / (ms_ap * 1e-3) / 1e12 if ms_ap > 0 else 0.0
+    roof = dict(bound="alu", achieved=round(ach, 2), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / FP64_VECTOR_PEAK_TFLOPS, 4),
+                kernel=f"k_bem_apply<{1 if form == 'iefpcm' else 0}, 3> + k_bem_sum (the shared phase's step)",
+                launches=launches, avg_launch_ms=round(ms_ap / max(launches, 1), 4),
+                flop_note=f"{BEM_PAIR_FLOP[form]} + 2 x 3 FP64 FLOP per tessera pair (N^2 pairs), peak = FP64 vector")
     w = int(np.argmax(r["sigma"]))
+    t0 = time.perf_counter()
     q = s.charges(w, 0)
+    t_q = time.perf_counter() - t0
     s.close()
-    b = O.bem_rhs(m, 0, 1e-4)
-    res = float(np.linalg.norm(b - O.bem_apply(m, eps[w:w + 1], 1.0, q[None, :])[0]) / np.linalg.norm(b))
+    if form == "iefpcm":
+        b = O.bem_ief_rhs(m, 0, 1e-4)
+        y = O.bem_ief_potential(m, q[None, :])
+        res = float(np.linalg.norm(b - O.bem_ief_apply(m, eps[w:w + 1], 1.0, y)[0]) / np.linalg.norm(b))
+    else:
+        b = O.bem_rhs(m, 0, 1e-4)
+        res = float(np.linalg.norm(b - O.bem_apply(m, eps[w:w + 1], 1.0, q[None, :])[0]) / np.linalg.norm(b))
     s64, r64 = run(precision=pxm.PX_FP64, shifted=0)
     s64.close()
     ncol = len(om) * 3
-    return dict(workload="ag_bem_sphere_20480_64w_xyz", tesserae=len(m["area"]), columns=ncol,
-                seconds=round(r["seconds"], 3), solves_per_s=round(ncol / r["seconds"], 2), status=r["status"],
-                phase_steps_max=r["steps"], fp64_blocked_s=round(r64["seconds"], 2),
-                fp64_blocked_solves_per_s=round(ncol / r64["seconds"], 2),
-                speedup_vs_fp64_blocked=round(r64["seconds"] / r["seconds"], 2),
-                sigma_rel_err_vs_fp64_blocked=float(np.max(np.abs(r["sigma"] - r64["sigma"])) /
-                                                    np.max(np.abs(r64["sigma"]))),
-                oracle_rel_residual_at_peak=res, peak_ev=round(float(om[w]), 3))
+    out = dict(workload=f"ag_bem_{form}_sphere_20480_64w_xyz", tesserae=len(m["area"]), columns=ncol,
+               seconds=round(r["seconds"], 3), solves_per_s=round(ncol / r["seconds"], 2), status=r["status"],
+               phase_steps_max=r["steps"], fp64_blocked_s=round(r64["seconds"], 2),
+               fp64_blocked_solves_per_s=round(ncol / r64["seconds"], 2),
+               speedup_vs_fp64_blocked=round(r64["seconds"] / r["seconds"], 2),
+               sigma_rel_err_vs_fp64_blocked=float(np.max(np.abs(r["sigma"] - r64["sigma"])) /
+                                                   np.max(np.abs(r64["sigma"]))),
+               oracle_rel_residual_at_peak=res, peak_ev=round(float(om[w]), 3), roofline=roof)
+    if form == "iefpcm":
+        out.update(create_s=round(r["create_s"], 3), charges_one_column_s=round(t_q, 4))
+    return out
 
 
 def make_structure(pxm, case):
@@ -675,11 +713,13 @@ def main():
                          "with --no-shifted one blocked restart cycle of 4 steps (with --t-apply)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only copy this many GiB device-to-device (scales HBM counters) and exit")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving", "serving-full", "serving-wfq-full", "probe", "batch"],
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "serving", "serving-full", "serving-wfq-full", "probe", "batch",
+                                                           "bem"],
                     help="sphere: the headline line with every config's extra; serving: the serving mix alone; "
                          "serving-wfq-full: the omegaFQ requests of the 1k-100k mix; serving-full: the serving mix at "
                          "1k-100k atoms; probe: the induced-field evaluation; batch: the 64-structure graphene "
-                         "batch alone, first and warm call; printed as their own JSON lines")
+                         "batch alone, first and warm call; bem: the BEM sphere in both forms; printed as their own "
+                         "JSON lines")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads (rod, batch, serving, BEM)")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked mixed-precision comparison step")
     ap.add_argument("--no-shifted", action="store_true",
@@ -728,6 +768,10 @@ def main():
             r = batch_run(pxm, cases, pxm.PX_MIXED)
             print(json.dumps({"workload": "graphene_batch_64", "call": label, "seconds": round(r["seconds"], 3),
                               "status": r["status"], "relres_max": r["relres_max"]}), flush=True)
+        return
+    if args.workload == "bem":
+        for form in ("dpcm", "iefpcm"):
+            print(json.dumps(bem_extra(pxm, form)), flush=True)
         return
     if args.workload == "serving":
         out = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
@@ -907,6 +951,8 @@ def main():
         extra["serving"] = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
         log("[bench] BEM sphere ...")
         extra["bem"] = bem_extra(pxm)
+        log("[bench] BEM sphere, IEFPCM ...")
+        extra["bem_iefpcm"] = bem_extra(pxm, "iefpcm")
 
     out = {
         "metric": "omegaFQ freq-solves/s at N=20k (rel res 1e-8)",

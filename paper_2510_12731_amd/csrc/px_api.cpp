@@ -216,7 +216,8 @@ void ensure_vectors(pxStructure_t* s, int lda)
     W.zq = dalloc<double2>(lda);
     W.zmu = dalloc<double2>(lda);
     W.het = dalloc<double2>((size_t)6 * lda);
-    W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, 8);
+    // (a BEM structure applies every column of the block in one call)
+    W.narrow_bytes = px::tapply_f64_scratch_bytes(s->g, s->g.bem ? 2 * lda : 8);
     W.narrow = dalloc<double>(W.narrow_bytes / sizeof(double) + 1);
     W.split32 = dalloc<float>(px::tapply_f32_scratch_bytes(s->g, 2 * lda) / sizeof(float) + 1);
     // the omegaFQ narrow FP64 T-apply takes its near field from a stored list
@@ -836,6 +837,10 @@ class PhaseRun {
         if (side_s_) (void)hipStreamDestroy(side_s_);
     }
     bool ended() const { return ended_; }
+    // After finish(): relres holds every pair's true FP64 residual (not the
+    // Givens estimate), so the blocked solver need only take the pairs above
+    // rel_tol.
+    bool verified() const { return verified_; }
     // Enqueues at most max_steps steps; without `wait`, returns (blocked set)
     // rather than wait for a Givens batch still on the device.
     int advance(int max_steps, bool wait, bool& blocked)
@@ -908,6 +913,7 @@ class PhaseRun {
     hipStream_t side_s_ = nullptr;
     hipEvent_t side_e_ = nullptr;
     int method_ = TA_FLY;
+    bool verified_ = false;
 
   private:
     void givens_side(int k0, int kn, int at_step)
@@ -1180,11 +1186,47 @@ class BlockShiftedRun : public PhaseRun {
         double2* ycoef = sc_.get<double2>(std::max<size_t>(1, (size_t)kcols * P));
         px::msb_finish_solve(R, Hb_, ldh_, NW, kcols, z_, rc_, rs_, done_, rst, g_, ycoef, V_, vstride_, s->x, s->ldg,
                              s->g.nup, st);
+        // When the basis is narrow beside the pairs (BEM: 15 block steps for
+        // 192 pairs), every pair's true FP64 residual comes from one operator
+        // apply over the basis: T x = (T V) y, the same coefficients as x =
+        // V y, then b - (Kbar T x - z x); the blocked solver then takes only
+        // the pairs above rel_tol instead of applying T to all of them.
+        const int64_t nup = s->g.nup;
+        const int kpad = s->g.bem ? (kcols + 15) / 16 * 16 : (kcols + 127) / 128 * 128;
+        std::vector<double> tn;
+        if (kcols > 0 && kpad <= P) {
+            double* Wb = sc_.get<double>((size_t)nup * kpad);
+            double* Zb = sc_.get<double>((size_t)nup * kpad);
+            double* TV = sc_.get<double>((size_t)launched * vstride_);
+            double2* TX = sc_.get<double2>((size_t)nup * s->ldg);
+            double2* Rr = sc_.get<double2>((size_t)nup * s->ldg);
+            const int nchunk = px::arnoldi_chunks(nup);
+            double* npart = sc_.get<double>((size_t)nchunk * s->ldg);
+            double* nrm = sc_.get<double>(s->ldg);
+            px::msb_basis_gather(R, V_, vstride_, kcols, nup, Wb, kpad, st);
+            const int meth = tapply_method(s, false, Wb, Zb, kpad, kpad, o_, true);
+            tapply(s, meth, false, Wb, Zb, kpad, kpad, nullptr, nullptr, kpad);
+            px::msb_basis_scatter(R, Zb, kpad, kcols, nup, TV, vstride_, st);
+            px::msb_xcombine(R, TV, vstride_, kcols, done_, ycoef, P, TX, s->ldg, nup, st);
+            px::spmm_shift(s->g, TX, false, 2 * s->ldg, s->x, z_, z_, s->b, Rr, P, s->ldg, SOLVER_MU_SIGN, st);
+            px::col_norm_partial(Rr, npart, P, s->ldg, nup, st);
+            px::reduce_norms(npart, nchunk, nrm, P, s->ldg, st);
+            tn.resize(P);
+            HC(hipMemcpyAsync(tn.data(), nrm, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+            const double nu = (double)s->g.nu;
+            s->counts[3] += 1;
+            s->counts[4] += kpad;
+            s->counts[5] += kcols;
+            s->work[1] += 2.0 * nu * nu * kcols;
+            s->work[2] += 80.0 * nu * P;
+            verified_ = true;
+        }
         std::vector<int32_t> dh(P);
         std::vector<double> rh(P);
         HC(hipMemcpyAsync(dh.data(), done_, sizeof(int32_t) * P, hipMemcpyDeviceToHost, st));
         HC(hipMemcpyAsync(rh.data(), resid_, sizeof(double) * P, hipMemcpyDeviceToHost, st));
         HC(hipStreamSynchronize(st));
+        if (verified_) rh = tn;
         sc_.idle = true;   // nothing on either stream uses the scratch any more
         int executed = 0;
         for (int p = 0; p < P; ++p) {
@@ -1319,6 +1361,13 @@ class WholeSolve {
                 did += phase_->advance(max_steps - did, wait, blocked);
                 if (phase_->ended()) {
                     phase_->finish();
+                    if (phase_->verified()) {
+                        // only the pairs whose true residual is above rel_tol go on
+                        pending_.clear();
+                        for (int c = 0; c < s_->ncol; ++c)
+                            if (!(s_->relres[c] <= o_.rel_tol)) pending_.push_back(c);
+                        use_pending_ = true;
+                    }
                     phase_.reset();
                     next_block();
                     ++did;
@@ -1343,7 +1392,15 @@ class WholeSolve {
   private:
     void next_block()
     {
-        if (c0_ < s_->ncol) {
+        if (use_pending_) {
+            if (p0_ < pending_.size()) {
+                const size_t e = std::min(pending_.size(), p0_ + (size_t)blk_);
+                std::vector<int> cols(pending_.begin() + p0_, pending_.begin() + e);
+                p0_ = e;
+                block_.reset(new BlockRun(s_, cols, o_));
+                return;
+            }
+        } else if (c0_ < s_->ncol) {
             std::vector<int> cols;
             for (int c = c0_; c < std::min(s_->ncol, c0_ + blk_); ++c) cols.push_back(c);
             c0_ += blk_;
@@ -1380,6 +1437,10 @@ class WholeSolve {
     hipEvent_t ev_ = nullptr;
     bool moved_ = false, fin_ = false;
     int blk_ = 0, c0_ = 0;
+    // the columns left after a phase that checked every true residual
+    std::vector<int> pending_;
+    size_t p0_ = 0;
+    bool use_pending_ = false;
     std::unique_ptr<PhaseRun> phase_;
     std::unique_ptr<BlockRun> block_;
 };
@@ -1509,7 +1570,7 @@ double solve_footprint(const pxStructure_t* s, const pxSolveOptions& o)
     const int blk = o.max_block_cols > 0 ? std::min(o.max_block_cols, s->ncol) : s->ncol;
     const double lda = pad_cols(blk, true);
     const double nup = (double)s->g.nup, vec = nup * lda;
-    double b = vec * (5 * 16 + 8 + 8 + 16) + (double)px::tapply_f64_scratch_bytes(s->g, 8) +
+    double b = vec * (5 * 16 + 8 + 8 + 16) + (double)px::tapply_f64_scratch_bytes(s->g, s->g.bem ? 2 * (int)lda : 8) +
                (double)px::tapply_f32_scratch_bytes(s->g, 2 * (int)lda);
     if (s->model == PX_WFQ) b += 6000.0 * (double)s->g.n;   // near-field list (about 400 entries per atom)
     const int m_max = std::max(o.restart_m, o.max_restart_m);

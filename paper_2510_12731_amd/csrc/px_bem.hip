@@ -35,6 +35,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace px {
@@ -43,7 +44,11 @@ namespace {
 constexpr double BEM_SELF = 1.0694;   // self-patch factor of the approximate F diagonal
 constexpr int BEM_ROWS = 256;         // rows per workgroup
 constexpr int BEM_UNIT = 256;         // sources per split unit
-constexpr int BEM_NC = 8;             // real columns per launch (wider blocks: several launches)
+constexpr int BEM_NC = 8;             // real columns per launch of a narrow block
+constexpr int BEM_NC_WIDE = 16;       // per launch of a block wider than BEM_NC
+// rows per thread of the apply: two for narrow launches, one for the wide
+// launch (whose 16 accumulators per row already fill the registers)
+constexpr int bem_rpt(int nc) { return nc <= BEM_NC ? 2 : 1; }
 constexpr double kSingleLayerTol = 1e-12;   // the dipole weights' solve
 constexpr int kSingleLayerMaxIter = 20000;
 
@@ -58,69 +63,116 @@ __device__ __forceinline__ double rsqrt2_pos(double q)
 // Split y of row block x: part[y][i][c] = sum_j K_ij X[j][c0 + c] over the
 // source units y, y + nsplit, ... (the self pair excluded), plus the diagonal
 // K_ii X[i][c0 + c] in split 0, for K = M (MODE 0), F (MODE 1) or S A^-1
-// (MODE 2).  s, na: [np] (x, y, z, -) and (n_x, n_y, n_z, A); ghost
-// tesserae have A = 0: zero rows and columns of M and F, identity rows and
-// zero columns of S A^-1.
-template <int MODE, int NC>
-__global__ __launch_bounds__(BEM_ROWS) void k_bem_apply(const double4* __restrict__ s, const double4* __restrict__ na,
-                                                      const double* __restrict__ X, int ldx, int c0,
-                                                      double* __restrict__ part, int np, double inv_2r,
-                                                      const int32_t* __restrict__ stop)
+// (MODE 2).  A thread holds RPT rows (t, t + BEM_ROWS / RPT of the block), so
+// every source's wave-uniform loads feed RPT rows.
+//   pc [np]: positions relative to the mesh centre with |p|^2 in w, so that
+//       r^2 = |p_i|^2 + |p_j|^2 - 2 p_i.p_j takes four instructions (its
+//       rounding, a few units of FP64 rounding times |p|^2 / r^2, stays near
+//       1e-12 of a term for the nearest tesserae of a 100k-tesserae sphere);
+//   na [np]: (n, A); an [np]: (A n, A p.n) for the double layer, so that
+//       A_j (s_i - s_j).n_j = p_i.(A_j n_j) - A_j p_j.n_j takes three.
+// Ghost tesserae have A = 0: zero rows of all three, zero columns of F; the
+// columns of X are zero on ghost rows (M and S A^-1 do not mask them), and
+// S A^-1 has identity ghost rows.
+template <int MODE, int NC, int RPT>
+__global__ __launch_bounds__(BEM_ROWS / RPT) void k_bem_apply(const double4* __restrict__ pc,
+                                                            const double4* __restrict__ na,
+                                                            const double4* __restrict__ an,
+                                                            const double* __restrict__ X, int ldx, int c0,
+                                                            double* __restrict__ part, int np, double inv_2r,
+                                                            const int32_t* __restrict__ stop)
 {
     if (stop && *stop) return;
-    const int i = blockIdx.x * BEM_ROWS + threadIdx.x;
-    const double4 si = s[i], ni = na[i];
-    double acc[NC];
+    constexpr int BT = BEM_ROWS / RPT;
+    const int base = blockIdx.x * BEM_ROWS;
+    // per row: -2 p_i, |p_i|^2; MODE 0: n_i and p_i.n_i; MODE 1: p_i
+    double qx[RPT], qy[RPT], qz[RPT], qw[RPT], ux[RPT], uy[RPT], uz[RPT], uw[RPT];
+    double acc[RPT][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int r = 0; r < RPT; ++r) {
+        const int i = base + threadIdx.x + r * BT;
+        const double4 p = pc[i];
+        qx[r] = -2.0 * p.x;
+        qy[r] = -2.0 * p.y;
+        qz[r] = -2.0 * p.z;
+        qw[r] = p.w;
+        if (MODE == 0) {
+            const double4 n = na[i];
+            ux[r] = n.x;
+            uy[r] = n.y;
+            uz[r] = n.z;
+            uw[r] = fma(p.x, n.x, fma(p.y, n.y, p.z * n.z));
+        } else {
+            ux[r] = p.x;
+            uy[r] = p.y;
+            uz[r] = p.z;
+            uw[r] = 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = 0.0;
+    }
     const int nunit = np / BEM_UNIT;
-    const int row_unit = (blockIdx.x * BEM_ROWS) / BEM_UNIT;
+    const int row_unit = base / BEM_UNIT;
+    // one source j for every row of the thread; SELF: the unit holds the rows
+    // themselves (the pair j == i is skipped), every other unit takes the
+    // loop without that test
+    auto pair = [&](int j, auto self_tag) {
+        constexpr bool SELF = decltype(self_tag)::value;
+        const double4 pj = pc[j];
+        double xj[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xj[c] = X[(size_t)j * ldx + c0 + c];
+        double4 aj = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (MODE == 1) aj = an[j];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const double r2 = fma(qx[r], pj.x, fma(qy[r], pj.y, fma(qz[r], pj.z, qw[r]))) + pj.w;
+            const bool diag = SELF && j == base + (int)threadIdx.x + r * BT;
+            const double y = rsqrt2_pos(diag ? 1.0 : r2);
+            double t;
+            if (MODE == 0) t = fma(-pj.x, ux[r], fma(-pj.y, uy[r], fma(-pj.z, uz[r], uw[r]))) * (y * y * y);
+            else if (MODE == 1) t = fma(ux[r], aj.x, fma(uy[r], aj.y, fma(uz[r], aj.z, -aj.w))) * (y * y * y);
+            else t = y;
+            if (diag) t = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[r][c] = fma(t, xj[c], acc[r][c]);
+        }
+    };
     for (int u = blockIdx.y; u < nunit; u += gridDim.y) {
         const int j0 = u * BEM_UNIT;
-        const bool self = u == row_unit;
+        if (u != row_unit) {
 #pragma unroll 4
-        for (int jj = 0; jj < BEM_UNIT; ++jj) {
-            const int j = j0 + jj;
-            const double4 sj = s[j];
-            const double dx = si.x - sj.x, dy = si.y - sj.y, dz = si.z - sj.z;
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const double y = rsqrt2_pos(self && j == i ? 1.0 : r2);
-            double t;
-            if (MODE == 0) {
-                const double dn = fma(dx, ni.x, fma(dy, ni.y, dz * ni.z));
-                t = dn * (y * y * y);
-            } else if (MODE == 1) {
-                const double4 nj = na[j];
-                const double dn = fma(dx, nj.x, fma(dy, nj.y, dz * nj.z));
-                t = nj.w * dn * (y * y * y);
-            } else {
-                t = na[j].w > 0.0 ? y : 0.0;
-            }
-            if (self && j == i) t = 0.0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] = fma(t, X[(size_t)j * ldx + c0 + c], acc[c]);
+            for (int jj = 0; jj < BEM_UNIT; ++jj) pair(j0 + jj, std::false_type{});
+        } else {
+#pragma unroll 4
+            for (int jj = 0; jj < BEM_UNIT; ++jj) pair(j0 + jj, std::true_type{});
         }
     }
     // 2 / r: the factor 1/2 (S A^-1), (2 / r)^3 = 8 / r^3: 1/8 (M, F); the
     // row's area (M) or ghost mask (F, S A^-1), and the diagonal once
-    const bool real_row = ni.w > 0.0;
-    double w, kii;
-    if (MODE == 0) {
-        w = 0.125 * ni.w;
-        kii = BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
-    } else if (MODE == 1) {
-        w = real_row ? 0.125 : 0.0;
-        kii = -BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
-    } else {
-        w = real_row ? 0.5 : 0.0;
-        kii = real_row ? BEM_SELF * sqrt(4.0 * M_PI / ni.w) : 1.0;
-    }
-    double* out = part + (size_t)blockIdx.y * np * NC + (size_t)i * NC;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        double v = w * acc[c];
-        if (blockIdx.y == 0) v = fma(kii, X[(size_t)i * ldx + c0 + c], v);
-        out[c] = v;
+    for (int r = 0; r < RPT; ++r) {
+        const int i = base + threadIdx.x + r * BT;
+        const double4 ni = na[i];
+        const bool real_row = ni.w > 0.0;
+        double w, kii;
+        if (MODE == 0) {
+            w = 0.125 * ni.w;
+            kii = BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
+        } else if (MODE == 1) {
+            w = real_row ? 0.125 : 0.0;
+            kii = -BEM_SELF * sqrt(4.0 * M_PI * ni.w) * inv_2r;
+        } else {
+            w = real_row ? 0.5 : 0.0;
+            kii = real_row ? BEM_SELF * sqrt(4.0 * M_PI / ni.w) : 1.0;
+        }
+        double* out = part + (size_t)blockIdx.y * np * NC + (size_t)i * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double v = w * acc[r][c];
+            if (blockIdx.y == 0) v = fma(kii, X[(size_t)i * ldx + c0 + c], v);
+            out[c] = v;
+        }
     }
 }
 
@@ -402,7 +454,10 @@ int bem_splits(const Geometry& g)
     return (nunit + ups - 1) / ups;
 }
 
-size_t bem_scratch_bytes(const Geometry& g) { return (size_t)bem_splits(g) * g.np * BEM_NC * sizeof(double); }
+size_t bem_scratch_bytes(const Geometry& g, int ncols)
+{
+    return (size_t)bem_splits(g) * g.np * (ncols > BEM_NC ? BEM_NC_WIDE : BEM_NC) * sizeof(double);
+}
 
 namespace {
 
@@ -415,12 +470,13 @@ void bem_apply_mode(const Geometry& g, const double* X, double* Y, int ldx, int 
     const dim3 grid((unsigned)(np / BEM_ROWS), (unsigned)nsplit);
     const double inv_2r = 1.0 / (2.0 * g.bem_r);
     hipEvent_t e0 = ev ? ev[0] : nullptr, e1 = ev ? ev[1] : nullptr;
-    for (int c0 = 0; c0 < ncols; c0 += BEM_NC) {
-        const int nc = std::min(BEM_NC, ncols - c0);
+    for (int c0 = 0; c0 < ncols;) {
+        const int nc = ncols - c0 >= BEM_NC_WIDE ? BEM_NC_WIDE : std::min(BEM_NC, ncols - c0);
         const bool first = c0 == 0, last = c0 + nc >= ncols;
 #define PX_BEM(NC)                                                                                                   \
-    hipExtLaunchKernelGGL(k_bem_apply<MODE, NC>, grid, dim3(BEM_ROWS), 0, st, first ? e0 : nullptr, nullptr, 0,     \
-                          (const double4*)g.xyz64, (const double4*)g.bem_na, X, ldx, c0, scratch, np, inv_2r, stop)
+    hipExtLaunchKernelGGL((k_bem_apply<MODE, NC, bem_rpt(NC)>), grid, dim3(BEM_ROWS / bem_rpt(NC)), 0, st,         \
+                          first ? e0 : nullptr, nullptr, 0, (const double4*)g.xyzc, (const double4*)g.bem_na,        \
+                          (const double4*)g.bem_an, X, ldx, c0, scratch, np, inv_2r, stop)
         switch (nc) {
         case 1: PX_BEM(1); break;
         case 2: PX_BEM(2); break;
@@ -429,12 +485,14 @@ void bem_apply_mode(const Geometry& g, const double* X, double* Y, int ldx, int 
         case 5: PX_BEM(5); break;
         case 6: PX_BEM(6); break;
         case 7: PX_BEM(7); break;
-        default: PX_BEM(8); break;
+        case 8: PX_BEM(8); break;
+        default: PX_BEM(16); break;
         }
 #undef PX_BEM
         const int64_t len = (int64_t)np * nc;
         hipExtLaunchKernelGGL(k_bem_sum, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, nullptr,
                               last ? e1 : nullptr, 0, (const double*)scratch, nsplit, np, nc, nc, Y, ldx, c0, stop);
+        c0 += nc;
     }
 }
 
@@ -481,7 +539,7 @@ hipError_t bem_single_layer_solve(const Geometry& g, const double* B, int ldb, i
     PXCG(px::dev_malloc((void**)&p, sizeof(double) * vec));
     PXCG(px::dev_malloc((void**)&q, sizeof(double) * vec));
     PXCG(px::dev_malloc((void**)&part, sizeof(double) * nblk * 2 * CG_NC));
-    PXCG(px::dev_malloc((void**)&scr, bem_scratch_bytes(g)));
+    PXCG(px::dev_malloc((void**)&scr, bem_scratch_bytes(g, nc)));
     PXCG(px::dev_malloc((void**)&cs, sizeof(CgState)));
     const double4* na = (const double4*)g.bem_na;
     const double tol2 = tol * tol;
@@ -560,6 +618,27 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
         }
         s32[(size_t)i] = make_float4((float)s[(size_t)i].x, (float)s[(size_t)i].y, (float)s[(size_t)i].z, 0.0f);
     }
+    // the kernels' source data: positions relative to the centre of the
+    // tesserae's bounding box with |p|^2 in w, and (A n, A p.n)
+    double lo[3] = {s[0].x, s[0].y, s[0].z}, hi[3] = {s[0].x, s[0].y, s[0].z};
+    for (int64_t i = 1; i < n; ++i) {
+        const double v[3] = {s[(size_t)i].x, s[(size_t)i].y, s[(size_t)i].z};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], v[k]);
+            hi[k] = std::max(hi[k], v[k]);
+        }
+    }
+    const double cx = 0.5 * (lo[0] + hi[0]), cy = 0.5 * (lo[1] + hi[1]), cz = 0.5 * (lo[2] + hi[2]);
+    std::vector<double4> pcv((size_t)np), anv((size_t)np);
+    for (int64_t i = 0; i < np; ++i) {
+        const double x = s[(size_t)i].x - cx, y = s[(size_t)i].y - cy, z = s[(size_t)i].z - cz;
+        pcv[(size_t)i] = make_double4(x, y, z, x * x + y * y + z * z);
+        const double4 a = na[(size_t)i];
+        anv[(size_t)i] = make_double4(a.w * a.x, a.w * a.y, a.w * a.z, a.w * (x * a.x + y * a.y + z * a.z));
+    }
+    g.cx = cx;
+    g.cy = cy;
+    g.cz = cz;
     // the identity in place of Kbar (CSR over the real tesserae)
     std::vector<int32_t> rp((size_t)n + 1), ci((size_t)std::max<int64_t>(n, 1));
     std::vector<double> cv((size_t)std::max<int64_t>(n, 1), 1.0);
@@ -570,12 +649,16 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     PXCHK(px::dev_malloc((void**)&g.xyz64, sizeof(double4) * np));
     PXCHK(px::dev_malloc((void**)&g.xyz32, sizeof(float4) * np));
     PXCHK(px::dev_malloc((void**)&g.bem_na, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.xyzc, sizeof(double4) * np));
+    PXCHK(px::dev_malloc((void**)&g.bem_an, sizeof(double4) * np));
     PXCHK(px::dev_malloc((void**)&g.row_ptr, sizeof(int32_t) * (n + 1)));
     PXCHK(px::dev_malloc((void**)&g.col, sizeof(int32_t) * ci.size()));
     PXCHK(px::dev_malloc((void**)&g.val, sizeof(double) * cv.size()));
     PXCHK(hipMemcpyAsync(g.xyz64, s.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.xyz32, s32.data(), sizeof(float4) * np, hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.bem_na, na.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
+    PXCHK(hipMemcpyAsync(g.xyzc, pcv.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
+    PXCHK(hipMemcpyAsync(g.bem_an, anv.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.row_ptr, rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.col, ci.data(), sizeof(int32_t) * ci.size(), hipMemcpyHostToDevice, st));
     PXCHK(hipMemcpyAsync(g.val, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice, st));
@@ -590,7 +673,7 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     PXCHK(px::dev_malloc((void**)&g.bem_w, sizeof(double4) * np));
     PXCHK(hipMemsetAsync(g.bem_rv, 0, sizeof(double4) * np, st));
     double *scr = nullptr, *w3 = nullptr;
-    e = px::dev_malloc((void**)&scr, bem_scratch_bytes(g));
+    e = px::dev_malloc((void**)&scr, bem_scratch_bytes(g, 3));
     if (e == hipSuccess) e = px::dev_malloc((void**)&w3, sizeof(double) * 3 * np);
     if (e == hipSuccess) {
         bem_apply_mode<1>(g, (const double*)g.xyz64, (double*)g.bem_rv, 4, 3, st, scr, nullptr, nullptr);

@@ -75,9 +75,11 @@ struct Geometry {
     // kernel every atom's position relative to it with its squared norm in w
     double cx = 0, cy = 0, cz = 0;
     double4* xyzc = nullptr;   // [np], built with the near-field list
-    // BEM: the sites are tesserae (barycentres in xyz64), with their outward
-    // unit normal and area in bem_na [np] (ghosts: area 0), the identity in
-    // place of Kbar and the radius enclosing the mesh (bohr).  DPCM solves for
+    // BEM: the sites are tesserae (barycentres in xyz64, and relative to the
+    // centre (cx, cy, cz) with |p|^2 in w in xyzc), with their outward unit
+    // normal and area in bem_na [np] (ghosts: area 0) and (A n, A p.n) in
+    // bem_an, the identity in place of Kbar and the radius enclosing the mesh
+    // (bohr).  DPCM solves for
     // the charges; IEFPCM (bem_ief) for the potential y = S A^-1 q they make,
     // with bem_rv [np] = 2 pi s + F s (the right-hand side per unit field,
     // component l for polarization l) and bem_w [np] = (S A^-1)^-1 s (the
@@ -85,6 +87,7 @@ struct Geometry {
     bool bem = false;
     bool bem_ief = false;
     double4* bem_na = nullptr;
+    double4* bem_an = nullptr;
     double4* bem_rv = nullptr;
     double4* bem_w = nullptr;
     double bem_r = 0.0;
@@ -97,8 +100,9 @@ struct Geometry {
 hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double* nrm, const double* area_bohr2,
                               double r_enc_bohr, bool ief, hipStream_t st, int* status);
 // Y = M X (DPCM) or Y = F X (IEFPCM) for ncols real columns (X, Y row-major,
-// ld ldx), generated on the fly in FP64; scratch of bem_scratch_bytes(g).
-size_t bem_scratch_bytes(const Geometry& g);
+// ld ldx), generated on the fly in FP64; scratch of bem_scratch_bytes(g, ncols)
+// (wider launches above 8 columns).
+size_t bem_scratch_bytes(const Geometry& g, int ncols);
 void bem_apply_f64(const Geometry& g, const double* X, double* Y, int ldx, int ncols, hipStream_t st, double* scratch,
                    const int32_t* stop = nullptr, const hipEvent_t* ev = nullptr);
 // Solves (S A^-1) X = B for nc <= 8 real columns (IEFPCM's single layer, ghost
@@ -356,6 +360,16 @@ void msb_givens(int R, const double* Hb, int ldh, int NW, int K0, int nc, const 
 // triangular factors (rst: msb_rst_elems(NW, kcols) complex), back
 // substitution (kcols <= 4096) and x = V y over kcols columns
 size_t msb_rst_elems(int NW, int kcols);
+// The basis (kcols columns in the block layout) as a row-major [nup][ldw]
+// matrix (columns kcols..ldw-1 zero), and a product Z [nup][ldz] with it back
+// in the block layout; x = V y per pair over its done[p] (else kcols) columns
+// for any basis in that layout.
+void msb_basis_gather(int R, const double* V, int64_t vstride, int kcols, int64_t nup, double* W, int ldw,
+                      hipStream_t st);
+void msb_basis_scatter(int R, const double* Z, int ldz, int kcols, int64_t nup, double* TV, int64_t vstride,
+                       hipStream_t st);
+void msb_xcombine(int R, const double* V, int64_t vstride, int kcols, const int32_t* done, const double2* y, int P,
+                  double2* x, int ldx, int64_t nup, hipStream_t st);
 void msb_finish_solve(int R, const double* Hb, int ldh, int NW, int kcols, const double2* z, const double* rc,
                       const double2* rs, const int32_t* done, double2* rst, const double2* g, double2* y,
                       const double* V, int64_t vstride, double2* x, int ldx, int64_t nup, hipStream_t st);

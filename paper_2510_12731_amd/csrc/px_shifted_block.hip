@@ -864,6 +864,30 @@ __global__ __launch_bounds__(BST) void k_msb_backsub(const double2* __restrict__
     }
 }
 
+// W[row][K] = Vcol_K[row] = V[K / R][row][K % R] for K < kcols, 0 up to ldw:
+// the basis as one row-major matrix, for a single operator apply over it.
+__global__ void k_msb_basis_gather(const double* __restrict__ V, int64_t vstride, int R, int kcols, int64_t nup,
+                                   double* __restrict__ W, int ldw)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nup * ldw) return;
+    const int64_t row = t / ldw;
+    const int K = (int)(t - row * ldw);
+    W[t] = K < kcols ? V[(size_t)(K / R) * vstride + (size_t)row * R + K % R] : 0.0;
+}
+
+// TV[K / R][row][K % R] = Z[row][K] for K < kcols: an operator's product with
+// the basis back in the basis layout.
+__global__ void k_msb_basis_scatter(const double* __restrict__ Z, int ldz, int R, int kcols, int64_t nup,
+                                    double* __restrict__ TV, int64_t vstride)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nup * kcols) return;
+    const int64_t row = t / kcols;
+    const int K = (int)(t - row * kcols);
+    TV[(size_t)(K / R) * vstride + (size_t)row * R + K % R] = Z[(size_t)row * ldz + K];
+}
+
 // x[row][p] = sum_K Vcol_K[row] y[K][p] over the pair's K_p columns,
 // Vcol_K = V[K / R][row][K % R]: tiles of 32 rows x 64 pairs, TJB blocks of the
 // basis per LDS stage, up to the tile's largest K_p (blocks of steps issued
@@ -1037,6 +1061,34 @@ void msb_givens(int R, const double* Hb, int ldh, int NW, int K0, int nc, const 
 }
 
 size_t msb_rst_elems(int NW, int kcols) { return (size_t)kcols * (kcols + 1) / 2 * NW; }
+
+void msb_basis_gather(int R, const double* V, int64_t vstride, int kcols, int64_t nup, double* W, int ldw,
+                      hipStream_t st)
+{
+    const int64_t len = nup * ldw;
+    hipLaunchKernelGGL(k_msb_basis_gather, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, V, vstride, R, kcols,
+                       nup, W, ldw);
+}
+
+void msb_basis_scatter(int R, const double* Z, int ldz, int kcols, int64_t nup, double* TV, int64_t vstride,
+                       hipStream_t st)
+{
+    const int64_t len = nup * kcols;
+    if (len == 0) return;
+    hipLaunchKernelGGL(k_msb_basis_scatter, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, Z, ldz, R, kcols,
+                       nup, TV, vstride);
+}
+
+void msb_xcombine(int R, const double* V, int64_t vstride, int kcols, const int32_t* done, const double2* y, int P,
+                  double2* x, int ldx, int64_t nup, hipStream_t st)
+{
+    if (kcols < 1) return;
+    const dim3 gx((unsigned)((nup + 31) / 32), (unsigned)((P + 63) / 64));
+    if (R == 2)
+        hipLaunchKernelGGL(k_msb_xcombine<2>, gx, dim3(256), 0, st, V, vstride, kcols, done, y, P, x, ldx, nup);
+    else
+        hipLaunchKernelGGL(k_msb_xcombine<3>, gx, dim3(256), 0, st, V, vstride, kcols, done, y, P, x, ldx, nup);
+}
 
 void msb_finish_solve(int R, const double* Hb, int ldh, int NW, int kcols, const double2* z, const double* rc,
                       const double2* rs, const int32_t* done, double2* rst, const double2* g, double2* y,

@@ -455,7 +455,7 @@ struct pxStructure_t {
     ~pxStructure_t()
     {
         ws.release();
-        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, g.bem_rv, g.bem_w, d_perm, d_col_pol, d_omega, x, b};
+        void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, g.bem_an, g.bem_rv, g.bem_w, d_perm, d_col_pol, d_omega, x, b};
         for (void* p : ps) pxs::dfree(p);
         // the stored T came from the block cache
         for (void* p : {(void*)t32, (void*)t64}) {

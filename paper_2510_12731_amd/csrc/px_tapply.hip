@@ -1673,7 +1673,7 @@ void tapply_f32(const Geometry& g, const float* X, float* Y, int ldx, int ncols,
 
 size_t tapply_f64_scratch_bytes(const Geometry& g, int ncols)
 {
-    if (g.bem) return bem_scratch_bytes(g);
+    if (g.bem) return bem_scratch_bytes(g, ncols);
     if (ncols > 8) return 0;
     const int ns = g.model ? narrow_splits(g) : std::max(narrow_splits(g), narrow_q_splits(g));
     return (size_t)ns * (g.model ? 4 : 1) * g.np * ncols * sizeof(double);

@@ -224,3 +224,28 @@ def test_bem_ief_sphere_full_size():
         say(f"   column (w={om[w]:.3f} eV, pol {pol}): oracle residual {rel:.2e}")
         assert rel <= 1e-8 + 1e-9
     s.close()
+
+
+@pytest.mark.parametrize("form", ["dpcm", "iefpcm"])
+def test_bem_phase_true_residuals_and_short_phase(form):
+    """The block phase checks every pair's true FP64 residual through one
+    operator apply over its basis: with the default step cap no pair needs a
+    blocked cycle (one cycle each, relres <= rel_tol); with the phase cut
+    short (4 block steps) the blocked solver takes every pair above rel_tol,
+    and both spectra match the oracle."""
+    c = cases()[0]
+    solve = O.bem_ief_solve_spectrum if form == "iefpcm" else O.bem_solve_spectrum
+    ref = solve(c["mesh"], c["om"], c["eps"], 1.0, c["pol"], 1e-4)
+    for cap in (400, 4):
+        s = px.Structure.bem(c["mesh"], 1.0, px.default_stream(), form=form)
+        s.set_frequencies(c["om"], c["pol"], 1e-4, c["eps"])
+        st = s.solve(precision=px.PX_FP64, rel_tol=1e-12, shifted_max_steps=cap)
+        it, cyc, rr = s.stats()
+        e = rel_err(s.spectrum()[1], ref["sigma"])
+        say(f"[bem {form} phase cap {cap}] status {st} cycles max {cyc.max()} relres {rr.max():.1e} sigma {e:.1e}")
+        assert st == px.PX_OK and rr.max() <= 1e-12 and e <= 1e-10
+        if cap == 400:
+            assert cyc.max() == 1
+        else:
+            assert cyc.max() > 1
+        s.close()
