@@ -89,6 +89,29 @@ def test_capped_block_phase_hands_over_to_blocked_solver(precision, tol, bound):
     s.close()
 
 
+def test_block_phase_checks_true_residuals_through_its_basis():
+    """128 frequencies x 3 polarizations of the small sphere: the phase's
+    basis (k R real columns) is narrower than the pairs' 768 real columns, so
+    every pair's true FP64 residual comes from one apply over the basis
+    (T x = (T V) y, then b - (Kbar T x - z x)) instead of one over all pairs;
+    the spectrum matches the oracle and every pair ends inside the phase."""
+    c = C.small_sphere()
+    om = np.linspace(float(c["omega_ev"].min()), float(c["omega_ev"].max()), 128)
+    say(f"[block basis residual] small sphere {len(c['xyz'])} atoms, {len(om)} frequencies, xyz")
+    ref = O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), om, 0b111, 1e-4)
+    s, st, alpha, sigma, it, cyc, rr = solve(c["xyz"], c["params"], om, 0b111, px.PX_FP64, 1e-11, shifted=2)
+    tm = s.timings()
+    applied = tm["cols_f64_padded"] - 3 * (tm["n_tapply_f64"] - 1)
+    say(f"   status {st} block steps max {it.max()} cycles max {cyc.max()} relres max {rr.max():.2e}; "
+        f"residual apply over {applied} real columns")
+    assert st == px.PX_OK and rr.max() <= 1e-11 and cyc.max() == 1
+    assert applied < 2 * len(om) * 3, "the residual check went through the basis"
+    e, ea = rel_err(sigma, ref["sigma"]), rel_err(alpha, ref["alpha"])
+    say(f"   rel_err sigma {e:.2e} alpha {ea:.2e}")
+    assert e <= 1e-10 and ea <= 1e-9
+    s.close()
+
+
 def test_flat_structure_falls_back_per_polarization():
     """A graphene disk's z right-hand side is zero: shifted = 2 runs one
     process per polarization there, with the same result as shifted = 1; its
