@@ -307,6 +307,32 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
  * missed rel_tol within max_cycles (results stay readable). */
 pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt);
 
+/* The same solve, started without waiting for it: the call enqueues the
+ * solve's first steps on the structure's stream and returns.  The solve's
+ * restart and convergence decisions are taken on the host, so it advances
+ * only inside later calls: pxSolveProgress enqueues what it can without
+ * waiting for the device (call it between other host work), pxSolveWait
+ * drives it to the end, and every other call on the structure (pxGet*,
+ * pxSetFrequencies, another solve, pxApplyOperator, the probe fields,
+ * pxSolveBatch, pxServerSubmit, pxSolveFootprint) first completes it.
+ * pxDestroyStructure abandons a solve in progress once the device is idle.
+ * Errors: as pxSolveSpectrum for the arguments (PX_E_STATE without
+ * frequencies, PX_E_INVALID for bad options); PX_E_OOM / PX_E_DEVICE from the
+ * first steps. */
+pxStatus pxSolveSpectrumAsync(pxStructure s, const pxSolveOptions* opt);
+
+/* Advances an asynchronous solve without waiting for the device; *done = 1
+ * once it has finished (also when none was started), else 0.  The solve's
+ * status is then read with pxGetSolveStatus (or pxSolveWait).  Errors:
+ * PX_E_INVALID for null arguments; PX_E_DEVICE / PX_E_OOM if the solve failed
+ * (it is dropped). */
+pxStatus pxSolveProgress(pxStructure s, int32_t* done);
+
+/* Completes an asynchronous solve (returns at once if none is in progress)
+ * and returns the status of the structure's last solve: PX_OK, PX_E_NOTCONV
+ * (results readable), or the error that ended it. */
+pxStatus pxSolveWait(pxStructure s);
+
 /* Solves several structures together (all must use the same HIP stream, have
  * their frequencies set, and appear once).  One-material PX_WFQ structures
  * with opt->shifted >= 1 (default 2), and every structure of 1024 atoms or

@@ -29,7 +29,8 @@ EXPORTED = ["pxDefaultSolveOptions", "pxCreateStructure", "pxCreateStructureHete
             "pxDestroyStructure", "pxLastError", "pxServerCreate", "pxServerSubmit", "pxServerStep",
             "pxServerQuery", "pxServerDestroy", "pxInducedField", "pxProbeField", "pxGetProbeStats",
             "pxServerMemory", "pxSolveFootprint", "pxGetSolveStatus", "pxApplyOperatorNoAlloc", "pxCreateBem",
-            "pxCreateBemIefpcm", "pxSetAllocator", "pxReleaseCache"]
+            "pxCreateBemIefpcm", "pxSetAllocator", "pxReleaseCache", "pxSolveSpectrumAsync", "pxSolveProgress",
+            "pxSolveWait"]
 
 
 class PxError(RuntimeError):
@@ -85,6 +86,9 @@ def load(path: str = LIB_PATH):
                                             ctypes.POINTER(_vp)]
     lib.pxSetFrequencies.argtypes = [_vp, i32, _dp, u32, ctypes.c_double, _dp]
     lib.pxSolveSpectrum.argtypes = [_vp, ctypes.POINTER(pxSolveOptions)]
+    lib.pxSolveSpectrumAsync.argtypes = [_vp, ctypes.POINTER(pxSolveOptions)]
+    lib.pxSolveProgress.argtypes = [_vp, ctypes.POINTER(i32)]
+    lib.pxSolveWait.argtypes = [_vp]
     lib.pxSolveBatch.argtypes = [ctypes.POINTER(_vp), i32, ctypes.POINTER(pxSolveOptions)]
     lib.pxGetCharges.argtypes = [_vp, i32, i32, _dp, _dp]
     lib.pxGetSpectrum.argtypes = [_vp, _dp, _dp]
@@ -265,6 +269,20 @@ def pxSetFrequencies(h, omega_ev, pol_mask, e0_au, alpha_ib=None):
 
 def pxSolveSpectrum(h, opt: pxSolveOptions | None = None):
     return _check(load().pxSolveSpectrum(h, None if opt is None else ctypes.byref(opt)), (PX_OK, PX_E_NOTCONV))
+
+
+def pxSolveSpectrumAsync(h, opt: pxSolveOptions | None = None):
+    return _check(load().pxSolveSpectrumAsync(h, None if opt is None else ctypes.byref(opt)))
+
+
+def pxSolveProgress(h):
+    done = ctypes.c_int32()
+    _check(load().pxSolveProgress(h, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def pxSolveWait(h):
+    return _check(load().pxSolveWait(h), (PX_OK, PX_E_NOTCONV))
 
 
 def pxSolveBatch(handles, opt: pxSolveOptions | None = None):
@@ -544,6 +562,17 @@ class Structure:
 
     def solve(self, **kw):
         return pxSolveSpectrum(self.h, solve_options(**kw))
+
+    def solve_async(self, **kw):
+        """Starts the solve (pxSolveSpectrumAsync); progress() advances it,
+        wait() completes it."""
+        return pxSolveSpectrumAsync(self.h, solve_options(**kw))
+
+    def progress(self):
+        return pxSolveProgress(self.h)
+
+    def wait(self):
+        return pxSolveWait(self.h)
 
     def spectrum(self):
         return pxGetSpectrum(self.h, self.n_omega)

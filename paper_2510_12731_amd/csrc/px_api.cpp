@@ -1455,6 +1455,7 @@ pxStatus solve_impl(pxStructure_t* s, const pxSolveOptions& o)
     return PX_OK;
 }
 
+
 bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 pxStatus status_of(const HipError& h) { return h.e == hipErrorOutOfMemory ? PX_E_OOM : PX_E_DEVICE; }
@@ -1472,6 +1473,57 @@ pxStatus guarded(F&& f)
         return fail(PX_E_DEVICE, "unexpected exception");
     }
 }
+
+// A solve of pxSolveSpectrumAsync: the whole solve on the structure's stream,
+// advanced by later calls.
+class AsyncSolve : public pxs::PendingSolve {
+  public:
+    AsyncSolve(pxStructure_t* s, const pxSolveOptions& o) : w(s, o, false) {}
+    WholeSolve w;
+};
+
+// Steps enqueued per non-blocking call of an asynchronous solve.
+constexpr int kAsyncSteps = 64;
+
+// Advances s's asynchronous solve (to its end when `wait`); the solve is
+// dropped once finished or when it fails.  Returns whether it finished.
+bool advance_pending(pxStructure_t* s, bool wait)
+{
+    auto* a = static_cast<AsyncSolve*>(s->pending.get());
+    try {
+        if (wait) {
+            while (!a->w.finished()) a->w.advance(1 << 30, true);
+        } else {
+            a->w.advance(kAsyncSteps, false);
+        }
+    } catch (...) {
+        (void)hipDeviceSynchronize();
+        s->pending.reset();
+        s->last_status = PX_E_DEVICE;
+        s->last_error = "the asynchronous solve failed";
+        throw;
+    }
+    if (!a->w.finished()) return false;
+    s->pending.reset();
+    return true;
+}
+
+// Every call on a structure first completes an asynchronous solve in
+// progress (its own status stays readable with pxGetSolveStatus).
+pxStatus settle(pxStructure_t* s)
+{
+    if (!s || !s->pending) return PX_OK;
+    return guarded([&]() -> pxStatus {
+        advance_pending(s, true);
+        return PX_OK;
+    });
+}
+
+#define PX_SETTLE(s)                            \
+    do {                                        \
+        const pxStatus st_ = settle(s);         \
+        if (st_ != PX_OK) return st_;           \
+    } while (0)
 
 // ---- several whole solves at once from one host thread (batch and server) ----
 // Each structure runs as a WholeSolve on a stream of its own; the driver
@@ -1844,6 +1896,7 @@ pxStatus pxSetFrequencies(pxStructure s, int32_t n_omega, const double* omega_ev
                           const double* alpha_ib)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !omega_ev) return fail(PX_E_INVALID, "null argument");
     if (n_omega < 1) return fail(PX_E_INVALID, "n_omega must be >= 1");
     if ((pol_mask & 7u) == 0 || (pol_mask & ~7u)) return fail(PX_E_INVALID, "pol_mask must be a non-empty subset of 0b111");
@@ -1905,15 +1958,57 @@ pxStatus pxSolveSpectrum(pxStructure s, const pxSolveOptions* opt)
 {
     g_err.clear();
     if (!s) return fail(PX_E_INVALID, "null structure");
+    PX_SETTLE(s);
     pxSolveOptions o;
     pxDefaultSolveOptions(&o);
     if (opt) o = *opt;
     return guarded([&]() -> pxStatus { return solve_impl(s, o); });
 }
 
+pxStatus pxSolveSpectrumAsync(pxStructure s, const pxSolveOptions* opt)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    PX_SETTLE(s);
+    pxSolveOptions o;
+    pxDefaultSolveOptions(&o);
+    if (opt) o = *opt;
+    if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveSpectrumAsync: call pxSetFrequencies first");
+    if (check_options(o) != PX_OK) return PX_E_INVALID;
+    return guarded([&]() -> pxStatus {
+        s->pending.reset(new AsyncSolve(s, o));
+        advance_pending(s, false);
+        return PX_OK;
+    });
+}
+
+pxStatus pxSolveProgress(pxStructure s, int32_t* done)
+{
+    g_err.clear();
+    if (!s || !done) return fail(PX_E_INVALID, "null argument");
+    *done = 1;
+    if (!s->pending) return PX_OK;
+    return guarded([&]() -> pxStatus {
+        *done = advance_pending(s, false) ? 1 : 0;
+        return PX_OK;
+    });
+}
+
+pxStatus pxSolveWait(pxStructure s)
+{
+    g_err.clear();
+    if (!s) return fail(PX_E_INVALID, "null structure");
+    PX_SETTLE(s);
+    if (s->last_status != PX_OK) return fail(s->last_status, s->last_error);
+    return PX_OK;
+}
+
 pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* opt)
 {
     g_err.clear();
+    if (ss)
+        for (int32_t k = 0; k < n; ++k)
+            if (ss[k]) PX_SETTLE(ss[k]);
     if (!ss || n < 0) return fail(PX_E_INVALID, "null argument");
     if (n == 0) return PX_OK;
     pxSolveOptions o;
@@ -2013,6 +2108,7 @@ pxStatus pxSolveBatch(const pxStructure* ss, int32_t n, const pxSolveOptions* op
 pxStatus pxGetCharges(pxStructure s, int32_t i_omega, int32_t pol, double* q, double* mu)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !q) return fail(PX_E_INVALID, "null argument");
     if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
     if (i_omega < 0 || i_omega >= s->n_omega || pol < 0 || pol > 2 || !(s->pol_mask & (1u << pol)))
@@ -2119,6 +2215,7 @@ pxStatus pxInducedField(pxStructure s, int32_t i_omega, int32_t pol, int64_t npt
                         double* field, double* density)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxInducedField: invalid argument");
     if (s->model == PX_BEM) return fail(PX_E_INVALID, "pxInducedField: the Gaussian densities are those of the atomistic models");
     if (!s->solved) return fail(PX_E_STATE, "pxInducedField: no solved spectrum");
@@ -2141,6 +2238,7 @@ pxStatus pxProbeField(pxStructure s, const double* q, const double* mu, int64_t 
                       double* field, double* density)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !q || npts < 0 || (npts > 0 && !pts_ang)) return fail(PX_E_INVALID, "pxProbeField: invalid argument");
     if (s->model == PX_BEM) return fail(PX_E_INVALID, "pxProbeField: the Gaussian densities are those of the atomistic models");
     if (mu && s->model != PX_WFQFMU) return fail(PX_E_INVALID, "pxProbeField: dipoles given for an omegaFQ structure");
@@ -2168,6 +2266,7 @@ pxStatus pxProbeField(pxStructure s, const double* q, const double* mu, int64_t 
 pxStatus pxGetProbeStats(pxStructure s, double* out2)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !out2) return fail(PX_E_INVALID, "null argument");
     out2[0] = s->probe[0];
     out2[1] = s->probe[1];
@@ -2177,6 +2276,7 @@ pxStatus pxGetProbeStats(pxStructure s, double* out2)
 pxStatus pxGetSpectrum(pxStructure s, double* alpha, double* sigma_abs)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
     if (alpha) std::copy(s->alpha.begin(), s->alpha.end(), alpha);
@@ -2187,6 +2287,7 @@ pxStatus pxGetSpectrum(pxStructure s, double* alpha, double* sigma_abs)
 pxStatus pxGetSolveStats(pxStructure s, int32_t* iterations, int32_t* cycles, double* rel_res)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (!s->solved) return fail(PX_E_STATE, "no solved spectrum");
     if (iterations) std::copy(s->iters.begin(), s->iters.end(), iterations);
@@ -2199,6 +2300,7 @@ pxStatus pxApplyOperator(pxStructure s, int32_t precision, int32_t ncol, const d
                          const double* alpha_ib, const double* x, double* y)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !omega_ev || !x || !y) return fail(PX_E_INVALID, "null argument");
     if (ncol < 1) return fail(PX_E_INVALID, "ncol must be >= 1");
     if (precision != PX_FP64 && precision != PX_MIXED) return fail(PX_E_INVALID, "unknown precision");
@@ -2265,6 +2367,7 @@ pxStatus pxApplyOperatorNoAlloc(pxStructure s, int32_t ncol, const double* omega
                                 const double* x, double* y)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !omega_ev || !x || !y) return fail(PX_E_INVALID, "null argument");
     if (ncol < 1 || ncol > 4) return fail(PX_E_INVALID, "pxApplyOperatorNoAlloc: ncol must be in [1, 4]");
     if (s->model == PX_WFQFMU && !alpha_ib) return fail(PX_E_INVALID, "alpha_ib required for the dipole model");
@@ -2346,6 +2449,7 @@ pxStatus pxGetSize(pxStructure s, int64_t* n_atoms, int64_t* n_unknowns)
 pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double* flop4)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (launches4) std::copy(s->tstats, s->tstats + 4, launches4);
     if (ms4) std::copy(s->tms, s->tms + 4, ms4);
@@ -2356,6 +2460,7 @@ pxStatus pxGetTApplyStats(pxStructure s, int64_t* launches4, double* ms4, double
 pxStatus pxGetWork(pxStructure s, double* work3)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !work3) return fail(PX_E_INVALID, "null argument");
     std::copy(s->work, s->work + 3, work3);
     return PX_OK;
@@ -2364,6 +2469,7 @@ pxStatus pxGetWork(pxStructure s, double* work3)
 pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s) return fail(PX_E_INVALID, "null structure");
     if (ms6) std::copy(s->ms, s->ms + 6, ms6);
     if (counts6) std::copy(s->counts, s->counts + 6, counts6);
@@ -2373,8 +2479,13 @@ pxStatus pxGetTimings(pxStructure s, double* ms6, int64_t* counts6)
 void pxDestroyStructure(pxStructure s)
 {
     if (!s) return;
+    // an asynchronous solve in progress is abandoned once the stream is idle
     const hipError_t e = s->st ? hipStreamSynchronize(s->st) : hipDeviceSynchronize();
     s->idle = e == hipSuccess;
+    if (s->pending) {
+        (void)hipDeviceSynchronize();   // its second stream too
+        s->pending.reset();
+    }
     delete s;
 }
 
@@ -2424,6 +2535,7 @@ pxStatus pxServerCreate(double memory_budget_bytes, const pxSolveOptions* opt, v
 pxStatus pxServerSubmit(pxServer sv, pxStructure s)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!sv || !s) return fail(PX_E_INVALID, "null argument");
     if (s->ncol == 0) return fail(PX_E_STATE, "pxServerSubmit: call pxSetFrequencies first");
     if (s->st != sv->st) return fail(PX_E_INVALID, "pxServerSubmit: structure uses another stream");
@@ -2526,6 +2638,7 @@ pxStatus pxServerMemory(pxServer sv, double* bytes_in_use, double* budget_bytes,
 pxStatus pxSolveFootprint(pxStructure s, const pxSolveOptions* opt, double* bytes)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !bytes) return fail(PX_E_INVALID, "null argument");
     if (s->ncol == 0) return fail(PX_E_STATE, "pxSolveFootprint: call pxSetFrequencies first");
     pxSolveOptions o;
@@ -2539,6 +2652,7 @@ pxStatus pxSolveFootprint(pxStructure s, const pxSolveOptions* opt, double* byte
 pxStatus pxGetSolveStatus(pxStructure s, int32_t* status, char* message, int32_t message_len)
 {
     g_err.clear();
+    if (s) PX_SETTLE(s);
     if (!s || !status) return fail(PX_E_INVALID, "null argument");
     *status = (int32_t)s->last_status;
     if (message && message_len > 0) {

@@ -7,6 +7,7 @@
 #include <string>
 #include <array>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -399,6 +400,14 @@ namespace pxs {
 void shift_bem_of(const pxStructure_t* s, const double* e2, double& zr, double& zi);
 }  // namespace pxs
 
+namespace pxs {
+// A solve started by pxSolveSpectrumAsync and not finished yet (px_api.cpp).
+class PendingSolve {
+  public:
+    virtual ~PendingSolve() = default;
+};
+}  // namespace pxs
+
 struct pxStructure_t {
     px::Geometry g;
     pxModel model = PX_WFQ;
@@ -452,8 +461,11 @@ struct pxStructure_t {
     pxStatus last_status = PX_E_STATE;
     std::string last_error = "not solved";
 
+    std::unique_ptr<pxs::PendingSolve> pending;   // an asynchronous solve in progress
+
     ~pxStructure_t()
     {
+        pending.reset();
         ws.release();
         void* ps[] = {g.xyz32, g.xyz64, g.glo, g.ghi, g.row_ptr, g.col, g.val, g.type, g.hrow, g.near_off, g.near_col, g.near_val, g.xyzc, g.bem_na, g.bem_an, g.bem_rv, g.bem_w, d_perm, d_col_pol, d_omega, x, b};
         for (void* p : ps) pxs::dfree(p);
