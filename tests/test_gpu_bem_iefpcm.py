@@ -249,3 +249,28 @@ def test_bem_phase_true_residuals_and_short_phase(form):
         else:
             assert cyc.max() > 1
         s.close()
+
+
+@pytest.mark.parametrize("form", ["dpcm", "iefpcm"])
+def test_bem_four_tesserae(form):
+    """The smallest closed mesh: the four faces of a regular tetrahedron (edge
+    20 Angstrom), one tile of 256 rows with 252 ghosts, against the oracle."""
+    a = 20.0
+    v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=float) * a / np.sqrt(8.0)
+    faces = [(1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1)]
+    cen = np.array([v[list(f)].mean(axis=0) for f in faces])
+    nrm = cen / np.linalg.norm(cen, axis=1)[:, None]
+    area = np.full(4, np.sqrt(3.0) / 4.0 * a * a)
+    m = dict(cen=cen, nrm=nrm, area=area, r_enc=float(np.linalg.norm(v[0])))
+    om = np.linspace(2.5, 4.0, 5)
+    eps = M.drude_permittivity(AG, om)
+    solve = O.bem_ief_solve_spectrum if form == "iefpcm" else O.bem_solve_spectrum
+    ref = solve(m, om, eps, 1.0, 0b101, 1e-4)
+    s = px.Structure.bem(m, 1.0, px.default_stream(), form=form)
+    s.set_frequencies(om, 0b101, 1e-4, eps)
+    assert s.solve(precision=px.PX_FP64, rel_tol=1e-12) == px.PX_OK
+    e_s, e_a = rel_err(s.spectrum()[1], ref["sigma"]), rel_err(s.spectrum()[0], ref["alpha"])
+    e_q = rel_err(s.charges(2, 2), ref["q"][2, 1])
+    say(f"[bem {form} tetrahedron] sigma {e_s:.1e} alpha {e_a:.1e} charges {e_q:.1e}")
+    assert e_s <= 1e-10 and e_a <= 1e-9 and e_q <= 1e-8
+    s.close()
