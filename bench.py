@@ -206,7 +206,9 @@ def host_info():
 # oracle is single-threaded C): 'c1' the small spectrum in full, 'lu' one
 # frequency of an N-atom sphere of the headline's lattice (dense assembly of
 # A(w), its complete LU, three polarizations' solves), 'asm' the dense
-# assembly alone at the headline's size.
+# assembly alone at the headline's size; 'bem' / 'bemief' one frequency of an
+# icosphere of R = 80 A (refinement level argv[4]) in the DPCM / IEFPCM form,
+# three polarizations (matrices, the IEFPCM product, LU, solves).
 _ORACLE_TASK = r"""
 import json, os, sys, time
 os.sched_setaffinity(0, {int(sys.argv[2])})
@@ -222,6 +224,14 @@ if task == "c1":
     c = C.small_sphere()
     O.solve_spectrum(0, c["xyz"], M.param_vector(c["params"]), c["omega_ev"], c["pol_mask"], c["e0"])
     out = dict(seconds=time.perf_counter() - t0, columns=len(c["omega_ev"]))
+elif task in ("bem", "bemief"):
+    from workloads import mesh as ME
+    m = ME.sphere(80.0, int(sys.argv[4]))
+    om = np.array([3.6])
+    eps = M.drude_permittivity(M.load("ag_bem"), om)
+    solve = O.bem_ief_solve_spectrum if task == "bemief" else O.bem_solve_spectrum
+    solve(m, om, eps, 1.0, 0b111, 1e-4)
+    out = dict(seconds=time.perf_counter() - t0, n=len(m["area"]))
 else:
     n = int(sys.argv[4])
     c = C.sphere_20k(n, 3)
@@ -294,6 +304,26 @@ def cpu_baseline(n_head, npol, n_lu=3000, all_core_cap=16):
                                note=(f"{k} independent frequency shards at N={n_lu} on {k} pinned cores at once "
                                      "(measured), each scaled to the headline's N as above")),
                 measured_s=round(time.perf_counter() - t0, 1))
+
+
+def bem_cpu_baseline(k_mesh=3, k_bench=5):
+    """The oracle's BEM direct solve on the host, both forms at once on two
+    pinned cores: one frequency (three polarizations) of the level-k_mesh
+    icosphere, scaled by (n_bench / n)^3 to the benchmark's level-k_bench
+    sphere (the LU and, for IEFPCM, the dense product dominate)."""
+    cores = sorted(os.sched_getaffinity(0))
+    c0, c1 = cores[0], cores[1 % len(cores)]
+    r = _oracle_children([(c0, ("bem", k_mesh)), (c1, ("bemief", k_mesh))])
+    n_bench = 20 * 4 ** k_bench
+    out = {}
+    for form, x in zip(("dpcm", "iefpcm"), r):
+        scale = (n_bench / x["n"]) ** 3
+        out[form] = dict(value=round(3.0 / (x["seconds"] * scale), 8), unit="freq-solves/s", cores=1, kind="oracle",
+                         sample=(f"one core (pinned): one frequency, 3 polarizations, of the {x['n']}-tesserae "
+                                 f"sphere in full ({x['seconds']:.1f} s: matrices"
+                                 f"{', the product F S A^-1' if form == 'iefpcm' else ''}, LU, solves), scaled by "
+                                 f"({n_bench}/{x['n']})^3 = {scale:.0f}; extrapolated, not run at {n_bench}"))
+    return out
 
 
 def config1_parity(pxm):
@@ -404,7 +434,7 @@ def batch_full_extra(pxm, fp64_every=8):
 BEM_PAIR_FLOP = {"dpcm": 21, "iefpcm": 22}
 
 
-def bem_extra(pxm, form="dpcm"):
+def bem_extra(pxm, form="dpcm", cpu=None):
     """BEM (DPCM or IEFPCM): a 20,480-tesserae Ag sphere (R = 80 A), 64 w x 3
     pol, the default solve against the FP64 blocked solver, and the oracle
     residual of a sampled column (IEFPCM: its charges in the printed
@@ -475,6 +505,8 @@ def bem_extra(pxm, form="dpcm"):
                oracle_rel_residual_at_peak=res, peak_ev=round(float(om[w]), 3), roofline=roof)
     if form == "iefpcm":
         out.update(create_s=round(r["create_s"], 3), charges_one_column_s=round(t_q, 4))
+    if cpu is not None:
+        out["cpu_baseline"] = cpu[form]
     return out
 
 
@@ -739,6 +771,11 @@ def main():
         log("[bench] oracle CPU baseline (pinned cores) ...")
         cpu = cpu_baseline(args.n, 3, n_lu=args.cpu_lu_n)
         log(f"[bench] oracle CPU baseline done in {cpu['measured_s']} s")
+    bem_cpu = None
+    if not (args.no_cpu_baseline or args.kernel_sample or args.copy_calibration > 0 or args.no_extras or
+            args.workload not in ("sphere", "bem")):
+        log("[bench] oracle CPU baseline, BEM (two pinned cores) ...")
+        bem_cpu = bem_cpu_baseline()
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -771,7 +808,7 @@ def main():
         return
     if args.workload == "bem":
         for form in ("dpcm", "iefpcm"):
-            print(json.dumps(bem_extra(pxm, form)), flush=True)
+            print(json.dumps(bem_extra(pxm, form, bem_cpu)), flush=True)
         return
     if args.workload == "serving":
         out = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
@@ -950,9 +987,9 @@ def main():
         log("[bench] config 5: serving mix (1k-8k atoms) ...")
         extra["serving"] = serving_extra(pxm, 16, 1000, 8000, 5, 0.75)
         log("[bench] BEM sphere ...")
-        extra["bem"] = bem_extra(pxm)
+        extra["bem"] = bem_extra(pxm, "dpcm", bem_cpu)
         log("[bench] BEM sphere, IEFPCM ...")
-        extra["bem_iefpcm"] = bem_extra(pxm, "iefpcm")
+        extra["bem_iefpcm"] = bem_extra(pxm, "iefpcm", bem_cpu)
 
     out = {
         "metric": "omegaFQ freq-solves/s at N=20k (rel res 1e-8)",
