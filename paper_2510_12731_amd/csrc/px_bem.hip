@@ -19,12 +19,12 @@
 // M and F are real and shared by every frequency, so the structure runs
 // through the omegaFQ solver with the tesserae as its sites, the identity in
 // place of Kbar, M or F in place of T and z(w) in place of z_q(w): the
-// shared-Krylov phase (one Arnoldi process per polarization for every
-// frequency), the blocked solver's true FP64 residuals and the observables
-// are the same code.
+// shared-Krylov phase (one block Arnoldi process over the polarizations, or
+// one per polarization, for every frequency), the true FP64 residuals and
+// the observables are the same code.
 //
 // The operators are generated on the fly in FP64 (M and F are not symmetric
-// and not stored): one thread per row i, the source tesserae read
+// and not stored): one or two rows per thread, the source tesserae read
 // wave-uniform (through the scalar cache) in source splits, a deterministic
 // split sum.  The single-layer solves are Jacobi-preconditioned conjugate
 // gradients with every scalar kept on the device.
