@@ -403,10 +403,11 @@ void pxServerDestroy(pxServer sv);
 
 /* HBM footprint (bytes) of solving s whole with the options opt (NULL:
  * defaults): the active column block's vectors and T-apply scratch, the
- * near-field list, and the shared-Krylov phase's basis and factors at
- * opt->shifted_max_steps or the blocked solver's basis at max_restart_m; the
- * figure the server admits whole solves by.  PX_E_STATE before
- * pxSetFrequencies. */
+ * near-field list, a stored T the tuner may build (FP64 up to 4 GiB, FP32
+ * for PX_MIXED; kept by the structure), and the shared-Krylov phase's basis,
+ * factors and true-residual buffers at opt->shifted_max_steps or the blocked
+ * solver's basis at max_restart_m; the figure the server admits whole solves
+ * by.  PX_E_STATE before pxSetFrequencies. */
 pxStatus pxSolveFootprint(pxStructure s, const pxSolveOptions* opt, double* bytes);
 
 /* Status of the structure's last solve (pxSolveSpectrum, pxSolveBatch or the

@@ -825,6 +825,14 @@ bool pooled_solve(const pxStructure_t* s, const pxSolveOptions& o)
     return shifted_applies(s, o) || s->g.n >= kPoolMinAtoms;
 }
 
+// A block Krylov space of R columns per step spans all nu unknowns after
+// ceil(nu / R) steps, where every pair's GMRES iterate is exact: the phase
+// never needs more (two steps of margin for the rounding).
+int phase_step_limit(const pxStructure_t* s, int R)
+{
+    return (int)std::min<int64_t>((s->g.nu + R - 1) / R + 2, 1 << 20);
+}
+
 // The step loop of a shared-Krylov phase: steps on the structure's stream, the
 // frequencies' Givens QRs in batches on a second stream of the same priority
 // (beside the next steps' T-applies), the stop flag published once per batch
@@ -959,7 +967,7 @@ class ShiftedRun : public PhaseRun {
         // basis, Hessenberg matrices and triangular factors within a quarter of the free device memory
         size_t fr = 0, tot = 0;
         HC(hipMemGetInfo(&fr, &tot));
-        int kcap = o.shifted_max_steps;
+        int kcap = std::min(o.shifted_max_steps, phase_step_limit(s, 1));
         auto bytes_for = [&](double k) {
             return (k + 1) * (double)nup * R * 8.0 + (k + 1) * k * R * 8.0 + k * (double)P * (8 + 16 + 16 + 16) +
                    k * (k + 1) / 2 * P * 16.0 + (double)px::ms_part2_doubles(R, nup, (int)k) * 8.0;
@@ -1104,7 +1112,7 @@ class BlockShiftedRun : public PhaseRun {
         HC(hipMemGetInfo(&fr, &tot));
         // the back substitution holds a frequency's kcap R rows of its right-hand
         // sides in registers (at most 4096)
-        int kcap = std::min(o.shifted_max_steps, 4096 / R);
+        int kcap = std::min(std::min(o.shifted_max_steps, 4096 / R), phase_step_limit(s, R));
         auto bytes_for = [&](double k) {
             const double kc = k * R;
             return (k + 1) * (double)nup * R * 8.0 + (kc + R) * kc * 8.0 + kc * R * NW * 24.0 +
@@ -1625,10 +1633,26 @@ double solve_footprint(const pxStructure_t* s, const pxSolveOptions& o)
     double b = vec * (5 * 16 + 8 + 8 + 16) + (double)px::tapply_f64_scratch_bytes(s->g, s->g.bem ? 2 * (int)lda : 8) +
                (double)px::tapply_f32_scratch_bytes(s->g, 2 * (int)lda);
     if (s->model == PX_WFQ) b += 6000.0 * (double)s->g.n;   // near-field list (about 400 entries per atom)
+    if (!s->g.bem) {
+        // a stored T the tuner may build and the structure then keeps: FP64
+        // for the true residuals (up to the size it tunes), FP32 for the
+        // mixed-precision blocked cycles
+        const double t64 = nup * nup * 8.0;
+        if (t64 <= kSingleUseTuneMaxBytes) b += t64;
+        if (o.precision == PX_MIXED) b += nup * nup * 4.0;
+    }
     const int m_max = std::max(o.restart_m, o.max_restart_m);
     if (shifted_applies(s, o)) {
-        const double k = o.shifted_max_steps, R = s->npol, P = s->ncol;
+        const double R = s->npol, P = s->ncol;
+        // the block phase's step limit (one process per polarization, its
+        // fallback for a zero right-hand side, can take up to nu steps)
+        const int rk = o.shifted == 2 && s->npol >= 2 ? s->npol : 1;
+        const double k = std::min(o.shifted_max_steps, phase_step_limit(s, rk));
         b += (k + 1) * nup * R * 8.0 + (k + 1) * k * R * R * 8.0 + k * P * 56.0 + k * (k + 1) / 2.0 * P * 16.0;
+        // the true residuals through the basis (taken when its padded width
+        // is at most P): the basis as a matrix and its product (each at most
+        // P columns), the product in the basis layout, T x and the residuals
+        b += 2.0 * nup * P * 8.0 + std::min(k + 1, P / R + 1) * nup * R * 8.0 + 2.0 * nup * (double)s->ldg * 16.0;
     } else {
         b += (m_max + 1.0) * vec * 16.0 + 2.0 * m_max * (m_max + 1.0) * lda * 16.0;
     }

@@ -117,3 +117,36 @@ def test_refusing_allocator_gives_oom_and_leaks_nothing():
         assert state["used"] == 0 and torch.cuda.memory_allocated() == base
     finally:
         px.use_hip_allocator()
+
+
+@pytest.mark.parametrize("what", ["wfq_block_phase", "bem_iefpcm_block_phase"])
+def test_solve_footprint_bounds_the_solve_peak(what):
+    """pxSolveFootprint (the server's admission figure) is at least what a
+    solve takes from the caller's allocator at its peak: the omegaFQ block
+    phase, and the IEFPCM block phase whose true residuals go through its
+    basis (the buffers of that route included)."""
+    import torch
+    from workloads import mesh as ME
+    if what.startswith("wfq"):
+        make = lambda: px.Structure(0, G.fcc_sphere_n(1500, seed=4), AG, px.default_stream())
+        om, extra = OM, None
+    else:
+        m = ME.sphere(40.0, 3)
+        make = lambda: px.Structure.bem(m, 1.0, px.default_stream(), form="iefpcm")
+        om = np.linspace(3.0, 4.4, 48)
+        extra = M.drude_permittivity(M.load("ag_bem"), om)
+    px.use_torch_allocator()
+    try:
+        s = make()
+        s.set_frequencies(om, 0b111, 1e-4, extra)
+        fp = s.footprint(precision=px.PX_FP64, rel_tol=1e-10)
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        assert s.solve(precision=px.PX_FP64, rel_tol=1e-10) == px.PX_OK
+        peak = torch.cuda.max_memory_allocated() - base
+        say(f"[footprint {what}] solve peak {peak / 2**20:.1f} MiB, footprint {fp / 2**20:.1f} MiB")
+        assert 0 < peak <= fp
+        s.close()
+    finally:
+        px.use_hip_allocator()
