@@ -388,7 +388,8 @@ def bem_ief_matrices(m):
 
 
 def bem_ief_rhs(m, pol, e0):
-    """-(2 pi I + F) V with V_i = -E0 s_i,pol: [n] complex."""
+    """-(2 pi I + F) V with V_i = -E0 (s_i - c)_pol, c the area-weighted
+    centroid of the tesserae: [n] complex."""
     n, cen, nrm, area, r = _mesh(m)
     b = np.zeros(n, dtype=np.complex128)
     _load().or_bem_ief_rhs(n, _d(cen), _d(nrm), _d(area), r, int(pol), float(e0), _d(b.view(np.float64)))

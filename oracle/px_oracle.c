@@ -1205,7 +1205,7 @@ int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nr
  *     S_ii = 1.0694 sqrt(4 pi A_i)                   (the self patch of 1/r)
  *     F_ij = A_j (s_i - s_j) . n_j / |s_i - s_j|^3   (i != j)
  *     F_ii = -1.0694 sqrt(4 pi A_i) / (2 R)
- *     V_i  = -E0 s_i,l   (the applied field's potential at the barycentre)
+ *     V_i  = -E0 (s_i - c)_l   (the applied field's potential at the barycentre)
  *     [ 2 pi f I + F ] S A^-1 q = -(2 pi I + F) V,  f = (eps2 + eps1) / (eps2 - eps1).
  * S A^-1 q is the potential the charges make at the barycentres and F is the
  * double-layer operator (normal derivative of 1/|s - s'| at the source, area
@@ -1218,7 +1218,16 @@ int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nr
  * With the printed sign a meshed sphere misses the Clausius-Mossotti value
  * by O(1) near resonance; with this one it converges at second order
  * (pinned, with the row sums -2 pi of Gauss's solid-angle identity and the
- * sphere eigenvalues of S and F). */
+ * sphere eigenvalues of S and F).
+ * Reading of V's zero: the potential of a uniform field is defined up to a
+ * constant, which drops out of the continuous equation ((2 pi + D) 1 = 0 on
+ * a closed surface) but not of the discrete one, where it leaks in at the
+ * discretization error times the constant: a sphere moved 1000 Angstrom from
+ * the origin changed its polarizability by 81 %.  V is taken relative to c,
+ * the area-weighted centroid of the tesserae, and the dipole likewise
+ * (d = sum_i q_i (s_i - c); the discrete charges are neutral only up to the
+ * discretization), so that the result does not depend on where the mesh
+ * sits (pinned). */
 
 static double ief_s(const bem_mesh* b, int64_t i, int64_t j)
 {
@@ -1243,6 +1252,18 @@ static double ief_f(const bem_mesh* b, int64_t i, int64_t j)
     return b->a[j] * dn / (r2 * sqrt(r2));
 }
 
+/* c = sum_i A_i s_i / sum_i A_i (bohr) */
+static void ief_centroid(const bem_mesh* b, double c[3])
+{
+    double w = 0.0;
+    c[0] = c[1] = c[2] = 0.0;
+    for (int64_t i = 0; i < b->n; ++i) {
+        w += b->a[i];
+        for (int k = 0; k < 3; ++k) c[k] += b->a[i] * b->s[3 * i + k];
+    }
+    for (int k = 0; k < 3; ++k) c[k] /= w;
+}
+
 /* S (bohr) and F (dimensionless) as dense row-major n x n matrices. */
 void or_bem_ief_matrices(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,
                          double r_enc_ang, double* s_out, double* f_out)
@@ -1261,8 +1282,10 @@ void or_bem_ief_rhs(int64_t n, const double* cen_ang, const double* nrm, const d
                     int l, double e0, double* b_out)
 {
     bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
+    double c[3];
+    ief_centroid(&b, c);
     double* v = (double*)malloc(sizeof(double) * n);
-    for (int64_t i = 0; i < n; ++i) v[i] = -e0 * b.s[3 * i + l];
+    for (int64_t i = 0; i < n; ++i) v[i] = -e0 * (b.s[3 * i + l] - c[l]);
     for (int64_t i = 0; i < n; ++i) {
         double fv = 0.0;
         for (int64_t j = 0; j < n; ++j) fv += ief_f(&b, i, j) * v[j];
@@ -1324,7 +1347,7 @@ void or_bem_ief_apply(int64_t n, const double* cen_ang, const double* nrm, const
 
 /* Direct-solve IEFPCM spectrum: P = F S A^-1 once (real), then per frequency
  * LU of 2 pi f S A^-1 + P (own LU, partial pivoting), every requested
- * polarization solved for the charges q, d = sum_i q_i s_i (Section 7),
+ * polarization solved for the charges q, d = sum_i q_i (s_i - c) (Section 7),
  * alpha_kl = d_k / E0 and sigma_abs as for DPCM.  q_out [n_omega][npol][n],
  * alpha_out [n_omega][3][3], complex interleaved; returns 0, or k + 1 if the
  * k-th factorization failed. */
@@ -1356,12 +1379,14 @@ int64_t or_bem_ief_solve_spectrum(int64_t n, const double* cen_ang, const double
             for (int64_t j = 0; j < n; ++j) p[i * n + j] += fik * sa[k * n + j];
         }
     }
-    /* -(2 pi I + F) V for each polarization, V_i = -E0 s_i,l */
+    /* -(2 pi I + F) V for each polarization, V_i = -E0 (s_i - c)_l */
+    double c[3];
+    ief_centroid(&b, c);
     for (int l = 0; l < 3; ++l)
         for (int64_t i = 0; i < n; ++i) {
             double fv = 0.0;
-            for (int64_t j = 0; j < n; ++j) fv += f[i * n + j] * (-e0 * b.s[3 * j + l]);
-            brhs[2 * (l * n + i)] = -(2.0 * PI * (-e0 * b.s[3 * i + l]) + fv);
+            for (int64_t j = 0; j < n; ++j) fv += f[i * n + j] * (-e0 * (b.s[3 * j + l] - c[l]));
+            brhs[2 * (l * n + i)] = -(2.0 * PI * (-e0 * (b.s[3 * i + l] - c[l])) + fv);
             brhs[2 * (l * n + i) + 1] = 0.0;
         }
     int64_t status = 0;
@@ -1386,8 +1411,8 @@ int64_t or_bem_ief_solve_spectrum(int64_t n, const double* cen_ang, const double
             for (int k = 0; k < 3; ++k) {
                 double dr = 0.0, di = 0.0;
                 for (int64_t i = 0; i < n; ++i) {
-                    dr += rhs[2 * i] * b.s[3 * i + k];
-                    di += rhs[2 * i + 1] * b.s[3 * i + k];
+                    dr += rhs[2 * i] * (b.s[3 * i + k] - c[k]);
+                    di += rhs[2 * i + 1] * (b.s[3 * i + k] - c[k]);
                 }
                 al[2 * (3 * k + l)] = dr / e0;
                 al[2 * (3 * k + l) + 1] = di / e0;

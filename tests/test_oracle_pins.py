@@ -963,9 +963,10 @@ def test_bem_ief_apply_rhs_and_direct_solution_agree():
         ref = F @ x[c] + 2 * np.pi * f * x[c]
         assert np.abs(y[c] - ref).max() <= 1e-12 * np.abs(ref).max()
     out = O.bem_ief_solve_spectrum(m, om, eps2, 1.3, 0b011, 1e-4)
+    c = (a[:, None] * s).sum(axis=0) / a.sum()
     for l in (0, 1):
         b = O.bem_ief_rhs(m, l, 1e-4)
-        v = -1e-4 * s[:, l]
+        v = -1e-4 * (s[:, l] - c[l])
         assert np.abs(b + (2 * np.pi * v + F @ v)).max() <= 1e-12 * np.abs(b).max()
         for w in range(2):
             f = (eps2[w] + 1.3) / (eps2[w] - 1.3)
@@ -991,3 +992,22 @@ def test_bem_ief_potential_is_the_single_layer_over_the_areas():
     y = O.bem_ief_potential(m, out["q"][0, 0])[0]
     r = O.bem_ief_apply(m, eps2, 1.0, y[None, :])[0] - O.bem_ief_rhs(m, 0, 1e-4)
     assert np.abs(r).max() <= 1e-10 * np.abs(O.bem_ief_rhs(m, 0, 1e-4)).max()
+
+
+def test_bem_ief_does_not_depend_on_where_the_mesh_sits():
+    """A constant in V drops out of the continuous equation but not of the
+    discrete one; with V and the dipole taken relative to the tesserae's
+    area-weighted centroid, two unequal spheres (neutral only up to the
+    discretization) give the same polarizability and charges wherever they
+    sit (moved by 1000 Angstrom; an uncentred V changes alpha by ~80 %)."""
+    s1, s2 = ME.sphere(20.0, 2), ME.sphere(30.0, 2)
+    m = dict(cen=np.vstack([s1["cen"], s2["cen"] + np.array([60.0, 0.0, 0.0])]),
+             nrm=np.vstack([s1["nrm"], s2["nrm"]]), area=np.concatenate([s1["area"], s2["area"]]), r_enc=60.0)
+    eps2 = np.array([-3.0 + 0.3j])
+    ref = O.bem_ief_solve_spectrum(m, np.array([3.0]), eps2, 1.0, 0b101, 1e-4)
+    moved = O.bem_ief_solve_spectrum(dict(m, cen=m["cen"] + np.array([1000.0, -300.0, 50.0])), np.array([3.0]), eps2,
+                                     1.0, 0b101, 1e-4)
+    assert np.abs(moved["alpha"] - ref["alpha"]).max() <= 1e-9 * np.abs(ref["alpha"]).max()
+    assert np.abs(moved["q"] - ref["q"]).max() <= 1e-9 * np.abs(ref["q"]).max()
+    q = ref["q"][0, 0]
+    assert 1e-6 < abs(q.sum()) / np.abs(q).sum() < 1e-2       # not neutral by symmetry here
