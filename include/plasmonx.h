@@ -275,7 +275,10 @@ pxStatus pxCreateBem(int64_t n_tess, const double* cen_ang, const double* normal
  *   [ 2 pi f I + F ] S A^-1 q = -(2 pi I + F) V,  f = (eps2 + eps1) / (eps2 - eps1),
  *   S_ij = A_j / |s_i - s_j|, S_ii = 1.0694 sqrt(4 pi A_i),
  *   F_ij = A_j (s_i - s_j).n_j / |s_i - s_j|^3, F_ii = -1.0694 sqrt(4 pi A_i) / (2R),
- *   V_i = -E0 s_i,l (the applied field's potential; the caller's origin).
+ *   V_i = -E0 (s_i - c)_l (the applied field's potential), d = sum_i q_i (s_i - c),
+ * with c the area-weighted centroid of the tesserae: a constant in V drops
+ * out of the continuous equation but not of the discrete one, so V's zero is
+ * put at c and the result does not depend on where the mesh sits.
  * F's diagonal is the double layer's self patch on a sphere (negative; the
  * printed positive value belongs to the DPCM operator).  The solver's unknown
  * is the potential y = S A^-1 q of every column, from [F - z I] y = b with

@@ -12,10 +12,12 @@
 //     [ F - z(w) I ] y = -(2 pi I + F) V,   z(w) = -2 pi (eps2 + eps1) / (eps2 - eps1),
 //     F_ij = A_j (s_i - s_j) . n_j / |s_i - s_j|^3   (i != j),
 //     F_ii = -1.0694 sqrt(4 pi A_i) / (2 R)   (the double layer's self patch),
-//     V_i = -E0 s_i,l,  then q = (S A^-1)^-1 y with
-//     (S A^-1)_ij = 1 / |s_i - s_j|,  (S A^-1)_ii = 1.0694 sqrt(4 pi / A_i).
-// S A^-1 is symmetric, so the dipole needs no charges: d_k = s_k . q =
-// w_k . y with w_k = (S A^-1)^-1 s_k, three real solves per mesh.
+//     V_i = -E0 (s_i - c)_l,  then q = (S A^-1)^-1 y with
+//     (S A^-1)_ij = 1 / |s_i - s_j|,  (S A^-1)_ii = 1.0694 sqrt(4 pi / A_i),
+// c the tesserae's area-weighted centroid (a constant in V would not drop
+// out of the discrete equation).  S A^-1 is symmetric, so the dipole needs no
+// charges: d_k = (s - c)_k . q = w_k . y with w_k = (S A^-1)^-1 (s - c)_k,
+// three real solves per mesh.
 // M and F are real and shared by every frequency, so the structure runs
 // through the omegaFQ solver with the tesserae as its sites, the identity in
 // place of Kbar, M or F in place of T and z(w) in place of z_q(w): the
@@ -667,23 +669,40 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     g.bem = true;
     g.bem_r = r_enc_bohr;
     if (!ief) return hipSuccess;
-    // IEFPCM: rv = 2 pi s + F s, then the dipole weights w = (S A^-1)^-1 s
+    // IEFPCM, with positions relative to the tesserae's area-weighted centroid
+    // c (the zero of the applied field's potential V and the dipole's origin:
+    // a constant in V does not drop out of the discrete equation): rv =
+    // 2 pi (s - c) + F (s - c), then the dipole weights w = (S A^-1)^-1 (s - c)
     g.bem_ief = true;
+    double cw = 0.0, cc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        const double a = area_bohr2[i];
+        cw += a;
+        for (int k = 0; k < 3; ++k) cc[k] += a * cen_bohr[3 * i + k];
+    }
+    for (int k = 0; k < 3; ++k) cc[k] /= cw;
+    std::vector<double4> sc((size_t)np);
+    for (int64_t i = 0; i < np; ++i)
+        sc[(size_t)i] = i < n ? make_double4(s[(size_t)i].x - cc[0], s[(size_t)i].y - cc[1], s[(size_t)i].z - cc[2], 0.0)
+                              : make_double4(0.0, 0.0, 0.0, 0.0);
     PXCHK(px::dev_malloc((void**)&g.bem_rv, sizeof(double4) * np));
     PXCHK(px::dev_malloc((void**)&g.bem_w, sizeof(double4) * np));
     PXCHK(hipMemsetAsync(g.bem_rv, 0, sizeof(double4) * np, st));
     double *scr = nullptr, *w3 = nullptr;
+    double4* scd = nullptr;
     e = px::dev_malloc((void**)&scr, bem_scratch_bytes(g, 3));
     if (e == hipSuccess) e = px::dev_malloc((void**)&w3, sizeof(double) * 3 * np);
+    if (e == hipSuccess) e = px::dev_malloc((void**)&scd, sizeof(double4) * np);
+    if (e == hipSuccess) e = hipMemcpyAsync(scd, sc.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        bem_apply_mode<1>(g, (const double*)g.xyz64, (double*)g.bem_rv, 4, 3, st, scr, nullptr, nullptr);
-        hipLaunchKernelGGL(k_bem_ief_rv, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st,
-                           (const double4*)g.xyz64, (const double4*)g.bem_na, g.bem_rv, np);
+        bem_apply_mode<1>(g, (const double*)scd, (double*)g.bem_rv, 4, 3, st, scr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_bem_ief_rv, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, (const double4*)scd,
+                           (const double4*)g.bem_na, g.bem_rv, np);
         e = hipGetLastError();
     }
     if (e == hipSuccess)
-        e = bem_single_layer_solve(g, (const double*)g.xyz64, 4, 3, w3, kSingleLayerTol, kSingleLayerMaxIter, st,
-                                   status, nullptr, nullptr);
+        e = bem_single_layer_solve(g, (const double*)scd, 4, 3, w3, kSingleLayerTol, kSingleLayerMaxIter, st, status,
+                                   nullptr, nullptr);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_bem_pack_w, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, (const double*)w3,
                            g.bem_w, np);
@@ -692,6 +711,7 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     px::dev_free(scr);
     px::dev_free(w3);
+    px::dev_free(scd);
 #undef PXCHK
     return e;
 }

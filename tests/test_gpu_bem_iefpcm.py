@@ -122,7 +122,9 @@ def test_bem_ief_charges_give_the_spectrum_dipole():
     s = make(c)
     assert s.solve(precision=px.PX_FP64, rel_tol=1e-12) == px.PX_OK
     alpha = s.spectrum()[0]
-    s_b = c["mesh"]["cen"] / BOHR
+    a = c["mesh"]["area"]
+    cen = c["mesh"]["cen"]
+    s_b = (cen - (a[:, None] * cen).sum(axis=0) / a.sum()) / BOHR   # relative to the area-weighted centroid
     worst = 0.0
     for w in range(0, len(c["om"]), 5):
         for l in range(3):
@@ -274,3 +276,29 @@ def test_bem_four_tesserae(form):
     say(f"[bem {form} tetrahedron] sigma {e_s:.1e} alpha {e_a:.1e} charges {e_q:.1e}")
     assert e_s <= 1e-10 and e_a <= 1e-9 and e_q <= 1e-8
     s.close()
+
+
+def test_bem_ief_does_not_depend_on_where_the_mesh_sits():
+    """Two unequal spheres (not neutral by symmetry) and the same pair moved
+    by 1000 Angstrom: the same spectrum and charges on the GPU, both against
+    the oracle (V and the dipole are taken relative to the tesserae's
+    area-weighted centroid)."""
+    s1, s2 = ME.sphere(20.0, 2), ME.sphere(30.0, 2)
+    m = dict(cen=np.vstack([s1["cen"], s2["cen"] + np.array([60.0, 0.0, 0.0])]),
+             nrm=np.vstack([s1["nrm"], s2["nrm"]]), area=np.concatenate([s1["area"], s2["area"]]), r_enc=60.0)
+    moved = dict(m, cen=m["cen"] + np.array([1000.0, -300.0, 50.0]))
+    om = np.linspace(3.0, 4.0, 12)
+    eps = M.drude_permittivity(AG, om)
+    ref = O.bem_ief_solve_spectrum(m, om, eps, 1.0, 0b011, 1e-4)
+    out = []
+    for mesh in (m, moved):
+        s = px.Structure.bem(mesh, 1.0, px.default_stream(), form="iefpcm")
+        s.set_frequencies(om, 0b011, 1e-4, eps)
+        assert s.solve(precision=px.PX_FP64, rel_tol=1e-12) == px.PX_OK
+        out.append((s.spectrum()[0], s.charges(4, 0)))
+        s.close()
+    e_move = rel_err(out[1][0], out[0][0])
+    e_ref = rel_err(out[0][0], ref["alpha"])
+    e_q = rel_err(out[1][1], ref["q"][4, 0])
+    say(f"[bem ief moved] alpha moved vs not {e_move:.1e}, vs oracle {e_ref:.1e}, charges {e_q:.1e}")
+    assert e_move <= 1e-9 and e_ref <= 1e-9 and e_q <= 1e-8
