@@ -1025,7 +1025,10 @@ void or_probe(int model, int64_t n, const double* xyz_ang, const double* p, cons
  * (bem-dpcm) (the printed form mixes an area-weighted and a dimensionless
  * term, and its normal index does not fit its positive diagonal): the unknowns
  * are the tessera charges q_i (the paper's sigma_i, so that d = sum_i q_i s_i
- * as in its Section 7), E_n,i = E . n_i, eps2 the metal inside and eps1 the
+ * as in its Section 7, with s_i taken from the tesserae's area-weighted
+ * centroid c: the discrete charges are neutral only up to the
+ * discretization, and the centroid keeps the dipole independent of where the
+ * mesh sits), E_n,i = E . n_i, eps2 the metal inside and eps1 the
  * medium outside, and
  *     [ M - 2 pi (eps2 + eps1) / (eps2 - eps1) I ] q = -A E_n,
  *     M_ij = A_i (s_i - s_j) . n_i / |s_i - s_j|^3   (i != j),
@@ -1064,6 +1067,18 @@ static bem_mesh bem_load(int64_t n, const double* cen_ang, const double* nrm, co
 }
 
 static void bem_free(bem_mesh* b) { free(b->s); free(b->nv); free(b->a); }
+
+/* c = sum_i A_i s_i / sum_i A_i (bohr) */
+static void bem_centroid(const bem_mesh* b, double c[3])
+{
+    double w = 0.0;
+    c[0] = c[1] = c[2] = 0.0;
+    for (int64_t i = 0; i < b->n; ++i) {
+        w += b->a[i];
+        for (int k = 0; k < 3; ++k) c[k] += b->a[i] * b->s[3 * i + k];
+    }
+    for (int k = 0; k < 3; ++k) c[k] /= w;
+}
 
 /* one element of M (see above) */
 static double bem_m(const bem_mesh* b, int64_t i, int64_t j)
@@ -1137,7 +1152,9 @@ void or_bem_apply(int64_t n, const double* cen_ang, const double* nrm, const dou
 
 /* Direct-solve spectrum of a BEM mesh: for each frequency, LU of
  * M - z(eps2(w)) I (own LU, partial pivoting), every requested polarization
- * solved, d = sum_i q_i s_i (Section 7), alpha_kl = d_k / E0, sigma_abs as for
+ * solved, d = sum_i q_i (s_i - c) (Section 7, c the tesserae's area-weighted
+ * centroid: the discrete charges are neutral only up to the discretization, so
+ * the dipole's origin is fixed on the mesh), alpha_kl = d_k / E0, sigma_abs as for
  * the atomistic models.  q_out [n_omega][npol][n], alpha_out [n_omega][3][3],
  * complex interleaved; returns 0, or k + 1 if the k-th factorization failed. */
 int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,
@@ -1155,6 +1172,8 @@ int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nr
     int64_t* piv = (int64_t*)malloc(sizeof(int64_t) * n);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j < n; ++j) m[i * n + j] = bem_m(&b, i, j);
+    double c[3];
+    bem_centroid(&b, c);
     int64_t status = 0;
     for (int64_t w = 0; w < n_omega; ++w) {
         double z[2];
@@ -1181,8 +1200,8 @@ int64_t or_bem_solve_spectrum(int64_t n, const double* cen_ang, const double* nr
             for (int k = 0; k < 3; ++k) {
                 double dr = 0.0, di = 0.0;
                 for (int64_t i = 0; i < n; ++i) {
-                    dr += rhs[2 * i] * b.s[3 * i + k];
-                    di += rhs[2 * i + 1] * b.s[3 * i + k];
+                    dr += rhs[2 * i] * (b.s[3 * i + k] - c[k]);
+                    di += rhs[2 * i + 1] * (b.s[3 * i + k] - c[k]);
                 }
                 al[2 * (3 * k + l)] = dr / e0;
                 al[2 * (3 * k + l) + 1] = di / e0;
@@ -1252,17 +1271,6 @@ static double ief_f(const bem_mesh* b, int64_t i, int64_t j)
     return b->a[j] * dn / (r2 * sqrt(r2));
 }
 
-/* c = sum_i A_i s_i / sum_i A_i (bohr) */
-static void ief_centroid(const bem_mesh* b, double c[3])
-{
-    double w = 0.0;
-    c[0] = c[1] = c[2] = 0.0;
-    for (int64_t i = 0; i < b->n; ++i) {
-        w += b->a[i];
-        for (int k = 0; k < 3; ++k) c[k] += b->a[i] * b->s[3 * i + k];
-    }
-    for (int k = 0; k < 3; ++k) c[k] /= w;
-}
 
 /* S (bohr) and F (dimensionless) as dense row-major n x n matrices. */
 void or_bem_ief_matrices(int64_t n, const double* cen_ang, const double* nrm, const double* area_ang2,
@@ -1283,7 +1291,7 @@ void or_bem_ief_rhs(int64_t n, const double* cen_ang, const double* nrm, const d
 {
     bem_mesh b = bem_load(n, cen_ang, nrm, area_ang2, r_enc_ang);
     double c[3];
-    ief_centroid(&b, c);
+    bem_centroid(&b, c);
     double* v = (double*)malloc(sizeof(double) * n);
     for (int64_t i = 0; i < n; ++i) v[i] = -e0 * (b.s[3 * i + l] - c[l]);
     for (int64_t i = 0; i < n; ++i) {
@@ -1381,7 +1389,7 @@ int64_t or_bem_ief_solve_spectrum(int64_t n, const double* cen_ang, const double
     }
     /* -(2 pi I + F) V for each polarization, V_i = -E0 (s_i - c)_l */
     double c[3];
-    ief_centroid(&b, c);
+    bem_centroid(&b, c);
     for (int l = 0; l < 3; ++l)
         for (int64_t i = 0; i < n; ++i) {
             double fv = 0.0;
