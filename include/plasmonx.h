@@ -253,8 +253,10 @@ pxStatus pxCreateStructureHetero(pxModel model, int64_t n_atoms, const double* x
  * returns them in the caller's tessera order) and the solved system is
  *   [ M - 2 pi (eps2 + eps1) / (eps2 - eps1) I ] q = -A E_n,
  *   M_ij = A_i (s_i - s_j).n_i / |s_i - s_j|^3, M_ii = 1.0694 sqrt(4 pi A_i) / (2R),
- * with E_n,i = E0 e_l . n_i; d = sum_i q_i s_i (Section 7) and alpha, sigma_abs
- * as for the atomistic models.  pxSetFrequencies takes the metal permittivity
+ * with E_n,i = E0 e_l . n_i; d = sum_i q_i (s_i - c) (Section 7, c the
+ * area-weighted centroid of the tesserae: the discrete charges are neutral
+ * only up to the discretization, so the dipole's origin is fixed on the mesh)
+ * and alpha, sigma_abs as for the atomistic models.  pxSetFrequencies takes the metal permittivity
  * eps2(omega_w) per frequency in its alpha_ib argument (2 * n_omega doubles,
  * interleaved complex, != eps1).  M is real and the same at every frequency,
  * so pxSolveSpectrum (shifted >= 1) runs the shared-Krylov phase over all

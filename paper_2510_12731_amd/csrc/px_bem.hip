@@ -668,12 +668,10 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     g.nnz = n;
     g.bem = true;
     g.bem_r = r_enc_bohr;
-    if (!ief) return hipSuccess;
-    // IEFPCM, with positions relative to the tesserae's area-weighted centroid
-    // c (the zero of the applied field's potential V and the dipole's origin:
-    // a constant in V does not drop out of the discrete equation): rv =
-    // 2 pi (s - c) + F (s - c), then the dipole weights w = (S A^-1)^-1 (s - c)
-    g.bem_ief = true;
+    // positions relative to the tesserae's area-weighted centroid c: the
+    // dipole's origin (the discrete charges are neutral only up to the
+    // discretization), and for IEFPCM the zero of the applied field's
+    // potential V (a constant in V does not drop out of the discrete equation)
     double cw = 0.0, cc[3] = {0.0, 0.0, 0.0};
     for (int64_t i = 0; i < n; ++i) {
         const double a = area_bohr2[i];
@@ -685,8 +683,17 @@ hipError_t build_bem_geometry(Geometry& g, const double* cen_bohr, const double*
     for (int64_t i = 0; i < np; ++i)
         sc[(size_t)i] = i < n ? make_double4(s[(size_t)i].x - cc[0], s[(size_t)i].y - cc[1], s[(size_t)i].z - cc[2], 0.0)
                               : make_double4(0.0, 0.0, 0.0, 0.0);
-    PXCHK(px::dev_malloc((void**)&g.bem_rv, sizeof(double4) * np));
     PXCHK(px::dev_malloc((void**)&g.bem_w, sizeof(double4) * np));
+    if (!ief) {
+        // DPCM's dipole weights: the centred positions (d_k = w_k . q)
+        PXCHK(hipMemcpyAsync(g.bem_w, sc.data(), sizeof(double4) * np, hipMemcpyHostToDevice, st));
+        PXCHK(hipStreamSynchronize(st));
+        return hipSuccess;
+    }
+    // IEFPCM, with u = s - c: rv = 2 pi u + F u, then the dipole weights
+    // w = (S A^-1)^-1 u
+    g.bem_ief = true;
+    PXCHK(px::dev_malloc((void**)&g.bem_rv, sizeof(double4) * np));
     PXCHK(hipMemsetAsync(g.bem_rv, 0, sizeof(double4) * np, st));
     double *scr = nullptr, *w3 = nullptr;
     double4* scd = nullptr;

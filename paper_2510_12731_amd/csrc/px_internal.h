@@ -79,12 +79,12 @@ struct Geometry {
     // centre (cx, cy, cz) with |p|^2 in w in xyzc), with their outward unit
     // normal and area in bem_na [np] (ghosts: area 0) and (A n, A p.n) in
     // bem_an, the identity in place of Kbar and the radius enclosing the mesh
-    // (bohr).  DPCM solves for the charges; IEFPCM (bem_ief) for the
-    // potential y = S A^-1 q they make, with u = s - c (c the tesserae's
-    // area-weighted centroid), bem_rv [np] = 2 pi u + F u (the right-hand
-    // side per unit field, component l for polarization l) and bem_w [np] =
-    // (S A^-1)^-1 u (the dipole weights: d_k = w_k . y, S A^-1 being
-    // symmetric)
+    // (bohr).  With u = s - c (c the tesserae's area-weighted centroid), DPCM
+    // solves for the charges with the dipole weights bem_w [np] = u (d_k =
+    // w_k . q); IEFPCM (bem_ief) for the potential y = S A^-1 q they make,
+    // with bem_rv [np] = 2 pi u + F u (the right-hand side per unit field,
+    // component l for polarization l) and bem_w [np] = (S A^-1)^-1 u (d_k =
+    // w_k . y, S A^-1 being symmetric)
     bool bem = false;
     bool bem_ief = false;
     double4* bem_na = nullptr;

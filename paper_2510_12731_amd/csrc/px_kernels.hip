@@ -1611,9 +1611,10 @@ void scatter_cols(const double2* src, int lds, double2* dst, int ldd, const int3
 void observables(const Geometry& g, const double2* x, int ncol, int ldx, double2* dpart, double2* d, hipStream_t st)
 {
     int nch = nchunks(g.n);
-    // an IEFPCM structure's unknowns are potentials: its dipole weights in
-    // place of the positions
-    const double4* pos = g.bem_ief ? g.bem_w : g.xyz64;
+    // a BEM structure's dipole weights in place of the positions: the
+    // positions from the tesserae's centroid (DPCM) or their single-layer
+    // solve (IEFPCM, whose unknowns are potentials)
+    const double4* pos = g.bem ? g.bem_w : g.xyz64;
     hipLaunchKernelGGL(k_dipole_partial, dim3(nch, (unsigned)((ncol + 63) / 64)), dim3(64), 0, st, x, pos, g.n,
                        g.np, g.model, ncol, ldx, dpart);
     hipLaunchKernelGGL(k_dipole_reduce, dim3((unsigned)((3 * ncol + 255) / 256)), dim3(256), 0, st, dpart, nch, ncol,

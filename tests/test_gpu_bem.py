@@ -208,3 +208,27 @@ def test_bem_sphere_full_size():
         say(f"   column (w={om[w]:.3f} eV, pol {pol}): oracle residual {rel:.2e}")
         assert rel <= 1e-8 + 1e-10
     s.close()
+
+
+def test_bem_dipole_does_not_depend_on_where_the_mesh_sits():
+    """Two unequal spheres (charges neutral only to ~1e-4 of sum |q|) and the
+    same pair moved by 1000 Angstrom: the same polarizability on the GPU (the
+    dipole is taken from the tesserae's area-weighted centroid), and the
+    oracle's."""
+    s1, s2 = ME.sphere(20.0, 2), ME.sphere(30.0, 2)
+    m = dict(cen=np.vstack([s1["cen"], s2["cen"] + np.array([60.0, 0.0, 0.0])]),
+             nrm=np.vstack([s1["nrm"], s2["nrm"]]), area=np.concatenate([s1["area"], s2["area"]]), r_enc=60.0)
+    moved = dict(m, cen=m["cen"] + np.array([1000.0, -300.0, 50.0]))
+    om = np.linspace(3.0, 4.0, 12)
+    eps = M.drude_permittivity(AG, om)
+    ref = O.bem_solve_spectrum(m, om, eps, 1.0, 0b011, 1e-4)
+    al = []
+    for mesh in (m, moved):
+        s = px.Structure.bem(mesh, 1.0, px.default_stream())
+        s.set_frequencies(om, 0b011, 1e-4, eps)
+        assert s.solve(precision=px.PX_FP64, rel_tol=1e-12) == px.PX_OK
+        al.append(s.spectrum()[0])
+        s.close()
+    e_move, e_ref = rel_err(al[1], al[0]), rel_err(al[0], ref["alpha"])
+    say(f"[bem moved] alpha moved vs not {e_move:.1e}, vs oracle {e_ref:.1e}")
+    assert e_move <= 1e-9 and e_ref <= 1e-9
